@@ -1,0 +1,182 @@
+#!/usr/bin/env python
+"""Throughput of the clustering hot path on one MI355X.
+
+One step = Euclidean MST (Boruvka screen + exact recheck + contraction + FP64
+lengths + rooting) followed by the optimal k-subpartition of the tree
+(speculative bisection over Algorithm 1, labels), on the image-like workload
+n = 200,000 points, d = 784, k = 10, sigma = median MST edge, points resident
+in HBM before the timed region.  Prints one JSON line (rank 0).
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
+WORKLOAD = 3
+PEAKS_TFLOPS = {"bf16": 2500.0, "fp32_mfma": 157.3, "fp32_valu": 157.3}
+SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/mst.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def screen_source_sha():
+    h = hashlib.sha256()
+    for p in SCREEN_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(precision):
+    """HBM bytes per screen launch from committed rocprofv3 counter runs, or
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "screen_%s_traffic.json" % precision)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != screen_source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n_full, k, sample_n):
+    """The FP64 oracle (single thread) on a subsample of the same recipe; the
+    O(n^2 d) MST cost is scaled to the full n."""
+    import oracle
+    from paper_1702_04739_amd import datagen
+    X = datagen.config(WORKLOAD, n=sample_n)
+    t0 = time.perf_counter()
+    parent, length, _, _ = oracle.prim_mst(X)
+    t1 = time.perf_counter()
+    oracle.subpartition(parent, length, k)
+    t2 = time.perf_counter()
+    t_full = (t1 - t0) * (n_full / sample_n) ** 2 + (t2 - t1) * (n_full / sample_n)
+    return {
+        "value": n_full / t_full,
+        "unit": "points/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "same recipe at n=%d (MST %.2f s, tree search %.3f s, single thread); MST time scaled by "
+                  "(n/%d)^2 and tree time by n/%d to n=%d" % (sample_n, t1 - t0, t2 - t1, sample_n, sample_n, n_full),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=6000)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the MST screen shards over tile pairs with one min-all-reduce per "
+              "Boruvka round, but no multi-GPU path is built; run with --gpus 1", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1702_04739_amd as iso
+    from paper_1702_04739_amd import _lib, datagen
+
+    cfg = datagen.CONFIGS[WORKLOAD]
+    n = args.n or cfg["n"]
+    d, k = cfg["d"], cfg["k"]
+    log("generating %s n=%d d=%d" % (cfg["name"], n, d))
+    X = torch.from_numpy(datagen.config(WORKLOAD, n=n)).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        return iso.cluster(X, k, precision=args.precision, recheck=args.recheck)
+
+    for w in range(args.warmup):
+        log("warmup %d" % w)
+        step()
+    torch.cuda.synchronize()
+    _lib.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for s in range(args.steps):
+        last = step()
+        log("step %d done" % s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    T = _lib.timing_read()
+    _lib.timing_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms / 1e3)
+
+    labels, ik, info = last
+    flops = 2.0 * d * T["screen_pairs"]
+    achieved = flops / (T["screen_ms"] * 1e-3) / 1e12 if T["screen_ms"] > 0 else None
+    if args.precision == "bf16":
+        bound, peak = "mfma", PEAKS_TFLOPS["bf16"]
+    else:
+        bound, peak = "alu", PEAKS_TFLOPS["fp32_valu"]
+    launches = max(T["screen_launches"], 1)
+    tb = traffic_from_profiles(args.precision)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": cfg["name"] if args.n is None else "%s@n=%d" % (cfg["name"], n), "n": n, "d": d,
+                   "k": k, "sigma": "median MST edge", "screen": args.precision, "recheck": args.recheck,
+                   "tree": "f64", "parallelism": "none"},
+        "roofline": {
+            "kernel": "k_screen_f32" if args.precision == "fp32" else "k_screen_bf16",
+            "bound": bound,
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": (achieved / peak) if achieved else None,
+            "traffic": tb,
+            "flops_per_launch": flops / launches,
+            "avg_launch_ms": T["screen_ms"] / launches,
+            "launches": T["screen_launches"],
+        },
+        "phases": {"mst_ms_per_step": T["mst_ms"] / max(T["mst_calls"], 1),
+                   "sub_ms_per_step": T["sub_ms"] / max(T["sub_calls"], 1),
+                   "screen_ms_per_step": T["screen_ms"] / args.steps,
+                   "rounds": info["mst"]["rounds"], "candidates": info["mst"]["candidates"],
+                   "rescanned_rows": info["mst"]["rescanned_rows"], "bisection_iters": info["sub"]["iters"],
+                   "passes": info["sub"]["passes"], "max_depth": info["sub"]["max_depth"],
+                   "i_k": ik, "mst_weight": info["mst"]["mst_weight"]},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, n=%d sample)" % args.cpu_sample_n)
+        out["cpu_baseline"] = cpu_baseline(n, k, args.cpu_sample_n)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * isoclust.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of "An Efficient Parallel Data Clustering Algorithm Using Isoperimetric
+ * Number of Trees" (Javadi & Ashkboos, arXiv 1702.04739):
+ *
+ *   iso_mst           Euclidean minimum spanning tree of n points in R^d
+ *                     (Sec. 2.2 step 2, Sec. 3.5), returned as the paper's
+ *                     "parent list" (Sec. 3.3): parent[] and edge lengths.
+ *   iso_subpartition  the tree's optimal k-subpartition and the k-th
+ *                     isoperimetric number MISO_k(T) (eqs. 2.4 and 2.6), by the
+ *                     decision procedure of Algorithm 1 inside the bisection of
+ *                     Algorithm 2, labelled as in Algorithm 4.
+ *   iso_backward      gradient of the total tree length and of the optimal
+ *                     subpartition's cost with respect to the points and sigma,
+ *                     with the tree and the subpartition held fixed.
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless marked (host).  Device buffers are
+ *     owned by the caller; the library never frees them and keeps no state
+ *     between calls.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     An entry point that writes a (host) result synchronises `stream` before
+ *     it returns; the others return once their work is enqueued.
+ *   - Vertex ids are int32 (n < 2^31).  Points are FP32, row-major, row stride
+ *     `ld` elements (ld >= d).
+ *   - Every argument is validated before any device work is enqueued.  On
+ *     error the return value is negative, device outputs are unspecified, and
+ *     iso_last_error() describes the failure.
+ *   - Workspace: pass ws = NULL to let the library allocate (hipMallocAsync on
+ *     `stream`, freed before return), or a device buffer of at least the size
+ *     the matching *_workspace_size call reports (else ISO_ERR_WORKSPACE).
+ */
+#ifndef ISOCLUST_H
+#define ISOCLUST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t iso_status;
+#define ISO_OK 0
+#define ISO_ERR_INVALID_ARG (-1)  /* argument outside its documented domain        */
+#define ISO_ERR_NONFINITE (-2)    /* a point coordinate is NaN or infinite          */
+#define ISO_ERR_NO_DEVICE (-3)    /* no usable gfx950 device                        */
+#define ISO_ERR_HIP (-4)          /* a HIP runtime call failed                      */
+#define ISO_ERR_OOM (-5)          /* device allocation failed                       */
+#define ISO_ERR_WORKSPACE (-6)    /* caller workspace smaller than required         */
+#define ISO_ERR_INTERNAL (-7)     /* an internal consistency check failed           */
+
+/* Precision of the Gram tiles ||x||^2 + ||y||^2 - 2 x.y used to screen pairs.
+ * Every pair that can be a component's minimum under the error bound of the
+ * screen is re-evaluated exactly (iso_recheck), so the tree does not depend on
+ * the screen's precision. */
+#define ISO_PREC_FP32 0
+#define ISO_PREC_BF16 1
+
+/* Arithmetic of the exact re-evaluation of candidate distances, which defines
+ * the order of the edges:
+ *   FP32: D^2 = sum_t (x_t - y_t)^2 in FP32, in a fixed order;
+ *   FP64: D^2 = sum_t (x_t - y_t)^2 in FP64, left to right over t, each term
+ *         rounded separately (parity mode). */
+#define ISO_RECHECK_FP32 0
+#define ISO_RECHECK_FP64 1
+
+/* Vertex weight omega (eq. 2.2) and flow phi (eq. 2.1) readings. */
+#define ISO_OMEGA_TREE 0   /* omega(v) = sum of phi over v's tree edges         */
+#define ISO_PHI_EXP_DIST 0 /* phi = exp(-D / sigma), as printed in eq. 2.1      */
+#define ISO_PHI_GAUSS_SQ 1 /* phi = exp(-D^2 / (2 sigma^2))                      */
+/* Initial bracket of the bisection (Algorithm 2). */
+#define ISO_BRACKET_POW2 0  /* alpha0 rounded down, beta0 up, to powers of two  */
+#define ISO_BRACKET_PAPER 1 /* printed alpha0, beta0 (beta0 moved up one ulp)   */
+
+typedef struct {
+    int32_t rounds;          /* Boruvka rounds                                   */
+    int32_t reserved0;
+    int64_t candidates;      /* candidate pairs re-evaluated exactly (all rounds) */
+    int64_t rescanned_rows;  /* rows whose candidate list overflowed and were
+                                re-evaluated against every other point          */
+    double mst_weight;       /* sum of the n-1 FP64 edge lengths                 */
+} iso_mst_info;
+
+/* Device bytes iso_mst needs as workspace for n points in d dimensions. */
+iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_t *bytes /* host */);
+
+/* Euclidean minimum spanning tree of the complete graph on the n points X
+ * (Sec. 2.2 step 2 / Sec. 3.5).  The n x n distance matrix is never stored:
+ * distances are formed tile by tile.  Edges are totally ordered by (D^2 under
+ * `recheck`, smaller end id, larger end id), so the tree is unique.
+ *   X       [n*ld] FP32 points (read only).
+ *   parent  [n] out: tree rooted at vertex 0, parent[0] = -1.
+ *   length  [n] out: FP64 Euclidean length of the edge (v, parent[v]),
+ *                    sqrt of the left-to-right FP64 sum of squared coordinate
+ *                    differences; length[0] = 0.
+ *   info    (host, nullable) out: statistics; requires a stream sync.
+ * Errors: n < 2, d < 1, ld < d, null pointers, unknown precision/recheck
+ * (INVALID_ARG); a non-finite coordinate (NONFINITE). */
+iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t precision, int32_t recheck,
+                   int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes, void *stream);
+
+typedef struct {
+    int32_t omega;     /* ISO_OMEGA_*   (default TREE)      */
+    int32_t phi;       /* ISO_PHI_*     (default EXP_DIST)  */
+    int32_t bracket;   /* ISO_BRACKET_* (default POW2)      */
+    int32_t max_iters; /* bisection step cap, <= 0 => 2000  */
+} iso_sub_opts;
+
+typedef struct {
+    double sigma;                 /* sigma used                                        */
+    double alpha0_raw, beta0_raw; /* printed bracket of Algorithm 2                    */
+    double alpha0, beta0;         /* bracket used                                      */
+    double alpha, beta;           /* final bracket; the subpartition is the one
+                                     Algorithm 1 returns at N = beta                    */
+    double i_k;                   /* cost of the returned subpartition (eq. 2.4)       */
+    int32_t t_paper;              /* printed iteration count of Algorithm 2 (reported) */
+    int32_t iters;                /* bisection steps taken (to FP64 resolution)        */
+    int32_t passes;               /* device passes (several bisection steps each)      */
+    int32_t max_depth;            /* depth of the rooted tree                          */
+    int32_t jstar;                /* smallest cluster index attaining i_k              */
+    int32_t reserved0;
+} iso_sub_info;
+
+/* Device bytes iso_subpartition needs as workspace. */
+iso_status iso_sub_workspace_size(int64_t n, int32_t k, size_t *bytes /* host */);
+
+/* Optimal k-subpartition of the weighted tree (parent, length) and its cost
+ * MISO_k(T) (eq. 2.6), by Algorithm 1 inside the bisection of Algorithm 2,
+ * run to FP64 resolution (the bisection stops when the midpoint equals an end
+ * point).  The x-order of Algorithm 1 is (depth descending, id ascending).
+ *   parent  [n] tree rooted at `root` (parent[root] = -1).
+ *   length  [n] FP64 edge lengths (length[root] ignored).
+ *   sigma   > 0, or 0 for the lower median of the n-1 edge lengths.
+ *   opts    (host, nullable) readings; NULL = defaults.
+ *   labels  [n] out: cluster 0..k-1 in x-order of the cut vertices, or -1 for
+ *                    residual (outlier) vertices.
+ *   i_k     (host) out: MISO_k as found (requires a stream sync).
+ *   cluster_num, cluster_den [k] FP64, cluster_size [k] int32 (nullable) out:
+ *                    phi(delta A_j) + p(A_j), omega(A_j) and |A_j|.
+ *   info    (host, nullable) out.
+ * Errors: n < 2, k < 2, k > n, root outside [0, n), sigma < 0 or not finite,
+ * parent not a tree rooted at root (INVALID_ARG). */
+iso_status iso_subpartition(const int32_t *parent, const double *length, int64_t n, int32_t root, int32_t k,
+                            double sigma, const iso_sub_opts *opts, int32_t *labels, double *i_k /* host */,
+                            double *cluster_num, double *cluster_den, int32_t *cluster_size, iso_sub_info *info,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* Optional phase timing, for benchmarks: while enabled, iso_mst brackets every
+ * screen launch with hipEvents on its stream and counts the unordered pairs
+ * of points in different components that the launch must cover, and both entry
+ * points record their own duration.  Totals accumulate in process-wide
+ * counters (not thread safe) until the next iso_timing_enable call, which
+ * resets them.  Enabling timing adds synchronisation-free event records and,
+ * per Boruvka round, a component-size reduction. */
+typedef struct {
+    int32_t enabled;
+    int32_t screen_launches;  /* screen kernel launches timed                       */
+    double screen_ms;         /* summed durations of those launches                 */
+    double screen_pairs;      /* summed unordered inter-component pairs they cover  */
+    double screen_dim;        /* padded dimension the screen contracts over         */
+    int32_t mst_calls, sub_calls;
+    double mst_ms;            /* summed iso_mst durations (first to last launch)    */
+    double sub_ms;            /* summed iso_subpartition durations                  */
+    int32_t sub_passes;       /* speculative bisection passes                       */
+    int32_t reserved0;
+} iso_timing;
+
+iso_status iso_timing_enable(int32_t on);
+iso_status iso_timing_read(iso_timing *out /* host */);
+
+/* Text of the last error on the calling thread (valid until its next call). */
+const char *iso_last_error(void);
+
+/* Library version string. */
+const char *iso_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISOCLUST_H */

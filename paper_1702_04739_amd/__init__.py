@@ -1,0 +1,117 @@
+"""isoclust -- MI355X (gfx950) implementation of the data-parallel hot path of
+"An Efficient Parallel Data Clustering Algorithm Using Isoperimetric Number of
+Trees" (Javadi & Ashkboos, arXiv 1702.04739).
+
+    parent, length, info = mst(points)                      # Sec. 2.2 step 2, Sec. 3.5
+    labels, i_k, info = isoperimetric_subpartition(parent, length, k)   # Algorithms 1, 2, 4
+    labels, i_k, info = cluster(points, k)                  # both
+
+Tensors live on the GPU (torch is used for device memory and streams only);
+all computation runs in the HIP library libisoclust.so through its C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+__all__ = ["mst", "isoperimetric_subpartition", "cluster", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require_cuda(t, name, dtype=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+
+
+def version() -> str:
+    return _lib.load().iso_version().decode()
+
+
+def mst(points, precision: str = "fp32", recheck: str = "fp32"):
+    """Euclidean minimum spanning tree of the rows of ``points`` (n x d, float32, GPU).
+
+    Returns (parent int32[n] rooted at 0 with parent[0] = -1, length float64[n]
+    with length[0] = 0, info dict).  ``precision`` selects the Gram screen
+    ("fp32" or "bf16"); ``recheck`` the exact arithmetic that orders the edges
+    ("fp32", or "fp64" for parity with the FP64 oracle)."""
+    torch = _torch()
+    _require_cuda(points, "points", torch.float32)
+    if points.dim() != 2:
+        raise ValueError("points must be 2-D")
+    if points.stride(1) != 1:
+        points = points.contiguous()
+    n, d = points.shape
+    ld = points.stride(0)
+    lib = _lib.load()
+    need = ctypes.c_size_t(0)
+    _lib.check(lib.iso_mst_workspace_size(n, d, _lib.PRECISION[precision], ctypes.byref(need)), "iso_mst_workspace_size")
+    dev = points.device
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    length = torch.empty(n, dtype=torch.float64, device=dev)
+    info = _lib.MstInfo()
+    rc = lib.iso_mst(ctypes.c_void_p(points.data_ptr()), n, d, ld, _lib.PRECISION[precision], _lib.RECHECK[recheck],
+                     ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), ctypes.byref(info),
+                     ctypes.c_void_p(ws.data_ptr()), int(need.value), _stream_ptr(dev))
+    _lib.check(rc, "iso_mst")
+    return parent, length, {"rounds": info.rounds, "candidates": info.candidates,
+                            "rescanned_rows": info.rescanned_rows, "mst_weight": info.mst_weight}
+
+
+def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = None, root: int = 0, phi: str = "exp",
+                               bracket: str = "pow2", max_iters: int = 2000, return_clusters: bool = False):
+    """Optimal k-subpartition of the weighted tree and MISO_k (eqs. 2.4, 2.6).
+
+    ``sigma`` None (or 0) selects the lower median edge length.  Returns
+    (labels int32[n] with -1 for residual vertices, i_k, info dict); with
+    ``return_clusters`` the info also holds per-cluster num, den and size."""
+    torch = _torch()
+    _require_cuda(parent, "parent", torch.int32)
+    _require_cuda(length, "length", torch.float64)
+    parent = parent.contiguous()
+    length = length.contiguous()
+    n = parent.shape[0]
+    if length.shape[0] != n:
+        raise ValueError("parent and length differ in size")
+    lib = _lib.load()
+    need = ctypes.c_size_t(0)
+    _lib.check(lib.iso_sub_workspace_size(n, int(k), ctypes.byref(need)), "iso_sub_workspace_size")
+    dev = parent.device
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    cnum = torch.empty(k, dtype=torch.float64, device=dev)
+    cden = torch.empty(k, dtype=torch.float64, device=dev)
+    csize = torch.empty(k, dtype=torch.int32, device=dev)
+    opts = _lib.SubOpts(_lib.OMEGA["tree"], _lib.PHI[phi], _lib.BRACKET[bracket], int(max_iters))
+    info = _lib.SubInfo()
+    ik = ctypes.c_double(0.0)
+    rc = lib.iso_subpartition(ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), n, int(root),
+                              int(k), float(sigma or 0.0), ctypes.byref(opts), ctypes.c_void_p(labels.data_ptr()),
+                              ctypes.byref(ik), ctypes.c_void_p(cnum.data_ptr()), ctypes.c_void_p(cden.data_ptr()),
+                              ctypes.c_void_p(csize.data_ptr()), ctypes.byref(info), ctypes.c_void_p(ws.data_ptr()),
+                              int(need.value), _stream_ptr(dev))
+    _lib.check(rc, "iso_subpartition")
+    out = {f: getattr(info, f) for f, _ in _lib.SubInfo._fields_ if f != "reserved0"}
+    if return_clusters:
+        out.update(cluster_num=cnum, cluster_den=cden, cluster_size=csize)
+    return labels, float(ik.value), out
+
+
+def cluster(points, k: int, sigma: float | None = None, precision: str = "fp32", recheck: str = "fp32", **kw):
+    """MST followed by the optimal k-subpartition (the paper's full hot path)."""
+    parent, length, minfo = mst(points, precision=precision, recheck=recheck)
+    labels, ik, sinfo = isoperimetric_subpartition(parent, length, k, sigma=sigma, **kw)
+    return labels, ik, {"mst": minfo, "sub": sinfo, "parent": parent, "length": length}

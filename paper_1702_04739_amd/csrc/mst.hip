@@ -1,0 +1,890 @@
+// mst.hip -- Euclidean minimum spanning tree on gfx950 by Boruvka rounds over
+// on-the-fly distance tiles (the paper builds the MST with Prim over a stored
+// n x n affinity matrix, Secs. 3.4-3.5; here the matrix is never stored).
+//
+// One Boruvka round:
+//   screen    : every row i sweeps all column tiles, forming
+//               Dhat^2 = ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j tile by tile and
+//               keeping, over columns j in another component, the running
+//               minimum b_i and every (j, Dhat^2) with Dhat^2 <= b_i + 2 E_i,
+//               where E_i bounds |Dhat^2 - D^2| for the row (candidates);
+//   comp_ub   : U_c = min over rows of component c of b_i + E_i, an upper
+//               bound on c's lightest outgoing edge;
+//   recheck   : exact D^2 of the candidates that can still reach U_c, giving
+//               each row its lightest outgoing edge under the total order
+//               (D^2, smaller id, larger id); rows whose candidate list
+//               overflowed are re-evaluated against every point (rescan);
+//   comp_min  : lightest outgoing edge per component (two 64-bit atomic mins);
+//   hook/jump : each component hooks onto the component across its edge;
+//               mutual pairs keep the smaller id as root; pointer jumping;
+//   relabel   : compact component ids by an exclusive scan.
+// After the last round: FP64 edge lengths and a BFS from vertex 0 give the
+// parent list (Sec. 3.3) rooted at 0.
+#include <cfloat>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace iso {
+
+namespace {
+
+constexpr int GT = 128;        // screen tile edge (rows and columns)
+constexpr int GK = 16;         // K chunk staged through LDS
+constexpr int GB = 256;        // threads per screen workgroup
+constexpr int CAND = 32;       // candidate slots per row
+constexpr float F_INF = __builtin_huge_valf();
+constexpr uint32_t U32_MAX = 0xFFFFFFFFu;
+constexpr uint64_t U64_MAX = ~0ull;
+
+enum Counter : int {
+    C_EDGES = 0,        // edges appended so far
+    C_NCOMP = 1,        // components after relabel
+    C_NONFINITE = 2,    // nonfinite coordinate seen
+    C_OVF = 3,          // overflow rows this round
+    C_NOEDGE = 4,       // a component without an outgoing edge (internal error)
+    C_SEEN = 5,         // vertices reached by the rooting BFS
+    C_CAND = 8,         // candidates re-evaluated (int64 at [8..9])
+    C_RESCAN = 10,      // rows rescanned (int64 at [10..11])
+    C_SUMSQ = 12,       // sum over components of size^2 (int64 at [12..13], timing only)
+    C_COUNT = 16
+};
+
+// ------------------------------------------------------------------ small kernels
+
+template <class T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+void fill(T *p, T v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = grid_for(n, 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(256), 0, s, p, v, n);
+    LAUNCH_CHECK();
+}
+
+// FP32 k-major padded copy XT[t][i] (t < d_pad, i < n_pad), zeros outside.
+__global__ __launch_bounds__(256) void k_transpose_pad(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                       int64_t n_pad, int64_t d_pad, float *__restrict__ XT) {
+    __shared__ float tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64, t0 = (int64_t)blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    for (int r = ty; r < 64; r += 4) {
+        int64_t i = i0 + r, t = t0 + tx;
+        tile[r][tx] = (i < n && t < d) ? X[i * ld + t] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        int64_t t = t0 + r, i = i0 + tx;
+        if (t < d_pad && i < n_pad) XT[t * n_pad + i] = tile[tx][r];
+    }
+}
+
+// Squared norm per row (FP32, fixed order), nonfinite check, global max.
+__global__ __launch_bounds__(256) void k_norms(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                               float *__restrict__ sq, uint32_t *__restrict__ sqmax_bits,
+                                               int32_t *__restrict__ counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const float *x = X + row * ld;
+    float acc = 0.0f;
+    bool bad = false;
+    for (int64_t t = lane; t < d; t += 64) {
+        float v = x[t];
+        bad |= !isfinite(v);
+        acc = fmaf(v, v, acc);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (__any(bad) && lane == 0) atomicExch(&counters[C_NONFINITE], 1);
+    if (lane == 0) {
+        sq[row] = acc;
+        atomicMax(sqmax_bits, __float_as_uint(acc));
+    }
+}
+
+// Per-row bound E_i >= |Dhat^2_ij - D^2_ij| for every j (FP32 screen):
+//   |error| <= g (s_i + s_j + 2 m_i m_j),  g = gamma_{d+4} with unit roundoff
+// 2^-23 (valid for any faithful rounding and any accumulation order), s the
+// squared norms, m the norms; j's terms are replaced by their maxima.  A 2^-10
+// relative margin covers the rounding of this evaluation itself.
+__global__ __launch_bounds__(256) void k_row_bound(const float *__restrict__ sq, int64_t n, int64_t d,
+                                                   const uint32_t *__restrict__ sqmax_bits, float *__restrict__ E) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double u = 1.0 / 8388608.0;  // 2^-23
+    const double du = (double)(d + 4) * u;
+    const double g = du / (1.0 - du);
+    const double smax = (double)__uint_as_float(*sqmax_bits);
+    const double si = (double)sq[i];
+    double e = g * (si + smax + 2.0 * sqrt(si) * sqrt(smax));
+    e *= (1.0 + 1.0 / 1024.0);
+    E[i] = (float)e * (1.0f + 1.0f / 1024.0f);
+}
+
+__global__ void k_iota_comp(int32_t *comp, int64_t n, int64_t n_pad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += (int64_t)gridDim.x * blockDim.x)
+        comp[i] = i < n ? (int32_t)i : -1;
+}
+
+// ------------------------------------------------------------------ screen (FP32 VALU)
+
+// Row block of GT rows per workgroup; each thread owns an 8 x 8 micro-tile:
+// rows ty + 16 r, columns tx + 16 c (r, c < 8).
+__global__ __launch_bounds__(GB) void k_screen_f32(const float *__restrict__ XT, int64_t n, int64_t n_pad, int d_pad,
+                                                   const float *__restrict__ sq, const float *__restrict__ E,
+                                                   const int32_t *__restrict__ comp, float *__restrict__ best_out,
+                                                   int32_t *__restrict__ ccnt, int32_t *__restrict__ cj,
+                                                   float *__restrict__ cv) {
+    __shared__ float As[GK][GT];
+    __shared__ float Bs[GK][GT];
+    __shared__ uint32_t rowbest[GT];
+    __shared__ int32_t rowcnt[GT];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * GT;
+
+    float si[8], ei[8];
+    int ci[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        int64_t i = i0 + ty + 16 * r;
+        si[r] = sq[i];
+        ci[r] = comp[i];
+        ei[r] = ci[r] >= 0 ? 2.0f * E[i] : 0.0f;
+    }
+    if (tid < GT) {
+        rowbest[tid] = __float_as_uint(F_INF);
+        rowcnt[tid] = 0;
+    }
+    __syncthreads();
+
+    for (int64_t j0 = 0; j0 < n_pad; j0 += GT) {
+        float acc[8][8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[r][c] = 0.0f;
+
+        for (int k0 = 0; k0 < d_pad; k0 += GK) {
+#pragma unroll
+            for (int q = 0; q < (GK * GT) / GB; ++q) {
+                int idx = tid + GB * q;
+                int k = idx / GT, ii = idx % GT;
+                As[k][ii] = XT[(int64_t)(k0 + k) * n_pad + i0 + ii];
+                Bs[k][ii] = XT[(int64_t)(k0 + k) * n_pad + j0 + ii];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < GK; ++k) {
+                float a[8], b[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) a[r] = As[k][ty + 16 * r];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) b[c] = Bs[k][tx + 16 * c];
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
+            }
+            __syncthreads();
+        }
+
+        // epilogue: masked Dhat^2, per-row tile minimum, then capture
+        float sj[8];
+        int cjv[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int64_t j = j0 + tx + 16 * c;
+            sj[c] = sq[j];
+            cjv[c] = comp[j];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            float m = F_INF;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                float t = fmaxf(fmaf(-2.0f, acc[r][c], si[r] + sj[c]), 0.0f);
+                bool ok = ci[r] >= 0 && cjv[c] >= 0 && cjv[c] != ci[r];
+                acc[r][c] = ok ? t : F_INF;
+                m = fminf(m, acc[r][c]);
+            }
+            if (m < F_INF) atomicMin(&rowbest[ty + 16 * r], __float_as_uint(m));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            float b = __uint_as_float(rowbest[ty + 16 * r]);
+            float thr = (b + ei[r]) * 1.000001f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                float v = acc[r][c];
+                if (v <= thr && v < F_INF) {
+                    int pos = atomicAdd(&rowcnt[ty + 16 * r], 1);
+                    if (pos < CAND) {
+                        int64_t i = i0 + ty + 16 * r;
+                        cj[i * CAND + pos] = (int32_t)(j0 + tx + 16 * c);
+                        cv[i * CAND + pos] = v;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < GT) {
+        int64_t i = i0 + tid;
+        if (i < n) {
+            best_out[i] = __uint_as_float(rowbest[tid]);
+            ccnt[i] = rowcnt[tid];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ exact distances
+
+// FP32 exact-recheck distance: lane l sums (x_t - y_t)^2 for t = l, l+64, ...
+// with fused multiply-adds, then an xor butterfly over the 64 lanes.  Every
+// lane returns the same value, which depends only on the unordered pair.
+__device__ inline float d2_f32_wave(const float *__restrict__ x, const float *__restrict__ y, int64_t d) {
+    const int lane = threadIdx.x & 63;
+    float acc = 0.0f;
+    for (int64_t t = lane; t < d; t += 64) {
+        float df = x[t] - y[t];
+        acc = fmaf(df, df, acc);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    return acc;
+}
+
+// FP64 exact-recheck distance: left to right over t, each product and sum
+// rounded separately (the library is compiled without FP contraction).
+__device__ inline double d2_f64_lane(const float *__restrict__ x, const float *__restrict__ y, int64_t d) {
+    double s = 0.0;
+    for (int64_t t = 0; t < d; ++t) {
+        double df = (double)x[t] - (double)y[t];
+        double p = df * df;
+        s = s + p;
+    }
+    return s;
+}
+
+__device__ inline bool key_less(double d2a, int ja, double d2b, int jb) {
+    return d2a < d2b || (d2a == d2b && ja < jb);
+}
+
+// U_c = min over rows i of c of (b_i + E_i), rounded up.
+__global__ void k_comp_ub(const float *__restrict__ best, const float *__restrict__ E,
+                          const int32_t *__restrict__ comp, int64_t n, uint32_t *__restrict__ comp_ub) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float b = best[i];
+    if (!(b < F_INF)) return;
+    float u = (b + E[i]) * 1.000001f;
+    atomicMin(&comp_ub[comp[i]], __float_as_uint(u));
+}
+
+// One wave per row: exact D^2 of the row's surviving candidates, lightest by
+// (D^2, j).  Rows that cannot reach their component's bound are skipped; rows
+// whose candidate list overflowed are queued for the rescan.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_recheck(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                 const float *__restrict__ best, const float *__restrict__ E,
+                                                 const int32_t *__restrict__ comp,
+                                                 const uint32_t *__restrict__ comp_ub, const int32_t *__restrict__ ccnt,
+                                                 const int32_t *__restrict__ cj, const float *__restrict__ cv,
+                                                 double *__restrict__ rb_d2, int32_t *__restrict__ rb_j,
+                                                 int32_t *__restrict__ ovf, int32_t *__restrict__ counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const float b = best[i];
+    const float e = E[i];
+    const uint32_t ubits = comp_ub[comp[i]];
+    double out_d2 = __builtin_huge_val();
+    int out_j = -1;
+    if (b < F_INF && ubits != U32_MAX) {
+        const float U = __uint_as_float(ubits);
+        const float lower = b - e - (b + e) * (1.0f / 1048576.0f);
+        if (lower <= U) {
+            const int cnt = ccnt[i];
+            if (cnt > CAND) {
+                if (lane == 0) {
+                    int p = atomicAdd(&counters[C_OVF], 1);
+                    ovf[p] = (int32_t)i;
+                }
+                if (lane == 0) {
+                    rb_d2[i] = out_d2;
+                    rb_j[i] = out_j;
+                }
+                return;
+            }
+            const float thr = fminf(b + 2.0f * e, U + e) * 1.000001f;
+            const float *xi = X + i * ld;
+            int evaluated = 0;
+            if (!F64) {
+                for (int q = 0; q < cnt; ++q) {
+                    float v = cv[i * CAND + q];
+                    if (!(v <= thr)) continue;
+                    int j = cj[i * CAND + q];
+                    double d2 = (double)d2_f32_wave(xi, X + (int64_t)j * ld, d);
+                    ++evaluated;
+                    if (key_less(d2, j, out_d2, out_j)) {
+                        out_d2 = d2;
+                        out_j = j;
+                    }
+                }
+            } else {
+                double my = __builtin_huge_val();
+                int myj = -1;
+                if (lane < cnt) {
+                    float v = cv[i * CAND + lane];
+                    if (v <= thr) {
+                        myj = cj[i * CAND + lane];
+                        my = d2_f64_lane(xi, X + (int64_t)myj * ld, d);
+                    }
+                }
+                evaluated = __popcll(__ballot(myj >= 0));
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    double od = __shfl_xor(my, off, 64);
+                    int oj = __shfl_xor(myj, off, 64);
+                    if (oj >= 0 && (myj < 0 || key_less(od, oj, my, myj))) {
+                        my = od;
+                        myj = oj;
+                    }
+                }
+                out_d2 = my;
+                out_j = myj;
+            }
+            if (lane == 0 && evaluated) atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
+        }
+    }
+    if (lane == 0) {
+        rb_d2[i] = out_d2;
+        rb_j[i] = out_j;
+    }
+}
+
+// Exact re-evaluation of an overflowed row against every point of another
+// component: one workgroup per queued row, four waves over the columns.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_rescan(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                const int32_t *__restrict__ comp, const int32_t *__restrict__ ovf,
+                                                int32_t *__restrict__ counters, double *__restrict__ rb_d2,
+                                                int32_t *__restrict__ rb_j) {
+    __shared__ double s_d2[256];
+    __shared__ int s_j[256];
+    const int novf = counters[C_OVF];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int r = blockIdx.x; r < novf; r += gridDim.x) {
+        const int64_t i = ovf[r];
+        const int ci = comp[i];
+        const float *xi = X + i * ld;
+        double bd = __builtin_huge_val();
+        int bj = -1;
+        if (!F64) {
+            for (int64_t j = w; j < n; j += 4) {
+                if (comp[j] == ci) continue;
+                double d2 = (double)d2_f32_wave(xi, X + j * ld, d);
+                if (key_less(d2, (int)j, bd, bj)) {
+                    bd = d2;
+                    bj = (int)j;
+                }
+            }
+        } else {
+            for (int64_t j = threadIdx.x; j < n; j += 256) {
+                if (comp[j] == ci) continue;
+                double d2 = d2_f64_lane(xi, X + j * ld, d);
+                if (key_less(d2, (int)j, bd, bj)) {
+                    bd = d2;
+                    bj = (int)j;
+                }
+            }
+        }
+        s_d2[threadIdx.x] = bd;
+        s_j[threadIdx.x] = bj;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 1; q < 256; ++q)
+                if (s_j[q] >= 0 && (bj < 0 || key_less(s_d2[q], s_j[q], bd, bj))) {
+                    bd = s_d2[q];
+                    bj = s_j[q];
+                }
+            rb_d2[i] = bd;
+            rb_j[i] = bj;
+            atomicAdd((unsigned long long *)&counters[C_RESCAN], 1ull);
+        }
+        __syncthreads();
+    }
+    (void)lane;
+}
+
+// ------------------------------------------------------------------ contraction
+
+__global__ void k_comp_min1(const double *__restrict__ rb_d2, const int32_t *__restrict__ rb_j,
+                            const int32_t *__restrict__ comp, int64_t n, unsigned long long *__restrict__ ck1) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || rb_j[i] < 0) return;
+    atomicMin(&ck1[comp[i]], (unsigned long long)__double_as_longlong(rb_d2[i]));
+}
+
+__global__ void k_comp_min2(const double *__restrict__ rb_d2, const int32_t *__restrict__ rb_j,
+                            const int32_t *__restrict__ comp, int64_t n, const unsigned long long *__restrict__ ck1,
+                            unsigned long long *__restrict__ ck2) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || rb_j[i] < 0) return;
+    const int c = comp[i];
+    if ((unsigned long long)__double_as_longlong(rb_d2[i]) != ck1[c]) return;
+    const uint32_t j = (uint32_t)rb_j[i];
+    const uint32_t lo = (uint32_t)i < j ? (uint32_t)i : j;
+    const uint32_t hi = (uint32_t)i < j ? j : (uint32_t)i;
+    atomicMin(&ck2[c], ((unsigned long long)lo << 32) | hi);
+}
+
+__global__ void k_hook1(const unsigned long long *__restrict__ ck2, const int32_t *__restrict__ comp, int64_t ncomp,
+                        int32_t *__restrict__ cpar, int32_t *__restrict__ counters) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncomp) return;
+    unsigned long long key = ck2[c];
+    if (key == U64_MAX) {
+        atomicExch(&counters[C_NOEDGE], 1);
+        cpar[c] = (int32_t)c;
+        return;
+    }
+    int a = (int)(key >> 32), b = (int)(key & 0xFFFFFFFFu);
+    int ca = comp[a], cb = comp[b];
+    cpar[c] = (ca == (int)c) ? cb : ca;
+}
+
+__global__ void k_hook2(const unsigned long long *__restrict__ ck2, const int32_t *__restrict__ cpar, int64_t ncomp,
+                        int32_t *__restrict__ npar, int32_t *__restrict__ eu, int32_t *__restrict__ ev,
+                        int64_t edge_cap, int32_t *__restrict__ counters) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncomp) return;
+    int o = cpar[c];
+    if (o == (int)c) {
+        npar[c] = (int32_t)c;
+        return;
+    }
+    if (cpar[o] == (int)c && (int)c < o) {  // mutual pair: the smaller id is the root
+        npar[c] = (int32_t)c;
+        return;
+    }
+    npar[c] = o;
+    unsigned long long key = ck2[c];
+    int p = atomicAdd(&counters[C_EDGES], 1);
+    if (p < edge_cap) {  // more than n-1 edges would be an internal error, reported by the host
+        eu[p] = (int32_t)(key >> 32);
+        ev[p] = (int32_t)(key & 0xFFFFFFFFu);
+    }
+}
+
+__global__ void k_jump(int32_t *__restrict__ npar, int64_t ncomp) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncomp) return;
+    npar[c] = npar[npar[c]];
+}
+
+__global__ void k_isroot(const int32_t *__restrict__ npar, int64_t ncomp, int32_t *__restrict__ flag) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncomp) return;
+    flag[c] = npar[c] == (int32_t)c ? 1 : 0;
+}
+
+__global__ void k_relabel(int32_t *__restrict__ comp, int64_t n, const int32_t *__restrict__ npar,
+                          const int32_t *__restrict__ newid) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    comp[i] = newid[npar[comp[i]]];
+}
+
+// Component sizes and the sum of their squares (timing only: the screen of a
+// round must cover (n^2 - sum |c|^2) / 2 unordered pairs).
+__global__ void k_comp_sizes(const int32_t *__restrict__ comp, int64_t n, int32_t *__restrict__ size) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&size[comp[i]], 1);
+}
+
+__global__ __launch_bounds__(1024) void k_sum_squares(const int32_t *__restrict__ size, int64_t m,
+                                                      int32_t *__restrict__ counters) {
+    __shared__ unsigned long long s[1024];
+    unsigned long long acc = 0;
+    for (int64_t c = threadIdx.x; c < m; c += 1024) acc += (unsigned long long)size[c] * (unsigned long long)size[c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *(unsigned long long *)&counters[C_SUMSQ] = s[0];
+}
+
+// ------------------------------------------------------------------ FP64 lengths and rooting
+
+// Length of each tree edge: sqrt of the FP64 left-to-right sum of squared
+// coordinate differences.
+__global__ void k_refine(const float *__restrict__ X, int64_t d, int64_t ld, const int32_t *__restrict__ eu,
+                         const int32_t *__restrict__ ev, int64_t m, double *__restrict__ elen) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    elen[e] = sqrt(d2_f64_lane(X + (int64_t)eu[e] * ld, X + (int64_t)ev[e] * ld, d));
+}
+
+__global__ void k_degree(const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
+                         int32_t *__restrict__ deg) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    atomicAdd(&deg[eu[e]], 1);
+    atomicAdd(&deg[ev[e]], 1);
+}
+
+__global__ void k_fill_adj(const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
+                           const int32_t *__restrict__ off, int32_t *__restrict__ cursor, int32_t *__restrict__ adj,
+                           int32_t *__restrict__ adje) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    int a = eu[e], b = ev[e];
+    int pa = off[a] + atomicAdd(&cursor[a], 1);
+    adj[pa] = b;
+    adje[pa] = (int32_t)e;
+    int pb = off[b] + atomicAdd(&cursor[b], 1);
+    adj[pb] = a;
+    adje[pb] = (int32_t)e;
+}
+
+// Level-synchronous BFS from vertex 0 in one workgroup: parent, FP64 length
+// of the parent edge, and the depth.
+__global__ __launch_bounds__(1024) void k_bfs_root0(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                                                    const int32_t *__restrict__ adje, const double *__restrict__ elen,
+                                                    int64_t n, int32_t *__restrict__ parent,
+                                                    double *__restrict__ length, int32_t *__restrict__ depth,
+                                                    int32_t *__restrict__ fa, int32_t *__restrict__ fb,
+                                                    int32_t *__restrict__ counters) {
+    __shared__ int32_t s_next;
+    __shared__ int32_t s_size;
+    __shared__ int32_t s_seen;
+    if (threadIdx.x == 0) {
+        parent[0] = -1;
+        length[0] = 0.0;
+        depth[0] = 0;
+        fa[0] = 0;
+        s_size = 1;
+        s_next = 0;
+        s_seen = 1;
+    }
+    __syncthreads();
+    int32_t *cur = fa, *nxt = fb;
+    while (true) {
+        const int size = s_size;
+        if (size == 0) break;
+        for (int q = threadIdx.x; q < size; q += blockDim.x) {
+            const int v = cur[q];
+            const int pv = parent[v];
+            const int dv = depth[v];
+            for (int a = off[v]; a < off[v + 1]; ++a) {
+                const int w = adj[a];
+                if (w == pv) continue;
+                if (atomicCAS(&depth[w], -1, dv + 1) != -1) continue;  // visited (only on a malformed edge set)
+                parent[w] = v;
+                length[w] = elen[adje[a]];
+                nxt[atomicAdd(&s_next, 1)] = w;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_size = s_next;
+            s_seen += s_next;
+            s_next = 0;
+        }
+        __syncthreads();
+        int32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (threadIdx.x == 0) counters[C_SEEN] = s_seen;
+}
+
+// Deterministic FP64 sum of length[1..n) (one workgroup, fixed tree).
+__global__ __launch_bounds__(1024) void k_sum_lengths(const double *__restrict__ length, int64_t n,
+                                                      double *__restrict__ out) {
+    __shared__ double s[1024];
+    double acc = 0.0;
+    for (int64_t v = 1 + threadIdx.x; v < n; v += 1024) acc = acc + length[v];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] = s[threadIdx.x] + s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+// ------------------------------------------------------------------ plan
+
+struct MstPlan {
+    int64_t n, d, ld, n_pad, d_pad;
+    int32_t precision;
+    float *XT;
+    float *sq, *E, *best, *cv;
+    uint32_t *sqmax, *comp_ub;
+    int32_t *comp, *ccnt, *cj, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev, *ovf;
+    int32_t *deg, *aoff, *cursor, *adj, *adje, *fa, *fb, *depth;
+    double *rb_d2, *elen, *wsum;
+    unsigned long long *ck1, *ck2;
+    int32_t *counters;
+
+    void carve(Arena &a) {
+        XT = a.take<float>((size_t)d_pad * n_pad);
+        sq = a.take<float>(n_pad);
+        E = a.take<float>(n);
+        best = a.take<float>(n);
+        cv = a.take<float>((size_t)n * CAND);
+        sqmax = a.take<uint32_t>(1);
+        comp_ub = a.take<uint32_t>(n);
+        comp = a.take<int32_t>(n_pad);
+        ccnt = a.take<int32_t>(n);
+        cj = a.take<int32_t>((size_t)n * CAND);
+        rb_j = a.take<int32_t>(n);
+        cpar = a.take<int32_t>(n);
+        npar = a.take<int32_t>(n);
+        flag = a.take<int32_t>(n);
+        newid = a.take<int32_t>(n);
+        eu = a.take<int32_t>(n);
+        ev = a.take<int32_t>(n);
+        ovf = a.take<int32_t>(n);
+        deg = a.take<int32_t>(n + 1);
+        aoff = a.take<int32_t>(n + 1);
+        cursor = a.take<int32_t>(n);
+        adj = a.take<int32_t>(2 * n);
+        adje = a.take<int32_t>(2 * n);
+        fa = a.take<int32_t>(n);
+        fb = a.take<int32_t>(n);
+        depth = a.take<int32_t>(n);
+        rb_d2 = a.take<double>(n);
+        elen = a.take<double>(n);
+        wsum = a.take<double>(1);
+        ck1 = a.take<unsigned long long>(n);
+        ck2 = a.take<unsigned long long>(n);
+        counters = a.take<int32_t>(C_COUNT);
+    }
+};
+
+MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
+    MstPlan p{};
+    p.n = n;
+    p.d = d;
+    p.ld = ld;
+    p.precision = precision;
+    p.n_pad = (n + GT - 1) / GT * GT;
+    p.d_pad = (d + GK - 1) / GK * GK;
+    return p;
+}
+
+size_t plan_bytes(MstPlan p) {
+    Arena a;
+    p.carve(a);
+    return a.used;
+}
+
+void run_mst(MstPlan &P, const float *X, int32_t recheck, int32_t *parent, double *length, iso_mst_info *info,
+             hipStream_t s) {
+    const int64_t n = P.n, d = P.d, ld = P.ld;
+    const bool timed = timing().enabled != 0;
+    EventPair whole(timed), scr(timed);
+    whole.start(s);
+    fill<int32_t>(P.counters, 0, C_COUNT, s);
+    fill<uint32_t>(P.sqmax, 0u, 1, s);
+    fill<float>(P.sq, 0.0f, P.n_pad, s);
+    hipLaunchKernelGGL(k_norms, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.sq, P.sqmax, P.counters);
+    LAUNCH_CHECK();
+    int32_t h_nonfinite = 0;
+    HIP_CHECK(hipMemcpyAsync(&h_nonfinite, P.counters + C_NONFINITE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(h_nonfinite == 0, ISO_ERR_NONFINITE, "points contain a NaN or infinite coordinate");
+
+    hipLaunchKernelGGL(k_row_bound, dim3(grid_for(n, 256)), dim3(256), 0, s, P.sq, n, d, P.sqmax, P.E);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_transpose_pad, dim3((unsigned)(P.n_pad / 64), (unsigned)((P.d_pad + 63) / 64)), dim3(256), 0, s,
+                       X, n, d, ld, P.n_pad, P.d_pad, P.XT);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_iota_comp, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.comp, n, P.n_pad);
+    LAUNCH_CHECK();
+
+    int64_t ncomp = n;
+    int rounds = 0;
+    const int blocks_rows = (int)(P.n_pad / GT);
+    while (ncomp > 1) {
+        ++rounds;
+        ISO_REQUIRE(rounds <= 64, ISO_ERR_INTERNAL, "Boruvka did not converge");
+        if (timed) {
+            fill<int32_t>(P.flag, 0, ncomp, s);
+            hipLaunchKernelGGL(k_comp_sizes, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.flag);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(1024), 0, s, P.flag, ncomp, P.counters);
+            LAUNCH_CHECK();
+        }
+        scr.start(s);
+        hipLaunchKernelGGL(k_screen_f32, dim3(blocks_rows), dim3(GB), 0, s, P.XT, n, P.n_pad, (int)P.d_pad, P.sq, P.E,
+                           P.comp, P.best, P.ccnt, P.cj, P.cv);
+        LAUNCH_CHECK();
+        scr.stop(s);
+        fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
+        hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.E, P.comp, n, P.comp_ub);
+        LAUNCH_CHECK();
+        fill<int32_t>(P.counters + C_OVF, 0, 1, s);
+        if (recheck == ISO_RECHECK_FP64) {
+            hipLaunchKernelGGL(k_recheck<true>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best, P.E, P.comp,
+                               P.comp_ub, P.ccnt, P.cj, P.cv, P.rb_d2, P.rb_j, P.ovf, P.counters);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_rescan<true>, dim3(1024), dim3(256), 0, s, X, n, d, ld, P.comp, P.ovf, P.counters,
+                               P.rb_d2, P.rb_j);
+        } else {
+            hipLaunchKernelGGL(k_recheck<false>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best, P.E,
+                               P.comp, P.comp_ub, P.ccnt, P.cj, P.cv, P.rb_d2, P.rb_j, P.ovf, P.counters);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_rescan<false>, dim3(1024), dim3(256), 0, s, X, n, d, ld, P.comp, P.ovf, P.counters,
+                               P.rb_d2, P.rb_j);
+        }
+        LAUNCH_CHECK();
+        fill<unsigned long long>(P.ck1, U64_MAX, ncomp, s);
+        fill<unsigned long long>(P.ck2, U64_MAX, ncomp, s);
+        hipLaunchKernelGGL(k_comp_min1, dim3(grid_for(n, 256)), dim3(256), 0, s, P.rb_d2, P.rb_j, P.comp, n, P.ck1);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_comp_min2, dim3(grid_for(n, 256)), dim3(256), 0, s, P.rb_d2, P.rb_j, P.comp, n, P.ck1,
+                           P.ck2);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_hook1, dim3(grid_for(ncomp, 256)), dim3(256), 0, s, P.ck2, P.comp, ncomp, P.cpar,
+                           P.counters);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_hook2, dim3(grid_for(ncomp, 256)), dim3(256), 0, s, P.ck2, P.cpar, ncomp, P.npar, P.eu,
+                           P.ev, n - 1, P.counters);
+        LAUNCH_CHECK();
+        for (int it = 0; it <= ceil_log2(ncomp); ++it) {
+            hipLaunchKernelGGL(k_jump, dim3(grid_for(ncomp, 256)), dim3(256), 0, s, P.npar, ncomp);
+            LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_isroot, dim3(grid_for(ncomp, 256)), dim3(256), 0, s, P.npar, ncomp, P.flag);
+        LAUNCH_CHECK();
+        exclusive_scan_i32(P.flag, P.newid, ncomp, P.counters + C_NCOMP, s);
+        hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.npar, P.newid);
+        LAUNCH_CHECK();
+        int32_t h[5];
+        HIP_CHECK(hipMemcpyAsync(h, P.counters, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        ISO_REQUIRE(h[C_NOEDGE] == 0, ISO_ERR_INTERNAL, "a component found no outgoing edge in round %d", rounds);
+        ISO_REQUIRE(h[C_NCOMP] >= 1 && h[C_NCOMP] < ncomp, ISO_ERR_INTERNAL,
+                    "Boruvka round %d did not contract (%lld -> %d components)", rounds, (long long)ncomp, h[C_NCOMP]);
+        if (timed) {
+            unsigned long long sumsq = 0;
+            HIP_CHECK(hipMemcpy(&sumsq, P.counters + C_SUMSQ, sizeof(sumsq), hipMemcpyDeviceToHost));
+            iso_timing &T = timing();
+            T.screen_launches += 1;
+            T.screen_ms += scr.elapsed_ms();
+            T.screen_pairs += 0.5 * ((double)n * (double)n - (double)sumsq);
+            T.screen_dim = (double)P.d_pad;
+        }
+        ncomp = h[C_NCOMP];
+    }
+
+    const int64_t m = n - 1;
+    int32_t h_edges = 0;
+    HIP_CHECK(hipMemcpyAsync(&h_edges, P.counters + C_EDGES, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(h_edges == m, ISO_ERR_INTERNAL, "MST has %d edges, expected %lld", h_edges, (long long)m);
+
+    hipLaunchKernelGGL(k_refine, dim3(grid_for(m, 256)), dim3(256), 0, s, X, d, ld, P.eu, P.ev, m, P.elen);
+    LAUNCH_CHECK();
+    fill<int32_t>(P.deg, 0, n + 1, s);
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, m, P.deg);
+    LAUNCH_CHECK();
+    exclusive_scan_i32(P.deg, P.aoff, n + 1, nullptr, s);
+    fill<int32_t>(P.cursor, 0, n, s);
+    hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, m, P.aoff, P.cursor, P.adj,
+                       P.adje);
+    LAUNCH_CHECK();
+    fill<int32_t>(P.depth, -1, n, s);
+    hipLaunchKernelGGL(k_bfs_root0, dim3(1), dim3(1024), 0, s, P.aoff, P.adj, P.adje, P.elen, n, parent, length,
+                       P.depth, P.fa, P.fb, P.counters);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_lengths, dim3(1), dim3(1024), 0, s, length, n, P.wsum);
+    LAUNCH_CHECK();
+    int32_t h_seen = 0;
+    HIP_CHECK(hipMemcpyAsync(&h_seen, P.counters + C_SEEN, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(h_seen == n, ISO_ERR_INTERNAL, "tree BFS reached %d of %lld vertices", h_seen, (long long)n);
+    whole.stop(s);
+    if (timed) {
+        timing().mst_calls += 1;
+        timing().mst_ms += whole.elapsed_ms();
+    }
+    if (info) {
+        long long cand = 0, resc = 0;
+        HIP_CHECK(hipMemcpyAsync(&cand, P.counters + C_CAND, sizeof(cand), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&resc, P.counters + C_RESCAN, sizeof(resc), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&info->mst_weight, P.wsum, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        info->rounds = rounds;
+        info->reserved0 = 0;
+        info->candidates = cand;
+        info->rescanned_rows = resc;
+    }
+}
+
+}  // namespace
+
+}  // namespace iso
+
+using namespace iso;
+
+extern "C" iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_t *bytes) {
+    return guarded([&] {
+        ISO_REQUIRE(bytes != nullptr, ISO_ERR_INVALID_ARG, "bytes is NULL");
+        ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - GT, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+        ISO_REQUIRE(d >= 1, ISO_ERR_INVALID_ARG, "d = %lld < 1", (long long)d);
+        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16, ISO_ERR_INVALID_ARG,
+                    "unknown precision %d", precision);
+        *bytes = plan_bytes(make_plan(n, d, d, precision));
+    });
+}
+
+extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t precision, int32_t recheck,
+                              int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes,
+                              void *stream) {
+    return guarded([&] {
+        ISO_REQUIRE(X && parent && length, ISO_ERR_INVALID_ARG, "X, parent and length must be non-NULL");
+        ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - GT, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+        ISO_REQUIRE(d >= 1, ISO_ERR_INVALID_ARG, "d = %lld < 1", (long long)d);
+        ISO_REQUIRE(ld >= d, ISO_ERR_INVALID_ARG, "ld = %lld < d = %lld", (long long)ld, (long long)d);
+        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16, ISO_ERR_INVALID_ARG,
+                    "unknown precision %d", precision);
+        ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
+                    "unknown recheck %d", recheck);
+        require_device();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        MstPlan P = make_plan(n, d, ld, precision);
+        const size_t need = plan_bytes(P);
+        ScopedWorkspace owned;
+        if (ws == nullptr) {
+            owned.stream = s;
+            HIP_CHECK(hipMallocAsync(&owned.ptr, need, s));
+            ws = owned.ptr;
+            ws_bytes = need;
+        }
+        ISO_REQUIRE(ws_bytes >= need, ISO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+        Arena a{static_cast<char *>(ws), 0, ws_bytes};
+        P.carve(a);
+        run_mst(P, X, recheck, parent, length, info, s);
+    });
+}
+
+extern "C" const char *iso_last_error(void) { return iso::get_error(); }
+
+extern "C" const char *iso_version(void) { return "isoclust 0.1 (gfx950)"; }

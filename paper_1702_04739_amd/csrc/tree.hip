@@ -1,0 +1,752 @@
+// tree.hip -- optimal k-subpartition of a weighted tree on gfx950
+// (Sec. 2.2 Algorithms 1-2, parallelised depth by depth as in Sec. 3.6 /
+// Algorithm 4).
+//
+// Algorithm 1 visits the vertices in x-order (depth descending, id ascending)
+// and either cuts a vertex from its parent, joins it to its parent, or
+// discards it.  Each vertex's decision depends only on its children, so all
+// vertices of one depth are decided together (Sec. 3.2), deepest level first.
+// A vertex pulls its children's contributions in ascending id order, which is
+// exactly the order in which the sequential algorithm folds them into the
+// parent, so the FP64 arithmetic is the sequential algorithm's.
+//
+// Bisection (Algorithm 2) is speculative: one device pass evaluates the 63
+// midpoints of the next six bisection levels at once (one wave lane per
+// midpoint), then walks the six answers, so the sequence of brackets is
+// exactly the sequential one.  The bracket lives on the device; the host only
+// polls a done flag between batches of passes.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace iso {
+
+namespace {
+
+constexpr int SPEC_LEVELS = 6;
+constexpr int M = 64;                       // lanes per vertex in a speculative pass
+constexpr int NCAND = (1 << SPEC_LEVELS) - 1;  // 63 midpoints per pass
+constexpr int NARROW = 16;                  // levels with <= NARROW vertices run inside one workgroup
+constexpr int PASS_BATCH = 4;
+
+struct TreeState {
+    double alpha, beta;
+    double alpha0_raw, beta0_raw, alpha0, beta0;
+    double phi_sum, phi_min, om_sum, om_min, p_sum, p_min;
+    double sigma;
+    double i_k;
+    int32_t done, iters, passes, jstar;
+    int32_t ncuts, max_iters, k, bad;
+    int32_t maxdepth, pad0, pad1, pad2;
+};
+
+template <class T>
+__global__ void k_fill_t(T *p, T v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+void fill_t(T *p, T v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = grid_for(n, 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_t<T>, dim3(g), dim3(256), 0, s, p, v, n);
+    LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ validation and depth
+
+// anc = parent, dist = 1 (0 at the root); flags malformed entries.
+__global__ void k_check_tree(const int32_t *__restrict__ parent, const double *__restrict__ length, int64_t n,
+                             int32_t root, int32_t *__restrict__ anc, int32_t *__restrict__ dist,
+                             TreeState *__restrict__ st) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t p = parent[v];
+    bool bad;
+    if (v == root) {
+        bad = (p != -1);
+        dist[v] = 0;
+        anc[v] = -1;
+    } else {
+        double L = length[v];
+        bad = (p < 0 || p >= n || p == v || !(L >= 0.0) || !isfinite(L));
+        dist[v] = 1;
+        anc[v] = bad ? -1 : p;
+    }
+    if (bad) atomicOr(&st->bad, 1);
+}
+
+__global__ void k_depth_jump(const int32_t *__restrict__ anc_in, const int32_t *__restrict__ dist_in, int64_t n,
+                             int32_t *__restrict__ anc_out, int32_t *__restrict__ dist_out) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t a = anc_in[v];
+    if (a >= 0) {
+        dist_out[v] = dist_in[v] + dist_in[a];
+        anc_out[v] = anc_in[a];
+    } else {
+        dist_out[v] = dist_in[v];
+        anc_out[v] = -1;
+    }
+}
+
+// Cycle check (an ancestor pointer that never reached the root) and max depth.
+__global__ void k_depth_finish(const int32_t *__restrict__ anc, const int32_t *__restrict__ dist, int64_t n,
+                               TreeState *__restrict__ st) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (anc[v] != -1) atomicOr(&st->bad, 2);
+    atomicMax(&st->maxdepth, dist[v]);
+}
+
+// Sort keys: x-order key (maxdepth - depth) and child-list key (parent + 1).
+__global__ void k_sort_keys(const int32_t *__restrict__ depth, const int32_t *__restrict__ parent, int64_t n,
+                            int32_t maxdepth, uint32_t *__restrict__ okey, uint32_t *__restrict__ oval,
+                            uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval, int32_t *__restrict__ nchild) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    okey[v] = (uint32_t)(maxdepth - depth[v]);
+    oval[v] = (uint32_t)v;
+    int32_t p = parent[v];
+    ckey[v] = (uint32_t)(p + 1);
+    cval[v] = (uint32_t)v;
+    if (p >= 0) atomicAdd(&nchild[p], 1);
+}
+
+// level_start[L] = first x-order index of level key L (L = maxdepth - depth).
+__global__ void k_level_starts(const uint32_t *__restrict__ okey_sorted, int64_t n, int32_t maxdepth,
+                               int32_t *__restrict__ level_start) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t key = okey_sorted[i];
+    if (i == 0 || okey_sorted[i - 1] != key) level_start[key] = (int32_t)i;
+    if (i == 0) level_start[maxdepth + 1] = (int32_t)n;
+}
+
+// ------------------------------------------------------------------ weights (eqs. 2.1-2.2)
+
+__global__ void k_phi(const int32_t *__restrict__ parent, const double *__restrict__ length, int64_t n,
+                      const TreeState *__restrict__ st, int phi_kind, double *__restrict__ phi,
+                      double *__restrict__ p0) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const double sigma = st->sigma;
+    double f = 0.0;
+    if (parent[v] >= 0) {
+        const double dist = length[v];
+        f = (phi_kind == ISO_PHI_GAUSS_SQ) ? exp(-(dist * dist) / (2.0 * sigma * sigma)) : exp(-dist / sigma);
+    }
+    phi[v] = f;
+    p0[v] = 0.0;
+}
+
+// omega0(v): sum over tree neighbours w of v in ascending w of phi(vw),
+// starting from +0.0 (children come sorted by id; the parent is merged in).
+__global__ void k_omega_tree(const int32_t *__restrict__ parent, const double *__restrict__ phi,
+                             const uint32_t *__restrict__ kids, const int32_t *__restrict__ koff, int64_t n,
+                             double *__restrict__ om0) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t p = parent[v];
+    double s = 0.0;
+    bool parent_done = p < 0;
+    for (int32_t a = koff[v]; a < koff[v + 1]; ++a) {
+        const int32_t c = (int32_t)kids[a];
+        if (!parent_done && p < c) {
+            s = s + phi[v];
+            parent_done = true;
+        }
+        s = s + phi[c];
+    }
+    if (!parent_done) s = s + phi[v];
+    om0[v] = s;
+}
+
+// Sums and minima of phi (tree edges), omega0 and p0; bracket of Algorithm 2.
+__global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ parent, const double *__restrict__ phi,
+                                                const double *__restrict__ om0, const double *__restrict__ p0,
+                                                int64_t n, int bracket, TreeState *__restrict__ st) {
+    __shared__ double s_sum[3][1024];
+    __shared__ double s_min[3][1024];
+    double ps = 0.0, os = 0.0, qs = 0.0;
+    double pm = __builtin_huge_val(), om = __builtin_huge_val(), qm = __builtin_huge_val();
+    for (int64_t v = threadIdx.x; v < n; v += 1024) {
+        if (parent[v] >= 0) {
+            ps = ps + phi[v];
+            pm = fmin(pm, phi[v]);
+        }
+        os = os + om0[v];
+        om = fmin(om, om0[v]);
+        qs = qs + p0[v];
+        qm = fmin(qm, p0[v]);
+    }
+    s_sum[0][threadIdx.x] = ps;
+    s_sum[1][threadIdx.x] = os;
+    s_sum[2][threadIdx.x] = qs;
+    s_min[0][threadIdx.x] = pm;
+    s_min[1][threadIdx.x] = om;
+    s_min[2][threadIdx.x] = qm;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 3; ++q) {
+                s_sum[q][threadIdx.x] = s_sum[q][threadIdx.x] + s_sum[q][threadIdx.x + w];
+                s_min[q][threadIdx.x] = fmin(s_min[q][threadIdx.x], s_min[q][threadIdx.x + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->phi_sum = s_sum[0][0];
+        st->om_sum = s_sum[1][0];
+        st->p_sum = s_sum[2][0];
+        st->phi_min = s_min[0][0];
+        st->om_min = s_min[1][0];
+        st->p_min = s_min[2][0];
+        const double a0 = (st->phi_min + st->p_min) / st->om_sum;
+        const double b0 = (st->phi_sum + st->p_sum) / st->om_min;
+        st->alpha0_raw = a0;
+        st->beta0_raw = b0;
+        double a, b;
+        if (bracket == ISO_BRACKET_PAPER) {
+            a = a0;
+            b = nextafter(b0, __builtin_huge_val());
+        } else {
+            int e;
+            if (a0 > 0.0) {
+                frexp(a0, &e);
+                a = ldexp(1.0, e - 1);
+            } else {
+                a = 0.0;
+            }
+            frexp(b0, &e);
+            b = ldexp(1.0, e);
+        }
+        st->alpha0 = a;
+        st->beta0 = b;
+        st->alpha = a;
+        st->beta = b;
+        st->done = 0;
+        st->iters = 0;
+        st->passes = 0;
+        if (!(b0 > 0.0) || !isfinite(b0)) st->bad |= 4;
+    }
+}
+
+// ------------------------------------------------------------------ Algorithm 1, one vertex
+
+struct DPArgs {
+    const int32_t *order;
+    const int32_t *level_start;
+    const int32_t *parent;
+    const uint32_t *kids;
+    const int32_t *koff;
+    const double *phi, *om0, *p0;
+    const double *Nvals;
+    double *cw, *cp;
+    int32_t *cnt;
+    uint8_t *cut, *joined;
+    double *num, *den;
+    TreeState *st;
+};
+
+// Decision of Algorithm 1 for vertex v at threshold Nvals[m].  The vertex's
+// (omega, p) start from (omega0, p0) and absorb the children's contributions
+// in ascending child id; its own contribution to its parent is
+//   cut:     p += phi(e)           (the edge joins the boundary),
+//   join:    omega += omega(x), p += p(x),
+//   discard: p += phi(e).
+template <int MM, bool REC>
+__device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
+    const double N = A.Nvals[m];
+    double w = A.om0[v];
+    double p = A.p0[v];
+    int32_t c_cnt = 0;
+    for (int32_t a = A.koff[v]; a < A.koff[v + 1]; ++a) {
+        const int64_t c = (int64_t)A.kids[a] * MM + m;
+        p = p + A.cp[c];
+        w = w + A.cw[c];
+        c_cnt += A.cnt[c];
+    }
+    const bool is_root = A.parent[v] < 0;
+    const double fe = is_root ? 0.0 : A.phi[v];
+    const double lhs = fe + p;
+    const double rhs = N * w;
+    double op, ow;
+    int iscut = 0, isjoin = 0;
+    if (lhs <= rhs) {
+        iscut = 1;
+        op = fe;
+        ow = 0.0;
+    } else if (!is_root && (p - fe) < rhs) {
+        isjoin = 1;
+        op = p;
+        ow = w;
+    } else {
+        op = fe;
+        ow = 0.0;
+    }
+    const int64_t o = (int64_t)v * MM + m;
+    A.cp[o] = op;
+    A.cw[o] = ow;
+    A.cnt[o] = c_cnt + iscut;
+    if (REC) {
+        A.cut[v] = (uint8_t)iscut;
+        A.joined[v] = (uint8_t)isjoin;
+        A.num[v] = lhs;
+        A.den[v] = w;
+    }
+}
+
+// One wide level: MM consecutive threads per vertex.
+template <int MM, bool REC>
+__global__ __launch_bounds__(256) void k_dp_level(DPArgs A, int32_t lo, int32_t hi) {
+    if (!REC && A.st->done) return;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = lo + gid / MM;
+    const int m = (int)(gid % MM);
+    if (q >= hi) return;
+    dp_vertex<MM, REC>(A, A.order[q], m);
+}
+
+// A run of narrow levels [L0, L1) inside one workgroup, a barrier between levels.
+template <int MM, bool REC>
+__global__ __launch_bounds__(1024) void k_dp_narrow(DPArgs A, int32_t L0, int32_t L1) {
+    if (!REC && A.st->done) return;
+    const int m = threadIdx.x % MM;
+    const int slot = threadIdx.x / MM;
+    const int slots = blockDim.x / MM;
+    for (int32_t L = L0; L < L1; ++L) {
+        const int32_t lo = A.level_start[L], hi = A.level_start[L + 1];
+        for (int32_t q = lo + slot; q < hi; q += slots) dp_vertex<MM, REC>(A, A.order[q], m);
+        __syncthreads();
+    }
+}
+
+// Midpoints of the next SPEC_LEVELS bisection steps, heap order: node q over
+// bracket (lo, hi) has midpoint (lo+hi)/2, left child (lo, mid) (answer YES),
+// right child (mid, hi) (answer NO).
+__global__ void k_make_cands(TreeState *__restrict__ st, double *__restrict__ Nvals) {
+    if (threadIdx.x != 0 || st->done) return;
+    double lo[NCAND], hi[NCAND];
+    lo[0] = st->alpha;
+    hi[0] = st->beta;
+    for (int q = 0; q < NCAND; ++q) {
+        const double mid = (lo[q] + hi[q]) / 2.0;
+        Nvals[q] = mid;
+        if (2 * q + 2 < NCAND) {
+            lo[2 * q + 1] = lo[q];
+            hi[2 * q + 1] = mid;
+            lo[2 * q + 2] = mid;
+            hi[2 * q + 2] = hi[q];
+        }
+    }
+    Nvals[NCAND] = st->beta;  // the spare lane re-checks beta
+}
+
+// Walks the answers of one pass: YES (>= k cuts) => beta = mid, else alpha = mid.
+__global__ void k_resolve(TreeState *__restrict__ st, const double *__restrict__ Nvals,
+                          const int32_t *__restrict__ cnt, int32_t root) {
+    if (threadIdx.x != 0 || st->done) return;
+    st->passes += 1;
+    int q = 0;
+    for (int l = 0; l < SPEC_LEVELS; ++l) {
+        const double a = st->alpha, b = st->beta;
+        const double mid = (a + b) / 2.0;
+        if (mid <= a || mid >= b || st->iters >= st->max_iters) {
+            st->done = 1;
+            return;
+        }
+        if (mid != Nvals[q]) {  // cannot happen: the candidates were built from the same bracket
+            st->bad |= 8;
+            st->done = 1;
+            return;
+        }
+        const bool yes = cnt[(int64_t)root * M + q] >= st->k;
+        if (yes) {
+            st->beta = mid;
+            q = 2 * q + 1;
+        } else {
+            st->alpha = mid;
+            q = 2 * q + 2;
+        }
+        st->iters += 1;
+    }
+    if (cnt[(int64_t)root * M + NCAND] < st->k) st->bad |= 16;  // beta must stay YES
+    const double a = st->alpha, b = st->beta;
+    const double mid = (a + b) / 2.0;
+    if (mid <= a || mid >= b || st->iters >= st->max_iters) st->done = 1;
+}
+
+__global__ void k_set_final_N(TreeState *__restrict__ st, double *__restrict__ Nvals) {
+    if (threadIdx.x == 0) Nvals[0] = st->beta;
+}
+
+// ------------------------------------------------------------------ labels (Algorithm 4)
+
+__global__ void k_cut_in_xorder(const int32_t *__restrict__ order, const uint8_t *__restrict__ cut, int64_t n,
+                                int32_t *__restrict__ cf) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cf[i] = cut[order[i]];
+}
+
+// Cluster index of each vertex that is one of the first k cuts in x-order
+// (exclusive scan of Cut), -1 otherwise; rep pointer = parent if joined.
+__global__ void k_cluster_index(const int32_t *__restrict__ order, const uint8_t *__restrict__ cut,
+                                const int32_t *__restrict__ rank, const uint8_t *__restrict__ joined,
+                                const int32_t *__restrict__ parent, int64_t n, int32_t k,
+                                int32_t *__restrict__ cidx, int32_t *__restrict__ rep) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = order[i];
+    cidx[v] = (cut[v] && rank[i] < k) ? rank[i] : -1;
+    rep[v] = joined[v] ? parent[v] : v;
+}
+
+__global__ void k_rep_jump(const int32_t *__restrict__ rin, int64_t n, int32_t *__restrict__ rout) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    rout[v] = rin[rin[v]];
+}
+
+__global__ void k_labels(const int32_t *__restrict__ rep, const int32_t *__restrict__ cidx,
+                         const double *__restrict__ num, const double *__restrict__ den, int64_t n,
+                         int32_t *__restrict__ labels, double *__restrict__ cl_num, double *__restrict__ cl_den,
+                         int32_t *__restrict__ cl_size) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t l = cidx[rep[v]];
+    labels[v] = l;
+    if (l >= 0) atomicAdd(&cl_size[l], 1);
+    const int32_t j = cidx[v];
+    if (j >= 0) {
+        cl_num[j] = num[v];
+        cl_den[j] = den[v];
+    }
+}
+
+// i_k = max_j num_j / den_j, jstar = smallest argmax; cuts at beta.
+__global__ void k_final_cost(const double *__restrict__ cl_num, const double *__restrict__ cl_den, int32_t k,
+                             const int32_t *__restrict__ cnt, int32_t root, TreeState *__restrict__ st) {
+    if (threadIdx.x != 0) return;
+    double best = -1.0;
+    int js = 0;
+    for (int j = 0; j < k; ++j) {
+        const double c = cl_num[j] / cl_den[j];
+        if (c > best) {
+            best = c;
+            js = j;
+        }
+    }
+    st->i_k = best;
+    st->jstar = js;
+    st->ncuts = cnt[root];
+}
+
+// ------------------------------------------------------------------ plan
+
+struct SubPlan {
+    int64_t n;
+    int32_t k;
+    int32_t *anc0, *anc1, *dist0, *dist1;
+    uint32_t *okey, *oval, *ckey, *cval, *tk, *tv;
+    int32_t *nchild, *koff, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp;
+    double *phi, *om0, *p0, *cw, *cp, *Nvals, *num, *den, *cl_num_tmp, *cl_den_tmp;
+    uint8_t *cut, *joined;
+    TreeState *st;
+    void *sort_scratch, *sel_scratch;
+
+    void carve(Arena &a) {
+        anc0 = a.take<int32_t>(n);
+        anc1 = a.take<int32_t>(n);
+        dist0 = a.take<int32_t>(n);
+        dist1 = a.take<int32_t>(n);
+        okey = a.take<uint32_t>(n);
+        oval = a.take<uint32_t>(n);
+        ckey = a.take<uint32_t>(n);
+        cval = a.take<uint32_t>(n);
+        tk = a.take<uint32_t>(n);
+        tv = a.take<uint32_t>(n);
+        nchild = a.take<int32_t>(n + 1);
+        koff = a.take<int32_t>(n + 1);
+        level_start = a.take<int32_t>(n + 2);
+        cf = a.take<int32_t>(n);
+        rank = a.take<int32_t>(n);
+        cidx = a.take<int32_t>(n);
+        rep0 = a.take<int32_t>(n);
+        rep1 = a.take<int32_t>(n);
+        cnt = a.take<int32_t>((size_t)n * M);
+        cl_size_tmp = a.take<int32_t>(k);
+        phi = a.take<double>(n);
+        om0 = a.take<double>(n);
+        p0 = a.take<double>(n);
+        cw = a.take<double>((size_t)n * M);
+        cp = a.take<double>((size_t)n * M);
+        Nvals = a.take<double>(M);
+        num = a.take<double>(n);
+        den = a.take<double>(n);
+        cl_num_tmp = a.take<double>(k);
+        cl_den_tmp = a.take<double>(k);
+        cut = a.take<uint8_t>(n);
+        joined = a.take<uint8_t>(n);
+        st = a.take<TreeState>(1);
+        sort_scratch = a.take<char>(radix_sort_scratch_bytes(n));
+        sel_scratch = a.take<char>(radix_select_scratch_bytes());
+    }
+};
+
+size_t sub_plan_bytes(int64_t n, int32_t k) {
+    SubPlan p{};
+    p.n = n;
+    p.k = k;
+    Arena a;
+    p.carve(a);
+    return a.used;
+}
+
+int bits_for(int64_t maxval) {
+    int b = 0;
+    while (b < 32 && (int64_t(1) << b) <= maxval) ++b;
+    return b < 1 ? 1 : b;
+}
+
+// Launches Algorithm 1 over all levels, deepest first, grouping runs of
+// narrow levels into single-workgroup launches.
+template <int MM, bool REC>
+void launch_levels(const DPArgs &A, const std::vector<int32_t> &ls, int32_t maxdepth, hipStream_t s) {
+    const int narrow_cap = (REC ? 1024 : NARROW);
+    int32_t L = 0;
+    while (L <= maxdepth) {
+        const int32_t width = ls[L + 1] - ls[L];
+        if (width <= narrow_cap) {
+            int32_t L1 = L;
+            while (L1 <= maxdepth && ls[L1 + 1] - ls[L1] <= narrow_cap) ++L1;
+            hipLaunchKernelGGL((k_dp_narrow<MM, REC>), dim3(1), dim3(1024), 0, s, A, L, L1);
+            LAUNCH_CHECK();
+            L = L1;
+        } else {
+            const int64_t threads = (int64_t)width * MM;
+            hipLaunchKernelGGL((k_dp_level<MM, REC>), dim3(grid_for(threads, 256)), dim3(256), 0, s, A, ls[L], ls[L + 1]);
+            LAUNCH_CHECK();
+            ++L;
+        }
+    }
+}
+
+void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t root, double sigma,
+             const iso_sub_opts &o, int32_t *labels, double *i_k, double *cl_num, double *cl_den, int32_t *cl_size,
+             iso_sub_info *info, hipStream_t s) {
+    const int64_t n = P.n;
+    const int32_t k = P.k;
+    const unsigned gn = grid_for(n, 256);
+    const bool timed = timing().enabled != 0;
+    EventPair whole(timed);
+    whole.start(s);
+    // state
+    TreeState h0{};
+    h0.max_iters = o.max_iters > 0 ? o.max_iters : 2000;
+    h0.k = k;
+    h0.sigma = sigma;
+    HIP_CHECK(hipMemcpyAsync(P.st, &h0, sizeof(h0), hipMemcpyHostToDevice, s));
+
+    // validation + depth by pointer jumping
+    hipLaunchKernelGGL(k_check_tree, dim3(gn), dim3(256), 0, s, parent, length, n, root, P.anc0, P.dist0, P.st);
+    LAUNCH_CHECK();
+    int32_t *ai = P.anc0, *ao = P.anc1, *di = P.dist0, *dout = P.dist1;
+    for (int it = 0; it <= ceil_log2(n); ++it) {
+        hipLaunchKernelGGL(k_depth_jump, dim3(gn), dim3(256), 0, s, ai, di, n, ao, dout);
+        LAUNCH_CHECK();
+        std::swap(ai, ao);
+        std::swap(di, dout);
+    }
+    hipLaunchKernelGGL(k_depth_finish, dim3(gn), dim3(256), 0, s, ai, di, n, P.st);
+    LAUNCH_CHECK();
+    TreeState h{};
+    HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(!(h.bad & 1), ISO_ERR_INVALID_ARG,
+                "parent/length malformed: parent[root] must be -1, other parents in [0,n) and not self, lengths finite "
+                "and >= 0");
+    ISO_REQUIRE(!(h.bad & 2), ISO_ERR_INVALID_ARG, "parent array has a cycle (not a tree rooted at %d)", root);
+    const int32_t maxdepth = h.maxdepth;
+    const int32_t *depth = di;
+
+    // x-order and child lists (stable radix sorts)
+    fill_t<int32_t>(P.nchild, 0, n + 1, s);
+    hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, s, depth, parent, n, maxdepth, P.okey, P.oval, P.ckey,
+                       P.cval, P.nchild);
+    LAUNCH_CHECK();
+    radix_sort_pairs_u32(P.okey, P.oval, P.tk, P.tv, n, bits_for(maxdepth), P.sort_scratch, s);
+    radix_sort_pairs_u32(P.ckey, P.cval, P.tk, P.tv, n, bits_for(n), P.sort_scratch, s);
+    exclusive_scan_i32(P.nchild, P.koff, n + 1, nullptr, s);
+    hipLaunchKernelGGL(k_level_starts, dim3(gn), dim3(256), 0, s, P.okey, n, maxdepth, P.level_start);
+    LAUNCH_CHECK();
+    const int32_t *order = reinterpret_cast<const int32_t *>(P.oval);
+    const uint32_t *kids = P.cval + 1;  // the root (key 0) sorts first
+
+    // sigma, phi, omega0, stats, bracket
+    if (sigma == 0.0) {
+        radix_select_f64(length, parent, n, (n - 2) / 2, &P.st->sigma, P.sel_scratch, s);
+    }
+    hipLaunchKernelGGL(k_phi, dim3(gn), dim3(256), 0, s, parent, length, n, P.st, o.phi, P.phi, P.p0);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_omega_tree, dim3(gn), dim3(256), 0, s, parent, P.phi, kids, P.koff, n, P.om0);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, parent, P.phi, P.om0, P.p0, n, o.bracket, P.st);
+    LAUNCH_CHECK();
+    std::vector<int32_t> ls(maxdepth + 2);
+    HIP_CHECK(hipMemcpyAsync(ls.data(), P.level_start, sizeof(int32_t) * (maxdepth + 2), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(h.sigma > 0.0 && std::isfinite(h.sigma), ISO_ERR_INVALID_ARG,
+                "sigma must be positive (the median edge length is %g)", h.sigma);
+    ISO_REQUIRE(!(h.bad & 4), ISO_ERR_INVALID_ARG, "degenerate weights: the bracket of the bisection is not finite");
+
+    DPArgs A{};
+    A.order = order;
+    A.level_start = P.level_start;
+    A.parent = parent;
+    A.kids = kids;
+    A.koff = P.koff;
+    A.phi = P.phi;
+    A.om0 = P.om0;
+    A.p0 = P.p0;
+    A.Nvals = P.Nvals;
+    A.cw = P.cw;
+    A.cp = P.cp;
+    A.cnt = P.cnt;
+    A.cut = P.cut;
+    A.joined = P.joined;
+    A.num = P.num;
+    A.den = P.den;
+    A.st = P.st;
+
+    // speculative bisection passes
+    const int max_batches = (h.max_iters / SPEC_LEVELS) / PASS_BATCH + 3;
+    int batches = 0;
+    while (true) {
+        for (int b = 0; b < PASS_BATCH; ++b) {
+            hipLaunchKernelGGL(k_make_cands, dim3(1), dim3(64), 0, s, P.st, P.Nvals);
+            LAUNCH_CHECK();
+            launch_levels<M, false>(A, ls, maxdepth, s);
+            hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, s, P.st, P.Nvals, P.cnt, root);
+            LAUNCH_CHECK();
+        }
+        HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        ISO_REQUIRE(!(h.bad & 8), ISO_ERR_INTERNAL, "bisection candidates out of step");
+        ISO_REQUIRE(!(h.bad & 16), ISO_ERR_INTERNAL, "decision at beta turned NO during bisection");
+        if (h.done) break;
+        ISO_REQUIRE(++batches < max_batches, ISO_ERR_INTERNAL, "bisection did not terminate");
+    }
+
+    // final decision at beta, recording Cut and eta (Algorithm 4)
+    hipLaunchKernelGGL(k_set_final_N, dim3(1), dim3(64), 0, s, P.st, P.Nvals);
+    LAUNCH_CHECK();
+    launch_levels<1, true>(A, ls, maxdepth, s);
+    hipLaunchKernelGGL(k_cut_in_xorder, dim3(gn), dim3(256), 0, s, order, P.cut, n, P.cf);
+    LAUNCH_CHECK();
+    exclusive_scan_i32(P.cf, P.rank, n, nullptr, s);
+    hipLaunchKernelGGL(k_cluster_index, dim3(gn), dim3(256), 0, s, order, P.cut, P.rank, P.joined, parent, n, k, P.cidx,
+                       P.rep0);
+    LAUNCH_CHECK();
+    int32_t *ri = P.rep0, *ro = P.rep1;
+    for (int it = 0; it <= ceil_log2(maxdepth + 1); ++it) {
+        hipLaunchKernelGGL(k_rep_jump, dim3(gn), dim3(256), 0, s, ri, n, ro);
+        LAUNCH_CHECK();
+        std::swap(ri, ro);
+    }
+    double *cn = cl_num ? cl_num : P.cl_num_tmp;
+    double *cd = cl_den ? cl_den : P.cl_den_tmp;
+    int32_t *cs = cl_size ? cl_size : P.cl_size_tmp;
+    fill_t<int32_t>(cs, 0, k, s);
+    hipLaunchKernelGGL(k_labels, dim3(gn), dim3(256), 0, s, ri, P.cidx, P.num, P.den, n, labels, cn, cd, cs);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_final_cost, dim3(1), dim3(64), 0, s, cn, cd, k, P.cnt, root, P.st);
+    LAUNCH_CHECK();
+    HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(h.ncuts >= k, ISO_ERR_INTERNAL, "decision at beta found %d < k = %d cuts", h.ncuts, k);
+    whole.stop(s);
+    if (timed) {
+        timing().sub_calls += 1;
+        timing().sub_ms += whole.elapsed_ms();
+        timing().sub_passes += h.passes;
+    }
+    *i_k = h.i_k;
+    if (info) {
+        info->sigma = h.sigma;
+        info->alpha0_raw = h.alpha0_raw;
+        info->beta0_raw = h.beta0_raw;
+        info->alpha0 = h.alpha0;
+        info->beta0 = h.beta0;
+        info->alpha = h.alpha;
+        info->beta = h.beta;
+        info->i_k = h.i_k;
+        const double tt = std::log2(2.0 * h.om_sum * h.om_sum * (h.beta0_raw - h.alpha0_raw)) -
+                          std::log2(h.phi_min + h.p_min);
+        info->t_paper = std::isfinite(tt) ? (int32_t)std::ceil(tt) : -1;
+        info->iters = h.iters;
+        info->passes = h.passes;
+        info->max_depth = maxdepth;
+        info->jstar = h.jstar;
+        info->reserved0 = 0;
+    }
+}
+
+}  // namespace
+
+}  // namespace iso
+
+using namespace iso;
+
+extern "C" iso_status iso_sub_workspace_size(int64_t n, int32_t k, size_t *bytes) {
+    return guarded([&] {
+        ISO_REQUIRE(bytes != nullptr, ISO_ERR_INVALID_ARG, "bytes is NULL");
+        ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - 2, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+        ISO_REQUIRE(k >= 2 && k <= n, ISO_ERR_INVALID_ARG, "k = %d outside [2, n]", k);
+        *bytes = sub_plan_bytes(n, k);
+    });
+}
+
+extern "C" iso_status iso_subpartition(const int32_t *parent, const double *length, int64_t n, int32_t root, int32_t k,
+                                       double sigma, const iso_sub_opts *opts, int32_t *labels, double *i_k,
+                                       double *cluster_num, double *cluster_den, int32_t *cluster_size,
+                                       iso_sub_info *info, void *ws, size_t ws_bytes, void *stream) {
+    return guarded([&] {
+        ISO_REQUIRE(parent && length && labels && i_k, ISO_ERR_INVALID_ARG,
+                    "parent, length, labels and i_k must be non-NULL");
+        ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - 2, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+        ISO_REQUIRE(k >= 2 && k <= n, ISO_ERR_INVALID_ARG, "k = %d outside [2, n]", k);
+        ISO_REQUIRE(root >= 0 && root < n, ISO_ERR_INVALID_ARG, "root = %d outside [0, n)", root);
+        ISO_REQUIRE(sigma >= 0.0 && std::isfinite(sigma), ISO_ERR_INVALID_ARG, "sigma = %g must be finite and >= 0",
+                    sigma);
+        iso_sub_opts o{ISO_OMEGA_TREE, ISO_PHI_EXP_DIST, ISO_BRACKET_POW2, 2000};
+        if (opts) o = *opts;
+        ISO_REQUIRE(o.omega == ISO_OMEGA_TREE, ISO_ERR_INVALID_ARG, "unsupported omega reading %d", o.omega);
+        ISO_REQUIRE(o.phi == ISO_PHI_EXP_DIST || o.phi == ISO_PHI_GAUSS_SQ, ISO_ERR_INVALID_ARG, "unknown phi %d", o.phi);
+        ISO_REQUIRE(o.bracket == ISO_BRACKET_POW2 || o.bracket == ISO_BRACKET_PAPER, ISO_ERR_INVALID_ARG,
+                    "unknown bracket %d", o.bracket);
+        require_device();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        SubPlan P{};
+        P.n = n;
+        P.k = k;
+        const size_t need = sub_plan_bytes(n, k);
+        ScopedWorkspace owned;
+        if (ws == nullptr) {
+            owned.stream = s;
+            HIP_CHECK(hipMallocAsync(&owned.ptr, need, s));
+            ws = owned.ptr;
+            ws_bytes = need;
+        }
+        ISO_REQUIRE(ws_bytes >= need, ISO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+        Arena a{static_cast<char *>(ws), 0, ws_bytes};
+        P.carve(a);
+        run_sub(P, parent, length, root, sigma, o, labels, i_k, cluster_num, cluster_den, cluster_size, info, s);
+    });
+}
