@@ -146,6 +146,29 @@ iso_status iso_subpartition(const int32_t *parent, const double *length, int64_t
                             double *cluster_num, double *cluster_den, int32_t *cluster_size, iso_sub_info *info,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* Device bytes iso_backward needs as workspace. */
+iso_status iso_backward_workspace_size(int64_t n, size_t *bytes /* host */);
+
+/* Adjoint of W = total length of the tree's edges and of I = cost (eq. 2.4,
+ * tree-degree omega, p = 0) of cluster `jstar` of `labels`, with the tree and
+ * the subpartition held fixed (a subgradient of MISO_k at the returned
+ * subpartition when jstar attains it):
+ *   gX = gW dW/dX + gI dI/dX,   *gsigma = gI dI/dsigma.
+ * Edge lengths are recomputed from X in FP64.  Each vertex sums the terms of
+ * its incident edges (parent edge, then children by ascending id) in FP64, so
+ * the result is deterministic; an edge of length 0 contributes a zero
+ * subgradient.
+ *   X       [n*ld] FP32 points;  parent [n] tree (one or more roots = -1);
+ *   labels  [n] cluster of each vertex (-1 = residual), as from iso_subpartition;
+ *   sigma   > 0, the scale used in phi (eq. 2.1);  phi_kind ISO_PHI_*;
+ *   gX      [n*ldg] out, FP32;  gsigma, I_out (host, I_out nullable) out.
+ * Errors: null pointers, n < 2, d < 1, ld < d, ldg < d, sigma <= 0, unknown
+ * phi_kind, non-finite gW/gI, parent entries outside [-1, n) (INVALID_ARG). */
+iso_status iso_backward(const float *X, int64_t n, int64_t d, int64_t ld, const int32_t *parent,
+                        const int32_t *labels, int32_t jstar, double sigma, int32_t phi_kind, double gW, double gI,
+                        float *gX, int64_t ldg, double *gsigma /* host */, double *I_out /* host */, void *ws,
+                        size_t ws_bytes, void *stream);
+
 /* Optional phase timing, for benchmarks: while enabled, iso_mst brackets every
  * screen launch with hipEvents on its stream and counts the unordered pairs
  * of points in different components that the launch must cover, and both entry

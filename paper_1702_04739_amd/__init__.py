@@ -15,7 +15,7 @@ import ctypes
 
 from . import _lib
 
-__all__ = ["mst", "isoperimetric_subpartition", "cluster", "version"]
+__all__ = ["mst", "isoperimetric_subpartition", "cluster", "adjoint", "MSTIsoCost", "version"]
 
 
 def _torch():
@@ -115,3 +115,85 @@ def cluster(points, k: int, sigma: float | None = None, precision: str = "fp32",
     parent, length, minfo = mst(points, precision=precision, recheck=recheck)
     labels, ik, sinfo = isoperimetric_subpartition(parent, length, k, sigma=sigma, **kw)
     return labels, ik, {"mst": minfo, "sub": sinfo, "parent": parent, "length": length}
+
+
+def adjoint(points, parent, labels, jstar: int, sigma: float, gW: float = 1.0, gI: float = 1.0, phi: str = "exp"):
+    """Gradient of gW * W + gI * I with respect to the points and sigma, where W
+    is the total length of the tree (parent) and I the cost (eq. 2.4) of
+    cluster ``jstar`` of ``labels``, tree and subpartition held fixed.
+
+    Returns (grad_points float32[n, d], grad_sigma float, I float)."""
+    torch = _torch()
+    _require_cuda(points, "points", torch.float32)
+    _require_cuda(parent, "parent", torch.int32)
+    _require_cuda(labels, "labels", torch.int32)
+    if points.stride(1) != 1:
+        points = points.contiguous()
+    parent = parent.contiguous()
+    labels = labels.contiguous()
+    n, d = points.shape
+    lib = _lib.load()
+    need = ctypes.c_size_t(0)
+    _lib.check(lib.iso_backward_workspace_size(n, ctypes.byref(need)), "iso_backward_workspace_size")
+    dev = points.device
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    gX = torch.empty((n, d), dtype=torch.float32, device=dev)
+    gs = ctypes.c_double(0.0)
+    I = ctypes.c_double(0.0)
+    rc = lib.iso_backward(ctypes.c_void_p(points.data_ptr()), n, d, points.stride(0),
+                          ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                          int(jstar), float(sigma), _lib.PHI[phi], float(gW), float(gI), ctypes.c_void_p(gX.data_ptr()),
+                          d, ctypes.byref(gs), ctypes.byref(I), ctypes.c_void_p(ws.data_ptr()), int(need.value),
+                          _stream_ptr(dev))
+    _lib.check(rc, "iso_backward")
+    return gX, float(gs.value), float(I.value)
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class MSTIsoCost(torch.autograd.Function):
+        """(W, i_k, labels) = MSTIsoCost.apply(points, sigma, k, precision, recheck, phi).
+
+        W is the total MST length and i_k = MISO_k of the tree with phi at scale
+        ``sigma`` (a 0-d tensor or float).  The backward pass holds the tree and
+        the optimal subpartition fixed and differentiates W and the cost of the
+        cluster attaining i_k with respect to the points and sigma."""
+
+        @staticmethod
+        def forward(ctx, points, sigma, k, precision="fp32", recheck="fp32", phi="exp"):
+            sig = float(sigma)
+            parent, length, minfo = mst(points.detach(), precision=precision, recheck=recheck)
+            labels, ik, sinfo = isoperimetric_subpartition(parent, length, int(k), sigma=sig, phi=phi)
+            ctx.save_for_backward(points.detach(), parent, labels)
+            ctx.jstar = sinfo["jstar"]
+            ctx.sigma = sig
+            ctx.phi = phi
+            ctx.sigma_is_tensor = isinstance(sigma, torch.Tensor)
+            ctx.mark_non_differentiable(labels)
+            W = torch.tensor(minfo["mst_weight"], dtype=torch.float64, device=points.device)
+            I = torch.tensor(ik, dtype=torch.float64, device=points.device)
+            return W, I, labels
+
+        @staticmethod
+        def backward(ctx, gW, gI, _glabels):
+            points, parent, labels = ctx.saved_tensors
+            gw = float(gW) if gW is not None else 0.0
+            gi = float(gI) if gI is not None else 0.0
+            gX, gs, _ = adjoint(points, parent, labels, ctx.jstar, ctx.sigma, gw, gi, ctx.phi)
+            gsig = torch.tensor(gs, dtype=torch.float64, device=points.device) if ctx.sigma_is_tensor else None
+            return gX, gsig, None, None, None, None
+
+    return MSTIsoCost
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+MSTIsoCost = _LazyAutograd()

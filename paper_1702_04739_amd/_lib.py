@@ -24,8 +24,9 @@ PHI = {"exp": 0, "gauss_sq": 1}
 BRACKET = {"pow2": 0, "paper": 1}
 
 # Every symbol include/isoclust.h declares.
-EXPORTS = ["iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition", "iso_timing_enable",
-           "iso_timing_read", "iso_last_error", "iso_version"]
+EXPORTS = ["iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
+           "iso_backward_workspace_size", "iso_backward", "iso_timing_enable", "iso_timing_read", "iso_last_error",
+           "iso_version"]
 
 
 class IsoError(RuntimeError):
@@ -79,7 +80,11 @@ def load(build_if_missing: bool = True):
     lib.iso_sub_workspace_size.argtypes = [I64, I32, ctypes.POINTER(SZ)]
     lib.iso_subpartition.argtypes = [P, P, I64, I32, I32, D, ctypes.POINTER(SubOpts), P, ctypes.POINTER(D), P, P, P,
                                      ctypes.POINTER(SubInfo), P, SZ, P]
-    for f in ("iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition"):
+    lib.iso_backward_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
+    lib.iso_backward.argtypes = [P, I64, I64, I64, P, P, I32, D, I32, D, D, P, I64, ctypes.POINTER(D),
+                                 ctypes.POINTER(D), P, SZ, P]
+    for f in ("iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
+              "iso_backward_workspace_size", "iso_backward"):
         getattr(lib, f).restype = ctypes.c_int32
     lib.iso_timing_enable.argtypes = [I32]
     lib.iso_timing_enable.restype = ctypes.c_int32

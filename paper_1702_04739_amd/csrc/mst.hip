@@ -22,19 +22,16 @@
 // parent list (Sec. 3.3) rooted at 0.
 #include <cfloat>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
-#include "common.hpp"
+#include "screen.hpp"
 
 namespace iso {
 
 namespace {
 
-constexpr int GT = 128;        // screen tile edge (rows and columns)
-constexpr int GK = 16;         // K chunk staged through LDS
-constexpr int GB = 256;        // threads per screen workgroup
-constexpr int CAND = 32;       // candidate slots per row
-constexpr float F_INF = __builtin_huge_valf();
+constexpr int GT = SCR_ROWS;   // row padding granule
 constexpr uint32_t U32_MAX = 0xFFFFFFFFu;
 constexpr uint64_t U64_MAX = ~0ull;
 
@@ -45,6 +42,7 @@ enum Counter : int {
     C_OVF = 3,          // overflow rows this round
     C_NOEDGE = 4,       // a component without an outgoing edge (internal error)
     C_SEEN = 5,         // vertices reached by the rooting BFS
+    C_GATHER = 6,       // rows queued for the gathered pass this round
     C_CAND = 8,         // candidates re-evaluated (int64 at [8..9])
     C_RESCAN = 10,      // rows rescanned (int64 at [10..11])
     C_SUMSQ = 12,       // sum over components of size^2 (int64 at [12..13], timing only)
@@ -68,182 +66,132 @@ void fill(T *p, T v, int64_t n, hipStream_t s) {
     LAUNCH_CHECK();
 }
 
-// FP32 k-major padded copy XT[t][i] (t < d_pad, i < n_pad), zeros outside.
-__global__ __launch_bounds__(256) void k_transpose_pad(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
-                                                       int64_t n_pad, int64_t d_pad, float *__restrict__ XT) {
-    __shared__ float tile[64][65];
-    const int64_t i0 = (int64_t)blockIdx.x * 64, t0 = (int64_t)blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-    for (int r = ty; r < 64; r += 4) {
-        int64_t i = i0 + r, t = t0 + tx;
-        tile[r][tx] = (i < n && t < d) ? X[i * ld + t] : 0.0f;
+// ------------------------------------------------------------------ screen representation
+
+constexpr int COL_RB = 1024;   // rows per partial column sum
+
+// Partial per-coordinate sums (FP64) and maxima of |x| over row blocks;
+// non-finite check.
+__global__ __launch_bounds__(256) void k_colstats_partial(const float *__restrict__ X, int64_t n, int64_t d,
+                                                          int64_t ld, double *__restrict__ psum,
+                                                          float *__restrict__ pmax, int32_t *__restrict__ counters) {
+    const int64_t t = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    const int64_t rb = blockIdx.x;
+    if (t >= d) return;
+    const int64_t lo = rb * COL_RB, hi = lo + COL_RB < n ? lo + COL_RB : n;
+    double s = 0.0;
+    float m = 0.0f;
+    bool bad = false;
+    for (int64_t i = lo; i < hi; ++i) {
+        const float x = X[i * ld + t];
+        bad |= !isfinite(x);
+        s = s + (double)x;
+        m = fmaxf(m, fabsf(x));
     }
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        int64_t t = t0 + r, i = i0 + tx;
-        if (t < d_pad && i < n_pad) XT[t * n_pad + i] = tile[tx][r];
-    }
+    psum[rb * d + t] = s;
+    pmax[rb * d + t] = m;
+    if (bad) atomicExch(&counters[C_NONFINITE], 1);
 }
 
-// Squared norm per row (FP32, fixed order), nonfinite check, global max.
-__global__ __launch_bounds__(256) void k_norms(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
-                                               float *__restrict__ sq, uint32_t *__restrict__ sqmax_bits,
-                                               int32_t *__restrict__ counters) {
+// Centre mu_t: the coordinate mean rounded to the bf16 spacing at the
+// coordinate's largest magnitude (so centring keeps values that sit on that
+// grid, e.g. q/256, on it); 0 beyond d.
+__global__ void k_colstats_final(const double *__restrict__ psum, const float *__restrict__ pmax, int64_t nrb,
+                                 int64_t n, int64_t d, int64_t d_pad, float *__restrict__ mu) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d_pad) return;
+    if (t >= d) {
+        mu[t] = 0.0f;
+        return;
+    }
+    double s = 0.0;
+    float m = 0.0f;
+    for (int64_t rb = 0; rb < nrb; ++rb) {
+        s = s + psum[rb * d + t];
+        m = fmaxf(m, pmax[rb * d + t]);
+    }
+    if (!(m > 0.0f)) {
+        mu[t] = 0.0f;
+        return;
+    }
+    int e;
+    frexp((double)m, &e);                      // m = f 2^e, f in [0.5, 1)
+    const double grid = ldexp(1.0, e - 8);     // bf16 spacing at m
+    mu[t] = (float)(rint((s / (double)n) / grid) * grid);
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// One wave per (padded) row: x' = rep(x - mu) written row-major, s = fl(||x'||^2)
+// (fixed order), and upper bounds r >= ||x'||, e >= ||x' - (x - mu)||.
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                   int64_t n_pad, int64_t d_pad, const float *__restrict__ mu,
+                                                   void *__restrict__ Xr, float *__restrict__ sq,
+                                                   float *__restrict__ rn, float *__restrict__ re,
+                                                   uint32_t *__restrict__ rmax_bits, uint32_t *__restrict__ emax_bits) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= n) return;
-    const float *x = X + row * ld;
-    float acc = 0.0f;
-    bool bad = false;
-    for (int64_t t = lane; t < d; t += 64) {
-        float v = x[t];
-        bad |= !isfinite(v);
-        acc = fmaf(v, v, acc);
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_pad) return;
+    float s = 0.0f;
+    double m2 = 0.0, e2 = 0.0;
+    for (int64_t t = lane; t < d_pad; t += 64) {
+        float xv = 0.0f, y = 0.0f;
+        if (i < n && t < d) {
+            xv = X[i * ld + t];
+            y = xv - mu[t];
+        }
+        float yr;
+        if (BF16) {
+            const uint16_t b = bf16_rne(y);
+            static_cast<uint16_t *>(Xr)[i * d_pad + t] = b;
+            yr = bf16_to_f32(b);
+        } else {
+            static_cast<float *>(Xr)[i * d_pad + t] = y;
+            yr = y;
+        }
+        s = fmaf(yr, yr, s);
+        const double yd = (double)yr;
+        m2 = m2 + yd * yd;
+        if (i < n && t < d) {
+            const double df = yd - ((double)xv - (double)mu[t]);
+            e2 = e2 + df * df;
+        }
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (__any(bad) && lane == 0) atomicExch(&counters[C_NONFINITE], 1);
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        m2 += __shfl_xor(m2, off, 64);
+        e2 += __shfl_xor(e2, off, 64);
+    }
     if (lane == 0) {
-        sq[row] = acc;
-        atomicMax(sqmax_bits, __float_as_uint(acc));
+        sq[i] = s;
+        const float r = __double2float_ru(sqrt(m2) * (1.0 + 0x1p-40));
+        const float e = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40));
+        rn[i] = r;
+        re[i] = e;
+        atomicMax(rmax_bits, __float_as_uint(r));
+        atomicMax(emax_bits, __float_as_uint(e));
     }
 }
 
-// Per-row bound E_i >= |Dhat^2_ij - D^2_ij| for every j (FP32 screen):
-//   |error| <= g (s_i + s_j + 2 m_i m_j),  g = gamma_{d+4} with unit roundoff
-// 2^-23 (valid for any faithful rounding and any accumulation order), s the
-// squared norms, m the norms; j's terms are replaced by their maxima.  A 2^-10
-// relative margin covers the rounding of this evaluation itself.
-__global__ __launch_bounds__(256) void k_row_bound(const float *__restrict__ sq, int64_t n, int64_t d,
-                                                   const uint32_t *__restrict__ sqmax_bits, float *__restrict__ E) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_row_bound(const float *__restrict__ rn, const float *__restrict__ re, int64_t n, float g,
+                            const uint32_t *__restrict__ rmax_bits, const uint32_t *__restrict__ emax_bits,
+                            float *__restrict__ Emax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double u = 1.0 / 8388608.0;  // 2^-23
-    const double du = (double)(d + 4) * u;
-    const double g = du / (1.0 - du);
-    const double smax = (double)__uint_as_float(*sqmax_bits);
-    const double si = (double)sq[i];
-    double e = g * (si + smax + 2.0 * sqrt(si) * sqrt(smax));
-    e *= (1.0 + 1.0 / 1024.0);
-    E[i] = (float)e * (1.0f + 1.0f / 1024.0f);
+    Emax[i] = pair_bound(g, rn[i], __uint_as_float(*rmax_bits), re[i], __uint_as_float(*emax_bits)) + 1e-30f;
 }
 
 __global__ void k_iota_comp(int32_t *comp, int64_t n, int64_t n_pad) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += (int64_t)gridDim.x * blockDim.x)
         comp[i] = i < n ? (int32_t)i : -1;
-}
-
-// ------------------------------------------------------------------ screen (FP32 VALU)
-
-// Row block of GT rows per workgroup; each thread owns an 8 x 8 micro-tile:
-// rows ty + 16 r, columns tx + 16 c (r, c < 8).
-__global__ __launch_bounds__(GB) void k_screen_f32(const float *__restrict__ XT, int64_t n, int64_t n_pad, int d_pad,
-                                                   const float *__restrict__ sq, const float *__restrict__ E,
-                                                   const int32_t *__restrict__ comp, float *__restrict__ best_out,
-                                                   int32_t *__restrict__ ccnt, int32_t *__restrict__ cj,
-                                                   float *__restrict__ cv) {
-    __shared__ float As[GK][GT];
-    __shared__ float Bs[GK][GT];
-    __shared__ uint32_t rowbest[GT];
-    __shared__ int32_t rowcnt[GT];
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-    const int64_t i0 = (int64_t)blockIdx.x * GT;
-
-    float si[8], ei[8];
-    int ci[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        int64_t i = i0 + ty + 16 * r;
-        si[r] = sq[i];
-        ci[r] = comp[i];
-        ei[r] = ci[r] >= 0 ? 2.0f * E[i] : 0.0f;
-    }
-    if (tid < GT) {
-        rowbest[tid] = __float_as_uint(F_INF);
-        rowcnt[tid] = 0;
-    }
-    __syncthreads();
-
-    for (int64_t j0 = 0; j0 < n_pad; j0 += GT) {
-        float acc[8][8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc[r][c] = 0.0f;
-
-        for (int k0 = 0; k0 < d_pad; k0 += GK) {
-#pragma unroll
-            for (int q = 0; q < (GK * GT) / GB; ++q) {
-                int idx = tid + GB * q;
-                int k = idx / GT, ii = idx % GT;
-                As[k][ii] = XT[(int64_t)(k0 + k) * n_pad + i0 + ii];
-                Bs[k][ii] = XT[(int64_t)(k0 + k) * n_pad + j0 + ii];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < GK; ++k) {
-                float a[8], b[8];
-#pragma unroll
-                for (int r = 0; r < 8; ++r) a[r] = As[k][ty + 16 * r];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) b[c] = Bs[k][tx + 16 * c];
-#pragma unroll
-                for (int r = 0; r < 8; ++r)
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
-            }
-            __syncthreads();
-        }
-
-        // epilogue: masked Dhat^2, per-row tile minimum, then capture
-        float sj[8];
-        int cjv[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int64_t j = j0 + tx + 16 * c;
-            sj[c] = sq[j];
-            cjv[c] = comp[j];
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            float m = F_INF;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                float t = fmaxf(fmaf(-2.0f, acc[r][c], si[r] + sj[c]), 0.0f);
-                bool ok = ci[r] >= 0 && cjv[c] >= 0 && cjv[c] != ci[r];
-                acc[r][c] = ok ? t : F_INF;
-                m = fminf(m, acc[r][c]);
-            }
-            if (m < F_INF) atomicMin(&rowbest[ty + 16 * r], __float_as_uint(m));
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            float b = __uint_as_float(rowbest[ty + 16 * r]);
-            float thr = (b + ei[r]) * 1.000001f;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                float v = acc[r][c];
-                if (v <= thr && v < F_INF) {
-                    int pos = atomicAdd(&rowcnt[ty + 16 * r], 1);
-                    if (pos < CAND) {
-                        int64_t i = i0 + ty + 16 * r;
-                        cj[i * CAND + pos] = (int32_t)(j0 + tx + 16 * c);
-                        cv[i * CAND + pos] = v;
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();
-    if (tid < GT) {
-        int64_t i = i0 + tid;
-        if (i < n) {
-            best_out[i] = __uint_as_float(rowbest[tid]);
-            ccnt[i] = rowcnt[tid];
-        }
-    }
 }
 
 // ------------------------------------------------------------------ exact distances
@@ -279,112 +227,167 @@ __device__ inline bool key_less(double d2a, int ja, double d2b, int jb) {
     return d2a < d2b || (d2a == d2b && ja < jb);
 }
 
-// U_c = min over rows i of c of (b_i + E_i), rounded up.
-__global__ void k_comp_ub(const float *__restrict__ best, const float *__restrict__ E,
-                          const int32_t *__restrict__ comp, int64_t n, uint32_t *__restrict__ comp_ub) {
+// U_c = min over rows i of c of (b_i + Emax_i) (1 + rho), rounded up: an upper
+// bound on the recheck value of c's lightest outgoing edge.
+__global__ void k_comp_ub(const float *__restrict__ best, const float *__restrict__ Emax,
+                          const int32_t *__restrict__ comp, int64_t n, float up, uint32_t *__restrict__ comp_ub) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float b = best[i];
-    if (!(b < F_INF)) return;
-    float u = (b + E[i]) * 1.000001f;
+    if (!(b < SCR_INF)) return;
+    float u = (b + Emax[i]) * up;
     atomicMin(&comp_ub[comp[i]], __float_as_uint(u));
 }
 
-// One wave per row: exact D^2 of the row's surviving candidates, lightest by
-// (D^2, j).  Rows that cannot reach their component's bound are skipped; rows
-// whose candidate list overflowed are queued for the rescan.
+// Exact lightest candidate of row i among the cnt entries (js, ls) whose lower
+// bound is <= thr, by (D^2, j).  One wave; every lane returns the result.
 template <bool F64>
-__global__ __launch_bounds__(256) void k_recheck(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
-                                                 const float *__restrict__ best, const float *__restrict__ E,
-                                                 const int32_t *__restrict__ comp,
-                                                 const uint32_t *__restrict__ comp_ub, const int32_t *__restrict__ ccnt,
-                                                 const int32_t *__restrict__ cj, const float *__restrict__ cv,
-                                                 double *__restrict__ rb_d2, int32_t *__restrict__ rb_j,
-                                                 int32_t *__restrict__ ovf, int32_t *__restrict__ counters) {
+__device__ inline void eval_candidates(const float *__restrict__ X, int64_t ld, int64_t d, int64_t i,
+                                       const int32_t *__restrict__ js, const float *__restrict__ ls, int cnt, float thr,
+                                       double &out_d2, int &out_j, int &evaluated) {
+    const int lane = threadIdx.x & 63;
+    const float *xi = X + i * ld;
+    out_d2 = __builtin_huge_val();
+    out_j = -1;
+    evaluated = 0;
+    if (!F64) {
+        for (int q = 0; q < cnt; ++q) {
+            if (!(ls[q] <= thr)) continue;
+            const int j = js[q];
+            const double d2 = (double)d2_f32_wave(xi, X + (int64_t)j * ld, d);
+            ++evaluated;
+            if (key_less(d2, j, out_d2, out_j)) {
+                out_d2 = d2;
+                out_j = j;
+            }
+        }
+    } else {
+        double my = __builtin_huge_val();
+        int myj = -1;
+        for (int q0 = 0; q0 < cnt; q0 += 64) {
+            const int q = q0 + lane;
+            if (q < cnt && ls[q] <= thr) {
+                const int j = js[q];
+                const double d2 = d2_f64_lane(xi, X + (int64_t)j * ld, d);
+                ++evaluated;
+                if (key_less(d2, j, my, myj)) {
+                    my = d2;
+                    myj = j;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double od = __shfl_xor(my, off, 64);
+            const int oj = __shfl_xor(myj, off, 64);
+            evaluated += __shfl_xor(evaluated, off, 64);
+            if (oj >= 0 && (myj < 0 || key_less(od, oj, my, myj))) {
+                my = od;
+                myj = oj;
+            }
+        }
+        out_d2 = my;
+        out_j = myj;
+    }
+}
+
+// Threshold for a row's candidates (on the real-D^2 scale of the lower
+// bounds): they must be able to beat both the row's own minimum and the
+// component's bound U (a recheck value, so divided by 1 - rho).
+__device__ inline bool row_threshold(const float *__restrict__ best, const float *__restrict__ Emax,
+                                     const int32_t *__restrict__ comp, const uint32_t *__restrict__ comp_ub,
+                                     int64_t i, float kappa, float dn, float &thr) {
+    const float b = best[i];
+    const uint32_t ubits = comp_ub[comp[i]];
+    if (!(b < SCR_INF) || ubits == 0xFFFFFFFFu) return false;
+    const float U = __uint_as_float(ubits) * dn;
+    const float E = Emax[i];
+    if (lower_of(b, E) > U) return false;  // the row cannot hold its component's lightest edge
+    thr = fminf((b + E) * kappa, U);
+    return true;
+}
+
+// One wave per row: exact recheck of the sweep's candidates.  Rows whose
+// list overflowed are queued for the gathered pass.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_recheck_rows(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                      const float *__restrict__ best, const float *__restrict__ Emax,
+                                                      const int32_t *__restrict__ comp,
+                                                      const uint32_t *__restrict__ comp_ub,
+                                                      const int32_t *__restrict__ ccnt, const int32_t *__restrict__ cj,
+                                                      const float *__restrict__ cl, float kappa, float dn,
+                                                      double *__restrict__ rb_d2, int32_t *__restrict__ rb_j,
+                                                      int32_t *__restrict__ glist, int32_t *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
-    const float b = best[i];
-    const float e = E[i];
-    const uint32_t ubits = comp_ub[comp[i]];
     double out_d2 = __builtin_huge_val();
-    int out_j = -1;
-    if (b < F_INF && ubits != U32_MAX) {
-        const float U = __uint_as_float(ubits);
-        const float lower = b - e - (b + e) * (1.0f / 1048576.0f);
-        if (lower <= U) {
-            const int cnt = ccnt[i];
-            if (cnt > CAND) {
-                if (lane == 0) {
-                    int p = atomicAdd(&counters[C_OVF], 1);
-                    ovf[p] = (int32_t)i;
-                }
-                if (lane == 0) {
-                    rb_d2[i] = out_d2;
-                    rb_j[i] = out_j;
-                }
-                return;
-            }
-            const float thr = fminf(b + 2.0f * e, U + e) * 1.000001f;
-            const float *xi = X + i * ld;
-            int evaluated = 0;
-            if (!F64) {
-                for (int q = 0; q < cnt; ++q) {
-                    float v = cv[i * CAND + q];
-                    if (!(v <= thr)) continue;
-                    int j = cj[i * CAND + q];
-                    double d2 = (double)d2_f32_wave(xi, X + (int64_t)j * ld, d);
-                    ++evaluated;
-                    if (key_less(d2, j, out_d2, out_j)) {
-                        out_d2 = d2;
-                        out_j = j;
-                    }
-                }
-            } else {
-                double my = __builtin_huge_val();
-                int myj = -1;
-                if (lane < cnt) {
-                    float v = cv[i * CAND + lane];
-                    if (v <= thr) {
-                        myj = cj[i * CAND + lane];
-                        my = d2_f64_lane(xi, X + (int64_t)myj * ld, d);
-                    }
-                }
-                evaluated = __popcll(__ballot(myj >= 0));
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    double od = __shfl_xor(my, off, 64);
-                    int oj = __shfl_xor(myj, off, 64);
-                    if (oj >= 0 && (myj < 0 || key_less(od, oj, my, myj))) {
-                        my = od;
-                        myj = oj;
-                    }
-                }
-                out_d2 = my;
-                out_j = myj;
-            }
-            if (lane == 0 && evaluated) atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
+    int out_j = -1, evaluated = 0;
+    float thr;
+    if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
+        const int cnt = ccnt[i];
+        if (cnt > SCR_CAP) {
+            if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
+        } else {
+            eval_candidates<F64>(X, ld, d, i, cj + i * SCR_CAP, cl + i * SCR_CAP, cnt, thr, out_d2, out_j, evaluated);
         }
     }
     if (lane == 0) {
         rb_d2[i] = out_d2;
         rb_j[i] = out_j;
+        if (evaluated) atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
     }
 }
 
-// Exact re-evaluation of an overflowed row against every point of another
-// component: one workgroup per queued row, four waves over the columns.
+// One wave per gathered row: exact recheck of the gathered pass's candidates;
+// rows that overflowed again are queued for the exact rescan.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_recheck_gather(const float *__restrict__ X, int64_t d, int64_t ld,
+                                                        const float *__restrict__ best, const float *__restrict__ Emax,
+                                                        const int32_t *__restrict__ comp,
+                                                        const uint32_t *__restrict__ comp_ub,
+                                                        const int32_t *__restrict__ glist, int32_t ng,
+                                                        const int32_t *__restrict__ gcnt,
+                                                        const int32_t *__restrict__ gcj,
+                                                        const float *__restrict__ gcl, float kappa, float dn,
+                                                        double *__restrict__ rb_d2, int32_t *__restrict__ rb_j,
+                                                        int32_t *__restrict__ rlist, int32_t *__restrict__ counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= ng) return;
+    const int64_t i = glist[q];
+    double out_d2 = __builtin_huge_val();
+    int out_j = -1, evaluated = 0;
+    float thr;
+    if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
+        const int cnt = gcnt[q];
+        if (cnt > SCR_CAP2) {
+            if (lane == 0) rlist[atomicAdd(&counters[C_OVF], 1)] = (int32_t)i;
+        } else {
+            eval_candidates<F64>(X, ld, d, i, gcj + q * SCR_CAP2, gcl + q * SCR_CAP2, cnt, thr, out_d2, out_j,
+                                 evaluated);
+        }
+    }
+    if (lane == 0) {
+        rb_d2[i] = out_d2;
+        rb_j[i] = out_j;
+        if (evaluated) atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
+    }
+}
+
+// Exact re-evaluation of a row against every point of another component: one
+// workgroup per queued row, four waves over the columns.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_rescan(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
-                                                const int32_t *__restrict__ comp, const int32_t *__restrict__ ovf,
+                                                const int32_t *__restrict__ comp, const int32_t *__restrict__ rlist,
                                                 int32_t *__restrict__ counters, double *__restrict__ rb_d2,
                                                 int32_t *__restrict__ rb_j) {
     __shared__ double s_d2[256];
     __shared__ int s_j[256];
-    const int novf = counters[C_OVF];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int r = blockIdx.x; r < novf; r += gridDim.x) {
-        const int64_t i = ovf[r];
+    const int nr = counters[C_OVF];
+    const int w = threadIdx.x >> 6;
+    for (int r = blockIdx.x; r < nr; r += gridDim.x) {
+        const int64_t i = rlist[r];
         const int ci = comp[i];
         const float *xi = X + i * ld;
         double bd = __builtin_huge_val();
@@ -423,7 +426,6 @@ __global__ __launch_bounds__(256) void k_rescan(const float *__restrict__ X, int
         }
         __syncthreads();
     }
-    (void)lane;
 }
 
 // ------------------------------------------------------------------ contraction
@@ -630,28 +632,39 @@ __global__ __launch_bounds__(1024) void k_sum_lengths(const double *__restrict__
 // ------------------------------------------------------------------ plan
 
 struct MstPlan {
-    int64_t n, d, ld, n_pad, d_pad;
+    int64_t n, d, ld, n_pad, d_pad, nrb;
     int32_t precision;
-    float *XT;
-    float *sq, *E, *best, *cv;
-    uint32_t *sqmax, *comp_ub;
-    int32_t *comp, *ccnt, *cj, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev, *ovf;
+    void *Xr;                       // screen representation (FP32 or BF16), [n_pad][d_pad]
+    float *mu, *pmax, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
+    double *psum;
+    uint32_t *rmax, *emax, *comp_ub;
+    int32_t *comp, *ccnt, *cj, *glist, *gcnt, *gcj, *rlist, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev;
     int32_t *deg, *aoff, *cursor, *adj, *adje, *fa, *fb, *depth;
     double *rb_d2, *elen, *wsum;
     unsigned long long *ck1, *ck2;
     int32_t *counters;
 
     void carve(Arena &a) {
-        XT = a.take<float>((size_t)d_pad * n_pad);
+        const size_t esz = precision == ISO_PREC_BF16 ? 2 : 4;
+        Xr = a.take<char>((size_t)n_pad * d_pad * esz);
+        mu = a.take<float>(d_pad);
+        psum = a.take<double>((size_t)nrb * d);
+        pmax = a.take<float>((size_t)nrb * d);
         sq = a.take<float>(n_pad);
-        E = a.take<float>(n);
+        rn = a.take<float>(n_pad);
+        re = a.take<float>(n_pad);
+        Emax = a.take<float>(n);
         best = a.take<float>(n);
-        cv = a.take<float>((size_t)n * CAND);
-        sqmax = a.take<uint32_t>(1);
+        cl = a.take<float>((size_t)n * SCR_CAP);
+        rmax = a.take<uint32_t>(1);
+        emax = a.take<uint32_t>(1);
         comp_ub = a.take<uint32_t>(n);
         comp = a.take<int32_t>(n_pad);
         ccnt = a.take<int32_t>(n);
-        cj = a.take<int32_t>((size_t)n * CAND);
+        cj = a.take<int32_t>((size_t)n * SCR_CAP);
+        glist = a.take<int32_t>(n);
+        gcnt = a.take<int32_t>(n);
+        rlist = a.take<int32_t>(n);
         rb_j = a.take<int32_t>(n);
         cpar = a.take<int32_t>(n);
         npar = a.take<int32_t>(n);
@@ -659,7 +672,6 @@ struct MstPlan {
         newid = a.take<int32_t>(n);
         eu = a.take<int32_t>(n);
         ev = a.take<int32_t>(n);
-        ovf = a.take<int32_t>(n);
         deg = a.take<int32_t>(n + 1);
         aoff = a.take<int32_t>(n + 1);
         cursor = a.take<int32_t>(n);
@@ -675,6 +687,9 @@ struct MstPlan {
         ck2 = a.take<unsigned long long>(n);
         counters = a.take<int32_t>(C_COUNT);
     }
+    // The gathered pass's candidate lists reuse the memory of nothing else:
+    // they are sized for all rows (rows are gathered at most once per round).
+    size_t gather_bytes() const { return (size_t)n * SCR_CAP2 * (sizeof(int32_t) + sizeof(float)); }
 };
 
 MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
@@ -684,43 +699,98 @@ MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
     p.ld = ld;
     p.precision = precision;
     p.n_pad = (n + GT - 1) / GT * GT;
-    p.d_pad = (d + GK - 1) / GK * GK;
+    const int64_t kc = precision == ISO_PREC_BF16 ? 32 : 16;
+    p.d_pad = (d + kc - 1) / kc * kc;
+    p.nrb = (n + COL_RB - 1) / COL_RB;
     return p;
 }
 
 size_t plan_bytes(MstPlan p) {
     Arena a;
     p.carve(a);
+    a.take<char>(p.gather_bytes());
     return a.used;
 }
 
-void run_mst(MstPlan &P, const float *X, int32_t recheck, int32_t *parent, double *length, iso_mst_info *info,
-             hipStream_t s) {
+void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t *parent, double *length,
+             iso_mst_info *info, hipStream_t s) {
     const int64_t n = P.n, d = P.d, ld = P.ld;
     const bool timed = timing().enabled != 0;
+    const bool bf16 = P.precision == ISO_PREC_BF16;
+    const bool f64 = recheck == ISO_RECHECK_FP64;
     EventPair whole(timed), scr(timed);
     whole.start(s);
+    // gathered-pass lists: [n][SCR_CAP2] of j and of lower bounds
+    char *gbuf = arena.take<char>(P.gather_bytes());
+    P.gcj = reinterpret_cast<int32_t *>(gbuf);
+    P.gcl = reinterpret_cast<float *>(gbuf + (size_t)n * SCR_CAP2 * sizeof(int32_t));
+
     fill<int32_t>(P.counters, 0, C_COUNT, s);
-    fill<uint32_t>(P.sqmax, 0u, 1, s);
-    fill<float>(P.sq, 0.0f, P.n_pad, s);
-    hipLaunchKernelGGL(k_norms, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.sq, P.sqmax, P.counters);
+    fill<uint32_t>(P.rmax, 0u, 1, s);
+    fill<uint32_t>(P.emax, 0u, 1, s);
+    hipLaunchKernelGGL(k_colstats_partial, dim3((unsigned)P.nrb, (unsigned)((d + 255) / 256)), dim3(256), 0, s, X, n, d,
+                       ld, P.psum, P.pmax, P.counters);
     LAUNCH_CHECK();
     int32_t h_nonfinite = 0;
     HIP_CHECK(hipMemcpyAsync(&h_nonfinite, P.counters + C_NONFINITE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     ISO_REQUIRE(h_nonfinite == 0, ISO_ERR_NONFINITE, "points contain a NaN or infinite coordinate");
-
-    hipLaunchKernelGGL(k_row_bound, dim3(grid_for(n, 256)), dim3(256), 0, s, P.sq, n, d, P.sqmax, P.E);
+    hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.psum, P.pmax, P.nrb, n, d,
+                       P.d_pad, P.mu);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_transpose_pad, dim3((unsigned)(P.n_pad / 64), (unsigned)((P.d_pad + 63) / 64)), dim3(256), 0, s,
-                       X, n, d, ld, P.n_pad, P.d_pad, P.XT);
+    if (bf16)
+        hipLaunchKernelGGL(k_repr_rows<true>, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad,
+                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax);
+    else
+        hipLaunchKernelGGL(k_repr_rows<false>, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad,
+                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax);
+    LAUNCH_CHECK();
+    const double u = 1.0 / 8388608.0;  // 2^-23
+    const double du = (double)(d + 4) * u;
+    const float g = (float)(du / (1.0 - du) * (1.0 + 1.0 / 1024.0));
+    // recheck order vs real D^2: relative error <= rho = gamma_{d+2} at the
+    // recheck's unit roundoff (2^-24 FP32, 2^-53 FP64)
+    const double ur = f64 ? 0x1p-53 : 0x1p-24;
+    const double rho = (double)(d + 2) * ur / (1.0 - (double)(d + 2) * ur);
+    const float kappa = (float)((1.0 + rho) / (1.0 - rho) * (1.0 + 0x1p-20));
+    const float up = (float)((1.0 + rho) * (1.0 + 0x1p-20));
+    const float dn = (float)(1.0 / (1.0 - rho) * (1.0 + 0x1p-20));
+    hipLaunchKernelGGL(k_row_bound, dim3(grid_for(n, 256)), dim3(256), 0, s, P.rn, P.re, n, g, P.rmax, P.emax, P.Emax);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_iota_comp, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.comp, n, P.n_pad);
     LAUNCH_CHECK();
 
+    ScreenArgs SA{};
+    SA.XT = bf16 ? nullptr : static_cast<const float *>(P.Xr);
+    SA.XB = bf16 ? static_cast<const uint16_t *>(P.Xr) : nullptr;
+    SA.n = n;
+    SA.n_pad = P.n_pad;
+    SA.d_pad = P.d_pad;
+    SA.sq = P.sq;
+    SA.rn = P.rn;
+    SA.re = P.re;
+    SA.Emax = P.Emax;
+    SA.comp = P.comp;
+    SA.g = g;
+    SA.kappa = kappa;
+    SA.best = P.best;
+    SA.ccnt = P.ccnt;
+    SA.cj = P.cj;
+    SA.cl = P.cl;
+    SA.best_in = P.best;
+    SA.rows = P.glist;
+    SA.gcnt = P.gcnt;
+    SA.gcj = P.gcj;
+    SA.gcl = P.gcl;
+    auto screen = [&](bool gather) {
+        if (bf16)
+            launch_screen_bf16(SA, gather, s);
+        else
+            launch_screen_f32(SA, gather, s);
+    };
+
     int64_t ncomp = n;
     int rounds = 0;
-    const int blocks_rows = (int)(P.n_pad / GT);
     while (ncomp > 1) {
         ++rounds;
         ISO_REQUIRE(rounds <= 64, ISO_ERR_INTERNAL, "Boruvka did not converge");
@@ -732,28 +802,52 @@ void run_mst(MstPlan &P, const float *X, int32_t recheck, int32_t *parent, doubl
             LAUNCH_CHECK();
         }
         scr.start(s);
-        hipLaunchKernelGGL(k_screen_f32, dim3(blocks_rows), dim3(GB), 0, s, P.XT, n, P.n_pad, (int)P.d_pad, P.sq, P.E,
-                           P.comp, P.best, P.ccnt, P.cj, P.cv);
-        LAUNCH_CHECK();
+        SA.rows = nullptr;
+        SA.nrows = 0;
+        screen(false);
         scr.stop(s);
         fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-        hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.E, P.comp, n, P.comp_ub);
+        hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,
+                           P.comp_ub);
         LAUNCH_CHECK();
         fill<int32_t>(P.counters + C_OVF, 0, 1, s);
-        if (recheck == ISO_RECHECK_FP64) {
-            hipLaunchKernelGGL(k_recheck<true>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best, P.E, P.comp,
-                               P.comp_ub, P.ccnt, P.cj, P.cv, P.rb_d2, P.rb_j, P.ovf, P.counters);
-            LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_rescan<true>, dim3(1024), dim3(256), 0, s, X, n, d, ld, P.comp, P.ovf, P.counters,
-                               P.rb_d2, P.rb_j);
-        } else {
-            hipLaunchKernelGGL(k_recheck<false>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best, P.E,
-                               P.comp, P.comp_ub, P.ccnt, P.cj, P.cv, P.rb_d2, P.rb_j, P.ovf, P.counters);
-            LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_rescan<false>, dim3(1024), dim3(256), 0, s, X, n, d, ld, P.comp, P.ovf, P.counters,
-                               P.rb_d2, P.rb_j);
-        }
+        fill<int32_t>(P.counters + C_GATHER, 0, 1, s);
+        if (f64)
+            hipLaunchKernelGGL(k_recheck_rows<true>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best, P.Emax,
+                               P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist, P.counters);
+        else
+            hipLaunchKernelGGL(k_recheck_rows<false>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best,
+                               P.Emax, P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist, P.counters);
         LAUNCH_CHECK();
+        int32_t h_gather = 0;
+        HIP_CHECK(hipMemcpyAsync(&h_gather, P.counters + C_GATHER, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (timed) {
+            iso_timing &T = timing();
+            T.screen_launches += 1;
+            T.screen_ms += scr.elapsed_ms();
+        }
+        if (h_gather > 0) {
+            SA.rows = P.glist;
+            SA.nrows = h_gather;
+            screen(true);
+            if (f64)
+                hipLaunchKernelGGL(k_recheck_gather<true>, dim3(grid_for(h_gather, 4)), dim3(256), 0, s, X, d, ld,
+                                   P.best, P.Emax, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa, dn,
+                                   P.rb_d2, P.rb_j, P.rlist, P.counters);
+            else
+                hipLaunchKernelGGL(k_recheck_gather<false>, dim3(grid_for(h_gather, 4)), dim3(256), 0, s, X, d, ld,
+                                   P.best, P.Emax, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa, dn,
+                                   P.rb_d2, P.rb_j, P.rlist, P.counters);
+            LAUNCH_CHECK();
+            if (f64)
+                hipLaunchKernelGGL(k_rescan<true>, dim3(1024), dim3(256), 0, s, X, n, d, ld, P.comp, P.rlist, P.counters,
+                                   P.rb_d2, P.rb_j);
+            else
+                hipLaunchKernelGGL(k_rescan<false>, dim3(1024), dim3(256), 0, s, X, n, d, ld, P.comp, P.rlist,
+                                   P.counters, P.rb_d2, P.rb_j);
+            LAUNCH_CHECK();
+        }
         fill<unsigned long long>(P.ck1, U64_MAX, ncomp, s);
         fill<unsigned long long>(P.ck2, U64_MAX, ncomp, s);
         hipLaunchKernelGGL(k_comp_min1, dim3(grid_for(n, 256)), dim3(256), 0, s, P.rb_d2, P.rb_j, P.comp, n, P.ck1);
@@ -776,7 +870,7 @@ void run_mst(MstPlan &P, const float *X, int32_t recheck, int32_t *parent, doubl
         exclusive_scan_i32(P.flag, P.newid, ncomp, P.counters + C_NCOMP, s);
         hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.npar, P.newid);
         LAUNCH_CHECK();
-        int32_t h[5];
+        int32_t h[C_COUNT];
         HIP_CHECK(hipMemcpyAsync(h, P.counters, sizeof(h), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         ISO_REQUIRE(h[C_NOEDGE] == 0, ISO_ERR_INTERNAL, "a component found no outgoing edge in round %d", rounds);
@@ -784,10 +878,8 @@ void run_mst(MstPlan &P, const float *X, int32_t recheck, int32_t *parent, doubl
                     "Boruvka round %d did not contract (%lld -> %d components)", rounds, (long long)ncomp, h[C_NCOMP]);
         if (timed) {
             unsigned long long sumsq = 0;
-            HIP_CHECK(hipMemcpy(&sumsq, P.counters + C_SUMSQ, sizeof(sumsq), hipMemcpyDeviceToHost));
+            memcpy(&sumsq, &h[C_SUMSQ], sizeof(sumsq));
             iso_timing &T = timing();
-            T.screen_launches += 1;
-            T.screen_ms += scr.elapsed_ms();
             T.screen_pairs += 0.5 * ((double)n * (double)n - (double)sumsq);
             T.screen_dim = (double)P.d_pad;
         }
@@ -881,7 +973,7 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         ISO_REQUIRE(ws_bytes >= need, ISO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
         Arena a{static_cast<char *>(ws), 0, ws_bytes};
         P.carve(a);
-        run_mst(P, X, recheck, parent, length, info, s);
+        run_mst(P, a, X, recheck, parent, length, info, s);
     });
 }
 

@@ -1,0 +1,204 @@
+// screen.hpp -- shared pieces of the Boruvka screen kernels (FP32 VALU and
+// BF16 MFMA): the error bound of the Gram-form distance, and the epilogue that
+// keeps a running minimum per row and captures every column that can still be
+// the row's lightest outgoing edge.
+//
+// Representation: x'_i = rep(x_i - mu) with mu a per-coordinate centre (exact
+// translation invariance of distances), rep = FP32 rounding or BF16 rounding.
+// The screen forms Dhat^2_ij = fl(s_i + s_j - 2 G_ij), s_i = fl(||x'_i||^2),
+// G_ij the FP32-accumulated dot product, clamped at 0.  With r_i >= ||x'_i||,
+// e_i >= ||x'_i - (x_i - mu)|| and g = gamma_{d+4} (unit roundoff 2^-23, so the
+// bound holds for any faithful rounding and any accumulation order):
+//   |Dhat^2_ij - D^2_ij| <= E_ij = g (r_i + r_j)^2 + (e_i + e_j)(2 (r_i + r_j) + e_i + e_j).
+// (The first term bounds the norms' and the dot product's rounding, using
+//  s_i + s_j + 2 r_i r_j = (r_i + r_j)^2; the second the representation error
+//  through |D - D'| <= e_i + e_j and D' <= r_i + r_j.)
+// Emax_i = E with j's terms replaced by their maxima bounds E_ij for all j.
+//
+// A column j of row i is a candidate when its lower bound
+//   L_ij = Dhat^2_ij - E_ij  <=  kappa (b_i + Emax_i),
+// b_i the running minimum of Dhat^2 over the row; b_i only decreases, so a
+// column that is never captured can never be the row's lightest edge.  The
+// edges are ordered by the exact recheck value O(i,j), which differs from the
+// real D^2 by at most rho D^2 (rho = gamma_{d+2} at the recheck's unit
+// roundoff); kappa = (1 + rho) / (1 - rho) (1 + 2^-20) makes the capture hold
+// every column whose O can reach the row's minimum O.
+#pragma once
+
+#include "common.hpp"
+
+namespace iso {
+
+constexpr int SCR_ROWS = 128;    // rows per workgroup
+constexpr int SCR_COLS = 128;    // columns per tile
+constexpr int SCR_CAP = 32;      // candidate slots per row in the sweep (LDS)
+constexpr int SCR_CAP2 = 512;    // candidate slots per row in the gathered pass (global)
+constexpr float SCR_INF = __builtin_huge_valf();
+constexpr float THR_UP = 1.0f + 1.0f / 1048576.0f;  // covers the rounding of a sum of two nonnegative terms
+
+struct ScreenArgs {
+    const float *XT;         // FP32 screen: [n_pad][d_pad] centred, row-major
+    const uint16_t *XB;      // BF16 screen: [n_pad][d_pad] centred, row-major (bf16 bits)
+    int64_t n, n_pad, d_pad;
+    const float *sq;         // [n_pad] fl(||x'||^2) as used in Dhat^2 (0 on padding)
+    const float *rn;         // [n_pad] r_i
+    const float *re;         // [n_pad] e_i
+    const float *Emax;       // [n]
+    const int32_t *comp;     // [n_pad] component of each point, -1 on padding
+    float g;                 // gamma_{d+4}
+    float kappa;             // capture threshold scale (recheck order slack and rounding)
+    // gathered pass (rows == nullptr for the full sweep)
+    const int32_t *rows;     // [nrows] row of each gathered slot
+    int32_t nrows;
+    const float *best_in;    // [n] running minimum from the sweep
+    int32_t *gcnt;           // [nrows] candidates per slot (> SCR_CAP2 = overflow)
+    int32_t *gcj;            // [nrows * SCR_CAP2]
+    float *gcl;              // [nrows * SCR_CAP2]
+    // sweep outputs
+    float *best;             // [n]
+    int32_t *ccnt;           // [n] candidates (> SCR_CAP = overflow)
+    int32_t *cj;             // [n * SCR_CAP]
+    float *cl;               // [n * SCR_CAP]
+};
+
+struct ScreenLDS {
+    uint32_t rowbest[SCR_ROWS];
+    int32_t rowcnt[SCR_ROWS];
+    int32_t rowovf[SCR_ROWS];
+    float rowE[SCR_ROWS];
+    int32_t lj[SCR_ROWS][SCR_CAP];
+    float ll[SCR_ROWS][SCR_CAP];
+    float csq[SCR_COLS], crn[SCR_COLS], cre[SCR_COLS];
+    int32_t ccomp[SCR_COLS];
+};
+
+__device__ __forceinline__ float pair_bound(float g, float ri, float rj, float ei, float ej) {
+    const float t = ri + rj, f = ei + ej;
+    return (g * t * t + f * (2.0f * t + f)) * (1.0f + 1.0f / 1024.0f);
+}
+
+// Lower bound of D^2 from Dhat^2 = v and the bound E (both >= 0): the 2^-21
+// slack covers the two roundings of this evaluation.
+__device__ __forceinline__ float lower_of(float v, float E) { return fmaf(-0x1p-21f, v + E, v - E); }
+
+// Workgroup-wide initialisation of the per-row state; `row_of(q)` gives the
+// global row of local slot q (or -1).
+template <bool GATHER>
+__device__ __forceinline__ void screen_init_rows(ScreenLDS &S, const ScreenArgs &A, int64_t i0) {
+    for (int q = threadIdx.x; q < SCR_ROWS; q += blockDim.x) {
+        int64_t i;
+        if (GATHER) {
+            const int64_t slot = i0 + q;
+            i = slot < A.nrows ? A.rows[slot] : -1;
+        } else {
+            i = i0 + q < A.n ? i0 + q : -1;
+        }
+        S.rowbest[q] = (GATHER && i >= 0) ? __float_as_uint(A.best_in[i]) : __float_as_uint(SCR_INF);
+        S.rowcnt[q] = 0;
+        S.rowovf[q] = 0;
+        S.rowE[q] = i >= 0 ? A.Emax[i] : 0.0f;
+    }
+}
+
+// Column constants of the tile starting at j0.
+__device__ __forceinline__ void screen_load_cols(ScreenLDS &S, const ScreenArgs &A, int64_t j0) {
+    for (int q = threadIdx.x; q < SCR_COLS; q += blockDim.x) {
+        const int64_t j = j0 + q;
+        S.csq[q] = A.sq[j];
+        S.crn[q] = A.rn[j];
+        S.cre[q] = A.re[j];
+        S.ccomp[q] = A.comp[j];
+    }
+}
+
+// Masked Dhat^2 of one element.
+__device__ __forceinline__ float screen_value(float G, float si, float sj, int ci, int cj) {
+    const float t = fmaxf(fmaf(-2.0f, G, si + sj), 0.0f);
+    return (ci >= 0 && cj >= 0 && cj != ci) ? t : SCR_INF;
+}
+
+__device__ __forceinline__ void screen_row_min(ScreenLDS &S, int rl, float m) {
+    if (m < SCR_INF) atomicMin(&S.rowbest[rl], __float_as_uint(m));
+}
+
+// Capture test and store of one element (v = masked Dhat^2).
+template <bool GATHER>
+__device__ __forceinline__ void screen_capture(ScreenLDS &S, const ScreenArgs &A, int rl, int64_t slot, float v,
+                                               float thr_cheap, float thr, float g, float ri, float ei, int cl,
+                                               int64_t j) {
+    if (!(v <= thr_cheap)) return;
+    const float E = pair_bound(g, ri, S.crn[cl], ei, S.cre[cl]);
+    const float L = lower_of(v, E);
+    if (!(L <= thr)) return;
+    const int pos = atomicAdd(&S.rowcnt[rl], 1);
+    if (GATHER) {
+        if (pos < SCR_CAP2) {
+            A.gcj[slot * SCR_CAP2 + pos] = (int32_t)j;
+            A.gcl[slot * SCR_CAP2 + pos] = L;
+        }
+    } else {
+        if (pos < SCR_CAP) {
+            S.lj[rl][pos] = (int32_t)j;
+            S.ll[rl][pos] = L;
+        } else {
+            S.rowovf[rl] = 1;
+        }
+    }
+}
+
+// Per-row thresholds from the current running minimum.
+__device__ __forceinline__ void screen_thresholds(const ScreenLDS &S, int rl, float kappa, float &thr_cheap,
+                                                  float &thr) {
+    const float b = __uint_as_float(S.rowbest[rl]);
+    const float E = S.rowE[rl];
+    thr_cheap = (b + 2.0f * E) * kappa;
+    thr = (b + E) * kappa;
+}
+
+// Drops captured entries that the current minimum has ruled out, for rows
+// whose list is more than half full.  One thread per row.
+__device__ __forceinline__ void screen_compact(ScreenLDS &S, float kappa) {
+    for (int rl = threadIdx.x; rl < SCR_ROWS; rl += blockDim.x) {
+        const int cnt = S.rowcnt[rl];
+        if (S.rowovf[rl] || cnt <= SCR_CAP / 2) continue;
+        float tc, thr;
+        screen_thresholds(S, rl, kappa, tc, thr);
+        int keep = 0;
+        for (int q = 0; q < cnt && q < SCR_CAP; ++q) {
+            const float L = S.ll[rl][q];
+            if (L <= thr) {
+                S.lj[rl][keep] = S.lj[rl][q];
+                S.ll[rl][keep] = L;
+                ++keep;
+            }
+        }
+        S.rowcnt[rl] = keep;
+    }
+}
+
+// Writes the per-row results of the workgroup.
+template <bool GATHER>
+__device__ __forceinline__ void screen_finish(ScreenLDS &S, const ScreenArgs &A, int64_t i0) {
+    for (int rl = threadIdx.x; rl < SCR_ROWS; rl += blockDim.x) {
+        if (GATHER) {
+            const int64_t slot = i0 + rl;
+            if (slot < A.nrows) A.gcnt[slot] = S.rowcnt[rl];
+        } else {
+            const int64_t i = i0 + rl;
+            if (i >= A.n) continue;
+            A.best[i] = __uint_as_float(S.rowbest[rl]);
+            const int cnt = S.rowovf[rl] ? SCR_CAP + 1 : S.rowcnt[rl];
+            A.ccnt[i] = cnt;
+            for (int q = 0; q < cnt && q < SCR_CAP; ++q) {
+                A.cj[i * SCR_CAP + q] = S.lj[rl][q];
+                A.cl[i * SCR_CAP + q] = S.ll[rl][q];
+            }
+        }
+    }
+}
+
+// Launchers (screen_f32 in mst.hip, screen_bf16 in screen_bf16.hip).
+void launch_screen_f32(const ScreenArgs &A, bool gather, hipStream_t s);
+void launch_screen_bf16(const ScreenArgs &A, bool gather, hipStream_t s);
+
+}  // namespace iso

@@ -1,0 +1,214 @@
+// screen_mfma.hip -- Boruvka screen on the matrix cores (gfx950).
+//
+// Each workgroup owns SCR_ROWS rows (points i) and sweeps every column tile
+// (points j), forming the Gram tile G = X'_I X'_J^T on MFMA with FP32
+// accumulation, then the masked Dhat^2 = s_i + s_j - 2 G, a running minimum per
+// row and the capture of near-minimal columns (screen.hpp).  The n x n
+// distance matrix is never stored: each tile lives in accumulators only.
+//
+// The MFMA is issued transposed (MFMA rows = columns j, MFMA columns = rows
+// i), so that each lane of the 32 x 32 result holds one row i and sixteen
+// columns j: the row state stays in registers and the column constants are
+// broadcast from LDS.
+//   BF16: v_mfma_f32_32x32x16_bf16, lane l supplies row (l mod 32), k = 8 (l div 32) .. +7
+//   FP32: v_mfma_f32_32x32x2_f32,    lane l supplies row (l mod 32), k = l div 32
+//   result register q of lane l: MFMA row 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32.
+// Workgroup: 4 waves in a 2 x 2 grid, each wave a 64 x 64 sub-tile (2 x 2 MFMA blocks).
+#include "screen.hpp"
+
+namespace iso {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <bool BF16>
+struct Prec;
+
+template <>
+struct Prec<true> {
+    using T = uint16_t;                       // bf16 bits
+    static constexpr int KC = 32;             // K elements per LDS stage
+    static constexpr int LDK = KC + 8;        // padded LDS row (elements)
+    static constexpr int KSTEP = 16;          // K per MFMA
+    static constexpr int VEC = 8;             // elements per lane per operand
+};
+
+template <>
+struct Prec<false> {
+    using T = float;
+    static constexpr int KC = 16;
+    static constexpr int LDK = KC + 4;
+    static constexpr int KSTEP = 2;
+    static constexpr int VEC = 1;
+};
+
+template <bool BF16, bool GATHER>
+__global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
+    using P = Prec<BF16>;
+    using T = typename P::T;
+    __shared__ ScreenLDS S;
+    __shared__ __attribute__((aligned(16))) T As[SCR_COLS * P::LDK];  // column points j
+    __shared__ __attribute__((aligned(16))) T Bs[SCR_ROWS * P::LDK];  // row points i
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wi = w >> 1, wj = w & 1;
+    const int64_t i0 = (int64_t)blockIdx.x * SCR_ROWS;
+    const T *X = BF16 ? reinterpret_cast<const T *>(A.XB) : reinterpret_cast<const T *>(A.XT);
+    const int64_t d_pad = A.d_pad;
+
+    screen_init_rows<GATHER>(S, A, i0);
+
+    // this lane's two rows (local index, global index, constants)
+    int rl[2];
+    int64_t gi[2];
+    float si[2], ri[2], ei[2];
+    int ci[2];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+        rl[ib] = 64 * wi + 32 * ib + (lane & 31);
+        int64_t i;
+        if (GATHER) {
+            const int64_t slot = i0 + rl[ib];
+            i = slot < A.nrows ? A.rows[slot] : -1;
+        } else {
+            i = i0 + rl[ib] < A.n ? i0 + rl[ib] : -1;
+        }
+        gi[ib] = i;
+        si[ib] = i >= 0 ? A.sq[i] : 0.0f;
+        ri[ib] = i >= 0 ? A.rn[i] : 0.0f;
+        ei[ib] = i >= 0 ? A.re[i] : 0.0f;
+        ci[ib] = i >= 0 ? A.comp[i] : -1;
+    }
+    // source row of each staged B row (this thread's loads)
+    constexpr int CHUNK = 16 / sizeof(T);               // elements per 16-byte load
+    constexpr int PARTS = P::KC / CHUNK;                // 16-byte loads per staged row
+    constexpr int LOADS = SCR_ROWS * PARTS / 256;       // per thread per operand
+    int64_t brow[LOADS];
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+        const int idx = tid + 256 * q;
+        const int r = idx / PARTS;
+        if (GATHER) {
+            const int64_t slot = i0 + r;
+            brow[q] = slot < A.nrows ? A.rows[slot] : -1;
+        } else {
+            brow[q] = i0 + r;
+        }
+    }
+    __syncthreads();
+
+    for (int64_t j0 = 0; j0 < A.n_pad; j0 += SCR_COLS) {
+        screen_load_cols(S, A, j0);
+        floatx16 acc[2][2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[ib][jb][q] = 0.0f;
+
+        for (int64_t k0 = 0; k0 < d_pad; k0 += P::KC) {
+#pragma unroll
+            for (int q = 0; q < LOADS; ++q) {
+                const int idx = tid + 256 * q;
+                const int r = idx / PARTS, part = idx % PARTS;
+                const uint4 va = *reinterpret_cast<const uint4 *>(X + (j0 + r) * d_pad + k0 + part * CHUNK);
+                *reinterpret_cast<uint4 *>(&As[r * P::LDK + part * CHUNK]) = va;
+                uint4 vb = make_uint4(0, 0, 0, 0);
+                if (brow[q] >= 0) vb = *reinterpret_cast<const uint4 *>(X + brow[q] * d_pad + k0 + part * CHUNK);
+                *reinterpret_cast<uint4 *>(&Bs[r * P::LDK + part * CHUNK]) = vb;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < P::KC; ks += P::KSTEP) {
+                const int kofs = ks + (lane >> 5) * P::VEC;
+                if constexpr (BF16) {
+                    bf16x8 a[2], b[2];
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb)
+                        a[jb] = *reinterpret_cast<const bf16x8 *>(&As[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+                        b[ib] = *reinterpret_cast<const bf16x8 *>(&Bs[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                        for (int jb = 0; jb < 2; ++jb)
+                            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], b[ib], acc[ib][jb], 0, 0, 0);
+                } else {
+                    float a[2], b[2];
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb) a[jb] = As[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs];
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib) b[ib] = Bs[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs];
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                        for (int jb = 0; jb < 2; ++jb)
+                            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], b[ib], acc[ib][jb], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+
+        // phase A: masked Dhat^2 and the row minima
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+            float m = SCR_INF;
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    const float v = screen_value(acc[ib][jb][q], si[ib], S.csq[jl], ci[ib], S.ccomp[jl]);
+                    acc[ib][jb][q] = v;
+                    m = fminf(m, v);
+                }
+            screen_row_min(S, rl[ib], m);
+        }
+        __syncthreads();
+        // phase B: capture
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+            if (gi[ib] < 0) continue;
+            float tc, thr;
+            screen_thresholds(S, rl[ib], A.kappa, tc, thr);
+            const int64_t slot = GATHER ? i0 + rl[ib] : gi[ib];
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    screen_capture<GATHER>(S, A, rl[ib], slot, acc[ib][jb][q], tc, thr, A.g, ri[ib], ei[ib], jl,
+                                           j0 + jl);
+                }
+        }
+        __syncthreads();
+        if (!GATHER) screen_compact(S, A.kappa);
+    }
+    __syncthreads();
+    screen_finish<GATHER>(S, A, i0);
+}
+
+template <bool BF16>
+void launch(const ScreenArgs &A, bool gather, hipStream_t s) {
+    if (gather) {
+        if (A.nrows <= 0) return;
+        const unsigned blocks = (unsigned)((A.nrows + SCR_ROWS - 1) / SCR_ROWS);
+        hipLaunchKernelGGL((k_screen_mfma<BF16, true>), dim3(blocks), dim3(256), 0, s, A);
+    } else {
+        const unsigned blocks = (unsigned)(A.n_pad / SCR_ROWS);
+        hipLaunchKernelGGL((k_screen_mfma<BF16, false>), dim3(blocks), dim3(256), 0, s, A);
+    }
+    LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void launch_screen_f32(const ScreenArgs &A, bool gather, hipStream_t s) { launch<false>(A, gather, s); }
+void launch_screen_bf16(const ScreenArgs &A, bool gather, hipStream_t s) { launch<true>(A, gather, s); }
+
+}  // namespace iso

@@ -63,11 +63,12 @@ def _oracle_tree(orc, name):
     return _cache[name]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_mst_fp64_recheck_identical(iso, orc, name):
+def test_mst_fp64_recheck_identical(iso, orc, name, precision):
     X, op, ol = _oracle_tree(orc, name)
-    H.log("case %s n=%d d=%d fp32 screen + fp64 recheck" % (name, *X.shape))
-    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision="fp32", recheck="fp64")
+    H.log("case %s n=%d d=%d %s screen + fp64 recheck" % (name, *X.shape, precision))
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64")
     gp = parent.cpu().numpy()
     gl = length.cpu().numpy()
     assert H.edge_set(gp) == H.edge_set(op)
@@ -77,11 +78,12 @@ def test_mst_fp64_recheck_identical(iso, orc, name):
     assert abs(info["mst_weight"] - W) <= 1e-12 * max(W, 1e-300)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_mst_fp32_recheck_near_ties_only(iso, orc, name):
+def test_mst_fp32_recheck_near_ties_only(iso, orc, name, precision):
     X, op, ol = _oracle_tree(orc, name)
-    H.log("case %s n=%d d=%d fp32 screen + fp32 recheck" % (name, *X.shape))
-    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision="fp32", recheck="fp32")
+    H.log("case %s n=%d d=%d %s screen + fp32 recheck" % (name, *X.shape, precision))
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp32")
     gp = parent.cpu().numpy()
     swaps = H.check_tree_vs_oracle(X, gp, op, H.screen_tol(X.shape[1]))
     W = ol.sum()
@@ -122,24 +124,26 @@ def test_subpartition_on_oracle_tree(iso, orc, name, k, phi, bracket):
         assert abs(info[key] - getattr(ref, key)) <= 1e-13 * abs(getattr(ref, key))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("name,k", [("c1-n2000-d16", 5), ("c5-n3000-d128", 16), ("c3-n1500-d784", 10),
                                     ("c2-n2500-d64", 20)])
-def test_end_to_end(iso, orc, name, k):
+def test_end_to_end(iso, orc, name, k, precision):
     X, op, ol = _oracle_tree(orc, name)
-    H.log("case %s end to end k=%d" % (name, k))
+    H.log("case %s end to end k=%d %s screen" % (name, k, precision))
     ref = orc.subpartition(op, ol, k)
-    labels, ik, info = iso.cluster(torch.from_numpy(X).cuda(), k, recheck="fp32")
+    labels, ik, info = iso.cluster(torch.from_numpy(X).cuda(), k, precision=precision, recheck="fp32")
     gp = info["parent"].cpu().numpy()
     assert abs(ik - ref.i_k) <= 1e-9 * ref.i_k
     if H.edge_set(gp) == H.edge_set(op):
         np.testing.assert_array_equal(labels.cpu().numpy(), ref.labels)
 
 
-def test_determinism(iso):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_determinism(iso, precision):
     X = torch.from_numpy(datagen.config(5, n=4000)).cuda()
-    H.log("determinism n=4000 d=128")
-    a = iso.cluster(X, 16)
-    b = iso.cluster(X, 16)
+    H.log("determinism n=4000 d=128 %s" % precision)
+    a = iso.cluster(X, 16, precision=precision)
+    b = iso.cluster(X, 16, precision=precision)
     assert torch.equal(a[0], b[0]) and a[1] == b[1]
     assert torch.equal(a[2]["parent"], b[2]["parent"]) and torch.equal(a[2]["length"], b[2]["length"])
 
@@ -160,3 +164,14 @@ def test_errors(iso):
     with pytest.raises(IsoError) as e:
         iso.isoperimetric_subpartition(parent, length, 2)
     assert e.value.code == -1
+
+
+def test_screen_precision_does_not_change_tree(iso):
+    """The screen only proposes candidates: FP32 and BF16 screens give the same
+    tree under the same recheck."""
+    X = torch.from_numpy(datagen.config(3, n=3000)).cuda()
+    H.log("screen precision invariance c3 n=3000")
+    a = iso.mst(X, precision="fp32")
+    b = iso.mst(X, precision="bf16")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[2]["rescanned_rows"] == 0 and b[2]["rescanned_rows"] == 0
