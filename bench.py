@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
 WORKLOAD = 3
-PEAKS_TFLOPS = {"bf16": 2500.0, "fp32_mfma": 157.3, "fp32_valu": 157.3}
+PEAKS_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
 SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/mst.hip"]
 
 
@@ -128,10 +128,7 @@ def main():
     labels, ik, info = last
     flops = 2.0 * d * T["screen_pairs"]
     achieved = flops / (T["screen_ms"] * 1e-3) / 1e12 if T["screen_ms"] > 0 else None
-    if args.precision == "bf16":
-        bound, peak = "mfma", PEAKS_TFLOPS["bf16"]
-    else:
-        bound, peak = "alu", PEAKS_TFLOPS["fp32_valu"]
+    bound, peak = "mfma", PEAKS_TFLOPS[args.precision]
     launches = max(T["screen_launches"], 1)
     tb = traffic_from_profiles(args.precision)
     out = {
@@ -151,7 +148,7 @@ def main():
                    "k": k, "sigma": "median MST edge", "screen": args.precision, "recheck": args.recheck,
                    "tree": "f64", "parallelism": "none"},
         "roofline": {
-            "kernel": "k_screen_f32" if args.precision == "fp32" else "k_screen_bf16",
+            "kernel": "k_screen_mfma<%s>" % args.precision,
             "bound": bound,
             "achieved": achieved,
             "peak": peak,
