@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
 WORKLOAD = 3
 PEAKS_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
-SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/mst.hip"]
+SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/screen_mfma.hip", "paper_1702_04739_amd/csrc/screen.hpp"]
 
 
 def log(*a):
@@ -79,11 +79,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32-screen comparison step")
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=6000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the steps, run one plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -103,6 +106,15 @@ def main():
     log("generating %s n=%d d=%d" % (cfg["name"], n, d))
     X = torch.from_numpy(datagen.config(WORKLOAD, n=n)).cuda()
     torch.cuda.synchronize()
+
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (src.numel() * 4, dst.numel() * 4))
+        del src, dst
 
     def step():
         return iso.cluster(X, k, precision=args.precision, recheck=args.recheck)
@@ -167,6 +179,18 @@ def main():
                    "passes": info["sub"]["passes"], "max_depth": info["sub"]["max_depth"],
                    "i_k": ik, "mst_weight": info["mst"]["mst_weight"]},
     }
+    if not args.no_compare and args.precision != "fp32":
+        log("comparison: FP32 screen, 1 warm-up + 1 step")
+        iso.cluster(X, k, precision="fp32", recheck=args.recheck)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        lab32, ik32, info32 = iso.cluster(X, k, precision="fp32", recheck=args.recheck)
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        out["compare"] = {"screen": "fp32", "value": n / (c1 - c0), "ms_per_step": (c1 - c0) * 1e3,
+                          "speedup_of_value": value / (n / (c1 - c0)),
+                          "same_tree": bool(torch.equal(info32["parent"], info["parent"])),
+                          "same_labels": bool(torch.equal(lab32, labels)), "i_k": ik32}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, n=%d sample)" % args.cpu_sample_n)
         out["cpu_baseline"] = cpu_baseline(n, k, args.cpu_sample_n)

@@ -69,34 +69,46 @@ void fill(T *p, T v, int64_t n, hipStream_t s) {
 // ------------------------------------------------------------------ screen representation
 
 constexpr int COL_RB = 1024;   // rows per partial column sum
+constexpr int GRID_NONE = 1 << 20;
+
+// Exponent q of the coarsest binary grid 2^q holding the finite float x
+// (x = odd integer * 2^q); GRID_NONE for 0.
+__device__ __forceinline__ int grid_exponent(float x) {
+    const uint32_t u = __float_as_uint(x) & 0x7FFFFFFFu;
+    if (u == 0u) return GRID_NONE;
+    const int ef = (int)(u >> 23);
+    const uint32_t mant = u & 0x7FFFFFu;
+    if (ef == 0) return -149 + __builtin_ctz(mant);  // subnormal
+    return ef - 150 + __builtin_ctz(mant | 0x800000u);
+}
 
 // Partial per-coordinate sums (FP64) and maxima of |x| over row blocks;
 // non-finite check.
 __global__ __launch_bounds__(256) void k_colstats_partial(const float *__restrict__ X, int64_t n, int64_t d,
                                                           int64_t ld, double *__restrict__ psum,
-                                                          float *__restrict__ pmax, int32_t *__restrict__ counters) {
+                                                          int32_t *__restrict__ pgrid, int32_t *__restrict__ counters) {
     const int64_t t = (int64_t)blockIdx.y * 256 + threadIdx.x;
     const int64_t rb = blockIdx.x;
     if (t >= d) return;
     const int64_t lo = rb * COL_RB, hi = lo + COL_RB < n ? lo + COL_RB : n;
     double s = 0.0;
-    float m = 0.0f;
+    int q = GRID_NONE;
     bool bad = false;
     for (int64_t i = lo; i < hi; ++i) {
         const float x = X[i * ld + t];
         bad |= !isfinite(x);
         s = s + (double)x;
-        m = fmaxf(m, fabsf(x));
+        q = min(q, grid_exponent(x));
     }
     psum[rb * d + t] = s;
-    pmax[rb * d + t] = m;
+    pgrid[rb * d + t] = q;
     if (bad) atomicExch(&counters[C_NONFINITE], 1);
 }
 
-// Centre mu_t: the coordinate mean rounded to the bf16 spacing at the
-// coordinate's largest magnitude (so centring keeps values that sit on that
-// grid, e.g. q/256, on it); 0 beyond d.
-__global__ void k_colstats_final(const double *__restrict__ psum, const float *__restrict__ pmax, int64_t nrb,
+// Centre mu_t: the coordinate mean rounded to the coarsest binary grid 2^q_t
+// that holds every value of the column, so that centring keeps values that
+// sit on a grid (e.g. q/256) on it; 0 for empty columns and beyond d.
+__global__ void k_colstats_final(const double *__restrict__ psum, const int32_t *__restrict__ pgrid, int64_t nrb,
                                  int64_t n, int64_t d, int64_t d_pad, float *__restrict__ mu) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= d_pad) return;
@@ -105,18 +117,16 @@ __global__ void k_colstats_final(const double *__restrict__ psum, const float *_
         return;
     }
     double s = 0.0;
-    float m = 0.0f;
+    int q = GRID_NONE;
     for (int64_t rb = 0; rb < nrb; ++rb) {
         s = s + psum[rb * d + t];
-        m = fmaxf(m, pmax[rb * d + t]);
+        q = min(q, pgrid[rb * d + t]);
     }
-    if (!(m > 0.0f)) {
+    if (q == GRID_NONE) {
         mu[t] = 0.0f;
         return;
     }
-    int e;
-    frexp((double)m, &e);                      // m = f 2^e, f in [0.5, 1)
-    const double grid = ldexp(1.0, e - 8);     // bf16 spacing at m
+    const double grid = ldexp(1.0, q);
     mu[t] = (float)(rint((s / (double)n) / grid) * grid);
 }
 
@@ -135,12 +145,14 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
                                                    int64_t n_pad, int64_t d_pad, const float *__restrict__ mu,
                                                    void *__restrict__ Xr, float *__restrict__ sq,
                                                    float *__restrict__ rn, float *__restrict__ re,
-                                                   uint32_t *__restrict__ rmax_bits, uint32_t *__restrict__ emax_bits) {
+                                                   uint32_t *__restrict__ rmax_bits, uint32_t *__restrict__ emax_bits,
+                                                   int32_t *__restrict__ grid_min) {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n_pad) return;
     float s = 0.0f;
     double m2 = 0.0, e2 = 0.0;
+    int q = GRID_NONE;
     for (int64_t t = lane; t < d_pad; t += 64) {
         float xv = 0.0f, y = 0.0f;
         if (i < n && t < d) {
@@ -157,6 +169,7 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
             yr = y;
         }
         s = fmaf(yr, yr, s);
+        q = min(q, grid_exponent(yr));
         const double yd = (double)yr;
         m2 = m2 + yd * yd;
         if (i < n && t < d) {
@@ -169,8 +182,10 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
         s += __shfl_xor(s, off, 64);
         m2 += __shfl_xor(m2, off, 64);
         e2 += __shfl_xor(e2, off, 64);
+        q = min(q, __shfl_xor(q, off, 64));
     }
     if (lane == 0) {
+        if (q != GRID_NONE) atomicMin(grid_min, q);
         sq[i] = s;
         const float r = __double2float_ru(sqrt(m2) * (1.0 + 0x1p-40));
         const float e = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40));
@@ -181,12 +196,12 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
     }
 }
 
-__global__ void k_row_bound(const float *__restrict__ rn, const float *__restrict__ re, int64_t n, float g,
+__global__ void k_row_bound(const float *__restrict__ rn, const float *__restrict__ re, int64_t n, ScreenBound B,
                             const uint32_t *__restrict__ rmax_bits, const uint32_t *__restrict__ emax_bits,
                             float *__restrict__ Emax) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Emax[i] = pair_bound(g, rn[i], __uint_as_float(*rmax_bits), re[i], __uint_as_float(*emax_bits)) + 1e-30f;
+    Emax[i] = pair_bound(B, rn[i], __uint_as_float(*rmax_bits), re[i], __uint_as_float(*emax_bits)) + 1e-30f;
 }
 
 __global__ void k_iota_comp(int32_t *comp, int64_t n, int64_t n_pad) {
@@ -635,7 +650,8 @@ struct MstPlan {
     int64_t n, d, ld, n_pad, d_pad, nrb;
     int32_t precision;
     void *Xr;                       // screen representation (FP32 or BF16), [n_pad][d_pad]
-    float *mu, *pmax, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
+    float *mu, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
+    int32_t *pgrid, *grid_min;
     double *psum;
     uint32_t *rmax, *emax, *comp_ub;
     int32_t *comp, *ccnt, *cj, *glist, *gcnt, *gcj, *rlist, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev;
@@ -649,7 +665,8 @@ struct MstPlan {
         Xr = a.take<char>((size_t)n_pad * d_pad * esz);
         mu = a.take<float>(d_pad);
         psum = a.take<double>((size_t)nrb * d);
-        pmax = a.take<float>((size_t)nrb * d);
+        pgrid = a.take<int32_t>((size_t)nrb * d);
+        grid_min = a.take<int32_t>(1);
         sq = a.take<float>(n_pad);
         rn = a.take<float>(n_pad);
         re = a.take<float>(n_pad);
@@ -728,26 +745,41 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     fill<int32_t>(P.counters, 0, C_COUNT, s);
     fill<uint32_t>(P.rmax, 0u, 1, s);
     fill<uint32_t>(P.emax, 0u, 1, s);
+    fill<int32_t>(P.grid_min, GRID_NONE, 1, s);
     hipLaunchKernelGGL(k_colstats_partial, dim3((unsigned)P.nrb, (unsigned)((d + 255) / 256)), dim3(256), 0, s, X, n, d,
-                       ld, P.psum, P.pmax, P.counters);
+                       ld, P.psum, P.pgrid, P.counters);
     LAUNCH_CHECK();
     int32_t h_nonfinite = 0;
     HIP_CHECK(hipMemcpyAsync(&h_nonfinite, P.counters + C_NONFINITE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     ISO_REQUIRE(h_nonfinite == 0, ISO_ERR_NONFINITE, "points contain a NaN or infinite coordinate");
-    hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.psum, P.pmax, P.nrb, n, d,
+    hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.psum, P.pgrid, P.nrb, n, d,
                        P.d_pad, P.mu);
     LAUNCH_CHECK();
     if (bf16)
         hipLaunchKernelGGL(k_repr_rows<true>, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad,
-                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax);
+                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax, P.grid_min);
     else
         hipLaunchKernelGGL(k_repr_rows<false>, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad,
-                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax);
+                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax, P.grid_min);
     LAUNCH_CHECK();
     const double u = 1.0 / 8388608.0;  // 2^-23
     const double du = (double)(d + 4) * u;
-    const float g = (float)(du / (1.0 - du) * (1.0 + 1.0 / 1024.0));
+    ScreenBound bound{};
+    bound.g = (float)(du / (1.0 - du) * (1.0 + 1.0 / 1024.0));
+    // Exact-accumulation certificate: when every screen value is a multiple of
+    // 2^q, products are multiples of 2^2q, and a pair whose norms are at most
+    // R = 2^(11.5 + q) has every partial sum of its dot product and of both
+    // squared norms below 2^(23 + 2q) in magnitude, so all of them are exact in
+    // FP32; only fl(s_i + s_j) and the final fused multiply-add round, which
+    // costs at most 3.01 u (r_i + r_j)^2.
+    int32_t h_grid = GRID_NONE;
+    HIP_CHECK(hipMemcpyAsync(&h_grid, P.grid_min, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    bound.g_exact = (float)(4.0 * u);
+    bound.rlim = (h_grid != GRID_NONE && h_grid > -120)
+                     ? (float)(std::sqrt(2.0) * std::ldexp(1.0, h_grid + 11) * (1.0 - 0x1p-20))
+                     : 0.0f;
     // recheck order vs real D^2: relative error <= rho = gamma_{d+2} at the
     // recheck's unit roundoff (2^-24 FP32, 2^-53 FP64)
     const double ur = f64 ? 0x1p-53 : 0x1p-24;
@@ -755,7 +787,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     const float kappa = (float)((1.0 + rho) / (1.0 - rho) * (1.0 + 0x1p-20));
     const float up = (float)((1.0 + rho) * (1.0 + 0x1p-20));
     const float dn = (float)(1.0 / (1.0 - rho) * (1.0 + 0x1p-20));
-    hipLaunchKernelGGL(k_row_bound, dim3(grid_for(n, 256)), dim3(256), 0, s, P.rn, P.re, n, g, P.rmax, P.emax, P.Emax);
+    hipLaunchKernelGGL(k_row_bound, dim3(grid_for(n, 256)), dim3(256), 0, s, P.rn, P.re, n, bound, P.rmax, P.emax,
+                       P.Emax);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_iota_comp, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.comp, n, P.n_pad);
     LAUNCH_CHECK();
@@ -771,7 +804,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.re = P.re;
     SA.Emax = P.Emax;
     SA.comp = P.comp;
-    SA.g = g;
+    SA.bound = bound;
     SA.kappa = kappa;
     SA.best = P.best;
     SA.ccnt = P.ccnt;

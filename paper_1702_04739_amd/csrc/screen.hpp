@@ -36,6 +36,15 @@ constexpr int SCR_CAP2 = 512;    // candidate slots per row in the gathered pass
 constexpr float SCR_INF = __builtin_huge_valf();
 constexpr float THR_UP = 1.0f + 1.0f / 1048576.0f;  // covers the rounding of a sum of two nonnegative terms
 
+// Constants of the error bound: g = gamma_{d+4}; pairs whose norm bounds are
+// both <= rlim are certified exactly accumulated (see the exact-accumulation
+// certificate in mst.hip) and use g_exact instead.
+struct ScreenBound {
+    float g;
+    float g_exact;
+    float rlim;
+};
+
 struct ScreenArgs {
     const float *XT;         // FP32 screen: [n_pad][d_pad] centred, row-major
     const uint16_t *XB;      // BF16 screen: [n_pad][d_pad] centred, row-major (bf16 bits)
@@ -45,7 +54,7 @@ struct ScreenArgs {
     const float *re;         // [n_pad] e_i
     const float *Emax;       // [n]
     const int32_t *comp;     // [n_pad] component of each point, -1 on padding
-    float g;                 // gamma_{d+4}
+    ScreenBound bound;       // error bound constants
     float kappa;             // capture threshold scale (recheck order slack and rounding)
     // gathered pass (rows == nullptr for the full sweep)
     const int32_t *rows;     // [nrows] row of each gathered slot
@@ -72,8 +81,9 @@ struct ScreenLDS {
     int32_t ccomp[SCR_COLS];
 };
 
-__device__ __forceinline__ float pair_bound(float g, float ri, float rj, float ei, float ej) {
+__device__ __forceinline__ float pair_bound(const ScreenBound &B, float ri, float rj, float ei, float ej) {
     const float t = ri + rj, f = ei + ej;
+    const float g = fmaxf(ri, rj) <= B.rlim ? B.g_exact : B.g;
     return (g * t * t + f * (2.0f * t + f)) * (1.0f + 1.0f / 1024.0f);
 }
 
@@ -124,10 +134,10 @@ __device__ __forceinline__ void screen_row_min(ScreenLDS &S, int rl, float m) {
 // Capture test and store of one element (v = masked Dhat^2).
 template <bool GATHER>
 __device__ __forceinline__ void screen_capture(ScreenLDS &S, const ScreenArgs &A, int rl, int64_t slot, float v,
-                                               float thr_cheap, float thr, float g, float ri, float ei, int cl,
+                                               float thr_cheap, float thr, float ri, float ei, int cl,
                                                int64_t j) {
     if (!(v <= thr_cheap)) return;
-    const float E = pair_bound(g, ri, S.crn[cl], ei, S.cre[cl]);
+    const float E = pair_bound(A.bound, ri, S.crn[cl], ei, S.cre[cl]);
     const float L = lower_of(v, E);
     if (!(L <= thr)) return;
     const int pos = atomicAdd(&S.rowcnt[rl], 1);

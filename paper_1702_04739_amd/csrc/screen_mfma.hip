@@ -49,8 +49,8 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
     using P = Prec<BF16>;
     using T = typename P::T;
     __shared__ ScreenLDS S;
-    __shared__ __attribute__((aligned(16))) T As[SCR_COLS * P::LDK];  // column points j
-    __shared__ __attribute__((aligned(16))) T Bs[SCR_ROWS * P::LDK];  // row points i
+    __shared__ __attribute__((aligned(16))) T As[2][SCR_COLS * P::LDK];  // column points j (double buffer)
+    __shared__ __attribute__((aligned(16))) T Bs[2][SCR_ROWS * P::LDK];  // row points i
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -82,23 +82,42 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
         ei[ib] = i >= 0 ? A.re[i] : 0.0f;
         ci[ib] = i >= 0 ? A.comp[i] : -1;
     }
-    // source row of each staged B row (this thread's loads)
+    // staging: each thread moves LOADS 16-byte pieces of each operand per chunk
     constexpr int CHUNK = 16 / sizeof(T);               // elements per 16-byte load
     constexpr int PARTS = P::KC / CHUNK;                // 16-byte loads per staged row
     constexpr int LOADS = SCR_ROWS * PARTS / 256;       // per thread per operand
-    int64_t brow[LOADS];
-#pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-        const int idx = tid + 256 * q;
-        const int r = idx / PARTS;
-        if (GATHER) {
-            const int64_t slot = i0 + r;
-            brow[q] = slot < A.nrows ? A.rows[slot] : -1;
-        } else {
-            brow[q] = i0 + r;
-        }
+    static_assert(LOADS == 2, "staging assumes two pieces per thread and operand");
+    const int srow0 = tid / PARTS, spart0 = tid % PARTS;
+    const int srow1 = (tid + 256) / PARTS, spart1 = (tid + 256) % PARTS;
+    int64_t brow0, brow1;
+    if (GATHER) {
+        brow0 = i0 + srow0 < A.nrows ? A.rows[i0 + srow0] : -1;
+        brow1 = i0 + srow1 < A.nrows ? A.rows[i0 + srow1] : -1;
+    } else {
+        brow0 = i0 + srow0;
+        brow1 = i0 + srow1;
     }
+    uint4 ra0, ra1, rb0, rb1;
+#define ISO_GLOAD(J0, K0)                                                                                   \
+    {                                                                                                      \
+        ra0 = *reinterpret_cast<const uint4 *>(X + ((J0) + srow0) * d_pad + (K0) + spart0 * CHUNK);          \
+        ra1 = *reinterpret_cast<const uint4 *>(X + ((J0) + srow1) * d_pad + (K0) + spart1 * CHUNK);          \
+        rb0 = brow0 >= 0 ? *reinterpret_cast<const uint4 *>(X + brow0 * d_pad + (K0) + spart0 * CHUNK)      \
+                         : make_uint4(0, 0, 0, 0);                                                         \
+        rb1 = brow1 >= 0 ? *reinterpret_cast<const uint4 *>(X + brow1 * d_pad + (K0) + spart1 * CHUNK)      \
+                         : make_uint4(0, 0, 0, 0);                                                         \
+    }
+#define ISO_SSTORE(BUF)                                                                                     \
+    {                                                                                                      \
+        *reinterpret_cast<uint4 *>(&As[(BUF)][srow0 * P::LDK + spart0 * CHUNK]) = ra0;                       \
+        *reinterpret_cast<uint4 *>(&As[(BUF)][srow1 * P::LDK + spart1 * CHUNK]) = ra1;                       \
+        *reinterpret_cast<uint4 *>(&Bs[(BUF)][srow0 * P::LDK + spart0 * CHUNK]) = rb0;                       \
+        *reinterpret_cast<uint4 *>(&Bs[(BUF)][srow1 * P::LDK + spart1 * CHUNK]) = rb1;                       \
+    }
+    ISO_GLOAD(0, 0)
+    ISO_SSTORE(0)
     __syncthreads();
+    int buf = 0;
 
     for (int64_t j0 = 0; j0 < A.n_pad; j0 += SCR_COLS) {
         screen_load_cols(S, A, j0);
@@ -111,17 +130,18 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                 for (int q = 0; q < 16; ++q) acc[ib][jb][q] = 0.0f;
 
         for (int64_t k0 = 0; k0 < d_pad; k0 += P::KC) {
-#pragma unroll
-            for (int q = 0; q < LOADS; ++q) {
-                const int idx = tid + 256 * q;
-                const int r = idx / PARTS, part = idx % PARTS;
-                const uint4 va = *reinterpret_cast<const uint4 *>(X + (j0 + r) * d_pad + k0 + part * CHUNK);
-                *reinterpret_cast<uint4 *>(&As[r * P::LDK + part * CHUNK]) = va;
-                uint4 vb = make_uint4(0, 0, 0, 0);
-                if (brow[q] >= 0) vb = *reinterpret_cast<const uint4 *>(X + brow[q] * d_pad + k0 + part * CHUNK);
-                *reinterpret_cast<uint4 *>(&Bs[r * P::LDK + part * CHUNK]) = vb;
+            // prefetch the next chunk (of this tile, or the first of the next tile)
+            int64_t nj0 = j0, nk0 = k0 + P::KC;
+            if (nk0 >= d_pad) {
+                nk0 = 0;
+                nj0 = j0 + SCR_COLS;
             }
-            __syncthreads();
+            const bool has_next = nj0 < A.n_pad;
+            if (has_next) {
+                ISO_GLOAD(nj0, nk0)
+            }
+            const T *Ab = As[buf];
+            const T *Bb = Bs[buf];
 #pragma unroll
             for (int ks = 0; ks < P::KC; ks += P::KSTEP) {
                 const int kofs = ks + (lane >> 5) * P::VEC;
@@ -129,10 +149,10 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                     bf16x8 a[2], b[2];
 #pragma unroll
                     for (int jb = 0; jb < 2; ++jb)
-                        a[jb] = *reinterpret_cast<const bf16x8 *>(&As[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs]);
+                        a[jb] = *reinterpret_cast<const bf16x8 *>(&Ab[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs]);
 #pragma unroll
                     for (int ib = 0; ib < 2; ++ib)
-                        b[ib] = *reinterpret_cast<const bf16x8 *>(&Bs[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs]);
+                        b[ib] = *reinterpret_cast<const bf16x8 *>(&Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs]);
 #pragma unroll
                     for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -141,9 +161,9 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                 } else {
                     float a[2], b[2];
 #pragma unroll
-                    for (int jb = 0; jb < 2; ++jb) a[jb] = As[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs];
+                    for (int jb = 0; jb < 2; ++jb) a[jb] = Ab[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs];
 #pragma unroll
-                    for (int ib = 0; ib < 2; ++ib) b[ib] = Bs[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs];
+                    for (int ib = 0; ib < 2; ++ib) b[ib] = Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs];
 #pragma unroll
                     for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -151,7 +171,11 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], b[ib], acc[ib][jb], 0, 0, 0);
                 }
             }
+            if (has_next) {
+                ISO_SSTORE(buf ^ 1)
+            }
             __syncthreads();
+            buf ^= 1;
         }
 
         // phase A: masked Dhat^2 and the row minima
@@ -182,8 +206,7 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    screen_capture<GATHER>(S, A, rl[ib], slot, acc[ib][jb][q], tc, thr, A.g, ri[ib], ei[ib], jl,
-                                           j0 + jl);
+                    screen_capture<GATHER>(S, A, rl[ib], slot, acc[ib][jb][q], tc, thr, ri[ib], ei[ib], jl, j0 + jl);
                 }
         }
         __syncthreads();
@@ -191,6 +214,8 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
     }
     __syncthreads();
     screen_finish<GATHER>(S, A, i0);
+#undef ISO_GLOAD
+#undef ISO_SSTORE
 }
 
 template <bool BF16>
