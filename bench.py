@@ -52,6 +52,43 @@ def traffic_from_profiles(precision):
     return rec.get("hbm_bytes_per_launch")
 
 
+def traffic_report(fetch_dir, write_dir, precision, copy_mib):
+    """Per-launch HBM bytes of the screen kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by what the
+    same counter reads for the plain device copy of copy_mib MiB that the
+    profiled command ran first (--calibrate-copy)."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        vals, copy = [], None
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                sweep = "k_screen_mfma<%s, false>" % ("true" if precision == "bf16" else "false")
+                if sweep in r["Kernel_Name"]:
+                    vals.append(v)
+                elif "copyBuffer" in r["Kernel_Name"] and copy is None and v > 0.25 * copy_mib * 1024:
+                    copy = v
+        return vals, copy
+
+    fv, fc = per_kernel(fetch_dir, "FETCH_SIZE")
+    wv, wc = per_kernel(write_dir, "WRITE_SIZE")
+    nbytes = copy_mib * (1 << 20)
+    f_scale = nbytes / (fc * 1024.0)
+    w_scale = nbytes / (wc * 1024.0)
+    fetch = sum(fv) / len(fv) * 1024.0 * f_scale
+    write = sum(wv) / len(wv) * 1024.0 * w_scale
+    rec = {"kernel": "k_screen_mfma<%s>" % precision, "source_sha": screen_source_sha(),
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "hbm_bytes_per_launch": fetch + write, "launches": len(fv),
+           "copy_calibration": {"bytes": nbytes, "fetch_kib": fc, "write_kib": wc, "fetch_scale": f_scale,
+                                "write_scale": w_scale}}
+    return rec
+
+
 def cpu_baseline(n_full, k, sample_n):
     """The FP64 oracle (single thread) on a subsample of the same recipe; the
     O(n^2 d) MST cost is scaled to the full n."""
@@ -87,7 +124,18 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=6000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, run one plain device copy of MIB MiB (reference for HBM counters)")
+    ap.add_argument("--traffic-report", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs into profiles/screen_<precision>_traffic.json and exit")
     args = ap.parse_args()
+
+    if args.traffic_report:
+        rec = traffic_report(args.traffic_report[0], args.traffic_report[1], args.precision,
+                             args.calibrate_copy or 1024)
+        path = os.path.join(ROOT, "profiles", "screen_%s_traffic.json" % args.precision)
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the MST screen shards over tile pairs with one min-all-reduce per "
