@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
 WORKLOAD = 3
 PEAKS_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
-SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/screen_mfma.hip", "paper_1702_04739_amd/csrc/screen.hpp"]
+SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/screen_pairs.hip", "paper_1702_04739_amd/csrc/screen.hpp"]
 
 
 def log(*a):
@@ -67,7 +67,7 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
                 if r["Counter_Name"] != counter:
                     continue
                 v = float(r["Counter_Value"])
-                sweep = "k_screen_mfma<%s, false>" % ("true" if precision == "bf16" else "false")
+                sweep = "k_screen_pairs<%s>" % ("true" if precision == "bf16" else "false")
                 if sweep in r["Kernel_Name"]:
                     vals.append(v)
                 elif "copyBuffer" in r["Kernel_Name"] and copy is None and v > 0.25 * copy_mib * 1024:
@@ -81,7 +81,7 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
     w_scale = nbytes / (wc * 1024.0)
     fetch = sum(fv) / len(fv) * 1024.0 * f_scale
     write = sum(wv) / len(wv) * 1024.0 * w_scale
-    rec = {"kernel": "k_screen_mfma<%s>" % precision, "source_sha": screen_source_sha(),
+    rec = {"kernel": "k_screen_pairs<%s>" % precision, "source_sha": screen_source_sha(),
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "hbm_bytes_per_launch": fetch + write, "launches": len(fv),
            "copy_calibration": {"bytes": nbytes, "fetch_kib": fc, "write_kib": wc, "fetch_scale": f_scale,
@@ -208,7 +208,7 @@ def main():
                    "k": k, "sigma": "median MST edge", "screen": args.precision, "recheck": args.recheck,
                    "tree": "f64", "parallelism": "none"},
         "roofline": {
-            "kernel": "k_screen_mfma<%s>" % args.precision,
+            "kernel": "k_screen_pairs<%s>" % args.precision,
             "bound": bound,
             "achieved": achieved,
             "peak": peak,

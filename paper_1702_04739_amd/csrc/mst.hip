@@ -31,7 +31,7 @@ namespace iso {
 
 namespace {
 
-constexpr int GT = SCR_ROWS;   // row padding granule
+constexpr int GT = 256;        // row padding granule (the tile-pair screen's tile)
 constexpr uint32_t U32_MAX = 0xFFFFFFFFu;
 constexpr uint64_t U64_MAX = ~0ull;
 
@@ -652,6 +652,8 @@ struct MstPlan {
     void *Xr;                       // screen representation (FP32 or BF16), [n_pad][d_pad]
     float *mu, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
     int32_t *pgrid, *grid_min;
+    int2 *pairs;
+    int64_t npairs;
     double *psum;
     uint32_t *rmax, *emax, *comp_ub;
     int32_t *comp, *ccnt, *cj, *glist, *gcnt, *gcj, *rlist, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev;
@@ -703,6 +705,7 @@ struct MstPlan {
         ck1 = a.take<unsigned long long>(n);
         ck2 = a.take<unsigned long long>(n);
         counters = a.take<int32_t>(C_COUNT);
+        pairs = a.take<int2>(npairs);
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
     // they are sized for all rows (rows are gathered at most once per round).
@@ -719,6 +722,8 @@ MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
     const int64_t kc = precision == ISO_PREC_BF16 ? 32 : 16;
     p.d_pad = (d + kc - 1) / kc * kc;
     p.nrb = (n + COL_RB - 1) / COL_RB;
+    const int64_t nt = p.n_pad / pair_tile();
+    p.npairs = nt * (nt + 1) / 2;
     return p;
 }
 
@@ -821,6 +826,13 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         else
             launch_screen_f32(SA, gather, s);
     };
+    {
+        const std::vector<int2> order = make_pair_order(P.n_pad / pair_tile());
+        ISO_REQUIRE((int64_t)order.size() == P.npairs, ISO_ERR_INTERNAL, "tile-pair order has %zu entries",
+                    order.size());
+        HIP_CHECK(hipMemcpyAsync(P.pairs, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
 
     int64_t ncomp = n;
     int rounds = 0;
@@ -834,10 +846,12 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(1024), 0, s, P.flag, ncomp, P.counters);
             LAUNCH_CHECK();
         }
-        scr.start(s);
+        fill<uint32_t>(reinterpret_cast<uint32_t *>(P.best), 0x7F800000u, n, s);  // +inf
+        fill<int32_t>(P.ccnt, 0, n, s);
         SA.rows = nullptr;
         SA.nrows = 0;
-        screen(false);
+        scr.start(s);
+        launch_screen_pairs(SA, P.pairs, P.npairs, bf16, s);
         scr.stop(s);
         fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
         hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,

@@ -25,6 +25,8 @@
 // every column whose O can reach the row's minimum O.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace iso {
@@ -207,8 +209,15 @@ __device__ __forceinline__ void screen_finish(ScreenLDS &S, const ScreenArgs &A,
     }
 }
 
-// Launchers (screen_f32 in mst.hip, screen_bf16 in screen_bf16.hip).
+// Row-sweep screen (screen_mfma.hip): every workgroup owns SCR_ROWS rows and
+// sweeps all columns; used for the gathered second pass.
 void launch_screen_f32(const ScreenArgs &A, bool gather, hipStream_t s);
 void launch_screen_bf16(const ScreenArgs &A, bool gather, hipStream_t s);
+
+// Symmetric tile-pair screen (screen_pairs.hip): best[] must hold +inf and
+// ccnt[] zero on entry; both are updated with atomics.
+int64_t pair_tile();
+std::vector<int2> make_pair_order(int64_t ntiles);
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, bool bf16, hipStream_t s);
 
 }  // namespace iso

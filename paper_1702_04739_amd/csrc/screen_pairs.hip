@@ -1,0 +1,353 @@
+// screen_pairs.hip -- symmetric Boruvka screen over tile pairs (gfx950 MFMA).
+//
+// The points are cut into tiles of PT = 256.  One workgroup handles one tile
+// pair (I, J) with I <= J, so every unordered pair of points is formed once:
+// the Gram tile G = X'_J X'_I^T is accumulated on MFMA (FP32 accumulate), then
+//   Dhat^2 = s_i + s_j - 2 G  (masked: valid points, different components,
+//                              and i < j on the diagonal tile pairs)
+// updates both sides: the running minimum of every row i of I (over the
+// tile's columns) and of every column j of J (over the tile's rows) is merged
+// into a global per-point minimum with one atomic min per point and tile, and
+// every element whose lower bound can still beat that point's minimum is
+// appended to the point's global candidate list (screen.hpp gives the bound).
+// Lists are append-only: an entry stays even when a later minimum rules it
+// out (the recheck filters it), and a point whose list overflows is re-screened
+// by the row-sweep kernel starting from its final minimum.
+//
+// Tile pairs are enumerated in blocks of SB x SB tiles, and each XCD receives a
+// contiguous run of that order (workgroup ids are dealt to the eight XCDs in
+// turn), so the workgroups resident on one XCD share their I and J tiles in
+// its L2.
+//
+// Workgroup: 8 waves; wave (wi, wj) computes rows i in [64 wi, +64) x
+// columns j in [128 wj, +128) as 2 x 4 blocks of the transposed 32 x 32 MFMA
+// (MFMA rows = columns j, MFMA columns = rows i; result register q of lane l
+// is MFMA row 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32).
+#include <vector>
+
+#include "screen.hpp"
+
+namespace iso {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int PT = 256;  // points per tile
+
+template <bool BF16>
+struct PPrec;
+
+template <>
+struct PPrec<true> {
+    using T = uint16_t;
+    static constexpr int KC = 32;
+    static constexpr int LDK = KC + 8;
+    static constexpr int KSTEP = 16;
+    static constexpr int VEC = 8;
+};
+
+template <>
+struct PPrec<false> {
+    using T = float;
+    static constexpr int KC = 16;
+    static constexpr int LDK = KC + 4;
+    static constexpr int KSTEP = 2;
+    static constexpr int VEC = 1;
+};
+
+struct PairLDS {
+    uint32_t rmin[PT], cmin[PT];   // tile minima of rows (I) and columns (J)
+    float rthr[PT], cthr[PT];      // current global minima after the merge
+    float rE[PT], cE[PT];          // Emax of the tile's rows and columns
+    float csq[PT], crn[PT], cre[PT];
+    int32_t ccomp[PT];
+    float rrn[PT], rre[PT];
+    uint32_t chot[PT / 32];        // bit set: column's tile minimum is within its capture margin
+    int32_t rhot[PT];              // row's tile minimum is within its capture margin
+};
+
+template <bool BF16>
+__global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
+                                                         int64_t per_xcd, int64_t npairs) {
+    using P = PPrec<BF16>;
+    using T = typename P::T;
+    __shared__ PairLDS S;
+    __shared__ __attribute__((aligned(16))) T Aj[2][PT * P::LDK];  // column points j
+    __shared__ __attribute__((aligned(16))) T Bi[2][PT * P::LDK];  // row points i
+
+    // XCD-aware placement: workgroup b runs on XCD b mod 8
+    const int64_t b = blockIdx.x;
+    const int64_t idx = (b & 7) * per_xcd + (b >> 3);
+    if (idx >= npairs) return;
+    const int2 pr = pairs[idx];
+    const int64_t I0 = (int64_t)pr.x * PT, J0 = (int64_t)pr.y * PT;
+    const bool diag = pr.x == pr.y;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wi = w >> 1, wj = w & 1;  // wi in 0..3, wj in 0..1
+    const T *X = BF16 ? reinterpret_cast<const T *>(A.XB) : reinterpret_cast<const T *>(A.XT);
+    const int64_t d_pad = A.d_pad;
+
+    // tile constants
+    if (tid < PT) {
+        const int64_t i = I0 + tid, j = J0 + tid;
+        S.rmin[tid] = __float_as_uint(SCR_INF);
+        S.cmin[tid] = __float_as_uint(SCR_INF);
+        S.rE[tid] = i < A.n ? A.Emax[i] : 0.0f;
+        S.cE[tid] = j < A.n ? A.Emax[j] : 0.0f;
+        S.rrn[tid] = A.rn[i];
+        S.rre[tid] = A.re[i];
+        S.csq[tid] = A.sq[j];
+        S.crn[tid] = A.rn[j];
+        S.cre[tid] = A.re[j];
+        S.ccomp[tid] = A.comp[j];
+    }
+    float si[2];
+    int ci[2];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+        const int64_t i = I0 + 64 * wi + 32 * ib + (lane & 31);
+        si[ib] = A.sq[i];
+        ci[ib] = A.comp[i];
+    }
+
+    // staging: 256 rows x KC per operand, 4 sixteen-byte pieces per row; thread t
+    // moves the pieces of row (t mod 256) of operand (t div 256)
+    constexpr int CHUNK = 16 / sizeof(T);
+    constexpr int PARTS = P::KC / CHUNK;
+    static_assert(PARTS == 4, "staging assumes four 16-byte pieces per row");
+    const int prow = tid & (PT - 1);
+    const bool op_j = tid < PT;
+    const T *src = X + ((op_j ? J0 : I0) + prow) * d_pad;
+    uint4 rv0, rv1, rv2, rv3;
+#define ISO_PLOAD(K0)                                                                                       \
+    {                                                                                                      \
+        rv0 = *reinterpret_cast<const uint4 *>(src + (K0) + 0 * CHUNK);                                      \
+        rv1 = *reinterpret_cast<const uint4 *>(src + (K0) + 1 * CHUNK);                                      \
+        rv2 = *reinterpret_cast<const uint4 *>(src + (K0) + 2 * CHUNK);                                      \
+        rv3 = *reinterpret_cast<const uint4 *>(src + (K0) + 3 * CHUNK);                                      \
+    }
+#define ISO_PSTORE(BUF)                                                                                     \
+    {                                                                                                      \
+        T *dst = op_j ? &Aj[(BUF)][prow * P::LDK] : &Bi[(BUF)][prow * P::LDK];                               \
+        *reinterpret_cast<uint4 *>(dst + 0 * CHUNK) = rv0;                                                   \
+        *reinterpret_cast<uint4 *>(dst + 1 * CHUNK) = rv1;                                                   \
+        *reinterpret_cast<uint4 *>(dst + 2 * CHUNK) = rv2;                                                   \
+        *reinterpret_cast<uint4 *>(dst + 3 * CHUNK) = rv3;                                                   \
+    }
+
+    floatx16 acc[2][4];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[ib][jb][q] = 0.0f;
+
+    ISO_PLOAD(0)
+    ISO_PSTORE(0)
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < d_pad; k0 += P::KC) {
+        const bool has_next = k0 + P::KC < d_pad;
+        if (has_next) ISO_PLOAD(k0 + P::KC)
+        const T *Ab = Aj[buf];
+        const T *Bb = Bi[buf];
+#pragma unroll
+        for (int ks = 0; ks < P::KC; ks += P::KSTEP) {
+            const int kofs = ks + (lane >> 5) * P::VEC;
+            if constexpr (BF16) {
+                bf16x8 a[4], bb[2];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    a[jb] = *reinterpret_cast<const bf16x8 *>(&Ab[(128 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+                    bb[ib] = *reinterpret_cast<const bf16x8 *>(&Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+                        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);
+            } else {
+                float a[4], bb[2];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) a[jb] = Ab[(128 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs];
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) bb[ib] = Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs];
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+                        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);
+            }
+        }
+        if (has_next) ISO_PSTORE(buf ^ 1)
+        __syncthreads();
+        buf ^= 1;
+    }
+#undef ISO_PLOAD
+#undef ISO_PSTORE
+
+    // ---- epilogue 1: masked Dhat^2, tile minima of rows and columns (one pass
+    // over this lane's 64 columns, each used for the lane's two rows)
+    {
+        const int il0 = 64 * wi + (lane & 31), il1 = il0 + 32;
+        float m0 = SCR_INF, m1 = SCR_INF;
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int jl = 128 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const float sj = S.csq[jl];
+                const int cjj = S.ccomp[jl];
+                float v0 = screen_value(acc[0][jb][q], si[0], sj, ci[0], cjj);
+                float v1 = screen_value(acc[1][jb][q], si[1], sj, ci[1], cjj);
+                if (diag) {  // each unordered pair once on the diagonal
+                    if (jl <= il0) v0 = SCR_INF;
+                    if (jl <= il1) v1 = SCR_INF;
+                }
+                acc[0][jb][q] = v0;
+                acc[1][jb][q] = v1;
+                m0 = fminf(m0, v0);
+                m1 = fminf(m1, v1);
+                float v = fminf(v0, v1);
+#pragma unroll
+                for (int off = 1; off < 32; off <<= 1) v = fminf(v, __shfl_xor(v, off, 64));
+                if (((16 * jb + q) & 31) == (lane & 31) && v < SCR_INF) atomicMin(&S.cmin[jl], __float_as_uint(v));
+                __builtin_amdgcn_sched_barrier(0);  // one column live at a time
+            }
+        m0 = fminf(m0, __shfl_xor(m0, 32, 64));  // lanes l and l+32 hold the same rows
+        m1 = fminf(m1, __shfl_xor(m1, 32, 64));
+        if ((lane >> 5) == 0) {
+            if (m0 < SCR_INF) atomicMin(&S.rmin[il0], __float_as_uint(m0));
+            if (m1 < SCR_INF) atomicMin(&S.rmin[il1], __float_as_uint(m1));
+        }
+    }
+    __syncthreads();
+
+    // ---- epilogue 2: merge into the global minima; thresholds from the merged
+    // values; flag the rows and columns whose tile minimum can still be captured
+    if (tid < PT / 32) S.chot[tid] = 0u;
+    __syncthreads();
+    {
+        const int t = tid & (PT - 1);
+        const bool is_row = tid < PT;
+        const int64_t p = (is_row ? I0 : J0) + t;
+        float cur = SCR_INF;
+        const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
+        if (p < A.n) {
+            const uint32_t old = m < __float_as_uint(SCR_INF)
+                                     ? atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m)
+                                     : reinterpret_cast<const volatile uint32_t *>(A.best)[p];
+            cur = __uint_as_float(old < m ? old : m);
+        }
+        const float E = is_row ? S.rE[t] : S.cE[t];
+        const bool hot = p < A.n && __uint_as_float(m) <= (cur + 2.0f * E) * A.kappa;
+        if (is_row) {
+            S.rthr[t] = cur;
+            S.rhot[t] = hot ? 1 : 0;
+        } else {
+            S.cthr[t] = cur;
+            if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
+        }
+    }
+    __syncthreads();
+
+    // ---- epilogue 3: capture candidates (rows of hot rows, columns of hot columns)
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+        const int il = 64 * wi + 32 * ib + (lane & 31);
+        if (!S.rhot[il]) continue;
+        const int64_t i = I0 + il;
+        const float Ei = S.rE[il];
+        const float rb_ = S.rthr[il];
+        const float r_cheap = (rb_ + 2.0f * Ei) * A.kappa;
+        const float r_thr = (rb_ + Ei) * A.kappa;
+        const float ri = S.rrn[il], ei = S.rre[il];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const float v = acc[ib][jb][q];
+                if (!(v <= r_cheap)) continue;
+                const int jl = 128 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const float L = lower_of(v, pair_bound(A.bound, ri, S.crn[jl], ei, S.cre[jl]));
+                if (!(L <= r_thr)) continue;
+                const int pos = atomicAdd(&A.ccnt[i], 1);
+                if (pos < SCR_CAP) {
+                    A.cj[i * SCR_CAP + pos] = (int32_t)(J0 + jl);
+                    A.cl[i * SCR_CAP + pos] = L;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+    }
+    // columns: this wave's 128 columns are bits [128 wj, +128) of the hot set
+    const uint32_t h0 = S.chot[4 * wj + 0], h1 = S.chot[4 * wj + 1], h2 = S.chot[4 * wj + 2],
+                   h3 = S.chot[4 * wj + 3];
+    if (h0 | h1 | h2 | h3) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const uint32_t hw = jb == 0 ? h0 : (jb == 1 ? h1 : (jb == 2 ? h2 : h3));
+            if (!hw) continue;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);  // column within the 32-block
+                if (!((hw >> jc) & 1u)) continue;
+                const int jl = 128 * wj + 32 * jb + jc;
+                const int64_t j = J0 + jl;
+                const float Ej = S.cE[jl];
+                const float cb = S.cthr[jl];
+                const float c_cheap = (cb + 2.0f * Ej) * A.kappa;
+                const float c_thr = (cb + Ej) * A.kappa;
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    const float v = acc[ib][jb][q];
+                    if (!(v <= c_cheap)) continue;
+                    const int il = 64 * wi + 32 * ib + (lane & 31);
+                    const float L = lower_of(v, pair_bound(A.bound, S.rrn[il], S.crn[jl], S.rre[il], S.cre[jl]));
+                    if (!(L <= c_thr)) continue;
+                    const int pos = atomicAdd(&A.ccnt[j], 1);
+                    if (pos < SCR_CAP) {
+                        A.cj[j * SCR_CAP + pos] = (int32_t)(I0 + il);
+                        A.cl[j * SCR_CAP + pos] = L;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int64_t pair_tile() { return PT; }
+
+// Tile pairs (I <= J) of nt tiles in blocks of SB x SB tiles.
+std::vector<int2> make_pair_order(int64_t nt) {
+    constexpr int64_t SB = 4;
+    std::vector<int2> out;
+    out.reserve((size_t)(nt * (nt + 1) / 2));
+    const int64_t nb = (nt + SB - 1) / SB;
+    for (int64_t bi = 0; bi < nb; ++bi)
+        for (int64_t bj = bi; bj < nb; ++bj)
+            for (int64_t I = bi * SB; I < (bi + 1) * SB && I < nt; ++I)
+                for (int64_t J = bj * SB; J < (bj + 1) * SB && J < nt; ++J)
+                    if (I <= J) out.push_back(make_int2((int)I, (int)J));
+    return out;
+}
+
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, bool bf16, hipStream_t s) {
+    const int64_t per_xcd = (npairs + 7) / 8;
+    const unsigned blocks = (unsigned)(per_xcd * 8);
+    if (bf16)
+        hipLaunchKernelGGL(k_screen_pairs<true>, dim3(blocks), dim3(512), 0, s, A, pairs, per_xcd, npairs);
+    else
+        hipLaunchKernelGGL(k_screen_pairs<false>, dim3(blocks), dim3(512), 0, s, A, pairs, per_xcd, npairs);
+    LAUNCH_CHECK();
+}
+
+}  // namespace iso
