@@ -34,7 +34,11 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int PT = 256;  // points per tile
+constexpr int PT = 256;     // points per tile
+constexpr int NSTAGE = 4;   // LDS stages of the K pipeline (loads run NSTAGE-1 chunks ahead)
+
+// s_waitcnt immediate waiting for vmcnt <= n (expcnt and lgkmcnt left at their maxima)
+#define VMCNT(n) (((n) & 0xF) | (((n) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
 
 template <bool BF16>
 struct PPrec;
@@ -74,8 +78,14 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
     using P = PPrec<BF16>;
     using T = typename P::T;
     __shared__ PairLDS S;
-    __shared__ __attribute__((aligned(16))) T Aj[2][PT * P::LDK];  // column points j
-    __shared__ __attribute__((aligned(16))) T Bi[2][PT * P::LDK];  // row points i
+    // NSTAGE staging buffers of one K chunk: rows 0..255 = tile J (columns j),
+    // rows 256..511 = tile I (rows i); 64 bytes per row in four 16-byte slots,
+    // slot (row, part) at row * 4 + (part xor ((row >> 2) & 3)), which makes
+    // the MFMA fragment reads (16 consecutive rows, one part) bank-conflict free.
+    __shared__ __attribute__((aligned(16))) uint4 stage0[2 * PT * 4];
+    __shared__ __attribute__((aligned(16))) uint4 stage1[2 * PT * 4];
+    __shared__ __attribute__((aligned(16))) uint4 stage2[2 * PT * 4];
+    __shared__ __attribute__((aligned(16))) uint4 stage3[2 * PT * 4];
 
     // XCD-aware placement: workgroup b runs on XCD b mod 8
     const int64_t b = blockIdx.x;
@@ -114,29 +124,25 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         ci[ib] = A.comp[i];
     }
 
-    // staging: 256 rows x KC per operand, 4 sixteen-byte pieces per row; thread t
-    // moves the pieces of row (t mod 256) of operand (t div 256)
-    constexpr int CHUNK = 16 / sizeof(T);
-    constexpr int PARTS = P::KC / CHUNK;
-    static_assert(PARTS == 4, "staging assumes four 16-byte pieces per row");
-    const int prow = tid & (PT - 1);
-    const bool op_j = tid < PT;
-    const T *src = X + ((op_j ? J0 : I0) + prow) * d_pad;
-    uint4 rv0, rv1, rv2, rv3;
-#define ISO_PLOAD(K0)                                                                                       \
-    {                                                                                                      \
-        rv0 = *reinterpret_cast<const uint4 *>(src + (K0) + 0 * CHUNK);                                      \
-        rv1 = *reinterpret_cast<const uint4 *>(src + (K0) + 1 * CHUNK);                                      \
-        rv2 = *reinterpret_cast<const uint4 *>(src + (K0) + 2 * CHUNK);                                      \
-        rv3 = *reinterpret_cast<const uint4 *>(src + (K0) + 3 * CHUNK);                                      \
+    // asynchronous staging: each wave moves four 1 KB runs of slots per chunk
+    // with global_load_lds_dwordx4 (lane L of a run fills slot base + L)
+    constexpr int CHUNK = 16 / sizeof(T);  // elements per slot
+    static_assert(P::KC * sizeof(T) == 64, "one K chunk is 64 bytes per row");
+    const T *srcp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int slot = (w * 4 + r) * 64 + lane;
+        const int row = slot >> 2;
+        const int part = (slot & 3) ^ ((row >> 2) & 3);
+        const int64_t g = row < PT ? J0 + row : I0 + (row - PT);
+        srcp[r] = X + g * d_pad + part * CHUNK;
     }
-#define ISO_PSTORE(BUF)                                                                                     \
-    {                                                                                                      \
-        T *dst = op_j ? &Aj[(BUF)][prow * P::LDK] : &Bi[(BUF)][prow * P::LDK];                               \
-        *reinterpret_cast<uint4 *>(dst + 0 * CHUNK) = rv0;                                                   \
-        *reinterpret_cast<uint4 *>(dst + 1 * CHUNK) = rv1;                                                   \
-        *reinterpret_cast<uint4 *>(dst + 2 * CHUNK) = rv2;                                                   \
-        *reinterpret_cast<uint4 *>(dst + 3 * CHUNK) = rv3;                                                   \
+    const int nchunks = (int)(d_pad / P::KC);
+#define ISO_ISSUE(STG, C)                                                                                     \
+    {                                                                                                        \
+        _Pragma("unroll") for (int r = 0; r < 4; ++r) __builtin_amdgcn_global_load_lds(                     \
+            (const void *)(srcp[r] + (int64_t)(C) * P::KC),                                                  \
+            (__attribute__((address_space(3))) void *)&STG[(w * 4 + r) * 64], 16, 0, 0);                   \
     }
 
     floatx16 acc[2][4];
@@ -147,50 +153,82 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[ib][jb][q] = 0.0f;
 
-    ISO_PLOAD(0)
-    ISO_PSTORE(0)
-    __syncthreads();
-    int buf = 0;
-    for (int64_t k0 = 0; k0 < d_pad; k0 += P::KC) {
-        const bool has_next = k0 + P::KC < d_pad;
-        if (has_next) ISO_PLOAD(k0 + P::KC)
-        const T *Ab = Aj[buf];
-        const T *Bb = Bi[buf];
-#pragma unroll
-        for (int ks = 0; ks < P::KC; ks += P::KSTEP) {
-            const int kofs = ks + (lane >> 5) * P::VEC;
-            if constexpr (BF16) {
-                bf16x8 a[4], bb[2];
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb)
-                    a[jb] = *reinterpret_cast<const bf16x8 *>(&Ab[(128 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs]);
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib)
-                    bb[ib] = *reinterpret_cast<const bf16x8 *>(&Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs]);
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-                        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);
-            } else {
-                float a[4], bb[2];
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) a[jb] = Ab[(128 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs];
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib) bb[ib] = Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs];
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-                        acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);
-            }
-        }
-        if (has_next) ISO_PSTORE(buf ^ 1)
-        __syncthreads();
-        buf ^= 1;
+    // fragment slot of (operand row, k offset in elements) in a stage
+    auto frag_slot = [](int row, int kel) {
+        const int part = (kel * (int)sizeof(T)) >> 4;
+        return row * 4 + (part ^ ((row >> 2) & 3));
+    };
+
+    // One pipeline step on chunk C held in stage SB: wait for it (chunks C+1, C+2
+    // may stay in flight), barrier (no fence: the DMA data is in LDS once the
+    // issuing wave's vmcnt has dropped), refill stage SN with chunk C+3, compute.
+#define ISO_STEP(SB, SN, C)                                                                                   \
+    if ((C) < nchunks) {                                                                                     \
+        if ((C) + 2 < nchunks)                                                                               \
+            __builtin_amdgcn_s_waitcnt(VMCNT(8));                                                            \
+        else if ((C) + 1 < nchunks)                                                                          \
+            __builtin_amdgcn_s_waitcnt(VMCNT(4));                                                            \
+        else                                                                                                 \
+            __builtin_amdgcn_s_waitcnt(VMCNT(0));                                                            \
+        __builtin_amdgcn_s_barrier();                                                                        \
+        if ((C) + 3 < nchunks) ISO_ISSUE(SN, (C) + 3)                                                        \
+        ISO_COMPUTE(SB)                                                                                      \
     }
-#undef ISO_PLOAD
-#undef ISO_PSTORE
+
+    if constexpr (BF16) {
+#define ISO_COMPUTE(SB)                                                                                       \
+    _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
+        const int kel = ks + (lane >> 5) * P::VEC;                                                             \
+        bf16x8 a[4], bb[2];                                                                                   \
+        _Pragma("unroll") for (int jb = 0; jb < 4; ++jb) {                                                    \
+            const uint4 v = SB[frag_slot(128 * wj + 32 * jb + (lane & 31), kel)];                              \
+            a[jb] = *reinterpret_cast<const bf16x8 *>(&v);                                                    \
+        }                                                                                                     \
+        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) {                                                    \
+            const uint4 v = SB[frag_slot(PT + 64 * wi + 32 * ib + (lane & 31), kel)];                          \
+            bb[ib] = *reinterpret_cast<const bf16x8 *>(&v);                                                   \
+        }                                                                                                     \
+        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int jb = 0; jb < 4; ++jb)     \
+            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);        \
+    }
+        if (0 < nchunks) ISO_ISSUE(stage0, 0)
+        if (1 < nchunks) ISO_ISSUE(stage1, 1)
+        if (2 < nchunks) ISO_ISSUE(stage2, 2)
+        for (int c = 0; c < nchunks; c += 4) {
+            ISO_STEP(stage0, stage3, c)
+            ISO_STEP(stage1, stage0, c + 1)
+            ISO_STEP(stage2, stage1, c + 2)
+            ISO_STEP(stage3, stage2, c + 3)
+        }
+#undef ISO_COMPUTE
+    } else {
+#define ISO_COMPUTE(SB)                                                                                       \
+    _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
+        const int kel = ks + (lane >> 5) * P::VEC;                                                             \
+        const float *sf = reinterpret_cast<const float *>(SB);                                                \
+        const int within = kel & 3;                                                                           \
+        float a[4], bb[2];                                                                                    \
+        _Pragma("unroll") for (int jb = 0; jb < 4; ++jb) a[jb] =                                              \
+            sf[frag_slot(128 * wj + 32 * jb + (lane & 31), kel) * 4 + within];                                 \
+        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) bb[ib] =                                             \
+            sf[frag_slot(PT + 64 * wi + 32 * ib + (lane & 31), kel) * 4 + within];                             \
+        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int jb = 0; jb < 4; ++jb)     \
+            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);           \
+    }
+        if (0 < nchunks) ISO_ISSUE(stage0, 0)
+        if (1 < nchunks) ISO_ISSUE(stage1, 1)
+        if (2 < nchunks) ISO_ISSUE(stage2, 2)
+        for (int c = 0; c < nchunks; c += 4) {
+            ISO_STEP(stage0, stage3, c)
+            ISO_STEP(stage1, stage0, c + 1)
+            ISO_STEP(stage2, stage1, c + 2)
+            ISO_STEP(stage3, stage2, c + 3)
+        }
+#undef ISO_COMPUTE
+    }
+#undef ISO_STEP
+#undef ISO_ISSUE
+    __syncthreads();  // all DMA traffic retired before LDS is reused by the epilogue
 
     // ---- epilogue 1: masked Dhat^2, tile minima of rows and columns (one pass
     // over this lane's 64 columns, each used for the lane's two rows)
