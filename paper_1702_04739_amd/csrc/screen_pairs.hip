@@ -72,6 +72,16 @@ struct PairLDS {
     int32_t rhot[PT];              // row's tile minimum is within its capture margin
 };
 
+// Minimum over the 32 lanes of each half wave (every lane receives it): DPP
+// min within quads, 8-lane and 16-lane rows, then one swap across the rows.
+__device__ __forceinline__ float min32(float v) {
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false)));   // quad xor 1
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false)));   // quad xor 2
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)));  // half-row mirror
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false)));  // row mirror
+    return fminf(v, __shfl_xor(v, 16, 64));
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
                                                          int64_t per_xcd, int64_t npairs) {
@@ -252,11 +262,9 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
                 acc[1][jb][q] = v1;
                 m0 = fminf(m0, v0);
                 m1 = fminf(m1, v1);
-                float v = fminf(v0, v1);
-#pragma unroll
-                for (int off = 1; off < 32; off <<= 1) v = fminf(v, __shfl_xor(v, off, 64));
+                const float v = min32(fminf(v0, v1));
                 if (((16 * jb + q) & 31) == (lane & 31) && v < SCR_INF) atomicMin(&S.cmin[jl], __float_as_uint(v));
-                __builtin_amdgcn_sched_barrier(0);  // one column live at a time
+                if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the columns in flight
             }
         m0 = fminf(m0, __shfl_xor(m0, 32, 64));  // lanes l and l+32 hold the same rows
         m1 = fminf(m1, __shfl_xor(m1, 32, 64));
