@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
     }
     if (lane == 0) {
         if (q != GRID_NONE) atomicMin(grid_min, q);
-        sq[i] = s;
+        sq[i] = i < n ? s : __builtin_huge_valf();  // padding: every Dhat^2 with it is +inf
         const float r = __double2float_ru(sqrt(m2) * (1.0 + 0x1p-40));
         const float e = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40));
         rn[i] = r;

@@ -19,8 +19,8 @@
 // turn), so the workgroups resident on one XCD share their I and J tiles in
 // its L2.
 //
-// Workgroup: 8 waves; wave (wi, wj) computes rows i in [64 wi, +64) x
-// columns j in [128 wj, +128) as 2 x 4 blocks of the transposed 32 x 32 MFMA
+// Workgroup: 8 waves; wave (wi, wj) computes rows i in [128 wi, +128) x
+// columns j in [64 wj, +64) as 4 x 2 blocks of the transposed 32 x 32 MFMA
 // (MFMA rows = columns j, MFMA columns = rows i; result register q of lane l
 // is MFMA row 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32).
 #include <vector>
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int wi = w >> 1, wj = w & 1;  // wi in 0..3, wj in 0..1
+    const int wi = w >> 2, wj = w & 3;  // wi in 0..1 (128 rows), wj in 0..3 (64 columns)
     const T *X = BF16 ? reinterpret_cast<const T *>(A.XB) : reinterpret_cast<const T *>(A.XT);
     const int64_t d_pad = A.d_pad;
 
@@ -125,11 +125,11 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         S.cre[tid] = A.re[j];
         S.ccomp[tid] = A.comp[j];
     }
-    float si[2];
-    int ci[2];
+    float si[4];
+    int ci[4];
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib) {
-        const int64_t i = I0 + 64 * wi + 32 * ib + (lane & 31);
+    for (int ib = 0; ib < 4; ++ib) {
+        const int64_t i = I0 + 128 * wi + 32 * ib + (lane & 31);
         si[ib] = A.sq[i];
         ci[ib] = A.comp[i];
     }
@@ -155,11 +155,11 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
             (__attribute__((address_space(3))) void *)&STG[(w * 4 + r) * 64], 16, 0, 0);                   \
     }
 
-    floatx16 acc[2][4];
+    floatx16 acc[4][2];
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+    for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb)
+        for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[ib][jb][q] = 0.0f;
 
@@ -189,16 +189,16 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 #define ISO_COMPUTE(SB)                                                                                       \
     _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
         const int kel = ks + (lane >> 5) * P::VEC;                                                             \
-        bf16x8 a[4], bb[2];                                                                                   \
-        _Pragma("unroll") for (int jb = 0; jb < 4; ++jb) {                                                    \
-            const uint4 v = SB[frag_slot(128 * wj + 32 * jb + (lane & 31), kel)];                              \
+        bf16x8 a[2], bb[4];                                                                                   \
+        _Pragma("unroll") for (int jb = 0; jb < 2; ++jb) {                                                    \
+            const uint4 v = SB[frag_slot(64 * wj + 32 * jb + (lane & 31), kel)];                               \
             a[jb] = *reinterpret_cast<const bf16x8 *>(&v);                                                    \
         }                                                                                                     \
-        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) {                                                    \
-            const uint4 v = SB[frag_slot(PT + 64 * wi + 32 * ib + (lane & 31), kel)];                          \
+        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) {                                                    \
+            const uint4 v = SB[frag_slot(PT + 128 * wi + 32 * ib + (lane & 31), kel)];                         \
             bb[ib] = *reinterpret_cast<const bf16x8 *>(&v);                                                   \
         }                                                                                                     \
-        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int jb = 0; jb < 4; ++jb)     \
+        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) _Pragma("unroll") for (int jb = 0; jb < 2; ++jb)     \
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);        \
     }
         if (0 < nchunks) ISO_ISSUE(stage0, 0)
@@ -217,12 +217,12 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         const int kel = ks + (lane >> 5) * P::VEC;                                                             \
         const float *sf = reinterpret_cast<const float *>(SB);                                                \
         const int within = kel & 3;                                                                           \
-        float a[4], bb[2];                                                                                    \
-        _Pragma("unroll") for (int jb = 0; jb < 4; ++jb) a[jb] =                                              \
-            sf[frag_slot(128 * wj + 32 * jb + (lane & 31), kel) * 4 + within];                                 \
-        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) bb[ib] =                                             \
-            sf[frag_slot(PT + 64 * wi + 32 * ib + (lane & 31), kel) * 4 + within];                             \
-        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int jb = 0; jb < 4; ++jb)     \
+        float a[2], bb[4];                                                                                    \
+        _Pragma("unroll") for (int jb = 0; jb < 2; ++jb) a[jb] =                                              \
+            sf[frag_slot(64 * wj + 32 * jb + (lane & 31), kel) * 4 + within];                                  \
+        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) bb[ib] =                                             \
+            sf[frag_slot(PT + 128 * wi + 32 * ib + (lane & 31), kel) * 4 + within];                            \
+        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) _Pragma("unroll") for (int jb = 0; jb < 2; ++jb)     \
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);           \
     }
         if (0 < nchunks) ISO_ISSUE(stage0, 0)
@@ -240,37 +240,37 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 #undef ISO_ISSUE
     __syncthreads();  // all DMA traffic retired before LDS is reused by the epilogue
 
-    // ---- epilogue 1: masked Dhat^2, tile minima of rows and columns (one pass
-    // over this lane's 64 columns, each used for the lane's two rows)
+    // ---- epilogue 1: masked Dhat^2 (padding has s = +inf), tile minima of rows
+    // (in-lane over the lane's 32 columns, then lanes l, l+32) and of columns
+    // (in-lane over the lane's 4 rows, then the 32 lanes of the half wave)
     {
-        const int il0 = 64 * wi + (lane & 31), il1 = il0 + 32;
-        float m0 = SCR_INF, m1 = SCR_INF;
+        float m[4] = {SCR_INF, SCR_INF, SCR_INF, SCR_INF};
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb)
+        for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const int jl = 128 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
                 const float sj = S.csq[jl];
                 const int cjj = S.ccomp[jl];
-                float v0 = screen_value(acc[0][jb][q], si[0], sj, ci[0], cjj);
-                float v1 = screen_value(acc[1][jb][q], si[1], sj, ci[1], cjj);
-                if (diag) {  // each unordered pair once on the diagonal
-                    if (jl <= il0) v0 = SCR_INF;
-                    if (jl <= il1) v1 = SCR_INF;
+                float cmin = SCR_INF;
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) {
+                    const float t = fmaxf(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj), 0.0f);
+                    float v = (cjj == ci[ib]) ? SCR_INF : t;
+                    if (diag && jl <= 128 * wi + 32 * ib + (lane & 31)) v = SCR_INF;  // each pair once
+                    acc[ib][jb][q] = v;
+                    m[ib] = fminf(m[ib], v);
+                    cmin = fminf(cmin, v);
                 }
-                acc[0][jb][q] = v0;
-                acc[1][jb][q] = v1;
-                m0 = fminf(m0, v0);
-                m1 = fminf(m1, v1);
-                const float v = min32(fminf(v0, v1));
+                const float v = min32(cmin);
                 if (((16 * jb + q) & 31) == (lane & 31) && v < SCR_INF) atomicMin(&S.cmin[jl], __float_as_uint(v));
                 if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the columns in flight
             }
-        m0 = fminf(m0, __shfl_xor(m0, 32, 64));  // lanes l and l+32 hold the same rows
-        m1 = fminf(m1, __shfl_xor(m1, 32, 64));
-        if ((lane >> 5) == 0) {
-            if (m0 < SCR_INF) atomicMin(&S.rmin[il0], __float_as_uint(m0));
-            if (m1 < SCR_INF) atomicMin(&S.rmin[il1], __float_as_uint(m1));
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            const float mm = fminf(m[ib], __shfl_xor(m[ib], 32, 64));  // lanes l and l+32 hold the same rows
+            if ((lane >> 5) == 0 && mm < SCR_INF)
+                atomicMin(&S.rmin[128 * wi + 32 * ib + (lane & 31)], __float_as_uint(mm));
         }
     }
     __syncthreads();
@@ -286,9 +286,8 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         float cur = SCR_INF;
         const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
         if (p < A.n) {
-            const uint32_t old = m < __float_as_uint(SCR_INF)
-                                     ? atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m)
-                                     : reinterpret_cast<const volatile uint32_t *>(A.best)[p];
+            uint32_t old = reinterpret_cast<const volatile uint32_t *>(A.best)[p];
+            if (m < old) old = atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m);  // only when it can lower it
             cur = __uint_as_float(old < m ? old : m);
         }
         const float E = is_row ? S.rE[t] : S.cE[t];
@@ -305,8 +304,8 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 
     // ---- epilogue 3: capture candidates (rows of hot rows, columns of hot columns)
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib) {
-        const int il = 64 * wi + 32 * ib + (lane & 31);
+    for (int ib = 0; ib < 4; ++ib) {
+        const int il = 128 * wi + 32 * ib + (lane & 31);
         if (!S.rhot[il]) continue;
         const int64_t i = I0 + il;
         const float Ei = S.rE[il];
@@ -315,12 +314,12 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         const float r_thr = (rb_ + Ei) * A.kappa;
         const float ri = S.rrn[il], ei = S.rre[il];
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb)
+        for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const float v = acc[ib][jb][q];
                 if (!(v <= r_cheap)) continue;
-                const int jl = 128 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
                 const float L = lower_of(v, pair_bound(A.bound, ri, S.crn[jl], ei, S.cre[jl]));
                 if (!(L <= r_thr)) continue;
                 const int pos = atomicAdd(&A.ccnt[i], 1);
@@ -331,29 +330,28 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
                 __builtin_amdgcn_sched_barrier(0);
             }
     }
-    // columns: this wave's 128 columns are bits [128 wj, +128) of the hot set
-    const uint32_t h0 = S.chot[4 * wj + 0], h1 = S.chot[4 * wj + 1], h2 = S.chot[4 * wj + 2],
-                   h3 = S.chot[4 * wj + 3];
-    if (h0 | h1 | h2 | h3) {
+    // columns: this wave's 64 columns are bits [64 wj, +64) of the hot set
+    const uint32_t h0 = S.chot[2 * wj + 0], h1 = S.chot[2 * wj + 1];
+    if (h0 | h1) {
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const uint32_t hw = jb == 0 ? h0 : (jb == 1 ? h1 : (jb == 2 ? h2 : h3));
+        for (int jb = 0; jb < 2; ++jb) {
+            const uint32_t hw = jb == 0 ? h0 : h1;
             if (!hw) continue;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);  // column within the 32-block
                 if (!((hw >> jc) & 1u)) continue;
-                const int jl = 128 * wj + 32 * jb + jc;
+                const int jl = 64 * wj + 32 * jb + jc;
                 const int64_t j = J0 + jl;
                 const float Ej = S.cE[jl];
                 const float cb = S.cthr[jl];
                 const float c_cheap = (cb + 2.0f * Ej) * A.kappa;
                 const float c_thr = (cb + Ej) * A.kappa;
 #pragma unroll
-                for (int ib = 0; ib < 2; ++ib) {
+                for (int ib = 0; ib < 4; ++ib) {
                     const float v = acc[ib][jb][q];
                     if (!(v <= c_cheap)) continue;
-                    const int il = 64 * wi + 32 * ib + (lane & 31);
+                    const int il = 128 * wi + 32 * ib + (lane & 31);
                     const float L = lower_of(v, pair_bound(A.bound, S.rrn[il], S.crn[jl], S.rre[il], S.cre[jl]));
                     if (!(L <= c_thr)) continue;
                     const int pos = atomicAdd(&A.ccnt[j], 1);
