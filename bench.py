@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
 WORKLOAD = 3
 PEAKS_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
+# one screen launch = the diagonal tile pairs' dispatch followed by the off-diagonal one
+SCREEN_KERNEL = "k_screen_pairs<%s> (diagonal + off-diagonal dispatch)"
 SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/screen_pairs.hip", "paper_1702_04739_amd/csrc/screen.hpp"]
 
 
@@ -60,30 +62,34 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
     import csv
     import glob
 
+    prefix = "k_screen_pairs<%s, " % ("true" if precision == "bf16" else "false")
+
     def per_kernel(d, counter):
-        vals, copy = [], None
+        """Summed counter over the screen's dispatches (diagonal and
+        off-diagonal), the number of screen rounds, and the copy's value."""
+        total, rounds, copy = 0.0, 0, None
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
                 if r["Counter_Name"] != counter:
                     continue
                 v = float(r["Counter_Value"])
-                sweep = "k_screen_pairs<%s>" % ("true" if precision == "bf16" else "false")
-                if sweep in r["Kernel_Name"]:
-                    vals.append(v)
+                if prefix in r["Kernel_Name"]:
+                    total += v
+                    rounds += 1 if (prefix + "false") in r["Kernel_Name"] else 0
                 elif "copyBuffer" in r["Kernel_Name"] and copy is None and v > 0.25 * copy_mib * 1024:
                     copy = v
-        return vals, copy
+        return total, rounds, copy
 
-    fv, fc = per_kernel(fetch_dir, "FETCH_SIZE")
-    wv, wc = per_kernel(write_dir, "WRITE_SIZE")
+    ft, fr, fc = per_kernel(fetch_dir, "FETCH_SIZE")
+    wt, wr, wc = per_kernel(write_dir, "WRITE_SIZE")
     nbytes = copy_mib * (1 << 20)
     f_scale = nbytes / (fc * 1024.0)
     w_scale = nbytes / (wc * 1024.0)
-    fetch = sum(fv) / len(fv) * 1024.0 * f_scale
-    write = sum(wv) / len(wv) * 1024.0 * w_scale
-    rec = {"kernel": "k_screen_pairs<%s>" % precision, "source_sha": screen_source_sha(),
+    fetch = ft / fr * 1024.0 * f_scale
+    write = wt / wr * 1024.0 * w_scale
+    rec = {"kernel": SCREEN_KERNEL % precision, "source_sha": screen_source_sha(),
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-           "hbm_bytes_per_launch": fetch + write, "launches": len(fv),
+           "hbm_bytes_per_launch": fetch + write, "launches": fr,
            "copy_calibration": {"bytes": nbytes, "fetch_kib": fc, "write_kib": wc, "fetch_scale": f_scale,
                                 "write_scale": w_scale}}
     return rec
@@ -208,7 +214,7 @@ def main():
                    "k": k, "sigma": "median MST edge", "screen": args.precision, "recheck": args.recheck,
                    "tree": "f64", "parallelism": "none"},
         "roofline": {
-            "kernel": "k_screen_pairs<%s>" % args.precision,
+            "kernel": SCREEN_KERNEL % args.precision,
             "bound": bound,
             "achieved": achieved,
             "peak": peak,

@@ -36,6 +36,18 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int PT = 256;     // points per tile
 constexpr int NSTAGE = 4;   // LDS stages of the K pipeline (loads run NSTAGE-1 chunks ahead)
+#ifndef PAIR_WI
+#define PAIR_WI 2           // waves along the tile's rows
+#endif
+#ifndef PAIR_WJ
+#define PAIR_WJ 4           // waves along the tile's columns
+#endif
+#ifndef PAIR_SB
+#define PAIR_SB 8           // tile pairs are ordered in blocks of PAIR_SB x PAIR_SB tiles
+#endif
+#ifndef PAIR_SETPRIO
+#define PAIR_SETPRIO 0      // raise the wave priority while it issues MFMAs
+#endif
 
 // s_waitcnt immediate waiting for vmcnt <= n (expcnt and lgkmcnt left at their maxima)
 #define VMCNT(n) (((n) & 0xF) | (((n) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
@@ -72,19 +84,34 @@ struct PairLDS {
     int32_t rhot[PT];              // row's tile minimum is within its capture margin
 };
 
-// Minimum over the 32 lanes of each half wave (every lane receives it): DPP
-// min within quads, 8-lane and 16-lane rows, then one swap across the rows.
-__device__ __forceinline__ float min32(float v) {
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false)));   // quad xor 1
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false)));   // quad xor 2
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)));  // half-row mirror
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false)));  // row mirror
-    return fminf(v, __shfl_xor(v, 16, 64));
+constexpr uint32_t INF_BITS = 0x7F800000u;  // +inf; every screen value is a nonnegative float or +inf
+
+// Minimum over the 32 lanes of each half wave of nonnegative floats compared
+// as unsigned bit patterns (every lane receives it): DPP min within quads,
+// 8-lane and 16-lane rows, then a swap of neighbouring 16-lane rows.
+__device__ __forceinline__ uint32_t min32(uint32_t v) {
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0xB1, 0xF, 0xF, false));   // quad xor 1
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x4E, 0xF, 0xF, false));   // quad xor 2
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x141, 0xF, 0xF, false));  // half-row mirror
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x140, 0xF, 0xF, false));  // row mirror
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);  // rows 2k and 2k+1 exchange
+    return min(v, min((uint32_t)r[0], (uint32_t)r[1]));
 }
 
-template <bool BF16>
-__global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
-                                                         int64_t per_xcd, int64_t npairs) {
+// Minimum of lanes l and l xor 32.
+__device__ __forceinline__ uint32_t min_halves(uint32_t v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return min(v, min((uint32_t)r[0], (uint32_t)r[1]));
+}
+
+template <bool BF16, bool DIAG, int WI, int WJ>
+__global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
+                                                                int64_t per_xcd, int64_t npairs) {
+    constexpr int NW = WI * WJ;           // waves
+    constexpr int RW = PT / WI;           // rows per wave
+    constexpr int CW = PT / WJ;           // columns per wave
+    constexpr int NIB = RW / 32, NJB = CW / 32;
+    constexpr int RUNS = 2 * PT * 4 / 64 / NW;  // 1 KB DMA runs per wave and chunk
     using P = PPrec<BF16>;
     using T = typename P::T;
     __shared__ PairLDS S;
@@ -103,16 +130,16 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
     if (idx >= npairs) return;
     const int2 pr = pairs[idx];
     const int64_t I0 = (int64_t)pr.x * PT, J0 = (int64_t)pr.y * PT;
-    const bool diag = pr.x == pr.y;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
-    const int wi = w >> 2, wj = w & 3;  // wi in 0..1 (128 rows), wj in 0..3 (64 columns)
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wi = w / WJ, wj = w % WJ;
+    static_assert(NJB == 2, "each lane owns one of the wave's 64 columns");
     const T *X = BF16 ? reinterpret_cast<const T *>(A.XB) : reinterpret_cast<const T *>(A.XT);
     const int64_t d_pad = A.d_pad;
 
     // tile constants
-    if (tid < PT) {
+    for (int tid = threadIdx.x; tid < PT; tid += 64 * NW) {
         const int64_t i = I0 + tid, j = J0 + tid;
         S.rmin[tid] = __float_as_uint(SCR_INF);
         S.cmin[tid] = __float_as_uint(SCR_INF);
@@ -125,11 +152,22 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         S.cre[tid] = A.re[j];
         S.ccomp[tid] = A.comp[j];
     }
-    float si[4];
-    int ci[4];
+    // the global minima of the tile's rows (u < PT) and columns, read now so the
+    // load is hidden behind the K loop; a value read early is an upper bound of
+    // the current one, which only loosens the capture threshold
+    constexpr int NPRE = 2 * PT / (64 * NW);
+    uint32_t bpre[NPRE];
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib) {
-        const int64_t i = I0 + 128 * wi + 32 * ib + (lane & 31);
+    for (int e = 0; e < NPRE; ++e) {
+        const int u = tid + e * 64 * NW;
+        const int64_t p = (u < PT ? I0 : J0) + (u & (PT - 1));
+        bpre[e] = p < A.n ? reinterpret_cast<const volatile uint32_t *>(A.best)[p] : INF_BITS;
+    }
+    float si[NIB];
+    int ci[NIB];
+#pragma unroll
+    for (int ib = 0; ib < NIB; ++ib) {
+        const int64_t i = I0 + RW * wi + 32 * ib + (lane & 31);
         si[ib] = A.sq[i];
         ci[ib] = A.comp[i];
     }
@@ -138,28 +176,30 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
     // with global_load_lds_dwordx4 (lane L of a run fills slot base + L)
     constexpr int CHUNK = 16 / sizeof(T);  // elements per slot
     static_assert(P::KC * sizeof(T) == 64, "one K chunk is 64 bytes per row");
-    const T *srcp[4];
+    const char *XJb = reinterpret_cast<const char *>(X + J0 * d_pad);
+    const char *XIb = reinterpret_cast<const char *>(X + I0 * d_pad);
+    uint32_t soff[RUNS];  // byte offset of this lane's slot source within its tile
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int slot = (w * 4 + r) * 64 + lane;
+    for (int r = 0; r < RUNS; ++r) {
+        const int slot = (w * RUNS + r) * 64 + lane;
         const int row = slot >> 2;
         const int part = (slot & 3) ^ ((row >> 2) & 3);
-        const int64_t g = row < PT ? J0 + row : I0 + (row - PT);
-        srcp[r] = X + g * d_pad + part * CHUNK;
+        soff[r] = (uint32_t)((((int64_t)(row & (PT - 1))) * d_pad + part * CHUNK) * (int64_t)sizeof(T));
     }
     const int nchunks = (int)(d_pad / P::KC);
+    // a run covers 16 rows, all of tile J (runs 0..15) or all of tile I
 #define ISO_ISSUE(STG, C)                                                                                     \
     {                                                                                                        \
-        _Pragma("unroll") for (int r = 0; r < 4; ++r) __builtin_amdgcn_global_load_lds(                     \
-            (const void *)(srcp[r] + (int64_t)(C) * P::KC),                                                  \
-            (__attribute__((address_space(3))) void *)&STG[(w * 4 + r) * 64], 16, 0, 0);                   \
+        _Pragma("unroll") for (int r = 0; r < RUNS; ++r) __builtin_amdgcn_global_load_lds(                  \
+            (const void *)((w * RUNS + r < PT / 16 ? XJb : XIb) + (int64_t)(C) * 64 + soff[r]),              \
+            (__attribute__((address_space(3))) void *)&STG[(w * RUNS + r) * 64], 16, 0, 0);                \
     }
 
-    floatx16 acc[4][2];
+    floatx16 acc[NIB][NJB];
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
+    for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
+        for (int jb = 0; jb < NJB; ++jb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[ib][jb][q] = 0.0f;
 
@@ -175,9 +215,9 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 #define ISO_STEP(SB, SN, C)                                                                                   \
     if ((C) < nchunks) {                                                                                     \
         if ((C) + 2 < nchunks)                                                                               \
-            __builtin_amdgcn_s_waitcnt(VMCNT(8));                                                            \
+            __builtin_amdgcn_s_waitcnt(VMCNT(2 * RUNS));                                                     \
         else if ((C) + 1 < nchunks)                                                                          \
-            __builtin_amdgcn_s_waitcnt(VMCNT(4));                                                            \
+            __builtin_amdgcn_s_waitcnt(VMCNT(RUNS));                                                         \
         else                                                                                                 \
             __builtin_amdgcn_s_waitcnt(VMCNT(0));                                                            \
         __builtin_amdgcn_s_barrier();                                                                        \
@@ -189,17 +229,19 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 #define ISO_COMPUTE(SB)                                                                                       \
     _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
         const int kel = ks + (lane >> 5) * P::VEC;                                                             \
-        bf16x8 a[2], bb[4];                                                                                   \
-        _Pragma("unroll") for (int jb = 0; jb < 2; ++jb) {                                                    \
-            const uint4 v = SB[frag_slot(64 * wj + 32 * jb + (lane & 31), kel)];                               \
+        bf16x8 a[NJB], bb[NIB];                                                                               \
+        _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) {                                                  \
+            const uint4 v = SB[frag_slot(CW * wj + 32 * jb + (lane & 31), kel)];                               \
             a[jb] = *reinterpret_cast<const bf16x8 *>(&v);                                                    \
         }                                                                                                     \
-        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) {                                                    \
-            const uint4 v = SB[frag_slot(PT + 128 * wi + 32 * ib + (lane & 31), kel)];                         \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                                  \
+            const uint4 v = SB[frag_slot(PT + RW * wi + 32 * ib + (lane & 31), kel)];                          \
             bb[ib] = *reinterpret_cast<const bf16x8 *>(&v);                                                   \
         }                                                                                                     \
-        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) _Pragma("unroll") for (int jb = 0; jb < 2; ++jb)     \
+        if (PAIR_SETPRIO) __builtin_amdgcn_s_setprio(1);                                                      \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) \
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);        \
+        if (PAIR_SETPRIO) __builtin_amdgcn_s_setprio(0);                                                      \
     }
         if (0 < nchunks) ISO_ISSUE(stage0, 0)
         if (1 < nchunks) ISO_ISSUE(stage1, 1)
@@ -217,12 +259,12 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         const int kel = ks + (lane >> 5) * P::VEC;                                                             \
         const float *sf = reinterpret_cast<const float *>(SB);                                                \
         const int within = kel & 3;                                                                           \
-        float a[2], bb[4];                                                                                    \
-        _Pragma("unroll") for (int jb = 0; jb < 2; ++jb) a[jb] =                                              \
-            sf[frag_slot(64 * wj + 32 * jb + (lane & 31), kel) * 4 + within];                                  \
-        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) bb[ib] =                                             \
-            sf[frag_slot(PT + 128 * wi + 32 * ib + (lane & 31), kel) * 4 + within];                            \
-        _Pragma("unroll") for (int ib = 0; ib < 4; ++ib) _Pragma("unroll") for (int jb = 0; jb < 2; ++jb)     \
+        float a[NJB], bb[NIB];                                                                                \
+        _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) a[jb] =                                            \
+            sf[frag_slot(CW * wj + 32 * jb + (lane & 31), kel) * 4 + within];                                  \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) bb[ib] =                                           \
+            sf[frag_slot(PT + RW * wi + 32 * ib + (lane & 31), kel) * 4 + within];                             \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) \
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);           \
     }
         if (0 < nchunks) ISO_ISSUE(stage0, 0)
@@ -238,58 +280,65 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
     }
 #undef ISO_STEP
 #undef ISO_ISSUE
-    __syncthreads();  // all DMA traffic retired before LDS is reused by the epilogue
+    // (the epilogue uses only PairLDS, so no barrier is needed before it)
 
-    // ---- epilogue 1: masked Dhat^2 (padding has s = +inf), tile minima of rows
-    // (in-lane over the lane's 32 columns, then lanes l, l+32) and of columns
-    // (in-lane over the lane's 4 rows, then the 32 lanes of the half wave)
-    {
-        float m[4] = {SCR_INF, SCR_INF, SCR_INF, SCR_INF};
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const float sj = S.csq[jl];
-                const int cjj = S.ccomp[jl];
-                float cmin = SCR_INF;
-#pragma unroll
-                for (int ib = 0; ib < 4; ++ib) {
-                    const float t = fmaxf(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj), 0.0f);
-                    float v = (cjj == ci[ib]) ? SCR_INF : t;
-                    if (diag && jl <= 128 * wi + 32 * ib + (lane & 31)) v = SCR_INF;  // each pair once
-                    acc[ib][jb][q] = v;
-                    m[ib] = fminf(m[ib], v);
-                    cmin = fminf(cmin, v);
-                }
-                const float v = min32(cmin);
-                if (((16 * jb + q) & 31) == (lane & 31) && v < SCR_INF) atomicMin(&S.cmin[jl], __float_as_uint(v));
-                if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the columns in flight
-            }
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-            const float mm = fminf(m[ib], __shfl_xor(m[ib], 32, 64));  // lanes l and l+32 hold the same rows
-            if ((lane >> 5) == 0 && mm < SCR_INF)
-                atomicMin(&S.rmin[128 * wi + 32 * ib + (lane & 31)], __float_as_uint(mm));
-        }
+    // ---- epilogue 1: masked Dhat^2 as bit patterns (padding has s = +inf; a
+    // negative rounding result becomes +0), tile minima of rows (in-lane over
+    // the lane's 32 columns, then lanes l, l+32) and of columns (in-lane over the
+    // lane's 4 rows, then the 32 lanes of the half wave; lane 16 jb + q of each
+    // half keeps column (jb, q) and merges it into LDS once at the end)
+#define ISO_EPI1(DIAG)                                                                                        \
+    {                                                                                                        \
+        uint32_t m[NIB];                                                                                     \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) m[ib] = INF_BITS;                                 \
+        uint32_t cown = INF_BITS;                                                                            \
+        _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) _Pragma("unroll") for (int q = 0; q < 16; ++q) {   \
+            const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);                     \
+            const float sj = S.csq[jl];                                                                      \
+            const int cjj = S.ccomp[jl];                                                                     \
+            uint32_t cmin = INF_BITS;                                                                        \
+            _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                             \
+                const int32_t tb = __float_as_int(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj));                 \
+                uint32_t v = (cjj == ci[ib]) ? INF_BITS : (uint32_t)max(tb, 0);                             \
+                if (DIAG && jl <= RW * wi + 32 * ib + (lane & 31)) v = INF_BITS; /* each pair once */       \
+                acc[ib][jb][q] = __uint_as_float(v);                                                         \
+                m[ib] = min(m[ib], v);                                                                       \
+                cmin = min(cmin, v);                                                                         \
+            }                                                                                                \
+            const uint32_t cm = min32(cmin);                                                                 \
+            if ((lane & 31) == 16 * jb + q) cown = cm;                                                       \
+            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0); /* bound the columns in flight */          \
+        }                                                                                                    \
+        {                                                                                                    \
+            const int qo = lane & 15, jo = (lane >> 4) & 1;                                                  \
+            const int jl = CW * wj + 32 * jo + 8 * (qo >> 2) + 4 * (lane >> 5) + (qo & 3);                   \
+            if (cown < INF_BITS) atomicMin(&S.cmin[jl], cown);                                               \
+        }                                                                                                    \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                                 \
+            const uint32_t mm = min_halves(m[ib]); /* lanes l and l+32 hold the same rows */                 \
+            if ((lane >> 5) == 0 && mm < INF_BITS) atomicMin(&S.rmin[RW * wi + 32 * ib + (lane & 31)], mm);   \
+        }                                                                                                    \
     }
+    ISO_EPI1(DIAG)
+#undef ISO_EPI1
     __syncthreads();
 
-    // ---- epilogue 2: merge into the global minima; thresholds from the merged
-    // values; flag the rows and columns whose tile minimum can still be captured
+    // ---- epilogue 2: merge into the global minima (no-return atomics, only
+    // where the tile lowers the value read before the K loop); thresholds from
+    // the merged values; flag the rows and columns whose tile minimum can still
+    // be captured
     if (tid < PT / 32) S.chot[tid] = 0u;
     __syncthreads();
-    {
-        const int t = tid & (PT - 1);
-        const bool is_row = tid < PT;
+#pragma unroll
+    for (int e = 0; e < NPRE; ++e) {
+        const int u = tid + e * 64 * NW;
+        const int t = u & (PT - 1);
+        const bool is_row = u < PT;
         const int64_t p = (is_row ? I0 : J0) + t;
-        float cur = SCR_INF;
         const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
-        if (p < A.n) {
-            uint32_t old = reinterpret_cast<const volatile uint32_t *>(A.best)[p];
-            if (m < old) old = atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m);  // only when it can lower it
-            cur = __uint_as_float(old < m ? old : m);
-        }
+        const uint32_t old = bpre[e];
+        if (p < A.n && m < old) atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m);
+        const float cur = p < A.n ? __uint_as_float(min(old, m)) : SCR_INF;
         const float E = is_row ? S.rE[t] : S.cE[t];
         const bool hot = p < A.n && __uint_as_float(m) <= (cur + 2.0f * E) * A.kappa;
         if (is_row) {
@@ -304,8 +353,8 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 
     // ---- epilogue 3: capture candidates (rows of hot rows, columns of hot columns)
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib) {
-        const int il = 128 * wi + 32 * ib + (lane & 31);
+    for (int ib = 0; ib < NIB; ++ib) {
+        const int il = RW * wi + 32 * ib + (lane & 31);
         if (!S.rhot[il]) continue;
         const int64_t i = I0 + il;
         const float Ei = S.rE[il];
@@ -314,12 +363,12 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
         const float r_thr = (rb_ + Ei) * A.kappa;
         const float ri = S.rrn[il], ei = S.rre[il];
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
+        for (int jb = 0; jb < NJB; ++jb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const float v = acc[ib][jb][q];
                 if (!(v <= r_cheap)) continue;
-                const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
                 const float L = lower_of(v, pair_bound(A.bound, ri, S.crn[jl], ei, S.cre[jl]));
                 if (!(L <= r_thr)) continue;
                 const int pos = atomicAdd(&A.ccnt[i], 1);
@@ -330,37 +379,34 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
                 __builtin_amdgcn_sched_barrier(0);
             }
     }
-    // columns: this wave's 64 columns are bits [64 wj, +64) of the hot set
-    const uint32_t h0 = S.chot[2 * wj + 0], h1 = S.chot[2 * wj + 1];
-    if (h0 | h1) {
+    // columns: this wave's CW columns are bits [CW wj, +CW) of the hot set
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb) {
-            const uint32_t hw = jb == 0 ? h0 : h1;
-            if (!hw) continue;
+    for (int jb = 0; jb < NJB; ++jb) {
+        const uint32_t hw = S.chot[(CW * wj) / 32 + jb];
+        if (!hw) continue;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);  // column within the 32-block
-                if (!((hw >> jc) & 1u)) continue;
-                const int jl = 64 * wj + 32 * jb + jc;
-                const int64_t j = J0 + jl;
-                const float Ej = S.cE[jl];
-                const float cb = S.cthr[jl];
-                const float c_cheap = (cb + 2.0f * Ej) * A.kappa;
-                const float c_thr = (cb + Ej) * A.kappa;
+        for (int q = 0; q < 16; ++q) {
+            const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);  // column within the 32-block
+            if (!((hw >> jc) & 1u)) continue;
+            const int jl = CW * wj + 32 * jb + jc;
+            const int64_t j = J0 + jl;
+            const float Ej = S.cE[jl];
+            const float cb = S.cthr[jl];
+            const float c_cheap = (cb + 2.0f * Ej) * A.kappa;
+            const float c_thr = (cb + Ej) * A.kappa;
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) {
-                    const float v = acc[ib][jb][q];
-                    if (!(v <= c_cheap)) continue;
-                    const int il = 128 * wi + 32 * ib + (lane & 31);
-                    const float L = lower_of(v, pair_bound(A.bound, S.rrn[il], S.crn[jl], S.rre[il], S.cre[jl]));
-                    if (!(L <= c_thr)) continue;
-                    const int pos = atomicAdd(&A.ccnt[j], 1);
-                    if (pos < SCR_CAP) {
-                        A.cj[j * SCR_CAP + pos] = (int32_t)(I0 + il);
-                        A.cl[j * SCR_CAP + pos] = L;
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
+            for (int ib = 0; ib < NIB; ++ib) {
+                const float v = acc[ib][jb][q];
+                if (!(v <= c_cheap)) continue;
+                const int il = RW * wi + 32 * ib + (lane & 31);
+                const float L = lower_of(v, pair_bound(A.bound, S.rrn[il], S.crn[jl], S.rre[il], S.cre[jl]));
+                if (!(L <= c_thr)) continue;
+                const int pos = atomicAdd(&A.ccnt[j], 1);
+                if (pos < SCR_CAP) {
+                    A.cj[j * SCR_CAP + pos] = (int32_t)(I0 + il);
+                    A.cl[j * SCR_CAP + pos] = L;
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
@@ -370,28 +416,47 @@ __global__ __launch_bounds__(512, 1) void k_screen_pairs(ScreenArgs A, const int
 
 int64_t pair_tile() { return PT; }
 
-// Tile pairs (I <= J) of nt tiles in blocks of SB x SB tiles.
+// Tile pairs (I <= J) of nt tiles: the nt diagonal pairs first, then the
+// others in blocks of PAIR_SB x PAIR_SB tiles.
 std::vector<int2> make_pair_order(int64_t nt) {
-    constexpr int64_t SB = 4;
+    constexpr int64_t SB = PAIR_SB;
     std::vector<int2> out;
     out.reserve((size_t)(nt * (nt + 1) / 2));
+    for (int64_t I = 0; I < nt; ++I) out.push_back(make_int2((int)I, (int)I));
     const int64_t nb = (nt + SB - 1) / SB;
     for (int64_t bi = 0; bi < nb; ++bi)
         for (int64_t bj = bi; bj < nb; ++bj)
             for (int64_t I = bi * SB; I < (bi + 1) * SB && I < nt; ++I)
                 for (int64_t J = bj * SB; J < (bj + 1) * SB && J < nt; ++J)
-                    if (I <= J) out.push_back(make_int2((int)I, (int)J));
+                    if (I < J) out.push_back(make_int2((int)I, (int)J));
     return out;
 }
 
-void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, bool bf16, hipStream_t s) {
-    const int64_t per_xcd = (npairs + 7) / 8;
-    const unsigned blocks = (unsigned)(per_xcd * 8);
-    if (bf16)
-        hipLaunchKernelGGL(k_screen_pairs<true>, dim3(blocks), dim3(512), 0, s, A, pairs, per_xcd, npairs);
-    else
-        hipLaunchKernelGGL(k_screen_pairs<false>, dim3(blocks), dim3(512), 0, s, A, pairs, per_xcd, npairs);
+template <bool BF16>
+void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, hipStream_t s) {
+    const int64_t nt = A.n_pad / PT;
+    ISO_REQUIRE(npairs == nt * (nt + 1) / 2, ISO_ERR_INTERNAL, "tile-pair list does not match the padded size");
+    const dim3 block(64 * PAIR_WI * PAIR_WJ);
+    // diagonal tile pairs (only i < j counted) ...
+    int64_t per_xcd = (nt + 7) / 8;
+    hipLaunchKernelGGL((k_screen_pairs<BF16, true, PAIR_WI, PAIR_WJ>), dim3((unsigned)(per_xcd * 8)), block, 0, s, A,
+                       pairs, per_xcd, nt);
     LAUNCH_CHECK();
+    // ... then the others
+    const int64_t rest = npairs - nt;
+    if (rest > 0) {
+        per_xcd = (rest + 7) / 8;
+        hipLaunchKernelGGL((k_screen_pairs<BF16, false, PAIR_WI, PAIR_WJ>), dim3((unsigned)(per_xcd * 8)), block, 0, s,
+                           A, pairs + nt, per_xcd, rest);
+        LAUNCH_CHECK();
+    }
+}
+
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, bool bf16, hipStream_t s) {
+    if (bf16)
+        launch_pairs<true>(A, pairs, npairs, s);
+    else
+        launch_pairs<false>(A, pairs, npairs, s);
 }
 
 }  // namespace iso

@@ -117,6 +117,16 @@ __global__ void k_sort_keys(const int32_t *__restrict__ depth, const int32_t *__
 }
 
 // level_start[L] = first x-order index of level key L (L = maxdepth - depth).
+// Output slot of every vertex in the Algorithm 1 passes: a child's slot is
+// its position in the concatenated child lists (so a vertex finds its
+// children's contributions contiguously), the root takes the last slot.
+// cval_sorted[0] is the root; cval_sorted[1 + a] the child at position a.
+__global__ void k_slots(const uint32_t *__restrict__ cval_sorted, int64_t n, int32_t *__restrict__ slot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    slot[cval_sorted[i]] = i == 0 ? (int32_t)(n - 1) : (int32_t)(i - 1);
+}
+
 __global__ void k_level_starts(const uint32_t *__restrict__ okey_sorted, int64_t n, int32_t maxdepth,
                                int32_t *__restrict__ level_start) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,6 +254,7 @@ struct DPArgs {
     const int32_t *parent;
     const uint32_t *kids;
     const int32_t *koff;
+    const int32_t *slot;  // output slot of each vertex: its position among all child lists, n-1 for the root
     const double *phi, *om0, *p0;
     const double *Nvals;
     double *cw, *cp;
@@ -265,11 +276,29 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
     double w = A.om0[v];
     double p = A.p0[v];
     int32_t c_cnt = 0;
-    for (int32_t a = A.koff[v]; a < A.koff[v + 1]; ++a) {
-        const int64_t c = (int64_t)A.kids[a] * MM + m;
-        p = p + A.cp[c];
-        w = w + A.cw[c];
-        c_cnt += A.cnt[c];
+    // The children's contributions sit contiguously at slots koff[v] ..
+    // koff[v+1]-1 (ascending child id); sixteen are loaded at once, the sums
+    // still run one child after another.
+    const int64_t a0 = A.koff[v], a1 = A.koff[v + 1];
+    for (int64_t a = a0; a < a1; a += 16) {
+        const int64_t rem = a1 - a;
+        double pp[16], ww[16];
+        int32_t cc[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int64_t c = (u < rem ? a + u : a1 - 1) * MM + m;
+            pp[u] = A.cp[c];
+            ww[u] = A.cw[c];
+            cc[u] = A.cnt[c];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (u < rem) {
+                p = p + pp[u];
+                w = w + ww[u];
+                c_cnt += cc[u];
+            }
+        }
     }
     const bool is_root = A.parent[v] < 0;
     const double fe = is_root ? 0.0 : A.phi[v];
@@ -289,7 +318,7 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
         op = fe;
         ow = 0.0;
     }
-    const int64_t o = (int64_t)v * MM + m;
+    const int64_t o = (int64_t)A.slot[v] * MM + m;
     A.cp[o] = op;
     A.cw[o] = ow;
     A.cnt[o] = c_cnt + iscut;
@@ -349,7 +378,7 @@ __global__ void k_make_cands(TreeState *__restrict__ st, double *__restrict__ Nv
 
 // Walks the answers of one pass: YES (>= k cuts) => beta = mid, else alpha = mid.
 __global__ void k_resolve(TreeState *__restrict__ st, const double *__restrict__ Nvals,
-                          const int32_t *__restrict__ cnt, int32_t root) {
+                          const int32_t *__restrict__ cnt, int32_t root_slot) {
     if (threadIdx.x != 0 || st->done) return;
     st->passes += 1;
     int q = 0;
@@ -365,7 +394,7 @@ __global__ void k_resolve(TreeState *__restrict__ st, const double *__restrict__
             st->done = 1;
             return;
         }
-        const bool yes = cnt[(int64_t)root * M + q] >= st->k;
+        const bool yes = cnt[(int64_t)root_slot * M + q] >= st->k;
         if (yes) {
             st->beta = mid;
             q = 2 * q + 1;
@@ -375,7 +404,7 @@ __global__ void k_resolve(TreeState *__restrict__ st, const double *__restrict__
         }
         st->iters += 1;
     }
-    if (cnt[(int64_t)root * M + NCAND] < st->k) st->bad |= 16;  // beta must stay YES
+    if (cnt[(int64_t)root_slot * M + NCAND] < st->k) st->bad |= 16;  // beta must stay YES
     const double a = st->alpha, b = st->beta;
     const double mid = (a + b) / 2.0;
     if (mid <= a || mid >= b || st->iters >= st->max_iters) st->done = 1;
@@ -431,7 +460,7 @@ __global__ void k_labels(const int32_t *__restrict__ rep, const int32_t *__restr
 
 // i_k = max_j num_j / den_j, jstar = smallest argmax; cuts at beta.
 __global__ void k_final_cost(const double *__restrict__ cl_num, const double *__restrict__ cl_den, int32_t k,
-                             const int32_t *__restrict__ cnt, int32_t root, TreeState *__restrict__ st) {
+                             const int32_t *__restrict__ cnt, int32_t root_slot, TreeState *__restrict__ st) {
     if (threadIdx.x != 0) return;
     double best = -1.0;
     int js = 0;
@@ -444,7 +473,7 @@ __global__ void k_final_cost(const double *__restrict__ cl_num, const double *__
     }
     st->i_k = best;
     st->jstar = js;
-    st->ncuts = cnt[root];
+    st->ncuts = cnt[root_slot];
 }
 
 // ------------------------------------------------------------------ plan
@@ -454,7 +483,7 @@ struct SubPlan {
     int32_t k;
     int32_t *anc0, *anc1, *dist0, *dist1;
     uint32_t *okey, *oval, *ckey, *cval, *tk, *tv;
-    int32_t *nchild, *koff, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp;
+    int32_t *nchild, *koff, *slot, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp;
     double *phi, *om0, *p0, *cw, *cp, *Nvals, *num, *den, *cl_num_tmp, *cl_den_tmp;
     uint8_t *cut, *joined;
     TreeState *st;
@@ -473,6 +502,7 @@ struct SubPlan {
         tv = a.take<uint32_t>(n);
         nchild = a.take<int32_t>(n + 1);
         koff = a.take<int32_t>(n + 1);
+        slot = a.take<int32_t>(n);
         level_start = a.take<int32_t>(n + 2);
         cf = a.take<int32_t>(n);
         rank = a.take<int32_t>(n);
@@ -587,6 +617,9 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     LAUNCH_CHECK();
     const int32_t *order = reinterpret_cast<const int32_t *>(P.oval);
     const uint32_t *kids = P.cval + 1;  // the root (key 0) sorts first
+    hipLaunchKernelGGL(k_slots, dim3(gn), dim3(256), 0, s, P.cval, n, P.slot);
+    LAUNCH_CHECK();
+    const int32_t root_slot = (int32_t)(n - 1);
 
     // sigma, phi, omega0, stats, bracket
     if (sigma == 0.0) {
@@ -612,6 +645,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     A.parent = parent;
     A.kids = kids;
     A.koff = P.koff;
+    A.slot = P.slot;
     A.phi = P.phi;
     A.om0 = P.om0;
     A.p0 = P.p0;
@@ -633,7 +667,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
             hipLaunchKernelGGL(k_make_cands, dim3(1), dim3(64), 0, s, P.st, P.Nvals);
             LAUNCH_CHECK();
             launch_levels<M, false>(A, ls, maxdepth, s);
-            hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, s, P.st, P.Nvals, P.cnt, root);
+            hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, s, P.st, P.Nvals, P.cnt, root_slot);
             LAUNCH_CHECK();
         }
         HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -666,7 +700,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     fill_t<int32_t>(cs, 0, k, s);
     hipLaunchKernelGGL(k_labels, dim3(gn), dim3(256), 0, s, ri, P.cidx, P.num, P.den, n, labels, cn, cd, cs);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_final_cost, dim3(1), dim3(64), 0, s, cn, cd, k, P.cnt, root, P.st);
+    hipLaunchKernelGGL(k_final_cost, dim3(1), dim3(64), 0, s, cn, cd, k, P.cnt, root_slot, P.st);
     LAUNCH_CHECK();
     HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
