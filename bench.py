@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
 WORKLOAD = 3
-PEAKS_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
+PEAKS_TFLOPS = {"fp8": 5000.0, "bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
 # one screen launch = the diagonal tile pairs' dispatch followed by the off-diagonal one
 SCREEN_KERNEL = "k_screen_pairs<%s> (diagonal + off-diagonal dispatch)"
 SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/screen_pairs.hip", "paper_1702_04739_amd/csrc/screen.hpp"]
@@ -62,7 +62,7 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
     import csv
     import glob
 
-    prefix = "k_screen_pairs<%s, " % ("true" if precision == "bf16" else "false")
+    prefix = "k_screen_pairs<%d, " % {"fp32": 0, "bf16": 1, "fp8": 2}[precision]
 
     def per_kernel(d, counter):
         """Summed counter over the screen's dispatches (diagonal and
@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-screen comparison step")
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")

@@ -56,6 +56,11 @@ typedef int32_t iso_status;
  * the screen's precision. */
 #define ISO_PREC_FP32 0
 #define ISO_PREC_BF16 1
+/* FP8 E4M3 (OCP, max 448) screen on the FP8 matrix cores: coordinates are
+ * centred and rounded to E4M3 without scaling (values beyond +-448 saturate);
+ * the representation error of every point enters the screen's bound, so the
+ * tree is unchanged, only the number of candidates grows with it. */
+#define ISO_PREC_FP8 2
 
 /* Arithmetic of the exact re-evaluation of candidate distances, which defines
  * the order of the edges:
@@ -169,17 +174,18 @@ iso_status iso_backward(const float *X, int64_t n, int64_t d, int64_t ld, const 
                         float *gX, int64_t ldg, double *gsigma /* host */, double *I_out /* host */, void *ws,
                         size_t ws_bytes, void *stream);
 
-/* Optional phase timing, for benchmarks: while enabled, iso_mst brackets every
- * screen launch with hipEvents on its stream and counts the unordered pairs
- * of points in different components that the launch must cover, and both entry
+/* Optional phase timing, for benchmarks: while enabled, iso_mst brackets the
+ * screen of every Boruvka round (its diagonal-tile and off-diagonal kernel
+ * dispatches) with hipEvents on its stream and counts the unordered pairs of
+ * points in different components that the round must cover, and both entry
  * points record their own duration.  Totals accumulate in process-wide
  * counters (not thread safe) until the next iso_timing_enable call, which
  * resets them.  Enabling timing adds synchronisation-free event records and,
  * per Boruvka round, a component-size reduction. */
 typedef struct {
     int32_t enabled;
-    int32_t screen_launches;  /* screen kernel launches timed                       */
-    double screen_ms;         /* summed durations of those launches                 */
+    int32_t screen_launches;  /* screens timed (one per Boruvka round)              */
+    double screen_ms;         /* summed durations of those screens                  */
     double screen_pairs;      /* summed unordered inter-component pairs they cover  */
     double screen_dim;        /* padded dimension the screen contracts over         */
     int32_t mst_calls, sub_calls;

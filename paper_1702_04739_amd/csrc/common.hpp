@@ -57,6 +57,8 @@ iso_status guarded(F &&body) {
 
 // Ensures a usable device is current; throws NO_DEVICE otherwise.
 void require_device();
+// Compute units of the current device (cached per device).
+int device_cus();
 
 // ------------------------------------------------------------------ workspace
 

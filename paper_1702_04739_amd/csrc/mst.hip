@@ -3,17 +3,20 @@
 // n x n affinity matrix, Secs. 3.4-3.5; here the matrix is never stored).
 //
 // One Boruvka round:
-//   screen    : every row i sweeps all column tiles, forming
-//               Dhat^2 = ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j tile by tile and
-//               keeping, over columns j in another component, the running
-//               minimum b_i and every (j, Dhat^2) with Dhat^2 <= b_i + 2 E_i,
-//               where E_i bounds |Dhat^2 - D^2| for the row (candidates);
+//   screen    : every unordered pair of points is formed once, tile pair by
+//               tile pair (screen_pairs.hip): Dhat^2 = ||x_i||^2 + ||x_j||^2
+//               - 2 x_i.x_j on the matrix cores; over pairs in different
+//               components every point keeps its running minimum b_i and the
+//               partners whose lower bound Dhat^2 - E_ij can still reach
+//               b_i + E_i, where E bounds |Dhat^2 - D^2| (candidates); points
+//               whose list overflows are screened again from their final
+//               minimum (gathered pass, screen_mfma.hip);
 //   comp_ub   : U_c = min over rows of component c of b_i + E_i, an upper
 //               bound on c's lightest outgoing edge;
 //   recheck   : exact D^2 of the candidates that can still reach U_c, giving
 //               each row its lightest outgoing edge under the total order
-//               (D^2, smaller id, larger id); rows whose candidate list
-//               overflowed are re-evaluated against every point (rescan);
+//               (D^2, smaller id, larger id); rows whose list overflowed again
+//               are re-evaluated against every point (rescan);
 //   comp_min  : lightest outgoing edge per component (two 64-bit atomic mins);
 //   hook/jump : each component hooks onto the component across its edge;
 //               mutual pairs keep the smaller id as root; pointer jumping;
@@ -138,9 +141,19 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// E4M3 (OCP) rounding of x with saturation at +-448 (the hardware conversion
+// rounds to nearest even; the clamp keeps it away from the NaN code).
+__device__ __forceinline__ uint8_t fp8_rne(float x) {
+    const float c = fminf(fmaxf(x, -448.0f), 448.0f);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(c, 0.0f, 0, false) & 0xFF);
+}
+
+__device__ __forceinline__ float fp8_to_f32(uint8_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
+
 // One wave per (padded) row: x' = rep(x - mu) written row-major, s = fl(||x'||^2)
-// (fixed order), and upper bounds r >= ||x'||, e >= ||x' - (x - mu)||.
-template <bool BF16>
+// (fixed order), and upper bounds r >= ||x'||, e >= ||x' - (x - mu)|| computed
+// from the stored values.
+template <int REP>
 __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
                                                    int64_t n_pad, int64_t d_pad, const float *__restrict__ mu,
                                                    void *__restrict__ Xr, float *__restrict__ sq,
@@ -160,10 +173,14 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
             y = xv - mu[t];
         }
         float yr;
-        if (BF16) {
+        if (REP == ISO_PREC_BF16) {
             const uint16_t b = bf16_rne(y);
             static_cast<uint16_t *>(Xr)[i * d_pad + t] = b;
             yr = bf16_to_f32(b);
+        } else if (REP == ISO_PREC_FP8) {
+            const uint8_t b = fp8_rne(y);
+            static_cast<uint8_t *>(Xr)[i * d_pad + t] = b;
+            yr = fp8_to_f32(b);
         } else {
             static_cast<float *>(Xr)[i * d_pad + t] = y;
             yr = y;
@@ -649,7 +666,7 @@ __global__ __launch_bounds__(1024) void k_sum_lengths(const double *__restrict__
 struct MstPlan {
     int64_t n, d, ld, n_pad, d_pad, nrb;
     int32_t precision;
-    void *Xr;                       // screen representation (FP32 or BF16), [n_pad][d_pad]
+    void *Xr;                       // screen representation (FP32, BF16 or FP8), [n_pad][d_pad]
     float *mu, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
     int32_t *pgrid, *grid_min;
     int2 *pairs;
@@ -663,7 +680,7 @@ struct MstPlan {
     int32_t *counters;
 
     void carve(Arena &a) {
-        const size_t esz = precision == ISO_PREC_BF16 ? 2 : 4;
+        const size_t esz = precision == ISO_PREC_BF16 ? 2 : precision == ISO_PREC_FP8 ? 1 : 4;
         Xr = a.take<char>((size_t)n_pad * d_pad * esz);
         mu = a.take<float>(d_pad);
         psum = a.take<double>((size_t)nrb * d);
@@ -719,7 +736,7 @@ MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
     p.ld = ld;
     p.precision = precision;
     p.n_pad = (n + GT - 1) / GT * GT;
-    const int64_t kc = precision == ISO_PREC_BF16 ? 32 : 16;
+    const int64_t kc = 64 / (precision == ISO_PREC_BF16 ? 2 : precision == ISO_PREC_FP8 ? 1 : 4);  // 64-byte K chunks
     p.d_pad = (d + kc - 1) / kc * kc;
     p.nrb = (n + COL_RB - 1) / COL_RB;
     const int64_t nt = p.n_pad / pair_tile();
@@ -738,7 +755,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
              iso_mst_info *info, hipStream_t s) {
     const int64_t n = P.n, d = P.d, ld = P.ld;
     const bool timed = timing().enabled != 0;
-    const bool bf16 = P.precision == ISO_PREC_BF16;
+    const int32_t rep = P.precision;
     const bool f64 = recheck == ISO_RECHECK_FP64;
     EventPair whole(timed), scr(timed);
     whole.start(s);
@@ -761,12 +778,12 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.psum, P.pgrid, P.nrb, n, d,
                        P.d_pad, P.mu);
     LAUNCH_CHECK();
-    if (bf16)
-        hipLaunchKernelGGL(k_repr_rows<true>, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad,
-                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax, P.grid_min);
-    else
-        hipLaunchKernelGGL(k_repr_rows<false>, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad,
-                           P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re, P.rmax, P.emax, P.grid_min);
+    {
+        auto kern = rep == ISO_PREC_BF16 ? k_repr_rows<ISO_PREC_BF16>
+                                         : rep == ISO_PREC_FP8 ? k_repr_rows<ISO_PREC_FP8> : k_repr_rows<ISO_PREC_FP32>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad, P.d_pad, P.mu, P.Xr,
+                           P.sq, P.rn, P.re, P.rmax, P.emax, P.grid_min);
+    }
     LAUNCH_CHECK();
     const double u = 1.0 / 8388608.0;  // 2^-23
     const double du = (double)(d + 4) * u;
@@ -799,8 +816,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     LAUNCH_CHECK();
 
     ScreenArgs SA{};
-    SA.XT = bf16 ? nullptr : static_cast<const float *>(P.Xr);
-    SA.XB = bf16 ? static_cast<const uint16_t *>(P.Xr) : nullptr;
+    SA.rep = rep;
+    SA.XT = rep == ISO_PREC_FP32 ? static_cast<const float *>(P.Xr) : nullptr;
+    SA.XB = rep == ISO_PREC_BF16 ? static_cast<const uint16_t *>(P.Xr) : nullptr;
+    SA.XF8 = rep == ISO_PREC_FP8 ? static_cast<const uint8_t *>(P.Xr) : nullptr;
     SA.n = n;
     SA.n_pad = P.n_pad;
     SA.d_pad = P.d_pad;
@@ -820,12 +839,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.gcnt = P.gcnt;
     SA.gcj = P.gcj;
     SA.gcl = P.gcl;
-    auto screen = [&](bool gather) {
-        if (bf16)
-            launch_screen_bf16(SA, gather, s);
-        else
-            launch_screen_f32(SA, gather, s);
-    };
+    auto screen = [&](bool gather) { launch_screen_rows(SA, gather, s); };
     {
         const std::vector<int2> order = make_pair_order(P.n_pad / pair_tile());
         ISO_REQUIRE((int64_t)order.size() == P.npairs, ISO_ERR_INTERNAL, "tile-pair order has %zu entries",
@@ -851,7 +865,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         SA.rows = nullptr;
         SA.nrows = 0;
         scr.start(s);
-        launch_screen_pairs(SA, P.pairs, P.npairs, bf16, s);
+        launch_screen_pairs(SA, P.pairs, P.npairs, s);
         scr.stop(s);
         fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
         hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,
@@ -877,6 +891,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         if (h_gather > 0) {
             SA.rows = P.glist;
             SA.nrows = h_gather;
+            fill<int32_t>(P.gcnt, 0, h_gather, s);
             screen(true);
             if (f64)
                 hipLaunchKernelGGL(k_recheck_gather<true>, dim3(grid_for(h_gather, 4)), dim3(256), 0, s, X, d, ld,
@@ -988,8 +1003,8 @@ extern "C" iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t preci
         ISO_REQUIRE(bytes != nullptr, ISO_ERR_INVALID_ARG, "bytes is NULL");
         ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - GT, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
         ISO_REQUIRE(d >= 1, ISO_ERR_INVALID_ARG, "d = %lld < 1", (long long)d);
-        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16, ISO_ERR_INVALID_ARG,
-                    "unknown precision %d", precision);
+        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8,
+                    ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
         *bytes = plan_bytes(make_plan(n, d, d, precision));
     });
 }
@@ -1002,8 +1017,8 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - GT, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
         ISO_REQUIRE(d >= 1, ISO_ERR_INVALID_ARG, "d = %lld < 1", (long long)d);
         ISO_REQUIRE(ld >= d, ISO_ERR_INVALID_ARG, "ld = %lld < d = %lld", (long long)ld, (long long)d);
-        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16, ISO_ERR_INVALID_ARG,
-                    "unknown precision %d", precision);
+        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8,
+                    ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
         ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
                     "unknown recheck %d", recheck);
         require_device();

@@ -32,6 +32,18 @@ void require_device() {
                 "device %d is %s; this library is built for gfx950 only", dev, prop.gcnArchName);
 }
 
+int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64 && cached[dev] > 0) return cached[dev];
+    int cus = 0;
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    ISO_REQUIRE(cus > 0, ISO_ERR_HIP, "device %d reports %d compute units", dev, cus);
+    if (dev >= 0 && dev < 64) cached[dev] = cus;
+    return cus;
+}
+
 // ------------------------------------------------------------------ timing
 
 static iso_timing g_timing{};

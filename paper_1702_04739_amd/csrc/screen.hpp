@@ -1,10 +1,10 @@
-// screen.hpp -- shared pieces of the Boruvka screen kernels (FP32 VALU and
-// BF16 MFMA): the error bound of the Gram-form distance, and the epilogue that
+// screen.hpp -- shared pieces of the Boruvka screen kernels (FP32, BF16 and
+// FP8 MFMA): the error bound of the Gram-form distance, and the epilogue that
 // keeps a running minimum per row and captures every column that can still be
 // the row's lightest outgoing edge.
 //
 // Representation: x'_i = rep(x_i - mu) with mu a per-coordinate centre (exact
-// translation invariance of distances), rep = FP32 rounding or BF16 rounding.
+// translation invariance of distances), rep = FP32, BF16 or FP8 E4M3 rounding.
 // The screen forms Dhat^2_ij = fl(s_i + s_j - 2 G_ij), s_i = fl(||x'_i||^2),
 // G_ij the FP32-accumulated dot product, clamped at 0.  With r_i >= ||x'_i||,
 // e_i >= ||x'_i - (x_i - mu)|| and g = gamma_{d+4} (unit roundoff 2^-23, so the
@@ -48,8 +48,10 @@ struct ScreenBound {
 };
 
 struct ScreenArgs {
+    int32_t rep;             // ISO_PREC_FP32 / ISO_PREC_BF16 / ISO_PREC_FP8
     const float *XT;         // FP32 screen: [n_pad][d_pad] centred, row-major
     const uint16_t *XB;      // BF16 screen: [n_pad][d_pad] centred, row-major (bf16 bits)
+    const uint8_t *XF8;      // FP8 screen: [n_pad][d_pad] centred, row-major (E4M3 bytes)
     int64_t n, n_pad, d_pad;
     const float *sq;         // [n_pad] fl(||x'||^2) as used in Dhat^2 (0 on padding)
     const float *rn;         // [n_pad] r_i
@@ -62,7 +64,8 @@ struct ScreenArgs {
     const int32_t *rows;     // [nrows] row of each gathered slot
     int32_t nrows;
     const float *best_in;    // [n] running minimum from the sweep
-    int32_t *gcnt;           // [nrows] candidates per slot (> SCR_CAP2 = overflow)
+    int32_t *gcnt;           // [nrows] candidates per slot (> SCR_CAP2 = overflow); zero on entry
+    int64_t col_split;       // gathered pass: columns per workgroup (multiple of SCR_COLS)
     int32_t *gcj;            // [nrows * SCR_CAP2]
     float *gcl;              // [nrows * SCR_CAP2]
     // sweep outputs
@@ -142,13 +145,14 @@ __device__ __forceinline__ void screen_capture(ScreenLDS &S, const ScreenArgs &A
     const float E = pair_bound(A.bound, ri, S.crn[cl], ei, S.cre[cl]);
     const float L = lower_of(v, E);
     if (!(L <= thr)) return;
-    const int pos = atomicAdd(&S.rowcnt[rl], 1);
     if (GATHER) {
+        const int pos = atomicAdd(&A.gcnt[slot], 1);  // several workgroups share a slot
         if (pos < SCR_CAP2) {
             A.gcj[slot * SCR_CAP2 + pos] = (int32_t)j;
             A.gcl[slot * SCR_CAP2 + pos] = L;
         }
     } else {
+        const int pos = atomicAdd(&S.rowcnt[rl], 1);
         if (pos < SCR_CAP) {
             S.lj[rl][pos] = (int32_t)j;
             S.ll[rl][pos] = L;
@@ -193,8 +197,7 @@ template <bool GATHER>
 __device__ __forceinline__ void screen_finish(ScreenLDS &S, const ScreenArgs &A, int64_t i0) {
     for (int rl = threadIdx.x; rl < SCR_ROWS; rl += blockDim.x) {
         if (GATHER) {
-            const int64_t slot = i0 + rl;
-            if (slot < A.nrows) A.gcnt[slot] = S.rowcnt[rl];
+            // counts were accumulated in gcnt directly
         } else {
             const int64_t i = i0 + rl;
             if (i >= A.n) continue;
@@ -210,14 +213,15 @@ __device__ __forceinline__ void screen_finish(ScreenLDS &S, const ScreenArgs &A,
 }
 
 // Row-sweep screen (screen_mfma.hip): every workgroup owns SCR_ROWS rows and
-// sweeps all columns; used for the gathered second pass.
-void launch_screen_f32(const ScreenArgs &A, bool gather, hipStream_t s);
-void launch_screen_bf16(const ScreenArgs &A, bool gather, hipStream_t s);
+// sweeps a range of columns; used for the gathered second pass, where the
+// rows' final minima fix the thresholds, so the columns are split over
+// workgroups (gcnt must be zero on entry).
+void launch_screen_rows(const ScreenArgs &A, bool gather, hipStream_t s);
 
 // Symmetric tile-pair screen (screen_pairs.hip): best[] must hold +inf and
 // ccnt[] zero on entry; both are updated with atomics.
 int64_t pair_tile();
 std::vector<int2> make_pair_order(int64_t ntiles);
-void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, bool bf16, hipStream_t s);
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, hipStream_t s);
 
 }  // namespace iso

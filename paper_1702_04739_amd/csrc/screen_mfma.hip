@@ -1,7 +1,7 @@
 // screen_mfma.hip -- Boruvka screen on the matrix cores (gfx950).
 //
-// Each workgroup owns SCR_ROWS rows (points i) and sweeps every column tile
-// (points j), forming the Gram tile G = X'_I X'_J^T on MFMA with FP32
+// Each workgroup owns SCR_ROWS rows (points i) and sweeps a range of column
+// tiles (points j), forming the Gram tile G = X'_I X'_J^T on MFMA with FP32
 // accumulation, then the masked Dhat^2 = s_i + s_j - 2 G, a running minimum per
 // row and the capture of near-minimal columns (screen.hpp).  The n x n
 // distance matrix is never stored: each tile lives in accumulators only.
@@ -13,6 +13,8 @@
 //   BF16: v_mfma_f32_32x32x16_bf16, lane l supplies row (l mod 32), k = 8 (l div 32) .. +7
 //   FP32: v_mfma_f32_32x32x2_f32,    lane l supplies row (l mod 32), k = l div 32
 //   result register q of lane l: MFMA row 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32.
+//   FP8:  v_mfma_scale_f32_32x32x64_f8f6f4 (E4M3, unit block scales), lane l supplies row (l mod 32),
+//         k = 32 (l div 32) .. +31
 // Workgroup: 4 waves in a 2 x 2 grid, each wave a 64 x 64 sub-tile (2 x 2 MFMA blocks).
 #include "screen.hpp"
 
@@ -21,13 +23,14 @@ namespace iso {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <bool BF16>
+template <int REP>
 struct Prec;
 
 template <>
-struct Prec<true> {
+struct Prec<ISO_PREC_BF16> {
     using T = uint16_t;                       // bf16 bits
     static constexpr int KC = 32;             // K elements per LDS stage
     static constexpr int LDK = KC + 8;        // padded LDS row (elements)
@@ -36,7 +39,16 @@ struct Prec<true> {
 };
 
 template <>
-struct Prec<false> {
+struct Prec<ISO_PREC_FP8> {
+    using T = uint8_t;                        // E4M3 bytes
+    static constexpr int KC = 64;
+    static constexpr int LDK = KC + 16;
+    static constexpr int KSTEP = 64;
+    static constexpr int VEC = 32;
+};
+
+template <>
+struct Prec<ISO_PREC_FP32> {
     using T = float;
     static constexpr int KC = 16;
     static constexpr int LDK = KC + 4;
@@ -44,9 +56,9 @@ struct Prec<false> {
     static constexpr int VEC = 1;
 };
 
-template <bool BF16, bool GATHER>
+template <int REP, bool GATHER>
 __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
-    using P = Prec<BF16>;
+    using P = Prec<REP>;
     using T = typename P::T;
     __shared__ ScreenLDS S;
     __shared__ __attribute__((aligned(16))) T As[2][SCR_COLS * P::LDK];  // column points j (double buffer)
@@ -56,7 +68,9 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
     const int lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1;
     const int64_t i0 = (int64_t)blockIdx.x * SCR_ROWS;
-    const T *X = BF16 ? reinterpret_cast<const T *>(A.XB) : reinterpret_cast<const T *>(A.XT);
+    const T *X = REP == ISO_PREC_BF16  ? reinterpret_cast<const T *>(A.XB)
+                 : REP == ISO_PREC_FP8 ? reinterpret_cast<const T *>(A.XF8)
+                                       : reinterpret_cast<const T *>(A.XT);
     const int64_t d_pad = A.d_pad;
 
     screen_init_rows<GATHER>(S, A, i0);
@@ -114,12 +128,15 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
         *reinterpret_cast<uint4 *>(&Bs[(BUF)][srow0 * P::LDK + spart0 * CHUNK]) = rb0;                       \
         *reinterpret_cast<uint4 *>(&Bs[(BUF)][srow1 * P::LDK + spart1 * CHUNK]) = rb1;                       \
     }
-    ISO_GLOAD(0, 0)
+    // this workgroup's columns
+    const int64_t jbeg = (int64_t)blockIdx.y * A.col_split;
+    const int64_t jend = jbeg + A.col_split < A.n_pad ? jbeg + A.col_split : A.n_pad;
+    ISO_GLOAD(jbeg, 0)
     ISO_SSTORE(0)
     __syncthreads();
     int buf = 0;
 
-    for (int64_t j0 = 0; j0 < A.n_pad; j0 += SCR_COLS) {
+    for (int64_t j0 = jbeg; j0 < jend; j0 += SCR_COLS) {
         screen_load_cols(S, A, j0);
         floatx16 acc[2][2];
 #pragma unroll
@@ -136,7 +153,7 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                 nk0 = 0;
                 nj0 = j0 + SCR_COLS;
             }
-            const bool has_next = nj0 < A.n_pad;
+            const bool has_next = nj0 < jend;
             if (has_next) {
                 ISO_GLOAD(nj0, nk0)
             }
@@ -145,7 +162,21 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
 #pragma unroll
             for (int ks = 0; ks < P::KC; ks += P::KSTEP) {
                 const int kofs = ks + (lane >> 5) * P::VEC;
-                if constexpr (BF16) {
+                if constexpr (REP == ISO_PREC_FP8) {
+                    intx8 a[2], b[2];
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb)
+                        a[jb] = *reinterpret_cast<const intx8 *>(&Ab[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+                        b[ib] = *reinterpret_cast<const intx8 *>(&Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                        for (int jb = 0; jb < 2; ++jb)
+                            acc[ib][jb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[jb], b[ib], acc[ib][jb], 0, 0,
+                                                                                          0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
+                } else if constexpr (REP == ISO_PREC_BF16) {
                     bf16x8 a[2], b[2];
 #pragma unroll
                     for (int jb = 0; jb < 2; ++jb)
@@ -218,22 +249,37 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
 #undef ISO_SSTORE
 }
 
-template <bool BF16>
-void launch(const ScreenArgs &A, bool gather, hipStream_t s) {
+template <int REP>
+void launch(const ScreenArgs &A0, bool gather, hipStream_t s) {
+    ScreenArgs A = A0;
     if (gather) {
         if (A.nrows <= 0) return;
-        const unsigned blocks = (unsigned)((A.nrows + SCR_ROWS - 1) / SCR_ROWS);
-        hipLaunchKernelGGL((k_screen_mfma<BF16, true>), dim3(blocks), dim3(256), 0, s, A);
+        // enough workgroups to fill the chip: split the columns so that row
+        // blocks x column blocks >= 4 per CU (column blocks of whole tiles)
+        const int64_t rblocks = (A.nrows + SCR_ROWS - 1) / SCR_ROWS;
+        const int64_t tiles = A.n_pad / SCR_COLS;
+        int64_t splits = (4 * (int64_t)device_cus() + rblocks - 1) / rblocks;
+        splits = splits < 1 ? 1 : (splits > tiles ? tiles : splits);
+        A.col_split = (tiles + splits - 1) / splits * SCR_COLS;
+        splits = (A.n_pad + A.col_split - 1) / A.col_split;
+        hipLaunchKernelGGL((k_screen_mfma<REP, true>), dim3((unsigned)rblocks, (unsigned)splits), dim3(256), 0, s, A);
     } else {
+        A.col_split = A.n_pad;
         const unsigned blocks = (unsigned)(A.n_pad / SCR_ROWS);
-        hipLaunchKernelGGL((k_screen_mfma<BF16, false>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_screen_mfma<REP, false>), dim3(blocks), dim3(256), 0, s, A);
     }
     LAUNCH_CHECK();
 }
 
 }  // namespace
 
-void launch_screen_f32(const ScreenArgs &A, bool gather, hipStream_t s) { launch<false>(A, gather, s); }
-void launch_screen_bf16(const ScreenArgs &A, bool gather, hipStream_t s) { launch<true>(A, gather, s); }
+void launch_screen_rows(const ScreenArgs &A, bool gather, hipStream_t s) {
+    if (A.rep == ISO_PREC_BF16)
+        launch<ISO_PREC_BF16>(A, gather, s);
+    else if (A.rep == ISO_PREC_FP8)
+        launch<ISO_PREC_FP8>(A, gather, s);
+    else
+        launch<ISO_PREC_FP32>(A, gather, s);
+}
 
 }  // namespace iso

@@ -1,28 +1,35 @@
 // screen_pairs.hip -- symmetric Boruvka screen over tile pairs (gfx950 MFMA).
 //
-// The points are cut into tiles of PT = 256.  One workgroup handles one tile
-// pair (I, J) with I <= J, so every unordered pair of points is formed once:
-// the Gram tile G = X'_J X'_I^T is accumulated on MFMA (FP32 accumulate), then
+// The points are cut into tiles of PT = 256.  Every tile pair (I, J) with
+// I <= J is screened once, so every unordered pair of points is formed once:
+// the Gram block G = X'_J X'_I^T is accumulated on MFMA (FP32 accumulate), then
 //   Dhat^2 = s_i + s_j - 2 G  (masked: valid points, different components,
 //                              and i < j on the diagonal tile pairs)
 // updates both sides: the running minimum of every row i of I (over the
-// tile's columns) and of every column j of J (over the tile's rows) is merged
-// into a global per-point minimum with one atomic min per point and tile, and
-// every element whose lower bound can still beat that point's minimum is
-// appended to the point's global candidate list (screen.hpp gives the bound).
-// Lists are append-only: an entry stays even when a later minimum rules it
-// out (the recheck filters it), and a point whose list overflows is re-screened
-// by the row-sweep kernel starting from its final minimum.
+// block's columns) and of every column j of J (over the block's rows) is
+// merged into a global per-point minimum with atomic min, and every element
+// whose lower bound can still beat that point's minimum is appended to the
+// point's global candidate list (screen.hpp gives the bound).  Lists are
+// append-only: an entry stays even when a later minimum rules it out (the
+// recheck filters it), and a point whose list overflows is re-screened by the
+// row-sweep kernel starting from its final minimum.
 //
-// Tile pairs are enumerated in blocks of SB x SB tiles, and each XCD receives a
-// contiguous run of that order (workgroup ids are dealt to the eight XCDs in
-// turn), so the workgroups resident on one XCD share their I and J tiles in
-// its L2.
+// One workgroup (4 waves) screens one half of a tile pair: all PT rows of I
+// against PH = 128 columns of J.  Its LDS footprint (three 24 KB stages of the
+// K pipeline plus 5 KB of tile constants) lets two workgroups share a CU, so
+// one workgroup's epilogue, barriers and load latency overlap the other's
+// MFMA work.  Wave (wi, wj) computes rows [128 wi, +128) x columns
+// [64 wj, +64) as 4 x 2 blocks of the transposed 32 x 32 MFMA (MFMA rows =
+// columns j, MFMA columns = rows i; result register q of lane l is MFMA row
+// 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32): BF16
+// 32x32x16, FP8 E4M3 32x32x64 (unit block scales) or FP32 32x32x2.
 //
-// Workgroup: 8 waves; wave (wi, wj) computes rows i in [128 wi, +128) x
-// columns j in [64 wj, +64) as 4 x 2 blocks of the transposed 32 x 32 MFMA
-// (MFMA rows = columns j, MFMA columns = rows i; result register q of lane l
-// is MFMA row 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32).
+// Work items (tile pair, half) are enumerated with the diagonal pairs in a
+// launch of their own and the others in blocks of PAIR_SB x PAIR_SB tiles;
+// each XCD receives a contiguous run of that order (workgroup ids are dealt
+// to the eight XCDs in turn), so the workgroups resident on one XCD share
+// their I and J tiles in its L2.
+#include <algorithm>
 #include <vector>
 
 #include "screen.hpp"
@@ -32,56 +39,61 @@ namespace iso {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int PT = 256;     // points per tile
-constexpr int NSTAGE = 4;   // LDS stages of the K pipeline (loads run NSTAGE-1 chunks ahead)
-#ifndef PAIR_WI
-#define PAIR_WI 2           // waves along the tile's rows
-#endif
-#ifndef PAIR_WJ
-#define PAIR_WJ 4           // waves along the tile's columns
-#endif
+constexpr int PT = 256;                // points per tile (rows of a work item)
+constexpr int PH = 128;                // columns of a work item (half of tile J)
+constexpr int SROWS = PH + PT;         // staged rows per K chunk: the columns, then the rows
+constexpr int NW = 4;                  // waves per workgroup
+constexpr int RW = 128, CW = 64;       // rows and columns per wave
+constexpr int NIB = RW / 32, NJB = CW / 32;
+constexpr int RUNS = SROWS * 4 / 64 / NW;  // 1 KB DMA runs per wave and chunk
+constexpr int NPRE = (PT + PH + 64 * NW - 1) / (64 * NW);
 #ifndef PAIR_SB
-#define PAIR_SB 8           // tile pairs are ordered in blocks of PAIR_SB x PAIR_SB tiles
+#define PAIR_SB 8                      // tile pairs are ordered in blocks of PAIR_SB x PAIR_SB tiles
 #endif
-#ifndef PAIR_SETPRIO
-#define PAIR_SETPRIO 0      // raise the wave priority while it issues MFMAs
-#endif
+static_assert(RUNS * NW * 64 == SROWS * 4, "runs cover the staged slots");
+static_assert(PH % 16 == 0, "a run never straddles the column and row parts");
 
 // s_waitcnt immediate waiting for vmcnt <= n (expcnt and lgkmcnt left at their maxima)
 #define VMCNT(n) (((n) & 0xF) | (((n) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
 
-template <bool BF16>
+template <int REP>
 struct PPrec;
 
 template <>
-struct PPrec<true> {
+struct PPrec<ISO_PREC_BF16> {
     using T = uint16_t;
-    static constexpr int KC = 32;
-    static constexpr int LDK = KC + 8;
+    static constexpr int KC = 32;      // K elements per chunk (64 bytes per row)
     static constexpr int KSTEP = 16;
     static constexpr int VEC = 8;
 };
 
 template <>
-struct PPrec<false> {
+struct PPrec<ISO_PREC_FP8> {
+    using T = uint8_t;
+    static constexpr int KC = 64;
+    static constexpr int KSTEP = 64;
+    static constexpr int VEC = 32;
+};
+
+template <>
+struct PPrec<ISO_PREC_FP32> {
     using T = float;
     static constexpr int KC = 16;
-    static constexpr int LDK = KC + 4;
     static constexpr int KSTEP = 2;
     static constexpr int VEC = 1;
 };
 
 struct PairLDS {
-    uint32_t rmin[PT], cmin[PT];   // tile minima of rows (I) and columns (J)
-    float rthr[PT], cthr[PT];      // current global minima after the merge
-    float rE[PT], cE[PT];          // Emax of the tile's rows and columns
-    float csq[PT], crn[PT], cre[PT];
-    int32_t ccomp[PT];
-    float rrn[PT], rre[PT];
-    uint32_t chot[PT / 32];        // bit set: column's tile minimum is within its capture margin
-    int32_t rhot[PT];              // row's tile minimum is within its capture margin
+    uint32_t rmin[PT];     // tile minima of the rows; after the merge, the current global minima
+    uint32_t cmin[PH];     // same for the columns
+    float rE[PT], cE[PH];  // Emax
+    float csq[PH];         // s of the columns
+    int32_t ccomp[PH];     // component of the columns
+    int32_t rhot[PT];      // row's tile minimum is within its capture margin
+    uint32_t chot[PH / 32];
 };
 
 constexpr uint32_t INF_BITS = 0x7F800000u;  // +inf; every screen value is a nonnegative float or +inf
@@ -104,65 +116,51 @@ __device__ __forceinline__ uint32_t min_halves(uint32_t v) {
     return min(v, min((uint32_t)r[0], (uint32_t)r[1]));
 }
 
-template <bool BF16, bool DIAG, int WI, int WJ>
-__global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
-                                                                int64_t per_xcd, int64_t npairs) {
-    constexpr int NW = WI * WJ;           // waves
-    constexpr int RW = PT / WI;           // rows per wave
-    constexpr int CW = PT / WJ;           // columns per wave
-    constexpr int NIB = RW / 32, NJB = CW / 32;
-    constexpr int RUNS = 2 * PT * 4 / 64 / NW;  // 1 KB DMA runs per wave and chunk
-    using P = PPrec<BF16>;
+template <int REP, bool DIAG>
+__global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
+                                                            int64_t per_xcd, int64_t nitems) {
+    using P = PPrec<REP>;
     using T = typename P::T;
     __shared__ PairLDS S;
-    // NSTAGE staging buffers of one K chunk: rows 0..255 = tile J (columns j),
-    // rows 256..511 = tile I (rows i); 64 bytes per row in four 16-byte slots,
-    // slot (row, part) at row * 4 + (part xor ((row >> 2) & 3)), which makes
-    // the MFMA fragment reads (16 consecutive rows, one part) bank-conflict free.
-    __shared__ __attribute__((aligned(16))) uint4 stage0[2 * PT * 4];
-    __shared__ __attribute__((aligned(16))) uint4 stage1[2 * PT * 4];
-    __shared__ __attribute__((aligned(16))) uint4 stage2[2 * PT * 4];
-    __shared__ __attribute__((aligned(16))) uint4 stage3[2 * PT * 4];
-
-    // XCD-aware placement: workgroup b runs on XCD b mod 8
-    const int64_t b = blockIdx.x;
-    const int64_t idx = (b & 7) * per_xcd + (b >> 3);
-    if (idx >= npairs) return;
-    const int2 pr = pairs[idx];
-    const int64_t I0 = (int64_t)pr.x * PT, J0 = (int64_t)pr.y * PT;
+    // NSTAGE = 3 staging buffers of one K chunk: rows 0..PH-1 = the columns j,
+    // rows PH.. = the rows i; 64 bytes per row in four 16-byte slots, slot
+    // (row, part) at row * 4 + (part xor ((row >> 2) & 3)), which makes the
+    // MFMA fragment reads (16 consecutive rows, one part) bank-conflict free.
+    __shared__ __attribute__((aligned(16))) uint4 stage0[SROWS * 4];
+    __shared__ __attribute__((aligned(16))) uint4 stage1[SROWS * 4];
+    __shared__ __attribute__((aligned(16))) uint4 stage2[SROWS * 4];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wi = w / WJ, wj = w % WJ;
-    static_assert(NJB == 2, "each lane owns one of the wave's 64 columns");
-    const T *X = BF16 ? reinterpret_cast<const T *>(A.XB) : reinterpret_cast<const T *>(A.XT);
+    const int wi = w >> 1, wj = w & 1;
+    const T *X = REP == ISO_PREC_BF16  ? reinterpret_cast<const T *>(A.XB)
+                 : REP == ISO_PREC_FP8 ? reinterpret_cast<const T *>(A.XF8)
+                                       : reinterpret_cast<const T *>(A.XT);
     const int64_t d_pad = A.d_pad;
 
+    // XCD-aware placement: workgroup b runs on XCD b mod 8, and each XCD takes
+    // a contiguous run of the item order
+    const int64_t b = blockIdx.x;
+    const int64_t idx = (b & 7) * per_xcd + (b >> 3);
+    if (idx >= nitems) return;
+    const int2 pr = pairs[idx >> 1];
+    const int half = (int)(idx & 1);
+    const int64_t I0 = (int64_t)pr.x * PT, J0 = (int64_t)pr.y * PT + half * PH;
+
     // tile constants
-    for (int tid = threadIdx.x; tid < PT; tid += 64 * NW) {
-        const int64_t i = I0 + tid, j = J0 + tid;
-        S.rmin[tid] = __float_as_uint(SCR_INF);
-        S.cmin[tid] = __float_as_uint(SCR_INF);
+    {
+        const int64_t i = I0 + tid;
+        S.rmin[tid] = INF_BITS;
         S.rE[tid] = i < A.n ? A.Emax[i] : 0.0f;
-        S.cE[tid] = j < A.n ? A.Emax[j] : 0.0f;
-        S.rrn[tid] = A.rn[i];
-        S.rre[tid] = A.re[i];
-        S.csq[tid] = A.sq[j];
-        S.crn[tid] = A.rn[j];
-        S.cre[tid] = A.re[j];
-        S.ccomp[tid] = A.comp[j];
+        if (tid < PH) {
+            const int64_t j = J0 + tid;
+            S.cmin[tid] = INF_BITS;
+            S.cE[tid] = j < A.n ? A.Emax[j] : 0.0f;
+            S.csq[tid] = A.sq[j];
+            S.ccomp[tid] = A.comp[j];
+        }
     }
-    // the global minima of the tile's rows (u < PT) and columns, read now so the
-    // load is hidden behind the K loop; a value read early is an upper bound of
-    // the current one, which only loosens the capture threshold
-    constexpr int NPRE = 2 * PT / (64 * NW);
-    uint32_t bpre[NPRE];
-#pragma unroll
-    for (int e = 0; e < NPRE; ++e) {
-        const int u = tid + e * 64 * NW;
-        const int64_t p = (u < PT ? I0 : J0) + (u & (PT - 1));
-        bpre[e] = p < A.n ? reinterpret_cast<const volatile uint32_t *>(A.best)[p] : INF_BITS;
-    }
+    static_assert(64 * NW == PT, "one thread per row");
     float si[NIB];
     int ci[NIB];
 #pragma unroll
@@ -172,26 +170,27 @@ __global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, 
         ci[ib] = A.comp[i];
     }
 
-    // asynchronous staging: each wave moves four 1 KB runs of slots per chunk
-    // with global_load_lds_dwordx4 (lane L of a run fills slot base + L)
+    // asynchronous staging: each wave moves RUNS 1 KB runs of slots per chunk
+    // with global_load_lds_dwordx4 (lane L of a run fills slot base + L); a run
+    // covers 16 rows, all columns (runs < PH / 16) or all rows
     constexpr int CHUNK = 16 / sizeof(T);  // elements per slot
     static_assert(P::KC * sizeof(T) == 64, "one K chunk is 64 bytes per row");
     const char *XJb = reinterpret_cast<const char *>(X + J0 * d_pad);
     const char *XIb = reinterpret_cast<const char *>(X + I0 * d_pad);
-    uint32_t soff[RUNS];  // byte offset of this lane's slot source within its tile
+    uint32_t soff[RUNS];  // byte offset of this lane's slot source within its part
 #pragma unroll
     for (int r = 0; r < RUNS; ++r) {
         const int slot = (w * RUNS + r) * 64 + lane;
         const int row = slot >> 2;
         const int part = (slot & 3) ^ ((row >> 2) & 3);
-        soff[r] = (uint32_t)((((int64_t)(row & (PT - 1))) * d_pad + part * CHUNK) * (int64_t)sizeof(T));
+        const int64_t local = row < PH ? row : row - PH;
+        soff[r] = (uint32_t)((local * d_pad + part * CHUNK) * (int64_t)sizeof(T));
     }
     const int nchunks = (int)(d_pad / P::KC);
-    // a run covers 16 rows, all of tile J (runs 0..15) or all of tile I
 #define ISO_ISSUE(STG, C)                                                                                     \
     {                                                                                                        \
         _Pragma("unroll") for (int r = 0; r < RUNS; ++r) __builtin_amdgcn_global_load_lds(                  \
-            (const void *)((w * RUNS + r < PT / 16 ? XJb : XIb) + (int64_t)(C) * 64 + soff[r]),              \
+            (const void *)((w * RUNS + r < PH / 16 ? XJb : XIb) + (int64_t)(C) * 64 + soff[r]),              \
             (__attribute__((address_space(3))) void *)&STG[(w * RUNS + r) * 64], 16, 0, 0);                \
     }
 
@@ -203,29 +202,36 @@ __global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, 
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[ib][jb][q] = 0.0f;
 
-    // fragment slot of (operand row, k offset in elements) in a stage
+    // fragment slot of (staged row, k offset in elements) in a stage
     auto frag_slot = [](int row, int kel) {
         const int part = (kel * (int)sizeof(T)) >> 4;
         return row * 4 + (part ^ ((row >> 2) & 3));
     };
 
-    // One pipeline step on chunk C held in stage SB: wait for it (chunks C+1, C+2
-    // may stay in flight), barrier (no fence: the DMA data is in LDS once the
-    // issuing wave's vmcnt has dropped), refill stage SN with chunk C+3, compute.
+    // One pipeline step on chunk C held in stage SB: wait for it (chunk C+1 may
+    // stay in flight), barrier (no fence: the DMA data is in LDS once the
+    // issuing wave's vmcnt has dropped; every wave has finished reading stage
+    // SN, consumed in the previous step), refill stage SN with chunk C+2, compute.
 #define ISO_STEP(SB, SN, C)                                                                                   \
     if ((C) < nchunks) {                                                                                     \
-        if ((C) + 2 < nchunks)                                                                               \
-            __builtin_amdgcn_s_waitcnt(VMCNT(2 * RUNS));                                                     \
-        else if ((C) + 1 < nchunks)                                                                          \
+        if ((C) + 1 < nchunks)                                                                               \
             __builtin_amdgcn_s_waitcnt(VMCNT(RUNS));                                                         \
         else                                                                                                 \
             __builtin_amdgcn_s_waitcnt(VMCNT(0));                                                            \
         __builtin_amdgcn_s_barrier();                                                                        \
-        if ((C) + 3 < nchunks) ISO_ISSUE(SN, (C) + 3)                                                        \
+        if ((C) + 2 < nchunks) ISO_ISSUE(SN, (C) + 2)                                                        \
         ISO_COMPUTE(SB)                                                                                      \
     }
 
-    if constexpr (BF16) {
+#define ISO_PIPELINE                                                                                          \
+    if (0 < nchunks) ISO_ISSUE(stage0, 0)                                                                    \
+    if (1 < nchunks) ISO_ISSUE(stage1, 1)                                                                    \
+    for (int c = 0; c < nchunks; c += 3) {                                                                   \
+        ISO_STEP(stage0, stage2, c)                                                                          \
+        ISO_STEP(stage1, stage0, c + 1)                                                                      \
+        ISO_STEP(stage2, stage1, c + 2)                                                                      \
+    }
+    if constexpr (REP == ISO_PREC_BF16) {
 #define ISO_COMPUTE(SB)                                                                                       \
     _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
         const int kel = ks + (lane >> 5) * P::VEC;                                                             \
@@ -235,24 +241,37 @@ __global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, 
             a[jb] = *reinterpret_cast<const bf16x8 *>(&v);                                                    \
         }                                                                                                     \
         _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                                  \
-            const uint4 v = SB[frag_slot(PT + RW * wi + 32 * ib + (lane & 31), kel)];                          \
+            const uint4 v = SB[frag_slot(PH + RW * wi + 32 * ib + (lane & 31), kel)];                          \
             bb[ib] = *reinterpret_cast<const bf16x8 *>(&v);                                                   \
         }                                                                                                     \
-        if (PAIR_SETPRIO) __builtin_amdgcn_s_setprio(1);                                                      \
         _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) \
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);        \
-        if (PAIR_SETPRIO) __builtin_amdgcn_s_setprio(0);                                                      \
     }
-        if (0 < nchunks) ISO_ISSUE(stage0, 0)
-        if (1 < nchunks) ISO_ISSUE(stage1, 1)
-        if (2 < nchunks) ISO_ISSUE(stage2, 2)
-        for (int c = 0; c < nchunks; c += 4) {
-            ISO_STEP(stage0, stage3, c)
-            ISO_STEP(stage1, stage0, c + 1)
-            ISO_STEP(stage2, stage1, c + 2)
-            ISO_STEP(stage3, stage2, c + 3)
-        }
+        ISO_PIPELINE
 #undef ISO_COMPUTE
+    } else if constexpr (REP == ISO_PREC_FP8) {
+        // one 32 x 32 x 64 FP8 MFMA per block and chunk: lane l supplies row
+        // l mod 32 and k = 32 (l div 32) .. +31, i.e. slots 2 (l div 32) and
+        // 2 (l div 32) + 1 of the row; unit block scales (E8M0 code 127)
+#define ISO_FRAG8(SB, ROW, OUT)                                                                               \
+    {                                                                                                        \
+        const uint4 v0 = SB[frag_slot((ROW), 32 * (lane >> 5))];                                             \
+        const uint4 v1 = SB[frag_slot((ROW), 32 * (lane >> 5) + 16)];                                        \
+        OUT = intx8{(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, (int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w};  \
+    }
+#define ISO_COMPUTE(SB)                                                                                       \
+    {                                                                                                        \
+        intx8 a[NJB], bb[NIB];                                                                                \
+        _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) ISO_FRAG8(SB, CW * wj + 32 * jb + (lane & 31), a[jb]) \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib)                                                    \
+            ISO_FRAG8(SB, PH + RW * wi + 32 * ib + (lane & 31), bb[ib])                                       \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) \
+            acc[ib][jb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[jb], bb[ib], acc[ib][jb], 0, 0, 0,   \
+                                                                          0x7F7F7F7F, 0, 0x7F7F7F7F);         \
+    }
+        ISO_PIPELINE
+#undef ISO_COMPUTE
+#undef ISO_FRAG8
     } else {
 #define ISO_COMPUTE(SB)                                                                                       \
     _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
@@ -263,21 +282,14 @@ __global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, 
         _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) a[jb] =                                            \
             sf[frag_slot(CW * wj + 32 * jb + (lane & 31), kel) * 4 + within];                                  \
         _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) bb[ib] =                                           \
-            sf[frag_slot(PT + RW * wi + 32 * ib + (lane & 31), kel) * 4 + within];                             \
+            sf[frag_slot(PH + RW * wi + 32 * ib + (lane & 31), kel) * 4 + within];                             \
         _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) \
             acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);           \
     }
-        if (0 < nchunks) ISO_ISSUE(stage0, 0)
-        if (1 < nchunks) ISO_ISSUE(stage1, 1)
-        if (2 < nchunks) ISO_ISSUE(stage2, 2)
-        for (int c = 0; c < nchunks; c += 4) {
-            ISO_STEP(stage0, stage3, c)
-            ISO_STEP(stage1, stage0, c + 1)
-            ISO_STEP(stage2, stage1, c + 2)
-            ISO_STEP(stage3, stage2, c + 3)
-        }
+        ISO_PIPELINE
 #undef ISO_COMPUTE
     }
+#undef ISO_PIPELINE
 #undef ISO_STEP
 #undef ISO_ISSUE
     // (the epilogue uses only PairLDS, so no barrier is needed before it)
@@ -287,81 +299,86 @@ __global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, 
     // the lane's 32 columns, then lanes l, l+32) and of columns (in-lane over the
     // lane's 4 rows, then the 32 lanes of the half wave; lane 16 jb + q of each
     // half keeps column (jb, q) and merges it into LDS once at the end)
-#define ISO_EPI1(DIAG)                                                                                        \
-    {                                                                                                        \
-        uint32_t m[NIB];                                                                                     \
-        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) m[ib] = INF_BITS;                                 \
-        uint32_t cown = INF_BITS;                                                                            \
-        _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) _Pragma("unroll") for (int q = 0; q < 16; ++q) {   \
-            const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);                     \
-            const float sj = S.csq[jl];                                                                      \
-            const int cjj = S.ccomp[jl];                                                                     \
-            uint32_t cmin = INF_BITS;                                                                        \
-            _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                             \
-                const int32_t tb = __float_as_int(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj));                 \
-                uint32_t v = (cjj == ci[ib]) ? INF_BITS : (uint32_t)max(tb, 0);                             \
-                if (DIAG && jl <= RW * wi + 32 * ib + (lane & 31)) v = INF_BITS; /* each pair once */       \
-                acc[ib][jb][q] = __uint_as_float(v);                                                         \
-                m[ib] = min(m[ib], v);                                                                       \
-                cmin = min(cmin, v);                                                                         \
-            }                                                                                                \
-            const uint32_t cm = min32(cmin);                                                                 \
-            if ((lane & 31) == 16 * jb + q) cown = cm;                                                       \
-            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0); /* bound the columns in flight */          \
-        }                                                                                                    \
-        {                                                                                                    \
-            const int qo = lane & 15, jo = (lane >> 4) & 1;                                                  \
-            const int jl = CW * wj + 32 * jo + 8 * (qo >> 2) + 4 * (lane >> 5) + (qo & 3);                   \
-            if (cown < INF_BITS) atomicMin(&S.cmin[jl], cown);                                               \
-        }                                                                                                    \
-        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                                 \
-            const uint32_t mm = min_halves(m[ib]); /* lanes l and l+32 hold the same rows */                 \
-            if ((lane >> 5) == 0 && mm < INF_BITS) atomicMin(&S.rmin[RW * wi + 32 * ib + (lane & 31)], mm);   \
-        }                                                                                                    \
+    {
+        uint32_t m[NIB];
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib) m[ib] = INF_BITS;
+        uint32_t cown = INF_BITS;
+#pragma unroll
+        for (int jb = 0; jb < NJB; ++jb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const float sj = S.csq[jl];
+                const int cjj = S.ccomp[jl];
+                uint32_t cmin = INF_BITS;
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib) {
+                    const int32_t tb = __float_as_int(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj));
+                    uint32_t v = (cjj == ci[ib]) ? INF_BITS : (uint32_t)max(tb, 0);
+                    if (DIAG && half * PH + jl <= RW * wi + 32 * ib + (lane & 31)) v = INF_BITS;  // each pair once
+                    acc[ib][jb][q] = __uint_as_float(v);
+                    m[ib] = min(m[ib], v);
+                    cmin = min(cmin, v);
+                }
+                const uint32_t cm = min32(cmin);
+                if ((lane & 31) == 16 * jb + q) cown = cm;
+                if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the columns in flight
+            }
+        {
+            const int qo = lane & 15, jo = (lane >> 4) & 1;
+            const int jl = CW * wj + 32 * jo + 8 * (qo >> 2) + 4 * (lane >> 5) + (qo & 3);
+            if (cown < INF_BITS) atomicMin(&S.cmin[jl], cown);
+        }
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib) {
+            const uint32_t mm = min_halves(m[ib]);  // lanes l and l+32 hold the same rows
+            if ((lane >> 5) == 0 && mm < INF_BITS) atomicMin(&S.rmin[RW * wi + 32 * ib + (lane & 31)], mm);
+        }
     }
-    ISO_EPI1(DIAG)
-#undef ISO_EPI1
+    if (tid < PH / 32) S.chot[tid] = 0u;
     __syncthreads();
 
     // ---- epilogue 2: merge into the global minima (no-return atomics, only
-    // where the tile lowers the value read before the K loop); thresholds from
-    // the merged values; flag the rows and columns whose tile minimum can still
-    // be captured
-    if (tid < PT / 32) S.chot[tid] = 0u;
-    __syncthreads();
+    // where the item lowers the current value); the merged value
+    // replaces the tile minimum in LDS as the threshold base; flag the rows and
+    // columns whose tile minimum can still be captured
 #pragma unroll
     for (int e = 0; e < NPRE; ++e) {
         const int u = tid + e * 64 * NW;
-        const int t = u & (PT - 1);
+        if (u >= PT + PH) break;
         const bool is_row = u < PT;
-        const int64_t p = (is_row ? I0 : J0) + t;
+        const int t = is_row ? u : u - PT;
+        const int64_t p = is_row ? I0 + t : J0 + t;
         const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
-        const uint32_t old = bpre[e];
+        const uint32_t old = p < A.n ? reinterpret_cast<const volatile uint32_t *>(A.best)[p] : INF_BITS;
         if (p < A.n && m < old) atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m);
         const float cur = p < A.n ? __uint_as_float(min(old, m)) : SCR_INF;
         const float E = is_row ? S.rE[t] : S.cE[t];
         const bool hot = p < A.n && __uint_as_float(m) <= (cur + 2.0f * E) * A.kappa;
         if (is_row) {
-            S.rthr[t] = cur;
+            S.rmin[t] = __float_as_uint(cur);
             S.rhot[t] = hot ? 1 : 0;
         } else {
-            S.cthr[t] = cur;
+            S.cmin[t] = __float_as_uint(cur);
             if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
         }
     }
     __syncthreads();
 
-    // ---- epilogue 3: capture candidates (rows of hot rows, columns of hot columns)
+    // ---- epilogue 3: capture candidates (rows of hot rows, columns of hot
+    // columns); the norm and representation bounds are read from global memory
+    // on this rare path
 #pragma unroll
     for (int ib = 0; ib < NIB; ++ib) {
         const int il = RW * wi + 32 * ib + (lane & 31);
         if (!S.rhot[il]) continue;
         const int64_t i = I0 + il;
         const float Ei = S.rE[il];
-        const float rb_ = S.rthr[il];
+        const float rb_ = __uint_as_float(S.rmin[il]);
         const float r_cheap = (rb_ + 2.0f * Ei) * A.kappa;
         const float r_thr = (rb_ + Ei) * A.kappa;
-        const float ri = S.rrn[il], ei = S.rre[il];
+        const float ri = A.rn[i], ei = A.re[i];
 #pragma unroll
         for (int jb = 0; jb < NJB; ++jb)
 #pragma unroll
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, 
                 const float v = acc[ib][jb][q];
                 if (!(v <= r_cheap)) continue;
                 const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const float L = lower_of(v, pair_bound(A.bound, ri, S.crn[jl], ei, S.cre[jl]));
+                const float L = lower_of(v, pair_bound(A.bound, ri, A.rn[J0 + jl], ei, A.re[J0 + jl]));
                 if (!(L <= r_thr)) continue;
                 const int pos = atomicAdd(&A.ccnt[i], 1);
                 if (pos < SCR_CAP) {
@@ -391,15 +408,16 @@ __global__ __launch_bounds__(64 * WI * WJ, 1) void k_screen_pairs(ScreenArgs A, 
             const int jl = CW * wj + 32 * jb + jc;
             const int64_t j = J0 + jl;
             const float Ej = S.cE[jl];
-            const float cb = S.cthr[jl];
+            const float cb = __uint_as_float(S.cmin[jl]);
             const float c_cheap = (cb + 2.0f * Ej) * A.kappa;
             const float c_thr = (cb + Ej) * A.kappa;
+            const float rj = A.rn[j], ej = A.re[j];
 #pragma unroll
             for (int ib = 0; ib < NIB; ++ib) {
                 const float v = acc[ib][jb][q];
                 if (!(v <= c_cheap)) continue;
                 const int il = RW * wi + 32 * ib + (lane & 31);
-                const float L = lower_of(v, pair_bound(A.bound, S.rrn[il], S.crn[jl], S.rre[il], S.cre[jl]));
+                const float L = lower_of(v, pair_bound(A.bound, A.rn[I0 + il], rj, A.re[I0 + il], ej));
                 if (!(L <= c_thr)) continue;
                 const int pos = atomicAdd(&A.ccnt[j], 1);
                 if (pos < SCR_CAP) {
@@ -432,31 +450,38 @@ std::vector<int2> make_pair_order(int64_t nt) {
     return out;
 }
 
-template <bool BF16>
+namespace {
+
+template <int REP>
 void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, hipStream_t s) {
     const int64_t nt = A.n_pad / PT;
     ISO_REQUIRE(npairs == nt * (nt + 1) / 2, ISO_ERR_INTERNAL, "tile-pair list does not match the padded size");
-    const dim3 block(64 * PAIR_WI * PAIR_WJ);
-    // diagonal tile pairs (only i < j counted) ...
-    int64_t per_xcd = (nt + 7) / 8;
-    hipLaunchKernelGGL((k_screen_pairs<BF16, true, PAIR_WI, PAIR_WJ>), dim3((unsigned)(per_xcd * 8)), block, 0, s, A,
-                       pairs, per_xcd, nt);
+    ISO_REQUIRE(A.d_pad % PPrec<REP>::KC == 0, ISO_ERR_INTERNAL, "padded dimension is not a whole number of chunks");
+    const dim3 block(64 * NW);
+    auto grid = [](int64_t per_xcd) { return dim3((unsigned)(8 * per_xcd)); };
+    // diagonal tile pairs (only i < j counted), two halves each ...
+    int64_t items = 2 * nt;
+    int64_t per_xcd = (items + 7) / 8;
+    hipLaunchKernelGGL((k_screen_pairs<REP, true>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
     LAUNCH_CHECK();
     // ... then the others
-    const int64_t rest = npairs - nt;
-    if (rest > 0) {
-        per_xcd = (rest + 7) / 8;
-        hipLaunchKernelGGL((k_screen_pairs<BF16, false, PAIR_WI, PAIR_WJ>), dim3((unsigned)(per_xcd * 8)), block, 0, s,
-                           A, pairs + nt, per_xcd, rest);
+    items = 2 * (npairs - nt);
+    if (items > 0) {
+        per_xcd = (items + 7) / 8;
+        hipLaunchKernelGGL((k_screen_pairs<REP, false>), grid(per_xcd), block, 0, s, A, pairs + nt, per_xcd, items);
         LAUNCH_CHECK();
     }
 }
 
-void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, bool bf16, hipStream_t s) {
-    if (bf16)
-        launch_pairs<true>(A, pairs, npairs, s);
+}  // namespace
+
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, hipStream_t s) {
+    if (A.rep == ISO_PREC_BF16)
+        launch_pairs<ISO_PREC_BF16>(A, pairs, npairs, s);
+    else if (A.rep == ISO_PREC_FP8)
+        launch_pairs<ISO_PREC_FP8>(A, pairs, npairs, s);
     else
-        launch_pairs<false>(A, pairs, npairs, s);
+        launch_pairs<ISO_PREC_FP32>(A, pairs, npairs, s);
 }
 
 }  // namespace iso

@@ -40,6 +40,7 @@ CASES = {
     "c1-n2000-d16": lambda: datagen.config(1),
     "c2-n2500-d64": lambda: datagen.config(2, n=2500),
     "c3-n1500-d784": lambda: datagen.config(3, n=1500),
+    "c4-n1000-d4096": lambda: datagen.config(4, n=1000),
     "c5-n3000-d128": lambda: datagen.config(5, n=3000),
     "uniform-n333-d3": lambda: datagen.uniform(333, 3),
     "lattice-12x12": lambda: datagen.lattice(12, 2),
@@ -63,7 +64,7 @@ def _oracle_tree(orc, name):
     return _cache[name]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_mst_fp64_recheck_identical(iso, orc, name, precision):
     X, op, ol = _oracle_tree(orc, name)
@@ -78,7 +79,7 @@ def test_mst_fp64_recheck_identical(iso, orc, name, precision):
     assert abs(info["mst_weight"] - W) <= 1e-12 * max(W, 1e-300)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_mst_fp32_recheck_near_ties_only(iso, orc, name, precision):
     X, op, ol = _oracle_tree(orc, name)
@@ -124,9 +125,9 @@ def test_subpartition_on_oracle_tree(iso, orc, name, k, phi, bracket):
         assert abs(info[key] - getattr(ref, key)) <= 1e-13 * abs(getattr(ref, key))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("name,k", [("c1-n2000-d16", 5), ("c5-n3000-d128", 16), ("c3-n1500-d784", 10),
-                                    ("c2-n2500-d64", 20)])
+                                    ("c2-n2500-d64", 20), ("c4-n1000-d4096", 50)])
 def test_end_to_end(iso, orc, name, k, precision):
     X, op, ol = _oracle_tree(orc, name)
     H.log("case %s end to end k=%d %s screen" % (name, k, precision))
@@ -138,7 +139,7 @@ def test_end_to_end(iso, orc, name, k, precision):
         np.testing.assert_array_equal(labels.cpu().numpy(), ref.labels)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 def test_determinism(iso, precision):
     X = torch.from_numpy(datagen.config(5, n=4000)).cuda()
     H.log("determinism n=4000 d=128 %s" % precision)
@@ -166,12 +167,15 @@ def test_errors(iso):
     assert e.value.code == -1
 
 
-def test_screen_precision_does_not_change_tree(iso):
-    """The screen only proposes candidates: FP32 and BF16 screens give the same
-    tree under the same recheck."""
-    X = torch.from_numpy(datagen.config(3, n=3000)).cuda()
-    H.log("screen precision invariance c3 n=3000")
+@pytest.mark.parametrize("cfg,n", [(3, 3000), (4, 3000)])
+def test_screen_precision_does_not_change_tree(iso, cfg, n):
+    """The screen only proposes candidates: FP32, BF16 and FP8 screens give
+    the same tree under the same recheck."""
+    X = torch.from_numpy(datagen.config(cfg, n=n)).cuda()
+    H.log("screen precision invariance config %d n=%d" % (cfg, n))
     a = iso.mst(X, precision="fp32")
-    b = iso.mst(X, precision="bf16")
-    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
-    assert a[2]["rescanned_rows"] == 0 and b[2]["rescanned_rows"] == 0
+    for prec in ("bf16", "fp8"):
+        b = iso.mst(X, precision=prec)
+        H.log("  %s: candidates %d rescanned %d (fp32: %d, %d)" % (prec, b[2]["candidates"], b[2]["rescanned_rows"],
+                                                                   a[2]["candidates"], a[2]["rescanned_rows"]))
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
