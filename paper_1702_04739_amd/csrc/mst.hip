@@ -23,6 +23,7 @@
 //   relabel   : compact component ids by an exclusive scan.
 // After the last round: FP64 edge lengths and a BFS from vertex 0 give the
 // parent list (Sec. 3.3) rooted at 0.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -263,12 +264,11 @@ __device__ inline bool key_less(double d2a, int ja, double d2b, int jb) {
 // bound on the recheck value of c's lightest outgoing edge.
 __global__ void k_comp_ub(const float *__restrict__ best, const float *__restrict__ Emax,
                           const int32_t *__restrict__ comp, int64_t n, float up, uint32_t *__restrict__ comp_ub) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float b = best[i];
-    if (!(b < SCR_INF)) return;
-    float u = (b + Emax[i]) * up;
-    atomicMin(&comp_ub[comp[i]], __float_as_uint(u));
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float b = i < n ? best[i] : SCR_INF;
+    const bool active = b < SCR_INF;
+    const float u = active ? (b + Emax[i]) * up : 0.0f;
+    grouped_atomic_min(comp_ub, active ? comp[i] : 0, __float_as_uint(u), active);
 }
 
 // Exact lightest candidate of row i among the cnt entries (js, ls) whose lower
@@ -542,9 +542,9 @@ __global__ void k_relabel(int32_t *__restrict__ comp, int64_t n, const int32_t *
 // Component sizes and the sum of their squares (timing only: the screen of a
 // round must cover (n^2 - sum |c|^2) / 2 unordered pairs).
 __global__ void k_comp_sizes(const int32_t *__restrict__ comp, int64_t n, int32_t *__restrict__ size) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    atomicAdd(&size[comp[i]], 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    grouped_atomic_count(size, active ? comp[i] : 0, active);
 }
 
 __global__ __launch_bounds__(1024) void k_sum_squares(const int32_t *__restrict__ size, int64_t m,
@@ -565,11 +565,50 @@ __global__ __launch_bounds__(1024) void k_sum_squares(const int32_t *__restrict_
 
 // Length of each tree edge: sqrt of the FP64 left-to-right sum of squared
 // coordinate differences.
-__global__ void k_refine(const float *__restrict__ X, int64_t d, int64_t ld, const int32_t *__restrict__ eu,
-                         const int32_t *__restrict__ ev, int64_t m, double *__restrict__ elen) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    elen[e] = sqrt(d2_f64_lane(X + (int64_t)eu[e] * ld, X + (int64_t)ev[e] * ld, d));
+// FP64 edge lengths: one lane per edge sums its squared coordinate differences
+// left to right (as d2_f64_lane); the two rows of the wave's 64 edges are
+// staged through LDS 16 coordinates at a time with coalesced loads.
+constexpr int REF_T = 16;
+__global__ __launch_bounds__(256) void k_refine(const float *__restrict__ X, int64_t d, int64_t ld,
+                                                const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+                                                int64_t m, double *__restrict__ elen) {
+    __shared__ float st[4][2][64][REF_T + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+    // loader roles: slot k of this lane stages 4 coordinates of row (r) of edge
+    // e0 + ed, ed = idx / 8, r = (idx / 4) mod 2, part = idx mod 4, idx = lane + 64 k
+    const float *src[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int idx = lane + 64 * k;
+        const int64_t ee = e0 + (idx >> 3);
+        const int r = (idx >> 2) & 1;
+        src[k] = ee < m ? X + (int64_t)(r ? ev[ee] : eu[ee]) * ld + 4 * (idx & 3) : nullptr;
+    }
+    double s = 0.0;
+    for (int64_t t0 = 0; t0 < d; t0 += REF_T) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int idx = lane + 64 * k;
+            float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (src[k]) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (t0 + 4 * (idx & 3) + c < d) v[c] = src[k][t0 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) st[w][(idx >> 2) & 1][idx >> 3][4 * (idx & 3) + c] = v[c];
+        }
+        __syncthreads();
+        const int tn = d - t0 < REF_T ? (int)(d - t0) : REF_T;
+        for (int c = 0; c < tn; ++c) {
+            const double df = (double)st[w][0][lane][c] - (double)st[w][1][lane][c];
+            const double p = df * df;
+            s = s + p;
+        }
+        __syncthreads();
+    }
+    if (e0 + lane < m) elen[e0 + lane] = sqrt(s);
 }
 
 __global__ void k_degree(const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
@@ -594,56 +633,50 @@ __global__ void k_fill_adj(const int32_t *__restrict__ eu, const int32_t *__rest
     adje[pb] = (int32_t)e;
 }
 
-// Level-synchronous BFS from vertex 0 in one workgroup: parent, FP64 length
-// of the parent edge, and the depth.
-__global__ __launch_bounds__(1024) void k_bfs_root0(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
-                                                    const int32_t *__restrict__ adje, const double *__restrict__ elen,
-                                                    int64_t n, int32_t *__restrict__ parent,
-                                                    double *__restrict__ length, int32_t *__restrict__ depth,
-                                                    int32_t *__restrict__ fa, int32_t *__restrict__ fb,
-                                                    int32_t *__restrict__ counters) {
-    __shared__ int32_t s_next;
-    __shared__ int32_t s_size;
-    __shared__ int32_t s_seen;
-    if (threadIdx.x == 0) {
-        parent[0] = -1;
-        length[0] = 0.0;
-        depth[0] = 0;
-        fa[0] = 0;
-        s_size = 1;
-        s_next = 0;
-        s_seen = 1;
-    }
-    __syncthreads();
-    int32_t *cur = fa, *nxt = fb;
-    while (true) {
-        const int size = s_size;
-        if (size == 0) break;
-        for (int q = threadIdx.x; q < size; q += blockDim.x) {
-            const int v = cur[q];
-            const int pv = parent[v];
-            const int dv = depth[v];
-            for (int a = off[v]; a < off[v + 1]; ++a) {
-                const int w = adj[a];
-                if (w == pv) continue;
-                if (atomicCAS(&depth[w], -1, dv + 1) != -1) continue;  // visited (only on a malformed edge set)
-                parent[w] = v;
-                length[w] = elen[adje[a]];
-                nxt[atomicAdd(&s_next, 1)] = w;
-            }
+// Rooting BFS from vertex 0, one launch per level.  Level L occupies
+// order[start[L] .. start[L] + cnt[L]); one wave per frontier vertex walks its
+// adjacency 64 entries at a time and appends the unvisited neighbours to level
+// L+1 (the depth CAS admits every vertex at most once, so order never
+// overflows even on a malformed edge set).  A launch whose level is empty
+// returns at once, so levels can be launched past the tree's depth.
+__global__ void k_bfs_init(int32_t *__restrict__ parent, double *__restrict__ length, int32_t *__restrict__ depth,
+                           int32_t *__restrict__ order, int32_t *__restrict__ start, int32_t *__restrict__ cnt) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    parent[0] = -1;
+    length[0] = 0.0;
+    depth[0] = 0;
+    order[0] = 0;
+    start[0] = 0;
+    cnt[0] = 1;
+}
+
+__global__ __launch_bounds__(256) void k_bfs_level(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                                                   const int32_t *__restrict__ adje, const double *__restrict__ elen,
+                                                   int32_t L, int32_t *__restrict__ parent,
+                                                   double *__restrict__ length, int32_t *__restrict__ depth,
+                                                   int32_t *__restrict__ order, int32_t *__restrict__ start,
+                                                   int32_t *__restrict__ cnt) {
+    const int32_t c = cnt[L];
+    if (c == 0) return;
+    const int32_t s0 = start[L];
+    const int32_t s1 = s0 + c;  // start of level L+1
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[L + 1] = s1;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = wave; q < c; q += nwaves) {
+        const int32_t v = order[s0 + q];
+        const int32_t pv = parent[v];
+        const int32_t dv = depth[v];
+        for (int32_t a = off[v] + lane; a < off[v + 1]; a += 64) {
+            const int32_t w = adj[a];
+            if (w == pv) continue;
+            if (atomicCAS(&depth[w], -1, dv + 1) != -1) continue;
+            parent[w] = v;
+            length[w] = elen[adje[a]];
+            order[s1 + atomicAdd(&cnt[L + 1], 1)] = w;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            s_size = s_next;
-            s_seen += s_next;
-            s_next = 0;
-        }
-        __syncthreads();
-        int32_t *t = cur;
-        cur = nxt;
-        nxt = t;
     }
-    if (threadIdx.x == 0) counters[C_SEEN] = s_seen;
 }
 
 // Deterministic FP64 sum of length[1..n) (one workgroup, fixed tree).
@@ -674,7 +707,7 @@ struct MstPlan {
     double *psum;
     uint32_t *rmax, *emax, *comp_ub;
     int32_t *comp, *ccnt, *cj, *glist, *gcnt, *gcj, *rlist, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev;
-    int32_t *deg, *aoff, *cursor, *adj, *adje, *fa, *fb, *depth;
+    int32_t *deg, *aoff, *cursor, *adj, *adje, *fa, *fb, *lcnt, *depth;
     double *rb_d2, *elen, *wsum;
     unsigned long long *ck1, *ck2;
     int32_t *counters;
@@ -713,8 +746,9 @@ struct MstPlan {
         cursor = a.take<int32_t>(n);
         adj = a.take<int32_t>(2 * n);
         adje = a.take<int32_t>(2 * n);
-        fa = a.take<int32_t>(n);
-        fb = a.take<int32_t>(n);
+        fa = a.take<int32_t>(n);       // BFS order
+        fb = a.take<int32_t>(n + 1);   // BFS level starts
+        lcnt = a.take<int32_t>(n + 1); // BFS level sizes
         depth = a.take<int32_t>(n);
         rb_d2 = a.take<double>(n);
         elen = a.take<double>(n);
@@ -965,14 +999,44 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                        P.adje);
     LAUNCH_CHECK();
     fill<int32_t>(P.depth, -1, n, s);
-    hipLaunchKernelGGL(k_bfs_root0, dim3(1), dim3(1024), 0, s, P.aoff, P.adj, P.adje, P.elen, n, parent, length,
-                       P.depth, P.fa, P.fb, P.counters);
+    fill<int32_t>(P.lcnt, 0, n + 1, s);
+    hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, s, parent, length, P.depth, P.fa, P.fb, P.lcnt);
     LAUNCH_CHECK();
+    // levels in batches of 32 between checks; a tree has at most n levels
+    // vertices reached = start of the first empty level
+    int32_t h_seen = 0;
+    {
+        constexpr int BATCH = 32;
+        int32_t L0 = 0;
+        while (true) {
+            const int32_t L1 = (int32_t)std::min<int64_t>(L0 + BATCH, n);
+            for (int32_t L = L0; L < L1; ++L) {
+                hipLaunchKernelGGL(k_bfs_level, dim3(1024), dim3(256), 0, s, P.aoff, P.adj, P.adje, P.elen, L, parent,
+                                   length, P.depth, P.fa, P.fb, P.lcnt);
+                LAUNCH_CHECK();
+            }
+            // sizes and starts of levels L0 .. L1 (level L1 is written by launch L1 - 1)
+            int32_t hc[BATCH + 1], hs[BATCH + 1];
+            const int cntn = L1 - L0 + 1 <= (int32_t)(n + 1 - L0) ? L1 - L0 + 1 : (int)(n + 1 - L0);
+            HIP_CHECK(hipMemcpyAsync(hc, P.lcnt + L0, sizeof(int32_t) * cntn, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(hs, P.fb + L0, sizeof(int32_t) * cntn, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            int e = -1;
+            for (int q = 0; q < cntn; ++q)
+                if (hc[q] == 0) {
+                    e = q;
+                    break;
+                }
+            if (e >= 0) {
+                h_seen = hs[e];
+                break;
+            }
+            ISO_REQUIRE(L1 < n, ISO_ERR_INTERNAL, "tree BFS did not terminate");
+            L0 = L1;
+        }
+    }
     hipLaunchKernelGGL(k_sum_lengths, dim3(1), dim3(1024), 0, s, length, n, P.wsum);
     LAUNCH_CHECK();
-    int32_t h_seen = 0;
-    HIP_CHECK(hipMemcpyAsync(&h_seen, P.counters + C_SEEN, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
     ISO_REQUIRE(h_seen == n, ISO_ERR_INTERNAL, "tree BFS reached %d of %lld vertices", h_seen, (long long)n);
     whole.stop(s);
     if (timed) {

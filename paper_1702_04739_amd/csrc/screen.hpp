@@ -86,6 +86,54 @@ struct ScreenLDS {
     int32_t ccomp[SCR_COLS];
 };
 
+// Minimum over the 64 lanes of a wave (every lane receives it), unsigned.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0xB1, 0xF, 0xF, false));   // quad xor 1
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x4E, 0xF, 0xF, false));   // quad xor 2
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x141, 0xF, 0xF, false));  // half-row mirror
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x140, 0xF, 0xF, false));  // row mirror
+    const auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min(v, min((uint32_t)r16[0], (uint32_t)r16[1]));
+    const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return min(v, min((uint32_t)r32[0], (uint32_t)r32[1]));
+}
+
+// atomicMin(&base[key], val) for the active lanes of a wave, with lanes that
+// share a key combined first (up to four keys per wave; the rest go straight
+// to the atomic).  Every lane of the wave must call it.
+__device__ __forceinline__ void grouped_atomic_min(uint32_t *base, int key, uint32_t val, bool active) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int it = 0; it < 4; ++it) {
+        const unsigned long long act = __ballot(active);
+        if (act == 0ull) return;
+        const int leader = __ffsll((long long)act) - 1;
+        const int lk = __shfl(key, leader, 64);
+        const bool mine = active && key == lk;
+        const uint32_t m = wave_min_u32(mine ? val : 0xFFFFFFFFu);
+        if (lane == leader) atomicMin(&base[lk], m);
+        active = active && !mine;
+    }
+    if (active) atomicMin(&base[key], val);
+}
+
+// atomicAdd(&base[key], 1) for the active lanes, lanes sharing a key combined.
+__device__ __forceinline__ void grouped_atomic_count(int32_t *base, int key, bool active) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int it = 0; it < 4; ++it) {
+        const unsigned long long act = __ballot(active);
+        if (act == 0ull) return;
+        const int leader = __ffsll((long long)act) - 1;
+        const int lk = __shfl(key, leader, 64);
+        const bool mine = active && key == lk;
+        const unsigned long long grp = __ballot(mine);
+        if (lane == leader) atomicAdd(&base[lk], (int32_t)__popcll(grp));
+        active = active && !mine;
+    }
+    if (active) atomicAdd(&base[key], 1);
+}
+
 __device__ __forceinline__ float pair_bound(const ScreenBound &B, float ri, float rj, float ei, float ej) {
     const float t = ri + rj, f = ei + ej;
     const float g = fmaxf(ri, rj) <= B.rlim ? B.g_exact : B.g;

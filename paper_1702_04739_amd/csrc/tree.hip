@@ -24,10 +24,13 @@ namespace iso {
 
 namespace {
 
-constexpr int SPEC_LEVELS = 6;
-constexpr int M = 64;                       // lanes per vertex in a speculative pass
-constexpr int NCAND = (1 << SPEC_LEVELS) - 1;  // 63 midpoints per pass
-constexpr int NARROW = 16;                  // levels with <= NARROW vertices run inside one workgroup
+#ifndef ISO_SPEC_LEVELS
+#define ISO_SPEC_LEVELS 6
+#endif
+constexpr int SPEC_LEVELS = ISO_SPEC_LEVELS;       // bisection steps resolved per pass
+constexpr int M = 1 << SPEC_LEVELS;                // lanes per vertex in a speculative pass
+constexpr int NCAND = M - 1;                       // midpoints per pass (the last lane re-checks beta)
+constexpr int NARROW = 16 * 64 / M > 1 ? 16 * 64 / M : 1;  // levels this narrow run inside one workgroup
 constexpr int PASS_BATCH = 4;
 
 struct TreeState {
