@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=6000)
+    ap.add_argument("--cpu-sample-n", type=int, default=8000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, run one plain device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--traffic-report", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),

@@ -162,8 +162,12 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
                                                    uint32_t *__restrict__ rmax_bits, uint32_t *__restrict__ emax_bits,
                                                    int32_t *__restrict__ grid_min) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n_pad) return;
+    // rows are walked with the stride of all waves; the maxima of r and e and
+    // the grid exponent are merged into the globals once per wave
+    uint32_t wr = 0u, we = 0u;
+    int wq = GRID_NONE;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n_pad; i += nwaves) {
     float s = 0.0f;
     double m2 = 0.0, e2 = 0.0;
     int q = GRID_NONE;
@@ -202,15 +206,21 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
         e2 += __shfl_xor(e2, off, 64);
         q = min(q, __shfl_xor(q, off, 64));
     }
+    const float r = __double2float_ru(sqrt(m2) * (1.0 + 0x1p-40));
+    const float e = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40));
     if (lane == 0) {
-        if (q != GRID_NONE) atomicMin(grid_min, q);
         sq[i] = i < n ? s : __builtin_huge_valf();  // padding: every Dhat^2 with it is +inf
-        const float r = __double2float_ru(sqrt(m2) * (1.0 + 0x1p-40));
-        const float e = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40));
         rn[i] = r;
         re[i] = e;
-        atomicMax(rmax_bits, __float_as_uint(r));
-        atomicMax(emax_bits, __float_as_uint(e));
+    }
+    wq = min(wq, q);
+    wr = max(wr, __float_as_uint(r));
+    we = max(we, __float_as_uint(e));
+    }
+    if (lane == 0) {
+        if (wq != GRID_NONE) atomicMin(grid_min, wq);
+        if (wr) atomicMax(rmax_bits, wr);
+        if (we) atomicMax(emax_bits, we);
     }
 }
 
@@ -815,8 +825,9 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     {
         auto kern = rep == ISO_PREC_BF16 ? k_repr_rows<ISO_PREC_BF16>
                                          : rep == ISO_PREC_FP8 ? k_repr_rows<ISO_PREC_FP8> : k_repr_rows<ISO_PREC_FP32>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(P.n_pad, 4)), dim3(256), 0, s, X, n, d, ld, P.n_pad, P.d_pad, P.mu, P.Xr,
-                           P.sq, P.rn, P.re, P.rmax, P.emax, P.grid_min);
+        const unsigned g = std::min<unsigned>(grid_for(P.n_pad, 4), 8u * (unsigned)device_cus());
+        hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, X, n, d, ld, P.n_pad, P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re,
+                           P.rmax, P.emax, P.grid_min);
     }
     LAUNCH_CHECK();
     const double u = 1.0 / 8388608.0;  // 2^-23

@@ -360,23 +360,29 @@ __global__ __launch_bounds__(1024) void k_dp_narrow(DPArgs A, int32_t L0, int32_
 
 // Midpoints of the next SPEC_LEVELS bisection steps, heap order: node q over
 // bracket (lo, hi) has midpoint (lo+hi)/2, left child (lo, mid) (answer YES),
-// right child (mid, hi) (answer NO).
-__global__ void k_make_cands(TreeState *__restrict__ st, double *__restrict__ Nvals) {
-    if (threadIdx.x != 0 || st->done) return;
-    double lo[NCAND], hi[NCAND];
-    lo[0] = st->alpha;
-    hi[0] = st->beta;
-    for (int q = 0; q < NCAND; ++q) {
-        const double mid = (lo[q] + hi[q]) / 2.0;
-        Nvals[q] = mid;
-        if (2 * q + 2 < NCAND) {
-            lo[2 * q + 1] = lo[q];
-            hi[2 * q + 1] = mid;
-            lo[2 * q + 2] = mid;
-            hi[2 * q + 2] = hi[q];
-        }
+// right child (mid, hi) (answer NO).  Thread q walks from the root to its node
+// (the bits of q+1 below the leading one, left = 0), repeating exactly the
+// midpoint arithmetic the bisection itself performs; the spare lane re-checks
+// beta.  Launched with M threads.
+__global__ void k_make_cands(const TreeState *__restrict__ st, double *__restrict__ Nvals) {
+    if (st->done) return;
+    const int q = threadIdx.x;
+    if (q > NCAND) return;
+    if (q == NCAND) {
+        Nvals[NCAND] = st->beta;
+        return;
     }
-    Nvals[NCAND] = st->beta;  // the spare lane re-checks beta
+    double lo = st->alpha, hi = st->beta;
+    const int node = q + 1;
+    const int lvl = 31 - __clz(node);  // depth of the node below the root
+    for (int l = lvl - 1; l >= 0; --l) {
+        const double mid = (lo + hi) / 2.0;
+        if ((node >> l) & 1)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    Nvals[q] = (lo + hi) / 2.0;
 }
 
 // Walks the answers of one pass: YES (>= k cuts) => beta = mid, else alpha = mid.
@@ -667,7 +673,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     int batches = 0;
     while (true) {
         for (int b = 0; b < PASS_BATCH; ++b) {
-            hipLaunchKernelGGL(k_make_cands, dim3(1), dim3(64), 0, s, P.st, P.Nvals);
+            hipLaunchKernelGGL(k_make_cands, dim3(1), dim3(M), 0, s, P.st, P.Nvals);
             LAUNCH_CHECK();
             launch_levels<M, false>(A, ls, maxdepth, s);
             hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, s, P.st, P.Nvals, P.cnt, root_slot);
