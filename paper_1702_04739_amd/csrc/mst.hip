@@ -704,16 +704,79 @@ __global__ __launch_bounds__(1024) void k_sum_lengths(const double *__restrict__
     if (threadIdx.x == 0) *out = s[0];
 }
 
+// ------------------------------------------------------------------ tile order
+
+// Identity tile order (positions = point ids), padding included.
+__global__ void k_perm_identity(int32_t *__restrict__ perm, int64_t n_pad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += (int64_t)gridDim.x * blockDim.x)
+        perm[i] = (int32_t)i;
+}
+
+// Sort keys for the tile order: (component, id), stable sort by component.
+__global__ void k_perm_keys(const int32_t *__restrict__ comp, int64_t n, uint32_t *__restrict__ keys,
+                            int32_t *__restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = (uint32_t)comp[i];
+    vals[i] = (int32_t)i;
+}
+
+// Component range of every tile of the order (points sorted by component, so
+// the first and last valid point bound it).
+__global__ void k_tile_ranges(const int32_t *__restrict__ perm, const int32_t *__restrict__ comp, int64_t n,
+                              int64_t nt, int64_t tile, int32_t *__restrict__ tlo, int32_t *__restrict__ thi) {
+    const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= nt) return;
+    const int64_t first = T * tile;
+    const int64_t last = std::min<int64_t>(first + tile, n) - 1;
+    tlo[T] = first < n ? comp[perm[first]] : -1;
+    thi[T] = first < n ? comp[perm[last]] : -2;
+}
+
+// A tile pair is skipped when all of its points lie in one component (no pair
+// of it can be an outgoing edge).
+__global__ void k_pair_keep(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ tlo,
+                            const int32_t *__restrict__ thi, int32_t *__restrict__ keep) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npairs) return;
+    const int2 pr = pairs[k];
+    const bool one = tlo[pr.x] == thi[pr.x] && tlo[pr.y] == thi[pr.y] && tlo[pr.x] == tlo[pr.y];
+    keep[k] = one ? 0 : 1;
+}
+
+// Rows of the representation in the tile order: one wave per position.
+__global__ __launch_bounds__(256) void k_permute_rows(const uint4 *__restrict__ Xr, const int32_t *__restrict__ perm,
+                                                      int64_t n_pad, int64_t row_u4, uint4 *__restrict__ Xq) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < n_pad; q += nwaves) {
+        const uint4 *src = Xr + (int64_t)perm[q] * row_u4;
+        uint4 *dst = Xq + q * row_u4;
+        for (int64_t t = lane; t < row_u4; t += 64) dst[t] = src[t];
+    }
+}
+
+__global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ keep,
+                               const int32_t *__restrict__ pos, int2 *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npairs || !keep[k]) return;
+    out[pos[k]] = pairs[k];
+}
+
 // ------------------------------------------------------------------ plan
 
 struct MstPlan {
     int64_t n, d, ld, n_pad, d_pad, nrb;
     int32_t precision;
     void *Xr;                       // screen representation (FP32, BF16 or FP8), [n_pad][d_pad]
+    void *Xq;                       // the same rows in the tile order of the round
     float *mu, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
     int32_t *pgrid, *grid_min;
-    int2 *pairs;
-    int64_t npairs;
+    int2 *pairs, *pairs_r;          // all tile pairs (diagonal first); the pairs kept this round
+    int64_t npairs, nt;
+    int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos;
+    uint32_t *pkeys, *ptk, *ptv;
+    void *psort;
     double *psum;
     uint32_t *rmax, *emax, *comp_ub;
     int32_t *comp, *ccnt, *cj, *glist, *gcnt, *gcj, *rlist, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev;
@@ -725,6 +788,7 @@ struct MstPlan {
     void carve(Arena &a) {
         const size_t esz = precision == ISO_PREC_BF16 ? 2 : precision == ISO_PREC_FP8 ? 1 : 4;
         Xr = a.take<char>((size_t)n_pad * d_pad * esz);
+        Xq = a.take<char>((size_t)n_pad * d_pad * esz);
         mu = a.take<float>(d_pad);
         psum = a.take<double>((size_t)nrb * d);
         pgrid = a.take<int32_t>((size_t)nrb * d);
@@ -767,6 +831,17 @@ struct MstPlan {
         ck2 = a.take<unsigned long long>(n);
         counters = a.take<int32_t>(C_COUNT);
         pairs = a.take<int2>(npairs);
+        pairs_r = a.take<int2>(npairs);
+        perm = a.take<int32_t>(n_pad);
+        pvals = a.take<int32_t>(n);
+        pkeys = a.take<uint32_t>(n);
+        ptk = a.take<uint32_t>(n);
+        ptv = a.take<uint32_t>(n);
+        psort = a.take<char>(radix_sort_scratch_bytes(n));
+        tlo = a.take<int32_t>(nt);
+        thi = a.take<int32_t>(nt);
+        keep = a.take<int32_t>(npairs);
+        kpos = a.take<int32_t>(npairs + 1);
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
     // they are sized for all rows (rows are gathered at most once per round).
@@ -783,8 +858,8 @@ MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
     const int64_t kc = 64 / (precision == ISO_PREC_BF16 ? 2 : precision == ISO_PREC_FP8 ? 1 : 4);  // 64-byte K chunks
     p.d_pad = (d + kc - 1) / kc * kc;
     p.nrb = (n + COL_RB - 1) / COL_RB;
-    const int64_t nt = p.n_pad / pair_tile();
-    p.npairs = nt * (nt + 1) / 2;
+    p.nt = p.n_pad / pair_tile();
+    p.npairs = p.nt * (p.nt + 1) / 2;
     return p;
 }
 
@@ -892,6 +967,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         HIP_CHECK(hipMemcpyAsync(P.pairs, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice, s));
         HIP_CHECK(hipStreamSynchronize(s));
     }
+    hipLaunchKernelGGL(k_perm_identity, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad);
+    LAUNCH_CHECK();
+    SA.perm = P.perm;
+    SA.Xtile = P.Xr;
 
     int64_t ncomp = n;
     int rounds = 0;
@@ -905,12 +984,52 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(1024), 0, s, P.flag, ncomp, P.counters);
             LAUNCH_CHECK();
         }
+        // Tile order and tile pairs of this round: once components average at
+        // least a tile, the points are ordered by component and tile pairs
+        // lying inside one component are dropped (until then every tile pair
+        // holds points of several components, and the order stays the identity).
+        const int2 *pairs_use = P.pairs;
+        int64_t ndiag = P.nt, noff = P.npairs - P.nt;
+        if (rounds > 1 && ncomp * pair_tile() <= n) {
+            int kb = 1;
+            while ((int64_t(1) << kb) < ncomp) ++kb;
+            hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.pkeys, P.perm);
+            LAUNCH_CHECK();
+            radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, kb, P.psort, s);
+            {
+                const size_t esz = rep == ISO_PREC_BF16 ? 2 : rep == ISO_PREC_FP8 ? 1 : 4;
+                const int64_t row_u4 = (int64_t)(P.d_pad * esz / 16);
+                const unsigned g = std::min<unsigned>(grid_for(P.n_pad, 4), 8u * (unsigned)device_cus());
+                hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr), P.perm,
+                                   P.n_pad, row_u4, static_cast<uint4 *>(P.Xq));
+                LAUNCH_CHECK();
+                SA.Xtile = P.Xq;
+            }
+            hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(P.nt, 256)), dim3(256), 0, s, P.perm, P.comp, n, P.nt,
+                               pair_tile(), P.tlo, P.thi);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.tlo,
+                               P.thi, P.keep);
+            LAUNCH_CHECK();
+            exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, s);
+            hipLaunchKernelGGL(k_pair_scatter, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs,
+                               P.keep, P.kpos, P.pairs_r);
+            LAUNCH_CHECK();
+            int32_t hk[2] = {0, 0};
+            HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.nt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(&hk[1], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            ISO_REQUIRE(hk[0] >= 0 && hk[0] <= hk[1] && hk[1] <= P.npairs, ISO_ERR_INTERNAL, "tile-pair compaction");
+            pairs_use = P.pairs_r;
+            ndiag = hk[0];
+            noff = hk[1] - hk[0];
+        }
         fill<uint32_t>(reinterpret_cast<uint32_t *>(P.best), 0x7F800000u, n, s);  // +inf
         fill<int32_t>(P.ccnt, 0, n, s);
         SA.rows = nullptr;
         SA.nrows = 0;
         scr.start(s);
-        launch_screen_pairs(SA, P.pairs, P.npairs, s);
+        launch_screen_pairs(SA, pairs_use, ndiag, noff, s);
         scr.stop(s);
         fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
         hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,

@@ -58,6 +58,9 @@ struct ScreenArgs {
     const float *re;         // [n_pad] e_i
     const float *Emax;       // [n]
     const int32_t *comp;     // [n_pad] component of each point, -1 on padding
+    const int32_t *perm;     // tile-pair screen: [n_pad] point at each position of the tile order
+                             // (points sorted by component, padding last)
+    const void *Xtile;       // tile-pair screen: the representation with its rows in the tile order
     ScreenBound bound;       // error bound constants
     float kappa;             // capture threshold scale (recheck order slack and rounding)
     // gathered pass (rows == nullptr for the full sweep)
@@ -267,9 +270,11 @@ __device__ __forceinline__ void screen_finish(ScreenLDS &S, const ScreenArgs &A,
 void launch_screen_rows(const ScreenArgs &A, bool gather, hipStream_t s);
 
 // Symmetric tile-pair screen (screen_pairs.hip): best[] must hold +inf and
-// ccnt[] zero on entry; both are updated with atomics.
+// ccnt[] zero on entry; both are updated with atomics, indexed by point id.
 int64_t pair_tile();
 std::vector<int2> make_pair_order(int64_t ntiles);
-void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, hipStream_t s);
+// pairs: ndiag diagonal tile pairs, then noff others (positions in the tile
+// order A.perm).
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t noff, hipStream_t s);
 
 }  // namespace iso

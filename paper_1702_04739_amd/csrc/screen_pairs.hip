@@ -24,8 +24,11 @@
 // 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32): BF16
 // 32x32x16, FP8 E4M3 32x32x64 (unit block scales) or FP32 32x32x2.
 //
-// Work items (tile pair, half) are enumerated with the diagonal pairs in a
-// launch of their own and the others in blocks of PAIR_SB x PAIR_SB tiles;
+// Tiles are runs of 256 positions of a tile order (A.perm maps positions to
+// points); once components are large the order groups points by component
+// and the caller drops tile pairs inside one component.  Work items (tile
+// pair, half) are enumerated with the diagonal pairs in a launch of their own
+// and the others in blocks of PAIR_SB x PAIR_SB tiles;
 // each XCD receives a contiguous run of that order (workgroup ids are dealt
 // to the eight XCDs in turn), so the workgroups resident on one XCD share
 // their I and J tiles in its L2.
@@ -94,6 +97,7 @@ struct PairLDS {
     int32_t ccomp[PH];     // component of the columns
     int32_t rhot[PT];      // row's tile minimum is within its capture margin
     uint32_t chot[PH / 32];
+    int32_t rid[PT], cid[PH];  // point ids of the rows and columns
 };
 
 constexpr uint32_t INF_BITS = 0x7F800000u;  // +inf; every screen value is a nonnegative float or +inf
@@ -133,9 +137,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wi = w >> 1, wj = w & 1;
-    const T *X = REP == ISO_PREC_BF16  ? reinterpret_cast<const T *>(A.XB)
-                 : REP == ISO_PREC_FP8 ? reinterpret_cast<const T *>(A.XF8)
-                                       : reinterpret_cast<const T *>(A.XT);
+    const T *X = reinterpret_cast<const T *>(A.Xtile);  // rows in the tile order
     const int64_t d_pad = A.d_pad;
 
     // XCD-aware placement: workgroup b runs on XCD b mod 8, and each XCD takes
@@ -145,15 +147,19 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     if (idx >= nitems) return;
     const int2 pr = pairs[idx >> 1];
     const int half = (int)(idx & 1);
+    // positions in the tile order; A.perm maps them to point ids
     const int64_t I0 = (int64_t)pr.x * PT, J0 = (int64_t)pr.y * PT + half * PH;
+    const int32_t *__restrict__ perm = A.perm;
 
     // tile constants
     {
-        const int64_t i = I0 + tid;
+        const int64_t i = perm[I0 + tid];
+        S.rid[tid] = (int32_t)i;
         S.rmin[tid] = INF_BITS;
         S.rE[tid] = i < A.n ? A.Emax[i] : 0.0f;
         if (tid < PH) {
-            const int64_t j = J0 + tid;
+            const int64_t j = perm[J0 + tid];
+            S.cid[tid] = (int32_t)j;
             S.cmin[tid] = INF_BITS;
             S.cE[tid] = j < A.n ? A.Emax[j] : 0.0f;
             S.csq[tid] = A.sq[j];
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     int ci[NIB];
 #pragma unroll
     for (int ib = 0; ib < NIB; ++ib) {
-        const int64_t i = I0 + RW * wi + 32 * ib + (lane & 31);
+        const int64_t i = perm[I0 + RW * wi + 32 * ib + (lane & 31)];
         si[ib] = A.sq[i];
         ci[ib] = A.comp[i];
     }
@@ -349,7 +355,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         if (u >= PT + PH) break;
         const bool is_row = u < PT;
         const int t = is_row ? u : u - PT;
-        const int64_t p = is_row ? I0 + t : J0 + t;
+        const int64_t p = is_row ? S.rid[t] : S.cid[t];
         const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
         const uint32_t old = p < A.n ? reinterpret_cast<const volatile uint32_t *>(A.best)[p] : INF_BITS;
         if (p < A.n && m < old) atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m);
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     for (int ib = 0; ib < NIB; ++ib) {
         const int il = RW * wi + 32 * ib + (lane & 31);
         if (!S.rhot[il]) continue;
-        const int64_t i = I0 + il;
+        const int64_t i = S.rid[il];
         const float Ei = S.rE[il];
         const float rb_ = __uint_as_float(S.rmin[il]);
         const float r_cheap = (rb_ + 2.0f * Ei) * A.kappa;
@@ -386,11 +392,12 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                 const float v = acc[ib][jb][q];
                 if (!(v <= r_cheap)) continue;
                 const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const float L = lower_of(v, pair_bound(A.bound, ri, A.rn[J0 + jl], ei, A.re[J0 + jl]));
+                const int64_t j = S.cid[jl];
+                const float L = lower_of(v, pair_bound(A.bound, ri, A.rn[j], ei, A.re[j]));
                 if (!(L <= r_thr)) continue;
                 const int pos = atomicAdd(&A.ccnt[i], 1);
                 if (pos < SCR_CAP) {
-                    A.cj[i * SCR_CAP + pos] = (int32_t)(J0 + jl);
+                    A.cj[i * SCR_CAP + pos] = (int32_t)j;
                     A.cl[i * SCR_CAP + pos] = L;
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -406,7 +413,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);  // column within the 32-block
             if (!((hw >> jc) & 1u)) continue;
             const int jl = CW * wj + 32 * jb + jc;
-            const int64_t j = J0 + jl;
+            const int64_t j = S.cid[jl];
             const float Ej = S.cE[jl];
             const float cb = __uint_as_float(S.cmin[jl]);
             const float c_cheap = (cb + 2.0f * Ej) * A.kappa;
@@ -417,11 +424,12 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                 const float v = acc[ib][jb][q];
                 if (!(v <= c_cheap)) continue;
                 const int il = RW * wi + 32 * ib + (lane & 31);
-                const float L = lower_of(v, pair_bound(A.bound, A.rn[I0 + il], rj, A.re[I0 + il], ej));
+                const int64_t i = S.rid[il];
+                const float L = lower_of(v, pair_bound(A.bound, A.rn[i], rj, A.re[i], ej));
                 if (!(L <= c_thr)) continue;
                 const int pos = atomicAdd(&A.ccnt[j], 1);
                 if (pos < SCR_CAP) {
-                    A.cj[j * SCR_CAP + pos] = (int32_t)(I0 + il);
+                    A.cj[j * SCR_CAP + pos] = (int32_t)i;
                     A.cl[j * SCR_CAP + pos] = L;
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -453,35 +461,34 @@ std::vector<int2> make_pair_order(int64_t nt) {
 namespace {
 
 template <int REP>
-void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, hipStream_t s) {
-    const int64_t nt = A.n_pad / PT;
-    ISO_REQUIRE(npairs == nt * (nt + 1) / 2, ISO_ERR_INTERNAL, "tile-pair list does not match the padded size");
+void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t noff, hipStream_t s) {
     ISO_REQUIRE(A.d_pad % PPrec<REP>::KC == 0, ISO_ERR_INTERNAL, "padded dimension is not a whole number of chunks");
+    ISO_REQUIRE(A.perm != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without a tile order");
     const dim3 block(64 * NW);
     auto grid = [](int64_t per_xcd) { return dim3((unsigned)(8 * per_xcd)); };
     // diagonal tile pairs (only i < j counted), two halves each ...
-    int64_t items = 2 * nt;
-    int64_t per_xcd = (items + 7) / 8;
-    hipLaunchKernelGGL((k_screen_pairs<REP, true>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
-    LAUNCH_CHECK();
+    if (ndiag > 0) {
+        const int64_t items = 2 * ndiag, per_xcd = (items + 7) / 8;
+        hipLaunchKernelGGL((k_screen_pairs<REP, true>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
+        LAUNCH_CHECK();
+    }
     // ... then the others
-    items = 2 * (npairs - nt);
-    if (items > 0) {
-        per_xcd = (items + 7) / 8;
-        hipLaunchKernelGGL((k_screen_pairs<REP, false>), grid(per_xcd), block, 0, s, A, pairs + nt, per_xcd, items);
+    if (noff > 0) {
+        const int64_t items = 2 * noff, per_xcd = (items + 7) / 8;
+        hipLaunchKernelGGL((k_screen_pairs<REP, false>), grid(per_xcd), block, 0, s, A, pairs + ndiag, per_xcd, items);
         LAUNCH_CHECK();
     }
 }
 
 }  // namespace
 
-void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t npairs, hipStream_t s) {
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t noff, hipStream_t s) {
     if (A.rep == ISO_PREC_BF16)
-        launch_pairs<ISO_PREC_BF16>(A, pairs, npairs, s);
+        launch_pairs<ISO_PREC_BF16>(A, pairs, ndiag, noff, s);
     else if (A.rep == ISO_PREC_FP8)
-        launch_pairs<ISO_PREC_FP8>(A, pairs, npairs, s);
+        launch_pairs<ISO_PREC_FP8>(A, pairs, ndiag, noff, s);
     else
-        launch_pairs<ISO_PREC_FP32>(A, pairs, npairs, s);
+        launch_pairs<ISO_PREC_FP32>(A, pairs, ndiag, noff, s);
 }
 
 }  // namespace iso
