@@ -72,6 +72,9 @@ typedef int32_t iso_status;
 
 /* Vertex weight omega (eq. 2.2) and flow phi (eq. 2.1) readings. */
 #define ISO_OMEGA_TREE 0   /* omega(v) = sum of phi over v's tree edges         */
+#define ISO_OMEGA_FULL 1   /* omega(v) = sum over all j != v of phi(v, j), as
+                              computed by iso_graph_weights and passed in
+                              iso_sub_opts.omega0                               */
 #define ISO_PHI_EXP_DIST 0 /* phi = exp(-D / sigma), as printed in eq. 2.1      */
 #define ISO_PHI_GAUSS_SQ 1 /* phi = exp(-D^2 / (2 sigma^2))                      */
 /* Initial bracket of the bisection (Algorithm 2). */
@@ -106,10 +109,15 @@ iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t pre
                    int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes, void *stream);
 
 typedef struct {
-    int32_t omega;     /* ISO_OMEGA_*   (default TREE)      */
-    int32_t phi;       /* ISO_PHI_*     (default EXP_DIST)  */
-    int32_t bracket;   /* ISO_BRACKET_* (default POW2)      */
-    int32_t max_iters; /* bisection step cap, <= 0 => 2000  */
+    int32_t omega;         /* ISO_OMEGA_*   (default TREE)                          */
+    int32_t phi;           /* ISO_PHI_*     (default EXP_DIST)                      */
+    int32_t bracket;       /* ISO_BRACKET_* (default POW2)                          */
+    int32_t max_iters;     /* bisection step cap, <= 0 => 2000                      */
+    const double *omega0;  /* [n] device: vertex weights for ISO_OMEGA_FULL (from
+                              iso_graph_weights with the same sigma and phi);
+                              ignored for ISO_OMEGA_TREE                            */
+    const double *p0;      /* [n] device: potential p(v) of eq. 2.3 (from
+                              iso_graph_weights with alpha > 0); NULL => p = 0      */
 } iso_sub_opts;
 
 typedef struct {
@@ -150,6 +158,24 @@ iso_status iso_subpartition(const int32_t *parent, const double *length, int64_t
                             double sigma, const iso_sub_opts *opts, int32_t *labels, double *i_k /* host */,
                             double *cluster_num, double *cluster_den, int32_t *cluster_size, iso_sub_info *info,
                             void *ws, size_t ws_bytes, void *stream);
+
+/* Full-graph weights of eqs. 2.2 and 2.3 for the n points X, with distances
+ * D(v, j) = sqrt of the FP64 left-to-right sum of squared coordinate
+ * differences (each point pair formed on the fly, never stored):
+ *   omega0[v] = sum over j != v, ascending j, of phi(D(v, j))   (phi_kind ISO_PHI_*),
+ *   p0[v]     = alpha * sum over j != v, ascending j, of D(v, j) (exactly 0 when alpha == 0).
+ * O(n^2 d) FP64 work.  Either output may be NULL.  X [n*ld] FP32; sigma > 0.
+ * Errors: null X, n < 2, d < 1, ld < d, sigma <= 0 or not finite, alpha < 0 or
+ * not finite, unknown phi_kind (INVALID_ARG). */
+iso_status iso_graph_weights(const float *X, int64_t n, int64_t d, int64_t ld, double sigma, int32_t phi_kind,
+                             double alpha, double *omega0, double *p0, void *stream);
+
+/* sigma of eq. 2.1 as "the median MST edge": the lower median of length[v]
+ * over the n-1 vertices with parent[v] >= 0, written to *sigma (host); the
+ * value iso_subpartition uses when it is passed sigma = 0.
+ * Errors: null pointers, n < 2 (INVALID_ARG). */
+iso_status iso_sigma_median(const int32_t *parent, const double *length, int64_t n, double *sigma /* host */,
+                            void *stream);
 
 /* Device bytes iso_backward needs as workspace. */
 iso_status iso_backward_workspace_size(int64_t n, size_t *bytes /* host */);

@@ -71,13 +71,53 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32"):
                             "rescanned_rows": info.rescanned_rows, "mst_weight": info.mst_weight}
 
 
+def graph_weights(points, sigma: float, phi: str = "exp", alpha: float = 0.0, omega: bool = True, potential=None):
+    """Full-graph vertex weights (eq. 2.2) and potential (eq. 2.3) of the
+    points: (omega0 float64[n] or None, p0 float64[n] or None).  ``potential``
+    None computes p0 only when alpha > 0."""
+    torch = _torch()
+    _require_cuda(points, "points", torch.float32)
+    if points.dim() != 2:
+        raise ValueError("points must be n x d")
+    if points.stride(1) != 1:
+        points = points.contiguous()
+    n, d = points.shape
+    want_p = (alpha > 0.0) if potential is None else bool(potential)
+    om = torch.empty(n, dtype=torch.float64, device=points.device) if omega else None
+    p0 = torch.empty(n, dtype=torch.float64, device=points.device) if want_p else None
+    rc = _lib.load().iso_graph_weights(ctypes.c_void_p(points.data_ptr()), n, d, points.stride(0), float(sigma),
+                                       _lib.PHI[phi], float(alpha),
+                                       ctypes.c_void_p(om.data_ptr() if om is not None else 0),
+                                       ctypes.c_void_p(p0.data_ptr() if p0 is not None else 0),
+                                       _stream_ptr(points.device))
+    _lib.check(rc, "iso_graph_weights")
+    return om, p0
+
+
+def sigma_median(parent, length) -> float:
+    """The lower median of the tree's n-1 edge lengths (sigma of eq. 2.1)."""
+    torch = _torch()
+    _require_cuda(parent, "parent", torch.int32)
+    _require_cuda(length, "length", torch.float64)
+    out = ctypes.c_double(0.0)
+    rc = _lib.load().iso_sigma_median(ctypes.c_void_p(parent.contiguous().data_ptr()),
+                                      ctypes.c_void_p(length.contiguous().data_ptr()), parent.shape[0],
+                                      ctypes.byref(out), _stream_ptr(parent.device))
+    _lib.check(rc, "iso_sigma_median")
+    return float(out.value)
+
+
 def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = None, root: int = 0, phi: str = "exp",
-                               bracket: str = "pow2", max_iters: int = 2000, return_clusters: bool = False):
+                               bracket: str = "pow2", max_iters: int = 2000, return_clusters: bool = False,
+                               omega0=None, p0=None):
     """Optimal k-subpartition of the weighted tree and MISO_k (eqs. 2.4, 2.6).
 
-    ``sigma`` None (or 0) selects the lower median edge length.  Returns
-    (labels int32[n] with -1 for residual vertices, i_k, info dict); with
-    ``return_clusters`` the info also holds per-cluster num, den and size."""
+    ``sigma`` None (or 0) selects the lower median edge length.  ``omega0``
+    (float64[n], from graph_weights with the same sigma and phi) selects the
+    full-graph omega of eq. 2.2 instead of the tree degree; ``p0`` adds the
+    potential of eq. 2.3.  Returns (labels int32[n] with -1 for residual
+    vertices, i_k, info dict); with ``return_clusters`` the info also holds
+    per-cluster num, den and size."""
     torch = _torch()
     _require_cuda(parent, "parent", torch.int32)
     _require_cuda(length, "length", torch.float64)
@@ -95,7 +135,14 @@ def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = Non
     cnum = torch.empty(k, dtype=torch.float64, device=dev)
     cden = torch.empty(k, dtype=torch.float64, device=dev)
     csize = torch.empty(k, dtype=torch.int32, device=dev)
-    opts = _lib.SubOpts(_lib.OMEGA["tree"], _lib.PHI[phi], _lib.BRACKET[bracket], int(max_iters))
+    for name, arr in (("omega0", omega0), ("p0", p0)):
+        if arr is not None:
+            _require_cuda(arr, name, torch.float64)
+            if arr.shape[0] != n or not arr.is_contiguous():
+                raise ValueError("%s must be a contiguous float64[n]" % name)
+    opts = _lib.SubOpts(_lib.OMEGA["full" if omega0 is not None else "tree"], _lib.PHI[phi], _lib.BRACKET[bracket],
+                        int(max_iters), omega0.data_ptr() if omega0 is not None else None,
+                        p0.data_ptr() if p0 is not None else None)
     info = _lib.SubInfo()
     ik = ctypes.c_double(0.0)
     rc = lib.iso_subpartition(ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), n, int(root),
@@ -110,10 +157,20 @@ def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = Non
     return labels, float(ik.value), out
 
 
-def cluster(points, k: int, sigma: float | None = None, precision: str = "fp32", recheck: str = "fp32", **kw):
-    """MST followed by the optimal k-subpartition (the paper's full hot path)."""
+def cluster(points, k: int, sigma: float | None = None, precision: str = "fp32", recheck: str = "fp32",
+            omega: str = "tree", alpha: float = 0.0, **kw):
+    """MST followed by the optimal k-subpartition (the paper's full hot path).
+    ``omega="full"`` and/or ``alpha > 0`` use the full-graph weights of
+    eqs. 2.2 and 2.3 (O(n^2 d) extra work)."""
     parent, length, minfo = mst(points, precision=precision, recheck=recheck)
-    labels, ik, sinfo = isoperimetric_subpartition(parent, length, k, sigma=sigma, **kw)
+    om0 = p0 = None
+    if omega == "full" or alpha > 0.0:
+        if not sigma:
+            sigma = sigma_median(parent, length)
+        om0, p0 = graph_weights(points, sigma, phi=kw.get("phi", "exp"), alpha=alpha, omega=(omega == "full"))
+    elif omega != "tree":
+        raise ValueError("omega must be 'tree' or 'full'")
+    labels, ik, sinfo = isoperimetric_subpartition(parent, length, k, sigma=sigma, omega0=om0, p0=p0, **kw)
     return labels, ik, {"mst": minfo, "sub": sinfo, "parent": parent, "length": length}
 
 

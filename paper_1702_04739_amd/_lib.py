@@ -19,14 +19,14 @@ ERRORS = {
 }
 PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
 RECHECK = {"fp32": 0, "fp64": 1}
-OMEGA = {"tree": 0}
+OMEGA = {"tree": 0, "full": 1}
 PHI = {"exp": 0, "gauss_sq": 1}
 BRACKET = {"pow2": 0, "paper": 1}
 
 # Every symbol include/isoclust.h declares.
 EXPORTS = ["iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
-           "iso_backward_workspace_size", "iso_backward", "iso_timing_enable", "iso_timing_read", "iso_last_error",
-           "iso_version"]
+           "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median", "iso_timing_enable",
+           "iso_timing_read", "iso_last_error", "iso_version"]
 
 
 class IsoError(RuntimeError):
@@ -42,7 +42,7 @@ class MstInfo(ctypes.Structure):
 
 class SubOpts(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_int32), ("phi", ctypes.c_int32), ("bracket", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("omega0", ctypes.c_void_p), ("p0", ctypes.c_void_p)]
 
 
 class SubInfo(ctypes.Structure):
@@ -83,8 +83,10 @@ def load(build_if_missing: bool = True):
     lib.iso_backward_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
     lib.iso_backward.argtypes = [P, I64, I64, I64, P, P, I32, D, I32, D, D, P, I64, ctypes.POINTER(D),
                                  ctypes.POINTER(D), P, SZ, P]
+    lib.iso_graph_weights.argtypes = [P, I64, I64, I64, D, I32, D, P, P, P]
+    lib.iso_sigma_median.argtypes = [P, P, I64, ctypes.POINTER(D), P]
     for f in ("iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
-              "iso_backward_workspace_size", "iso_backward"):
+              "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median"):
         getattr(lib, f).restype = ctypes.c_int32
     lib.iso_timing_enable.argtypes = [I32]
     lib.iso_timing_enable.restype = ctypes.c_int32

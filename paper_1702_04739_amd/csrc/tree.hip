@@ -636,9 +636,16 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     }
     hipLaunchKernelGGL(k_phi, dim3(gn), dim3(256), 0, s, parent, length, n, P.st, o.phi, P.phi, P.p0);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_omega_tree, dim3(gn), dim3(256), 0, s, parent, P.phi, kids, P.koff, n, P.om0);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, parent, P.phi, P.om0, P.p0, n, o.bracket, P.st);
+    // vertex weights: the tree degree, or the caller's full-graph weights;
+    // potential p: zero, or the caller's (eq. 2.3)
+    const double *om0 = P.om0, *p0 = o.p0 ? o.p0 : P.p0;
+    if (o.omega == ISO_OMEGA_FULL) {
+        om0 = o.omega0;
+    } else {
+        hipLaunchKernelGGL(k_omega_tree, dim3(gn), dim3(256), 0, s, parent, P.phi, kids, P.koff, n, P.om0);
+        LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, parent, P.phi, om0, p0, n, o.bracket, P.st);
     LAUNCH_CHECK();
     std::vector<int32_t> ls(maxdepth + 2);
     HIP_CHECK(hipMemcpyAsync(ls.data(), P.level_start, sizeof(int32_t) * (maxdepth + 2), hipMemcpyDeviceToHost, s));
@@ -656,8 +663,8 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     A.koff = P.koff;
     A.slot = P.slot;
     A.phi = P.phi;
-    A.om0 = P.om0;
-    A.p0 = P.p0;
+    A.om0 = om0;
+    A.p0 = p0;
     A.Nvals = P.Nvals;
     A.cw = P.cw;
     A.cp = P.cp;
@@ -768,9 +775,12 @@ extern "C" iso_status iso_subpartition(const int32_t *parent, const double *leng
         ISO_REQUIRE(root >= 0 && root < n, ISO_ERR_INVALID_ARG, "root = %d outside [0, n)", root);
         ISO_REQUIRE(sigma >= 0.0 && std::isfinite(sigma), ISO_ERR_INVALID_ARG, "sigma = %g must be finite and >= 0",
                     sigma);
-        iso_sub_opts o{ISO_OMEGA_TREE, ISO_PHI_EXP_DIST, ISO_BRACKET_POW2, 2000};
+        iso_sub_opts o{ISO_OMEGA_TREE, ISO_PHI_EXP_DIST, ISO_BRACKET_POW2, 2000, nullptr, nullptr};
         if (opts) o = *opts;
-        ISO_REQUIRE(o.omega == ISO_OMEGA_TREE, ISO_ERR_INVALID_ARG, "unsupported omega reading %d", o.omega);
+        ISO_REQUIRE(o.omega == ISO_OMEGA_TREE || o.omega == ISO_OMEGA_FULL, ISO_ERR_INVALID_ARG,
+                    "unsupported omega reading %d", o.omega);
+        ISO_REQUIRE(o.omega != ISO_OMEGA_FULL || o.omega0 != nullptr, ISO_ERR_INVALID_ARG,
+                    "ISO_OMEGA_FULL needs the vertex weights in opts->omega0");
         ISO_REQUIRE(o.phi == ISO_PHI_EXP_DIST || o.phi == ISO_PHI_GAUSS_SQ, ISO_ERR_INVALID_ARG, "unknown phi %d", o.phi);
         ISO_REQUIRE(o.bracket == ISO_BRACKET_POW2 || o.bracket == ISO_BRACKET_PAPER, ISO_ERR_INVALID_ARG,
                     "unknown bracket %d", o.bracket);
