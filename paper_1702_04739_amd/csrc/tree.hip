@@ -32,6 +32,9 @@ constexpr int M = 1 << SPEC_LEVELS;                // lanes per vertex in a spec
 constexpr int NCAND = M - 1;                       // midpoints per pass (the last lane re-checks beta)
 constexpr int NARROW = 16 * 64 / M > 1 ? 16 * 64 / M : 1;  // levels this narrow run inside one workgroup
 constexpr int PASS_BATCH = 4;
+#ifndef DP_BATCH
+#define DP_BATCH 16                          // children loaded per round trip in Algorithm 1 (measured best)
+#endif
 
 struct TreeState {
     double alpha, beta;
@@ -260,7 +263,7 @@ struct DPArgs {
     const int32_t *slot;  // output slot of each vertex: its position among all child lists, n-1 for the root
     const double *phi, *om0, *p0;
     const double *Nvals;
-    double *cw, *cp;
+    double2 *cpw;  // [slot][MM] contribution (p, omega) to the parent
     int32_t *cnt;
     uint8_t *cut, *joined;
     double *num, *den;
@@ -280,25 +283,24 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
     double p = A.p0[v];
     int32_t c_cnt = 0;
     // The children's contributions sit contiguously at slots koff[v] ..
-    // koff[v+1]-1 (ascending child id); sixteen are loaded at once, the sums
-    // still run one child after another.
+    // koff[v+1]-1 (ascending child id), (p, omega) packed in 16 bytes; DP_BATCH
+    // children are loaded at once, the sums still run one child after another.
     const int64_t a0 = A.koff[v], a1 = A.koff[v + 1];
-    for (int64_t a = a0; a < a1; a += 16) {
+    for (int64_t a = a0; a < a1; a += DP_BATCH) {
         const int64_t rem = a1 - a;
-        double pp[16], ww[16];
-        int32_t cc[16];
+        double2 pw[DP_BATCH];
+        int32_t cc[DP_BATCH];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < DP_BATCH; ++u) {
             const int64_t c = (u < rem ? a + u : a1 - 1) * MM + m;
-            pp[u] = A.cp[c];
-            ww[u] = A.cw[c];
+            pw[u] = A.cpw[c];
             cc[u] = A.cnt[c];
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < DP_BATCH; ++u) {
             if (u < rem) {
-                p = p + pp[u];
-                w = w + ww[u];
+                p = p + pw[u].x;
+                w = w + pw[u].y;
                 c_cnt += cc[u];
             }
         }
@@ -322,8 +324,7 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
         ow = 0.0;
     }
     const int64_t o = (int64_t)A.slot[v] * MM + m;
-    A.cp[o] = op;
-    A.cw[o] = ow;
+    A.cpw[o] = make_double2(op, ow);
     A.cnt[o] = c_cnt + iscut;
     if (REC) {
         A.cut[v] = (uint8_t)iscut;
@@ -493,7 +494,8 @@ struct SubPlan {
     int32_t *anc0, *anc1, *dist0, *dist1;
     uint32_t *okey, *oval, *ckey, *cval, *tk, *tv;
     int32_t *nchild, *koff, *slot, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp;
-    double *phi, *om0, *p0, *cw, *cp, *Nvals, *num, *den, *cl_num_tmp, *cl_den_tmp;
+    double2 *cpw;
+    double *phi, *om0, *p0, *Nvals, *num, *den, *cl_num_tmp, *cl_den_tmp;
     uint8_t *cut, *joined;
     TreeState *st;
     void *sort_scratch, *sel_scratch;
@@ -523,8 +525,7 @@ struct SubPlan {
         phi = a.take<double>(n);
         om0 = a.take<double>(n);
         p0 = a.take<double>(n);
-        cw = a.take<double>((size_t)n * M);
-        cp = a.take<double>((size_t)n * M);
+        cpw = a.take<double2>((size_t)n * M);
         Nvals = a.take<double>(M);
         num = a.take<double>(n);
         den = a.take<double>(n);
@@ -666,8 +667,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     A.om0 = om0;
     A.p0 = p0;
     A.Nvals = P.Nvals;
-    A.cw = P.cw;
-    A.cp = P.cp;
+    A.cpw = P.cpw;
     A.cnt = P.cnt;
     A.cut = P.cut;
     A.joined = P.joined;
