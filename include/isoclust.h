@@ -159,6 +159,19 @@ iso_status iso_subpartition(const int32_t *parent, const double *length, int64_t
                             double *cluster_num, double *cluster_den, int32_t *cluster_size, iso_sub_info *info,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* The optimal k-subpartition for every k = 2 .. kmax of one tree (the same
+ * bisection, final bracket and labels as kmax - 1 separate iso_subpartition
+ * calls, each k walking its own bisection; the passes evaluate the midpoints
+ * of several k together).
+ *   i_k     (host) [kmax - 1] out: MISO_k for k = 2 .. kmax.
+ *   labels  [(kmax - 1) * n] out (nullable): row k - 2 holds the labels for k.
+ *   passes  (host, nullable) out: tree passes used.
+ * Workspace: iso_sub_workspace_size(n, kmax).  Errors as iso_subpartition,
+ * with kmax in place of k. */
+iso_status iso_subpartition_all_k(const int32_t *parent, const double *length, int64_t n, int32_t root, int32_t kmax,
+                                  double sigma, const iso_sub_opts *opts, double *i_k /* host */, int32_t *labels,
+                                  int32_t *passes /* host */, void *ws, size_t ws_bytes, void *stream);
+
 /* Full-graph weights of eqs. 2.2 and 2.3 for the n points X, with distances
  * D(v, j) = sqrt of the FP64 left-to-right sum of squared coordinate
  * differences (each point pair formed on the fly, never stored):

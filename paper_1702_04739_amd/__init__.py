@@ -157,6 +157,37 @@ def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = Non
     return labels, float(ik.value), out
 
 
+def subpartition_all_k(parent, length, kmax: int, sigma: float | None = None, root: int = 0, phi: str = "exp",
+                       bracket: str = "pow2", max_iters: int = 2000, omega0=None, p0=None, labels: bool = True):
+    """The optimal k-subpartition for every k = 2 .. kmax of one tree: (i_k
+    float64 numpy array indexed by k - 2, labels int32[kmax - 1, n] or None,
+    passes).  Equal, k by k, to isoperimetric_subpartition."""
+    torch = _torch()
+    _require_cuda(parent, "parent", torch.int32)
+    _require_cuda(length, "length", torch.float64)
+    parent = parent.contiguous()
+    length = length.contiguous()
+    n = parent.shape[0]
+    lib = _lib.load()
+    need = ctypes.c_size_t(0)
+    _lib.check(lib.iso_sub_workspace_size(n, int(kmax), ctypes.byref(need)), "iso_sub_workspace_size")
+    dev = parent.device
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    lab = torch.empty((kmax - 1, n), dtype=torch.int32, device=dev) if labels else None
+    ik = (ctypes.c_double * max(kmax - 1, 1))()
+    passes = ctypes.c_int32(0)
+    opts = _lib.SubOpts(_lib.OMEGA["full" if omega0 is not None else "tree"], _lib.PHI[phi], _lib.BRACKET[bracket],
+                        int(max_iters), omega0.data_ptr() if omega0 is not None else None,
+                        p0.data_ptr() if p0 is not None else None)
+    rc = lib.iso_subpartition_all_k(ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), n,
+                                    int(root), int(kmax), float(sigma or 0.0), ctypes.byref(opts), ik,
+                                    ctypes.c_void_p(lab.data_ptr() if lab is not None else 0), ctypes.byref(passes),
+                                    ctypes.c_void_p(ws.data_ptr()), int(need.value), _stream_ptr(dev))
+    _lib.check(rc, "iso_subpartition_all_k")
+    import numpy as np
+    return np.array(ik[:kmax - 1], dtype=np.float64), lab, int(passes.value)
+
+
 def cluster(points, k: int, sigma: float | None = None, precision: str = "fp32", recheck: str = "fp32",
             omega: str = "tree", alpha: float = 0.0, **kw):
     """MST followed by the optimal k-subpartition (the paper's full hot path).

@@ -493,7 +493,7 @@ struct SubPlan {
     int32_t k;
     int32_t *anc0, *anc1, *dist0, *dist1;
     uint32_t *okey, *oval, *ckey, *cval, *tk, *tv;
-    int32_t *nchild, *koff, *slot, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp;
+    int32_t *nchild, *koff, *slot, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp, *lab_tmp;
     double2 *cpw;
     double *phi, *om0, *p0, *Nvals, *num, *den, *cl_num_tmp, *cl_den_tmp;
     uint8_t *cut, *joined;
@@ -522,6 +522,7 @@ struct SubPlan {
         rep1 = a.take<int32_t>(n);
         cnt = a.take<int32_t>((size_t)n * M);
         cl_size_tmp = a.take<int32_t>(k);
+        lab_tmp = a.take<int32_t>(n);
         phi = a.take<double>(n);
         om0 = a.take<double>(n);
         p0 = a.take<double>(n);
@@ -577,9 +578,16 @@ void launch_levels(const DPArgs &A, const std::vector<int32_t> &ls, int32_t maxd
     }
 }
 
+// Single k (kmax == 0): the bisection runs on the device, several passes per
+// host check.  All k (kmax >= 2): for every k = 2 .. kmax the same bisection as
+// a single-k call, planned on the host: each pass gives every unfinished k the
+// next levels of its bisection tree (equal midpoints of different k share a
+// lane), and each k then walks its own answers; i_k_all[k - 2] and the label
+// rows labels_all[(k - 2) n ..] receive the results.
 void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t root, double sigma,
              const iso_sub_opts &o, int32_t *labels, double *i_k, double *cl_num, double *cl_den, int32_t *cl_size,
-             iso_sub_info *info, hipStream_t s) {
+             iso_sub_info *info, hipStream_t s, int32_t kmax = 0, double *i_k_all = nullptr,
+             int32_t *labels_all = nullptr, int32_t *passes_out = nullptr) {
     const int64_t n = P.n;
     const int32_t k = P.k;
     const unsigned gn = grid_for(n, 256);
@@ -675,7 +683,146 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     A.den = P.den;
     A.st = P.st;
 
-    // speculative bisection passes
+    // final decision at N = the device state's beta, recording Cut and eta
+    // (Algorithm 4), for cluster count kk; returns the device state after it
+    auto finalize = [&](int32_t kk, int32_t *lab, double *cn, double *cd, int32_t *cs) {
+        hipLaunchKernelGGL(k_set_final_N, dim3(1), dim3(64), 0, s, P.st, P.Nvals);
+        LAUNCH_CHECK();
+        launch_levels<1, true>(A, ls, maxdepth, s);
+        hipLaunchKernelGGL(k_cut_in_xorder, dim3(gn), dim3(256), 0, s, order, P.cut, n, P.cf);
+        LAUNCH_CHECK();
+        exclusive_scan_i32(P.cf, P.rank, n, nullptr, s);
+        hipLaunchKernelGGL(k_cluster_index, dim3(gn), dim3(256), 0, s, order, P.cut, P.rank, P.joined, parent, n, kk,
+                           P.cidx, P.rep0);
+        LAUNCH_CHECK();
+        int32_t *ri = P.rep0, *ro = P.rep1;
+        for (int it = 0; it <= ceil_log2(maxdepth + 1); ++it) {
+            hipLaunchKernelGGL(k_rep_jump, dim3(gn), dim3(256), 0, s, ri, n, ro);
+            LAUNCH_CHECK();
+            std::swap(ri, ro);
+        }
+        fill_t<int32_t>(cs, 0, kk, s);
+        hipLaunchKernelGGL(k_labels, dim3(gn), dim3(256), 0, s, ri, P.cidx, P.num, P.den, n, lab, cn, cd, cs);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_final_cost, dim3(1), dim3(64), 0, s, cn, cd, kk, P.cnt, root_slot, P.st);
+        LAUNCH_CHECK();
+        TreeState hf{};
+        HIP_CHECK(hipMemcpyAsync(&hf, P.st, sizeof(hf), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        ISO_REQUIRE(hf.ncuts >= kk, ISO_ERR_INTERNAL, "decision at beta found %d < k = %d cuts", hf.ncuts, kk);
+        return hf;
+    };
+
+    if (kmax >= 2) {
+        // ---- all k: host-planned bisections, one per k
+        struct Br {
+            double a, b;
+            int32_t iters;
+            bool done;
+        };
+        std::vector<Br> br((size_t)kmax + 1);
+        auto stop = [&](const Br &x) {
+            const double mid = (x.a + x.b) / 2.0;
+            return mid <= x.a || mid >= x.b || x.iters >= h.max_iters;
+        };
+        for (int32_t kk = 2; kk <= kmax; ++kk) {
+            br[kk] = Br{h.alpha0, h.beta0, 0, false};
+            br[kk].done = stop(br[kk]);
+        }
+        std::vector<double> vals;
+        std::vector<int32_t> cnts(M);
+        std::vector<int32_t> plan_levels((size_t)kmax + 1);
+        int32_t passes = 0;
+        while (true) {
+            int32_t nact = 0;
+            for (int32_t kk = 2; kk <= kmax; ++kk) nact += br[kk].done ? 0 : 1;
+            if (nact == 0) break;
+            ISO_REQUIRE(++passes <= 64 * h.max_iters, ISO_ERR_INTERNAL, "bisection did not terminate");
+            int L = 1;
+            while (L < SPEC_LEVELS && ((1 << (L + 1)) - 1) * nact <= NCAND) ++L;
+            vals.clear();
+            auto lane_of = [&](double v) -> int {
+                for (size_t q = 0; q < vals.size(); ++q)
+                    if (vals[q] == v) return (int)q;
+                if ((int)vals.size() == NCAND) return -1;
+                vals.push_back(v);
+                return (int)vals.size() - 1;
+            };
+            // plan: whole levels of each bracket's bisection tree while lanes last
+            for (int32_t kk = 2; kk <= kmax; ++kk) {
+                plan_levels[kk] = 0;
+                if (br[kk].done) continue;
+                std::vector<double> lo(1, br[kk].a), hi(1, br[kk].b);
+                for (int l = 0; l < L; ++l) {
+                    std::vector<double> nlo, nhi;
+                    bool fits = true;
+                    const size_t before = vals.size();
+                    for (size_t q = 0; q < lo.size(); ++q) {
+                        const double mid = (lo[q] + hi[q]) / 2.0;
+                        if (lane_of(mid) < 0) {
+                            fits = false;
+                            break;
+                        }
+                        nlo.push_back(lo[q]);
+                        nhi.push_back(mid);
+                        nlo.push_back(mid);
+                        nhi.push_back(hi[q]);
+                    }
+                    if (!fits) {
+                        vals.resize(before);
+                        break;
+                    }
+                    plan_levels[kk] = l + 1;
+                    lo.swap(nlo);
+                    hi.swap(nhi);
+                }
+            }
+            ISO_REQUIRE(!vals.empty(), ISO_ERR_INTERNAL, "bisection planning produced no midpoint");
+            std::vector<double> nv(M, vals[0]);
+            std::copy(vals.begin(), vals.end(), nv.begin());
+            HIP_CHECK(hipMemcpyAsync(P.Nvals, nv.data(), sizeof(double) * M, hipMemcpyHostToDevice, s));
+            launch_levels<M, false>(A, ls, maxdepth, s);
+            HIP_CHECK(hipMemcpyAsync(cnts.data(), P.cnt + (int64_t)root_slot * M, sizeof(int32_t) * M,
+                                     hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            // each k walks its own answers, exactly as the single-k bisection
+            for (int32_t kk = 2; kk <= kmax; ++kk) {
+                Br &x = br[kk];
+                for (int l = 0; l < plan_levels[kk] && !x.done; ++l) {
+                    const double mid = (x.a + x.b) / 2.0;
+                    int q = -1;
+                    for (size_t t = 0; t < vals.size(); ++t)
+                        if (vals[t] == mid) {
+                            q = (int)t;
+                            break;
+                        }
+                    ISO_REQUIRE(q >= 0, ISO_ERR_INTERNAL, "bisection midpoint was not planned");
+                    if (cnts[q] >= kk)
+                        x.b = mid;
+                    else
+                        x.a = mid;
+                    x.iters += 1;
+                    x.done = stop(x);
+                }
+            }
+        }
+        for (int32_t kk = 2; kk <= kmax; ++kk) {
+            HIP_CHECK(hipMemcpyAsync(&P.st->beta, &br[kk].b, sizeof(double), hipMemcpyHostToDevice, s));
+            int32_t *lab = labels_all ? labels_all + (int64_t)(kk - 2) * n : P.lab_tmp;
+            const TreeState hf = finalize(kk, lab, P.cl_num_tmp, P.cl_den_tmp, P.cl_size_tmp);
+            i_k_all[kk - 2] = hf.i_k;
+        }
+        if (passes_out) *passes_out = passes;
+        whole.stop(s);
+        if (timed) {
+            timing().sub_calls += 1;
+            timing().sub_ms += whole.elapsed_ms();
+            timing().sub_passes += passes;
+        }
+        return;
+    }
+
+    // ---- single k: speculative bisection passes on the device
     const int max_batches = (h.max_iters / SPEC_LEVELS) / PASS_BATCH + 3;
     int batches = 0;
     while (true) {
@@ -693,34 +840,12 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
         if (h.done) break;
         ISO_REQUIRE(++batches < max_batches, ISO_ERR_INTERNAL, "bisection did not terminate");
     }
-
-    // final decision at beta, recording Cut and eta (Algorithm 4)
-    hipLaunchKernelGGL(k_set_final_N, dim3(1), dim3(64), 0, s, P.st, P.Nvals);
-    LAUNCH_CHECK();
-    launch_levels<1, true>(A, ls, maxdepth, s);
-    hipLaunchKernelGGL(k_cut_in_xorder, dim3(gn), dim3(256), 0, s, order, P.cut, n, P.cf);
-    LAUNCH_CHECK();
-    exclusive_scan_i32(P.cf, P.rank, n, nullptr, s);
-    hipLaunchKernelGGL(k_cluster_index, dim3(gn), dim3(256), 0, s, order, P.cut, P.rank, P.joined, parent, n, k, P.cidx,
-                       P.rep0);
-    LAUNCH_CHECK();
-    int32_t *ri = P.rep0, *ro = P.rep1;
-    for (int it = 0; it <= ceil_log2(maxdepth + 1); ++it) {
-        hipLaunchKernelGGL(k_rep_jump, dim3(gn), dim3(256), 0, s, ri, n, ro);
-        LAUNCH_CHECK();
-        std::swap(ri, ro);
+    {
+        double *cn = cl_num ? cl_num : P.cl_num_tmp;
+        double *cd = cl_den ? cl_den : P.cl_den_tmp;
+        int32_t *cs = cl_size ? cl_size : P.cl_size_tmp;
+        h = finalize(k, labels, cn, cd, cs);
     }
-    double *cn = cl_num ? cl_num : P.cl_num_tmp;
-    double *cd = cl_den ? cl_den : P.cl_den_tmp;
-    int32_t *cs = cl_size ? cl_size : P.cl_size_tmp;
-    fill_t<int32_t>(cs, 0, k, s);
-    hipLaunchKernelGGL(k_labels, dim3(gn), dim3(256), 0, s, ri, P.cidx, P.num, P.den, n, labels, cn, cd, cs);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_final_cost, dim3(1), dim3(64), 0, s, cn, cd, k, P.cnt, root_slot, P.st);
-    LAUNCH_CHECK();
-    HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    ISO_REQUIRE(h.ncuts >= k, ISO_ERR_INTERNAL, "decision at beta found %d < k = %d cuts", h.ncuts, k);
     whole.stop(s);
     if (timed) {
         timing().sub_calls += 1;
@@ -760,6 +885,48 @@ extern "C" iso_status iso_sub_workspace_size(int64_t n, int32_t k, size_t *bytes
         ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - 2, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
         ISO_REQUIRE(k >= 2 && k <= n, ISO_ERR_INVALID_ARG, "k = %d outside [2, n]", k);
         *bytes = sub_plan_bytes(n, k);
+    });
+}
+
+extern "C" iso_status iso_subpartition_all_k(const int32_t *parent, const double *length, int64_t n, int32_t root,
+                                             int32_t kmax, double sigma, const iso_sub_opts *opts, double *i_k,
+                                             int32_t *labels, int32_t *passes, void *ws, size_t ws_bytes,
+                                             void *stream) {
+    return guarded([&] {
+        ISO_REQUIRE(parent && length && i_k, ISO_ERR_INVALID_ARG, "parent, length and i_k must be non-NULL");
+        ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - 2, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+        ISO_REQUIRE(kmax >= 2 && kmax <= n, ISO_ERR_INVALID_ARG, "kmax = %d outside [2, n]", kmax);
+        ISO_REQUIRE(root >= 0 && root < n, ISO_ERR_INVALID_ARG, "root = %d outside [0, n)", root);
+        ISO_REQUIRE(sigma >= 0.0 && std::isfinite(sigma), ISO_ERR_INVALID_ARG, "sigma = %g must be finite and >= 0",
+                    sigma);
+        iso_sub_opts o{ISO_OMEGA_TREE, ISO_PHI_EXP_DIST, ISO_BRACKET_POW2, 2000, nullptr, nullptr};
+        if (opts) o = *opts;
+        ISO_REQUIRE(o.omega == ISO_OMEGA_TREE || o.omega == ISO_OMEGA_FULL, ISO_ERR_INVALID_ARG,
+                    "unsupported omega reading %d", o.omega);
+        ISO_REQUIRE(o.omega != ISO_OMEGA_FULL || o.omega0 != nullptr, ISO_ERR_INVALID_ARG,
+                    "ISO_OMEGA_FULL needs the vertex weights in opts->omega0");
+        ISO_REQUIRE(o.phi == ISO_PHI_EXP_DIST || o.phi == ISO_PHI_GAUSS_SQ, ISO_ERR_INVALID_ARG, "unknown phi %d", o.phi);
+        ISO_REQUIRE(o.bracket == ISO_BRACKET_POW2 || o.bracket == ISO_BRACKET_PAPER, ISO_ERR_INVALID_ARG,
+                    "unknown bracket %d", o.bracket);
+        require_device();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        SubPlan P{};
+        P.n = n;
+        P.k = kmax;
+        const size_t need = sub_plan_bytes(n, kmax);
+        ScopedWorkspace owned;
+        if (ws == nullptr) {
+            owned.stream = s;
+            HIP_CHECK(hipMallocAsync(&owned.ptr, need, s));
+            ws = owned.ptr;
+            ws_bytes = need;
+        }
+        ISO_REQUIRE(ws_bytes >= need, ISO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+        Arena a{static_cast<char *>(ws), 0, ws_bytes};
+        P.carve(a);
+        double ik_dummy = 0.0;
+        run_sub(P, parent, length, root, sigma, o, P.lab_tmp, &ik_dummy, nullptr, nullptr, nullptr, nullptr, s, kmax,
+                i_k, labels, passes);
     });
 }
 
