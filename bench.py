@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--all-k", type=int, default=10, metavar="K",
+                    help="after the timed steps, time the all-k sweep k = 2..K on the last tree (0: skip)")
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, run one plain device copy of MIB MiB (reference for HBM counters)")
@@ -245,6 +247,26 @@ def main():
                           "speedup_of_value": value / (n / (c1 - c0)),
                           "same_tree": bool(torch.equal(info32["parent"], info["parent"])),
                           "same_labels": bool(torch.equal(lab32, labels)), "i_k": ik32}
+    if args.all_k >= 2:
+        # every k = 2 .. K of the last step's tree in shared passes, against
+        # separate single-k calls (outside the timed region)
+        parent, length = last[2]["parent"], last[2]["length"]
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        ik_all, _, passes = iso.subpartition_all_k(parent, length, args.all_k)
+        torch.cuda.synchronize()
+        a1 = time.perf_counter()
+        sep_passes = 0
+        for kk in range(2, args.all_k + 1):
+            _, ik1, info1 = iso.isoperimetric_subpartition(parent, length, kk)
+            sep_passes += info1["passes"]
+            if ik1 != ik_all[kk - 2]:
+                raise RuntimeError("all-k sweep differs from the single-k result at k=%d" % kk)
+        torch.cuda.synchronize()
+        a2 = time.perf_counter()
+        out["all_k"] = {"kmax": args.all_k, "ms": (a1 - a0) * 1e3, "passes": passes,
+                        "separate_calls_ms": (a2 - a1) * 1e3, "separate_calls_passes": sep_passes,
+                        "i_k": [float(v) for v in ik_all]}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, n=%d sample)" % args.cpu_sample_n)
         out["cpu_baseline"] = cpu_baseline(n, k, args.cpu_sample_n)

@@ -61,6 +61,12 @@ typedef int32_t iso_status;
  * the representation error of every point enters the screen's bound, so the
  * tree is unchanged, only the number of candidates grows with it. */
 #define ISO_PREC_FP8 2
+/* INT8 screen for 8-bit data (every coordinate on one binary grid 2^q, each
+ * column spanning at most 255 steps, d < 16384, e.g. q/256 pixel values): the
+ * coordinates are centred on grid values and held as exact integers, so the
+ * Gram tiles and norms are exact in int32 on the INT8 matrix cores; other
+ * data is rejected (INVALID_ARG). */
+#define ISO_PREC_INT8 3
 
 /* Arithmetic of the exact re-evaluation of candidate distances, which defines
  * the order of the edges:

@@ -45,7 +45,7 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32"):
 
     Returns (parent int32[n] rooted at 0 with parent[0] = -1, length float64[n]
     with length[0] = 0, info dict).  ``precision`` selects the Gram screen
-    ("fp32", "bf16" or "fp8"); ``recheck`` the exact arithmetic that orders the edges
+    ("fp32", "bf16", "fp8", or "int8" for 8-bit data); ``recheck`` the exact arithmetic that orders the edges
     ("fp32", or "fp64" for parity with the FP64 oracle)."""
     torch = _torch()
     _require_cuda(points, "points", torch.float32)

@@ -17,7 +17,7 @@ ERRORS = {
     -1: "ISO_ERR_INVALID_ARG", -2: "ISO_ERR_NONFINITE", -3: "ISO_ERR_NO_DEVICE", -4: "ISO_ERR_HIP",
     -5: "ISO_ERR_OOM", -6: "ISO_ERR_WORKSPACE", -7: "ISO_ERR_INTERNAL",
 }
-PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
+PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2, "int8": 3}
 RECHECK = {"fp32": 0, "fp64": 1}
 OMEGA = {"tree": 0, "full": 1}
 PHI = {"exp": 0, "gauss_sq": 1}

@@ -50,6 +50,7 @@ enum Counter : int {
     C_CAND = 8,         // candidates re-evaluated (int64 at [8..9])
     C_RESCAN = 10,      // rows rescanned (int64 at [10..11])
     C_SUMSQ = 12,       // sum over components of size^2 (int64 at [12..13], timing only)
+    C_I8BAD = 14,       // the points are not 8-bit integers on a common grid (INT8 screen)
     C_COUNT = 16
 };
 
@@ -90,7 +91,8 @@ __device__ __forceinline__ int grid_exponent(float x) {
 // non-finite check.
 __global__ __launch_bounds__(256) void k_colstats_partial(const float *__restrict__ X, int64_t n, int64_t d,
                                                           int64_t ld, double *__restrict__ psum,
-                                                          int32_t *__restrict__ pgrid, int32_t *__restrict__ counters) {
+                                                          int32_t *__restrict__ pgrid, float *__restrict__ pmin,
+                                                          float *__restrict__ pmax, int32_t *__restrict__ counters) {
     const int64_t t = (int64_t)blockIdx.y * 256 + threadIdx.x;
     const int64_t rb = blockIdx.x;
     if (t >= d) return;
@@ -98,14 +100,19 @@ __global__ __launch_bounds__(256) void k_colstats_partial(const float *__restric
     double s = 0.0;
     int q = GRID_NONE;
     bool bad = false;
+    float mn = __builtin_huge_valf(), mx = -__builtin_huge_valf();
     for (int64_t i = lo; i < hi; ++i) {
         const float x = X[i * ld + t];
         bad |= !isfinite(x);
         s = s + (double)x;
         q = min(q, grid_exponent(x));
+        mn = fminf(mn, x);
+        mx = fmaxf(mx, x);
     }
     psum[rb * d + t] = s;
     pgrid[rb * d + t] = q;
+    pmin[rb * d + t] = mn;
+    pmax[rb * d + t] = mx;
     if (bad) atomicExch(&counters[C_NONFINITE], 1);
 }
 
@@ -134,6 +141,50 @@ __global__ void k_colstats_final(const double *__restrict__ psum, const int32_t 
     mu[t] = (float)(rint((s / (double)n) / grid) * grid);
 }
 
+// INT8 representation, first step: every column's grid, minimum and maximum;
+// the common grid 2^qg (the finest column grid) into *qg.
+__global__ void k_colrange_i8(const int32_t *__restrict__ pgrid, const float *__restrict__ pmin,
+                              const float *__restrict__ pmax, int64_t nrb, int64_t d, float *__restrict__ cmin,
+                              float *__restrict__ cmax, int32_t *__restrict__ qg) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    int q = GRID_NONE;
+    float mn = __builtin_huge_valf(), mx = -__builtin_huge_valf();
+    for (int64_t rb = 0; rb < nrb; ++rb) {
+        q = min(q, pgrid[rb * d + t]);
+        mn = fminf(mn, pmin[rb * d + t]);
+        mx = fmaxf(mx, pmax[rb * d + t]);
+    }
+    cmin[t] = mn;
+    cmax[t] = mx;
+    if (q != GRID_NONE) atomicMin(qg, q);
+}
+
+// INT8 representation, second step: centre mu_t = min_t + 128 * 2^qg, so that
+// every (x - mu_t) / 2^qg is an integer in [-128, 127] exactly when the
+// column's range is at most 255 grid steps; a column that does not fit (or a
+// centre that does not round exactly) flags counters[C_I8BAD].
+__global__ void k_center_i8(const float *__restrict__ cmin, const float *__restrict__ cmax, int64_t d, int64_t d_pad,
+                            const int32_t *__restrict__ qg, float *__restrict__ mu, int32_t *__restrict__ counters) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d_pad) return;
+    if (t >= d) {
+        mu[t] = 0.0f;
+        return;
+    }
+    const int q = *qg;
+    if (q == GRID_NONE) {  // every coordinate is zero
+        mu[t] = 0.0f;
+        return;
+    }
+    const double step = ldexp(1.0, q);
+    const double m = (double)cmin[t] + 128.0 * step;
+    const bool fits = (double)cmax[t] - (double)cmin[t] <= 255.0 * step && (double)(float)m == m && q > -120 &&
+                      q < 100;
+    mu[t] = (float)m;
+    if (!fits) atomicExch(&counters[C_I8BAD], 1);
+}
+
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
     u += 0x7FFFu + ((u >> 16) & 1u);
@@ -160,7 +211,8 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
                                                    void *__restrict__ Xr, float *__restrict__ sq,
                                                    float *__restrict__ rn, float *__restrict__ re,
                                                    uint32_t *__restrict__ rmax_bits, uint32_t *__restrict__ emax_bits,
-                                                   int32_t *__restrict__ grid_min) {
+                                                   int32_t *__restrict__ grid_min, int32_t *__restrict__ sqi,
+                                                   float inv_step) {
     const int lane = threadIdx.x & 63;
     // rows are walked with the stride of all waves; the maxima of r and e and
     // the grid exponent are merged into the globals once per wave
@@ -171,6 +223,7 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
     float s = 0.0f;
     double m2 = 0.0, e2 = 0.0;
     int q = GRID_NONE;
+    int32_t si = 0;  // INT8: exact squared norm in grid units
     for (int64_t t = lane; t < d_pad; t += 64) {
         float xv = 0.0f, y = 0.0f;
         if (i < n && t < d) {
@@ -186,6 +239,13 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
             const uint8_t b = fp8_rne(y);
             static_cast<uint8_t *>(Xr)[i * d_pad + t] = b;
             yr = fp8_to_f32(b);
+        } else if (REP == ISO_PREC_INT8) {
+            // (x - mu) / 2^qg is an integer in [-128, 127] (checked by the
+            // centre); y = x - mu is exact
+            const int v = (int)rintf(y * inv_step);
+            static_cast<int8_t *>(Xr)[i * d_pad + t] = (int8_t)v;
+            si = si + v * v;
+            yr = y;
         } else {
             static_cast<float *>(Xr)[i * d_pad + t] = y;
             yr = y;
@@ -202,6 +262,7 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         s += __shfl_xor(s, off, 64);
+        si += __shfl_xor(si, off, 64);
         m2 += __shfl_xor(m2, off, 64);
         e2 += __shfl_xor(e2, off, 64);
         q = min(q, __shfl_xor(q, off, 64));
@@ -212,6 +273,7 @@ __global__ __launch_bounds__(256) void k_repr_rows(const float *__restrict__ X, 
         sq[i] = i < n ? s : __builtin_huge_valf();  // padding: every Dhat^2 with it is +inf
         rn[i] = r;
         re[i] = e;
+        if (REP == ISO_PREC_INT8) sqi[i] = i < n ? si : (1 << 30);  // padding: a distance at or beyond 2^30 means none
     }
     wq = min(wq, q);
     wr = max(wr, __float_as_uint(r));
@@ -765,13 +827,19 @@ __global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, c
 
 // ------------------------------------------------------------------ plan
 
+size_t rep_bytes(int32_t precision) {
+    return precision == ISO_PREC_BF16 ? 2 : (precision == ISO_PREC_FP8 || precision == ISO_PREC_INT8) ? 1 : 4;
+}
+
+
 struct MstPlan {
     int64_t n, d, ld, n_pad, d_pad, nrb;
     int32_t precision;
     void *Xr;                       // screen representation (FP32, BF16 or FP8), [n_pad][d_pad]
     void *Xq;                       // the same rows in the tile order of the round
     float *mu, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
-    int32_t *pgrid, *grid_min;
+    int32_t *pgrid, *grid_min, *sqi, *qg;
+    float *pmin, *pmax, *cmin, *cmax;
     int2 *pairs, *pairs_r;          // all tile pairs (diagonal first); the pairs kept this round
     int64_t npairs, nt;
     int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos;
@@ -786,12 +854,18 @@ struct MstPlan {
     int32_t *counters;
 
     void carve(Arena &a) {
-        const size_t esz = precision == ISO_PREC_BF16 ? 2 : precision == ISO_PREC_FP8 ? 1 : 4;
+        const size_t esz = rep_bytes(precision);
         Xr = a.take<char>((size_t)n_pad * d_pad * esz);
         Xq = a.take<char>((size_t)n_pad * d_pad * esz);
         mu = a.take<float>(d_pad);
         psum = a.take<double>((size_t)nrb * d);
         pgrid = a.take<int32_t>((size_t)nrb * d);
+        pmin = a.take<float>((size_t)nrb * d);
+        pmax = a.take<float>((size_t)nrb * d);
+        cmin = a.take<float>(d);
+        cmax = a.take<float>(d);
+        qg = a.take<int32_t>(1);
+        sqi = a.take<int32_t>(n_pad);
         grid_min = a.take<int32_t>(1);
         sq = a.take<float>(n_pad);
         rn = a.take<float>(n_pad);
@@ -855,7 +929,7 @@ MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
     p.ld = ld;
     p.precision = precision;
     p.n_pad = (n + GT - 1) / GT * GT;
-    const int64_t kc = 64 / (precision == ISO_PREC_BF16 ? 2 : precision == ISO_PREC_FP8 ? 1 : 4);  // 64-byte K chunks
+    const int64_t kc = 64 / (int64_t)rep_bytes(precision);  // 64-byte K chunks
     p.d_pad = (d + kc - 1) / kc * kc;
     p.nrb = (n + COL_RB - 1) / COL_RB;
     p.nt = p.n_pad / pair_tile();
@@ -888,21 +962,44 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     fill<uint32_t>(P.emax, 0u, 1, s);
     fill<int32_t>(P.grid_min, GRID_NONE, 1, s);
     hipLaunchKernelGGL(k_colstats_partial, dim3((unsigned)P.nrb, (unsigned)((d + 255) / 256)), dim3(256), 0, s, X, n, d,
-                       ld, P.psum, P.pgrid, P.counters);
+                       ld, P.psum, P.pgrid, P.pmin, P.pmax, P.counters);
     LAUNCH_CHECK();
     int32_t h_nonfinite = 0;
     HIP_CHECK(hipMemcpyAsync(&h_nonfinite, P.counters + C_NONFINITE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     ISO_REQUIRE(h_nonfinite == 0, ISO_ERR_NONFINITE, "points contain a NaN or infinite coordinate");
-    hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.psum, P.pgrid, P.nrb, n, d,
-                       P.d_pad, P.mu);
-    LAUNCH_CHECK();
+    float inv_step = 1.0f;  // INT8: 2^-qg
+    int32_t h_qg = GRID_NONE;
+    if (rep == ISO_PREC_INT8) {
+        ISO_REQUIRE(d < 16384, ISO_ERR_INVALID_ARG, "the INT8 screen needs d < 16384 (d = %lld)", (long long)d);
+        fill<int32_t>(P.qg, GRID_NONE, 1, s);
+        hipLaunchKernelGGL(k_colrange_i8, dim3(grid_for(d, 256)), dim3(256), 0, s, P.pgrid, P.pmin, P.pmax, P.nrb, d,
+                           P.cmin, P.cmax, P.qg);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_center_i8, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.cmin, P.cmax, d, P.d_pad, P.qg,
+                           P.mu, P.counters);
+        LAUNCH_CHECK();
+        int32_t hb[2] = {0, 0};
+        HIP_CHECK(hipMemcpyAsync(&hb[0], P.counters + C_I8BAD, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&h_qg, P.qg, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        ISO_REQUIRE(hb[0] == 0, ISO_ERR_INVALID_ARG,
+                    "the INT8 screen needs 8-bit data: every coordinate on one binary grid 2^q with each column "
+                    "spanning at most 255 steps");
+        if (h_qg != GRID_NONE) inv_step = (float)std::ldexp(1.0, -h_qg);
+    } else {
+        hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.psum, P.pgrid, P.nrb, n,
+                           d, P.d_pad, P.mu);
+        LAUNCH_CHECK();
+    }
     {
-        auto kern = rep == ISO_PREC_BF16 ? k_repr_rows<ISO_PREC_BF16>
-                                         : rep == ISO_PREC_FP8 ? k_repr_rows<ISO_PREC_FP8> : k_repr_rows<ISO_PREC_FP32>;
+        auto kern = rep == ISO_PREC_BF16   ? k_repr_rows<ISO_PREC_BF16>
+                    : rep == ISO_PREC_FP8  ? k_repr_rows<ISO_PREC_FP8>
+                    : rep == ISO_PREC_INT8 ? k_repr_rows<ISO_PREC_INT8>
+                                           : k_repr_rows<ISO_PREC_FP32>;
         const unsigned g = std::min<unsigned>(grid_for(P.n_pad, 4), 8u * (unsigned)device_cus());
         hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, X, n, d, ld, P.n_pad, P.d_pad, P.mu, P.Xr, P.sq, P.rn, P.re,
-                           P.rmax, P.emax, P.grid_min);
+                           P.rmax, P.emax, P.grid_min, P.sqi, inv_step);
     }
     LAUNCH_CHECK();
     const double u = 1.0 / 8388608.0;  // 2^-23
@@ -926,6 +1023,12 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     // recheck's unit roundoff (2^-24 FP32, 2^-53 FP64)
     const double ur = f64 ? 0x1p-53 : 0x1p-24;
     const double rho = (double)(d + 2) * ur / (1.0 - (double)(d + 2) * ur);
+    if (rep == ISO_PREC_INT8) {
+        // exact integer Gram and norms: the only rounding is the conversion of
+        // the exact integer Dhat^2 to FP32 (the power-of-two scale is exact)
+        bound.g = bound.g_exact = (float)(2.0 * u * (1.0 + 1.0 / 1024.0));
+        bound.rlim = 0.0f;
+    }
     const float kappa = (float)((1.0 + rho) / (1.0 - rho) * (1.0 + 0x1p-20));
     const float up = (float)((1.0 + rho) * (1.0 + 0x1p-20));
     const float dn = (float)(1.0 / (1.0 - rho) * (1.0 + 0x1p-20));
@@ -940,6 +1043,9 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.XT = rep == ISO_PREC_FP32 ? static_cast<const float *>(P.Xr) : nullptr;
     SA.XB = rep == ISO_PREC_BF16 ? static_cast<const uint16_t *>(P.Xr) : nullptr;
     SA.XF8 = rep == ISO_PREC_FP8 ? static_cast<const uint8_t *>(P.Xr) : nullptr;
+    SA.XI8 = rep == ISO_PREC_INT8 ? static_cast<const int8_t *>(P.Xr) : nullptr;
+    SA.sqi = P.sqi;
+    SA.scale2 = (rep == ISO_PREC_INT8 && h_qg != GRID_NONE) ? (float)std::ldexp(1.0, 2 * h_qg) : 1.0f;
     SA.n = n;
     SA.n_pad = P.n_pad;
     SA.d_pad = P.d_pad;
@@ -997,7 +1103,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             LAUNCH_CHECK();
             radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, kb, P.psort, s);
             {
-                const size_t esz = rep == ISO_PREC_BF16 ? 2 : rep == ISO_PREC_FP8 ? 1 : 4;
+                const size_t esz = rep_bytes(rep);
                 const int64_t row_u4 = (int64_t)(P.d_pad * esz / 16);
                 const unsigned g = std::min<unsigned>(grid_for(P.n_pad, 4), 8u * (unsigned)device_cus());
                 hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr), P.perm,
@@ -1197,7 +1303,8 @@ extern "C" iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t preci
         ISO_REQUIRE(bytes != nullptr, ISO_ERR_INVALID_ARG, "bytes is NULL");
         ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - GT, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
         ISO_REQUIRE(d >= 1, ISO_ERR_INVALID_ARG, "d = %lld < 1", (long long)d);
-        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8,
+        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8 ||
+                        precision == ISO_PREC_INT8,
                     ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
         *bytes = plan_bytes(make_plan(n, d, d, precision));
     });
@@ -1211,7 +1318,8 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - GT, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
         ISO_REQUIRE(d >= 1, ISO_ERR_INVALID_ARG, "d = %lld < 1", (long long)d);
         ISO_REQUIRE(ld >= d, ISO_ERR_INVALID_ARG, "ld = %lld < d = %lld", (long long)ld, (long long)d);
-        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8,
+        ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8 ||
+                        precision == ISO_PREC_INT8,
                     ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
         ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
                     "unknown recheck %d", recheck);

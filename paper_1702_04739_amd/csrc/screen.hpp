@@ -48,10 +48,13 @@ struct ScreenBound {
 };
 
 struct ScreenArgs {
-    int32_t rep;             // ISO_PREC_FP32 / ISO_PREC_BF16 / ISO_PREC_FP8
+    int32_t rep;             // ISO_PREC_FP32 / ISO_PREC_BF16 / ISO_PREC_FP8 / ISO_PREC_INT8
     const float *XT;         // FP32 screen: [n_pad][d_pad] centred, row-major
     const uint16_t *XB;      // BF16 screen: [n_pad][d_pad] centred, row-major (bf16 bits)
     const uint8_t *XF8;      // FP8 screen: [n_pad][d_pad] centred, row-major (E4M3 bytes)
+    const int8_t *XI8;       // INT8 screen: [n_pad][d_pad] (x - mu) / 2^q as integers, row-major
+    const int32_t *sqi;      // INT8 screen: [n_pad] exact ||(x - mu) / 2^q||^2, 2^30 on padding
+    float scale2;            // INT8 screen: 2^2q, the unit of the integer distances
     int64_t n, n_pad, d_pad;
     const float *sq;         // [n_pad] fl(||x'||^2) as used in Dhat^2 (0 on padding)
     const float *rn;         // [n_pad] r_i
@@ -87,6 +90,7 @@ struct ScreenLDS {
     float ll[SCR_ROWS][SCR_CAP];
     float csq[SCR_COLS], crn[SCR_COLS], cre[SCR_COLS];
     int32_t ccomp[SCR_COLS];
+    int32_t csqi[SCR_COLS];  // INT8: exact integer squared norms
 };
 
 // Minimum over the 64 lanes of a wave (every lane receives it), unsigned.
@@ -174,6 +178,7 @@ __device__ __forceinline__ void screen_load_cols(ScreenLDS &S, const ScreenArgs 
         S.crn[q] = A.rn[j];
         S.cre[q] = A.re[j];
         S.ccomp[q] = A.comp[j];
+        S.csqi[q] = A.sqi ? A.sqi[j] : 0;
     }
 }
 

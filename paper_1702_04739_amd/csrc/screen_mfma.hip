@@ -15,6 +15,8 @@
 //   result register q of lane l: MFMA row 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32.
 //   FP8:  v_mfma_scale_f32_32x32x64_f8f6f4 (E4M3, unit block scales), lane l supplies row (l mod 32),
 //         k = 32 (l div 32) .. +31
+//   INT8: v_mfma_i32_32x32x32_i8, lane l supplies row (l mod 32), k = 16 (l div 32) .. +15 (int32
+//         accumulators kept bit for bit in the FP32 accumulator registers)
 // Workgroup: 4 waves in a 2 x 2 grid, each wave a 64 x 64 sub-tile (2 x 2 MFMA blocks).
 #include "screen.hpp"
 
@@ -24,6 +26,8 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx16 __attribute__((ext_vector_type(16)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 template <int REP>
@@ -48,6 +52,15 @@ struct Prec<ISO_PREC_FP8> {
 };
 
 template <>
+struct Prec<ISO_PREC_INT8> {
+    using T = int8_t;                         // integer coordinates
+    static constexpr int KC = 64;
+    static constexpr int LDK = KC + 16;
+    static constexpr int KSTEP = 32;
+    static constexpr int VEC = 16;
+};
+
+template <>
 struct Prec<ISO_PREC_FP32> {
     using T = float;
     static constexpr int KC = 16;
@@ -68,9 +81,10 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
     const int lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1;
     const int64_t i0 = (int64_t)blockIdx.x * SCR_ROWS;
-    const T *X = REP == ISO_PREC_BF16  ? reinterpret_cast<const T *>(A.XB)
-                 : REP == ISO_PREC_FP8 ? reinterpret_cast<const T *>(A.XF8)
-                                       : reinterpret_cast<const T *>(A.XT);
+    const T *X = REP == ISO_PREC_BF16   ? reinterpret_cast<const T *>(A.XB)
+                 : REP == ISO_PREC_FP8  ? reinterpret_cast<const T *>(A.XF8)
+                 : REP == ISO_PREC_INT8 ? reinterpret_cast<const T *>(A.XI8)
+                                        : reinterpret_cast<const T *>(A.XT);
     const int64_t d_pad = A.d_pad;
 
     screen_init_rows<GATHER>(S, A, i0);
@@ -80,6 +94,7 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
     int64_t gi[2];
     float si[2], ri[2], ei[2];
     int ci[2];
+    int32_t sii[2];  // INT8: exact integer squared norms
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib) {
         rl[ib] = 64 * wi + 32 * ib + (lane & 31);
@@ -95,6 +110,7 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
         ri[ib] = i >= 0 ? A.rn[i] : 0.0f;
         ei[ib] = i >= 0 ? A.re[i] : 0.0f;
         ci[ib] = i >= 0 ? A.comp[i] : -1;
+        sii[ib] = (REP == ISO_PREC_INT8 && i >= 0) ? A.sqi[i] : 0;
     }
     // staging: each thread moves LOADS 16-byte pieces of each operand per chunk
     constexpr int CHUNK = 16 / sizeof(T);               // elements per 16-byte load
@@ -162,7 +178,22 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
 #pragma unroll
             for (int ks = 0; ks < P::KC; ks += P::KSTEP) {
                 const int kofs = ks + (lane >> 5) * P::VEC;
-                if constexpr (REP == ISO_PREC_FP8) {
+                if constexpr (REP == ISO_PREC_INT8) {
+                    intx4 a[2], b[2];
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb)
+                        a[jb] = *reinterpret_cast<const intx4 *>(&Ab[(64 * wj + 32 * jb + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+                        b[ib] = *reinterpret_cast<const intx4 *>(&Bb[(64 * wi + 32 * ib + (lane & 31)) * P::LDK + kofs]);
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                        for (int jb = 0; jb < 2; ++jb)
+                            acc[ib][jb] = __builtin_bit_cast(
+                                floatx16, __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                              a[jb], b[ib], __builtin_bit_cast(intx16, acc[ib][jb]), 0, 0, 0));
+                } else if constexpr (REP == ISO_PREC_FP8) {
                     intx8 a[2], b[2];
 #pragma unroll
                     for (int jb = 0; jb < 2; ++jb)
@@ -218,7 +249,16 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    const float v = screen_value(acc[ib][jb][q], si[ib], S.csq[jl], ci[ib], S.ccomp[jl]);
+                    float v;
+                    if constexpr (REP == ISO_PREC_INT8) {
+                        const uint32_t d2 = (uint32_t)sii[ib] + (uint32_t)S.csqi[jl] -
+                                            2u * (uint32_t)__float_as_int(acc[ib][jb][q]);
+                        v = (ci[ib] >= 0 && S.ccomp[jl] >= 0 && S.ccomp[jl] != ci[ib] && d2 < (1u << 30))
+                                ? (float)d2 * A.scale2
+                                : SCR_INF;
+                    } else {
+                        v = screen_value(acc[ib][jb][q], si[ib], S.csq[jl], ci[ib], S.ccomp[jl]);
+                    }
                     acc[ib][jb][q] = v;
                     m = fminf(m, v);
                 }
@@ -278,6 +318,8 @@ void launch_screen_rows(const ScreenArgs &A, bool gather, hipStream_t s) {
         launch<ISO_PREC_BF16>(A, gather, s);
     else if (A.rep == ISO_PREC_FP8)
         launch<ISO_PREC_FP8>(A, gather, s);
+    else if (A.rep == ISO_PREC_INT8)
+        launch<ISO_PREC_INT8>(A, gather, s);
     else
         launch<ISO_PREC_FP32>(A, gather, s);
 }

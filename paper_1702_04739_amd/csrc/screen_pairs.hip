@@ -43,6 +43,8 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx16 __attribute__((ext_vector_type(16)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int PT = 256;                // points per tile (rows of a work item)
@@ -82,6 +84,14 @@ struct PPrec<ISO_PREC_FP8> {
 };
 
 template <>
+struct PPrec<ISO_PREC_INT8> {
+    using T = int8_t;
+    static constexpr int KC = 64;
+    static constexpr int KSTEP = 32;
+    static constexpr int VEC = 16;
+};
+
+template <>
 struct PPrec<ISO_PREC_FP32> {
     using T = float;
     static constexpr int KC = 16;
@@ -98,6 +108,7 @@ struct PairLDS {
     int32_t rhot[PT];      // row's tile minimum is within its capture margin
     uint32_t chot[PH / 32];
     int32_t rid[PT], cid[PH];  // point ids of the rows and columns
+    int32_t csqi[PH];          // INT8: exact integer squared norms of the columns
 };
 
 constexpr uint32_t INF_BITS = 0x7F800000u;  // +inf; every screen value is a nonnegative float or +inf
@@ -163,17 +174,20 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             S.cmin[tid] = INF_BITS;
             S.cE[tid] = j < A.n ? A.Emax[j] : 0.0f;
             S.csq[tid] = A.sq[j];
+            if (REP == ISO_PREC_INT8) S.csqi[tid] = A.sqi[j];
             S.ccomp[tid] = A.comp[j];
         }
     }
     static_assert(64 * NW == PT, "one thread per row");
     float si[NIB];
     int ci[NIB];
+    int32_t sii[NIB];  // INT8: exact integer squared norms of the rows
 #pragma unroll
     for (int ib = 0; ib < NIB; ++ib) {
         const int64_t i = perm[I0 + RW * wi + 32 * ib + (lane & 31)];
         si[ib] = A.sq[i];
         ci[ib] = A.comp[i];
+        sii[ib] = REP == ISO_PREC_INT8 ? A.sqi[i] : 0;
     }
 
     // asynchronous staging: each wave moves RUNS 1 KB runs of slots per chunk
@@ -278,6 +292,27 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         ISO_PIPELINE
 #undef ISO_COMPUTE
 #undef ISO_FRAG8
+    } else if constexpr (REP == ISO_PREC_INT8) {
+        // two 32 x 32 x 32 INT8 MFMAs per block and chunk (int32 accumulators
+        // held in the FP32 accumulator registers, bit for bit)
+#define ISO_COMPUTE(SB)                                                                                       \
+    _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
+        const int kel = ks + (lane >> 5) * P::VEC;                                                             \
+        intx4 a[NJB], bb[NIB];                                                                                \
+        _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) {                                                  \
+            const uint4 v = SB[frag_slot(CW * wj + 32 * jb + (lane & 31), kel)];                               \
+            a[jb] = intx4{(int)v.x, (int)v.y, (int)v.z, (int)v.w};                                             \
+        }                                                                                                     \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                                  \
+            const uint4 v = SB[frag_slot(PH + RW * wi + 32 * ib + (lane & 31), kel)];                          \
+            bb[ib] = intx4{(int)v.x, (int)v.y, (int)v.z, (int)v.w};                                            \
+        }                                                                                                     \
+        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) \
+            acc[ib][jb] = __builtin_bit_cast(floatx16, __builtin_amdgcn_mfma_i32_32x32x32_i8(                  \
+                a[jb], bb[ib], __builtin_bit_cast(intx16, acc[ib][jb]), 0, 0, 0));                            \
+    }
+        ISO_PIPELINE
+#undef ISO_COMPUTE
     } else {
 #define ISO_COMPUTE(SB)                                                                                       \
     _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
@@ -317,10 +352,18 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                 const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
                 const float sj = S.csq[jl];
                 const int cjj = S.ccomp[jl];
+                const uint32_t sjq = REP == ISO_PREC_INT8 ? (uint32_t)S.csqi[jl] : 0u;
                 uint32_t cmin = INF_BITS;
 #pragma unroll
                 for (int ib = 0; ib < NIB; ++ib) {
-                    const int32_t tb = __float_as_int(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj));
+                    int32_t tb;
+                    if constexpr (REP == ISO_PREC_INT8) {
+                        // exact integer squared distance; 2^30 and beyond only with padding
+                        const uint32_t d2 = (uint32_t)sii[ib] + sjq - 2u * (uint32_t)__float_as_int(acc[ib][jb][q]);
+                        tb = d2 >= (1u << 30) ? (int32_t)INF_BITS : __float_as_int((float)d2 * A.scale2);
+                    } else {
+                        tb = __float_as_int(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj));
+                    }
                     uint32_t v = (cjj == ci[ib]) ? INF_BITS : (uint32_t)max(tb, 0);
                     if (DIAG && half * PH + jl <= RW * wi + 32 * ib + (lane & 31)) v = INF_BITS;  // each pair once
                     acc[ib][jb][q] = __uint_as_float(v);
@@ -487,6 +530,8 @@ void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, 
         launch_pairs<ISO_PREC_BF16>(A, pairs, ndiag, noff, s);
     else if (A.rep == ISO_PREC_FP8)
         launch_pairs<ISO_PREC_FP8>(A, pairs, ndiag, noff, s);
+    else if (A.rep == ISO_PREC_INT8)
+        launch_pairs<ISO_PREC_INT8>(A, pairs, ndiag, noff, s);
     else
         launch_pairs<ISO_PREC_FP32>(A, pairs, ndiag, noff, s);
 }

@@ -123,6 +123,14 @@ def test_fp32_screen_same_tree(c3):
     assert torch.equal(l32, info["length"])
 
 
+def test_int8_screen_same_tree(c3):
+    iso, X, Xg, labels, ik, info = c3
+    H.log("c3 full int8 screen")
+    p8, l8, i8 = iso.mst(Xg, precision="int8", recheck="fp32")
+    assert torch.equal(p8, info["parent"])
+    assert torch.equal(l8, info["length"])
+
+
 def test_tree_stage_matches_oracle(c3):
     import oracle
     iso, X, Xg, labels, ik, info = c3

@@ -174,8 +174,32 @@ def test_screen_precision_does_not_change_tree(iso, cfg, n):
     X = torch.from_numpy(datagen.config(cfg, n=n)).cuda()
     H.log("screen precision invariance config %d n=%d" % (cfg, n))
     a = iso.mst(X, precision="fp32")
-    for prec in ("bf16", "fp8"):
+    for prec in ("bf16", "fp8") + (("int8",) if cfg == 3 else ()):
         b = iso.mst(X, precision=prec)
         H.log("  %s: candidates %d rescanned %d (fp32: %d, %d)" % (prec, b[2]["candidates"], b[2]["rescanned_rows"],
                                                                    a[2]["candidates"], a[2]["rescanned_rows"]))
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("name", ["c3-n1500-d784", "lattice-12x12", "lattice-5^3"])
+@pytest.mark.parametrize("recheck", ["fp64", "fp32"])
+def test_int8_screen_8bit_data(iso, orc, name, recheck):
+    """8-bit data (q/256 coordinates, integer lattices): the INT8 screen's
+    exact integer distances give the same tree as the oracle (FP64 recheck)
+    and the same tree as the FP32 screen (either recheck)."""
+    X, op, ol = _oracle_tree(orc, name)
+    H.log("case %s int8 screen + %s recheck" % (name, recheck))
+    Xg = torch.from_numpy(X).cuda()
+    parent, length, info = iso.mst(Xg, precision="int8", recheck=recheck)
+    p32, l32, _ = iso.mst(Xg, precision="fp32", recheck=recheck)
+    assert torch.equal(parent, p32) and torch.equal(length, l32)
+    if recheck == "fp64":
+        np.testing.assert_array_equal(parent.cpu().numpy(), op)
+
+
+def test_int8_rejects_other_data(iso):
+    from paper_1702_04739_amd._lib import IsoError
+    X = torch.from_numpy(datagen.config(1, n=300)).cuda()
+    with pytest.raises(IsoError) as e:
+        iso.mst(X, precision="int8")
+    assert e.value.code == -1
