@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
 WORKLOAD = 3
-PEAKS_TFLOPS = {"fp8": 5000.0, "bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
+PEAKS_TFLOPS = {"int8": 5000.0, "fp8": 5000.0, "bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
 # one screen launch = the diagonal tile pairs' dispatch followed by the off-diagonal one
 SCREEN_KERNEL = "k_screen_pairs<%s> (diagonal + off-diagonal dispatch)"
 SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/screen_pairs.hip", "paper_1702_04739_amd/csrc/screen.hpp"]
@@ -62,7 +62,7 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
     import csv
     import glob
 
-    prefix = "k_screen_pairs<%d, " % {"fp32": 0, "bf16": 1, "fp8": 2}[precision]
+    prefix = "k_screen_pairs<%d, " % {"fp32": 0, "bf16": 1, "fp8": 2, "int8": 3}[precision]
 
     def per_kernel(d, counter):
         """Summed counter over the screen's dispatches (diagonal and
@@ -122,8 +122,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP32-screen comparison step")
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8", "int8"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32 and INT8 screen comparison steps")
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -235,18 +235,25 @@ def main():
                    "passes": info["sub"]["passes"], "max_depth": info["sub"]["max_depth"],
                    "i_k": ik, "mst_weight": info["mst"]["mst_weight"]},
     }
-    if not args.no_compare and args.precision != "fp32":
-        log("comparison: FP32 screen, 1 warm-up + 1 step")
-        iso.cluster(X, k, precision="fp32", recheck=args.recheck)
-        torch.cuda.synchronize()
-        c0 = time.perf_counter()
-        lab32, ik32, info32 = iso.cluster(X, k, precision="fp32", recheck=args.recheck)
-        torch.cuda.synchronize()
-        c1 = time.perf_counter()
-        out["compare"] = {"screen": "fp32", "value": n / (c1 - c0), "ms_per_step": (c1 - c0) * 1e3,
-                          "speedup_of_value": value / (n / (c1 - c0)),
-                          "same_tree": bool(torch.equal(info32["parent"], info["parent"])),
-                          "same_labels": bool(torch.equal(lab32, labels)), "i_k": ik32}
+    if not args.no_compare:
+        # the same step with other screen precisions (FP32: the reference
+        # precision; INT8: exact integer Gram tiles, for 8-bit data like this
+        # workload's q/256 coordinates), one warm-up + one step each
+        out["compare"] = []
+        for prec in ("fp32", "int8"):
+            if prec == args.precision:
+                continue
+            log("comparison: %s screen, 1 warm-up + 1 step" % prec)
+            iso.cluster(X, k, precision=prec, recheck=args.recheck)
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            labc, ikc, infoc = iso.cluster(X, k, precision=prec, recheck=args.recheck)
+            torch.cuda.synchronize()
+            c1 = time.perf_counter()
+            out["compare"].append({"screen": prec, "value": n / (c1 - c0), "ms_per_step": (c1 - c0) * 1e3,
+                                   "value_ratio": value / (n / (c1 - c0)),
+                                   "same_tree": bool(torch.equal(infoc["parent"], info["parent"])),
+                                   "same_labels": bool(torch.equal(labc, labels)), "i_k": ikc})
     if args.all_k >= 2:
         # every k = 2 .. K of the last step's tree in shared passes, against
         # separate single-k calls (outside the timed region)
