@@ -281,7 +281,7 @@ extern "C" iso_status iso_backward(const float *X, int64_t n, int64_t d, int64_t
         hipLaunchKernelGGL(k_bw_keys, dim3(gn), dim3(256), 0, s, parent, n, P.key, P.val);
         LAUNCH_CHECK();
         radix_sort_pairs_u32(P.key, P.val, P.tk, P.tv, n, bits_of(n), P.sort_scratch, s);
-        exclusive_scan_i32(P.nchild, P.koff, n + 1, nullptr, s);
+        exclusive_scan_i32(P.nchild, P.koff, n + 1, nullptr, nullptr, s);
         // vertices without a parent sort first (key 0); the child lists follow
         int32_t total_children = 0;
         HIP_CHECK(hipMemcpyAsync(&total_children, P.koff + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));

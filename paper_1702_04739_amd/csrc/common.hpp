@@ -145,8 +145,12 @@ inline int ceil_log2(int64_t x) {
 // ------------------------------------------------------------------ primitives (scan_sort.hip)
 
 // Exclusive scan of int32 in[0..n) into out[0..n) (in-place allowed); writes
-// the total to *total (device) when total != nullptr.  One workgroup.
-void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, hipStream_t s);
+// the total to *total (device) when total != nullptr.  With scratch (device,
+// scan_scratch_bytes(n)) long inputs are scanned by many workgroups; without
+// it, by one.
+size_t scan_scratch_bytes(int64_t n);
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, int32_t *scratch,
+                        hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs by the low `key_bits` bits of
 // key.  tmp_* are scratch of n entries each; results land in keys/vals.

@@ -842,7 +842,7 @@ struct MstPlan {
     float *pmin, *pmax, *cmin, *cmax;
     int2 *pairs, *pairs_r;          // all tile pairs (diagonal first); the pairs kept this round
     int64_t npairs, nt;
-    int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos;
+    int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos, *scan_scratch;
     uint32_t *pkeys, *ptk, *ptv;
     void *psort;
     double *psum;
@@ -916,6 +916,7 @@ struct MstPlan {
         thi = a.take<int32_t>(nt);
         keep = a.take<int32_t>(npairs);
         kpos = a.take<int32_t>(npairs + 1);
+        scan_scratch = a.take<int32_t>(scan_scratch_bytes(std::max<int64_t>(npairs, n + 1)) / sizeof(int32_t));
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
     // they are sized for all rows (rows are gathered at most once per round).
@@ -1117,7 +1118,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.tlo,
                                P.thi, P.keep);
             LAUNCH_CHECK();
-            exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, s);
+            exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, P.scan_scratch, s);
             hipLaunchKernelGGL(k_pair_scatter, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs,
                                P.keep, P.kpos, P.pairs_r);
             LAUNCH_CHECK();
@@ -1199,7 +1200,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         }
         hipLaunchKernelGGL(k_isroot, dim3(grid_for(ncomp, 256)), dim3(256), 0, s, P.npar, ncomp, P.flag);
         LAUNCH_CHECK();
-        exclusive_scan_i32(P.flag, P.newid, ncomp, P.counters + C_NCOMP, s);
+        exclusive_scan_i32(P.flag, P.newid, ncomp, P.counters + C_NCOMP, P.scan_scratch, s);
         hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.npar, P.newid);
         LAUNCH_CHECK();
         int32_t h[C_COUNT];
@@ -1229,7 +1230,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     fill<int32_t>(P.deg, 0, n + 1, s);
     hipLaunchKernelGGL(k_degree, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, m, P.deg);
     LAUNCH_CHECK();
-    exclusive_scan_i32(P.deg, P.aoff, n + 1, nullptr, s);
+    exclusive_scan_i32(P.deg, P.aoff, n + 1, nullptr, P.scan_scratch, s);
     fill<int32_t>(P.cursor, 0, n, s);
     hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, m, P.aoff, P.cursor, P.adj,
                        P.adje);

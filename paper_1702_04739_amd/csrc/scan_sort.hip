@@ -103,12 +103,60 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_exclusive_scan(const int32_t *in
     if (threadIdx.x == 0 && total) *total = s_total;
 }
 
-void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, hipStream_t s) {
+// Multi-block scan for long inputs: tiles of SCAN_TILE elements, each thread
+// holding elements base + r * SCAN_BLOCK + tid (r = 0 .. SCAN_ROUNDS-1, so the
+// loads are coalesced); tile sums, their exclusive scan, then each tile rescans
+// round by round in index order from its offset.
+constexpr int SCAN_ROUNDS = 8;
+constexpr int64_t SCAN_TILE = (int64_t)SCAN_BLOCK * SCAN_ROUNDS;
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tile_sums(const int32_t *in, int64_t n, int32_t *sums) {
+    __shared__ int32_t s_total;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int32_t v = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_ROUNDS; ++r) {
+        const int64_t i = base + (int64_t)r * SCAN_BLOCK + threadIdx.x;
+        v += i < n ? in[i] : 0;
+    }
+    (void)block_exclusive_scan(v, &s_total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s_total;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tile_apply(const int32_t *in, int32_t *out, int64_t n,
+                                                                const int32_t *offsets) {
+    __shared__ int32_t s_total;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int32_t run = offsets[blockIdx.x];
+    for (int r = 0; r < SCAN_ROUNDS; ++r) {
+        const int64_t i = base + (int64_t)r * SCAN_BLOCK + threadIdx.x;
+        const int32_t v = i < n ? in[i] : 0;
+        const int32_t pre = block_exclusive_scan(v, &s_total);
+        if (i < n) out[i] = run + pre;
+        run += s_total;
+    }
+}
+
+size_t scan_scratch_bytes(int64_t n) { return sizeof(int32_t) * 2 * (size_t)((n + SCAN_TILE - 1) / SCAN_TILE); }
+
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, int32_t *scratch,
+                        hipStream_t s) {
     if (n <= 0) {
         if (total) HIP_CHECK(hipMemsetAsync(total, 0, sizeof(int32_t), s));
         return;
     }
-    hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(SCAN_BLOCK), 0, s, in, out, n, total);
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles <= 8 || scratch == nullptr) {
+        hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(SCAN_BLOCK), 0, s, in, out, n, total);
+        LAUNCH_CHECK();
+        return;
+    }
+    int32_t *sums = scratch, *offs = scratch + tiles;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, in, n, sums);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(SCAN_BLOCK), 0, s, sums, offs, tiles, total);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, in, out, n, offs);
     LAUNCH_CHECK();
 }
 
@@ -194,7 +242,7 @@ void radix_sort_pairs_u32(uint32_t *keys, uint32_t *vals, uint32_t *tmp_keys, ui
     for (int shift = 0; shift < key_bits; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_BLOCK), 0, s, ka, n, shift, hist, nblocks);
         LAUNCH_CHECK();
-        exclusive_scan_i32(hist, hist, (int64_t)256 * nblocks, nullptr, s);
+        exclusive_scan_i32(hist, hist, (int64_t)256 * nblocks, nullptr, nullptr, s);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_BLOCK), 0, s, ka, va, kb, vb, n, shift, hist,
                            nblocks);
         LAUNCH_CHECK();

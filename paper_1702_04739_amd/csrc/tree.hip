@@ -493,7 +493,7 @@ struct SubPlan {
     int32_t k;
     int32_t *anc0, *anc1, *dist0, *dist1;
     uint32_t *okey, *oval, *ckey, *cval, *tk, *tv;
-    int32_t *nchild, *koff, *slot, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp, *lab_tmp;
+    int32_t *nchild, *koff, *slot, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp, *lab_tmp, *scan_scratch;
     double2 *cpw;
     double *phi, *om0, *p0, *Nvals, *num, *den, *cl_num_tmp, *cl_den_tmp;
     uint8_t *cut, *joined;
@@ -523,6 +523,7 @@ struct SubPlan {
         cnt = a.take<int32_t>((size_t)n * M);
         cl_size_tmp = a.take<int32_t>(k);
         lab_tmp = a.take<int32_t>(n);
+        scan_scratch = a.take<int32_t>(scan_scratch_bytes(n + 1) / sizeof(int32_t));
         phi = a.take<double>(n);
         om0 = a.take<double>(n);
         p0 = a.take<double>(n);
@@ -630,7 +631,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     LAUNCH_CHECK();
     radix_sort_pairs_u32(P.okey, P.oval, P.tk, P.tv, n, bits_for(maxdepth), P.sort_scratch, s);
     radix_sort_pairs_u32(P.ckey, P.cval, P.tk, P.tv, n, bits_for(n), P.sort_scratch, s);
-    exclusive_scan_i32(P.nchild, P.koff, n + 1, nullptr, s);
+    exclusive_scan_i32(P.nchild, P.koff, n + 1, nullptr, P.scan_scratch, s);
     hipLaunchKernelGGL(k_level_starts, dim3(gn), dim3(256), 0, s, P.okey, n, maxdepth, P.level_start);
     LAUNCH_CHECK();
     const int32_t *order = reinterpret_cast<const int32_t *>(P.oval);
@@ -691,7 +692,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
         launch_levels<1, true>(A, ls, maxdepth, s);
         hipLaunchKernelGGL(k_cut_in_xorder, dim3(gn), dim3(256), 0, s, order, P.cut, n, P.cf);
         LAUNCH_CHECK();
-        exclusive_scan_i32(P.cf, P.rank, n, nullptr, s);
+        exclusive_scan_i32(P.cf, P.rank, n, nullptr, P.scan_scratch, s);
         hipLaunchKernelGGL(k_cluster_index, dim3(gn), dim3(256), 0, s, order, P.cut, P.rank, P.joined, parent, n, kk,
                            P.cidx, P.rep0);
         LAUNCH_CHECK();
