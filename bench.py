@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paper-prim-n", type=int, default=20000, metavar="M",
+                    help="time the paper's Prim MST against this path's MST on an M-point sample (0: skip)")
     ap.add_argument("--all-k", type=int, default=10, metavar="K",
                     help="after the timed steps, time the all-k sweep k = 2..K on the last tree (0: skip)")
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
@@ -254,6 +256,23 @@ def main():
                                    "value_ratio": value / (n / (c1 - c0)),
                                    "same_tree": bool(torch.equal(infoc["parent"], info["parent"])),
                                    "same_labels": bool(torch.equal(labc, labels)), "i_k": ikc})
+    if args.paper_prim_n > 0:
+        # the paper's own MST construction (Prim, one min-reduction per step)
+        # against this path's Boruvka MST, on a subsample of the same recipe
+        m = min(args.paper_prim_n, n)
+        Xs = torch.from_numpy(datagen.config(WORKLOAD, n=m)).cuda()
+        iso.mst(Xs, precision=args.precision, recheck="fp64")
+        torch.cuda.synchronize()
+        b0 = time.perf_counter()
+        bp, bl, _ = iso.mst(Xs, precision=args.precision, recheck="fp64")
+        torch.cuda.synchronize()
+        b1 = time.perf_counter()
+        pp, pl = iso.mst_prim(Xs)
+        torch.cuda.synchronize()
+        b2 = time.perf_counter()
+        out["paper_mst"] = {"n": m, "algorithm": "Prim from vertex 0, FP64 (Algorithm 3)", "prim_ms": (b2 - b1) * 1e3,
+                            "boruvka_ms": (b1 - b0) * 1e3, "boruvka_screen": args.precision, "recheck": "fp64",
+                            "same_tree": bool(torch.equal(pp, bp) and torch.equal(pl, bl))}
     if args.all_k >= 2:
         # every k = 2 .. K of the last step's tree in shared passes, against
         # separate single-k calls (outside the timed region)

@@ -114,6 +114,20 @@ iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_
 iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t precision, int32_t recheck,
                    int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes, void *stream);
 
+/* The paper's own MST construction (Sec. 3.5, Algorithm 3), kept for
+ * comparison with iso_mst: Prim from vertex 0, adding per step the vertex with
+ * the lightest edge to the tree (a min-reduction over the vertices outside
+ * it) and lowering the others' keys with their FP64 distances to it.  Edges
+ * are ordered by (D^2, smaller id, larger id) with D^2 the FP64 left-to-right
+ * sum, so parent/length equal those of iso_mst with ISO_RECHECK_FP64.
+ * n - 1 sequential steps of O(n d) work each (two launches per step).
+ *   order   [n] out (nullable): vertex added at each step (order[0] = 0).
+ * Workspace: iso_mst_prim_workspace_size(n).  Errors: null X/parent/length,
+ * n < 2, d < 1, ld < d (INVALID_ARG). */
+iso_status iso_mst_prim_workspace_size(int64_t n, size_t *bytes /* host */);
+iso_status iso_mst_prim(const float *X, int64_t n, int64_t d, int64_t ld, int32_t *parent, double *length,
+                        int32_t *order, void *ws, size_t ws_bytes, void *stream);
+
 typedef struct {
     int32_t omega;         /* ISO_OMEGA_*   (default TREE)                          */
     int32_t phi;           /* ISO_PHI_*     (default EXP_DIST)                      */

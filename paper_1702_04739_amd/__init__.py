@@ -71,6 +71,30 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32"):
                             "rescanned_rows": info.rescanned_rows, "mst_weight": info.mst_weight}
 
 
+def mst_prim(points, return_order: bool = False):
+    """The paper's MST construction (Algorithm 3: Prim from vertex 0 with one
+    min-reduction per step) in exact FP64: (parent, length[, order]).  For
+    comparison with mst(); n sequential steps."""
+    torch = _torch()
+    _require_cuda(points, "points", torch.float32)
+    if points.stride(1) != 1:
+        points = points.contiguous()
+    n, d = points.shape
+    lib = _lib.load()
+    need = ctypes.c_size_t(0)
+    _lib.check(lib.iso_mst_prim_workspace_size(n, ctypes.byref(need)), "iso_mst_prim_workspace_size")
+    dev = points.device
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    length = torch.empty(n, dtype=torch.float64, device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev) if return_order else None
+    rc = lib.iso_mst_prim(ctypes.c_void_p(points.data_ptr()), n, d, points.stride(0), ctypes.c_void_p(parent.data_ptr()),
+                          ctypes.c_void_p(length.data_ptr()), ctypes.c_void_p(order.data_ptr() if order is not None else 0),
+                          ctypes.c_void_p(ws.data_ptr()), int(need.value), _stream_ptr(dev))
+    _lib.check(rc, "iso_mst_prim")
+    return (parent, length, order) if return_order else (parent, length)
+
+
 def graph_weights(points, sigma: float, phi: str = "exp", alpha: float = 0.0, omega: bool = True, potential=None):
     """Full-graph vertex weights (eq. 2.2) and potential (eq. 2.3) of the
     points: (omega0 float64[n] or None, p0 float64[n] or None).  ``potential``

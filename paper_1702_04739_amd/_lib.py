@@ -25,7 +25,8 @@ BRACKET = {"pow2": 0, "paper": 1}
 
 # Every symbol include/isoclust.h declares.
 EXPORTS = ["iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
-           "iso_subpartition_all_k", "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median", "iso_timing_enable",
+           "iso_subpartition_all_k", "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median", "iso_mst_prim_workspace_size", "iso_mst_prim",
+           "iso_timing_enable",
            "iso_timing_read", "iso_last_error", "iso_version"]
 
 
@@ -84,12 +85,14 @@ def load(build_if_missing: bool = True):
     lib.iso_backward.argtypes = [P, I64, I64, I64, P, P, I32, D, I32, D, D, P, I64, ctypes.POINTER(D),
                                  ctypes.POINTER(D), P, SZ, P]
     lib.iso_graph_weights.argtypes = [P, I64, I64, I64, D, I32, D, P, P, P]
+    lib.iso_mst_prim_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
+    lib.iso_mst_prim.argtypes = [P, I64, I64, I64, P, P, P, P, SZ, P]
     lib.iso_subpartition_all_k.argtypes = [P, P, I64, I32, I32, D, ctypes.POINTER(SubOpts), P, P,
                                            ctypes.POINTER(I32), P, SZ, P]
     lib.iso_sigma_median.argtypes = [P, P, I64, ctypes.POINTER(D), P]
     for f in ("iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
               "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median",
-              "iso_subpartition_all_k"):
+              "iso_subpartition_all_k", "iso_mst_prim_workspace_size", "iso_mst_prim"):
         getattr(lib, f).restype = ctypes.c_int32
     lib.iso_timing_enable.argtypes = [I32]
     lib.iso_timing_enable.restype = ctypes.c_int32

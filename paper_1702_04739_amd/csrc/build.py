@@ -23,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libisoclust.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "isoclust")
 
-SOURCES = ["scan_sort.hip", "mst.hip", "screen_mfma.hip", "screen_pairs.hip", "tree.hip", "backward.hip", "graph.hip"]
+SOURCES = ["scan_sort.hip", "mst.hip", "screen_mfma.hip", "screen_pairs.hip", "tree.hip", "backward.hip", "graph.hip", "prim.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
