@@ -203,3 +203,17 @@ def test_int8_rejects_other_data(iso):
     with pytest.raises(IsoError) as e:
         iso.mst(X, precision="int8")
     assert e.value.code == -1
+
+
+def test_identical_points(iso, orc):
+    """All points equal: every edge has length 0 (a valid tree, zero weight);
+    sigma = 0 is degenerate and the tree search rejects it cleanly."""
+    from paper_1702_04739_amd._lib import IsoError
+    X = np.full((300, 7), 0.25, np.float32)
+    p, l, _, _ = orc.prim_mst(X)
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision="bf16", recheck="fp64")
+    np.testing.assert_array_equal(parent.cpu().numpy(), p)
+    assert info["mst_weight"] == 0.0
+    with pytest.raises(IsoError) as e:
+        iso.isoperimetric_subpartition(parent, length, 3)
+    assert e.value.code == -1
