@@ -232,7 +232,8 @@ def main():
         "phases": {"mst_ms_per_step": T["mst_ms"] / max(T["mst_calls"], 1),
                    "sub_ms_per_step": T["sub_ms"] / max(T["sub_calls"], 1),
                    "screen_ms_per_step": T["screen_ms"] / args.steps,
-                   "rounds": info["mst"]["rounds"], "candidates": info["mst"]["candidates"],
+                   "rounds": info["mst"]["rounds"], "list_rounds": info["mst"]["list_rounds"],
+                   "candidates": info["mst"]["candidates"],
                    "rescanned_rows": info["mst"]["rescanned_rows"], "bisection_iters": info["sub"]["iters"],
                    "passes": info["sub"]["passes"], "max_depth": info["sub"]["max_depth"],
                    "i_k": ik, "mst_weight": info["mst"]["mst_weight"]},

@@ -89,7 +89,8 @@ typedef int32_t iso_status;
 
 typedef struct {
     int32_t rounds;          /* Boruvka rounds                                   */
-    int32_t reserved0;
+    int32_t list_rounds;     /* rounds decided by the neighbour lists of the
+                                second round's screen instead of a full screen  */
     int64_t candidates;      /* candidate pairs re-evaluated exactly (all rounds) */
     int64_t rescanned_rows;  /* rows whose candidate list overflowed and were
                                 re-evaluated against every other point          */

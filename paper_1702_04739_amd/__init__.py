@@ -67,7 +67,7 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32"):
                      ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), ctypes.byref(info),
                      ctypes.c_void_p(ws.data_ptr()), int(need.value), _stream_ptr(dev))
     _lib.check(rc, "iso_mst")
-    return parent, length, {"rounds": info.rounds, "candidates": info.candidates,
+    return parent, length, {"rounds": info.rounds, "list_rounds": info.list_rounds, "candidates": info.candidates,
                             "rescanned_rows": info.rescanned_rows, "mst_weight": info.mst_weight}
 
 

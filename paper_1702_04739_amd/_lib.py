@@ -37,7 +37,7 @@ class IsoError(RuntimeError):
 
 
 class MstInfo(ctypes.Structure):
-    _fields_ = [("rounds", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("candidates", ctypes.c_int64),
+    _fields_ = [("rounds", ctypes.c_int32), ("list_rounds", ctypes.c_int32), ("candidates", ctypes.c_int64),
                 ("rescanned_rows", ctypes.c_int64), ("mst_weight", ctypes.c_double)]
 
 

@@ -47,6 +47,7 @@ enum Counter : int {
     C_NOEDGE = 4,       // a component without an outgoing edge (internal error)
     C_SEEN = 5,         // vertices reached by the rooting BFS
     C_GATHER = 6,       // rows queued for the gathered pass this round
+    C_FORCE = 7,        // rows the neighbour lists leave undecided this round
     C_CAND = 8,         // candidates re-evaluated (int64 at [8..9])
     C_RESCAN = 10,      // rows rescanned (int64 at [10..11])
     C_SUMSQ = 12,       // sum over components of size^2 (int64 at [12..13], timing only)
@@ -412,7 +413,7 @@ __device__ inline bool row_threshold(const float *__restrict__ best, const float
 }
 
 // One wave per row: exact recheck of the sweep's candidates.  Rows whose
-// list overflowed are queued for the gathered pass.
+// list overflowed, and rows marked SCR_FORCE, are queued for the gathered pass.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_recheck_rows(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
                                                       const float *__restrict__ best, const float *__restrict__ Emax,
@@ -428,8 +429,10 @@ __global__ __launch_bounds__(256) void k_recheck_rows(const float *__restrict__ 
     double out_d2 = __builtin_huge_val();
     int out_j = -1, evaluated = 0;
     float thr;
-    if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
-        const int cnt = ccnt[i];
+    const int cnt = ccnt[i];
+    if (cnt == SCR_FORCE) {
+        if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
+    } else if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
         if (cnt > SCR_CAP) {
             if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
         } else {
@@ -530,6 +533,104 @@ __global__ __launch_bounds__(256) void k_rescan(const float *__restrict__ X, int
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------------ neighbour lists
+//
+// The tile-pair screen of the second round appends to each point i every
+// point j of another component with Dhat^2_ij <= tau_i = LIST_LAMBDA b_i, b_i
+// the point's first-round minimum (its nearest neighbour's Dhat^2).  Points
+// left out have Dhat^2_ij > tau_i, or >= the smallest dropped value once the
+// list was full, so t_i = min(tau_i, dropped) bounds every absent j from below:
+// D^2_ij >= t_i - E_ij >= t_i - Emax_i.  Components only merge, so a pair that
+// is absent because its points shared a component then stays irrelevant.  In a
+// later round a row is decided by its list when that lower bound exceeds the
+// recheck threshold the row's candidates are filtered with (min of
+// kappa (b + Emax) and the component bound U): every column that can still be
+// the row's or its component's lightest edge is then in the list, and the
+// row's list entries replace its screen.  Undecided rows are screened in the
+// gathered pass; when there are many, the round runs the full screen instead.
+
+constexpr float LIST_LAMBDA = 1.1f;
+
+__global__ void k_list_init(const float *__restrict__ best, int64_t n, float *__restrict__ ltau,
+                            int32_t *__restrict__ lcnt, uint32_t *__restrict__ ldrop) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b = best[i];
+    ltau[i] = b < SCR_INF ? b * LIST_LAMBDA : -1.0f;  // a point without a first-round minimum keeps no list
+    lcnt[i] = 0;
+    ldrop[i] = 0x7F800000u;
+}
+
+// One wave per row: b_i = min over the list's entries in other components of
+// their Dhat^2 (an upper bound of the row's minimum; +inf without such entries).
+__global__ __launch_bounds__(256) void k_list_best(int64_t n, const int32_t *__restrict__ comp,
+                                                   const int32_t *__restrict__ lcnt, const int32_t *__restrict__ lj,
+                                                   const float *__restrict__ lv, float *__restrict__ best) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int ci = comp[i];
+    const int cnt = min(lcnt[i], LIST_CAP);
+    uint32_t m = 0x7F800000u;
+    for (int q = lane; q < cnt; q += 64) {
+        const int32_t j = lj[i * LIST_CAP + q];
+        if (comp[j] != ci) m = min(m, __float_as_uint(lv[i * LIST_CAP + q]));
+    }
+    m = wave_min_u32(m);
+    if (lane == 0) best[i] = __uint_as_float(m);
+}
+
+// One wave per row: decide the row from its list (candidates into cj/cl as
+// the screen would leave them, ccnt > SCR_CAP on overflow) or mark it
+// SCR_FORCE for the gathered pass.
+__global__ __launch_bounds__(256) void k_list_capture(
+    int64_t n, const int32_t *__restrict__ comp, const uint32_t *__restrict__ comp_ub, const float *__restrict__ best,
+    const float *__restrict__ Emax, const float *__restrict__ rn, const float *__restrict__ re, ScreenBound bound,
+    const float *__restrict__ ltau, const int32_t *__restrict__ lcnt, const uint32_t *__restrict__ ldrop,
+    const int32_t *__restrict__ lj, const float *__restrict__ lv, float kappa, float dn, int32_t *__restrict__ ccnt,
+    int32_t *__restrict__ cj, float *__restrict__ cl, int32_t *__restrict__ counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int ci = comp[i];
+    const float b = best[i], E = Emax[i];
+    const uint32_t ubits = comp_ub[ci];
+    const float U = ubits == U32_MAX ? SCR_INF : __uint_as_float(ubits) * dn;
+    const float thr = fminf(b < SCR_INF ? (b + E) * kappa : SCR_INF, U);
+    const float t = fminf(ltau[i], __uint_as_float(ldrop[i]));
+    if (!(thr < SCR_INF) || !(lower_of(t, E) > thr)) {
+        if (lane == 0) {
+            ccnt[i] = SCR_FORCE;
+            atomicAdd(&counters[C_FORCE], 1);
+        }
+        return;
+    }
+    const int cnt = min(lcnt[i], LIST_CAP);
+    const float ri = rn[i], ei = re[i];
+    int taken = 0;
+    for (int q0 = 0; q0 < cnt; q0 += 64) {
+        const int q = q0 + lane;
+        bool keep = false;
+        int32_t j = 0;
+        float L = 0.0f;
+        if (q < cnt) {
+            j = lj[i * LIST_CAP + q];
+            if (comp[j] != ci) {
+                L = lower_of(lv[i * LIST_CAP + q], pair_bound(bound, ri, rn[j], ei, re[j]));
+                keep = L <= thr;
+            }
+        }
+        const unsigned long long bal = __ballot(keep);
+        const int pos = taken + __popcll(bal & ((1ull << lane) - 1ull));
+        if (keep && pos < SCR_CAP) {
+            cj[i * SCR_CAP + pos] = j;
+            cl[i * SCR_CAP + pos] = L;
+        }
+        taken += __popcll(bal);
+    }
+    if (lane == 0) ccnt[i] = taken > SCR_CAP ? SCR_CAP + 1 : taken;
 }
 
 // ------------------------------------------------------------------ contraction
@@ -849,6 +950,9 @@ struct MstPlan {
     uint32_t *rmax, *emax, *comp_ub;
     int32_t *comp, *ccnt, *cj, *glist, *gcnt, *gcj, *rlist, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev;
     int32_t *deg, *aoff, *cursor, *adj, *adje, *fa, *fb, *lcnt, *depth;
+    float *ltau, *lv;               // neighbour lists: thresholds, [n][LIST_CAP] values
+    int32_t *lscnt, *lj;            // entries offered, [n][LIST_CAP] partners
+    uint32_t *ldrop;                // smallest dropped value
     double *rb_d2, *elen, *wsum;
     unsigned long long *ck1, *ck2;
     int32_t *counters;
@@ -917,6 +1021,11 @@ struct MstPlan {
         keep = a.take<int32_t>(npairs);
         kpos = a.take<int32_t>(npairs + 1);
         scan_scratch = a.take<int32_t>(scan_scratch_bytes(std::max<int64_t>(npairs, n + 1)) / sizeof(int32_t));
+        ltau = a.take<float>(n);
+        lscnt = a.take<int32_t>(n);
+        ldrop = a.take<uint32_t>(n);
+        lj = a.take<int32_t>((size_t)n * LIST_CAP);
+        lv = a.take<float>((size_t)n * LIST_CAP);
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
     // they are sized for all rows (rows are gathered at most once per round).
@@ -1080,7 +1189,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.Xtile = P.Xr;
 
     int64_t ncomp = n;
-    int rounds = 0;
+    int rounds = 0, list_rounds = 0;
+    enum { LISTS_NONE, LISTS_BUILDING, LISTS_READY, LISTS_OFF } lists = LISTS_NONE;
     while (ncomp > 1) {
         ++rounds;
         ISO_REQUIRE(rounds <= 64, ISO_ERR_INTERNAL, "Boruvka did not converge");
@@ -1091,57 +1201,104 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(1024), 0, s, P.flag, ncomp, P.counters);
             LAUNCH_CHECK();
         }
-        // Tile order and tile pairs of this round: once components average at
-        // least a tile, the points are ordered by component and tile pairs
-        // lying inside one component are dropped (until then every tile pair
-        // holds points of several components, and the order stays the identity).
-        const int2 *pairs_use = P.pairs;
-        int64_t ndiag = P.nt, noff = P.npairs - P.nt;
-        if (rounds > 1 && ncomp * pair_tile() <= n) {
-            int kb = 1;
-            while ((int64_t(1) << kb) < ncomp) ++kb;
-            hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.pkeys, P.perm);
+        // From the third round on, rows are first decided by their neighbour
+        // lists; the round screens only when too many rows stay undecided.
+        bool list_round = false;
+        if (lists == LISTS_READY) {
+            hipLaunchKernelGGL(k_list_best, dim3(grid_for(n, 4)), dim3(256), 0, s, n, P.comp, P.lscnt, P.lj, P.lv,
+                               P.best);
             LAUNCH_CHECK();
-            radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, kb, P.psort, s);
-            {
-                const size_t esz = rep_bytes(rep);
-                const int64_t row_u4 = (int64_t)(P.d_pad * esz / 16);
-                const unsigned g = std::min<unsigned>(grid_for(P.n_pad, 4), 8u * (unsigned)device_cus());
-                hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr), P.perm,
-                                   P.n_pad, row_u4, static_cast<uint4 *>(P.Xq));
-                LAUNCH_CHECK();
-                SA.Xtile = P.Xq;
-            }
-            hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(P.nt, 256)), dim3(256), 0, s, P.perm, P.comp, n, P.nt,
-                               pair_tile(), P.tlo, P.thi);
+            fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
+            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,
+                               P.comp_ub);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.tlo,
-                               P.thi, P.keep);
+            fill<int32_t>(P.counters + C_FORCE, 0, 1, s);
+            hipLaunchKernelGGL(k_list_capture, dim3(grid_for(n, 4)), dim3(256), 0, s, n, P.comp, P.comp_ub, P.best,
+                               P.Emax, P.rn, P.re, bound, P.ltau, P.lscnt, P.ldrop, P.lj, P.lv, kappa, dn, P.ccnt, P.cj,
+                               P.cl, P.counters);
             LAUNCH_CHECK();
-            exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, P.scan_scratch, s);
-            hipLaunchKernelGGL(k_pair_scatter, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs,
-                               P.keep, P.kpos, P.pairs_r);
-            LAUNCH_CHECK();
-            int32_t hk[2] = {0, 0};
-            HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.nt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipMemcpyAsync(&hk[1], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            int32_t h_force = 0;
+            HIP_CHECK(hipMemcpyAsync(&h_force, P.counters + C_FORCE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
-            ISO_REQUIRE(hk[0] >= 0 && hk[0] <= hk[1] && hk[1] <= P.npairs, ISO_ERR_INTERNAL, "tile-pair compaction");
-            pairs_use = P.pairs_r;
-            ndiag = hk[0];
-            noff = hk[1] - hk[0];
+            // an undecided row costs a row sweep over all points, a screen
+            // round about half of one per row: lists pay below ~1/6 undecided
+            if ((double)h_force <= 0.15 * (double)n) {
+                list_round = true;
+                ++list_rounds;
+            } else {
+                lists = LISTS_OFF;  // components only grow: later rounds would fare worse
+            }
         }
-        fill<uint32_t>(reinterpret_cast<uint32_t *>(P.best), 0x7F800000u, n, s);  // +inf
-        fill<int32_t>(P.ccnt, 0, n, s);
-        SA.rows = nullptr;
-        SA.nrows = 0;
-        scr.start(s);
-        launch_screen_pairs(SA, pairs_use, ndiag, noff, s);
-        scr.stop(s);
-        fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-        hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,
-                           P.comp_ub);
-        LAUNCH_CHECK();
+        if (!list_round) {
+            // Tile order and tile pairs of this round: once components average at
+            // least a tile, the points are ordered by component and tile pairs
+            // lying inside one component are dropped (until then every tile pair
+            // holds points of several components, and the order stays the identity).
+            const int2 *pairs_use = P.pairs;
+            int64_t ndiag = P.nt, noff = P.npairs - P.nt;
+            if (rounds > 1 && ncomp * pair_tile() <= n) {
+                int kb = 1;
+                while ((int64_t(1) << kb) < ncomp) ++kb;
+                hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.pkeys, P.perm);
+                LAUNCH_CHECK();
+                radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, kb, P.psort, s);
+                {
+                    const size_t esz = rep_bytes(rep);
+                    const int64_t row_u4 = (int64_t)(P.d_pad * esz / 16);
+                    const unsigned g = std::min<unsigned>(grid_for(P.n_pad, 4), 8u * (unsigned)device_cus());
+                    hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr), P.perm,
+                                       P.n_pad, row_u4, static_cast<uint4 *>(P.Xq));
+                    LAUNCH_CHECK();
+                    SA.Xtile = P.Xq;
+                }
+                hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(P.nt, 256)), dim3(256), 0, s, P.perm, P.comp, n, P.nt,
+                                   pair_tile(), P.tlo, P.thi);
+                LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.tlo,
+                                   P.thi, P.keep);
+                LAUNCH_CHECK();
+                exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, P.scan_scratch, s);
+                hipLaunchKernelGGL(k_pair_scatter, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs,
+                                   P.keep, P.kpos, P.pairs_r);
+                LAUNCH_CHECK();
+                int32_t hk[2] = {0, 0};
+                HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.nt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipMemcpyAsync(&hk[1], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+                ISO_REQUIRE(hk[0] >= 0 && hk[0] <= hk[1] && hk[1] <= P.npairs, ISO_ERR_INTERNAL, "tile-pair compaction");
+                pairs_use = P.pairs_r;
+                ndiag = hk[0];
+                noff = hk[1] - hk[0];
+            }
+            if (lists == LISTS_NONE && rounds == 2) {
+                // the second round's screen builds the lists from the first
+                // round's minima (still in best)
+                hipLaunchKernelGGL(k_list_init, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, n, P.ltau, P.lscnt,
+                                   P.ldrop);
+                LAUNCH_CHECK();
+                SA.ltau = P.ltau;
+                SA.lcnt = P.lscnt;
+                SA.ldrop = P.ldrop;
+                SA.lj = P.lj;
+                SA.lv = P.lv;
+                lists = LISTS_BUILDING;
+            }
+            fill<uint32_t>(reinterpret_cast<uint32_t *>(P.best), 0x7F800000u, n, s);  // +inf
+            fill<int32_t>(P.ccnt, 0, n, s);
+            SA.rows = nullptr;
+            SA.nrows = 0;
+            scr.start(s);
+            launch_screen_pairs(SA, pairs_use, ndiag, noff, s);
+            scr.stop(s);
+            if (lists == LISTS_BUILDING) {
+                SA.lcnt = nullptr;
+                lists = LISTS_READY;
+            }
+            fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
+            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,
+                               P.comp_ub);
+            LAUNCH_CHECK();
+        }
         fill<int32_t>(P.counters + C_OVF, 0, 1, s);
         fill<int32_t>(P.counters + C_GATHER, 0, 1, s);
         if (f64)
@@ -1154,7 +1311,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         int32_t h_gather = 0;
         HIP_CHECK(hipMemcpyAsync(&h_gather, P.counters + C_GATHER, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        if (timed) {
+        if (timed && !list_round) {
             iso_timing &T = timing();
             T.screen_launches += 1;
             T.screen_ms += scr.elapsed_ms();
@@ -1164,6 +1321,13 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             SA.nrows = h_gather;
             fill<int32_t>(P.gcnt, 0, h_gather, s);
             screen(true);
+            if (list_round) {
+                // the gathered rows' minima are now exact: a tighter U
+                fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
+                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n,
+                                   up, P.comp_ub);
+                LAUNCH_CHECK();
+            }
             if (f64)
                 hipLaunchKernelGGL(k_recheck_gather<true>, dim3(grid_for(h_gather, 4)), dim3(256), 0, s, X, d, ld,
                                    P.best, P.Emax, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa, dn,
@@ -1209,7 +1373,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         ISO_REQUIRE(h[C_NOEDGE] == 0, ISO_ERR_INTERNAL, "a component found no outgoing edge in round %d", rounds);
         ISO_REQUIRE(h[C_NCOMP] >= 1 && h[C_NCOMP] < ncomp, ISO_ERR_INTERNAL,
                     "Boruvka round %d did not contract (%lld -> %d components)", rounds, (long long)ncomp, h[C_NCOMP]);
-        if (timed) {
+        if (timed && !list_round) {
             unsigned long long sumsq = 0;
             memcpy(&sumsq, &h[C_SUMSQ], sizeof(sumsq));
             iso_timing &T = timing();
@@ -1287,7 +1451,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         HIP_CHECK(hipMemcpyAsync(&info->mst_weight, P.wsum, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         info->rounds = rounds;
-        info->reserved0 = 0;
+        info->list_rounds = list_rounds;
         info->candidates = cand;
         info->rescanned_rows = resc;
     }

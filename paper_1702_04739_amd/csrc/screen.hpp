@@ -35,6 +35,8 @@ constexpr int SCR_ROWS = 128;    // rows per workgroup
 constexpr int SCR_COLS = 128;    // columns per tile
 constexpr int SCR_CAP = 32;      // candidate slots per row in the sweep (LDS)
 constexpr int SCR_CAP2 = 512;    // candidate slots per row in the gathered pass (global)
+constexpr int SCR_FORCE = SCR_CAP + 2;  // ccnt marker: the row must be screened in the gathered pass
+constexpr int LIST_CAP = 128;    // neighbour-list slots per point
 constexpr float SCR_INF = __builtin_huge_valf();
 constexpr float THR_UP = 1.0f + 1.0f / 1048576.0f;  // covers the rounding of a sum of two nonnegative terms
 
@@ -79,6 +81,14 @@ struct ScreenArgs {
     int32_t *ccnt;           // [n] candidates (> SCR_CAP = overflow)
     int32_t *cj;             // [n * SCR_CAP]
     float *cl;               // [n * SCR_CAP]
+    // neighbour lists (tile-pair screen; lcnt == nullptr: none are built):
+    // every pair with Dhat^2 <= ltau of one of its points is appended to that
+    // point's list; past LIST_CAP entries the smallest dropped value is kept
+    const float *ltau;       // [n] capture threshold
+    int32_t *lcnt;           // [n] entries offered (zero on entry)
+    uint32_t *ldrop;         // [n] smallest dropped Dhat^2 as bits (+inf on entry)
+    int32_t *lj;             // [n * LIST_CAP]
+    float *lv;               // [n * LIST_CAP] Dhat^2 of the entry
 };
 
 struct ScreenLDS {
@@ -270,8 +280,10 @@ __device__ __forceinline__ void screen_finish(ScreenLDS &S, const ScreenArgs &A,
 
 // Row-sweep screen (screen_mfma.hip): every workgroup owns SCR_ROWS rows and
 // sweeps a range of columns; used for the gathered second pass, where the
-// rows' final minima fix the thresholds, so the columns are split over
-// workgroups (gcnt must be zero on entry).
+// columns are split over workgroups (gcnt must be zero on entry).  best[] of a
+// gathered row enters as an upper bound of its minimum (the exact minimum
+// after a full screen) and leaves as the minimum: the column blocks merge
+// their running minima into it after every tile and continue from it.
 void launch_screen_rows(const ScreenArgs &A, bool gather, hipStream_t s);
 
 // Symmetric tile-pair screen (screen_pairs.hip): best[] must hold +inf and

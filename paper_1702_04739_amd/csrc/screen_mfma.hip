@@ -265,6 +265,22 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
             screen_row_min(S, rl[ib], m);
         }
         __syncthreads();
+        if (GATHER) {
+            // the column blocks of a row share its running minimum through
+            // best[] (a row may enter with only an upper bound of it)
+            for (int q = tid; q < SCR_ROWS; q += 256) {
+                const int64_t slot = i0 + q;
+                if (slot >= A.nrows) continue;
+                const int64_t i = A.rows[slot];
+                const uint32_t g = reinterpret_cast<const volatile uint32_t *>(A.best)[i];
+                const uint32_t m = S.rowbest[q];
+                if (m < g)
+                    atomicMin(reinterpret_cast<uint32_t *>(A.best) + i, m);
+                else
+                    S.rowbest[q] = g;
+            }
+            __syncthreads();
+        }
         // phase B: capture
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) {

@@ -12,7 +12,9 @@
 // point's global candidate list (screen.hpp gives the bound).  Lists are
 // append-only: an entry stays even when a later minimum rules it out (the
 // recheck filters it), and a point whose list overflows is re-screened by the
-// row-sweep kernel starting from its final minimum.
+// row-sweep kernel starting from its final minimum.  With neighbour lists
+// requested (A.lcnt set), every element at or below a point's list threshold
+// is also appended to that point's neighbour list.
 //
 // One workgroup (4 waves) screens one half of a tile pair: all PT rows of I
 // against PH = 128 columns of J.  Its LDS footprint (three 24 KB stages of the
@@ -105,8 +107,9 @@ struct PairLDS {
     float rE[PT], cE[PH];  // Emax
     float csq[PH];         // s of the columns
     int32_t ccomp[PH];     // component of the columns
-    int32_t rhot[PT];      // row's tile minimum is within its capture margin
+    int32_t rhot[PT];      // bit 0: row's tile minimum is within its capture margin; bit 1: within its list threshold
     uint32_t chot[PH / 32];
+    uint32_t clst[PH / 32];  // column's tile minimum is within its list threshold
     int32_t rid[PT], cid[PH];  // point ids of the rows and columns
     int32_t csqi[PH];          // INT8: exact integer squared norms of the columns
 };
@@ -131,7 +134,19 @@ __device__ __forceinline__ uint32_t min_halves(uint32_t v) {
     return min(v, min((uint32_t)r[0], (uint32_t)r[1]));
 }
 
-template <int REP, bool DIAG>
+// Appends (other, v) to point p's neighbour list, or lowers its smallest
+// dropped value once the list is full.
+__device__ __forceinline__ void list_push(const ScreenArgs &A, int64_t p, int32_t other, float v) {
+    const int pos = atomicAdd(&A.lcnt[p], 1);
+    if (pos < LIST_CAP) {
+        A.lj[p * LIST_CAP + pos] = other;
+        A.lv[p * LIST_CAP + pos] = v;
+    } else {
+        atomicMin(&A.ldrop[p], __float_as_uint(v));
+    }
+}
+
+template <int REP, bool DIAG, bool LIST>
 __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
                                                             int64_t per_xcd, int64_t nitems) {
     using P = PPrec<REP>;
@@ -385,7 +400,10 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             if ((lane >> 5) == 0 && mm < INF_BITS) atomicMin(&S.rmin[RW * wi + 32 * ib + (lane & 31)], mm);
         }
     }
-    if (tid < PH / 32) S.chot[tid] = 0u;
+    if (tid < PH / 32) {
+        S.chot[tid] = 0u;
+        S.clst[tid] = 0u;
+    }
     __syncthreads();
 
     // ---- epilogue 2: merge into the global minima (no-return atomics, only
@@ -405,12 +423,14 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const float cur = p < A.n ? __uint_as_float(min(old, m)) : SCR_INF;
         const float E = is_row ? S.rE[t] : S.cE[t];
         const bool hot = p < A.n && __uint_as_float(m) <= (cur + 2.0f * E) * A.kappa;
+        const bool lst = LIST && p < A.n && __uint_as_float(m) <= A.ltau[p];
         if (is_row) {
             S.rmin[t] = __float_as_uint(cur);
-            S.rhot[t] = hot ? 1 : 0;
+            S.rhot[t] = (hot ? 1 : 0) | (lst ? 2 : 0);
         } else {
             S.cmin[t] = __float_as_uint(cur);
             if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
+            if (lst) atomicOr(&S.clst[t >> 5], 1u << (t & 31));
         }
     }
     __syncthreads();
@@ -421,7 +441,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
 #pragma unroll
     for (int ib = 0; ib < NIB; ++ib) {
         const int il = RW * wi + 32 * ib + (lane & 31);
-        if (!S.rhot[il]) continue;
+        if (!(S.rhot[il] & 1)) continue;
         const int64_t i = S.rid[il];
         const float Ei = S.rE[il];
         const float rb_ = __uint_as_float(S.rmin[il]);
@@ -479,6 +499,47 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             }
         }
     }
+
+    // ---- epilogue 4: neighbour lists (rows, then columns, whose tile minimum
+    // reaches their list threshold)
+    if constexpr (LIST) {
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib) {
+            const int il = RW * wi + 32 * ib + (lane & 31);
+            if (!(S.rhot[il] & 2)) continue;
+            const int64_t i = S.rid[il];
+            const float tau = A.ltau[i];
+#pragma unroll
+            for (int jb = 0; jb < NJB; ++jb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const float v = acc[ib][jb][q];
+                    if (!(v <= tau)) continue;
+                    const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    list_push(A, i, S.cid[jl], v);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+        }
+#pragma unroll
+        for (int jb = 0; jb < NJB; ++jb) {
+            const uint32_t hw = S.clst[(CW * wj) / 32 + jb];
+            if (!hw) continue;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                if (!((hw >> jc) & 1u)) continue;
+                const int64_t j = S.cid[CW * wj + 32 * jb + jc];
+                const float tau = A.ltau[j];
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib) {
+                    const float v = acc[ib][jb][q];
+                    if (!(v <= tau)) continue;
+                    list_push(A, j, S.rid[RW * wi + 32 * ib + (lane & 31)], v);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -509,16 +570,25 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t
     ISO_REQUIRE(A.perm != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without a tile order");
     const dim3 block(64 * NW);
     auto grid = [](int64_t per_xcd) { return dim3((unsigned)(8 * per_xcd)); };
+    const bool list = A.lcnt != nullptr;
     // diagonal tile pairs (only i < j counted), two halves each ...
     if (ndiag > 0) {
         const int64_t items = 2 * ndiag, per_xcd = (items + 7) / 8;
-        hipLaunchKernelGGL((k_screen_pairs<REP, true>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
+        if (list)
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, true>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
+        else
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, false>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
         LAUNCH_CHECK();
     }
     // ... then the others
     if (noff > 0) {
         const int64_t items = 2 * noff, per_xcd = (items + 7) / 8;
-        hipLaunchKernelGGL((k_screen_pairs<REP, false>), grid(per_xcd), block, 0, s, A, pairs + ndiag, per_xcd, items);
+        if (list)
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, true>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+                               per_xcd, items);
+        else
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, false>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+                               per_xcd, items);
         LAUNCH_CHECK();
     }
 }

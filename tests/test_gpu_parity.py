@@ -217,3 +217,30 @@ def test_identical_points(iso, orc):
     with pytest.raises(IsoError) as e:
         iso.isoperimetric_subpartition(parent, length, 3)
     assert e.value.code == -1
+
+
+LIST_CASES = {
+    # 8-bit image-like rows (values q/256): the BF16 and INT8 screens are exact
+    # there, so the second round's neighbour lists decide the later rounds
+    "c3-n4000-d784": lambda: datagen.config(3, n=4000),
+    "c3-n2600-d784-seed9": lambda: datagen.config(3, n=2600, seed=9),
+}
+
+
+@pytest.mark.parametrize("precision", ["bf16", "int8", "fp32"])
+@pytest.mark.parametrize("name", list(LIST_CASES))
+def test_neighbour_list_rounds_match_oracle(iso, orc, name, precision):
+    """Rounds decided by the neighbour lists give the oracle's tree (FP64
+    recheck: identical edges, lengths to 1e-12), and the lists are used."""
+    if name not in _cache:
+        X = LIST_CASES[name]()
+        p, l, _, _ = orc.prim_mst(X)
+        _cache[name] = (X, p, l)
+    X, op, ol = _cache[name]
+    H.log("list rounds %s %s" % (name, precision))
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64")
+    np.testing.assert_array_equal(parent.cpu().numpy(), op)
+    np.testing.assert_allclose(length.cpu().numpy(), ol, rtol=1e-12, atol=0)
+    assert info["rounds"] >= 3
+    if precision != "fp32":
+        assert info["list_rounds"] >= 1, info
