@@ -112,7 +112,12 @@ struct PairLDS {
     uint32_t clst[PH / 32];  // column's tile minimum is within its list threshold
     int32_t rid[PT], cid[PH];  // point ids of the rows and columns
     int32_t csqi[PH];          // INT8: exact integer squared norms of the columns
+    int32_t nlist;             // neighbour-list entries staged by this work item
 };
+
+// Staged neighbour-list entries: after the K loop the first staging buffer
+// holds up to LIST_STAGE (point, partner, Dhat^2) triples.
+constexpr int LIST_STAGE = SROWS * 4 * 16 / 12;
 
 constexpr uint32_t INF_BITS = 0x7F800000u;  // +inf; every screen value is a nonnegative float or +inf
 
@@ -136,7 +141,7 @@ __device__ __forceinline__ uint32_t min_halves(uint32_t v) {
 
 // Appends (other, v) to point p's neighbour list, or lowers its smallest
 // dropped value once the list is full.
-__device__ __forceinline__ void list_push(const ScreenArgs &A, int64_t p, int32_t other, float v) {
+__device__ __forceinline__ void list_push_global(const ScreenArgs &A, int64_t p, int32_t other, float v) {
     const int pos = atomicAdd(&A.lcnt[p], 1);
     if (pos < LIST_CAP) {
         A.lj[p * LIST_CAP + pos] = other;
@@ -404,6 +409,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         S.chot[tid] = 0u;
         S.clst[tid] = 0u;
     }
+    if (tid == 0) S.nlist = 0;
     __syncthreads();
 
     // ---- epilogue 2: merge into the global minima (no-return atomics, only
@@ -450,8 +456,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const float ri = A.rn[i], ei = A.re[i];
 #pragma unroll
         for (int jb = 0; jb < NJB; ++jb)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
+#pragma unroll 1
+            for (int q = 0; q < 16; ++q) {  // rolled (uniform q: indexed register reads) to keep the code small
                 const float v = acc[ib][jb][q];
                 if (!(v <= r_cheap)) continue;
                 const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
@@ -463,7 +469,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                     A.cj[i * SCR_CAP + pos] = (int32_t)j;
                     A.cl[i * SCR_CAP + pos] = L;
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
     }
     // columns: this wave's CW columns are bits [CW wj, +CW) of the hot set
@@ -471,7 +476,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     for (int jb = 0; jb < NJB; ++jb) {
         const uint32_t hw = S.chot[(CW * wj) / 32 + jb];
         if (!hw) continue;
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < 16; ++q) {
             const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);  // column within the 32-block
             if (!((hw >> jc) & 1u)) continue;
@@ -495,14 +500,29 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                     A.cj[j * SCR_CAP + pos] = (int32_t)i;
                     A.cl[j * SCR_CAP + pos] = L;
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
 
     // ---- epilogue 4: neighbour lists (rows, then columns, whose tile minimum
-    // reaches their list threshold)
+    // reaches their list threshold).  Entries are staged in LDS (the staging
+    // buffers are idle after the K loop and the barrier before epilogue 2) and
+    // then appended by all threads at once, so the latency of the returning
+    // global atomics is paid once per work item.
     if constexpr (LIST) {
+        int32_t *lp = reinterpret_cast<int32_t *>(stage0);
+        int32_t *lo = lp + LIST_STAGE;
+        float *lvv = reinterpret_cast<float *>(lo + LIST_STAGE);
+        auto stage = [&](int64_t p, int32_t other, float v) {
+            const int pos = atomicAdd(&S.nlist, 1);
+            if (pos < LIST_STAGE) {
+                lp[pos] = (int32_t)p;
+                lo[pos] = other;
+                lvv[pos] = v;
+            } else {
+                list_push_global(A, p, other, v);
+            }
+        };
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib) {
             const int il = RW * wi + 32 * ib + (lane & 31);
@@ -511,20 +531,19 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const float tau = A.ltau[i];
 #pragma unroll
             for (int jb = 0; jb < NJB; ++jb)
-#pragma unroll
+#pragma unroll 1
                 for (int q = 0; q < 16; ++q) {
                     const float v = acc[ib][jb][q];
                     if (!(v <= tau)) continue;
                     const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    list_push(A, i, S.cid[jl], v);
-                    __builtin_amdgcn_sched_barrier(0);
+                    stage(i, S.cid[jl], v);
                 }
         }
 #pragma unroll
         for (int jb = 0; jb < NJB; ++jb) {
             const uint32_t hw = S.clst[(CW * wj) / 32 + jb];
             if (!hw) continue;
-#pragma unroll
+#pragma unroll 1
             for (int q = 0; q < 16; ++q) {
                 const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
                 if (!((hw >> jc) & 1u)) continue;
@@ -534,11 +553,14 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                 for (int ib = 0; ib < NIB; ++ib) {
                     const float v = acc[ib][jb][q];
                     if (!(v <= tau)) continue;
-                    list_push(A, j, S.rid[RW * wi + 32 * ib + (lane & 31)], v);
-                    __builtin_amdgcn_sched_barrier(0);
+                    stage(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v);
                 }
             }
         }
+        __syncthreads();
+        const int cnt = min(S.nlist, LIST_STAGE);
+#pragma unroll 1
+        for (int e = tid; e < cnt; e += 64 * NW) list_push_global(A, lp[e], lo[e], lvv[e]);
     }
 }
 
