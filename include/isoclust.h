@@ -75,6 +75,10 @@ typedef int32_t iso_status;
  *         rounded separately (parity mode). */
 #define ISO_RECHECK_FP32 0
 #define ISO_RECHECK_FP64 1
+/* Options of iso_mst, OR-ed into `recheck` (the tree is the same with any of
+ * them; they select which rounds may skip the full screen). */
+#define ISO_MST_NO_LISTS 0x100 /* no neighbour lists from the second round    */
+#define ISO_MST_NO_FINAL 0x200 /* no final round joining <= 64 components    */
 
 /* Vertex weight omega (eq. 2.2) and flow phi (eq. 2.1) readings. */
 #define ISO_OMEGA_TREE 0   /* omega(v) = sum of phi over v's tree edges         */
@@ -95,6 +99,9 @@ typedef struct {
     int64_t rescanned_rows;  /* rows whose candidate list overflowed and were
                                 re-evaluated against every other point          */
     double mst_weight;       /* sum of the n-1 FP64 edge lengths                 */
+    int32_t final_components;/* components joined at once by the final round
+                                (0: the last round was a plain round)           */
+    int32_t reserved1;
 } iso_mst_info;
 
 /* Device bytes iso_mst needs as workspace for n points in d dimensions. */

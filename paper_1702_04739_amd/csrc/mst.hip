@@ -633,6 +633,133 @@ __global__ __launch_bounds__(256) void k_list_capture(
     if (lane == 0) ccnt[i] = taken > SCR_CAP ? SCR_CAP + 1 : taken;
 }
 
+// ------------------------------------------------------------------ final round
+//
+// Once at most FR_KC components remain, one screen gives every point its
+// minimum into every other component (tiles hold single components, the
+// order padding each component to whole tiles), and the exact recheck of its
+// candidates gives, for every pair of components, their lightest edge under
+// the total order (D^2, smaller id, larger id).  The tree of the components
+// under these edges (Kruskal on at most FR_KC nodes) completes the MST: with
+// a total order the MST of the whole graph is the forest found so far plus
+// the MST of the graph contracted along it, where parallel edges between two
+// components reduce to the lightest.
+
+// Points of the component-sorted order into their padded positions: the
+// component c occupies [pstart[c], pstart[c] + |c|) of the tile order, its
+// points in sorted[sstart[c] ..).
+__global__ void k_fr_perm(const int32_t *__restrict__ sorted, const int32_t *__restrict__ comp, int64_t n,
+                          const int32_t *__restrict__ pstart, const int32_t *__restrict__ sstart,
+                          int32_t *__restrict__ permF) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int32_t id = sorted[q];
+    const int c = comp[id];
+    permF[pstart[c] + (q - sstart[c])] = id;
+}
+
+// One wave per row: exact values of the row's candidates that can still be
+// its lightest edge into their component and their pair of components' (the
+// screen's bound U), the row's lightest (D^2, j) per
+// other component (with i fixed the total order is (D^2, j)), and W1 = the
+// smallest D^2 per pair of components.  Rows whose candidate list overflowed
+// are counted (the round is then screened the plain way).
+template <bool F64>
+__global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                    const int32_t *__restrict__ comp, const float *__restrict__ Emax,
+                                                    const float *__restrict__ bestc, const uint32_t *__restrict__ upair,
+                                                    const int32_t *__restrict__ ccnt, const int32_t *__restrict__ gcj,
+                                                    const float *__restrict__ gcl, float kappa, float dn,
+                                                    double *__restrict__ rowd, int32_t *__restrict__ rowj,
+                                                    unsigned long long *__restrict__ W1,
+                                                    int32_t *__restrict__ counters) {
+    __shared__ unsigned long long td[4][FR_KC];
+    __shared__ int32_t tj[4][FR_KC];
+    __shared__ double dv[4][SCR_CAP2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    const bool valid = i < n;
+    const int cnt0 = valid ? ccnt[i] : 0;
+    if (valid && lane == 0 && cnt0 > SCR_CAP2) atomicAdd(&counters[C_OVF], 1);
+    const int cnt = cnt0 <= SCR_CAP2 ? cnt0 : 0;
+    const int ci = valid ? comp[i] : 0;
+    const float E = valid ? Emax[i] : 0.0f;
+    const float *xi = X + (valid ? i : 0) * ld;
+    const int32_t *js = gcj + (valid ? i : 0) * SCR_CAP2;
+    const float *ls = gcl + (valid ? i : 0) * SCR_CAP2;
+    for (int c = lane; c < FR_KC; c += 64) {
+        td[w][c] = U64_MAX;
+        tj[w][c] = 0x7FFFFFFF;
+    }
+    __syncthreads();
+    int evaluated = 0;
+    if (F64) {
+        for (int q = lane; q < cnt; q += 64) {
+            const int32_t j = js[q];
+            const int c2 = comp[j];
+            double v = __builtin_huge_val();
+            if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
+                v = d2_f64_lane(xi, X + (int64_t)j * ld, d);
+                ++evaluated;
+                atomicMin(&td[w][c2], (unsigned long long)__double_as_longlong(v));
+            }
+            dv[w][q] = v;
+        }
+    } else {
+        for (int q = 0; q < cnt; ++q) {
+            const int32_t j = js[q];
+            const int c2 = comp[j];
+            double v = __builtin_huge_val();
+            if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
+                v = (double)d2_f32_wave(xi, X + (int64_t)j * ld, d);
+                if (lane == 0) {
+                    ++evaluated;
+                    atomicMin(&td[w][c2], (unsigned long long)__double_as_longlong(v));
+                }
+            }
+            if (lane == 0) dv[w][q] = v;
+        }
+    }
+    __syncthreads();
+    for (int q = lane; q < cnt; q += 64) {
+        const double v = dv[w][q];
+        if (!(v < __builtin_huge_val())) continue;
+        const int32_t j = js[q];
+        const int c2 = comp[j];
+        if ((unsigned long long)__double_as_longlong(v) == td[w][c2]) atomicMin(&tj[w][c2], j);
+    }
+    __syncthreads();
+    if (valid) {
+        for (int c = lane; c < FR_KC; c += 64) {
+            const unsigned long long b = td[w][c];
+            rowd[i * FR_KC + c] = b == U64_MAX ? __builtin_huge_val() : __longlong_as_double((long long)b);
+            rowj[i * FR_KC + c] = b == U64_MAX ? -1 : tj[w][c];
+            if (b != U64_MAX) atomicMin(&W1[fr_pair(ci, c)], b);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) evaluated += __shfl_xor(evaluated, off, 64);
+    if (valid && lane == 0 && evaluated)
+        atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
+}
+
+// W2 = the smallest (smaller id, larger id) among the rows' records that reach
+// W1 of their pair of components.
+__global__ void k_fr_pick(const double *__restrict__ rowd, const int32_t *__restrict__ rowj,
+                          const int32_t *__restrict__ comp, int64_t n, const unsigned long long *__restrict__ W1,
+                          unsigned long long *__restrict__ W2) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n * FR_KC) return;
+    const int32_t j = rowj[g];
+    if (j < 0) return;
+    const int64_t i = g / FR_KC;
+    const int c = (int)(g % FR_KC);
+    const int pr = fr_pair(comp[i], c);
+    if ((unsigned long long)__double_as_longlong(rowd[g]) != W1[pr]) return;
+    const uint32_t lo = (uint32_t)min((int64_t)j, i), hi = (uint32_t)max((int64_t)j, i);
+    atomicMin(&W2[pr], ((unsigned long long)lo << 32) | hi);
+}
+
 // ------------------------------------------------------------------ contraction
 
 __global__ void k_comp_min1(const double *__restrict__ rb_d2, const int32_t *__restrict__ rb_j,
@@ -943,7 +1070,7 @@ struct MstPlan {
     float *pmin, *pmax, *cmin, *cmax;
     int2 *pairs, *pairs_r;          // all tile pairs (diagonal first); the pairs kept this round
     int64_t npairs, nt;
-    int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos, *scan_scratch;
+    int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos, *scan_scratch;  // pvals: the final round's sorted ids
     uint32_t *pkeys, *ptk, *ptv;
     void *psort;
     double *psum;
@@ -953,6 +1080,15 @@ struct MstPlan {
     float *ltau, *lv;               // neighbour lists: thresholds, [n][LIST_CAP] values
     int32_t *lscnt, *lj;            // entries offered, [n][LIST_CAP] partners
     uint32_t *ldrop;                // smallest dropped value
+    // final round: padded tile order, per (point, component) minima and records
+    int32_t *permF, *tcompF, *fr_pstart, *fr_sstart, *rowj;
+    int2 *pairsF;
+    int64_t ntF_cap;
+    int32_t options;                // ISO_MST_NO_LISTS / ISO_MST_NO_FINAL
+    float *bestc;
+    double *rowd;
+    unsigned long long *W1, *W2;
+    uint32_t *upair;
     double *rb_d2, *elen, *wsum;
     unsigned long long *ck1, *ck2;
     int32_t *counters;
@@ -960,7 +1096,7 @@ struct MstPlan {
     void carve(Arena &a) {
         const size_t esz = rep_bytes(precision);
         Xr = a.take<char>((size_t)n_pad * d_pad * esz);
-        Xq = a.take<char>((size_t)n_pad * d_pad * esz);
+        Xq = a.take<char>((size_t)(n_pad + FR_KC * GT) * d_pad * esz);  // room for the final round's padding
         mu = a.take<float>(d_pad);
         psum = a.take<double>((size_t)nrb * d);
         pgrid = a.take<int32_t>((size_t)nrb * d);
@@ -1026,6 +1162,17 @@ struct MstPlan {
         ldrop = a.take<uint32_t>(n);
         lj = a.take<int32_t>((size_t)n * LIST_CAP);
         lv = a.take<float>((size_t)n * LIST_CAP);
+        permF = a.take<int32_t>(n_pad + FR_KC * GT);
+        tcompF = a.take<int32_t>(ntF_cap);
+        fr_pstart = a.take<int32_t>(FR_KC);
+        fr_sstart = a.take<int32_t>(FR_KC);
+        pairsF = a.take<int2>(ntF_cap * (ntF_cap - 1) / 2);
+        bestc = a.take<float>((size_t)n * FR_KC);
+        rowd = a.take<double>((size_t)n * FR_KC);
+        rowj = a.take<int32_t>((size_t)n * FR_KC);
+        W1 = a.take<unsigned long long>(FR_KC * FR_KC);
+        W2 = a.take<unsigned long long>(FR_KC * FR_KC);
+        upair = a.take<uint32_t>(FR_KC * FR_KC);
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
     // they are sized for all rows (rows are gathered at most once per round).
@@ -1038,12 +1185,13 @@ MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
     p.d = d;
     p.ld = ld;
     p.precision = precision;
-    p.n_pad = (n + GT - 1) / GT * GT;
+    p.n_pad = (n / GT + 1) * GT;  // at least one padding row (the final round pads with it)
     const int64_t kc = 64 / (int64_t)rep_bytes(precision);  // 64-byte K chunks
     p.d_pad = (d + kc - 1) / kc * kc;
     p.nrb = (n + COL_RB - 1) / COL_RB;
     p.nt = p.n_pad / pair_tile();
     p.npairs = p.nt * (p.nt + 1) / 2;
+    p.ntF_cap = (n + pair_tile() - 1) / pair_tile() + FR_KC;
     return p;
 }
 
@@ -1189,8 +1337,148 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.Xtile = P.Xr;
 
     int64_t ncomp = n;
-    int rounds = 0, list_rounds = 0;
-    enum { LISTS_NONE, LISTS_BUILDING, LISTS_READY, LISTS_OFF } lists = LISTS_NONE;
+    int rounds = 0, list_rounds = 0, final_components = 0;
+    enum { LISTS_NONE, LISTS_BUILDING, LISTS_READY, LISTS_OFF } lists =
+        (P.options & ISO_MST_NO_LISTS) ? LISTS_OFF : LISTS_NONE;
+    bool final_off = (P.options & ISO_MST_NO_FINAL) != 0;
+
+    // The final round (at most FR_KC components left): true when it joined
+    // them all, false when a point's candidate list overflowed (the round is
+    // then screened the plain way).
+    auto final_round = [&]() -> bool {
+        const int K = (int)ncomp;
+        const size_t esz = rep_bytes(rep);
+        // component sizes -> padded tile order (host: at most FR_KC components)
+        fill<int32_t>(P.flag, 0, K, s);
+        hipLaunchKernelGGL(k_comp_sizes, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.flag);
+        LAUNCH_CHECK();
+        std::vector<int32_t> hs(K), pst(K), sst(K), tco;
+        HIP_CHECK(hipMemcpyAsync(hs.data(), P.flag, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        int64_t pos = 0, srt = 0;
+        for (int c = 0; c < K; ++c) {
+            sst[c] = (int32_t)srt;
+            pst[c] = (int32_t)pos;
+            srt += hs[c];
+            const int64_t tiles = (hs[c] + GT - 1) / GT;
+            for (int64_t t = 0; t < tiles; ++t) tco.push_back(c);
+            pos += tiles * GT;
+        }
+        const int64_t ntF = (int64_t)tco.size();
+        ISO_REQUIRE(srt == n && ntF <= P.ntF_cap, ISO_ERR_INTERNAL, "final-round tile order (%lld points, %lld tiles)",
+                    (long long)srt, (long long)ntF);
+        std::vector<int2> fpairs;
+        for (const int2 &pr : make_pair_order(ntF))
+            if (pr.x < pr.y && tco[pr.x] != tco[pr.y]) fpairs.push_back(pr);
+        HIP_CHECK(hipMemcpyAsync(P.fr_pstart, pst.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(P.fr_sstart, sst.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(P.tcompF, tco.data(), sizeof(int32_t) * ntF, hipMemcpyHostToDevice, s));
+        if (!fpairs.empty())
+            HIP_CHECK(hipMemcpyAsync(P.pairsF, fpairs.data(), sizeof(int2) * fpairs.size(), hipMemcpyHostToDevice, s));
+        // points sorted by component, then placed at their padded positions
+        // (padding positions hold the padding row n_pad - 1: +inf distances)
+        int kb = 1;
+        while ((int64_t(1) << kb) < K) ++kb;
+        // (sorted into pvals: perm keeps the plain rounds' order in case this round falls back)
+        hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.pkeys, P.pvals);
+        LAUNCH_CHECK();
+        radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.pvals), P.ptk, P.ptv, n, kb, P.psort, s);
+        fill<int32_t>(P.permF, (int32_t)(P.n_pad - 1), ntF * GT, s);
+        hipLaunchKernelGGL(k_fr_perm, dim3(grid_for(n, 256)), dim3(256), 0, s, P.pvals, P.comp, n, P.fr_pstart,
+                           P.fr_sstart, P.permF);
+        LAUNCH_CHECK();
+        {
+            const int64_t row_u4 = (int64_t)(P.d_pad * esz / 16);
+            const unsigned g = std::min<unsigned>(grid_for(ntF * GT, 4), 8u * (unsigned)device_cus());
+            hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr), P.permF,
+                               ntF * GT, row_u4, static_cast<uint4 *>(P.Xq));
+            LAUNCH_CHECK();
+        }
+        ScreenArgs FA = SA;
+        FA.perm = P.permF;
+        FA.Xtile = P.Xq;
+        FA.bestc = P.bestc;
+        FA.tcomp = P.tcompF;
+        FA.upair = P.upair;
+        FA.up = up;
+        FA.dn = dn;
+        FA.lcnt = nullptr;
+        FA.rows = nullptr;
+        FA.nrows = 0;
+        fill<uint32_t>(reinterpret_cast<uint32_t *>(P.bestc), 0x7F800000u, n * FR_KC, s);
+        fill<uint32_t>(P.upair, 0x7F800000u, FR_KC * FR_KC, s);
+        fill<int32_t>(P.ccnt, 0, n, s);
+        scr.start(s);
+        launch_screen_pairs(FA, P.pairsF, 0, (int64_t)fpairs.size(), s);
+        scr.stop(s);
+        fill<unsigned long long>(P.W1, U64_MAX, FR_KC * FR_KC, s);
+        fill<unsigned long long>(P.W2, U64_MAX, FR_KC * FR_KC, s);
+        fill<int32_t>(P.counters + C_OVF, 0, 1, s);
+        if (f64)
+            hipLaunchKernelGGL(k_fr_recheck<true>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.comp, P.Emax,
+                               P.bestc, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj, P.W1, P.counters);
+        else
+            hipLaunchKernelGGL(k_fr_recheck<false>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.comp,
+                               P.Emax, P.bestc, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj, P.W1,
+                               P.counters);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_fr_pick, dim3(grid_for(n * FR_KC, 256)), dim3(256), 0, s, P.rowd, P.rowj, P.comp, n,
+                           P.W1, P.W2);
+        LAUNCH_CHECK();
+        std::vector<unsigned long long> w1(FR_KC * FR_KC), w2(FR_KC * FR_KC);
+        int32_t h[C_COUNT];
+        HIP_CHECK(hipMemcpyAsync(w1.data(), P.W1, sizeof(unsigned long long) * w1.size(), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(w2.data(), P.W2, sizeof(unsigned long long) * w2.size(), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(h, P.counters, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (timed) {
+            unsigned long long sumsq = 0;
+            memcpy(&sumsq, &h[C_SUMSQ], sizeof(sumsq));
+            iso_timing &T = timing();
+            T.screen_launches += 1;
+            T.screen_ms += scr.elapsed_ms();
+            T.screen_pairs += 0.5 * ((double)n * (double)n - (double)sumsq);
+            T.screen_dim = (double)P.d_pad;
+        }
+        if (h[C_OVF] > 0) return false;
+        // Kruskal over the components' lightest edges, ordered by (D^2, ids)
+        struct CE {
+            unsigned long long d2, ids;
+            int a, b;
+        };
+        std::vector<CE> ce;
+        for (int a = 0; a < K; ++a)
+            for (int b = a + 1; b < K; ++b)
+                if (w2[a * FR_KC + b] != U64_MAX) ce.push_back({w1[a * FR_KC + b], w2[a * FR_KC + b], a, b});
+        std::sort(ce.begin(), ce.end(),
+                  [](const CE &x, const CE &y) { return x.d2 != y.d2 ? x.d2 < y.d2 : x.ids < y.ids; });
+        std::vector<int> uf(K);
+        for (int c = 0; c < K; ++c) uf[c] = c;
+        auto root = [&](int c) {
+            while (uf[c] != c) c = uf[c] = uf[uf[c]];
+            return c;
+        };
+        std::vector<int32_t> nu, nv;
+        for (const CE &e : ce) {
+            const int ra = root(e.a), rb = root(e.b);
+            if (ra == rb) continue;
+            uf[ra] = rb;
+            nu.push_back((int32_t)(e.ids >> 32));
+            nv.push_back((int32_t)(e.ids & 0xFFFFFFFFu));
+        }
+        ISO_REQUIRE((int)nu.size() == K - 1, ISO_ERR_INTERNAL, "final round joined %zu of %d components", nu.size() + 1,
+                    K);
+        const int32_t off = h[C_EDGES];
+        ISO_REQUIRE(off >= 0 && (int64_t)off + K - 1 <= n - 1, ISO_ERR_INTERNAL, "final round edge count");
+        HIP_CHECK(hipMemcpyAsync(P.eu + off, nu.data(), sizeof(int32_t) * nu.size(), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(P.ev + off, nv.data(), sizeof(int32_t) * nv.size(), hipMemcpyHostToDevice, s));
+        const int32_t total = off + K - 1;
+        HIP_CHECK(hipMemcpyAsync(P.counters + C_EDGES, &total, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        final_components = K;
+        return true;
+    };
+
     while (ncomp > 1) {
         ++rounds;
         ISO_REQUIRE(rounds <= 64, ISO_ERR_INTERNAL, "Boruvka did not converge");
@@ -1200,6 +1488,13 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             LAUNCH_CHECK();
             hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(1024), 0, s, P.flag, ncomp, P.counters);
             LAUNCH_CHECK();
+        }
+        if (!final_off && ncomp <= FR_KC && rounds >= 2) {
+            if (final_round()) {
+                ncomp = 1;
+                break;
+            }
+            final_off = true;  // a candidate list overflowed: this and later rounds screen the plain way
         }
         // From the third round on, rows are first decided by their neighbour
         // lists; the round screens only when too many rows stay undecided.
@@ -1452,6 +1747,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         HIP_CHECK(hipStreamSynchronize(s));
         info->rounds = rounds;
         info->list_rounds = list_rounds;
+        info->final_components = final_components;
+        info->reserved1 = 0;
         info->candidates = cand;
         info->rescanned_rows = resc;
     }
@@ -1486,11 +1783,16 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8 ||
                         precision == ISO_PREC_INT8,
                     ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
+        const int32_t options = recheck & ~0xFF;
+        recheck &= 0xFF;
         ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
                     "unknown recheck %d", recheck);
+        ISO_REQUIRE((options & ~(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL)) == 0, ISO_ERR_INVALID_ARG,
+                    "unknown options 0x%x", options);
         require_device();
         hipStream_t s = static_cast<hipStream_t>(stream);
         MstPlan P = make_plan(n, d, ld, precision);
+        P.options = options;
         const size_t need = plan_bytes(P);
         ScopedWorkspace owned;
         if (ws == nullptr) {

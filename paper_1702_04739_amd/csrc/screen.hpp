@@ -37,6 +37,7 @@ constexpr int SCR_CAP = 32;      // candidate slots per row in the sweep (LDS)
 constexpr int SCR_CAP2 = 512;    // candidate slots per row in the gathered pass (global)
 constexpr int SCR_FORCE = SCR_CAP + 2;  // ccnt marker: the row must be screened in the gathered pass
 constexpr int LIST_CAP = 128;    // neighbour-list slots per point
+constexpr int FR_KC = 64;        // final round: most components it joins at once
 constexpr float SCR_INF = __builtin_huge_valf();
 constexpr float THR_UP = 1.0f + 1.0f / 1048576.0f;  // covers the rounding of a sum of two nonnegative terms
 
@@ -89,7 +90,19 @@ struct ScreenArgs {
     uint32_t *ldrop;         // [n] smallest dropped Dhat^2 as bits (+inf on entry)
     int32_t *lj;             // [n * LIST_CAP]
     float *lv;               // [n * LIST_CAP] Dhat^2 of the entry
+    // final round (bestc != nullptr): every tile holds points of one
+    // component (tcomp), the minima are kept per (point, other component) in
+    // bestc[p * FR_KC + c], and candidates go to gcj/gcl (SCR_CAP2 per point,
+    // counted in ccnt)
+    float *bestc;
+    const int32_t *tcomp;    // [tiles] component of each tile of the order
+    uint32_t *upair;         // [FR_KC * FR_KC] (fr_pair) running bound of each pair of components' lightest
+                             // edge on the recheck scale, as float bits (+inf on entry)
+    float up, dn;            // recheck-scale factors: bound = (Dhat^2 + Emax) up; real-scale threshold = bound dn
 };
+
+// Slot of the unordered pair of components (a, b) in the final round's tables.
+__host__ __device__ inline int fr_pair(int a, int b) { return a < b ? a * FR_KC + b : b * FR_KC + a; }
 
 struct ScreenLDS {
     uint32_t rowbest[SCR_ROWS];

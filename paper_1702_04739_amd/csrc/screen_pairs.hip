@@ -14,7 +14,9 @@
 // recheck filters it), and a point whose list overflows is re-screened by the
 // row-sweep kernel starting from its final minimum.  With neighbour lists
 // requested (A.lcnt set), every element at or below a point's list threshold
-// is also appended to that point's neighbour list.
+// is also appended to that point's neighbour list.  In the final round
+// (A.bestc set) every tile holds one component and the minima and candidate
+// lists are kept per (point, other component).
 //
 // One workgroup (4 waves) screens one half of a tile pair: all PT rows of I
 // against PH = 128 columns of J.  Its LDS footprint (three 24 KB stages of the
@@ -113,11 +115,15 @@ struct PairLDS {
     int32_t rid[PT], cid[PH];  // point ids of the rows and columns
     int32_t csqi[PH];          // INT8: exact integer squared norms of the columns
     int32_t nlist;             // neighbour-list entries staged by this work item
+    int32_t ncap;              // candidates staged by this work item
+    uint32_t umin;             // final round: the item's bound of its pair of components' lightest edge
 };
 
-// Staged neighbour-list entries: after the K loop the first staging buffer
-// holds up to LIST_STAGE (point, partner, Dhat^2) triples.
+// After the K loop the first staging buffer holds up to LIST_STAGE
+// neighbour-list entries (point, partner, Dhat^2) and the second up to
+// CAP_STAGE candidates (point, partner, Dhat^2, threshold).
 constexpr int LIST_STAGE = SROWS * 4 * 16 / 12;
+constexpr int CAP_STAGE = SROWS * 4 * 16 / 16;
 
 constexpr uint32_t INF_BITS = 0x7F800000u;  // +inf; every screen value is a nonnegative float or +inf
 
@@ -151,9 +157,15 @@ __device__ __forceinline__ void list_push_global(const ScreenArgs &A, int64_t p,
     }
 }
 
-template <int REP, bool DIAG, bool LIST>
+// MODE: MODE_PLAIN, MODE_LIST (neighbour lists as well) or MODE_FINAL (minima
+// and candidates per (point, other component); no diagonal pairs).
+constexpr int MODE_PLAIN = 0, MODE_LIST = 1, MODE_FINAL = 2;
+
+template <int REP, bool DIAG, int MODE>
 __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
                                                             int64_t per_xcd, int64_t nitems) {
+    constexpr bool LIST = MODE == MODE_LIST, FINAL = MODE == MODE_FINAL;
+    static_assert(!(FINAL && DIAG), "the final round has no diagonal tile pairs");
     using P = PPrec<REP>;
     using T = typename P::T;
     __shared__ PairLDS S;
@@ -181,6 +193,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // positions in the tile order; A.perm maps them to point ids
     const int64_t I0 = (int64_t)pr.x * PT, J0 = (int64_t)pr.y * PT + half * PH;
     const int32_t *__restrict__ perm = A.perm;
+    // final round: rows' minima go to the column tile's component and back
+    const int32_t compI = FINAL ? A.tcomp[pr.x] : 0, compJ = FINAL ? A.tcomp[pr.y] : 0;
 
     // tile constants
     {
@@ -409,13 +423,23 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         S.chot[tid] = 0u;
         S.clst[tid] = 0u;
     }
-    if (tid == 0) S.nlist = 0;
+    if (tid == 0) {
+        S.nlist = 0;
+        S.ncap = 0;
+        S.umin = INF_BITS;
+    }
     __syncthreads();
 
     // ---- epilogue 2: merge into the global minima (no-return atomics, only
     // where the item lowers the current value); the merged value
     // replaces the tile minimum in LDS as the threshold base; flag the rows and
-    // columns whose tile minimum can still be captured
+    // columns whose tile minimum can still be captured.  In the final round
+    // every row and column of the item belongs to the same pair of components
+    // (compI, compJ): their merged minima also lower that pair's bound U (one
+    // atomic per item), and a row or column is hot only while its tile minimum
+    // can still reach U.
+    float upair = SCR_INF;  // final round: U on the real-D^2 scale
+    uint32_t tmin[NPRE];
 #pragma unroll
     for (int e = 0; e < NPRE; ++e) {
         const int u = tid + e * 64 * NW;
@@ -424,10 +448,21 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const int t = is_row ? u : u - PT;
         const int64_t p = is_row ? S.rid[t] : S.cid[t];
         const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
-        const uint32_t old = p < A.n ? reinterpret_cast<const volatile uint32_t *>(A.best)[p] : INF_BITS;
-        if (p < A.n && m < old) atomicMin(reinterpret_cast<uint32_t *>(A.best) + p, m);
+        uint32_t *const bp = FINAL ? reinterpret_cast<uint32_t *>(A.bestc) + p * FR_KC + (is_row ? compJ : compI)
+                                   : reinterpret_cast<uint32_t *>(A.best) + p;
+        const uint32_t old = p < A.n ? *reinterpret_cast<const volatile uint32_t *>(bp) : INF_BITS;
+        if (p < A.n && m < old) atomicMin(bp, m);
         const float cur = p < A.n ? __uint_as_float(min(old, m)) : SCR_INF;
         const float E = is_row ? S.rE[t] : S.cE[t];
+        if constexpr (FINAL) {
+            tmin[e] = m;
+            if (cur < SCR_INF) atomicMin(&S.umin, __float_as_uint((cur + E) * A.up));
+            if (is_row)
+                S.rmin[t] = __float_as_uint(cur);
+            else
+                S.cmin[t] = __float_as_uint(cur);
+            continue;
+        }
         const bool hot = p < A.n && __uint_as_float(m) <= (cur + 2.0f * E) * A.kappa;
         const bool lst = LIST && p < A.n && __uint_as_float(m) <= A.ltau[p];
         if (is_row) {
@@ -439,11 +474,70 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             if (lst) atomicOr(&S.clst[t >> 5], 1u << (t & 31));
         }
     }
+    if constexpr (FINAL) {
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t *const gp = A.upair + fr_pair(compI, compJ);
+            const uint32_t g = *reinterpret_cast<const volatile uint32_t *>(gp);
+            const uint32_t mine = S.umin;
+            if (mine < g) atomicMin(gp, mine);
+            S.umin = min(g, mine);
+        }
+        __syncthreads();
+        upair = __uint_as_float(S.umin) * A.dn;
+#pragma unroll
+        for (int e = 0; e < NPRE; ++e) {
+            const int u = tid + e * 64 * NW;
+            if (u >= PT + PH) break;
+            const bool is_row = u < PT;
+            const int t = is_row ? u : u - PT;
+            const int64_t p = is_row ? S.rid[t] : S.cid[t];
+            const float cur = __uint_as_float(is_row ? S.rmin[t] : S.cmin[t]);
+            const float E = is_row ? S.rE[t] : S.cE[t];
+            const float cheap = fminf((cur + 2.0f * E) * A.kappa, (upair + 2.0f * E) * (1.0f + 0x1p-18f));
+            const bool hot = p < A.n && __uint_as_float(tmin[e]) <= cheap;
+            if (is_row)
+                S.rhot[t] = hot ? 1 : 0;
+            else if (hot)
+                atomicOr(&S.chot[t >> 5], 1u << (t & 31));
+        }
+    }
     __syncthreads();
 
     // ---- epilogue 3: capture candidates (rows of hot rows, columns of hot
-    // columns); the norm and representation bounds are read from global memory
-    // on this rare path
+    // columns).  Elements that pass the cheap test are staged in LDS (the
+    // second staging buffer, idle since the barrier before epilogue 2) with
+    // their threshold; after the barrier below all threads finish them at
+    // once (norm bounds from global memory, bound test, append), so the
+    // latency of those loads and of the returning atomics is paid once per
+    // work item rather than once per candidate.
+    constexpr int CAP = FINAL ? SCR_CAP2 : SCR_CAP;
+    int32_t *const cjs = FINAL ? A.gcj : A.cj;
+    float *const cls = FINAL ? A.gcl : A.cl;
+    int32_t *const cp = reinterpret_cast<int32_t *>(stage1);
+    int32_t *const co = cp + CAP_STAGE;
+    float *const cv = reinterpret_cast<float *>(co + CAP_STAGE);
+    float *const ct = cv + CAP_STAGE;
+    auto commit = [&](int64_t p, int64_t o, float v, float thr) {
+        const float L = lower_of(v, pair_bound(A.bound, A.rn[p], A.rn[o], A.re[p], A.re[o]));
+        if (!(L <= thr)) return;
+        const int pos = atomicAdd(&A.ccnt[p], 1);
+        if (pos < CAP) {
+            cjs[p * CAP + pos] = (int32_t)o;
+            cls[p * CAP + pos] = L;
+        }
+    };
+    auto stage_cap = [&](int64_t p, int64_t o, float v, float thr) {
+        const int pos = atomicAdd(&S.ncap, 1);
+        if (pos < CAP_STAGE) {
+            cp[pos] = (int32_t)p;
+            co[pos] = (int32_t)o;
+            cv[pos] = v;
+            ct[pos] = thr;
+        } else {
+            commit(p, o, v, thr);
+        }
+    };
 #pragma unroll
     for (int ib = 0; ib < NIB; ++ib) {
         const int il = RW * wi + 32 * ib + (lane & 31);
@@ -451,9 +545,10 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const int64_t i = S.rid[il];
         const float Ei = S.rE[il];
         const float rb_ = __uint_as_float(S.rmin[il]);
-        const float r_cheap = (rb_ + 2.0f * Ei) * A.kappa;
-        const float r_thr = (rb_ + Ei) * A.kappa;
-        const float ri = A.rn[i], ei = A.re[i];
+        // (final round: also within reach of the pair's bound U; an element
+        // above the cheap bound has L > U: the 2^-18 covers lower_of's slack and the roundings)
+        const float r_cheap = fminf((rb_ + 2.0f * Ei) * A.kappa, (upair + 2.0f * Ei) * (1.0f + 0x1p-18f));
+        const float r_thr = fminf((rb_ + Ei) * A.kappa, upair);
 #pragma unroll
         for (int jb = 0; jb < NJB; ++jb)
 #pragma unroll 1
@@ -461,14 +556,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                 const float v = acc[ib][jb][q];
                 if (!(v <= r_cheap)) continue;
                 const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const int64_t j = S.cid[jl];
-                const float L = lower_of(v, pair_bound(A.bound, ri, A.rn[j], ei, A.re[j]));
-                if (!(L <= r_thr)) continue;
-                const int pos = atomicAdd(&A.ccnt[i], 1);
-                if (pos < SCR_CAP) {
-                    A.cj[i * SCR_CAP + pos] = (int32_t)j;
-                    A.cl[i * SCR_CAP + pos] = L;
-                }
+                stage_cap(i, S.cid[jl], v, r_thr);
             }
     }
     // columns: this wave's CW columns are bits [CW wj, +CW) of the hot set
@@ -484,31 +572,20 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const int64_t j = S.cid[jl];
             const float Ej = S.cE[jl];
             const float cb = __uint_as_float(S.cmin[jl]);
-            const float c_cheap = (cb + 2.0f * Ej) * A.kappa;
-            const float c_thr = (cb + Ej) * A.kappa;
-            const float rj = A.rn[j], ej = A.re[j];
+            const float c_cheap = fminf((cb + 2.0f * Ej) * A.kappa, (upair + 2.0f * Ej) * (1.0f + 0x1p-18f));
+            const float c_thr = fminf((cb + Ej) * A.kappa, upair);
 #pragma unroll
             for (int ib = 0; ib < NIB; ++ib) {
                 const float v = acc[ib][jb][q];
                 if (!(v <= c_cheap)) continue;
-                const int il = RW * wi + 32 * ib + (lane & 31);
-                const int64_t i = S.rid[il];
-                const float L = lower_of(v, pair_bound(A.bound, A.rn[i], rj, A.re[i], ej));
-                if (!(L <= c_thr)) continue;
-                const int pos = atomicAdd(&A.ccnt[j], 1);
-                if (pos < SCR_CAP) {
-                    A.cj[j * SCR_CAP + pos] = (int32_t)i;
-                    A.cl[j * SCR_CAP + pos] = L;
-                }
+                stage_cap(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v, c_thr);
             }
         }
     }
 
     // ---- epilogue 4: neighbour lists (rows, then columns, whose tile minimum
-    // reaches their list threshold).  Entries are staged in LDS (the staging
-    // buffers are idle after the K loop and the barrier before epilogue 2) and
-    // then appended by all threads at once, so the latency of the returning
-    // global atomics is paid once per work item.
+    // reaches their list threshold), staged in the first staging buffer and
+    // appended after the barrier like the candidates.
     if constexpr (LIST) {
         int32_t *lp = reinterpret_cast<int32_t *>(stage0);
         int32_t *lo = lp + LIST_STAGE;
@@ -557,7 +634,17 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                 }
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    {
+        const int cnt = min(S.ncap, CAP_STAGE);
+#pragma unroll 1
+        for (int e = tid; e < cnt; e += 64 * NW) commit(cp[e], co[e], cv[e], ct[e]);
+    }
+    if constexpr (LIST) {
+        const int32_t *lp = reinterpret_cast<const int32_t *>(stage0);
+        const int32_t *lo = lp + LIST_STAGE;
+        const float *lvv = reinterpret_cast<const float *>(lo + LIST_STAGE);
         const int cnt = min(S.nlist, LIST_STAGE);
 #pragma unroll 1
         for (int e = tid; e < cnt; e += 64 * NW) list_push_global(A, lp[e], lo[e], lvv[e]);
@@ -592,24 +679,30 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t
     ISO_REQUIRE(A.perm != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without a tile order");
     const dim3 block(64 * NW);
     auto grid = [](int64_t per_xcd) { return dim3((unsigned)(8 * per_xcd)); };
-    const bool list = A.lcnt != nullptr;
+    const bool list = A.lcnt != nullptr, final_round = A.bestc != nullptr;
+    ISO_REQUIRE(!(final_round && (list || ndiag > 0)), ISO_ERR_INTERNAL, "final round with lists or diagonal pairs");
     // diagonal tile pairs (only i < j counted), two halves each ...
     if (ndiag > 0) {
         const int64_t items = 2 * ndiag, per_xcd = (items + 7) / 8;
         if (list)
-            hipLaunchKernelGGL((k_screen_pairs<REP, true, true>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
+                               items);
         else
-            hipLaunchKernelGGL((k_screen_pairs<REP, true, false>), grid(per_xcd), block, 0, s, A, pairs, per_xcd, items);
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
+                               items);
         LAUNCH_CHECK();
     }
     // ... then the others
     if (noff > 0) {
         const int64_t items = 2 * noff, per_xcd = (items + 7) / 8;
-        if (list)
-            hipLaunchKernelGGL((k_screen_pairs<REP, false, true>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+        if (final_round)
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_FINAL>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+                               per_xcd, items);
+        else if (list)
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
                                per_xcd, items);
         else
-            hipLaunchKernelGGL((k_screen_pairs<REP, false, false>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
                                per_xcd, items);
         LAUNCH_CHECK();
     }

@@ -103,3 +103,21 @@ def test_no_cpu_fallback():
     import paper_1702_04739_amd as iso
     with pytest.raises(ValueError):
         iso.mst(torch.zeros(4, 2))
+
+
+def test_header_constants_match_binding():
+    """The binding's option and enum values are the header's."""
+    import re
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                            "isoclust.h")).read()
+    defs = {m.group(1): int(m.group(2), 0) for m in re.finditer(r"#define\s+(ISO_\w+)\s+\(?(-?(?:0x)?[0-9A-Fa-f]+)\)?", src)}
+    for name, v in _lib.PRECISION.items():
+        assert defs["ISO_PREC_" + name.upper()] == v
+    for name, v in _lib.RECHECK.items():
+        assert defs["ISO_RECHECK_" + name.upper()] == v
+    assert defs["ISO_MST_NO_LISTS"] == _lib.MST_NO_LISTS
+    assert defs["ISO_MST_NO_FINAL"] == _lib.MST_NO_FINAL
+    assert defs["ISO_OMEGA_FULL"] == _lib.OMEGA["full"]
+    for code, name in _lib.ERRORS.items():
+        if name in defs:
+            assert defs[name] == code

@@ -64,12 +64,19 @@ def _oracle_tree(orc, name):
     return _cache[name]
 
 
+@pytest.mark.parametrize("rounds", ["default", "plain"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_mst_fp64_recheck_identical(iso, orc, name, precision):
+def test_mst_fp64_recheck_identical(iso, orc, name, precision, rounds):
+    """Same tree as the oracle; "plain" screens every round (no neighbour
+    lists, no final round), "default" lets rounds skip the full screen."""
     X, op, ol = _oracle_tree(orc, name)
-    H.log("case %s n=%d d=%d %s screen + fp64 recheck" % (name, *X.shape, precision))
-    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64")
+    H.log("case %s n=%d d=%d %s screen + fp64 recheck, %s rounds" % (name, *X.shape, precision, rounds))
+    plain = rounds == "plain"
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64",
+                                   lists=not plain, final_round=not plain)
+    if plain:
+        assert info["list_rounds"] == 0 and info["final_components"] == 0
     gp = parent.cpu().numpy()
     gl = length.cpu().numpy()
     assert H.edge_set(gp) == H.edge_set(op)
@@ -238,9 +245,55 @@ def test_neighbour_list_rounds_match_oracle(iso, orc, name, precision):
         _cache[name] = (X, p, l)
     X, op, ol = _cache[name]
     H.log("list rounds %s %s" % (name, precision))
-    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64")
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64",
+                                   final_round=False)
     np.testing.assert_array_equal(parent.cpu().numpy(), op)
     np.testing.assert_allclose(length.cpu().numpy(), ol, rtol=1e-12, atol=0)
+    H.log("  info %s" % info)
     assert info["rounds"] >= 3
     if precision != "fp32":
         assert info["list_rounds"] >= 1, info
+
+
+def _cube_grid(side=6, dim=5, gap=3):
+    """side x side unit cubes {0,1}^dim, cube (a, b) shifted by gap (a e_1 + b e_2):
+    the first round joins each cube; between neighbouring cubes 2^(dim-1)
+    pairs tie at distance gap - 1 and every neighbouring pair of cubes ties,
+    so the final round's choices are all made by the id order."""
+    v = np.stack(np.meshgrid(*[np.arange(2)] * dim, indexing="ij"), -1).reshape(-1, dim)
+    pts = []
+    for a in range(side):
+        for b in range(side):
+            o = np.zeros(dim)
+            o[0], o[1] = gap * a, gap * b
+            pts.append(v + o)
+    return np.concatenate(pts).astype(np.float32)
+
+
+FINAL_CASES = {
+    "cubes-6x6-2^5": lambda: _cube_grid(),
+    "c3-n4000-d784": lambda: datagen.config(3, n=4000),
+    "c1-n2000-d16": lambda: datagen.config(1),
+    "c5-n3000-d128": lambda: datagen.config(5, n=3000),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "int8"])
+@pytest.mark.parametrize("name", list(FINAL_CASES))
+def test_final_round_matches_oracle(iso, orc, name, precision):
+    """The final round (all remaining components joined from their pairwise
+    lightest edges) gives the oracle's tree under the FP64 recheck."""
+    key = "final-" + name
+    if key not in _cache:
+        X = FINAL_CASES[name]()
+        p, l, _, _ = orc.prim_mst(X)
+        _cache[key] = (X, p, l)
+    X, op, ol = _cache[key]
+    if precision == "int8" and name.startswith(("c1", "c5")):
+        pytest.skip("the INT8 screen takes 8-bit data only")
+    H.log("final round %s %s" % (name, precision))
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64")
+    H.log("  info %s" % info)
+    np.testing.assert_array_equal(parent.cpu().numpy(), op)
+    np.testing.assert_allclose(length.cpu().numpy(), ol, rtol=1e-12, atol=0)
+    assert info["final_components"] >= 2, info
