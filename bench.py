@@ -91,7 +91,20 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "hbm_bytes_per_launch": fetch + write, "launches": fr,
            "copy_calibration": {"bytes": nbytes, "fetch_kib": fc, "write_kib": wc, "fetch_scale": f_scale,
-                                "write_scale": w_scale}}
+                                "write_scale": w_scale},
+           "commands": [
+               "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch_dir> -o run -- python3 "
+               "<repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-compare --all-k 0 --paper-prim-n 0 "
+               "--calibrate-copy %d --precision %s" % (copy_mib, precision),
+               "(the same with --pmc WRITE_SIZE -d <write_dir>)",
+               "python bench.py --traffic-report <fetch_dir> <write_dir> --precision %s --calibrate-copy %d"
+               % (precision, copy_mib)],
+           "note": "FETCH_SIZE and WRITE_SIZE summed over the screen's dispatches of every screened round (the "
+                   "plain first round, the second round that also builds the neighbour lists, the final round) "
+                   "and divided by the number of those rounds; each counter is scaled by what it reads for the "
+                   "plain device copy run first in the same process (FETCH_SIZE counts half the copied bytes, "
+                   "WRITE_SIZE all).  The algorithmic minimum is one read of the BF16 representation (n_pad x "
+                   "d_pad x 2 bytes, 314 MB) per screen; the rest are tile re-reads that miss L2."}
     return rec
 
 
