@@ -254,14 +254,19 @@ __global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ pare
 
 // ------------------------------------------------------------------ Algorithm 1, one vertex
 
+// Everything Algorithm 1 reads about the vertex at x-order position q, packed
+// so that a level's first load is indexed by the position itself.
+struct VtxMeta {
+    int32_t a0, a1;     // its children's output slots a0 .. a1-1
+    int32_t slot, v;    // its own output slot and id
+    int32_t root, pad;  // 1 for the root
+    double om0, p0;     // its weight and potential
+    double fe;          // phi of its parent edge (0 at the root)
+};
+
 struct DPArgs {
-    const int32_t *order;
     const int32_t *level_start;
-    const int32_t *parent;
-    const uint32_t *kids;
-    const int32_t *koff;
-    const int32_t *slot;  // output slot of each vertex: its position among all child lists, n-1 for the root
-    const double *phi, *om0, *p0;
+    const VtxMeta *meta;  // [n] by x-order position
     const double *Nvals;
     double2 *cpw;  // [slot][MM] contribution (p, omega) to the parent
     int32_t *cnt;
@@ -277,15 +282,16 @@ struct DPArgs {
 //   join:    omega += omega(x), p += p(x),
 //   discard: p += phi(e).
 template <int MM, bool REC>
-__device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
+__device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
+    const VtxMeta vm = A.meta[q];
     const double N = A.Nvals[m];
-    double w = A.om0[v];
-    double p = A.p0[v];
+    double w = vm.om0;
+    double p = vm.p0;
     int32_t c_cnt = 0;
-    // The children's contributions sit contiguously at slots koff[v] ..
-    // koff[v+1]-1 (ascending child id), (p, omega) packed in 16 bytes; DP_BATCH
-    // children are loaded at once, the sums still run one child after another.
-    const int64_t a0 = A.koff[v], a1 = A.koff[v + 1];
+    // The children's contributions sit contiguously at slots a0 .. a1-1
+    // (ascending child id), (p, omega) packed in 16 bytes; DP_BATCH children
+    // are loaded at once, the sums still run one child after another.
+    const int64_t a0 = vm.a0, a1 = vm.a1;
     for (int64_t a = a0; a < a1; a += DP_BATCH) {
         const int64_t rem = a1 - a;
         double2 pw[DP_BATCH];
@@ -305,8 +311,8 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
             }
         }
     }
-    const bool is_root = A.parent[v] < 0;
-    const double fe = is_root ? 0.0 : A.phi[v];
+    const bool is_root = vm.root != 0;
+    const double fe = vm.fe;
     const double lhs = fe + p;
     const double rhs = N * w;
     double op, ow;
@@ -323,15 +329,37 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t v, int m) {
         op = fe;
         ow = 0.0;
     }
-    const int64_t o = (int64_t)A.slot[v] * MM + m;
+    const int64_t o = (int64_t)vm.slot * MM + m;
     A.cpw[o] = make_double2(op, ow);
     A.cnt[o] = c_cnt + iscut;
     if (REC) {
+        const int32_t v = vm.v;
         A.cut[v] = (uint8_t)iscut;
         A.joined[v] = (uint8_t)isjoin;
         A.num[v] = lhs;
         A.den[v] = w;
     }
+}
+
+// The packed record of every x-order position (after slots and weights).
+__global__ void k_vtx_meta(const int32_t *__restrict__ order, const int32_t *__restrict__ koff,
+                           const int32_t *__restrict__ slot, const int32_t *__restrict__ parent,
+                           const double *__restrict__ om0, const double *__restrict__ p0,
+                           const double *__restrict__ phi, int64_t n, VtxMeta *__restrict__ meta) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int32_t v = order[q];
+    VtxMeta vm;
+    vm.a0 = koff[v];
+    vm.a1 = koff[v + 1];
+    vm.slot = slot[v];
+    vm.v = v;
+    vm.root = parent[v] < 0 ? 1 : 0;
+    vm.pad = 0;
+    vm.om0 = om0[v];
+    vm.p0 = p0[v];
+    vm.fe = parent[v] < 0 ? 0.0 : phi[v];
+    meta[q] = vm;
 }
 
 // One wide level: MM consecutive threads per vertex.
@@ -342,7 +370,7 @@ __global__ __launch_bounds__(256) void k_dp_level(DPArgs A, int32_t lo, int32_t 
     const int64_t q = lo + gid / MM;
     const int m = (int)(gid % MM);
     if (q >= hi) return;
-    dp_vertex<MM, REC>(A, A.order[q], m);
+    dp_vertex<MM, REC>(A, (int32_t)q, m);
 }
 
 // A run of narrow levels [L0, L1) inside one workgroup, a barrier between levels.
@@ -354,7 +382,7 @@ __global__ __launch_bounds__(1024) void k_dp_narrow(DPArgs A, int32_t L0, int32_
     const int slots = blockDim.x / MM;
     for (int32_t L = L0; L < L1; ++L) {
         const int32_t lo = A.level_start[L], hi = A.level_start[L + 1];
-        for (int32_t q = lo + slot; q < hi; q += slots) dp_vertex<MM, REC>(A, A.order[q], m);
+        for (int32_t q = lo + slot; q < hi; q += slots) dp_vertex<MM, REC>(A, q, m);
         __syncthreads();
     }
 }
@@ -499,6 +527,7 @@ struct SubPlan {
     uint8_t *cut, *joined;
     TreeState *st;
     void *sort_scratch, *sel_scratch;
+    VtxMeta *meta;  // per x-order position
 
     void carve(Arena &a) {
         anc0 = a.take<int32_t>(n);
@@ -538,6 +567,7 @@ struct SubPlan {
         st = a.take<TreeState>(1);
         sort_scratch = a.take<char>(radix_sort_scratch_bytes(n));
         sel_scratch = a.take<char>(radix_select_scratch_bytes());
+        meta = a.take<VtxMeta>(n);
     }
 };
 
@@ -665,16 +695,12 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
                 "sigma must be positive (the median edge length is %g)", h.sigma);
     ISO_REQUIRE(!(h.bad & 4), ISO_ERR_INVALID_ARG, "degenerate weights: the bracket of the bisection is not finite");
 
+    hipLaunchKernelGGL(k_vtx_meta, dim3(gn), dim3(256), 0, s, order, P.koff, P.slot, parent, om0, p0, P.phi, n,
+                       P.meta);
+    LAUNCH_CHECK();
     DPArgs A{};
-    A.order = order;
     A.level_start = P.level_start;
-    A.parent = parent;
-    A.kids = kids;
-    A.koff = P.koff;
-    A.slot = P.slot;
-    A.phi = P.phi;
-    A.om0 = om0;
-    A.p0 = p0;
+    A.meta = P.meta;
     A.Nvals = P.Nvals;
     A.cpw = P.cpw;
     A.cnt = P.cnt;
