@@ -142,6 +142,16 @@ inline int ceil_log2(int64_t x) {
     return r;
 }
 
+// ------------------------------------------------------------------ histogram
+
+constexpr int HIST_LDS_BINS = 4096;  // bins a workgroup counts in LDS before one global add per bin
+
+// count[key[i]] += 1 for i < n with key[i] in [0, nbins) (other keys are
+// skipped).  With at most HIST_LDS_BINS bins each workgroup counts in LDS and
+// adds its nonzero bins once; otherwise every element adds to global memory.
+// count must be zero (or hold the counts to add to) on entry.
+void histogram_i32(const int32_t *key, int64_t n, int64_t nbins, int32_t *count, hipStream_t s);
+
 // ------------------------------------------------------------------ primitives (scan_sort.hip)
 
 // Exclusive scan of int32 in[0..n) into out[0..n) (in-place allowed); writes

@@ -839,14 +839,8 @@ __global__ void k_relabel(int32_t *__restrict__ comp, int64_t n, const int32_t *
     comp[i] = newid[npar[comp[i]]];
 }
 
-// Component sizes and the sum of their squares (timing only: the screen of a
-// round must cover (n^2 - sum |c|^2) / 2 unordered pairs).
-__global__ void k_comp_sizes(const int32_t *__restrict__ comp, int64_t n, int32_t *__restrict__ size) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = i < n;
-    grouped_atomic_count(size, active ? comp[i] : 0, active);
-}
-
+// Sum of the squared component sizes (timing only: the screen of a round must
+// cover (n^2 - sum |c|^2) / 2 unordered pairs).
 __global__ __launch_bounds__(1024) void k_sum_squares(const int32_t *__restrict__ size, int64_t m,
                                                       int32_t *__restrict__ counters) {
     __shared__ unsigned long long s[1024];
@@ -1350,8 +1344,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         const size_t esz = rep_bytes(rep);
         // component sizes -> padded tile order (host: at most FR_KC components)
         fill<int32_t>(P.flag, 0, K, s);
-        hipLaunchKernelGGL(k_comp_sizes, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.flag);
-        LAUNCH_CHECK();
+        histogram_i32(P.comp, n, K, P.flag, s);
         std::vector<int32_t> hs(K), pst(K), sst(K), tco;
         HIP_CHECK(hipMemcpyAsync(hs.data(), P.flag, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
@@ -1484,8 +1477,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         ISO_REQUIRE(rounds <= 64, ISO_ERR_INTERNAL, "Boruvka did not converge");
         if (timed) {
             fill<int32_t>(P.flag, 0, ncomp, s);
-            hipLaunchKernelGGL(k_comp_sizes, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.flag);
-            LAUNCH_CHECK();
+            histogram_i32(P.comp, n, ncomp, P.flag, s);
             hipLaunchKernelGGL(k_sum_squares, dim3(1), dim3(1024), 0, s, P.flag, ncomp, P.counters);
             LAUNCH_CHECK();
         }

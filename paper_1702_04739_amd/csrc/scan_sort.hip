@@ -1,5 +1,6 @@
 // scan_sort.hip -- error state, device check, and the generic primitives the
 // pipeline needs: exclusive scan, stable radix sort, radix select.
+#include <algorithm>
 #include <cstring>
 
 #include "common.hpp"
@@ -320,6 +321,44 @@ void radix_select_f64(const double *vals, const int32_t *skip_if_neg, int64_t n,
         hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, st, shift, out, shift == 0);
         LAUNCH_CHECK();
     }
+}
+
+// ------------------------------------------------------------------ histogram
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_hist_lds(const int32_t *__restrict__ key, int64_t n, int32_t nbins,
+                                                  int32_t *__restrict__ count) {
+    __shared__ int32_t h[HIST_LDS_BINS];
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = key[i];
+        if (k >= 0 && k < nbins) atomicAdd(&h[k], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (h[b]) atomicAdd(&count[b], h[b]);
+}
+
+__global__ void k_hist_global(const int32_t *__restrict__ key, int64_t n, int64_t nbins, int32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t k = key[i];
+    if (k >= 0 && k < nbins) atomicAdd(&count[k], 1);
+}
+
+}  // namespace
+
+void histogram_i32(const int32_t *key, int64_t n, int64_t nbins, int32_t *count, hipStream_t s) {
+    if (n <= 0 || nbins <= 0) return;
+    if (nbins <= HIST_LDS_BINS) {
+        const unsigned g = std::min<unsigned>(grid_for(n, 256), 4u * (unsigned)device_cus());
+        hipLaunchKernelGGL(k_hist_lds, dim3(g), dim3(256), 0, s, key, n, (int32_t)nbins, count);
+    } else {
+        hipLaunchKernelGGL(k_hist_global, dim3(grid_for(n, 256)), dim3(256), 0, s, key, n, nbins, count);
+    }
+    LAUNCH_CHECK();
 }
 
 }  // namespace iso

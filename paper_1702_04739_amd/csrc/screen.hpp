@@ -147,23 +147,6 @@ __device__ __forceinline__ void grouped_atomic_min(uint32_t *base, int key, uint
     if (active) atomicMin(&base[key], val);
 }
 
-// atomicAdd(&base[key], 1) for the active lanes, lanes sharing a key combined.
-__device__ __forceinline__ void grouped_atomic_count(int32_t *base, int key, bool active) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll 1
-    for (int it = 0; it < 4; ++it) {
-        const unsigned long long act = __ballot(active);
-        if (act == 0ull) return;
-        const int leader = __ffsll((long long)act) - 1;
-        const int lk = __shfl(key, leader, 64);
-        const bool mine = active && key == lk;
-        const unsigned long long grp = __ballot(mine);
-        if (lane == leader) atomicAdd(&base[lk], (int32_t)__popcll(grp));
-        active = active && !mine;
-    }
-    if (active) atomicAdd(&base[key], 1);
-}
-
 __device__ __forceinline__ float pair_bound(const ScreenBound &B, float ri, float rj, float ei, float ej) {
     const float t = ri + rj, f = ei + ej;
     const float g = fmaxf(ri, rj) <= B.rlim ? B.g_exact : B.g;

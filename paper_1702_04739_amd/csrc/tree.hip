@@ -482,13 +482,11 @@ __global__ void k_rep_jump(const int32_t *__restrict__ rin, int64_t n, int32_t *
 
 __global__ void k_labels(const int32_t *__restrict__ rep, const int32_t *__restrict__ cidx,
                          const double *__restrict__ num, const double *__restrict__ den, int64_t n,
-                         int32_t *__restrict__ labels, double *__restrict__ cl_num, double *__restrict__ cl_den,
-                         int32_t *__restrict__ cl_size) {
+                         int32_t *__restrict__ labels, double *__restrict__ cl_num, double *__restrict__ cl_den) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int32_t l = cidx[rep[v]];
     labels[v] = l;
-    if (l >= 0) atomicAdd(&cl_size[l], 1);
     const int32_t j = cidx[v];
     if (j >= 0) {
         cl_num[j] = num[v];
@@ -729,8 +727,9 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
             std::swap(ri, ro);
         }
         fill_t<int32_t>(cs, 0, kk, s);
-        hipLaunchKernelGGL(k_labels, dim3(gn), dim3(256), 0, s, ri, P.cidx, P.num, P.den, n, lab, cn, cd, cs);
+        hipLaunchKernelGGL(k_labels, dim3(gn), dim3(256), 0, s, ri, P.cidx, P.num, P.den, n, lab, cn, cd);
         LAUNCH_CHECK();
+        histogram_i32(lab, n, kk, cs, s);  // cluster sizes (residual label -1 skipped)
         hipLaunchKernelGGL(k_final_cost, dim3(1), dim3(64), 0, s, cn, cd, kk, P.cnt, root_slot, P.st);
         LAUNCH_CHECK();
         TreeState hf{};
