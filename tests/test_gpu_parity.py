@@ -270,8 +270,19 @@ def _cube_grid(side=6, dim=5, gap=3):
     return np.concatenate(pts).astype(np.float32)
 
 
+def _two_clusters(n=600, d=12, seed=21):
+    """Two tight clusters far apart: the tree's last edge is much longer than the rest."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, d))
+    X[n // 2:, 0] += 60.0
+    return X[rng.permutation(n)].astype(np.float32)
+
+
 FINAL_CASES = {
     "cubes-6x6-2^5": lambda: _cube_grid(),
+    "uniform-n512-d8": lambda: datagen.uniform(512, 8),  # n a multiple of the 256-point tile
+    "uniform-n256-d5": lambda: datagen.uniform(256, 5),  # exactly one tile
+    "two-clusters-n600": lambda: _two_clusters(),
     "c3-n4000-d784": lambda: datagen.config(3, n=4000),
     "c1-n2000-d16": lambda: datagen.config(1),
     "c5-n3000-d128": lambda: datagen.config(5, n=3000),
@@ -289,7 +300,7 @@ def test_final_round_matches_oracle(iso, orc, name, precision):
         p, l, _, _ = orc.prim_mst(X)
         _cache[key] = (X, p, l)
     X, op, ol = _cache[key]
-    if precision == "int8" and name.startswith(("c1", "c5")):
+    if precision == "int8" and name.startswith(("c1", "c5", "uniform", "two-clusters")):
         pytest.skip("the INT8 screen takes 8-bit data only")
     H.log("final round %s %s" % (name, precision))
     parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision=precision, recheck="fp64")
