@@ -110,15 +110,24 @@ iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_
 /* Euclidean minimum spanning tree of the complete graph on the n points X
  * (Sec. 2.2 step 2 / Sec. 3.5).  The n x n distance matrix is never stored:
  * distances are formed tile by tile.  Edges are totally ordered by (D^2 under
- * `recheck`, smaller end id, larger end id), so the tree is unique.
+ * `recheck`, smaller end id, larger end id), so the tree is unique.  Rounds
+ * screen every inter-component pair, except that from the third round on a
+ * round may be decided by the neighbour lists the second round's screen
+ * builds, and once at most 64 components remain one final round joins them
+ * all (both are switched off by ISO_MST_NO_LISTS / ISO_MST_NO_FINAL in
+ * `recheck`; the tree does not change).
  *   X       [n*ld] FP32 points (read only).
  *   parent  [n] out: tree rooted at vertex 0, parent[0] = -1.
  *   length  [n] out: FP64 Euclidean length of the edge (v, parent[v]),
  *                    sqrt of the left-to-right FP64 sum of squared coordinate
  *                    differences; length[0] = 0.
  *   info    (host, nullable) out: statistics; requires a stream sync.
- * Errors: n < 2, d < 1, ld < d, null pointers, unknown precision/recheck
- * (INVALID_ARG); a non-finite coordinate (NONFINITE). */
+ *   ws      device workspace of iso_mst_workspace_size bytes, or NULL (the
+ *           library then allocates and frees it on `stream`).
+ *   stream  HIP stream (NULL: the default stream); the call synchronises it.
+ * Errors: n < 2, d < 1, ld < d, null pointers, unknown precision, recheck or
+ * option bits (INVALID_ARG); a non-finite coordinate (NONFINITE); the INT8
+ * screen on data that is not 8-bit (INVALID_ARG). */
 iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t precision, int32_t recheck,
                    int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes, void *stream);
 
