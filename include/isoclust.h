@@ -79,6 +79,8 @@ typedef int32_t iso_status;
  * them; they select which rounds may skip the full screen). */
 #define ISO_MST_NO_LISTS 0x100 /* no neighbour lists from the second round    */
 #define ISO_MST_NO_FINAL 0x200 /* no final round joining <= 64 components    */
+#define ISO_MST_NO_ESCALATE 0x400 /* keep the requested screen precision even
+                                     when its bound is too loose for the data  */
 
 /* Vertex weight omega (eq. 2.2) and flow phi (eq. 2.1) readings. */
 #define ISO_OMEGA_TREE 0   /* omega(v) = sum of phi over v's tree edges         */
@@ -101,10 +103,13 @@ typedef struct {
     double mst_weight;       /* sum of the n-1 FP64 edge lengths                 */
     int32_t final_components;/* components joined at once by the final round
                                 (0: the last round was a plain round)           */
-    int32_t reserved1;
+    int32_t screen_precision;/* precision of the screen that built the tree: the
+                                requested one, or ISO_PREC_FP32 when its error
+                                bound was too loose for the data (escalation)   */
 } iso_mst_info;
 
-/* Device bytes iso_mst needs as workspace for n points in d dimensions. */
+/* Device bytes iso_mst needs as workspace for n points in d dimensions (room
+ * for the FP32 screen included, which a loose low-precision screen escalates to). */
 iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_t *bytes /* host */);
 
 /* Euclidean minimum spanning tree of the complete graph on the n points X

@@ -40,7 +40,8 @@ def version() -> str:
     return _lib.load().iso_version().decode()
 
 
-def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = True, final_round: bool = True):
+def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = True, final_round: bool = True,
+        escalate: bool = True):
     """Euclidean minimum spanning tree of the rows of ``points`` (n x d, float32, GPU).
 
     Returns (parent int32[n] rooted at 0 with parent[0] = -1, length float64[n]
@@ -49,7 +50,9 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     ("fp32", or "fp64" for parity with the FP64 oracle).  ``lists`` and
     ``final_round`` allow the rounds that skip the full screen (neighbour lists
     from the second round, one final round for the last <= 64 components); the
-    tree is the same either way."""
+    tree is the same either way.  ``escalate`` lets a low-precision screen
+    whose error bound is too loose for the data hand over to the FP32 screen
+    (``info["screen_precision"]`` tells which one built the tree)."""
     torch = _torch()
     _require_cuda(points, "points", torch.float32)
     if points.dim() != 2:
@@ -66,14 +69,16 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     parent = torch.empty(n, dtype=torch.int32, device=dev)
     length = torch.empty(n, dtype=torch.float64, device=dev)
     info = _lib.MstInfo()
-    flags = _lib.RECHECK[recheck] | (0 if lists else _lib.MST_NO_LISTS) | (0 if final_round else _lib.MST_NO_FINAL)
+    flags = (_lib.RECHECK[recheck] | (0 if lists else _lib.MST_NO_LISTS) | (0 if final_round else _lib.MST_NO_FINAL)
+             | (0 if escalate else _lib.MST_NO_ESCALATE))
     rc = lib.iso_mst(ctypes.c_void_p(points.data_ptr()), n, d, ld, _lib.PRECISION[precision], flags,
                      ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), ctypes.byref(info),
                      ctypes.c_void_p(ws.data_ptr()), int(need.value), _stream_ptr(dev))
     _lib.check(rc, "iso_mst")
     return parent, length, {"rounds": info.rounds, "list_rounds": info.list_rounds, "candidates": info.candidates,
                             "rescanned_rows": info.rescanned_rows, "mst_weight": info.mst_weight,
-                            "final_components": info.final_components}
+                            "final_components": info.final_components,
+                            "screen_precision": {v: k for k, v in _lib.PRECISION.items()}[info.screen_precision]}
 
 
 def mst_prim(points, return_order: bool = False):

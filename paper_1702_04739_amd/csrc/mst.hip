@@ -52,7 +52,8 @@ enum Counter : int {
     C_RESCAN = 10,      // rows rescanned (int64 at [10..11])
     C_SUMSQ = 12,       // sum over components of size^2 (int64 at [12..13], timing only)
     C_I8BAD = 14,       // the points are not 8-bit integers on a common grid (INT8 screen)
-    C_COUNT = 16
+    C_FRWORK = 16,      // final round: candidates its recheck would evaluate (int64 at [16..17])
+    C_COUNT = 18
 };
 
 // ------------------------------------------------------------------ small kernels
@@ -552,6 +553,7 @@ __global__ __launch_bounds__(256) void k_rescan(const float *__restrict__ X, int
 // gathered pass; when there are many, the round runs the full screen instead.
 
 constexpr float LIST_LAMBDA = 1.1f;
+constexpr double FR_EVAL_PER_POINT = 16.0;  // final round: most exact evaluations per point on average
 
 __global__ void k_list_init(const float *__restrict__ best, int64_t n, float *__restrict__ ltau,
                             int32_t *__restrict__ lcnt, uint32_t *__restrict__ ldrop) {
@@ -662,8 +664,7 @@ __global__ void k_fr_perm(const int32_t *__restrict__ sorted, const int32_t *__r
 // its lightest edge into their component and their pair of components' (the
 // screen's bound U), the row's lightest (D^2, j) per
 // other component (with i fixed the total order is (D^2, j)), and W1 = the
-// smallest D^2 per pair of components.  Rows whose candidate list overflowed
-// are counted (the round is then screened the plain way).
+// smallest D^2 per pair of components.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
                                                     const int32_t *__restrict__ comp, const float *__restrict__ Emax,
@@ -680,8 +681,7 @@ __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X,
     const int64_t i = (int64_t)blockIdx.x * 4 + w;
     const bool valid = i < n;
     const int cnt0 = valid ? ccnt[i] : 0;
-    if (valid && lane == 0 && cnt0 > SCR_CAP2) atomicAdd(&counters[C_OVF], 1);
-    const int cnt = cnt0 <= SCR_CAP2 ? cnt0 : 0;
+    const int cnt = cnt0 <= SCR_CAP2 ? cnt0 : 0;  // (runs only when no list overflowed)
     const int ci = valid ? comp[i] : 0;
     const float E = valid ? Emax[i] : 0.0f;
     const float *xi = X + (valid ? i : 0) * ld;
@@ -741,6 +741,35 @@ __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X,
     for (int off = 32; off >= 1; off >>= 1) evaluated += __shfl_xor(evaluated, off, 64);
     if (valid && lane == 0 && evaluated)
         atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
+}
+
+// The work the recheck would do: candidates that pass its filter (C_FRWORK)
+// and rows whose list overflowed (C_OVF).  One wave per row.
+__global__ __launch_bounds__(256) void k_fr_count(int64_t n, const int32_t *__restrict__ comp,
+                                                  const float *__restrict__ Emax, const float *__restrict__ bestc,
+                                                  const uint32_t *__restrict__ upair,
+                                                  const int32_t *__restrict__ ccnt, const int32_t *__restrict__ gcj,
+                                                  const float *__restrict__ gcl, float kappa, float dn,
+                                                  int32_t *__restrict__ counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int cnt0 = ccnt[i];
+    if (cnt0 > SCR_CAP2) {
+        if (lane == 0) atomicAdd(&counters[C_OVF], 1);
+        return;
+    }
+    const int ci = comp[i];
+    const float E = Emax[i];
+    int pass = 0;
+    for (int q = lane; q < cnt0; q += 64) {
+        const int c2 = comp[gcj[i * SCR_CAP2 + q]];
+        pass += gcl[i * SCR_CAP2 + q] <=
+                fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) pass += __shfl_xor(pass, off, 64);
+    if (lane == 0 && pass) atomicAdd((unsigned long long *)&counters[C_FRWORK], (unsigned long long)pass);
 }
 
 // W2 = the smallest (smaller id, larger id) among the rows' records that reach
@@ -1078,7 +1107,7 @@ struct MstPlan {
     int32_t *permF, *tcompF, *fr_pstart, *fr_sstart, *rowj;
     int2 *pairsF;
     int64_t ntF_cap;
-    int32_t options;                // ISO_MST_NO_LISTS / ISO_MST_NO_FINAL
+    int32_t options;                // ISO_MST_NO_LISTS / ISO_MST_NO_FINAL / ISO_MST_NO_ESCALATE
     float *bestc;
     double *rowd;
     unsigned long long *W1, *W2;
@@ -1196,14 +1225,28 @@ size_t plan_bytes(MstPlan p) {
     return a.used;
 }
 
+// A screen whose error bound is too loose for the data (every row's candidates
+// overflow, and rows fall through to the exact O(n d) rescan) is abandoned:
+// run_mst sets *escalate and returns, and the caller starts again with the
+// FP32 screen, whose representation is exact.  Thresholds: more than a
+// quarter of the points in the gathered pass, or more than 64 + n/64 rescans.
+constexpr double ESCALATE_GATHER = 0.25, ESCALATE_RESCAN = 1.0 / 64.0;
+
 void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t *parent, double *length,
-             iso_mst_info *info, hipStream_t s) {
+             iso_mst_info *info, hipStream_t s, bool *escalate) {
     const int64_t n = P.n, d = P.d, ld = P.ld;
     const bool timed = timing().enabled != 0;
     const int32_t rep = P.precision;
     const bool f64 = recheck == ISO_RECHECK_FP64;
     EventPair whole(timed), scr(timed);
     whole.start(s);
+    *escalate = false;
+    const bool may_escalate = rep != ISO_PREC_FP32 && !(P.options & ISO_MST_NO_ESCALATE);
+    auto give_up = [&]() {
+        whole.stop(s);
+        if (timed) timing().mst_ms += whole.elapsed_ms();
+        *escalate = true;
+    };
     // gathered-pass lists: [n][SCR_CAP2] of j and of lower bounds
     char *gbuf = arena.take<char>(P.gather_bytes());
     P.gcj = reinterpret_cast<int32_t *>(gbuf);
@@ -1404,9 +1447,33 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         scr.start(s);
         launch_screen_pairs(FA, P.pairsF, 0, (int64_t)fpairs.size(), s);
         scr.stop(s);
+        // the recheck runs only when its work is modest: no overflowed list
+        // and at most FR_EVAL_PER_POINT candidates per point on average (with
+        // a loose screen bound, e.g. FP8 at large d, the plain rounds are cheaper)
+        {
+            int32_t hc[C_COUNT];
+            fill<int32_t>(P.counters + C_OVF, 0, 1, s);
+            fill<int32_t>(P.counters + C_FRWORK, 0, 2, s);
+            hipLaunchKernelGGL(k_fr_count, dim3(grid_for(n, 4)), dim3(256), 0, s, n, P.comp, P.Emax, P.bestc, P.upair,
+                               P.ccnt, P.gcj, P.gcl, kappa, dn, P.counters);
+            LAUNCH_CHECK();
+            HIP_CHECK(hipMemcpyAsync(hc, P.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            unsigned long long work = 0;
+            memcpy(&work, &hc[C_FRWORK], sizeof(work));
+            if (timed) {
+                unsigned long long sumsq = 0;
+                memcpy(&sumsq, &hc[C_SUMSQ], sizeof(sumsq));
+                iso_timing &T = timing();
+                T.screen_launches += 1;
+                T.screen_ms += scr.elapsed_ms();
+                T.screen_pairs += 0.5 * ((double)n * (double)n - (double)sumsq);
+                T.screen_dim = (double)P.d_pad;
+            }
+            if (hc[C_OVF] > 0 || (double)work > FR_EVAL_PER_POINT * (double)n) return false;
+        }
         fill<unsigned long long>(P.W1, U64_MAX, FR_KC * FR_KC, s);
         fill<unsigned long long>(P.W2, U64_MAX, FR_KC * FR_KC, s);
-        fill<int32_t>(P.counters + C_OVF, 0, 1, s);
         if (f64)
             hipLaunchKernelGGL(k_fr_recheck<true>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.comp, P.Emax,
                                P.bestc, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj, P.W1, P.counters);
@@ -1424,16 +1491,6 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         HIP_CHECK(hipMemcpyAsync(w2.data(), P.W2, sizeof(unsigned long long) * w2.size(), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipMemcpyAsync(h, P.counters, sizeof(h), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        if (timed) {
-            unsigned long long sumsq = 0;
-            memcpy(&sumsq, &h[C_SUMSQ], sizeof(sumsq));
-            iso_timing &T = timing();
-            T.screen_launches += 1;
-            T.screen_ms += scr.elapsed_ms();
-            T.screen_pairs += 0.5 * ((double)n * (double)n - (double)sumsq);
-            T.screen_dim = (double)P.d_pad;
-        }
-        if (h[C_OVF] > 0) return false;
         // Kruskal over the components' lightest edges, ordered by (D^2, ids)
         struct CE {
             unsigned long long d2, ids;
@@ -1603,6 +1660,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             T.screen_launches += 1;
             T.screen_ms += scr.elapsed_ms();
         }
+        if (may_escalate && (double)h_gather > ESCALATE_GATHER * (double)n) {
+            give_up();
+            return;
+        }
         if (h_gather > 0) {
             SA.rows = P.glist;
             SA.nrows = h_gather;
@@ -1624,6 +1685,15 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                    P.best, P.Emax, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa, dn,
                                    P.rb_d2, P.rb_j, P.rlist, P.counters);
             LAUNCH_CHECK();
+            if (may_escalate) {
+                int32_t h_ovf = 0;
+                HIP_CHECK(hipMemcpyAsync(&h_ovf, P.counters + C_OVF, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+                if ((double)h_ovf > 64.0 + ESCALATE_RESCAN * (double)n) {
+                    give_up();
+                    return;
+                }
+            }
             if (f64)
                 hipLaunchKernelGGL(k_rescan<true>, dim3(1024), dim3(256), 0, s, X, n, d, ld, P.comp, P.rlist, P.counters,
                                    P.rb_d2, P.rb_j);
@@ -1740,7 +1810,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         info->rounds = rounds;
         info->list_rounds = list_rounds;
         info->final_components = final_components;
-        info->reserved1 = 0;
+        info->screen_precision = rep;
         info->candidates = cand;
         info->rescanned_rows = resc;
     }
@@ -1760,7 +1830,8 @@ extern "C" iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t preci
         ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8 ||
                         precision == ISO_PREC_INT8,
                     ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
-        *bytes = plan_bytes(make_plan(n, d, d, precision));
+        // room for the FP32 screen too (a screen whose bound is too loose escalates to it)
+        *bytes = std::max(plan_bytes(make_plan(n, d, d, precision)), plan_bytes(make_plan(n, d, d, ISO_PREC_FP32)));
     });
 }
 
@@ -1779,13 +1850,13 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         recheck &= 0xFF;
         ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
                     "unknown recheck %d", recheck);
-        ISO_REQUIRE((options & ~(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL)) == 0, ISO_ERR_INVALID_ARG,
+        ISO_REQUIRE((options & ~(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL | ISO_MST_NO_ESCALATE)) == 0, ISO_ERR_INVALID_ARG,
                     "unknown options 0x%x", options);
         require_device();
         hipStream_t s = static_cast<hipStream_t>(stream);
         MstPlan P = make_plan(n, d, ld, precision);
         P.options = options;
-        const size_t need = plan_bytes(P);
+        const size_t need = std::max(plan_bytes(P), plan_bytes(make_plan(n, d, ld, ISO_PREC_FP32)));
         ScopedWorkspace owned;
         if (ws == nullptr) {
             owned.stream = s;
@@ -1796,7 +1867,16 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         ISO_REQUIRE(ws_bytes >= need, ISO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
         Arena a{static_cast<char *>(ws), 0, ws_bytes};
         P.carve(a);
-        run_mst(P, a, X, recheck, parent, length, info, s);
+        bool escalate = false;
+        run_mst(P, a, X, recheck, parent, length, info, s, &escalate);
+        if (escalate) {
+            MstPlan P32 = make_plan(n, d, ld, ISO_PREC_FP32);
+            P32.options = options;
+            Arena a32{static_cast<char *>(ws), 0, ws_bytes};
+            P32.carve(a32);
+            run_mst(P32, a32, X, recheck, parent, length, info, s, &escalate);
+            ISO_REQUIRE(!escalate, ISO_ERR_INTERNAL, "the FP32 screen cannot escalate");
+        }
     });
 }
 

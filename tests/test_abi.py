@@ -117,6 +117,7 @@ def test_header_constants_match_binding():
         assert defs["ISO_RECHECK_" + name.upper()] == v
     assert defs["ISO_MST_NO_LISTS"] == _lib.MST_NO_LISTS
     assert defs["ISO_MST_NO_FINAL"] == _lib.MST_NO_FINAL
+    assert defs["ISO_MST_NO_ESCALATE"] == _lib.MST_NO_ESCALATE
     assert defs["ISO_OMEGA_FULL"] == _lib.OMEGA["full"]
     for code, name in _lib.ERRORS.items():
         if name in defs:
