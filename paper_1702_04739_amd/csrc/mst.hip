@@ -64,6 +64,10 @@ __global__ void k_fill(T *p, T v, int64_t n) {
         p[i] = v;
 }
 
+// Workgroups (four waves, one row per wave per step) for a grid-stride walk
+// over n rows: enough to fill the chip, few enough to dispatch quickly.
+unsigned row_grid(int64_t n) { return std::min<unsigned>(grid_for(n, 4), 16u * (unsigned)device_cus()); }
+
 template <class T>
 void fill(T *p, T v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
@@ -309,7 +313,22 @@ __global__ void k_iota_comp(int32_t *comp, int64_t n, int64_t n_pad) {
 __device__ inline float d2_f32_wave(const float *__restrict__ x, const float *__restrict__ y, int64_t d) {
     const int lane = threadIdx.x & 63;
     float acc = 0.0f;
-    for (int64_t t = lane; t < d; t += 64) {
+    int64_t t = lane;
+    // eight strides loaded ahead, then folded in the same order as one at a time
+    for (; t + 7 * 64 < d; t += 8 * 64) {
+        float a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = x[t + 64 * u];
+            b[u] = y[t + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float df = a[u] - b[u];
+            acc = fmaf(df, df, acc);
+        }
+    }
+    for (; t < d; t += 64) {
         float df = x[t] - y[t];
         acc = fmaf(df, df, acc);
     }
@@ -425,26 +444,31 @@ __global__ __launch_bounds__(256) void k_recheck_rows(const float *__restrict__ 
                                                       double *__restrict__ rb_d2, int32_t *__restrict__ rb_j,
                                                       int32_t *__restrict__ glist, int32_t *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    double out_d2 = __builtin_huge_val();
-    int out_j = -1, evaluated = 0;
-    float thr;
-    const int cnt = ccnt[i];
-    if (cnt == SCR_FORCE) {
-        if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
-    } else if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
-        if (cnt > SCR_CAP) {
+    int evaluated = 0;
+    // rows are walked with the stride of all waves (a few thousand workgroups
+    // instead of one per four rows: the dispatch of 50k small workgroups costs
+    // more than their work)
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        double out_d2 = __builtin_huge_val();
+        int out_j = -1, ev = 0;
+        float thr;
+        const int cnt = ccnt[i];
+        if (cnt == SCR_FORCE) {
             if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
-        } else {
-            eval_candidates<F64>(X, ld, d, i, cj + i * SCR_CAP, cl + i * SCR_CAP, cnt, thr, out_d2, out_j, evaluated);
+        } else if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
+            if (cnt > SCR_CAP) {
+                if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
+            } else {
+                eval_candidates<F64>(X, ld, d, i, cj + i * SCR_CAP, cl + i * SCR_CAP, cnt, thr, out_d2, out_j, ev);
+            }
         }
+        if (lane == 0) {
+            rb_d2[i] = out_d2;
+            rb_j[i] = out_j;
+        }
+        evaluated += ev;
     }
-    if (lane == 0) {
-        rb_d2[i] = out_d2;
-        rb_j[i] = out_j;
-        if (evaluated) atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
-    }
+    if (lane == 0 && evaluated) atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
 }
 
 // One wave per gathered row: exact recheck of the gathered pass's candidates;
@@ -571,17 +595,17 @@ __global__ __launch_bounds__(256) void k_list_best(int64_t n, const int32_t *__r
                                                    const int32_t *__restrict__ lcnt, const int32_t *__restrict__ lj,
                                                    const float *__restrict__ lv, float *__restrict__ best) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    const int ci = comp[i];
-    const int cnt = min(lcnt[i], LIST_CAP);
-    uint32_t m = 0x7F800000u;
-    for (int q = lane; q < cnt; q += 64) {
-        const int32_t j = lj[i * LIST_CAP + q];
-        if (comp[j] != ci) m = min(m, __float_as_uint(lv[i * LIST_CAP + q]));
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        const int ci = comp[i];
+        const int cnt = min(lcnt[i], LIST_CAP);
+        uint32_t m = 0x7F800000u;
+        for (int q = lane; q < cnt; q += 64) {
+            const int32_t j = lj[i * LIST_CAP + q];
+            if (comp[j] != ci) m = min(m, __float_as_uint(lv[i * LIST_CAP + q]));
+        }
+        m = wave_min_u32(m);
+        if (lane == 0) best[i] = __uint_as_float(m);
     }
-    m = wave_min_u32(m);
-    if (lane == 0) best[i] = __uint_as_float(m);
 }
 
 // One wave per row: decide the row from its list (candidates into cj/cl as
@@ -594,45 +618,45 @@ __global__ __launch_bounds__(256) void k_list_capture(
     const int32_t *__restrict__ lj, const float *__restrict__ lv, float kappa, float dn, int32_t *__restrict__ ccnt,
     int32_t *__restrict__ cj, float *__restrict__ cl, int32_t *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    const int ci = comp[i];
-    const float b = best[i], E = Emax[i];
-    const uint32_t ubits = comp_ub[ci];
-    const float U = ubits == U32_MAX ? SCR_INF : __uint_as_float(ubits) * dn;
-    const float thr = fminf(b < SCR_INF ? (b + E) * kappa : SCR_INF, U);
-    const float t = fminf(ltau[i], __uint_as_float(ldrop[i]));
-    if (!(thr < SCR_INF) || !(lower_of(t, E) > thr)) {
-        if (lane == 0) {
-            ccnt[i] = SCR_FORCE;
-            atomicAdd(&counters[C_FORCE], 1);
-        }
-        return;
-    }
-    const int cnt = min(lcnt[i], LIST_CAP);
-    const float ri = rn[i], ei = re[i];
-    int taken = 0;
-    for (int q0 = 0; q0 < cnt; q0 += 64) {
-        const int q = q0 + lane;
-        bool keep = false;
-        int32_t j = 0;
-        float L = 0.0f;
-        if (q < cnt) {
-            j = lj[i * LIST_CAP + q];
-            if (comp[j] != ci) {
-                L = lower_of(lv[i * LIST_CAP + q], pair_bound(bound, ri, rn[j], ei, re[j]));
-                keep = L <= thr;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        const int ci = comp[i];
+        const float b = best[i], E = Emax[i];
+        const uint32_t ubits = comp_ub[ci];
+        const float U = ubits == U32_MAX ? SCR_INF : __uint_as_float(ubits) * dn;
+        const float thr = fminf(b < SCR_INF ? (b + E) * kappa : SCR_INF, U);
+        const float t = fminf(ltau[i], __uint_as_float(ldrop[i]));
+        if (!(thr < SCR_INF) || !(lower_of(t, E) > thr)) {
+            if (lane == 0) {
+                ccnt[i] = SCR_FORCE;
+                atomicAdd(&counters[C_FORCE], 1);
             }
+            continue;
         }
-        const unsigned long long bal = __ballot(keep);
-        const int pos = taken + __popcll(bal & ((1ull << lane) - 1ull));
-        if (keep && pos < SCR_CAP) {
-            cj[i * SCR_CAP + pos] = j;
-            cl[i * SCR_CAP + pos] = L;
+        const int cnt = min(lcnt[i], LIST_CAP);
+        const float ri = rn[i], ei = re[i];
+        int taken = 0;
+        for (int q0 = 0; q0 < cnt; q0 += 64) {
+            const int q = q0 + lane;
+            bool keep = false;
+            int32_t j = 0;
+            float L = 0.0f;
+            if (q < cnt) {
+                j = lj[i * LIST_CAP + q];
+                if (comp[j] != ci) {
+                    L = lower_of(lv[i * LIST_CAP + q], pair_bound(bound, ri, rn[j], ei, re[j]));
+                    keep = L <= thr;
+                }
+            }
+            const unsigned long long bal = __ballot(keep);
+            const int pos = taken + __popcll(bal & ((1ull << lane) - 1ull));
+            if (keep && pos < SCR_CAP) {
+                cj[i * SCR_CAP + pos] = j;
+                cl[i * SCR_CAP + pos] = L;
+            }
+            taken += __popcll(bal);
         }
-        taken += __popcll(bal);
+        if (lane == 0) ccnt[i] = taken > SCR_CAP ? SCR_CAP + 1 : taken;
     }
-    if (lane == 0) ccnt[i] = taken > SCR_CAP ? SCR_CAP + 1 : taken;
 }
 
 // ------------------------------------------------------------------ final round
@@ -678,68 +702,73 @@ __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X,
     __shared__ int32_t tj[4][FR_KC];
     __shared__ double dv[4][SCR_CAP2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 4 + w;
-    const bool valid = i < n;
-    const int cnt0 = valid ? ccnt[i] : 0;
-    const int cnt = cnt0 <= SCR_CAP2 ? cnt0 : 0;  // (runs only when no list overflowed)
-    const int ci = valid ? comp[i] : 0;
-    const float E = valid ? Emax[i] : 0.0f;
-    const float *xi = X + (valid ? i : 0) * ld;
-    const int32_t *js = gcj + (valid ? i : 0) * SCR_CAP2;
-    const float *ls = gcl + (valid ? i : 0) * SCR_CAP2;
-    for (int c = lane; c < FR_KC; c += 64) {
-        td[w][c] = U64_MAX;
-        tj[w][c] = 0x7FFFFFFF;
-    }
-    __syncthreads();
     int evaluated = 0;
-    if (F64) {
-        for (int q = lane; q < cnt; q += 64) {
-            const int32_t j = js[q];
-            const int c2 = comp[j];
-            double v = __builtin_huge_val();
-            if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
-                v = d2_f64_lane(xi, X + (int64_t)j * ld, d);
-                ++evaluated;
-                atomicMin(&td[w][c2], (unsigned long long)__double_as_longlong(v));
-            }
-            dv[w][q] = v;
+    // rows in a grid-stride walk; the trip count is the same for the four
+    // waves of a workgroup (the barriers below are workgroup-wide)
+    for (int64_t base = (int64_t)blockIdx.x * 4; base < n; base += (int64_t)gridDim.x * 4) {
+        const int64_t i = base + w;
+        const bool valid = i < n;
+        const int cnt0 = valid ? ccnt[i] : 0;
+        const int cnt = cnt0 <= SCR_CAP2 ? cnt0 : 0;  // (runs only when no list overflowed)
+        const int ci = valid ? comp[i] : 0;
+        const float E = valid ? Emax[i] : 0.0f;
+        const float *xi = X + (valid ? i : 0) * ld;
+        const int32_t *js = gcj + (valid ? i : 0) * SCR_CAP2;
+        const float *ls = gcl + (valid ? i : 0) * SCR_CAP2;
+        for (int c = lane; c < FR_KC; c += 64) {
+            td[w][c] = U64_MAX;
+            tj[w][c] = 0x7FFFFFFF;
         }
-    } else {
-        for (int q = 0; q < cnt; ++q) {
-            const int32_t j = js[q];
-            const int c2 = comp[j];
-            double v = __builtin_huge_val();
-            if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
-                v = (double)d2_f32_wave(xi, X + (int64_t)j * ld, d);
-                if (lane == 0) {
+        __syncthreads();
+        if (F64) {
+            for (int q = lane; q < cnt; q += 64) {
+                const int32_t j = js[q];
+                const int c2 = comp[j];
+                double v = __builtin_huge_val();
+                if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
+                    v = d2_f64_lane(xi, X + (int64_t)j * ld, d);
                     ++evaluated;
                     atomicMin(&td[w][c2], (unsigned long long)__double_as_longlong(v));
                 }
+                dv[w][q] = v;
             }
-            if (lane == 0) dv[w][q] = v;
+        } else {
+            for (int q = 0; q < cnt; ++q) {
+                const int32_t j = js[q];
+                const int c2 = comp[j];
+                double v = __builtin_huge_val();
+                if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
+                    v = (double)d2_f32_wave(xi, X + (int64_t)j * ld, d);
+                    if (lane == 0) {
+                        ++evaluated;
+                        atomicMin(&td[w][c2], (unsigned long long)__double_as_longlong(v));
+                    }
+                }
+                if (lane == 0) dv[w][q] = v;
+            }
         }
-    }
-    __syncthreads();
-    for (int q = lane; q < cnt; q += 64) {
-        const double v = dv[w][q];
-        if (!(v < __builtin_huge_val())) continue;
-        const int32_t j = js[q];
-        const int c2 = comp[j];
-        if ((unsigned long long)__double_as_longlong(v) == td[w][c2]) atomicMin(&tj[w][c2], j);
-    }
-    __syncthreads();
-    if (valid) {
-        for (int c = lane; c < FR_KC; c += 64) {
-            const unsigned long long b = td[w][c];
-            rowd[i * FR_KC + c] = b == U64_MAX ? __builtin_huge_val() : __longlong_as_double((long long)b);
-            rowj[i * FR_KC + c] = b == U64_MAX ? -1 : tj[w][c];
-            if (b != U64_MAX) atomicMin(&W1[fr_pair(ci, c)], b);
+        __syncthreads();
+        for (int q = lane; q < cnt; q += 64) {
+            const double v = dv[w][q];
+            if (!(v < __builtin_huge_val())) continue;
+            const int32_t j = js[q];
+            const int c2 = comp[j];
+            if ((unsigned long long)__double_as_longlong(v) == td[w][c2]) atomicMin(&tj[w][c2], j);
         }
+        __syncthreads();
+        if (valid) {
+            for (int c = lane; c < FR_KC; c += 64) {
+                const unsigned long long b = td[w][c];
+                rowd[i * FR_KC + c] = b == U64_MAX ? __builtin_huge_val() : __longlong_as_double((long long)b);
+                rowj[i * FR_KC + c] = b == U64_MAX ? -1 : tj[w][c];
+                if (b != U64_MAX) atomicMin(&W1[fr_pair(ci, c)], b);
+            }
+        }
+        __syncthreads();  // the next row reinitialises this wave's tables
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) evaluated += __shfl_xor(evaluated, off, 64);
-    if (valid && lane == 0 && evaluated)
+    if (lane == 0 && evaluated)
         atomicAdd((unsigned long long *)&counters[C_CAND], (unsigned long long)evaluated);
 }
 
@@ -752,20 +781,20 @@ __global__ __launch_bounds__(256) void k_fr_count(int64_t n, const int32_t *__re
                                                   const float *__restrict__ gcl, float kappa, float dn,
                                                   int32_t *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    const int cnt0 = ccnt[i];
-    if (cnt0 > SCR_CAP2) {
-        if (lane == 0) atomicAdd(&counters[C_OVF], 1);
-        return;
-    }
-    const int ci = comp[i];
-    const float E = Emax[i];
     int pass = 0;
-    for (int q = lane; q < cnt0; q += 64) {
-        const int c2 = comp[gcj[i * SCR_CAP2 + q]];
-        pass += gcl[i * SCR_CAP2 + q] <=
-                fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn);
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        const int cnt0 = ccnt[i];
+        if (cnt0 > SCR_CAP2) {
+            if (lane == 0) atomicAdd(&counters[C_OVF], 1);
+            continue;
+        }
+        const int ci = comp[i];
+        const float E = Emax[i];
+        for (int q = lane; q < cnt0; q += 64) {
+            const int c2 = comp[gcj[i * SCR_CAP2 + q]];
+            pass += gcl[i * SCR_CAP2 + q] <=
+                    fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn);
+        }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) pass += __shfl_xor(pass, off, 64);
@@ -1454,7 +1483,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             int32_t hc[C_COUNT];
             fill<int32_t>(P.counters + C_OVF, 0, 1, s);
             fill<int32_t>(P.counters + C_FRWORK, 0, 2, s);
-            hipLaunchKernelGGL(k_fr_count, dim3(grid_for(n, 4)), dim3(256), 0, s, n, P.comp, P.Emax, P.bestc, P.upair,
+            hipLaunchKernelGGL(k_fr_count, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.Emax, P.bestc, P.upair,
                                P.ccnt, P.gcj, P.gcl, kappa, dn, P.counters);
             LAUNCH_CHECK();
             HIP_CHECK(hipMemcpyAsync(hc, P.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -1475,10 +1504,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         fill<unsigned long long>(P.W1, U64_MAX, FR_KC * FR_KC, s);
         fill<unsigned long long>(P.W2, U64_MAX, FR_KC * FR_KC, s);
         if (f64)
-            hipLaunchKernelGGL(k_fr_recheck<true>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.comp, P.Emax,
+            hipLaunchKernelGGL(k_fr_recheck<true>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.comp, P.Emax,
                                P.bestc, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj, P.W1, P.counters);
         else
-            hipLaunchKernelGGL(k_fr_recheck<false>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.comp,
+            hipLaunchKernelGGL(k_fr_recheck<false>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.comp,
                                P.Emax, P.bestc, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj, P.W1,
                                P.counters);
         LAUNCH_CHECK();
@@ -1549,7 +1578,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         // lists; the round screens only when too many rows stay undecided.
         bool list_round = false;
         if (lists == LISTS_READY) {
-            hipLaunchKernelGGL(k_list_best, dim3(grid_for(n, 4)), dim3(256), 0, s, n, P.comp, P.lscnt, P.lj, P.lv,
+            hipLaunchKernelGGL(k_list_best, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.lscnt, P.lj, P.lv,
                                P.best);
             LAUNCH_CHECK();
             fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
@@ -1557,7 +1586,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                P.comp_ub);
             LAUNCH_CHECK();
             fill<int32_t>(P.counters + C_FORCE, 0, 1, s);
-            hipLaunchKernelGGL(k_list_capture, dim3(grid_for(n, 4)), dim3(256), 0, s, n, P.comp, P.comp_ub, P.best,
+            hipLaunchKernelGGL(k_list_capture, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.comp_ub, P.best,
                                P.Emax, P.rn, P.re, bound, P.ltau, P.lscnt, P.ldrop, P.lj, P.lv, kappa, dn, P.ccnt, P.cj,
                                P.cl, P.counters);
             LAUNCH_CHECK();
@@ -1646,10 +1675,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         fill<int32_t>(P.counters + C_OVF, 0, 1, s);
         fill<int32_t>(P.counters + C_GATHER, 0, 1, s);
         if (f64)
-            hipLaunchKernelGGL(k_recheck_rows<true>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best, P.Emax,
+            hipLaunchKernelGGL(k_recheck_rows<true>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.best, P.Emax,
                                P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist, P.counters);
         else
-            hipLaunchKernelGGL(k_recheck_rows<false>, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, P.best,
+            hipLaunchKernelGGL(k_recheck_rows<false>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.best,
                                P.Emax, P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist, P.counters);
         LAUNCH_CHECK();
         int32_t h_gather = 0;
