@@ -120,10 +120,20 @@ def cpu_baseline(n_full, k, sample_n):
     oracle.subpartition(parent, length, k)
     t2 = time.perf_counter()
     t_full = (t1 - t0) * (n_full / sample_n) ** 2 + (t2 - t1) * (n_full / sample_n)
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": n_full / t_full,
         "unit": "points/s",
         "cores": 1,
+        "cpu": cpu_model,
         "kind": "oracle",
         "sample": "same recipe at n=%d (MST %.2f s, tree search %.3f s, single thread); MST time scaled by "
                   "(n/%d)^2 and tree time by n/%d to n=%d" % (sample_n, t1 - t0, t2 - t1, sample_n, sample_n, n_full),
@@ -133,8 +143,8 @@ def cpu_baseline(n_full, k, sample_n):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8", "int8"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 and INT8 screen comparison steps")
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
