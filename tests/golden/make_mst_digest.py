@@ -1,0 +1,46 @@
+"""Writes tests/golden/mst_digest_<recipe>_n<n>.json: the FP64 oracle's MST
+(dense Prim from vertex 0, edges ordered by (D^2, smaller id, larger id)) of a
+seeded synthetic input, stored as the SHA-256 of its parent array (int32,
+little endian), its weight and its first entries.  Only the oracle computes it.
+
+    python tests/golden/make_mst_digest.py 3 50000     # image-like recipe, n = 50,000 (~20 min, one core)
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_1702_04739_amd import datagen  # noqa: E402
+
+RECIPE = {1: "gaussian-mixture", 2: "anisotropic-mixture", 3: "image-like", 4: "sparse-communities", 5: "blobs"}
+
+
+def main():
+    cfg, n = int(sys.argv[1]), int(sys.argv[2])
+    X = datagen.config(cfg, n=n)
+    t0 = time.time()
+    parent, length, _, _ = oracle.prim_mst(X)
+    rec = {
+        "recipe": RECIPE[cfg], "config": cfg, "n": n, "d": int(X.shape[1]),
+        "tree": "FP64 oracle, dense Prim from vertex 0, order (D^2, smaller id, larger id)",
+        "parent_sha256": hashlib.sha256(parent.astype("<i4").tobytes()).hexdigest(),
+        "weight": float(np.sum(length[1:])),
+        "parent_head": [int(v) for v in parent[:16]],
+        "oracle_seconds": round(time.time() - t0, 1),
+    }
+    path = os.path.join(HERE, "mst_digest_%s_n%d.json" % (RECIPE[cfg], n))
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -142,3 +142,29 @@ def test_tree_stage_matches_oracle(c3):
     np.testing.assert_array_equal(labels.cpu().numpy(), ref.labels)
     H.check_subpartition_structure(parent, length, labels.cpu().numpy(), 10, ref.sigma, ref.beta, ref.i_k,
                                    info["sub"]["jstar"])
+
+
+@pytest.mark.parametrize("precision", ["bf16", "int8"])
+def test_mst_matches_oracle_digest_image_like_n50000(precision):
+    """Exact parity at scale: the image-like recipe at n = 50,000 (neighbour-list
+    and final rounds included) gives, with the FP64 recheck, the oracle's tree
+    bit for bit (its parent array's SHA-256, stored by
+    tests/golden/make_mst_digest.py, which runs only the oracle)."""
+    import hashlib
+    import json
+    import os
+
+    import paper_1702_04739_amd as iso
+    from paper_1702_04739_amd import datagen
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mst_digest_image-like_n50000.json")
+    with open(path) as f:
+        rec = json.load(f)
+    X = torch.from_numpy(datagen.config(3, n=rec["n"])).cuda()
+    H.log("digest parity image-like n=%d %s + fp64 recheck" % (rec["n"], precision))
+    parent, length, info = iso.mst(X, precision=precision, recheck="fp64")
+    H.log("  info %s" % info)
+    p = parent.cpu().numpy()
+    assert [int(v) for v in p[:16]] == rec["parent_head"]
+    assert hashlib.sha256(p.astype("<i4").tobytes()).hexdigest() == rec["parent_sha256"]
+    assert abs(info["mst_weight"] - rec["weight"]) <= 1e-12 * rec["weight"]
