@@ -1086,15 +1086,21 @@ __global__ void k_pair_keep(const int2 *__restrict__ pairs, int64_t npairs, cons
     keep[k] = one ? 0 : 1;
 }
 
-// Rows of the representation in the tile order: one wave per position.
+// Rows of the representation in the tile order, stored tile by tile and,
+// within a tile, K chunk by K chunk: the 64-byte pieces of chunk c of the
+// tile's GT rows are contiguous (position q, 16-byte piece t of its row at
+// uint4 index (q / GT) GT row_u4 + (t / 4) 4 GT + (q mod GT) 4 + t mod 4), so
+// the tile-pair screen stages each chunk from whole, consecutive cache lines.
+// One workgroup per (tile, chunk); npos is a multiple of GT.
 __global__ __launch_bounds__(256) void k_permute_rows(const uint4 *__restrict__ Xr, const int32_t *__restrict__ perm,
-                                                      int64_t n_pad, int64_t row_u4, uint4 *__restrict__ Xq) {
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < n_pad; q += nwaves) {
-        const uint4 *src = Xr + (int64_t)perm[q] * row_u4;
-        uint4 *dst = Xq + q * row_u4;
-        for (int64_t t = lane; t < row_u4; t += 64) dst[t] = src[t];
+                                                      int64_t nchunks, int64_t row_u4, uint4 *__restrict__ Xq) {
+    static_assert(GT == 256, "four pieces per thread cover a chunk of the tile");
+    const int64_t tile = blockIdx.x / nchunks, c = blockIdx.x - tile * nchunks;
+    uint4 *dst = Xq + (tile * nchunks + c) * (4 * GT);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = k * 256 + (int)threadIdx.x;  // row e / 4 of the tile, piece e mod 4 of the chunk
+        dst[e] = Xr[(int64_t)perm[tile * GT + (e >> 2)] * row_u4 + c * 4 + (e & 3)];
     }
 }
 
@@ -1116,7 +1122,7 @@ struct MstPlan {
     int64_t n, d, ld, n_pad, d_pad, nrb;
     int32_t precision;
     void *Xr;                       // screen representation (FP32, BF16 or FP8), [n_pad][d_pad]
-    void *Xq;                       // the same rows in the tile order of the round
+    void *Xq;                       // the tile-pair screen's copy: rows in the tile order, chunk-major per tile
     float *mu, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
     int32_t *pgrid, *grid_min, *sqi, *qg;
     float *pmin, *pmax, *cmin, *cmax;
@@ -1399,8 +1405,21 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     }
     hipLaunchKernelGGL(k_perm_identity, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad);
     LAUNCH_CHECK();
+    // The tile-pair screen reads its own copy of the representation (Xq), in
+    // the tile order and chunk-major within each tile; xq_plain: Xq holds the
+    // rows in the order P.perm (the final round overwrites it with its own).
+    const int64_t row_u4 = (int64_t)(P.d_pad * rep_bytes(rep) / 16);
+    auto tile_copy = [&](const int32_t *order, int64_t npos) {
+        const int64_t nchunks = row_u4 / 4;
+        ISO_REQUIRE(npos % GT == 0 && row_u4 % 4 == 0, ISO_ERR_INTERNAL, "tile copy of %lld rows", (long long)npos);
+        hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)(npos / GT * nchunks)), dim3(256), 0, s,
+                           static_cast<const uint4 *>(P.Xr), order, nchunks, row_u4, static_cast<uint4 *>(P.Xq));
+        LAUNCH_CHECK();
+    };
+    tile_copy(P.perm, P.n_pad);
+    bool xq_plain = true;
     SA.perm = P.perm;
-    SA.Xtile = P.Xr;
+    SA.Xtile = P.Xq;
 
     int64_t ncomp = n;
     int rounds = 0, list_rounds = 0, final_components = 0;
@@ -1413,7 +1432,6 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     // then screened the plain way).
     auto final_round = [&]() -> bool {
         const int K = (int)ncomp;
-        const size_t esz = rep_bytes(rep);
         // component sizes -> padded tile order (host: at most FR_KC components)
         fill<int32_t>(P.flag, 0, K, s);
         histogram_i32(P.comp, n, K, P.flag, s);
@@ -1452,13 +1470,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         hipLaunchKernelGGL(k_fr_perm, dim3(grid_for(n, 256)), dim3(256), 0, s, P.pvals, P.comp, n, P.fr_pstart,
                            P.fr_sstart, P.permF);
         LAUNCH_CHECK();
-        {
-            const int64_t row_u4 = (int64_t)(P.d_pad * esz / 16);
-            const unsigned g = std::min<unsigned>(grid_for(ntF * GT, 4), 8u * (unsigned)device_cus());
-            hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr), P.permF,
-                               ntF * GT, row_u4, static_cast<uint4 *>(P.Xq));
-            LAUNCH_CHECK();
-        }
+        tile_copy(P.permF, ntF * GT);
+        xq_plain = false;
         ScreenArgs FA = SA;
         FA.perm = P.permF;
         FA.Xtile = P.Xq;
@@ -1615,15 +1628,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.pkeys, P.perm);
                 LAUNCH_CHECK();
                 radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, kb, P.psort, s);
-                {
-                    const size_t esz = rep_bytes(rep);
-                    const int64_t row_u4 = (int64_t)(P.d_pad * esz / 16);
-                    const unsigned g = std::min<unsigned>(grid_for(P.n_pad, 4), 8u * (unsigned)device_cus());
-                    hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr), P.perm,
-                                       P.n_pad, row_u4, static_cast<uint4 *>(P.Xq));
-                    LAUNCH_CHECK();
-                    SA.Xtile = P.Xq;
-                }
+                tile_copy(P.perm, P.n_pad);
+                xq_plain = true;
                 hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(P.nt, 256)), dim3(256), 0, s, P.perm, P.comp, n, P.nt,
                                    pair_tile(), P.tlo, P.thi);
                 LAUNCH_CHECK();
@@ -1642,6 +1648,9 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 pairs_use = P.pairs_r;
                 ndiag = hk[0];
                 noff = hk[1] - hk[0];
+            } else if (!xq_plain) {
+                tile_copy(P.perm, P.n_pad);  // after a final round that fell back
+                xq_plain = true;
             }
             if (lists == LISTS_NONE && rounds == 2) {
                 // the second round's screen builds the lists from the first

@@ -66,7 +66,8 @@ struct ScreenArgs {
     const int32_t *comp;     // [n_pad] component of each point, -1 on padding
     const int32_t *perm;     // tile-pair screen: [n_pad] point at each position of the tile order
                              // (points sorted by component, padding last)
-    const void *Xtile;       // tile-pair screen: the representation with its rows in the tile order
+    const void *Xtile;       // tile-pair screen: the representation, rows in the tile order, stored tile by
+                             // tile and chunk-major within a tile (the PT rows' bytes 64 c .. 64 c + 63 contiguous)
     ScreenBound bound;       // error bound constants
     float kappa;             // capture threshold scale (recheck order slack and rounding)
     // gathered pass (rows == nullptr for the full sweep)

@@ -227,24 +227,25 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // asynchronous staging: each wave moves RUNS 1 KB runs of slots per chunk
     // with global_load_lds_dwordx4 (lane L of a run fills slot base + L); a run
     // covers 16 rows, all columns (runs < PH / 16) or all rows
-    constexpr int CHUNK = 16 / sizeof(T);  // elements per slot
     static_assert(P::KC * sizeof(T) == 64, "one K chunk is 64 bytes per row");
-    const char *XJb = reinterpret_cast<const char *>(X + J0 * d_pad);
+    // Xtile is chunk-major within each tile: chunk C of the tile's PT rows is
+    // PT x 64 contiguous bytes, row t of the tile at byte 64 t
+    const char *XJb = reinterpret_cast<const char *>(X + (int64_t)pr.y * PT * d_pad);
     const char *XIb = reinterpret_cast<const char *>(X + I0 * d_pad);
-    uint32_t soff[RUNS];  // byte offset of this lane's slot source within its part
+    uint32_t soff[RUNS];  // byte offset of this lane's slot source within chunk 0 of its tile
 #pragma unroll
     for (int r = 0; r < RUNS; ++r) {
         const int slot = (w * RUNS + r) * 64 + lane;
         const int row = slot >> 2;
         const int part = (slot & 3) ^ ((row >> 2) & 3);
-        const int64_t local = row < PH ? row : row - PH;
-        soff[r] = (uint32_t)((local * d_pad + part * CHUNK) * (int64_t)sizeof(T));
+        const int trow = row < PH ? half * PH + row : row - PH;  // row within its tile
+        soff[r] = (uint32_t)(trow * 64 + part * 16);
     }
     const int nchunks = (int)(d_pad / P::KC);
 #define ISO_ISSUE(STG, C)                                                                                     \
     {                                                                                                        \
         _Pragma("unroll") for (int r = 0; r < RUNS; ++r) __builtin_amdgcn_global_load_lds(                  \
-            (const void *)((w * RUNS + r < PH / 16 ? XJb : XIb) + (int64_t)(C) * 64 + soff[r]),              \
+            (const void *)((w * RUNS + r < PH / 16 ? XJb : XIb) + (int64_t)(C) * (PT * 64) + soff[r]),              \
             (__attribute__((address_space(3))) void *)&STG[(w * RUNS + r) * 64], 16, 0, 0);                \
     }
 
