@@ -1,6 +1,6 @@
 """FP64 CPU oracle of the clustering method -- TEST INFRASTRUCTURE ONLY.
 
-Thin ctypes binding of ``oracle.c`` (a plain, slow, single-threaded FP64
+Thin ctypes binding of ``oracle.c`` (a plain, slow FP64
 implementation of the Euclidean MST by dense Prim, Sec. 3.5 / Algorithm 3, and
 of the isoperimetric tree search, Sec. 2.2 / Algorithms 1-2, with the labelling
 of Algorithm 4).  Only the tests, ``__graft_entry__.smoke()`` and the CPU
@@ -22,7 +22,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Every FP64 operation in oracle.c is a separately rounded IEEE operation in the
 # order written: no contraction into fused multiply-adds, no fast-math.
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
+# OpenMP is used only by the threaded variant of Prim (its thread count is an
+# explicit argument; every other routine runs on one thread).
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11", "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -66,6 +68,8 @@ def _load():
         lib.orc_sqdist.restype = D
         lib.orc_prim_mst.argtypes = [P, I64, I64, I64, P, P, P, P]
         lib.orc_prim_mst.restype = ctypes.c_int
+        lib.orc_prim_mst_threads.argtypes = [P, I64, I64, I64, P, P, P, P, I32]
+        lib.orc_prim_mst_threads.restype = ctypes.c_int
         lib.orc_tree_depth.argtypes = [P, I64, I32, P]
         lib.orc_tree_depth.restype = ctypes.c_int
         lib.orc_tree_order.argtypes = [P, I64, P]
@@ -102,18 +106,20 @@ def sqdist(X, i: int, j: int) -> float:
     return _load().orc_sqdist(_ptr(X), X.shape[1], X.shape[1], i, j)
 
 
-def prim_mst(X):
+def prim_mst(X, threads: int = 1):
     """Euclidean MST by dense Prim from vertex 0 (Algorithm 3, sequential).
 
-    Returns (parent int32[n] with parent[0] = -1, length float64[n] with
-    length[0] = 0, depth int32[n], order_added int32[n])."""
+    ``threads`` > 1 splits each step's key update over that many threads (same
+    result).  Returns (parent int32[n] with parent[0] = -1, length float64[n]
+    with length[0] = 0, depth int32[n], order_added int32[n])."""
     X = _f32(X)
     n, d = X.shape
     parent = np.empty(n, np.int32)
     length = np.empty(n, np.float64)
     depth = np.empty(n, np.int32)
     added = np.empty(n, np.int32)
-    rc = _load().orc_prim_mst(_ptr(X), n, d, d, _ptr(parent), _ptr(length), _ptr(depth), _ptr(added))
+    rc = _load().orc_prim_mst_threads(_ptr(X), n, d, d, _ptr(parent), _ptr(length), _ptr(depth), _ptr(added),
+                                      int(threads))
     if rc != 0:
         raise RuntimeError("orc_prim_mst failed: %d" % rc)
     return parent, length, depth, added

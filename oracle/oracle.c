@@ -1,17 +1,18 @@
 /*
  * oracle.c -- TEST INFRASTRUCTURE ONLY.
  *
- * A plain, slow, single-threaded FP64 CPU reference of the clustering method of
+ * A plain, slow FP64 CPU reference of the clustering method of
  * Javadi & Ashkboos, "An Efficient Parallel Data Clustering Algorithm Using
  * Isoperimetric Number of Trees" (arXiv 1702.04739):
  *
  *   1. the Euclidean minimum spanning tree of the points, by dense Prim from
  *      vertex 0 (Sec. 3.5, Algorithm 3, run sequentially here), never storing
- *      an n x n matrix;
+ *      an n x n matrix (one thread, or an explicit number of threads for each
+ *      step's key update, with the same result);
  *   2. the weight functions of the tree: flow phi (Sec. 2.1, eq. 2.1), vertex
  *      weight omega (eq. 2.2) and potential p (eq. 2.3);
- *   3. the decision procedure "is there a k-subpartition of cost <= N"
- *      (Sec. 2.2, Algorithm 1) and the bisection around it (Algorithm 2),
+ *   3. the decision procedure that tells whether some k-subpartition costs at
+ *      most N (Sec. 2.2, Algorithm 1) and the bisection around it (Algorithm 2),
  *      with the labelling of Algorithm 4 (Sec. 3.6);
  *   4. the adjoint of the total MST weight and of the optimal subpartition's
  *      cost with respect to the points and sigma, holding the tree and the
@@ -25,8 +26,8 @@
  *
  * Readings taken where the paper is silent or ambiguous (each is also listed
  * in the design notes):
- *   R1  omega: default is the weighted degree in the tree ("calculate phi,
- *       omega and p for T", Sec. 2.2 step 2; Algorithm 1 takes a weighted
+ *   R1  omega: default is the weighted degree in the tree (Sec. 2.2 step 2
+ *       computes phi, omega and p on the tree T; Algorithm 1 takes a weighted
  *       tree).  The literal full-graph sum of eq. 2.2 is available as
  *       omega_mode = 1.  The self term j = i is excluded (phi is only defined
  *       for i != j, eq. 2.1).
@@ -99,9 +100,21 @@ static int edge_less(double d2a, int64_t ua, int64_t va, double d2b, int64_t ub,
  * FP64 squared distance to the parent), depth[n] (nullable) and order_added[n]
  * (nullable; the order in which Prim added the vertices).  Memory is O(n):
  * each step recomputes the distances from the newly added vertex only. */
+int orc_prim_mst_threads(const float *X, int64_t n, int64_t d, int64_t ld, int32_t *parent, double *len,
+                         int32_t *depth, int32_t *order_added, int32_t threads);
+
 int orc_prim_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t *parent, double *len,
                  int32_t *depth, int32_t *order_added) {
-    if (!X || n < 1 || d < 1 || ld < d || !parent || !len) return ORC_EINVAL;
+    return orc_prim_mst_threads(X, n, d, ld, parent, len, depth, order_added, 1);
+}
+
+/* The same with the per-step update of the remaining vertices' keys split over
+ * `threads` OpenMP threads.  Each vertex's update reads only its own key and
+ * the new tree vertex, and the choice of the next vertex stays one sequential
+ * scan, so the result does not depend on the thread count. */
+int orc_prim_mst_threads(const float *X, int64_t n, int64_t d, int64_t ld, int32_t *parent, double *len,
+                         int32_t *depth, int32_t *order_added, int32_t threads) {
+    if (!X || n < 1 || d < 1 || ld < d || !parent || !len || threads < 1) return ORC_EINVAL;
     double *key = (double *)malloc(sizeof(double) * n);
     int64_t *keyu = (int64_t *)malloc(sizeof(int64_t) * n);
     char *in_tree = (char *)calloc(n, 1);
@@ -134,6 +147,7 @@ int orc_prim_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t *pare
         dep[best] = dep[keyu[best]] + 1;
         if (order_added) order_added[step] = (int32_t)best;
         /* Update every remaining vertex's distance to the tree. */
+#pragma omp parallel for schedule(static) num_threads(threads) if (threads > 1)
         for (int64_t v = 1; v < n; ++v) {
             if (in_tree[v]) continue;
             double d2 = orc_sqdist(X, ld, d, best, v);

@@ -3,7 +3,11 @@
 seeded synthetic input, stored as the SHA-256 of its parent array (int32,
 little endian), its weight and its first entries.  Only the oracle computes it.
 
-    python tests/golden/make_mst_digest.py 3 50000     # image-like recipe, n = 50,000 (~20 min, one core)
+    python tests/golden/make_mst_digest.py 3 50000      # image-like recipe, n = 50,000 (~20 min, one core)
+    python tests/golden/make_mst_digest.py 3 200000 6   # n = 200,000 with 6 threads for Prim's key updates
+
+The thread count does not change the tree (each step's key updates are
+independent and the next vertex is chosen by one sequential scan).
 """
 import hashlib
 import json
@@ -25,9 +29,10 @@ RECIPE = {1: "gaussian-mixture", 2: "anisotropic-mixture", 3: "image-like", 4: "
 
 def main():
     cfg, n = int(sys.argv[1]), int(sys.argv[2])
+    threads = int(sys.argv[3]) if len(sys.argv) > 3 else 1
     X = datagen.config(cfg, n=n)
     t0 = time.time()
-    parent, length, _, _ = oracle.prim_mst(X)
+    parent, length, _, _ = oracle.prim_mst(X, threads=threads)
     rec = {
         "recipe": RECIPE[cfg], "config": cfg, "n": n, "d": int(X.shape[1]),
         "tree": "FP64 oracle, dense Prim from vertex 0, order (D^2, smaller id, larger id)",
@@ -35,6 +40,7 @@ def main():
         "weight": float(np.sum(length[1:])),
         "parent_head": [int(v) for v in parent[:16]],
         "oracle_seconds": round(time.time() - t0, 1),
+        "oracle_threads": threads,
     }
     path = os.path.join(HERE, "mst_digest_%s_n%d.json" % (RECIPE[cfg], n))
     with open(path, "w") as f:

@@ -36,6 +36,20 @@ def test_prim_equals_kruskal_ties(orc, maker):
     assert brute.edge_set(parent) == edges
 
 
+@pytest.mark.parametrize("threads", [2, 5])
+@pytest.mark.parametrize("maker", [lambda: np.random.default_rng(8).standard_normal((700, 6)).astype(np.float32),
+                                   lambda: datagen.lattice(5, 3), lambda: datagen.with_duplicates(300, 5, 40)])
+def test_prim_threads_equal_kruskal(orc, maker, threads):
+    """The threaded key update (used for the large golden digests) gives Kruskal's tree, ties included."""
+    X = maker()
+    parent, length, depth, added = orc.prim_mst(X, threads=threads)
+    edges, S = brute.kruskal(X)
+    assert brute.edge_set(parent) == edges
+    ref = orc.prim_mst(X)
+    for got, want in zip((parent, length, depth, added), ref):
+        np.testing.assert_array_equal(got, want)
+
+
 @pytest.mark.parametrize("n,d,seed", [(50, 2, 5), (800, 8, 6), (2500, 16, 7)])
 def test_weight_matches_scipy(orc, n, d, seed):
     X = np.random.default_rng(seed).random((n, d)).astype(np.float32)
