@@ -14,6 +14,9 @@ arithmetic can check one by one, and properties that hold at any size.
   - the tree stage equals the oracle's tree stage on the same tree: labels
     identical, i_k within 1e-12.
 """
+import glob
+import os
+
 import numpy as np
 import pytest
 
@@ -144,20 +147,24 @@ def test_tree_stage_matches_oracle(c3):
                                    info["sub"]["jstar"])
 
 
+_DIGESTS = sorted(glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                         "mst_digest_image-like_n*.json")),
+                  key=lambda p: int(p.rsplit("_n", 1)[1].split(".")[0]))
+
+
+@pytest.mark.parametrize("path", _DIGESTS, ids=[os.path.basename(p)[len("mst_digest_"):-5] for p in _DIGESTS])
 @pytest.mark.parametrize("precision", ["bf16", "int8"])
-def test_mst_matches_oracle_digest_image_like_n50000(precision):
-    """Exact parity at scale: the image-like recipe at n = 50,000 (neighbour-list
-    and final rounds included) gives, with the FP64 recheck, the oracle's tree
-    bit for bit (its parent array's SHA-256, stored by
+def test_mst_matches_oracle_digest_image_like(precision, path):
+    """Exact parity at scale: the image-like recipe at n = 50,000 and above
+    (neighbour-list and final rounds included) gives, with the FP64 recheck,
+    the oracle's tree bit for bit (its parent array's SHA-256, stored by
     tests/golden/make_mst_digest.py, which runs only the oracle)."""
     import hashlib
     import json
-    import os
 
     import paper_1702_04739_amd as iso
     from paper_1702_04739_amd import datagen
 
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mst_digest_image-like_n50000.json")
     with open(path) as f:
         rec = json.load(f)
     X = torch.from_numpy(datagen.config(3, n=rec["n"])).cuda()
