@@ -1411,7 +1411,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     const int64_t row_u4 = (int64_t)(P.d_pad * rep_bytes(rep) / 16);
     auto tile_copy = [&](const int32_t *order, int64_t npos) {
         const int64_t nchunks = row_u4 / 4;
-        ISO_REQUIRE(npos % GT == 0 && row_u4 % 4 == 0, ISO_ERR_INTERNAL, "tile copy of %lld rows", (long long)npos);
+        ISO_REQUIRE(npos % GT == 0 && row_u4 % 4 == 0 && npos / GT * nchunks <= (int64_t)UINT32_MAX, ISO_ERR_INTERNAL,
+                    "tile copy of %lld rows", (long long)npos);
         hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)(npos / GT * nchunks)), dim3(256), 0, s,
                            static_cast<const uint4 *>(P.Xr), order, nchunks, row_u4, static_cast<uint4 *>(P.Xq));
         LAUNCH_CHECK();
