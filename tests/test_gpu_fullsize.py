@@ -175,3 +175,27 @@ def test_mst_matches_oracle_digest_image_like(precision, path):
     assert [int(v) for v in p[:16]] == rec["parent_head"]
     assert hashlib.sha256(p.astype("<i4").tobytes()).hexdigest() == rec["parent_sha256"]
     assert abs(info["mst_weight"] - rec["weight"]) <= 1e-12 * rec["weight"]
+
+
+@pytest.mark.parametrize("path", _DIGESTS, ids=[os.path.basename(p)[len("mst_digest_"):-5] for p in _DIGESTS])
+def test_fp32_recheck_weight_matches_oracle_digest(path):
+    """The configuration the benchmark times (BF16 screen + FP32 recheck) against
+    the oracle at scale: the FP32 recheck may swap certified near ties, so its
+    MST weight must equal the oracle's within 1e-6 (the FP32-recheck bar); the
+    log says whether the parent array is also the oracle's."""
+    import hashlib
+    import json
+
+    import paper_1702_04739_amd as iso
+
+    with open(path) as f:
+        rec = json.load(f)
+    X = torch.from_numpy(datagen.config(3, n=rec["n"])).cuda()
+    H.log("digest weight image-like n=%d bf16 + fp32 recheck" % rec["n"])
+    parent, length, info = iso.mst(X, precision="bf16", recheck="fp32")
+    p = parent.cpu().numpy()
+    same = hashlib.sha256(p.astype("<i4").tobytes()).hexdigest() == rec["parent_sha256"]
+    H.log("  weight %.17g oracle %.17g, parent array %s" % (info["mst_weight"], rec["weight"],
+                                                             "identical" if same else "differs (near ties)"))
+    assert info["screen_precision"] == "bf16"
+    assert abs(info["mst_weight"] - rec["weight"]) <= 1e-6 * rec["weight"]
