@@ -60,7 +60,7 @@ constexpr int NIB = RW / 32, NJB = CW / 32;
 constexpr int RUNS = SROWS * 4 / 64 / NW;  // 1 KB DMA runs per wave and chunk
 constexpr int NPRE = (PT + PH + 64 * NW - 1) / (64 * NW);
 #ifndef PAIR_SB
-#define PAIR_SB 8                      // tile pairs are ordered in blocks of PAIR_SB x PAIR_SB tiles
+#define PAIR_SB 4                      // tile pairs are ordered in blocks of PAIR_SB x PAIR_SB tiles
 #endif
 static_assert(RUNS * NW * 64 == SROWS * 4, "runs cover the staged slots");
 static_assert(PH % 16 == 0, "a run never straddles the column and row parts");
