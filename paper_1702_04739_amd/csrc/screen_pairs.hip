@@ -26,7 +26,11 @@
 // [64 wj, +64) as 4 x 2 blocks of the transposed 32 x 32 MFMA (MFMA rows =
 // columns j, MFMA columns = rows i; result register q of lane l is MFMA row
 // 8 (q div 4) + 4 (l div 32) + (q mod 4), MFMA column l mod 32): BF16
-// 32x32x16, FP8 E4M3 32x32x64 (unit block scales) or FP32 32x32x2.
+// 32x32x16, FP8 E4M3 32x32x64 (unit block scales), INT8 32x32x32 (int32
+// accumulate) or FP32 32x32x2.  The operands come from a copy of the
+// representation stored chunk-major within each tile (the 64-byte K chunk c
+// of a tile's PT rows is contiguous), so each wave's 1 KB DMA run of a chunk
+// reads eight consecutive whole cache lines.
 //
 // Tiles are runs of 256 positions of a tile order (A.perm maps positions to
 // points); once components are large the order groups points by component
