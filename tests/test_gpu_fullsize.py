@@ -199,3 +199,39 @@ def test_fp32_recheck_weight_matches_oracle_digest(path):
                                                              "identical" if same else "differs (near ties)"))
     assert info["screen_precision"] == "bf16"
     assert abs(info["mst_weight"] - rec["weight"]) <= 1e-6 * rec["weight"]
+
+
+_OTHER_DIGESTS = sorted(p for p in glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                                           "mst_digest_*_n*.json")) if "image-like" not in p)
+
+
+@pytest.mark.parametrize("path", _OTHER_DIGESTS,
+                         ids=[os.path.basename(p)[len("mst_digest_"):-5] for p in _OTHER_DIGESTS])
+@pytest.mark.parametrize("precision,recheck", [("fp32", "fp64"), ("bf16", "fp64"), ("fp32", "fp32")])
+def test_mst_matches_oracle_digest_gaussian_recipes(precision, recheck, path):
+    """Full-size parity on the Gaussian workloads (values off any binary grid,
+    so a BF16 request hands over to the FP32 screen): with the FP64 recheck
+    the parent array is the oracle's (SHA-256 stored by the oracle-only
+    tests/golden/make_mst_digest.py); with the FP32 recheck the MST weight is
+    within 1e-6 of the oracle's."""
+    import hashlib
+    import json
+
+    import paper_1702_04739_amd as iso
+
+    with open(path) as f:
+        rec = json.load(f)
+    X = torch.from_numpy(datagen.config(rec["config"], n=rec["n"])).cuda()
+    H.log("digest %s n=%d d=%d %s + %s recheck" % (rec["recipe"], rec["n"], rec["d"], precision, recheck))
+    parent, length, info = iso.mst(X, precision=precision, recheck=recheck)
+    H.log("  info %s" % info)
+    p = parent.cpu().numpy()
+    same = hashlib.sha256(p.astype("<i4").tobytes()).hexdigest() == rec["parent_sha256"]
+    if recheck == "fp64":
+        assert [int(v) for v in p[:16]] == rec["parent_head"]
+        assert same
+        assert abs(info["mst_weight"] - rec["weight"]) <= 1e-12 * rec["weight"]
+    else:
+        H.log("  weight %.17g oracle %.17g, parent array %s" % (info["mst_weight"], rec["weight"],
+                                                                 "identical" if same else "differs (near ties)"))
+        assert abs(info["mst_weight"] - rec["weight"]) <= 1e-6 * rec["weight"]
