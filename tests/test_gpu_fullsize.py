@@ -207,7 +207,7 @@ _OTHER_DIGESTS = sorted(p for p in glob.glob(os.path.join(os.path.dirname(os.pat
 
 @pytest.mark.parametrize("path", _OTHER_DIGESTS,
                          ids=[os.path.basename(p)[len("mst_digest_"):-5] for p in _OTHER_DIGESTS])
-@pytest.mark.parametrize("precision,recheck", [("fp32", "fp64"), ("bf16", "fp64"), ("fp32", "fp32")])
+@pytest.mark.parametrize("precision,recheck", [("fp32", "fp64"), ("bf16", "fp64"), ("fp8", "fp64"), ("fp32", "fp32")])
 def test_mst_matches_oracle_digest_gaussian_recipes(precision, recheck, path):
     """Full-size parity on the Gaussian workloads (values off any binary grid,
     so a BF16 request hands over to the FP32 screen): with the FP64 recheck
