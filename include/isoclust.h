@@ -75,12 +75,13 @@ typedef int32_t iso_status;
  *         rounded separately (parity mode). */
 #define ISO_RECHECK_FP32 0
 #define ISO_RECHECK_FP64 1
-/* Options of iso_mst, OR-ed into `recheck` (the tree is the same with any of
- * them; they select which rounds may skip the full screen). */
-#define ISO_MST_NO_LISTS 0x100 /* no neighbour lists from the second round    */
-#define ISO_MST_NO_FINAL 0x200 /* no final round joining <= 64 components    */
-#define ISO_MST_NO_ESCALATE 0x400 /* keep the requested screen precision even
-                                     when its bound is too loose for the data  */
+/* Bits of iso_mst's `flags` argument (0 = every shortcut allowed).  The tree is
+ * the same with any of them: they only select which rounds may skip the full
+ * screen and which screen precision may run. */
+#define ISO_MST_NO_LISTS 0x1    /* no neighbour lists from the second round    */
+#define ISO_MST_NO_FINAL 0x2    /* no final round joining <= 64 components    */
+#define ISO_MST_NO_ESCALATE 0x4 /* keep the requested screen precision even
+                                   when its bound is too loose for the data  */
 
 /* Vertex weight omega (eq. 2.2) and flow phi (eq. 2.1) readings. */
 #define ISO_OMEGA_TREE 0   /* omega(v) = sum of phi over v's tree edges         */
@@ -120,8 +121,10 @@ iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_
  * round may be decided by the neighbour lists the second round's screen
  * builds, and once at most 64 components remain one final round joins them
  * all (both are switched off by ISO_MST_NO_LISTS / ISO_MST_NO_FINAL in
- * `recheck`; the tree does not change).
+ * `flags`; the tree does not change).
  *   X       [n*ld] FP32 points (read only).
+ *   precision  ISO_PREC_* of the screen;  recheck  ISO_RECHECK_* (edge order);
+ *   flags   OR of ISO_MST_NO_* bits, or 0.
  *   parent  [n] out: tree rooted at vertex 0, parent[0] = -1.
  *   length  [n] out: FP64 Euclidean length of the edge (v, parent[v]),
  *                    sqrt of the left-to-right FP64 sum of squared coordinate
@@ -131,10 +134,11 @@ iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_
  *           library then allocates and frees it on `stream`).
  *   stream  HIP stream (NULL: the default stream); the call synchronises it.
  * Errors: n < 2, d < 1, ld < d, null pointers, unknown precision, recheck or
- * option bits (INVALID_ARG); a non-finite coordinate (NONFINITE); the INT8
+ * flag bits (INVALID_ARG); a non-finite coordinate (NONFINITE); the INT8
  * screen on data that is not 8-bit (INVALID_ARG). */
 iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t precision, int32_t recheck,
-                   int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes, void *stream);
+                   uint32_t flags, int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes,
+                   void *stream);
 
 /* The paper's own MST construction (Sec. 3.5, Algorithm 3), kept for
  * comparison with iso_mst: Prim from vertex 0, adding per step the vertex with
@@ -201,10 +205,11 @@ iso_status iso_subpartition(const int32_t *parent, const double *length, int64_t
                             double *cluster_num, double *cluster_den, int32_t *cluster_size, iso_sub_info *info,
                             void *ws, size_t ws_bytes, void *stream);
 
-/* The optimal k-subpartition for every k = 2 .. kmax of one tree (the same
- * bisection, final bracket and labels as kmax - 1 separate iso_subpartition
- * calls, each k walking its own bisection; the passes evaluate the midpoints
- * of several k together).
+/* The optimal k-subpartition for every k = 2 .. kmax of one tree: MISO_k of
+ * eq. 2.6 for each k, each by Algorithm 1 inside its own bisection of
+ * Algorithm 2 (Sec. 2.2), labelled as in Algorithm 4 -- the same bisection,
+ * final bracket and labels as kmax - 1 separate iso_subpartition calls; the
+ * passes evaluate the midpoints of several k together.
  *   i_k     (host) [kmax - 1] out: MISO_k for k = 2 .. kmax.
  *   labels  [(kmax - 1) * n] out (nullable): row k - 2 holds the labels for k.
  *   passes  (host, nullable) out: tree passes used.

@@ -293,38 +293,86 @@ int orc_tree_weights(const int32_t *parent, const double *len, int64_t n, int32_
 /* Algorithm 1: decision "exists A in D_k(X) with cost(A) <= N"         */
 /* ------------------------------------------------------------------ */
 
-/* Runs Algorithm 1 over the x-order.  Returns the number of cut vertices j
- * reached (<= k); the answer is YES iff the return value equals k.
- * When rec_cut is non-NULL the first j cut vertices (in x-order) are stored
- * with their phi(delta A)+p(A) in rec_num and omega(A) in rec_den, and
- * joined[v] = 1 marks the vertices that joined their parent (eta(u) <- eta(u)
- * U eta(x)).  Vertices never reached keep joined = 0. */
+/* Decision "is there a k-subpartition of cost at most N" (Sec. 2.2,
+ * Algorithm 1), written as a fold over the rooted tree.
+ *
+ * Each vertex x owns a pending set eta(x): x itself plus the descendants that
+ * were merged into it.  Two numbers describe eta(x) once all of x's children
+ * are settled: its weight w(x) = omega(eta(x)) and its charge p(x) = the
+ * potential of eta(x) plus the flow of the tree edges that leave eta(x)
+ * downwards (to children that were not merged).  The only edge of eta(x) not
+ * yet accounted for is x's parent edge e, of flow fe (0 at the root).
+ *
+ * By eq. 2.4, eta(x) is a valid cluster at level N when its cost, parent edge
+ * included, is at most N:   fe + p(x) <= N w(x)   ->  x is CUT (a cluster).
+ * Otherwise eta(x) is either merged into the parent's set, or left behind as
+ * residual vertices.  Either way the parent's own test N w - p changes:
+ *   merged:  w += w(x), p += p(x)     (e becomes an inner edge),
+ *   left:    p += fe                  (e becomes a boundary edge of the parent).
+ * Merging is taken when it leaves the parent more room, i.e. when
+ * N w(x) - p(x) > -fe, evaluated as   p(x) - fe < N w(x)   ->  x is JOINED;
+ * else x is DROPPED.  A cut child also puts its edge on the parent's boundary
+ * (p += fe).  The root has no parent edge and can only be cut or dropped.
+ *
+ * Vertices are settled in x-order (children before parents); a vertex folds its
+ * children's outcomes in ascending child id.  The sweep stops at the k-th cut.
+ * Returns the number of cuts reached (<= k); the answer is YES iff it equals k.
+ * wbuf/pbuf [n] receive w and p of the settled vertices.  With rec_cut the
+ * first cuts (in x-order) are stored with fe + p(x) in rec_num and w(x) in
+ * rec_den, and joined[v] = 1 marks the merged vertices.  Returns -1 when its
+ * scratch memory cannot be allocated. */
+enum { ORC_OPEN = 0, ORC_CUT = 1, ORC_JOINED = 2, ORC_DROPPED = 3 };
+
 int64_t orc_decide(const int32_t *parent, const int32_t *order, const double *phi, const double *omega0,
                    const double *p0, int64_t n, int64_t k, double N, double *wbuf, double *pbuf,
                    int32_t *rec_cut, double *rec_num, double *rec_den, uint8_t *joined) {
-    memcpy(wbuf, omega0, sizeof(double) * n);
-    memcpy(pbuf, p0, sizeof(double) * n);
+    /* children of every vertex in ascending id (counting sort on the parent) */
+    int64_t *first = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *kids = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t *state = (uint8_t *)calloc((size_t)n, 1);
+    if (!first || !kids || !state) { free(first); free(kids); free(state); return -1; }
+    for (int64_t v = 0; v < n; ++v) if (parent[v] >= 0) first[parent[v] + 1]++;
+    for (int64_t u = 0; u < n; ++u) first[u + 1] += first[u];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        if (!fill) { free(first); free(kids); free(state); return -1; }
+        memcpy(fill, first, sizeof(int64_t) * (size_t)n);
+        for (int64_t v = 0; v < n; ++v) if (parent[v] >= 0) kids[fill[parent[v]]++] = (int32_t)v;
+        free(fill);
+    }
     if (joined) memset(joined, 0, (size_t)n);
-    int64_t j = 0;
-    for (int64_t i = 0; i < n && j < k; ++i) {
-        int32_t x = order[i];
-        int32_t u = parent[x];
-        double fe = (u >= 0) ? phi[x] : 0.0;
-        double lhs_cut = fe + pbuf[x];
-        double rhs = N * wbuf[x];
-        if (lhs_cut <= rhs) {
-            if (rec_cut) { rec_cut[j] = x; rec_num[j] = lhs_cut; rec_den[j] = wbuf[x]; }
-            j = j + 1;
-            if (u >= 0) pbuf[u] = pbuf[u] + fe;
-        } else if (u >= 0 && (pbuf[x] - fe) < rhs) {
+
+    int64_t cuts = 0;
+    for (int64_t i = 0; i < n && cuts < k; ++i) {
+        const int32_t x = order[i];
+        double w = omega0[x], p = p0[x];
+        for (int64_t c = first[x]; c < first[x + 1]; ++c) {
+            const int32_t y = kids[c];
+            if (state[y] == ORC_JOINED) {
+                w = w + wbuf[y];
+                p = p + pbuf[y];
+            } else {
+                p = p + phi[y];   /* cut or dropped child: its edge bounds eta(x) */
+            }
+        }
+        wbuf[x] = w;
+        pbuf[x] = p;
+        const int has_parent = parent[x] >= 0;
+        const double fe = has_parent ? phi[x] : 0.0;
+        const double room = N * w;
+        if (fe + p <= room) {
+            state[x] = ORC_CUT;
+            if (rec_cut) { rec_cut[cuts] = x; rec_num[cuts] = fe + p; rec_den[cuts] = w; }
+            cuts = cuts + 1;
+        } else if (has_parent && p - fe < room) {
+            state[x] = ORC_JOINED;
             if (joined) joined[x] = 1;
-            wbuf[u] = wbuf[u] + wbuf[x];
-            pbuf[u] = pbuf[u] + pbuf[x];
-        } else if (u >= 0) {
-            pbuf[u] = pbuf[u] + fe;
+        } else {
+            state[x] = ORC_DROPPED;
         }
     }
-    return j;
+    free(first); free(kids); free(state);
+    return cuts;
 }
 
 /* ------------------------------------------------------------------ */
@@ -431,20 +479,21 @@ int orc_subpartition(const int32_t *parent, const double *len, int64_t n, int32_
         goto done;
     }
 
-    /* Algorithm 2: bisection; decide(beta) stays YES throughout. */
+    /* Algorithm 2: MISO_k lies in (lo, hi] with decide(hi) = YES.  Each step
+     * asks decide at the FP64 midpoint and keeps the half that still holds the
+     * threshold; it ends when no double lies strictly between the two ends
+     * (FP64 resolution, R7) or after max_iters steps. */
     {
-        double a = info->alpha0, b = info->beta0;
-        int32_t it = 0;
-        while (it < max_iters) {
-            double mid = (a + b) / 2.0;
-            if (mid <= a || mid >= b) break;
-            if (orc_decide(parent, order, phi, om, p0, n, k, mid, wb, pb, NULL, NULL, NULL, NULL) == k)
-                b = mid;
-            else
-                a = mid;
-            it = it + 1;
+        double lo = info->alpha0, hi = info->beta0;
+        int32_t steps = 0;
+        for (; steps < max_iters; ++steps) {
+            const double mid = (lo + hi) / 2.0;
+            if (!(lo < mid && mid < hi)) break;
+            const int64_t cuts = orc_decide(parent, order, phi, om, p0, n, k, mid, wb, pb, NULL, NULL, NULL, NULL);
+            if (cuts < 0) { rc = ORC_ENOMEM; goto done; }
+            if (cuts == k) hi = mid; else lo = mid;
         }
-        info->alpha = a; info->beta = b; info->iters = it;
+        info->alpha = lo; info->beta = hi; info->iters = steps;
     }
 
     /* Final decision at beta, recording Cut and eta (Algorithm 4). */

@@ -69,9 +69,10 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     parent = torch.empty(n, dtype=torch.int32, device=dev)
     length = torch.empty(n, dtype=torch.float64, device=dev)
     info = _lib.MstInfo()
-    flags = (_lib.RECHECK[recheck] | (0 if lists else _lib.MST_NO_LISTS) | (0 if final_round else _lib.MST_NO_FINAL)
+    flags = ((0 if lists else _lib.MST_NO_LISTS) | (0 if final_round else _lib.MST_NO_FINAL)
              | (0 if escalate else _lib.MST_NO_ESCALATE))
-    rc = lib.iso_mst(ctypes.c_void_p(points.data_ptr()), n, d, ld, _lib.PRECISION[precision], flags,
+    rc = lib.iso_mst(ctypes.c_void_p(points.data_ptr()), n, d, ld, _lib.PRECISION[precision], _lib.RECHECK[recheck],
+                     flags,
                      ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), ctypes.byref(info),
                      ctypes.c_void_p(ws.data_ptr()), int(need.value), _stream_ptr(dev))
     _lib.check(rc, "iso_mst")
@@ -278,20 +279,22 @@ def _make_autograd():
         """(W, i_k, labels) = MSTIsoCost.apply(points, sigma, k, precision, recheck, phi).
 
         W is the total MST length and i_k = MISO_k of the tree with phi at scale
-        ``sigma`` (a 0-d tensor or float).  The backward pass holds the tree and
-        the optimal subpartition fixed and differentiates W and the cost of the
-        cluster attaining i_k with respect to the points and sigma."""
+        ``sigma`` (a 0-d tensor or float; None or 0 selects the lower median
+        MST edge length, which is then a constant with no gradient).  The
+        backward pass holds the tree and the optimal subpartition fixed and
+        differentiates W and the cost of the cluster attaining i_k with respect
+        to the points and (when given) sigma."""
 
         @staticmethod
         def forward(ctx, points, sigma, k, precision="fp32", recheck="fp32", phi="exp"):
-            sig = float(sigma)
+            sig = 0.0 if sigma is None else float(sigma)
             parent, length, minfo = mst(points.detach(), precision=precision, recheck=recheck)
             labels, ik, sinfo = isoperimetric_subpartition(parent, length, int(k), sigma=sig, phi=phi)
             ctx.save_for_backward(points.detach(), parent, labels)
             ctx.jstar = sinfo["jstar"]
-            ctx.sigma = sig
+            ctx.sigma = sinfo["sigma"]  # the scale actually used (the median when sig == 0)
             ctx.phi = phi
-            ctx.sigma_is_tensor = isinstance(sigma, torch.Tensor)
+            ctx.sigma_grad = isinstance(sigma, torch.Tensor) and sig != 0.0
             ctx.mark_non_differentiable(labels)
             W = torch.tensor(minfo["mst_weight"], dtype=torch.float64, device=points.device)
             I = torch.tensor(ik, dtype=torch.float64, device=points.device)
@@ -303,7 +306,7 @@ def _make_autograd():
             gw = float(gW) if gW is not None else 0.0
             gi = float(gI) if gI is not None else 0.0
             gX, gs, _ = adjoint(points, parent, labels, ctx.jstar, ctx.sigma, gw, gi, ctx.phi)
-            gsig = torch.tensor(gs, dtype=torch.float64, device=points.device) if ctx.sigma_is_tensor else None
+            gsig = torch.tensor(gs, dtype=torch.float64, device=points.device) if ctx.sigma_grad else None
             return gX, gsig, None, None, None, None
 
     return MSTIsoCost

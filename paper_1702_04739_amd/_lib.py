@@ -19,9 +19,9 @@ ERRORS = {
 }
 PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2, "int8": 3}
 RECHECK = {"fp32": 0, "fp64": 1}
-MST_NO_LISTS = 0x100
-MST_NO_FINAL = 0x200
-MST_NO_ESCALATE = 0x400
+MST_NO_LISTS = 0x1
+MST_NO_FINAL = 0x2
+MST_NO_ESCALATE = 0x4
 OMEGA = {"tree": 0, "full": 1}
 PHI = {"exp": 0, "gauss_sq": 1}
 BRACKET = {"pow2": 0, "paper": 1}
@@ -81,7 +81,7 @@ def load(build_if_missing: bool = True):
     lib = ctypes.CDLL(LIB_PATH)
     P, I64, I32, D, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
     lib.iso_mst_workspace_size.argtypes = [I64, I64, I32, ctypes.POINTER(SZ)]
-    lib.iso_mst.argtypes = [P, I64, I64, I64, I32, I32, P, P, ctypes.POINTER(MstInfo), P, SZ, P]
+    lib.iso_mst.argtypes = [P, I64, I64, I64, I32, I32, ctypes.c_uint32, P, P, ctypes.POINTER(MstInfo), P, SZ, P]
     lib.iso_sub_workspace_size.argtypes = [I64, I32, ctypes.POINTER(SZ)]
     lib.iso_subpartition.argtypes = [P, P, I64, I32, I32, D, ctypes.POINTER(SubOpts), P, ctypes.POINTER(D), P, P, P,
                                      ctypes.POINTER(SubInfo), P, SZ, P]

@@ -229,23 +229,85 @@ extern "C" iso_status iso_backward_workspace_size(int64_t n, size_t *bytes) {
     });
 }
 
+namespace iso {
+namespace {
+
+void check_backward_args(const float *X, int64_t n, int64_t d, int64_t ld, const int32_t *parent,
+                         const int32_t *labels, double sigma, int32_t phi_kind, double gW, double gI, const float *gX,
+                         int64_t ldg, const double *gsigma) {
+    ISO_REQUIRE(X && parent && labels && gX && gsigma, ISO_ERR_INVALID_ARG,
+                "X, parent, labels, gX and gsigma must be non-NULL");
+    ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - 2, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+    ISO_REQUIRE(d >= 1 && ld >= d && ldg >= d, ISO_ERR_INVALID_ARG, "need d >= 1, ld >= d, ldg >= d");
+    ISO_REQUIRE(sigma > 0.0 && std::isfinite(sigma), ISO_ERR_INVALID_ARG, "sigma = %g must be positive", sigma);
+    ISO_REQUIRE(phi_kind == ISO_PHI_EXP_DIST || phi_kind == ISO_PHI_GAUSS_SQ, ISO_ERR_INVALID_ARG,
+                "unknown phi %d", phi_kind);
+    ISO_REQUIRE(std::isfinite(gW) && std::isfinite(gI), ISO_ERR_INVALID_ARG, "gW and gI must be finite");
+}
+
+// The adjoint proper, on a workspace of at least bw_bytes(n) bytes.  Every
+// buffer that must start at a known value is set by a kernel or a copy here,
+// so the workspace may hold anything (e.g. a previous call's state).
+void run_backward(const float *X, int64_t n, int64_t d, int64_t ld, const int32_t *parent, const int32_t *labels,
+                  int32_t jstar, double sigma, int32_t phi_kind, double gW, double gI, float *gX, int64_t ldg,
+                  double *gsigma, double *I_out, void *ws, size_t ws_bytes, hipStream_t s) {
+    BwPlan P{};
+    P.n = n;
+    Arena a{static_cast<char *>(ws), 0, ws_bytes};
+    P.carve(a);
+    const unsigned gn = grid_for(n, 256);
+    hipLaunchKernelGGL(k_fill_b<int32_t>, dim3(gn), dim3(256), 0, s, P.nchild, 0, n + 1);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fill_b<int32_t>, dim3(1), dim3(64), 0, s, P.ndeg, 0, (int64_t)1);
+    LAUNCH_CHECK();
+    BwState h0{};
+    HIP_CHECK(hipMemcpyAsync(P.st, &h0, sizeof(h0), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bw_edges, dim3(gn), dim3(256), 0, s, X, n, d, ld, parent, labels, jstar, sigma, phi_kind,
+                       P.De, P.phi, P.kind, P.nchild, P.st);
+    LAUNCH_CHECK();
+    BwState h{};
+    HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(h.bad == 0, ISO_ERR_INVALID_ARG, "parent entries must be -1 or in [0, n)");
+    hipLaunchKernelGGL(k_bw_sums, dim3(1), dim3(1024), 0, s, P.phi, P.kind, n, P.st);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bw_coef, dim3(gn), dim3(256), 0, s, P.De, P.phi, P.kind, parent, n, sigma, phi_kind, gW, gI,
+                       P.st, P.coef, P.sterm, P.ndeg);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bw_sigma, dim3(1), dim3(1024), 0, s, P.sterm, n, P.st);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bw_keys, dim3(gn), dim3(256), 0, s, parent, n, P.key, P.val);
+    LAUNCH_CHECK();
+    radix_sort_pairs_u32(P.key, P.val, P.tk, P.tv, n, bits_of(n), P.sort_scratch, s);
+    exclusive_scan_i32(P.nchild, P.koff, n + 1, nullptr, nullptr, s);
+    // vertices without a parent sort first (key 0); the child lists follow
+    int32_t total_children = 0;
+    HIP_CHECK(hipMemcpyAsync(&total_children, P.koff + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    const int64_t nroots = n - total_children;
+    hipLaunchKernelGGL(k_bw_scatter, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, parent, P.coef,
+                       P.val + nroots, P.koff, gX, ldg);
+    LAUNCH_CHECK();
+    HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    *gsigma = h.gs;
+    if (I_out) {
+        const double den = 2.0 * h.inner + h.num;
+        *I_out = den > 0.0 ? h.num / den : 0.0;
+    }
+}
+
+}  // namespace
+}  // namespace iso
+
 extern "C" iso_status iso_backward(const float *X, int64_t n, int64_t d, int64_t ld, const int32_t *parent,
                                    const int32_t *labels, int32_t jstar, double sigma, int32_t phi_kind, double gW,
                                    double gI, float *gX, int64_t ldg, double *gsigma, double *I_out, void *ws,
                                    size_t ws_bytes, void *stream) {
     return guarded([&] {
-        ISO_REQUIRE(X && parent && labels && gX && gsigma, ISO_ERR_INVALID_ARG,
-                    "X, parent, labels, gX and gsigma must be non-NULL");
-        ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - 2, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
-        ISO_REQUIRE(d >= 1 && ld >= d && ldg >= d, ISO_ERR_INVALID_ARG, "need d >= 1, ld >= d, ldg >= d");
-        ISO_REQUIRE(sigma > 0.0 && std::isfinite(sigma), ISO_ERR_INVALID_ARG, "sigma = %g must be positive", sigma);
-        ISO_REQUIRE(phi_kind == ISO_PHI_EXP_DIST || phi_kind == ISO_PHI_GAUSS_SQ, ISO_ERR_INVALID_ARG,
-                    "unknown phi %d", phi_kind);
-        ISO_REQUIRE(std::isfinite(gW) && std::isfinite(gI), ISO_ERR_INVALID_ARG, "gW and gI must be finite");
+        check_backward_args(X, n, d, ld, parent, labels, sigma, phi_kind, gW, gI, gX, ldg, gsigma);
         require_device();
         hipStream_t s = static_cast<hipStream_t>(stream);
-        BwPlan P{};
-        P.n = n;
         const size_t need = bw_bytes(n);
         ScopedWorkspace owned;
         if (ws == nullptr) {
@@ -255,47 +317,7 @@ extern "C" iso_status iso_backward(const float *X, int64_t n, int64_t d, int64_t
             ws_bytes = need;
         }
         ISO_REQUIRE(ws_bytes >= need, ISO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
-        Arena a{static_cast<char *>(ws), 0, ws_bytes};
-        P.carve(a);
-        const unsigned gn = grid_for(n, 256);
-        hipLaunchKernelGGL(k_fill_b<int32_t>, dim3(gn), dim3(256), 0, s, P.nchild, 0, n + 1);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_fill_b<int32_t>, dim3(1), dim3(64), 0, s, P.ndeg, 0, (int64_t)1);
-        LAUNCH_CHECK();
-        BwState h0{};
-        HIP_CHECK(hipMemcpyAsync(P.st, &h0, sizeof(h0), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_bw_edges, dim3(gn), dim3(256), 0, s, X, n, d, ld, parent, labels, jstar, sigma, phi_kind,
-                           P.De, P.phi, P.kind, P.nchild, P.st);
-        LAUNCH_CHECK();
-        BwState h{};
-        HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        ISO_REQUIRE(h.bad == 0, ISO_ERR_INVALID_ARG, "parent entries must be -1 or in [0, n)");
-        hipLaunchKernelGGL(k_bw_sums, dim3(1), dim3(1024), 0, s, P.phi, P.kind, n, P.st);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_bw_coef, dim3(gn), dim3(256), 0, s, P.De, P.phi, P.kind, parent, n, sigma, phi_kind, gW, gI,
-                           P.st, P.coef, P.sterm, P.ndeg);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_bw_sigma, dim3(1), dim3(1024), 0, s, P.sterm, n, P.st);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_bw_keys, dim3(gn), dim3(256), 0, s, parent, n, P.key, P.val);
-        LAUNCH_CHECK();
-        radix_sort_pairs_u32(P.key, P.val, P.tk, P.tv, n, bits_of(n), P.sort_scratch, s);
-        exclusive_scan_i32(P.nchild, P.koff, n + 1, nullptr, nullptr, s);
-        // vertices without a parent sort first (key 0); the child lists follow
-        int32_t total_children = 0;
-        HIP_CHECK(hipMemcpyAsync(&total_children, P.koff + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        const int64_t nroots = n - total_children;
-        hipLaunchKernelGGL(k_bw_scatter, dim3(grid_for(n, 4)), dim3(256), 0, s, X, n, d, ld, parent, P.coef,
-                           P.val + nroots, P.koff, gX, ldg);
-        LAUNCH_CHECK();
-        HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        *gsigma = h.gs;
-        if (I_out) {
-            const double den = 2.0 * h.inner + h.num;
-            *I_out = den > 0.0 ? h.num / den : 0.0;
-        }
+        run_backward(X, n, d, ld, parent, labels, jstar, sigma, phi_kind, gW, gI, gX, ldg, gsigma, I_out, ws, ws_bytes,
+                     s);
     });
 }

@@ -1875,8 +1875,8 @@ extern "C" iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t preci
 }
 
 extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, int32_t precision, int32_t recheck,
-                              int32_t *parent, double *length, iso_mst_info *info, void *ws, size_t ws_bytes,
-                              void *stream) {
+                              uint32_t flags, int32_t *parent, double *length, iso_mst_info *info, void *ws,
+                              size_t ws_bytes, void *stream) {
     return guarded([&] {
         ISO_REQUIRE(X && parent && length, ISO_ERR_INVALID_ARG, "X, parent and length must be non-NULL");
         ISO_REQUIRE(n >= 2 && n < (int64_t(1) << 31) - GT, ISO_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
@@ -1885,12 +1885,11 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         ISO_REQUIRE(precision == ISO_PREC_FP32 || precision == ISO_PREC_BF16 || precision == ISO_PREC_FP8 ||
                         precision == ISO_PREC_INT8,
                     ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
-        const int32_t options = recheck & ~0xFF;
-        recheck &= 0xFF;
         ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
                     "unknown recheck %d", recheck);
-        ISO_REQUIRE((options & ~(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL | ISO_MST_NO_ESCALATE)) == 0, ISO_ERR_INVALID_ARG,
-                    "unknown options 0x%x", options);
+        ISO_REQUIRE((flags & ~(uint32_t)(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL | ISO_MST_NO_ESCALATE)) == 0,
+                    ISO_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+        const int32_t options = (int32_t)flags;
         require_device();
         hipStream_t s = static_cast<hipStream_t>(stream);
         MstPlan P = make_plan(n, d, ld, precision);

@@ -1,10 +1,14 @@
 """Writes tests/golden/mst_digest_<recipe>_n<n>.json: the FP64 oracle's MST
 (dense Prim from vertex 0, edges ordered by (D^2, smaller id, larger id)) of a
 seeded synthetic input, stored as the SHA-256 of its parent array (int32,
-little endian), its weight and its first entries.  Only the oracle computes it.
+little endian), its weight and its first entries.  With --save-parent the
+parent array itself is also written, compressed, to
+tests/golden/mst_parent_<recipe>_n<n>.npz (key "parent").  Only the oracle
+computes it.
 
     python tests/golden/make_mst_digest.py 3 50000      # image-like recipe, n = 50,000 (~20 min, one core)
     python tests/golden/make_mst_digest.py 3 200000 6   # n = 200,000 with 6 threads for Prim's key updates
+    python tests/golden/make_mst_digest.py 4 100000 6 --save-parent
 
 The thread count does not change the tree (each step's key updates are
 independent and the next vertex is chosen by one sequential scan).
@@ -28,8 +32,10 @@ RECIPE = {1: "gaussian-mixture", 2: "anisotropic-mixture", 3: "image-like", 4: "
 
 
 def main():
-    cfg, n = int(sys.argv[1]), int(sys.argv[2])
-    threads = int(sys.argv[3]) if len(sys.argv) > 3 else 1
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    save_parent = "--save-parent" in sys.argv[1:]
+    cfg, n = int(args[0]), int(args[1])
+    threads = int(args[2]) if len(args) > 2 else 1
     X = datagen.config(cfg, n=n)
     t0 = time.time()
     parent, length, _, _ = oracle.prim_mst(X, threads=threads)
@@ -42,6 +48,9 @@ def main():
         "oracle_seconds": round(time.time() - t0, 1),
         "oracle_threads": threads,
     }
+    if save_parent:
+        np.savez_compressed(os.path.join(HERE, "mst_parent_%s_n%d.npz" % (RECIPE[cfg], n)),
+                            parent=parent.astype("<i4"))
     path = os.path.join(HERE, "mst_digest_%s_n%d.json" % (RECIPE[cfg], n))
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)

@@ -61,15 +61,30 @@ def test_mst_argument_validation():
     info = _lib.MstInfo()
     dummy = _p(0x1000)
     # NULL points
-    assert lib.iso_mst(None, 10, 4, 4, 0, 0, dummy, dummy, ctypes.byref(info), None, 0, None) == -1
+    assert lib.iso_mst(None, 10, 4, 4, 0, 0, 0, dummy, dummy, ctypes.byref(info), None, 0, None) == -1
     assert b"non-NULL" in lib.iso_last_error()
     # n < 2, d < 1, ld < d, unknown precision / recheck
-    assert lib.iso_mst(dummy, 1, 4, 4, 0, 0, dummy, dummy, None, None, 0, None) == -1
-    assert lib.iso_mst(dummy, 10, 0, 4, 0, 0, dummy, dummy, None, None, 0, None) == -1
-    assert lib.iso_mst(dummy, 10, 4, 3, 0, 0, dummy, dummy, None, None, 0, None) == -1
+    assert lib.iso_mst(dummy, 1, 4, 4, 0, 0, 0, dummy, dummy, None, None, 0, None) == -1
+    assert lib.iso_mst(dummy, 10, 0, 4, 0, 0, 0, dummy, dummy, None, None, 0, None) == -1
+    assert lib.iso_mst(dummy, 10, 4, 3, 0, 0, 0, dummy, dummy, None, None, 0, None) == -1
     assert b"ld" in lib.iso_last_error()
-    assert lib.iso_mst(dummy, 10, 4, 4, 7, 0, dummy, dummy, None, None, 0, None) == -1
-    assert lib.iso_mst(dummy, 10, 4, 4, 0, 5, dummy, dummy, None, None, 0, None) == -1
+    assert lib.iso_mst(dummy, 10, 4, 4, 7, 0, 0, dummy, dummy, None, None, 0, None) == -1
+    assert lib.iso_mst(dummy, 10, 4, 4, 0, 5, 0, dummy, dummy, None, None, 0, None) == -1
+    # the old encoding (option bits OR-ed into recheck) is rejected: recheck is
+    # only ISO_RECHECK_*, the options have their own argument
+    assert lib.iso_mst(dummy, 10, 4, 4, 0, 0x100, 0, dummy, dummy, None, None, 0, None) == -1
+    assert b"recheck" in lib.iso_last_error()
+
+
+def test_mst_flags_validation():
+    """iso_mst's flags argument takes exactly the ISO_MST_NO_* bits; unknown
+    bits are rejected before any device work."""
+    lib = _lib.load()
+    dummy = _p(0x1000)
+    for bad in (0x8, 0x10, 0x100, 0x80000000):
+        assert lib.iso_mst(dummy, 10, 4, 4, 0, 0, bad, dummy, dummy, None, None, 0, None) == -1
+        assert b"flag" in lib.iso_last_error()
+    assert _lib.MST_NO_LISTS | _lib.MST_NO_FINAL | _lib.MST_NO_ESCALATE == 0x7
 
 
 def test_subpartition_argument_validation():
