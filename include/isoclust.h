@@ -205,6 +205,24 @@ iso_status iso_subpartition(const int32_t *parent, const double *length, int64_t
                             double *cluster_num, double *cluster_den, int32_t *cluster_size, iso_sub_info *info,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* iso_subpartition for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid device
+ * allocation): the same computation, arguments and results, with the
+ * workspace taken from a fixed device array inside the library instead of a
+ * caller buffer or a library allocation.  That array (ISO_SUB_NOALLOC_BYTES)
+ * is reserved on every GPU the library runs on until the process ends; its
+ * address is looked up once per device, on the first call made with that
+ * device current.  Every call on one GPU uses the same array, so calls that
+ * overlap in time on one GPU (concurrent streams or threads) race and must be
+ * serialised by the caller; nothing is kept from one call to the next.
+ * Errors: as iso_subpartition, and n > ISO_SUB_NOALLOC_MAX_N (INVALID_ARG). */
+#define ISO_SUB_NOALLOC_MAX_N 32768
+#define ISO_SUB_NOALLOC_BYTES ((size_t)64 << 20)
+iso_status iso_subpartition_noalloc(const int32_t *parent, const double *length, int64_t n, int32_t root, int32_t k,
+                                    double sigma, const iso_sub_opts *opts, int32_t *labels, double *i_k /* host */,
+                                    double *cluster_num, double *cluster_den, int32_t *cluster_size,
+                                    iso_sub_info *info, void *stream);
+
 /* The optimal k-subpartition for every k = 2 .. kmax of one tree: MISO_k of
  * eq. 2.6 for each k, each by Algorithm 1 inside its own bisection of
  * Algorithm 2 (Sec. 2.2), labelled as in Algorithm 4 -- the same bisection,

@@ -144,7 +144,7 @@ def sigma_median(parent, length) -> float:
 
 def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = None, root: int = 0, phi: str = "exp",
                                bracket: str = "pow2", max_iters: int = 2000, return_clusters: bool = False,
-                               omega0=None, p0=None):
+                               omega0=None, p0=None, noalloc: bool = False):
     """Optimal k-subpartition of the weighted tree and MISO_k (eqs. 2.4, 2.6).
 
     ``sigma`` None (or 0) selects the lower median edge length.  ``omega0``
@@ -152,7 +152,8 @@ def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = Non
     full-graph omega of eq. 2.2 instead of the tree degree; ``p0`` adds the
     potential of eq. 2.3.  Returns (labels int32[n] with -1 for residual
     vertices, i_k, info dict); with ``return_clusters`` the info also holds
-    per-cluster num, den and size."""
+    per-cluster num, den and size.  ``noalloc`` runs the allocation-free entry
+    point (workspace in the library's fixed device array, n <= 32768)."""
     torch = _torch()
     _require_cuda(parent, "parent", torch.int32)
     _require_cuda(length, "length", torch.float64)
@@ -162,10 +163,12 @@ def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = Non
     if length.shape[0] != n:
         raise ValueError("parent and length differ in size")
     lib = _lib.load()
-    need = ctypes.c_size_t(0)
-    _lib.check(lib.iso_sub_workspace_size(n, int(k), ctypes.byref(need)), "iso_sub_workspace_size")
     dev = parent.device
-    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    need = ctypes.c_size_t(0)
+    ws = None
+    if not noalloc:
+        _lib.check(lib.iso_sub_workspace_size(n, int(k), ctypes.byref(need)), "iso_sub_workspace_size")
+        ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     cnum = torch.empty(k, dtype=torch.float64, device=dev)
     cden = torch.empty(k, dtype=torch.float64, device=dev)
@@ -180,12 +183,15 @@ def isoperimetric_subpartition(parent, length, k: int, sigma: float | None = Non
                         p0.data_ptr() if p0 is not None else None)
     info = _lib.SubInfo()
     ik = ctypes.c_double(0.0)
-    rc = lib.iso_subpartition(ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), n, int(root),
-                              int(k), float(sigma or 0.0), ctypes.byref(opts), ctypes.c_void_p(labels.data_ptr()),
-                              ctypes.byref(ik), ctypes.c_void_p(cnum.data_ptr()), ctypes.c_void_p(cden.data_ptr()),
-                              ctypes.c_void_p(csize.data_ptr()), ctypes.byref(info), ctypes.c_void_p(ws.data_ptr()),
-                              int(need.value), _stream_ptr(dev))
-    _lib.check(rc, "iso_subpartition")
+    args = (ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), n, int(root), int(k),
+            float(sigma or 0.0), ctypes.byref(opts), ctypes.c_void_p(labels.data_ptr()), ctypes.byref(ik),
+            ctypes.c_void_p(cnum.data_ptr()), ctypes.c_void_p(cden.data_ptr()), ctypes.c_void_p(csize.data_ptr()),
+            ctypes.byref(info))
+    if noalloc:
+        _lib.check(lib.iso_subpartition_noalloc(*args, _stream_ptr(dev)), "iso_subpartition_noalloc")
+    else:
+        _lib.check(lib.iso_subpartition(*args, ctypes.c_void_p(ws.data_ptr()), int(need.value), _stream_ptr(dev)),
+                   "iso_subpartition")
     out = {f: getattr(info, f) for f, _ in _lib.SubInfo._fields_ if f != "reserved0"}
     if return_clusters:
         out.update(cluster_num=cnum, cluster_den=cden, cluster_size=csize)

@@ -28,7 +28,7 @@ BRACKET = {"pow2": 0, "paper": 1}
 
 # Every symbol include/isoclust.h declares.
 EXPORTS = ["iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
-           "iso_subpartition_all_k", "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median", "iso_mst_prim_workspace_size", "iso_mst_prim",
+           "iso_subpartition_all_k", "iso_subpartition_noalloc", "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median", "iso_mst_prim_workspace_size", "iso_mst_prim",
            "iso_timing_enable",
            "iso_timing_read", "iso_last_error", "iso_version"]
 
@@ -85,6 +85,8 @@ def load(build_if_missing: bool = True):
     lib.iso_sub_workspace_size.argtypes = [I64, I32, ctypes.POINTER(SZ)]
     lib.iso_subpartition.argtypes = [P, P, I64, I32, I32, D, ctypes.POINTER(SubOpts), P, ctypes.POINTER(D), P, P, P,
                                      ctypes.POINTER(SubInfo), P, SZ, P]
+    lib.iso_subpartition_noalloc.argtypes = [P, P, I64, I32, I32, D, ctypes.POINTER(SubOpts), P, ctypes.POINTER(D), P,
+                                             P, P, ctypes.POINTER(SubInfo), P]
     lib.iso_backward_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
     lib.iso_backward.argtypes = [P, I64, I64, I64, P, P, I32, D, I32, D, D, P, I64, ctypes.POINTER(D),
                                  ctypes.POINTER(D), P, SZ, P]
@@ -96,7 +98,7 @@ def load(build_if_missing: bool = True):
     lib.iso_sigma_median.argtypes = [P, P, I64, ctypes.POINTER(D), P]
     for f in ("iso_mst_workspace_size", "iso_mst", "iso_sub_workspace_size", "iso_subpartition",
               "iso_backward_workspace_size", "iso_backward", "iso_graph_weights", "iso_sigma_median",
-              "iso_subpartition_all_k", "iso_mst_prim_workspace_size", "iso_mst_prim"):
+              "iso_subpartition_all_k", "iso_subpartition_noalloc", "iso_mst_prim_workspace_size", "iso_mst_prim"):
         getattr(lib, f).restype = ctypes.c_int32
     lib.iso_timing_enable.argtypes = [I32]
     lib.iso_timing_enable.restype = ctypes.c_int32

@@ -16,6 +16,7 @@
 // exactly the sequential one.  The bracket lives on the device; the host only
 // polls a done flag between batches of passes.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -901,6 +902,39 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
 
 }  // namespace
 
+// ------------------------------------------------------------------ allocation-free workspace
+
+// Workspace of iso_subpartition_noalloc: one fixed array per device, reserved
+// for the life of the process.  In host code `scratch` names only the host-side
+// shadow of the symbol; kernels receive the device address that
+// hipGetSymbolAddress reports for the current device.
+static __device__ __align__(256) char scratch[ISO_SUB_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current.
+char *noalloc_scratch() {
+    int dev = -1;
+    HIP_CHECK(hipGetDevice(&dev));
+    ISO_REQUIRE(dev >= 0 && dev < MAX_DEVICES, ISO_ERR_NO_DEVICE, "device ordinal %d outside [0, %d)", dev,
+                MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        ISO_REQUIRE(ptr != nullptr, ISO_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 }  // namespace iso
 
 using namespace iso;
@@ -992,6 +1026,44 @@ extern "C" iso_status iso_subpartition(const int32_t *parent, const double *leng
         }
         ISO_REQUIRE(ws_bytes >= need, ISO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
         Arena a{static_cast<char *>(ws), 0, ws_bytes};
+        P.carve(a);
+        run_sub(P, parent, length, root, sigma, o, labels, i_k, cluster_num, cluster_den, cluster_size, info, s);
+    });
+}
+
+extern "C" iso_status iso_subpartition_noalloc(const int32_t *parent, const double *length, int64_t n, int32_t root,
+                                               int32_t k, double sigma, const iso_sub_opts *opts, int32_t *labels,
+                                               double *i_k, double *cluster_num, double *cluster_den,
+                                               int32_t *cluster_size, iso_sub_info *info, void *stream) {
+    return guarded([&] {
+        ISO_REQUIRE(parent && length && labels && i_k, ISO_ERR_INVALID_ARG,
+                    "parent, length, labels and i_k must be non-NULL");
+        ISO_REQUIRE(n >= 2 && n <= ISO_SUB_NOALLOC_MAX_N, ISO_ERR_INVALID_ARG,
+                    "n = %lld outside [2, %d] (the allocation-free entry point's maximum)", (long long)n,
+                    ISO_SUB_NOALLOC_MAX_N);
+        ISO_REQUIRE(k >= 2 && k <= n, ISO_ERR_INVALID_ARG, "k = %d outside [2, n]", k);
+        ISO_REQUIRE(root >= 0 && root < n, ISO_ERR_INVALID_ARG, "root = %d outside [0, n)", root);
+        ISO_REQUIRE(sigma >= 0.0 && std::isfinite(sigma), ISO_ERR_INVALID_ARG, "sigma = %g must be finite and >= 0",
+                    sigma);
+        iso_sub_opts o{ISO_OMEGA_TREE, ISO_PHI_EXP_DIST, ISO_BRACKET_POW2, 2000, nullptr, nullptr};
+        if (opts) o = *opts;
+        ISO_REQUIRE(o.omega == ISO_OMEGA_TREE || o.omega == ISO_OMEGA_FULL, ISO_ERR_INVALID_ARG,
+                    "unsupported omega reading %d", o.omega);
+        ISO_REQUIRE(o.omega != ISO_OMEGA_FULL || o.omega0 != nullptr, ISO_ERR_INVALID_ARG,
+                    "ISO_OMEGA_FULL needs the vertex weights in opts->omega0");
+        ISO_REQUIRE(o.phi == ISO_PHI_EXP_DIST || o.phi == ISO_PHI_GAUSS_SQ, ISO_ERR_INVALID_ARG, "unknown phi %d", o.phi);
+        ISO_REQUIRE(o.bracket == ISO_BRACKET_POW2 || o.bracket == ISO_BRACKET_PAPER, ISO_ERR_INVALID_ARG,
+                    "unknown bracket %d", o.bracket);
+        const size_t need = sub_plan_bytes(n, k);
+        ISO_REQUIRE(need <= ISO_SUB_NOALLOC_BYTES, ISO_ERR_INTERNAL, "workspace %zu bytes exceeds the fixed %zu", need,
+                    (size_t)ISO_SUB_NOALLOC_BYTES);
+        require_device();
+        char *ws = noalloc_scratch();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        SubPlan P{};
+        P.n = n;
+        P.k = k;
+        Arena a{ws, 0, (size_t)ISO_SUB_NOALLOC_BYTES};
         P.carve(a);
         run_sub(P, parent, length, root, sigma, o, labels, i_k, cluster_num, cluster_den, cluster_size, info, s);
     });

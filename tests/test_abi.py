@@ -112,6 +112,26 @@ def test_subpartition_argument_validation():
                                 None, None, None, 0, None) == -1
 
 
+def test_subpartition_noalloc_argument_validation():
+    """The allocation-free entry point validates like iso_subpartition and
+    rejects n beyond its fixed array's maximum, before any device work."""
+    lib = _lib.load()
+    dummy = _p(0x1000)
+    ik = ctypes.c_double(0)
+
+    def call(n=10, k=3, root=0, sigma=0.0, parent=dummy):
+        return lib.iso_subpartition_noalloc(parent, dummy, n, root, k, sigma, None, dummy, ctypes.byref(ik), None,
+                                            None, None, None, None)
+
+    assert call(parent=None) == -1
+    assert call(n=1) == -1
+    assert call(k=11) == -1
+    assert call(root=10) == -1
+    assert call(sigma=float("nan")) == -1
+    assert call(n=32769, k=4) == -1
+    assert b"maximum" in lib.iso_last_error()
+
+
 def test_no_cpu_fallback():
     """The Python API has no CPU path: CPU tensors are rejected."""
     torch = pytest.importorskip("torch")
