@@ -108,18 +108,37 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
     return rec
 
 
-def cpu_baseline(n_full, k, sample_n):
-    """The FP64 oracle (single thread) on a subsample of the same recipe; the
-    O(n^2 d) MST cost is scaled to the full n."""
+def cpu_baseline(n_full, k, sample_ns, tree=None):
+    """The FP64 oracle (single thread) on subsamples of the same recipe: its
+    O(n^2 d) MST time is measured at each sample size, the exponent fitted
+    between the two, and the largest sample's time scaled by (n/sample)^2.
+    With ``tree`` (the timed step's parent and length arrays) the oracle's
+    tree search also runs once at the full size, on that tree: its time enters
+    the baseline unscaled, and its MISO_k is returned for the i_k check."""
+    import math
+
     import oracle
     from paper_1702_04739_amd import datagen
-    X = datagen.config(WORKLOAD, n=sample_n)
-    t0 = time.perf_counter()
-    parent, length, _, _ = oracle.prim_mst(X)
-    t1 = time.perf_counter()
-    oracle.subpartition(parent, length, k)
-    t2 = time.perf_counter()
-    t_full = (t1 - t0) * (n_full / sample_n) ** 2 + (t2 - t1) * (n_full / sample_n)
+    mst_s = []
+    for m in sample_ns:
+        X = datagen.config(WORKLOAD, n=m)
+        t0 = time.perf_counter()
+        parent, length, _, _ = oracle.prim_mst(X)
+        mst_s.append(time.perf_counter() - t0)
+    sample_n = sample_ns[-1]
+    expo = (math.log(mst_s[-1] / mst_s[0]) / math.log(sample_ns[-1] / sample_ns[0])) if len(sample_ns) > 1 else None
+    ik_oracle = None
+    if tree is not None:
+        t1 = time.perf_counter()
+        ref = oracle.subpartition(tree[0], tree[1], k)
+        t_tree = time.perf_counter() - t1
+        ik_oracle = ref.i_k
+        t_full = mst_s[-1] * (n_full / sample_n) ** 2 + t_tree
+    else:
+        t1 = time.perf_counter()
+        oracle.subpartition(parent, length, k)
+        t_tree = time.perf_counter() - t1
+        t_full = mst_s[-1] * (n_full / sample_n) ** 2 + t_tree * (n_full / sample_n)
     cpu_model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -133,11 +152,142 @@ def cpu_baseline(n_full, k, sample_n):
         "value": n_full / t_full,
         "unit": "points/s",
         "cores": 1,
+        "nproc": os.cpu_count(),
         "cpu": cpu_model,
         "kind": "oracle",
-        "sample": "same recipe at n=%d (MST %.2f s, tree search %.3f s, single thread); MST time scaled by "
-                  "(n/%d)^2 and tree time by n/%d to n=%d" % (sample_n, t1 - t0, t2 - t1, sample_n, sample_n, n_full),
+        "sample": "oracle MST (dense Prim, one thread) on the same recipe at n=%s: %s s (fitted exponent %s); "
+                  "the n=%d time scaled by (n/%d)^2 to n=%d; tree search %s %.3f s" % (
+                      "/".join(str(m) for m in sample_ns), "/".join("%.2f" % t for t in mst_s),
+                      "%.2f" % expo if expo is not None else "n/a", sample_n, sample_n, n_full,
+                      "on the timed step's tree at full n" if tree is not None else "at the sample size, scaled by n",
+                      t_tree),
+        "mst_sample_s": dict(zip([str(m) for m in sample_ns], mst_s)),
+        "tree_search_s": t_tree,
+        "_ik_oracle": ik_oracle,
     }
+
+
+def _timed(fn, reps=3):
+    """Median wall time (ms) of reps calls after one warm-up call, with device
+    synchronisation around each."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def oracle_digest_parity(info, n):
+    """The timed step's MST against the FP64 oracle's, as stored by the
+    oracle-only digest script: parent-array identity (SHA-256) and the
+    relative error of the MST weight."""
+    path = os.path.join(ROOT, "tests", "golden", "mst_digest_image-like_n%d.json" % n)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    p = info["parent"].cpu().numpy().astype("<i4")
+    w = info["mst"]["mst_weight"]
+    return {"oracle_digest": os.path.relpath(path, ROOT),
+            "parent_identical_to_oracle": hashlib.sha256(p.tobytes()).hexdigest() == rec["parent_sha256"],
+            "mst_weight": w, "mst_weight_oracle": rec["weight"],
+            "mst_weight_rel_err_vs_oracle": abs(w - rec["weight"]) / rec["weight"]}
+
+
+def other_workloads():
+    """MST + subpartition at full size on the Gaussian-mixture (n = 2000,
+    d = 16), anisotropic-mixture (n = 50,000, d = 64) and blobs (n = 20,000,
+    d = 128) workloads with the FP32 screen and FP32 recheck (their values lie
+    on no binary grid, so a BF16 request hands over to FP32); for the blobs
+    workload also the forward pass plus the adjoint through MSTIsoCost (the
+    gradient of W + i_k with respect to the points and sigma)."""
+    import torch
+
+    import paper_1702_04739_amd as iso
+    from paper_1702_04739_amd import datagen
+    out = {}
+    for cfg in (1, 2, 5):
+        c = datagen.CONFIGS[cfg]
+        log("workload %s" % c["name"])
+        X = torch.from_numpy(datagen.config(cfg)).cuda()
+        ms = _timed(lambda: iso.cluster(X, c["k"], precision="fp32", recheck="fp32"))
+        rec = {"n": c["n"], "d": c["d"], "k": c["k"], "screen": "fp32", "recheck": "fp32", "ms": ms,
+               "points_per_s": c["n"] / (ms * 1e-3)}
+        if cfg == 5:
+            _, _, info = iso.cluster(X, c["k"])
+            sig0 = info["sub"]["sigma"]
+
+            def fwd_bwd():
+                pts = X.clone().requires_grad_(True)
+                sig = torch.tensor(sig0, dtype=torch.float64, device=X.device, requires_grad=True)
+                W, I, _ = iso.MSTIsoCost.apply(pts, sig, c["k"])
+                (W + I).backward()
+
+            rec["forward_adjoint_ms"] = _timed(fwd_bwd)
+            labels, _, info = iso.cluster(X, c["k"])
+            rec["adjoint_ms"] = _timed(lambda: iso.adjoint(X, info["parent"], labels, info["sub"]["jstar"], sig0))
+        out[c["name"]] = rec
+    return out
+
+
+def precision_sparse_communities():
+    """The MST of the sparse-communities workload (n = 100,000, d = 4096) with
+    the FP32, BF16 and FP8 screens (FP32 recheck): one call each after one
+    FP32 warm-up.  A low-precision screen whose error bound is too loose for
+    the data hands over to FP32 (screen_precision tells which one built the
+    tree); the tree is the same in every case."""
+    import torch
+
+    import paper_1702_04739_amd as iso
+    from paper_1702_04739_amd import datagen
+    c = datagen.CONFIGS[4]
+    log("precision comparison %s" % c["name"])
+    X = torch.from_numpy(datagen.config(4)).cuda()
+    iso.mst(X, precision="fp32")
+    torch.cuda.synchronize()
+    out = {"workload": c["name"], "n": c["n"], "d": c["d"], "recheck": "fp32"}
+    ref = None
+    for prec in ("fp32", "bf16", "fp8"):
+        t0 = time.perf_counter()
+        parent, _, info = iso.mst(X, precision=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if ref is None:
+            ref = parent
+        out[prec] = {"ms": ms, "points_per_s": c["n"] / (ms * 1e-3), "screen_precision": info["screen_precision"],
+                     "rounds": info["rounds"], "candidates_per_point": info["candidates"] / c["n"],
+                     "rescanned_rows": info["rescanned_rows"], "same_tree_as_fp32": bool(torch.equal(parent, ref))}
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
+def graph_weights_timing():
+    """Full-graph vertex weights and potential (eqs. 2.2-2.3, FP64 on the
+    vector units) at the blobs (n = 20,000, d = 128) and anisotropic-mixture
+    (n = 50,000, d = 64) sizes: time and FP64 rate, counting 3 d flops per
+    ordered pair of points (difference, square, sum) against the 78.6 TFLOP/s
+    FP64 vector peak."""
+    import torch
+
+    import paper_1702_04739_amd as iso
+    from paper_1702_04739_amd import datagen
+    out = {}
+    for cfg in (5, 2):
+        c = datagen.CONFIGS[cfg]
+        log("graph weights %s" % c["name"])
+        X = torch.from_numpy(datagen.config(cfg)).cuda()
+        ms = _timed(lambda: iso.graph_weights(X, 1.0, alpha=0.05), reps=1)
+        fl = 3.0 * c["d"] * c["n"] * (c["n"] - 1)
+        out[c["name"]] = {"n": c["n"], "d": c["d"], "ms": ms, "fp64_tflops": fl / (ms * 1e-3) / 1e12,
+                          "frac_fp64_peak": fl / (ms * 1e-3) / 78.6e12}
+    return out
 
 
 def main():
@@ -154,7 +304,9 @@ def main():
                     help="time the paper's Prim MST against this path's MST on an M-point sample (0: skip)")
     ap.add_argument("--all-k", type=int, default=10, metavar="K",
                     help="after the timed steps, time the all-k sweep k = 2..K on the last tree (0: skip)")
-    ap.add_argument("--cpu-sample-n", type=int, default=8000)
+    ap.add_argument("--cpu-sample-n", type=int, nargs="+", default=[4000, 8000])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads, the sparse-communities precision comparison and graph weights")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, run one plain device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--traffic-report", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -317,9 +469,21 @@ def main():
         out["all_k"] = {"kmax": args.all_k, "ms": (a1 - a0) * 1e3, "passes": passes,
                         "separate_calls_ms": (a2 - a1) * 1e3, "separate_calls_passes": sep_passes,
                         "i_k": [float(v) for v in ik_all]}
+    if args.n is None:
+        out["parity"] = oracle_digest_parity(info, n)
+    if not args.no_extras:
+        out["workloads"] = other_workloads()
+        out["precision_sparse_communities"] = precision_sparse_communities()
+        out["graph_weights"] = graph_weights_timing()
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, n=%d sample)" % args.cpu_sample_n)
-        out["cpu_baseline"] = cpu_baseline(n, k, args.cpu_sample_n)
+        log("cpu baseline (oracle, n=%s samples)" % args.cpu_sample_n)
+        tree = (info["parent"].cpu().numpy(), info["length"].cpu().numpy())
+        cb = cpu_baseline(n, k, args.cpu_sample_n, tree=tree)
+        ik_or = cb.pop("_ik_oracle")
+        out["cpu_baseline"] = cb
+        if ik_or is not None and "parity" in out:
+            out["parity"]["ik_oracle_on_this_tree"] = ik_or
+            out["parity"]["ik_rel_err_vs_oracle"] = abs(ik - ik_or) / ik_or
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -10,11 +10,17 @@
 // exactly the order in which the sequential algorithm folds them into the
 // parent, so the FP64 arithmetic is the sequential algorithm's.
 //
-// Bisection (Algorithm 2) is speculative: one device pass evaluates the 63
-// midpoints of the next six bisection levels at once (one wave lane per
-// midpoint), then walks the six answers, so the sequence of brackets is
-// exactly the sequential one.  The bracket lives on the device; the host only
-// polls a done flag between batches of passes.
+// Bisection (Algorithm 2) is speculative: one device pass evaluates 64
+// thresholds at once (one wave lane each) -- the midpoints of the next six
+// bisection levels, or, while every answer so far has gone one way, the next
+// 64 midpoints along that direction -- then walks the answers, so the
+// sequence of brackets is exactly the sequential one.  The bracket lives on
+// the device; the host polls a done flag after every pass.
+//
+// Once the bracket is narrow most subtrees decide alike over all of it: such
+// a subtree's contribution to its parent no longer depends on the threshold,
+// so it is frozen (its value written to every lane) and later passes visit
+// only the remaining vertices.
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -31,8 +37,18 @@ namespace {
 constexpr int SPEC_LEVELS = ISO_SPEC_LEVELS;       // bisection steps resolved per pass
 constexpr int M = 1 << SPEC_LEVELS;                // lanes per vertex in a speculative pass
 constexpr int NCAND = M - 1;                       // midpoints per pass (the last lane re-checks beta)
-constexpr int NARROW = 16 * 64 / M > 1 ? 16 * 64 / M : 1;  // levels this narrow run inside one workgroup
-constexpr int PASS_BATCH = 4;
+// Candidate layouts of a speculative pass.  SPEC_TREE: the 63 midpoints of the
+// next six bisection levels in heap order, the last lane re-checks beta.
+// SPEC_DOWN / SPEC_UP: the next 64 midpoints along the path on which every
+// answer is YES (the bracket's upper end keeps falling) or every answer is NO
+// (its lower end keeps rising); the pass resolves the steps up to and
+// including the first opposite answer.  While the bisection has only ever
+// answered one way the spine is the likely path: from a power-of-two bracket
+// far wider than MISO_k the leading steps are a run of YES answers.
+constexpr int SPEC_TREE = 0, SPEC_DOWN = 1, SPEC_UP = 2;
+// Levels with at most this many vertices are run inside one workgroup
+// (several vertices of a level one after another when it has more than 16).
+constexpr int NARROW_VERTS = 48;
 #ifndef DP_BATCH
 #define DP_BATCH 16                          // children loaded per round trip in Algorithm 1 (measured best)
 #endif
@@ -45,7 +61,10 @@ struct TreeState {
     double i_k;
     int32_t done, iters, passes, jstar;
     int32_t ncuts, max_iters, k, bad;
-    int32_t maxdepth, pad0, pad1, pad2;
+    int32_t maxdepth;
+    int32_t lo_lane;  // lane of the last pass's final lower end (-1: the lower end did not move)
+    int32_t mode;     // candidate layout of the current pass (SPEC_TREE, SPEC_DOWN, SPEC_UP)
+    int32_t nfrozen;  // vertices frozen so far
 };
 
 template <class T>
@@ -266,8 +285,12 @@ struct VtxMeta {
 };
 
 struct DPArgs {
-    const int32_t *level_start;
+    const int32_t *level_start;  // level L occupies entries level_start[L] .. level_start[L+1]-1 of the position list
+    const int32_t *act;          // position list (x-order positions of the vertices a pass visits), or NULL = all
     const VtxMeta *meta;  // [n] by x-order position
+    const int32_t *nextl;  // [M] lane holding the next larger evaluated threshold, -1 if it was not evaluated
+    uint64_t *smask;       // [slot] bit l: the vertex's subtree decides alike at lane l's threshold and at
+                           // lane nextl[l]'s (~0 for frozen vertices)
     const double *Nvals;
     double2 *cpw;  // [slot][MM] contribution (p, omega) to the parent
     int32_t *cnt;
@@ -282,13 +305,22 @@ struct DPArgs {
 //   cut:     p += phi(e)           (the edge joins the boundary),
 //   join:    omega += omega(x), p += p(x),
 //   discard: p += phi(e).
-template <int MM, bool REC>
+//
+// With MASK (speculative passes, one wave of MM = 64 lanes per vertex) the wave
+// also records, for every lane l whose next larger threshold was evaluated,
+// whether the whole subtree takes the same decisions at both thresholds.  A
+// vertex's decision is monotone in N for fixed (omega, p) -- discard, then
+// join, then cut as N grows -- and (omega, p) are fixed when every child's
+// subtree is constant, so a subtree that decides alike at both ends of an
+// interval decides alike, and contributes the same, everywhere inside it.
+template <int MM, bool REC, bool MASK>
 __device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
     const VtxMeta vm = A.meta[q];
     const double N = A.Nvals[m];
     double w = vm.om0;
     double p = vm.p0;
     int32_t c_cnt = 0;
+    uint64_t sm = ~0ull;
     // The children's contributions sit contiguously at slots a0 .. a1-1
     // (ascending child id), (p, omega) packed in 16 bytes; DP_BATCH children
     // are loaded at once, the sums still run one child after another.
@@ -297,11 +329,14 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
         const int64_t rem = a1 - a;
         double2 pw[DP_BATCH];
         int32_t cc[DP_BATCH];
+        uint64_t cm[DP_BATCH];
 #pragma unroll
         for (int u = 0; u < DP_BATCH; ++u) {
-            const int64_t c = (u < rem ? a + u : a1 - 1) * MM + m;
+            const int64_t ch = u < rem ? a + u : a1 - 1;
+            const int64_t c = ch * MM + m;
             pw[u] = A.cpw[c];
             cc[u] = A.cnt[c];
+            if (MASK) cm[u] = A.smask[ch];
         }
 #pragma unroll
         for (int u = 0; u < DP_BATCH; ++u) {
@@ -309,6 +344,7 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
                 p = p + pw[u].x;
                 w = w + pw[u].y;
                 c_cnt += cc[u];
+                if (MASK) sm &= cm[u];
             }
         }
     }
@@ -333,6 +369,13 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
     const int64_t o = (int64_t)vm.slot * MM + m;
     A.cpw[o] = make_double2(op, ow);
     A.cnt[o] = c_cnt + iscut;
+    if (MASK) {
+        const int dec = iscut * 2 + isjoin;
+        const int nx = A.nextl[m];
+        const int dn = __shfl(dec, nx < 0 ? m : nx, 64);
+        const uint64_t eq = __ballot(nx >= 0 && dn == dec);
+        if (m == 0) A.smask[vm.slot] = sm & eq;
+    }
     if (REC) {
         const int32_t v = vm.v;
         A.cut[v] = (uint8_t)iscut;
@@ -363,19 +406,21 @@ __global__ void k_vtx_meta(const int32_t *__restrict__ order, const int32_t *__r
     meta[q] = vm;
 }
 
-// One wide level: MM consecutive threads per vertex.
-template <int MM, bool REC>
+// One wide level: MM consecutive threads per vertex (entries lo .. hi-1 of the
+// position list).
+template <int MM, bool REC, bool MASK>
 __global__ __launch_bounds__(256) void k_dp_level(DPArgs A, int32_t lo, int32_t hi) {
     if (!REC && A.st->done) return;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t q = lo + gid / MM;
+    const int64_t e = lo + gid / MM;
     const int m = (int)(gid % MM);
-    if (q >= hi) return;
-    dp_vertex<MM, REC>(A, (int32_t)q, m);
+    if (e >= hi) return;
+    const int32_t q = A.act ? A.act[e] : (int32_t)e;
+    dp_vertex<MM, REC, MASK>(A, q, m);
 }
 
 // A run of narrow levels [L0, L1) inside one workgroup, a barrier between levels.
-template <int MM, bool REC>
+template <int MM, bool REC, bool MASK>
 __global__ __launch_bounds__(1024) void k_dp_narrow(DPArgs A, int32_t L0, int32_t L1) {
     if (!REC && A.st->done) return;
     const int m = threadIdx.x % MM;
@@ -383,26 +428,60 @@ __global__ __launch_bounds__(1024) void k_dp_narrow(DPArgs A, int32_t L0, int32_
     const int slots = blockDim.x / MM;
     for (int32_t L = L0; L < L1; ++L) {
         const int32_t lo = A.level_start[L], hi = A.level_start[L + 1];
-        for (int32_t q = lo + slot; q < hi; q += slots) dp_vertex<MM, REC>(A, q, m);
+        for (int32_t e = lo + slot; e < hi; e += slots) dp_vertex<MM, REC, MASK>(A, A.act ? A.act[e] : e, m);
         __syncthreads();
     }
 }
 
-// Midpoints of the next SPEC_LEVELS bisection steps, heap order: node q over
-// bracket (lo, hi) has midpoint (lo+hi)/2, left child (lo, mid) (answer YES),
-// right child (mid, hi) (answer NO).  Thread q walks from the root to its node
-// (the bits of q+1 below the leading one, left = 0), repeating exactly the
-// midpoint arithmetic the bisection itself performs; the spare lane re-checks
-// beta.  Launched with M threads.
-__global__ void k_make_cands(const TreeState *__restrict__ st, double *__restrict__ Nvals) {
+// In-order successor of heap node h (1-based) in the complete tree of NCAND
+// nodes, as a lane (node - 1); the largest node's successor is beta's lane.
+__device__ inline int tree_next_lane(int lane) {
+    int h = lane + 1;
+    if (h < M / 2) {  // leftmost node of the right subtree
+        h = 2 * h + 1;
+        while (h < M / 2) h = 2 * h;
+        return h - 1;
+    }
+    while (h > 1 && (h & 1)) h >>= 1;  // climb while a right child
+    return h == 1 ? NCAND : (h >> 1) - 1;
+}
+
+// Thresholds of one speculative pass and, per lane, the lane holding the next
+// larger threshold (-1: not evaluated in this pass).  The layout follows the
+// answers so far: SPEC_DOWN while the lower end of the bracket has never
+// moved, SPEC_UP while the upper end has never moved, else SPEC_TREE.  Every
+// threshold repeats exactly the midpoint arithmetic the sequential bisection
+// performs on its way to it.  Launched with M threads.
+//   SPEC_TREE: node q over bracket (lo, hi) has midpoint (lo+hi)/2, left child
+//              (lo, mid) (answer YES), right child (mid, hi) (answer NO);
+//              thread q walks from the root to its node (the bits of q+1 below
+//              the leading one, left = 0); the spare lane re-checks beta.
+//   SPEC_DOWN: lane q holds the (q+1)-th midpoint when every answer is YES.
+//   SPEC_UP:   lane q holds the (q+1)-th midpoint when every answer is NO.
+__global__ void k_make_cands(TreeState *__restrict__ st, double *__restrict__ Nvals, int32_t *__restrict__ nextl) {
     if (st->done) return;
     const int q = threadIdx.x;
-    if (q > NCAND) return;
-    if (q == NCAND) {
-        Nvals[NCAND] = st->beta;
+    if (q >= M) return;
+    double lo = st->alpha, hi = st->beta;
+    const int mode = lo == st->alpha0 ? SPEC_DOWN : (hi == st->beta0 ? SPEC_UP : SPEC_TREE);
+    if (q == 0) st->mode = mode;
+    if (mode == SPEC_DOWN) {
+        for (int l = 0; l < q; ++l) hi = (lo + hi) / 2.0;
+        Nvals[q] = (lo + hi) / 2.0;
+        nextl[q] = q - 1;
         return;
     }
-    double lo = st->alpha, hi = st->beta;
+    if (mode == SPEC_UP) {
+        for (int l = 0; l < q; ++l) lo = (lo + hi) / 2.0;
+        Nvals[q] = (lo + hi) / 2.0;
+        nextl[q] = q + 1 < M ? q + 1 : -1;
+        return;
+    }
+    if (q == NCAND) {
+        Nvals[NCAND] = hi;
+        nextl[NCAND] = -1;
+        return;
+    }
     const int node = q + 1;
     const int lvl = 31 - __clz(node);  // depth of the node below the root
     for (int l = lvl - 1; l >= 0; --l) {
@@ -413,15 +492,21 @@ __global__ void k_make_cands(const TreeState *__restrict__ st, double *__restric
             hi = mid;
     }
     Nvals[q] = (lo + hi) / 2.0;
+    nextl[q] = tree_next_lane(q);
 }
 
-// Walks the answers of one pass: YES (>= k cuts) => beta = mid, else alpha = mid.
+// Walks the answers of one pass: YES (>= k cuts) => beta = mid, else alpha = mid
+// (SPEC_TREE: six levels; SPEC_DOWN / SPEC_UP: up to and including the first
+// NO / YES).  lo_lane records the lane of the final lower end when it moved.
 __global__ void k_resolve(TreeState *__restrict__ st, const double *__restrict__ Nvals,
                           const int32_t *__restrict__ cnt, int32_t root_slot) {
     if (threadIdx.x != 0 || st->done) return;
     st->passes += 1;
+    st->lo_lane = -1;
+    const int mode = st->mode;
+    const int steps = mode == SPEC_TREE ? SPEC_LEVELS : M;
     int q = 0;
-    for (int l = 0; l < SPEC_LEVELS; ++l) {
+    for (int l = 0; l < steps; ++l) {
         const double a = st->alpha, b = st->beta;
         const double mid = (a + b) / 2.0;
         if (mid <= a || mid >= b || st->iters >= st->max_iters) {
@@ -434,19 +519,76 @@ __global__ void k_resolve(TreeState *__restrict__ st, const double *__restrict__
             return;
         }
         const bool yes = cnt[(int64_t)root_slot * M + q] >= st->k;
+        st->iters += 1;
         if (yes) {
             st->beta = mid;
-            q = 2 * q + 1;
         } else {
             st->alpha = mid;
-            q = 2 * q + 2;
+            st->lo_lane = q;
         }
-        st->iters += 1;
+        if (mode == SPEC_TREE) {
+            q = yes ? 2 * q + 1 : 2 * q + 2;
+        } else {
+            if ((mode == SPEC_DOWN) != yes) break;  // the walk left the spine
+            q = l + 1;
+        }
     }
-    if (cnt[(int64_t)root_slot * M + NCAND] < st->k) st->bad |= 16;  // beta must stay YES
+    if (mode == SPEC_TREE && cnt[(int64_t)root_slot * M + NCAND] < st->k) st->bad |= 16;  // beta must stay YES
     const double a = st->alpha, b = st->beta;
     const double mid = (a + b) / 2.0;
     if (mid <= a || mid >= b || st->iters >= st->max_iters) st->done = 1;
+}
+
+// Freezes the vertices whose subtree decides alike over the whole new bracket
+// [alpha, beta] (bit lo_lane of the mask): every later threshold lies inside
+// it, so their contribution is the one at lane lo_lane, now written to every
+// lane; their mask becomes all ones and later passes skip them.  One thread
+// per entry of the position list.
+__global__ void k_freeze(DPArgs A, int32_t nact, uint8_t *__restrict__ frozen) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lo = A.st->lo_lane;
+    bool froze = false;
+    if (e < nact && !A.st->done && lo >= 0) {
+        const int32_t q = A.act ? A.act[e] : (int32_t)e;
+        if (!frozen[q]) {
+            const int64_t slot = A.meta[q].slot;
+            if ((A.smask[slot] >> lo) & 1ull) {
+                const double2 v = A.cpw[slot * M + lo];
+                const int32_t c = A.cnt[slot * M + lo];
+                for (int l = 0; l < M; ++l) {
+                    A.cpw[slot * M + l] = v;
+                    A.cnt[slot * M + l] = c;
+                }
+                A.smask[slot] = ~0ull;
+                frozen[q] = 1;
+                froze = true;
+            }
+        }
+    }
+    const uint64_t b = __ballot(froze);
+    if (b && (threadIdx.x & 63) == __ffsll((unsigned long long)b) - 1) atomicAdd(&A.st->nfrozen, __popcll(b));
+}
+
+// Position list without the frozen vertices (stable, so still in x-order):
+// keep flags, their exclusive scan, the scatter, and the level starts.
+__global__ void k_keep_flags(const int32_t *__restrict__ act, int32_t nact, const uint8_t *__restrict__ frozen,
+                             int32_t *__restrict__ keep) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > nact) return;
+    keep[e] = e == nact ? 0 : (frozen[act ? act[e] : (int32_t)e] ? 0 : 1);
+}
+
+__global__ void k_compact(const int32_t *__restrict__ act, int32_t nact, const int32_t *__restrict__ keep,
+                          const int32_t *__restrict__ kpos, int32_t *__restrict__ act_out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nact || !keep[e]) return;
+    act_out[kpos[e]] = act ? act[e] : (int32_t)e;
+}
+
+__global__ void k_active_starts(const int32_t *__restrict__ ls_old, int32_t nl, const int32_t *__restrict__ kpos,
+                                int32_t *__restrict__ ls_new) {
+    const int32_t L = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (L < nl) ls_new[L] = kpos[ls_old[L]];
 }
 
 __global__ void k_set_final_N(TreeState *__restrict__ st, double *__restrict__ Nvals) {
@@ -527,6 +669,9 @@ struct SubPlan {
     TreeState *st;
     void *sort_scratch, *sel_scratch;
     VtxMeta *meta;  // per x-order position
+    uint64_t *smask;                   // [slot] subtree masks of the speculative passes
+    uint8_t *frozen;                   // [x-order position]
+    int32_t *act0, *act1, *keep, *kpos, *als0, *als1, *nextl;  // position lists, their level starts, next lanes
 
     void carve(Arena &a) {
         anc0 = a.take<int32_t>(n);
@@ -567,6 +712,15 @@ struct SubPlan {
         sort_scratch = a.take<char>(radix_sort_scratch_bytes(n));
         sel_scratch = a.take<char>(radix_select_scratch_bytes());
         meta = a.take<VtxMeta>(n);
+        smask = a.take<uint64_t>(n);
+        frozen = a.take<uint8_t>(n);
+        act0 = a.take<int32_t>(n);
+        act1 = a.take<int32_t>(n);
+        keep = a.take<int32_t>(n + 1);
+        kpos = a.take<int32_t>(n + 1);
+        als0 = a.take<int32_t>(n + 2);
+        als1 = a.take<int32_t>(n + 2);
+        nextl = a.take<int32_t>(M);
     }
 };
 
@@ -587,21 +741,29 @@ int bits_for(int64_t maxval) {
 
 // Launches Algorithm 1 over all levels, deepest first, grouping runs of
 // narrow levels into single-workgroup launches.
-template <int MM, bool REC>
+// ls holds the level starts of A's position list (A.level_start on the device).
+template <int MM, bool REC, bool MASK>
 void launch_levels(const DPArgs &A, const std::vector<int32_t> &ls, int32_t maxdepth, hipStream_t s) {
-    const int narrow_cap = (REC ? 1024 : NARROW);
+    const int narrow_cap = (REC ? 1024 : NARROW_VERTS);
     int32_t L = 0;
     while (L <= maxdepth) {
         const int32_t width = ls[L + 1] - ls[L];
         if (width <= narrow_cap) {
             int32_t L1 = L;
-            while (L1 <= maxdepth && ls[L1 + 1] - ls[L1] <= narrow_cap) ++L1;
-            hipLaunchKernelGGL((k_dp_narrow<MM, REC>), dim3(1), dim3(1024), 0, s, A, L, L1);
-            LAUNCH_CHECK();
+            bool any = false;
+            while (L1 <= maxdepth && ls[L1 + 1] - ls[L1] <= narrow_cap) {
+                any = any || ls[L1 + 1] > ls[L1];
+                ++L1;
+            }
+            if (any) {
+                hipLaunchKernelGGL((k_dp_narrow<MM, REC, MASK>), dim3(1), dim3(1024), 0, s, A, L, L1);
+                LAUNCH_CHECK();
+            }
             L = L1;
         } else {
             const int64_t threads = (int64_t)width * MM;
-            hipLaunchKernelGGL((k_dp_level<MM, REC>), dim3(grid_for(threads, 256)), dim3(256), 0, s, A, ls[L], ls[L + 1]);
+            hipLaunchKernelGGL((k_dp_level<MM, REC, MASK>), dim3(grid_for(threads, 256)), dim3(256), 0, s, A, ls[L],
+                               ls[L + 1]);
             LAUNCH_CHECK();
             ++L;
         }
@@ -714,7 +876,7 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
     auto finalize = [&](int32_t kk, int32_t *lab, double *cn, double *cd, int32_t *cs) {
         hipLaunchKernelGGL(k_set_final_N, dim3(1), dim3(64), 0, s, P.st, P.Nvals);
         LAUNCH_CHECK();
-        launch_levels<1, true>(A, ls, maxdepth, s);
+        launch_levels<1, true, false>(A, ls, maxdepth, s);
         hipLaunchKernelGGL(k_cut_in_xorder, dim3(gn), dim3(256), 0, s, order, P.cut, n, P.cf);
         LAUNCH_CHECK();
         exclusive_scan_i32(P.cf, P.rank, n, nullptr, P.scan_scratch, s);
@@ -775,10 +937,23 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
                 vals.push_back(v);
                 return (int)vals.size() - 1;
             };
-            // plan: whole levels of each bracket's bisection tree while lanes last
+            // plan, while lanes last: for a bracket whose lower (upper) end has
+            // never moved, the midpoints along its all-YES (all-NO) path; else
+            // whole levels of its bisection tree
             for (int32_t kk = 2; kk <= kmax; ++kk) {
                 plan_levels[kk] = 0;
                 if (br[kk].done) continue;
+                const bool down = br[kk].a == h.alpha0, up = !down && br[kk].b == h.beta0;
+                if (down || up) {
+                    double lo = br[kk].a, hi = br[kk].b;
+                    for (int l = 0; l < M; ++l) {
+                        const double mid = (lo + hi) / 2.0;
+                        if (!(mid > lo && mid < hi) || lane_of(mid) < 0) break;
+                        plan_levels[kk] = l + 1;
+                        (down ? hi : lo) = mid;
+                    }
+                    continue;
+                }
                 std::vector<double> lo(1, br[kk].a), hi(1, br[kk].b);
                 for (int l = 0; l < L; ++l) {
                     std::vector<double> nlo, nhi;
@@ -808,14 +983,17 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
             std::vector<double> nv(M, vals[0]);
             std::copy(vals.begin(), vals.end(), nv.begin());
             HIP_CHECK(hipMemcpyAsync(P.Nvals, nv.data(), sizeof(double) * M, hipMemcpyHostToDevice, s));
-            launch_levels<M, false>(A, ls, maxdepth, s);
+            launch_levels<M, false, false>(A, ls, maxdepth, s);
             HIP_CHECK(hipMemcpyAsync(cnts.data(), P.cnt + (int64_t)root_slot * M, sizeof(int32_t) * M,
                                      hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
-            // each k walks its own answers, exactly as the single-k bisection
+            // each k walks its own answers, exactly as the single-k bisection,
+            // as long as its next midpoint was evaluated in this pass (by its
+            // own plan or, with an equal value, by another k's)
             for (int32_t kk = 2; kk <= kmax; ++kk) {
                 Br &x = br[kk];
-                for (int l = 0; l < plan_levels[kk] && !x.done; ++l) {
+                int walked = 0;
+                while (!x.done) {
                     const double mid = (x.a + x.b) / 2.0;
                     int q = -1;
                     for (size_t t = 0; t < vals.size(); ++t)
@@ -823,14 +1001,16 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
                             q = (int)t;
                             break;
                         }
-                    ISO_REQUIRE(q >= 0, ISO_ERR_INTERNAL, "bisection midpoint was not planned");
+                    if (q < 0) break;
                     if (cnts[q] >= kk)
                         x.b = mid;
                     else
                         x.a = mid;
                     x.iters += 1;
                     x.done = stop(x);
+                    ++walked;
                 }
+                ISO_REQUIRE(walked > 0 || plan_levels[kk] == 0, ISO_ERR_INTERNAL, "bisection midpoint was not planned");
             }
         }
         for (int32_t kk = 2; kk <= kmax; ++kk) {
@@ -849,15 +1029,27 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
         return;
     }
 
-    // ---- single k: speculative bisection passes on the device
-    const int max_batches = (h.max_iters / SPEC_LEVELS) / PASS_BATCH + 3;
-    int batches = 0;
+    // ---- single k: speculative bisection passes on the device.  After every
+    // pass the vertices whose subtree decides alike over the new bracket are
+    // frozen (their contribution no longer depends on the threshold), and once
+    // enough have frozen the position list the passes visit drops them.
+    DPArgs B = A;
+    B.nextl = P.nextl;
+    B.smask = P.smask;
+    fill_t<uint8_t>(P.frozen, 0, n, s);
+    std::vector<int32_t> als = ls;  // level starts of B's position list
+    int32_t nact = (int32_t)n;
+    int32_t *act_next = P.act0, *als_next = P.als0;
+    int32_t frozen_listed = 0;  // frozen vertices when the list was last rebuilt
+    int passes = 0;
     while (true) {
-        for (int b = 0; b < PASS_BATCH; ++b) {
-            hipLaunchKernelGGL(k_make_cands, dim3(1), dim3(M), 0, s, P.st, P.Nvals);
-            LAUNCH_CHECK();
-            launch_levels<M, false>(A, ls, maxdepth, s);
-            hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, s, P.st, P.Nvals, P.cnt, root_slot);
+        hipLaunchKernelGGL(k_make_cands, dim3(1), dim3(M), 0, s, P.st, P.Nvals, P.nextl);
+        LAUNCH_CHECK();
+        if (nact > 0) launch_levels<M, false, true>(B, als, maxdepth, s);
+        hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, s, P.st, P.Nvals, P.cnt, root_slot);
+        LAUNCH_CHECK();
+        if (nact > 0) {
+            hipLaunchKernelGGL(k_freeze, dim3(grid_for(nact, 256)), dim3(256), 0, s, B, nact, P.frozen);
             LAUNCH_CHECK();
         }
         HIP_CHECK(hipMemcpyAsync(&h, P.st, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -865,7 +1057,28 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
         ISO_REQUIRE(!(h.bad & 8), ISO_ERR_INTERNAL, "bisection candidates out of step");
         ISO_REQUIRE(!(h.bad & 16), ISO_ERR_INTERNAL, "decision at beta turned NO during bisection");
         if (h.done) break;
-        ISO_REQUIRE(++batches < max_batches, ISO_ERR_INTERNAL, "bisection did not terminate");
+        ISO_REQUIRE(++passes <= h.max_iters + 8, ISO_ERR_INTERNAL, "bisection did not terminate");
+        if (h.nfrozen - frozen_listed > nact / 8) {
+            hipLaunchKernelGGL(k_keep_flags, dim3(grid_for((int64_t)nact + 1, 256)), dim3(256), 0, s, B.act, nact,
+                               P.frozen, P.keep);
+            LAUNCH_CHECK();
+            exclusive_scan_i32(P.keep, P.kpos, (int64_t)nact + 1, nullptr, P.scan_scratch, s);
+            hipLaunchKernelGGL(k_compact, dim3(grid_for(nact, 256)), dim3(256), 0, s, B.act, nact, P.keep, P.kpos,
+                               act_next);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_active_starts, dim3(grid_for(maxdepth + 2, 256)), dim3(256), 0, s, B.level_start,
+                               maxdepth + 2, P.kpos, als_next);
+            LAUNCH_CHECK();
+            HIP_CHECK(hipMemcpyAsync(als.data(), als_next, sizeof(int32_t) * (maxdepth + 2), hipMemcpyDeviceToHost,
+                                     s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            B.act = act_next;
+            B.level_start = als_next;
+            act_next = act_next == P.act0 ? P.act1 : P.act0;
+            als_next = als_next == P.als0 ? P.als1 : P.als0;
+            nact = als[maxdepth + 1];
+            frozen_listed = h.nfrozen;
+        }
     }
     {
         double *cn = cl_num ? cl_num : P.cl_num_tmp;
