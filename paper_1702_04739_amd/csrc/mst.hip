@@ -1104,6 +1104,25 @@ __global__ __launch_bounds__(256) void k_permute_rows(const uint4 *__restrict__ 
     }
 }
 
+// The same copy in the BF16 screen's fragment order: within the 16 KB of
+// chunk c of a tile, 32-row block b at uint4 128 b, 16-wide K step t at +64 t,
+// then lane l = 32 h + (row mod 32) at +l, holding elements 16 t + 8 h .. +7
+// of the chunk (the row's 16-byte piece 2 t + h): the operand one lane feeds to
+// a 32 x 32 x 16 MFMA, so a wave reads a block's K step as one contiguous 1 KB.
+__global__ __launch_bounds__(256) void k_permute_rows_frag(const uint4 *__restrict__ Xr,
+                                                           const int32_t *__restrict__ perm, int64_t nchunks,
+                                                           int64_t row_u4, uint4 *__restrict__ Xq) {
+    static_assert(GT == 256, "four pieces per thread cover a chunk of the tile");
+    const int64_t tile = blockIdx.x / nchunks, c = blockIdx.x - tile * nchunks;
+    uint4 *dst = Xq + (tile * nchunks + c) * (4 * GT);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int u = k * 256 + (int)threadIdx.x;  // destination slot
+        const int row = 32 * (u >> 7) + (u & 31), piece = 2 * ((u >> 6) & 1) + ((u >> 5) & 1);
+        dst[u] = Xr[(int64_t)perm[tile * GT + row] * row_u4 + c * 4 + piece];
+    }
+}
+
 __global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ keep,
                                const int32_t *__restrict__ pos, int2 *__restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1413,8 +1432,9 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         const int64_t nchunks = row_u4 / 4;
         ISO_REQUIRE(npos % GT == 0 && row_u4 % 4 == 0 && npos / GT * nchunks <= (int64_t)UINT32_MAX, ISO_ERR_INTERNAL,
                     "tile copy of %lld rows", (long long)npos);
-        hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)(npos / GT * nchunks)), dim3(256), 0, s,
-                           static_cast<const uint4 *>(P.Xr), order, nchunks, row_u4, static_cast<uint4 *>(P.Xq));
+        hipLaunchKernelGGL(rep == ISO_PREC_BF16 ? k_permute_rows_frag : k_permute_rows,
+                           dim3((unsigned)(npos / GT * nchunks)), dim3(256), 0, s, static_cast<const uint4 *>(P.Xr),
+                           order, nchunks, row_u4, static_cast<uint4 *>(P.Xq));
         LAUNCH_CHECK();
     };
     tile_copy(P.perm, P.n_pad);

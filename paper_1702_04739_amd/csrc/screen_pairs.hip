@@ -59,9 +59,8 @@ constexpr int PT = 256;                // points per tile (rows of a work item)
 constexpr int PH = 128;                // columns of a work item (half of tile J)
 constexpr int SROWS = PH + PT;         // staged rows per K chunk: the columns, then the rows
 constexpr int NW = 4;                  // waves per workgroup
-constexpr int RW = 128, CW = 64;       // rows and columns per wave
-constexpr int NIB = RW / 32, NJB = CW / 32;
-constexpr int RUNS = SROWS * 4 / 64 / NW;  // 1 KB DMA runs per wave and chunk
+constexpr int RUNS = SROWS * 4 / 64 / NW;  // 1 KB DMA runs per wave and chunk (both operands staged)
+constexpr int CRUNS = PH * 4 / 64 / NW;    // 1 KB DMA runs per wave and chunk (columns only)
 constexpr int NPRE = (PT + PH + 64 * NW - 1) / (64 * NW);
 #ifndef PAIR_SB
 #define PAIR_SB 4                      // tile pairs are ordered in blocks of PAIR_SB x PAIR_SB tiles
@@ -165,6 +164,19 @@ __device__ __forceinline__ void list_push_global(const ScreenArgs &A, int64_t p,
 // and candidates per (point, other component); no diagonal pairs).
 constexpr int MODE_PLAIN = 0, MODE_LIST = 1, MODE_FINAL = 2;
 
+// BF16 (register rows): wave w computes rows [64 w, +64) x all PH columns as
+// 2 x 4 blocks; the rows' operand is loaded straight into registers (each
+// wave's rows are its own), only the columns, which all four waves read, are
+// staged in LDS.  The other precisions: wave (wi, wj) computes rows
+// [128 wi, +128) x columns [64 wj, +64) as 4 x 2 blocks, both operands staged.
+template <int REP>
+struct PWave {
+    static constexpr bool RR = REP == ISO_PREC_BF16;  // rows in registers
+    static constexpr int RW = RR ? 64 : 128, CW = RR ? PH : 64;
+    static constexpr int NIB = RW / 32, NJB = CW / 32;
+    static constexpr int STAGE_U4 = (RR ? PH : SROWS) * 4;  // uint4 slots of one LDS stage
+};
+
 template <int REP, bool DIAG, int MODE>
 __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
                                                             int64_t per_xcd, int64_t nitems) {
@@ -172,18 +184,28 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     static_assert(!(FINAL && DIAG), "the final round has no diagonal tile pairs");
     using P = PPrec<REP>;
     using T = typename P::T;
+    using WL = PWave<REP>;
+    constexpr bool RR = WL::RR;
+    constexpr int RW = WL::RW, CW = WL::CW, NIB = WL::NIB, NJB = WL::NJB;
     __shared__ PairLDS S;
-    // NSTAGE = 3 staging buffers of one K chunk: rows 0..PH-1 = the columns j,
-    // rows PH.. = the rows i; 64 bytes per row in four 16-byte slots, slot
-    // (row, part) at row * 4 + (part xor ((row >> 2) & 3)), which makes the
-    // MFMA fragment reads (16 consecutive rows, one part) bank-conflict free.
-    __shared__ __attribute__((aligned(16))) uint4 stage0[SROWS * 4];
-    __shared__ __attribute__((aligned(16))) uint4 stage1[SROWS * 4];
-    __shared__ __attribute__((aligned(16))) uint4 stage2[SROWS * 4];
+    // NSTAGE = 3 staging buffers of one K chunk.  Both operands staged: rows
+    // 0..PH-1 = the columns j, rows PH.. = the rows i; 64 bytes per row in four
+    // 16-byte slots, slot (row, part) at row * 4 + (part xor ((row >> 2) & 3)),
+    // which makes the MFMA fragment reads (16 consecutive rows, one part)
+    // bank-conflict free.  Register rows (BF16): the PH columns in the
+    // fragment order of the screen copy (1 KB per 32-column block and 16-wide
+    // K step, lane l's 16 bytes at 16 l), so every fragment read is one
+    // contiguous 1 KB.
+    __shared__ __attribute__((aligned(16))) uint4 stage0[WL::STAGE_U4];
+    __shared__ __attribute__((aligned(16))) uint4 stage1[WL::STAGE_U4];
+    __shared__ __attribute__((aligned(16))) uint4 stage2[WL::STAGE_U4];
+    // register rows: the epilogue's list and candidate staging, which the
+    // other layout keeps in the idle K stages
+    __shared__ __attribute__((aligned(16))) uint4 xstage[RR ? 2 * SROWS * 4 : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wi = w >> 1, wj = w & 1;
+    const int wi = RR ? w : w >> 1, wj = RR ? 0 : w & 1;
     const T *X = reinterpret_cast<const T *>(A.Xtile);  // rows in the tile order
     const int64_t d_pad = A.d_pad;
 
@@ -290,24 +312,80 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         ISO_STEP(stage1, stage0, c + 1)                                                                      \
         ISO_STEP(stage2, stage1, c + 2)                                                                      \
     }
-    if constexpr (REP == ISO_PREC_BF16) {
-#define ISO_COMPUTE(SB)                                                                                       \
-    _Pragma("unroll") for (int ks = 0; ks < P::KC; ks += P::KSTEP) {                                          \
-        const int kel = ks + (lane >> 5) * P::VEC;                                                             \
-        bf16x8 a[NJB], bb[NIB];                                                                               \
+    if constexpr (RR) {
+        // Register rows (BF16 only).  The screen copy is in fragment order:
+        // chunk C of a tile is 16 KB, 32-row block b at 2 KB b, 16-wide K step
+        // t at +1 KB t, lane l's 16 bytes at +16 l (row 32 b + l mod 32, K
+        // elements 32 C + 16 t + 8 (l div 32) .. +7).  The PH columns of the
+        // item are blocks 4 half .. 4 half + 3 of tile J (8 KB, staged by
+        // CRUNS 1 KB DMA runs per wave); wave w's rows are blocks 2 w, 2 w + 1
+        // of tile I (four 16-byte loads per lane and chunk, straight into
+        // registers, issued two chunks ahead).
+        static_assert(NIB == 2 && NJB * 32 == PH && CRUNS == 2, "register-row layout");
+        const char *colb = XJb + half * (PH * 64) + (int64_t)lane * 16;
+        const char *rowb = XIb + (int64_t)(2 * w) * 2048 + (int64_t)lane * 16;
+        uint4 rg0[2][2], rg1[2][2], rg2[2][2];  // [block][K step] of chunks c, c+1, c+2 (mod 3)
+#define ISO_RISSUE(STG, RG, C)                                                                                \
+    {                                                                                                        \
+        _Pragma("unroll") for (int r = 0; r < CRUNS; ++r) __builtin_amdgcn_global_load_lds(                 \
+            (const void *)(colb + (int64_t)(C) * (PT * 64) + (w * CRUNS + r) * 1024),                         \
+            (__attribute__((address_space(3))) void *)&STG[(w * CRUNS + r) * 64], 16, 0, 0);                \
+        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int t = 0; t < 2; ++t) RG[ib][t] = \
+            *reinterpret_cast<const uint4 *>(rowb + (int64_t)(C) * (PT * 64) + ib * 2048 + t * 1024);        \
+    }
+#define ISO_RCOMPUTE(SB, RG)                                                                                  \
+    _Pragma("unroll") for (int t = 0; t < 2; ++t) {                                                          \
+        bf16x8 a[NJB];                                                                                        \
         _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) {                                                  \
-            const uint4 v = SB[frag_slot(CW * wj + 32 * jb + (lane & 31), kel)];                               \
+            const uint4 v = SB[(jb * 2 + t) * 64 + lane];                                                     \
             a[jb] = *reinterpret_cast<const bf16x8 *>(&v);                                                    \
         }                                                                                                     \
-        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) {                                                  \
-            const uint4 v = SB[frag_slot(PH + RW * wi + 32 * ib + (lane & 31), kel)];                          \
-            bb[ib] = *reinterpret_cast<const bf16x8 *>(&v);                                                   \
+        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) {                                                    \
+            const bf16x8 bb = *reinterpret_cast<const bf16x8 *>(&RG[ib][t]);                                  \
+            _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) acc[ib][jb] =                                  \
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb, acc[ib][jb], 0, 0, 0);                     \
         }                                                                                                     \
-        _Pragma("unroll") for (int ib = 0; ib < NIB; ++ib) _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) \
-            acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[jb], bb[ib], acc[ib][jb], 0, 0, 0);        \
     }
-        ISO_PIPELINE
-#undef ISO_COMPUTE
+#define ISO_RSTEP(SB, RG, SN, RN, C)                                                                          \
+    if ((C) < nchunks) {                                                                                     \
+        if ((C) + 1 < nchunks)                                                                               \
+            __builtin_amdgcn_s_waitcnt(VMCNT(CRUNS + 4));                                                    \
+        else                                                                                                 \
+            __builtin_amdgcn_s_waitcnt(VMCNT(0));                                                            \
+        __builtin_amdgcn_s_barrier();                                                                        \
+        if ((C) + 2 < nchunks) ISO_RISSUE(SN, RN, (C) + 2)                                                   \
+        ISO_RCOMPUTE(SB, RG)                                                                                 \
+    }
+        // Steps inside the loop issue unconditionally, so every step finds
+        // exactly two chunks (12 loads) in flight and the register loads need
+        // no wait beyond the one before the barrier; the last one to four
+        // chunks run in the guarded steps after it.
+#define ISO_RSTEP_FULL(SB, RG, SN, RN, C)                                                                     \
+    {                                                                                                        \
+        __builtin_amdgcn_s_waitcnt(VMCNT(CRUNS + 4));                                                        \
+        __builtin_amdgcn_s_barrier();                                                                        \
+        ISO_RISSUE(SN, RN, (C) + 2)                                                                          \
+        ISO_RCOMPUTE(SB, RG)                                                                                 \
+    }
+        // (both prologue issues unconditional -- with one chunk the second
+        // re-reads chunk 0 and is never used -- so that the loop's first step
+        // sees the same loads in flight from either predecessor)
+        ISO_RISSUE(stage0, rg0, 0)
+        ISO_RISSUE(stage1, rg1, nchunks > 1 ? 1 : 0)
+        int c = 0;
+        for (; c + 4 < nchunks; c += 3) {
+            ISO_RSTEP_FULL(stage0, rg0, stage2, rg2, c)
+            ISO_RSTEP_FULL(stage1, rg1, stage0, rg0, c + 1)
+            ISO_RSTEP_FULL(stage2, rg2, stage1, rg1, c + 2)
+        }
+        ISO_RSTEP(stage0, rg0, stage2, rg2, c)
+        ISO_RSTEP(stage1, rg1, stage0, rg0, c + 1)
+        ISO_RSTEP(stage2, rg2, stage1, rg1, c + 2)
+        ISO_RSTEP(stage0, rg0, stage2, rg2, c + 3)
+#undef ISO_RSTEP_FULL
+#undef ISO_RSTEP
+#undef ISO_RCOMPUTE
+#undef ISO_RISSUE
     } else if constexpr (REP == ISO_PREC_FP8) {
         // one 32 x 32 x 64 FP8 MFMA per block and chunk: lane l supplies row
         // l mod 32 and k = 32 (l div 32) .. +31, i.e. slots 2 (l div 32) and
@@ -383,7 +461,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         uint32_t m[NIB];
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib) m[ib] = INF_BITS;
-        uint32_t cown = INF_BITS;
+        uint32_t cown[NJB / 2];  // lane 16 (jb mod 2) + q of each half keeps column (jb, q) in slot jb / 2
+#pragma unroll
+        for (int o = 0; o < NJB / 2; ++o) cown[o] = INF_BITS;
 #pragma unroll
         for (int jb = 0; jb < NJB; ++jb)
 #pragma unroll
@@ -410,13 +490,14 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                     cmin = min(cmin, v);
                 }
                 const uint32_t cm = min32(cmin);
-                if ((lane & 31) == 16 * jb + q) cown = cm;
+                if ((lane & 31) == 16 * (jb & 1) + q) cown[jb >> 1] = cm;
                 if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the columns in flight
             }
-        {
-            const int qo = lane & 15, jo = (lane >> 4) & 1;
+#pragma unroll
+        for (int o = 0; o < NJB / 2; ++o) {
+            const int qo = lane & 15, jo = 2 * o + ((lane >> 4) & 1);
             const int jl = CW * wj + 32 * jo + 8 * (qo >> 2) + 4 * (lane >> 5) + (qo & 3);
-            if (cown < INF_BITS) atomicMin(&S.cmin[jl], cown);
+            if (cown[o] < INF_BITS) atomicMin(&S.cmin[jl], cown[o]);
         }
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib) {
@@ -519,7 +600,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     constexpr int CAP = FINAL ? SCR_CAP2 : SCR_CAP;
     int32_t *const cjs = FINAL ? A.gcj : A.cj;
     float *const cls = FINAL ? A.gcl : A.cl;
-    int32_t *const cp = reinterpret_cast<int32_t *>(stage1);
+    int32_t *const cp = reinterpret_cast<int32_t *>(RR ? xstage + SROWS * 4 : stage1);
     int32_t *const co = cp + CAP_STAGE;
     float *const cv = reinterpret_cast<float *>(co + CAP_STAGE);
     float *const ct = cv + CAP_STAGE;
@@ -592,7 +673,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // reaches their list threshold), staged in the first staging buffer and
     // appended after the barrier like the candidates.
     if constexpr (LIST) {
-        int32_t *lp = reinterpret_cast<int32_t *>(stage0);
+        int32_t *lp = reinterpret_cast<int32_t *>(RR ? xstage : stage0);
         int32_t *lo = lp + LIST_STAGE;
         float *lvv = reinterpret_cast<float *>(lo + LIST_STAGE);
         auto stage = [&](int64_t p, int32_t other, float v) {
@@ -647,7 +728,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         for (int e = tid; e < cnt; e += 64 * NW) commit(cp[e], co[e], cv[e], ct[e]);
     }
     if constexpr (LIST) {
-        const int32_t *lp = reinterpret_cast<const int32_t *>(stage0);
+        const int32_t *lp = reinterpret_cast<const int32_t *>(RR ? xstage : stage0);
         const int32_t *lo = lp + LIST_STAGE;
         const float *lvv = reinterpret_cast<const float *>(lo + LIST_STAGE);
         const int cnt = min(S.nlist, LIST_STAGE);
