@@ -108,6 +108,48 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
     return rec
 
 
+def kernel_traffic_table(fetch_dir, write_dir, stats_csv, copy_mib, patterns=()):
+    """Markdown table of HBM bytes and rates per kernel from two rocprofv3
+    --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, each scaled by
+    what it reads for the plain device copy of copy_mib MiB run first) and the
+    kernel statistics of a --kernel-trace --stats run of the same command."""
+    import collections
+    import csv
+    import glob
+    import re
+
+    def per_kernel(d, counter):
+        tot, calls, copy = collections.defaultdict(float), collections.defaultdict(int), None
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                v, k = float(r["Counter_Value"]), r["Kernel_Name"]
+                if "copyBuffer" in k and copy is None and v > 0.25 * copy_mib * 1024:
+                    copy = v
+                    continue
+                tot[k] += v
+                calls[k] += 1
+        return tot, calls, copy
+
+    ft, fc, fcopy = per_kernel(fetch_dir, "FETCH_SIZE")
+    wt, _, wcopy = per_kernel(write_dir, "WRITE_SIZE")
+    nb = copy_mib * (1 << 20)
+    fs, ws = nb / (fcopy * 1024.0), nb / (wcopy * 1024.0)
+    dur = {r["Name"]: float(r["TotalDurationNs"]) for r in csv.DictReader(open(stats_csv))}
+    lines = ["copy calibration: FETCH_SIZE x %.4f, WRITE_SIZE x %.4f" % (fs, ws), "",
+             "| kernel | calls | fetch MB | write MB | kernel ms | GB/s |", "|---|---:|---:|---:|---:|---:|"]
+    for k in sorted(set(ft) | set(wt), key=lambda k: -(ft.get(k, 0) + wt.get(k, 0))):
+        m = re.search(r"(k_\w+|__amd\w+)(<[^()]*>)?", k)
+        name = m.group(0) if m else k[:60]
+        if patterns and not any(p in name for p in patterns):
+            continue
+        fb, wb, ns = ft.get(k, 0) * 1024 * fs, wt.get(k, 0) * 1024 * ws, dur.get(k, 0.0)
+        lines.append("| `%s` | %d | %.1f | %.1f | %.3f | %s |" % (name, fc.get(k, 0), fb / 1e6, wb / 1e6, ns / 1e6,
+                                                              "%.0f" % ((fb + wb) / ns) if ns > 0 else "-"))
+    return "\n".join(lines)
+
+
 def cpu_baseline(n_full, k, sample_ns, tree=None):
     """The FP64 oracle (single thread) on subsamples of the same recipe: its
     O(n^2 d) MST time is measured at each sample size, the exponent fitted
@@ -311,6 +353,9 @@ def main():
                     help="before the steps, run one plain device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--traffic-report", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs into profiles/screen_<precision>_traffic.json and exit")
+    ap.add_argument("--kernel-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "STATS_CSV"),
+                    help="print the per-kernel HBM table of two rocprofv3 --pmc runs and a --stats run, and exit")
+    ap.add_argument("--kernels", nargs="*", default=[], help="with --kernel-traffic: kernel name substrings to keep")
     args = ap.parse_args()
 
     if args.traffic_report:
@@ -320,6 +365,10 @@ def main():
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)
         print(json.dumps(rec))
+        return
+
+    if args.kernel_traffic:
+        print(kernel_traffic_table(*args.kernel_traffic, args.calibrate_copy or 1024, args.kernels))
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

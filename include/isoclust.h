@@ -243,6 +243,8 @@ iso_status iso_subpartition_all_k(const int32_t *parent, const double *length, i
  *   omega0[v] = sum over j != v, ascending j, of phi(D(v, j))   (phi_kind ISO_PHI_*),
  *   p0[v]     = alpha * sum over j != v, ascending j, of D(v, j) (exactly 0 when alpha == 0).
  * O(n^2 d) FP64 work.  Either output may be NULL.  X [n*ld] FP32; sigma > 0.
+ * Scratch of about 8 n (d + 1024) bytes is allocated with hipMallocAsync on
+ * `stream` and released with hipFreeAsync in stream order (no synchronisation).
  * Errors: null X, n < 2, d < 1, ld < d, sigma <= 0 or not finite, alpha < 0 or
  * not finite, unknown phi_kind (INVALID_ARG). */
 iso_status iso_graph_weights(const float *X, int64_t n, int64_t d, int64_t ld, double sigma, int32_t phi_kind,

@@ -7,11 +7,13 @@
 // D(v, j) is the square root of the FP64 left-to-right sum over coordinates of
 // the squared differences (each difference and square rounded separately, as
 // everywhere on the exact path), so every distance is the same double the
-// FP64 definition gives.  One workgroup owns 64 rows and sweeps the column
-// blocks in ascending order; a block's 64 x 64 distances are formed in
-// registers (4 x 4 per thread) from coordinates staged in LDS, their phi and D
-// values pass through LDS, and one thread per row adds them in ascending j, so
-// the row sums follow the definition's order too.
+// FP64 definition gives.  The rows' sums must follow the definition's order,
+// so the work is split by column slabs of up to GW_SLAB columns: for each slab
+// in ascending order, k_gw_dist forms every distance D(i, j) of the slab in
+// parallel (64 x 64 tiles, 4 x 4 per thread, coordinates staged in LDS as
+// FP64) and stores it transposed (slab column major, so that the next pass
+// reads consecutive rows), then k_gw_sum lets one thread per row add the
+// slab's phi(D) and D to its running sums in ascending j.
 #include <cmath>
 
 #include "common.hpp"
@@ -20,73 +22,100 @@ namespace iso {
 
 namespace {
 
-constexpr int GW_T = 64;  // rows (and columns) per block
-constexpr int GW_K = 32;  // coordinates per LDS stage
+constexpr int GW_T = 64;       // rows and columns per distance tile
+constexpr int GW_K = 16;       // coordinates per LDS stage
+constexpr int64_t GW_SLAB = 1024;  // columns per slab
 
-template <int PHI>
-__global__ __launch_bounds__(256) void k_graph_weights(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
-                                                       double sigma, double alpha, double *__restrict__ omega0,
-                                                       double *__restrict__ p0) {
-    __shared__ float xr[GW_T][GW_K + 1], xc[GW_T][GW_K + 1];
-    __shared__ double fv[GW_T][GW_T + 1], dv[GW_T][GW_T + 1];
+// The points as FP64 (exact), row-major n x d.
+__global__ void k_gw_widen(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld, double *__restrict__ Xd) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * d; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / d, t = e - i * d;
+        Xd[e] = (double)X[i * ld + t];
+    }
+}
+
+// Dt[jj * n + i] = D(i, j0 + jj) for the slab's columns jj < w: the square
+// root of sum over t (left to right) of (x_it - x_jt)^2, each difference and
+// square rounded separately.
+__global__ __launch_bounds__(256) void k_gw_dist(const double *__restrict__ Xd, int64_t n, int64_t d, int64_t j0,
+                                                 int64_t w, double *__restrict__ Dt) {
+    __shared__ double xr[GW_T][GW_K + 1], xc[GW_T][GW_K + 1];
     const int tid = threadIdx.x;
-    const int tr = tid >> 4, tc = tid & 15;  // rows 4 tr .. +3, columns 4 tc .. +3 of the block
-    const int64_t i0 = (int64_t)blockIdx.x * GW_T;
-    double so = 0.0, sp = 0.0;  // running sums of row i0 + tid (threads < 64)
-    for (int64_t j0 = 0; j0 < n; j0 += GW_T) {
-        double acc[4][4];
+    const int ti = tid & 15, tj = tid >> 4;  // rows 4 ti .. +3, slab columns 4 tj .. +3 of the tile
+    const int64_t i0 = (int64_t)blockIdx.x * GW_T, c0 = (int64_t)blockIdx.y * GW_T;
+    double acc[4][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-        for (int64_t t0 = 0; t0 < d; t0 += GW_K) {
-            for (int q = tid; q < GW_T * GW_K; q += 256) {
-                const int r = q / GW_K, c = q % GW_K;
-                const int64_t t = t0 + c;
-                xr[r][c] = (i0 + r < n && t < d) ? X[(i0 + r) * ld + t] : 0.0f;
-                xc[r][c] = (j0 + r < n && t < d) ? X[(j0 + r) * ld + t] : 0.0f;
-            }
-            __syncthreads();
-            const int tn = d - t0 < GW_K ? (int)(d - t0) : GW_K;
-            for (int c = 0; c < tn; ++c) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const double df = (double)xr[4 * tr + a][c] - (double)xc[4 * tc + b][c];
-                        const double sq = df * df;
-                        acc[a][b] = acc[a][b] + sq;
-                    }
-            }
-            __syncthreads();
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int64_t t0 = 0; t0 < d; t0 += GW_K) {
+        for (int q = tid; q < GW_T * GW_K; q += 256) {
+            const int r = q / GW_K, c = q % GW_K;
+            const int64_t t = t0 + c;
+            xr[r][c] = (i0 + r < n && t < d) ? Xd[(i0 + r) * d + t] : 0.0;
+            xc[r][c] = (c0 + r < w && t < d) ? Xd[(j0 + c0 + r) * d + t] : 0.0;
         }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const double dist = sqrt(acc[a][b]);
-                fv[4 * tr + a][4 * tc + b] =
-                    PHI == ISO_PHI_GAUSS_SQ ? exp(-(dist * dist) / (2.0 * sigma * sigma)) : exp(-dist / sigma);
-                dv[4 * tr + a][4 * tc + b] = dist;
-            }
         __syncthreads();
-        if (tid < GW_T) {
-            const int64_t i = i0 + tid;
-            for (int c = 0; c < GW_T; ++c) {
-                const int64_t j = j0 + c;
-                if (j >= n) break;
-                if (j == i) continue;
-                so = so + fv[tid][c];
-                sp = sp + dv[tid][c];
-            }
+        const int tn = d - t0 < GW_K ? (int)(d - t0) : GW_K;
+        for (int c = 0; c < tn; ++c) {
+            double xa[4], xb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) xa[a] = xr[4 * ti + a][c];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xb[b] = xc[4 * tj + b][c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double df = xa[a] - xb[b];
+                    const double sq = df * df;
+                    acc[a][b] = acc[a][b] + sq;
+                }
         }
         __syncthreads();
     }
-    if (tid < GW_T && i0 + tid < n) {
-        const int64_t i = i0 + tid;
-        if (omega0) omega0[i] = so;
-        if (p0) p0[i] = alpha == 0.0 ? 0.0 : alpha * sp;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t jj = c0 + 4 * tj + b;
+        if (jj >= w) continue;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int64_t i = i0 + 4 * ti + a;
+            if (i < n) Dt[jj * n + i] = sqrt(acc[a][b]);
+        }
     }
+}
+
+// Row i adds phi(D(i, j)) and D(i, j) of the slab's columns, ascending j, j != i.
+template <int PHI>
+__global__ void k_gw_sum(const double *__restrict__ Dt, int64_t n, int64_t j0, int64_t w, double sigma,
+                         double *__restrict__ so, double *__restrict__ sp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a = so[i], b = sp[i];
+    for (int64_t jj = 0; jj < w; ++jj) {
+        if (j0 + jj == i) continue;
+        const double dist = Dt[jj * n + i];
+        a = a + (PHI == ISO_PHI_GAUSS_SQ ? exp(-(dist * dist) / (2.0 * sigma * sigma)) : exp(-dist / sigma));
+        b = b + dist;
+    }
+    so[i] = a;
+    sp[i] = b;
+}
+
+__global__ void k_gw_zero(double *__restrict__ so, double *__restrict__ sp, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    so[i] = 0.0;
+    sp[i] = 0.0;
+}
+
+__global__ void k_gw_finish(const double *__restrict__ so, const double *__restrict__ sp, int64_t n, double alpha,
+                            double *__restrict__ omega0, double *__restrict__ p0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (omega0) omega0[i] = so[i];
+    if (p0) p0[i] = alpha == 0.0 ? 0.0 : alpha * sp[i];
 }
 
 }  // namespace
@@ -110,13 +139,46 @@ extern "C" iso_status iso_graph_weights(const float *X, int64_t n, int64_t d, in
         require_device();
         if (omega0 == nullptr && p0 == nullptr) return;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const unsigned blocks = (unsigned)((n + GW_T - 1) / GW_T);
-        if (phi_kind == ISO_PHI_GAUSS_SQ)
-            hipLaunchKernelGGL(k_graph_weights<ISO_PHI_GAUSS_SQ>, dim3(blocks), dim3(256), 0, s, X, n, d, ld, sigma,
-                               alpha, omega0, p0);
-        else
-            hipLaunchKernelGGL(k_graph_weights<ISO_PHI_EXP_DIST>, dim3(blocks), dim3(256), 0, s, X, n, d, ld, sigma,
-                               alpha, omega0, p0);
+        // workspace: allocated and released in stream order (no synchronisation)
+        const int64_t slab = n < GW_SLAB ? n : GW_SLAB;
+        struct StreamBuffer {
+            void *p = nullptr;
+            hipStream_t s = nullptr;
+            ~StreamBuffer() {
+                if (p) (void)hipFreeAsync(p, s);
+            }
+        } buf;
+        buf.s = s;
+        Arena a;
+        auto carve = [&](double *&Xd, double *&Dt, double *&so, double *&sp) {
+            Xd = a.take<double>((size_t)(n * d));
+            Dt = a.take<double>((size_t)(slab * n));
+            so = a.take<double>((size_t)n);
+            sp = a.take<double>((size_t)n);
+        };
+        double *Xd, *Dt, *so, *sp;
+        carve(Xd, Dt, so, sp);
+        HIP_CHECK(hipMallocAsync(&buf.p, a.used, s));
+        a = Arena{static_cast<char *>(buf.p), 0, a.used};
+        carve(Xd, Dt, so, sp);
+        const unsigned gn = grid_for(n, 256);
+        const unsigned gw = grid_for(n * d, 256) < 65536 ? grid_for(n * d, 256) : 65536;
+        hipLaunchKernelGGL(k_gw_widen, dim3(gw), dim3(256), 0, s, X, n, d, ld, Xd);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gw_zero, dim3(gn), dim3(256), 0, s, so, sp, n);
+        LAUNCH_CHECK();
+        for (int64_t j0 = 0; j0 < n; j0 += slab) {
+            const int64_t w = n - j0 < slab ? n - j0 : slab;
+            hipLaunchKernelGGL(k_gw_dist, dim3((unsigned)((n + GW_T - 1) / GW_T), (unsigned)((w + GW_T - 1) / GW_T)),
+                               dim3(256), 0, s, Xd, n, d, j0, w, Dt);
+            LAUNCH_CHECK();
+            if (phi_kind == ISO_PHI_GAUSS_SQ)
+                hipLaunchKernelGGL(k_gw_sum<ISO_PHI_GAUSS_SQ>, dim3(gn), dim3(256), 0, s, Dt, n, j0, w, sigma, so, sp);
+            else
+                hipLaunchKernelGGL(k_gw_sum<ISO_PHI_EXP_DIST>, dim3(gn), dim3(256), 0, s, Dt, n, j0, w, sigma, so, sp);
+            LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_gw_finish, dim3(gn), dim3(256), 0, s, so, sp, n, alpha, omega0, p0);
         LAUNCH_CHECK();
     });
 }

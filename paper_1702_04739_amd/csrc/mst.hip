@@ -676,12 +676,14 @@ __global__ __launch_bounds__(256) void k_list_capture(
 // points in sorted[sstart[c] ..).
 __global__ void k_fr_perm(const int32_t *__restrict__ sorted, const int32_t *__restrict__ comp, int64_t n,
                           const int32_t *__restrict__ pstart, const int32_t *__restrict__ sstart,
-                          int32_t *__restrict__ permF) {
+                          int32_t *__restrict__ permF, int32_t *__restrict__ posF) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const int32_t id = sorted[q];
     const int c = comp[id];
-    permF[pstart[c] + (q - sstart[c])] = id;
+    const int32_t pos = pstart[c] + (int32_t)(q - sstart[c]);
+    permF[pos] = id;
+    posF[id] = pos;
 }
 
 // One wave per row: exact values of the row's candidates that can still be
@@ -692,7 +694,8 @@ __global__ void k_fr_perm(const int32_t *__restrict__ sorted, const int32_t *__r
 template <bool F64>
 __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
                                                     const int32_t *__restrict__ comp, const float *__restrict__ Emax,
-                                                    const float *__restrict__ bestc, const uint32_t *__restrict__ upair,
+                                                    const float *__restrict__ bestc, const int32_t *__restrict__ posF,
+                                                    int64_t bstride, const uint32_t *__restrict__ upair,
                                                     const int32_t *__restrict__ ccnt, const int32_t *__restrict__ gcj,
                                                     const float *__restrict__ gcl, float kappa, float dn,
                                                     double *__restrict__ rowd, int32_t *__restrict__ rowj,
@@ -713,6 +716,7 @@ __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X,
         const int ci = valid ? comp[i] : 0;
         const float E = valid ? Emax[i] : 0.0f;
         const float *xi = X + (valid ? i : 0) * ld;
+        const float *bci = bestc + (valid ? posF[i] : 0);  // the row's minima per component, stride bstride
         const int32_t *js = gcj + (valid ? i : 0) * SCR_CAP2;
         const float *ls = gcl + (valid ? i : 0) * SCR_CAP2;
         for (int c = lane; c < FR_KC; c += 64) {
@@ -725,7 +729,7 @@ __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X,
                 const int32_t j = js[q];
                 const int c2 = comp[j];
                 double v = __builtin_huge_val();
-                if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
+                if (ls[q] <= fminf((bci[c2 * bstride] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
                     v = d2_f64_lane(xi, X + (int64_t)j * ld, d);
                     ++evaluated;
                     atomicMin(&td[w][c2], (unsigned long long)__double_as_longlong(v));
@@ -737,7 +741,7 @@ __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X,
                 const int32_t j = js[q];
                 const int c2 = comp[j];
                 double v = __builtin_huge_val();
-                if (ls[q] <= fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
+                if (ls[q] <= fminf((bci[c2 * bstride] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn)) {
                     v = (double)d2_f32_wave(xi, X + (int64_t)j * ld, d);
                     if (lane == 0) {
                         ++evaluated;
@@ -776,6 +780,7 @@ __global__ __launch_bounds__(256) void k_fr_recheck(const float *__restrict__ X,
 // and rows whose list overflowed (C_OVF).  One wave per row.
 __global__ __launch_bounds__(256) void k_fr_count(int64_t n, const int32_t *__restrict__ comp,
                                                   const float *__restrict__ Emax, const float *__restrict__ bestc,
+                                                  const int32_t *__restrict__ posF, int64_t bstride,
                                                   const uint32_t *__restrict__ upair,
                                                   const int32_t *__restrict__ ccnt, const int32_t *__restrict__ gcj,
                                                   const float *__restrict__ gcl, float kappa, float dn,
@@ -790,10 +795,11 @@ __global__ __launch_bounds__(256) void k_fr_count(int64_t n, const int32_t *__re
         }
         const int ci = comp[i];
         const float E = Emax[i];
+        const float *bci = bestc + posF[i];
         for (int q = lane; q < cnt0; q += 64) {
             const int c2 = comp[gcj[i * SCR_CAP2 + q]];
             pass += gcl[i * SCR_CAP2 + q] <=
-                    fminf((bestc[i * FR_KC + c2] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn);
+                    fminf((bci[c2 * bstride] + E) * kappa, __uint_as_float(upair[fr_pair(ci, c2)]) * dn);
         }
     }
 #pragma unroll
@@ -1158,11 +1164,11 @@ struct MstPlan {
     int32_t *lscnt, *lj;            // entries offered, [n][LIST_CAP] partners
     uint32_t *ldrop;                // smallest dropped value
     // final round: padded tile order, per (point, component) minima and records
-    int32_t *permF, *tcompF, *fr_pstart, *fr_sstart, *rowj;
+    int32_t *permF, *posF, *tcompF, *fr_pstart, *fr_sstart, *rowj;
     int2 *pairsF;
     int64_t ntF_cap;
     int32_t options;                // ISO_MST_NO_LISTS / ISO_MST_NO_FINAL / ISO_MST_NO_ESCALATE
-    float *bestc;
+    float *bestc;                   // final round: [component][position] minima, ntF_cap * GT positions per row
     double *rowd;
     unsigned long long *W1, *W2;
     uint32_t *upair;
@@ -1240,11 +1246,12 @@ struct MstPlan {
         lj = a.take<int32_t>((size_t)n * LIST_CAP);
         lv = a.take<float>((size_t)n * LIST_CAP);
         permF = a.take<int32_t>(n_pad + FR_KC * GT);
+        posF = a.take<int32_t>(n);
         tcompF = a.take<int32_t>(ntF_cap);
         fr_pstart = a.take<int32_t>(FR_KC);
         fr_sstart = a.take<int32_t>(FR_KC);
         pairsF = a.take<int2>(ntF_cap * (ntF_cap - 1) / 2);
-        bestc = a.take<float>((size_t)n * FR_KC);
+        bestc = a.take<float>((size_t)FR_KC * ntF_cap * GT);
         rowd = a.take<double>((size_t)n * FR_KC);
         rowj = a.take<int32_t>((size_t)n * FR_KC);
         W1 = a.take<unsigned long long>(FR_KC * FR_KC);
@@ -1453,6 +1460,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     // then screened the plain way).
     auto final_round = [&]() -> bool {
         const int K = (int)ncomp;
+        const int64_t bstride = P.ntF_cap * GT;  // positions per component row of bestc
         // component sizes -> padded tile order (host: at most FR_KC components)
         fill<int32_t>(P.flag, 0, K, s);
         histogram_i32(P.comp, n, K, P.flag, s);
@@ -1489,7 +1497,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.pvals), P.ptk, P.ptv, n, kb, P.psort, s);
         fill<int32_t>(P.permF, (int32_t)(P.n_pad - 1), ntF * GT, s);
         hipLaunchKernelGGL(k_fr_perm, dim3(grid_for(n, 256)), dim3(256), 0, s, P.pvals, P.comp, n, P.fr_pstart,
-                           P.fr_sstart, P.permF);
+                           P.fr_sstart, P.permF, P.posF);
         LAUNCH_CHECK();
         tile_copy(P.permF, ntF * GT);
         xq_plain = false;
@@ -1497,6 +1505,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         FA.perm = P.permF;
         FA.Xtile = P.Xq;
         FA.bestc = P.bestc;
+        FA.bestc_stride = bstride;
         FA.tcomp = P.tcompF;
         FA.upair = P.upair;
         FA.up = up;
@@ -1504,7 +1513,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         FA.lcnt = nullptr;
         FA.rows = nullptr;
         FA.nrows = 0;
-        fill<uint32_t>(reinterpret_cast<uint32_t *>(P.bestc), 0x7F800000u, n * FR_KC, s);
+        fill<uint32_t>(reinterpret_cast<uint32_t *>(P.bestc), 0x7F800000u, (int64_t)K * bstride, s);
         fill<uint32_t>(P.upair, 0x7F800000u, FR_KC * FR_KC, s);
         fill<int32_t>(P.ccnt, 0, n, s);
         scr.start(s);
@@ -1517,8 +1526,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             int32_t hc[C_COUNT];
             fill<int32_t>(P.counters + C_OVF, 0, 1, s);
             fill<int32_t>(P.counters + C_FRWORK, 0, 2, s);
-            hipLaunchKernelGGL(k_fr_count, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.Emax, P.bestc, P.upair,
-                               P.ccnt, P.gcj, P.gcl, kappa, dn, P.counters);
+            hipLaunchKernelGGL(k_fr_count, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.Emax, P.bestc, P.posF,
+                               bstride, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.counters);
             LAUNCH_CHECK();
             HIP_CHECK(hipMemcpyAsync(hc, P.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
@@ -1539,11 +1548,12 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         fill<unsigned long long>(P.W2, U64_MAX, FR_KC * FR_KC, s);
         if (f64)
             hipLaunchKernelGGL(k_fr_recheck<true>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.comp, P.Emax,
-                               P.bestc, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj, P.W1, P.counters);
+                               P.bestc, P.posF, bstride, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj,
+                               P.W1, P.counters);
         else
             hipLaunchKernelGGL(k_fr_recheck<false>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.comp,
-                               P.Emax, P.bestc, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd, P.rowj, P.W1,
-                               P.counters);
+                               P.Emax, P.bestc, P.posF, bstride, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.rowd,
+                               P.rowj, P.W1, P.counters);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_fr_pick, dim3(grid_for(n * FR_KC, 256)), dim3(256), 0, s, P.rowd, P.rowj, P.comp, n,
                            P.W1, P.W2);

@@ -92,10 +92,12 @@ struct ScreenArgs {
     int32_t *lj;             // [n * LIST_CAP]
     float *lv;               // [n * LIST_CAP] Dhat^2 of the entry
     // final round (bestc != nullptr): every tile holds points of one
-    // component (tcomp), the minima are kept per (point, other component) in
-    // bestc[p * FR_KC + c], and candidates go to gcj/gcl (SCR_CAP2 per point,
-    // counted in ccnt)
+    // component (tcomp), the minima are kept per (other component, position
+    // in the tile order) in bestc[c * bestc_stride + pos] (so that an item's
+    // rows and columns read and lower consecutive entries), and candidates go
+    // to gcj/gcl (SCR_CAP2 per point, counted in ccnt)
     float *bestc;
+    int64_t bestc_stride;
     const int32_t *tcomp;    // [tiles] component of each tile of the order
     uint32_t *upair;         // [FR_KC * FR_KC] (fr_pair) running bound of each pair of components' lightest
                              // edge on the recheck scale, as float bits (+inf on entry)

@@ -222,34 +222,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // final round: rows' minima go to the column tile's component and back
     const int32_t compI = FINAL ? A.tcomp[pr.x] : 0, compJ = FINAL ? A.tcomp[pr.y] : 0;
 
-    // tile constants
-    {
-        const int64_t i = perm[I0 + tid];
-        S.rid[tid] = (int32_t)i;
-        S.rmin[tid] = INF_BITS;
-        S.rE[tid] = i < A.n ? A.Emax[i] : 0.0f;
-        if (tid < PH) {
-            const int64_t j = perm[J0 + tid];
-            S.cid[tid] = (int32_t)j;
-            S.cmin[tid] = INF_BITS;
-            S.cE[tid] = j < A.n ? A.Emax[j] : 0.0f;
-            S.csq[tid] = A.sq[j];
-            if (REP == ISO_PREC_INT8) S.csqi[tid] = A.sqi[j];
-            S.ccomp[tid] = A.comp[j];
-        }
-    }
-    static_assert(64 * NW == PT, "one thread per row");
-    float si[NIB];
-    int ci[NIB];
-    int32_t sii[NIB];  // INT8: exact integer squared norms of the rows
-#pragma unroll
-    for (int ib = 0; ib < NIB; ++ib) {
-        const int64_t i = perm[I0 + RW * wi + 32 * ib + (lane & 31)];
-        si[ib] = A.sq[i];
-        ci[ib] = A.comp[i];
-        sii[ib] = REP == ISO_PREC_INT8 ? A.sqi[i] : 0;
-    }
-
     // asynchronous staging: each wave moves RUNS 1 KB runs of slots per chunk
     // with global_load_lds_dwordx4 (lane L of a run fills slot base + L); a run
     // covers 16 rows, all columns (runs < PH / 16) or all rows
@@ -268,6 +240,67 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         soff[r] = (uint32_t)(trow * 64 + part * 16);
     }
     const int nchunks = (int)(d_pad / P::KC);
+    // Register rows (BF16): the first two chunks are requested before the tile
+    // constants, whose dependent loads then overlap them.  Both prologue issues
+    // are unconditional (with one chunk the second re-reads chunk 0 and is
+    // never used), so that the loop's first step sees the same loads in flight
+    // from either predecessor.
+    static_assert(!RR || (NIB == 2 && NJB * 32 == PH && CRUNS == 2), "register-row layout");
+    const char *colb = XJb + half * (PH * 64) + (int64_t)lane * 16;
+    const char *rowb = XIb + (int64_t)(2 * w) * 2048 + (int64_t)lane * 16;
+    uint4 rg0[2][2], rg1[2][2], rg2[2][2];  // [block][K step] of chunks c, c+1, c+2 (mod 3)
+#define ISO_RISSUE(STG, RG, C)                                                                                \
+    {                                                                                                        \
+        _Pragma("unroll") for (int r = 0; r < CRUNS; ++r) __builtin_amdgcn_global_load_lds(                 \
+            (const void *)(colb + (int64_t)(C) * (PT * 64) + (w * CRUNS + r) * 1024),                         \
+            (__attribute__((address_space(3))) void *)&STG[(w * CRUNS + r) * 64], 16, 0, 0);                \
+        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int t = 0; t < 2; ++t) RG[ib][t] = \
+            *reinterpret_cast<const uint4 *>(rowb + (int64_t)(C) * (PT * 64) + ib * 2048 + t * 1024);        \
+    }
+    if constexpr (RR) {
+        ISO_RISSUE(stage0, rg0, 0)
+        ISO_RISSUE(stage1, rg1, nchunks > 1 ? 1 : 0)
+    }
+
+    // tile constants: the point ids first, then every load that depends on
+    // them, unconditionally (padding ids are clamped for Emax, which has n
+    // entries), so that each level costs one round trip
+    static_assert(64 * NW == PT, "one thread per row");
+    const int32_t pid_r = perm[I0 + tid];
+    const int32_t pid_c = perm[J0 + (tid & (PH - 1))];
+    int32_t pid_w[NIB];
+#pragma unroll
+    for (int ib = 0; ib < NIB; ++ib) pid_w[ib] = perm[I0 + RW * wi + 32 * ib + (lane & 31)];
+    const int64_t nlast = A.n - 1;
+    const float er = A.Emax[pid_r < A.n ? pid_r : nlast];
+    const float ec = A.Emax[pid_c < A.n ? pid_c : nlast];
+    const float sqc = A.sq[pid_c];
+    const int32_t cpc = A.comp[pid_c];
+    const int32_t sqic = REP == ISO_PREC_INT8 ? A.sqi[pid_c] : 0;
+    float si[NIB];
+    int ci[NIB];
+    int32_t sii[NIB];  // INT8: exact integer squared norms of the rows
+#pragma unroll
+    for (int ib = 0; ib < NIB; ++ib) {
+        si[ib] = A.sq[pid_w[ib]];
+        ci[ib] = A.comp[pid_w[ib]];
+        sii[ib] = REP == ISO_PREC_INT8 ? A.sqi[pid_w[ib]] : 0;
+    }
+    S.rid[tid] = pid_r;
+    S.rmin[tid] = INF_BITS;
+    S.rE[tid] = pid_r < A.n ? er : 0.0f;
+    {
+        // threads t and t + PH write the same column's values (no branch, so
+        // that the loads above are not sunk behind one)
+        const int tc = tid & (PH - 1);
+        S.cid[tc] = pid_c;
+        S.cmin[tc] = INF_BITS;
+        S.cE[tc] = pid_c < A.n ? ec : 0.0f;
+        S.csq[tc] = sqc;
+        if (REP == ISO_PREC_INT8) S.csqi[tc] = sqic;
+        S.ccomp[tc] = cpc;
+    }
+
 #define ISO_ISSUE(STG, C)                                                                                     \
     {                                                                                                        \
         _Pragma("unroll") for (int r = 0; r < RUNS; ++r) __builtin_amdgcn_global_load_lds(                  \
@@ -321,18 +354,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         // CRUNS 1 KB DMA runs per wave); wave w's rows are blocks 2 w, 2 w + 1
         // of tile I (four 16-byte loads per lane and chunk, straight into
         // registers, issued two chunks ahead).
-        static_assert(NIB == 2 && NJB * 32 == PH && CRUNS == 2, "register-row layout");
-        const char *colb = XJb + half * (PH * 64) + (int64_t)lane * 16;
-        const char *rowb = XIb + (int64_t)(2 * w) * 2048 + (int64_t)lane * 16;
-        uint4 rg0[2][2], rg1[2][2], rg2[2][2];  // [block][K step] of chunks c, c+1, c+2 (mod 3)
-#define ISO_RISSUE(STG, RG, C)                                                                                \
-    {                                                                                                        \
-        _Pragma("unroll") for (int r = 0; r < CRUNS; ++r) __builtin_amdgcn_global_load_lds(                 \
-            (const void *)(colb + (int64_t)(C) * (PT * 64) + (w * CRUNS + r) * 1024),                         \
-            (__attribute__((address_space(3))) void *)&STG[(w * CRUNS + r) * 64], 16, 0, 0);                \
-        _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int t = 0; t < 2; ++t) RG[ib][t] = \
-            *reinterpret_cast<const uint4 *>(rowb + (int64_t)(C) * (PT * 64) + ib * 2048 + t * 1024);        \
-    }
 #define ISO_RCOMPUTE(SB, RG)                                                                                  \
     _Pragma("unroll") for (int t = 0; t < 2; ++t) {                                                          \
         bf16x8 a[NJB];                                                                                        \
@@ -367,11 +388,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         ISO_RISSUE(SN, RN, (C) + 2)                                                                          \
         ISO_RCOMPUTE(SB, RG)                                                                                 \
     }
-        // (both prologue issues unconditional -- with one chunk the second
-        // re-reads chunk 0 and is never used -- so that the loop's first step
-        // sees the same loads in flight from either predecessor)
-        ISO_RISSUE(stage0, rg0, 0)
-        ISO_RISSUE(stage1, rg1, nchunks > 1 ? 1 : 0)
         int c = 0;
         for (; c + 4 < nchunks; c += 3) {
             ISO_RSTEP_FULL(stage0, rg0, stage2, rg2, c)
@@ -534,7 +550,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const int t = is_row ? u : u - PT;
         const int64_t p = is_row ? S.rid[t] : S.cid[t];
         const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
-        uint32_t *const bp = FINAL ? reinterpret_cast<uint32_t *>(A.bestc) + p * FR_KC + (is_row ? compJ : compI)
+        uint32_t *const bp = FINAL ? reinterpret_cast<uint32_t *>(A.bestc) + (is_row ? compJ : compI) * A.bestc_stride +
+                                         (is_row ? I0 + t : J0 + t)
                                    : reinterpret_cast<uint32_t *>(A.best) + p;
         const uint32_t old = p < A.n ? *reinterpret_cast<const volatile uint32_t *>(bp) : INF_BITS;
         if (p < A.n && m < old) atomicMin(bp, m);
