@@ -82,6 +82,11 @@ typedef int32_t iso_status;
 #define ISO_MST_NO_FINAL 0x2    /* no final round joining <= 64 components    */
 #define ISO_MST_NO_ESCALATE 0x4 /* keep the requested screen precision even
                                    when its bound is too loose for the data  */
+#define ISO_MST_PAIR_BOUNDS 0x8 /* BF16 screen: capture thresholds from each
+                                   pair's own error bound instead of the
+                                   separable bound against the largest norm
+                                   (chosen by itself when the points' norms are
+                                   heavy tailed; every round is then screened) */
 
 /* Vertex weight omega (eq. 2.2) and flow phi (eq. 2.1) readings. */
 #define ISO_OMEGA_TREE 0   /* omega(v) = sum of phi over v's tree edges         */
@@ -107,6 +112,7 @@ typedef struct {
     int32_t screen_precision;/* precision of the screen that built the tree: the
                                 requested one, or ISO_PREC_FP32 when its error
                                 bound was too loose for the data (escalation)   */
+    int32_t pair_bounds;     /* 1 when that screen used per-pair bounds        */
 } iso_mst_info;
 
 /* Device bytes iso_mst needs as workspace for n points in d dimensions (room

@@ -41,7 +41,7 @@ def version() -> str:
 
 
 def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = True, final_round: bool = True,
-        escalate: bool = True):
+        escalate: bool = True, pair_bounds: bool = False):
     """Euclidean minimum spanning tree of the rows of ``points`` (n x d, float32, GPU).
 
     Returns (parent int32[n] rooted at 0 with parent[0] = -1, length float64[n]
@@ -52,7 +52,9 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     from the second round, one final round for the last <= 64 components); the
     tree is the same either way.  ``escalate`` lets a low-precision screen
     whose error bound is too loose for the data hand over to the FP32 screen
-    (``info["screen_precision"]`` tells which one built the tree)."""
+    (``info["screen_precision"]`` tells which one built the tree).
+    ``pair_bounds`` makes a BF16 screen use each pair's own error bound in its
+    capture thresholds (it does so by itself when the norms are heavy tailed)."""
     torch = _torch()
     _require_cuda(points, "points", torch.float32)
     if points.dim() != 2:
@@ -70,7 +72,7 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     length = torch.empty(n, dtype=torch.float64, device=dev)
     info = _lib.MstInfo()
     flags = ((0 if lists else _lib.MST_NO_LISTS) | (0 if final_round else _lib.MST_NO_FINAL)
-             | (0 if escalate else _lib.MST_NO_ESCALATE))
+             | (0 if escalate else _lib.MST_NO_ESCALATE) | (_lib.MST_PAIR_BOUNDS if pair_bounds else 0))
     rc = lib.iso_mst(ctypes.c_void_p(points.data_ptr()), n, d, ld, _lib.PRECISION[precision], _lib.RECHECK[recheck],
                      flags,
                      ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), ctypes.byref(info),
@@ -79,7 +81,8 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     return parent, length, {"rounds": info.rounds, "list_rounds": info.list_rounds, "candidates": info.candidates,
                             "rescanned_rows": info.rescanned_rows, "mst_weight": info.mst_weight,
                             "final_components": info.final_components,
-                            "screen_precision": {v: k for k, v in _lib.PRECISION.items()}[info.screen_precision]}
+                            "screen_precision": {v: k for k, v in _lib.PRECISION.items()}[info.screen_precision],
+                            "pair_bounds": bool(info.pair_bounds)}
 
 
 def mst_prim(points, return_order: bool = False):

@@ -300,6 +300,31 @@ __global__ void k_row_bound(const float *__restrict__ rn, const float *__restric
     Emax[i] = pair_bound(B, rn[i], __uint_as_float(*rmax_bits), re[i], __uint_as_float(*emax_bits)) + 1e-30f;
 }
 
+// Sums of r_i and e_i over the points (one atomic per workgroup each).
+__global__ __launch_bounds__(256) void k_norm_sums(const float *__restrict__ rn, const float *__restrict__ re,
+                                                  int64_t n, double *__restrict__ out) {
+    __shared__ double sr[256], se[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        a += rn[i];
+        b += re[i];
+    }
+    sr[threadIdx.x] = a;
+    se[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+            se[threadIdx.x] += se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], sr[0]);
+        atomicAdd(&out[1], se[0]);
+    }
+}
+
 __global__ void k_iota_comp(int32_t *comp, int64_t n, int64_t n_pad) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += (int64_t)gridDim.x * blockDim.x)
         comp[i] = i < n ? (int32_t)i : -1;
@@ -354,13 +379,15 @@ __device__ inline bool key_less(double d2a, int ja, double d2b, int jb) {
 }
 
 // U_c = min over rows i of c of (b_i + Emax_i) (1 + rho), rounded up: an upper
-// bound on the recheck value of c's lightest outgoing edge.
+// bound on the recheck value of c's lightest outgoing edge.  With pair bounds
+// (ub != nullptr) ub_i, the least Dhat^2 + E_ij screened, replaces b_i + Emax_i.
 __global__ void k_comp_ub(const float *__restrict__ best, const float *__restrict__ Emax,
-                          const int32_t *__restrict__ comp, int64_t n, float up, uint32_t *__restrict__ comp_ub) {
+                          const float *__restrict__ ub, const int32_t *__restrict__ comp, int64_t n, float up,
+                          uint32_t *__restrict__ comp_ub) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const float b = i < n ? best[i] : SCR_INF;
     const bool active = b < SCR_INF;
-    const float u = active ? (b + Emax[i]) * up : 0.0f;
+    const float u = active ? (ub ? ub[i] : b + Emax[i]) * up : 0.0f;
     grouped_atomic_min(comp_ub, active ? comp[i] : 0, __float_as_uint(u), active);
 }
 
@@ -419,16 +446,19 @@ __device__ inline void eval_candidates(const float *__restrict__ X, int64_t ld, 
 // Threshold for a row's candidates (on the real-D^2 scale of the lower
 // bounds): they must be able to beat both the row's own minimum and the
 // component's bound U (a recheck value, so divided by 1 - rho).
+// With pair bounds (ub != nullptr) the row's own upper bound ub_i replaces
+// b_i + Emax_i; the lower bound b_i - Emax_i stays (it must hold for every j).
 __device__ inline bool row_threshold(const float *__restrict__ best, const float *__restrict__ Emax,
-                                     const int32_t *__restrict__ comp, const uint32_t *__restrict__ comp_ub,
-                                     int64_t i, float kappa, float dn, float &thr) {
+                                     const float *__restrict__ ub, const int32_t *__restrict__ comp,
+                                     const uint32_t *__restrict__ comp_ub, int64_t i, float kappa, float dn,
+                                     float &thr) {
     const float b = best[i];
     const uint32_t ubits = comp_ub[comp[i]];
     if (!(b < SCR_INF) || ubits == 0xFFFFFFFFu) return false;
     const float U = __uint_as_float(ubits) * dn;
     const float E = Emax[i];
     if (lower_of(b, E) > U) return false;  // the row cannot hold its component's lightest edge
-    thr = fminf((b + E) * kappa, U);
+    thr = fminf((ub ? ub[i] : b + E) * kappa, U);
     return true;
 }
 
@@ -437,7 +467,7 @@ __device__ inline bool row_threshold(const float *__restrict__ best, const float
 template <bool F64>
 __global__ __launch_bounds__(256) void k_recheck_rows(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
                                                       const float *__restrict__ best, const float *__restrict__ Emax,
-                                                      const int32_t *__restrict__ comp,
+                                                      const float *__restrict__ ub, const int32_t *__restrict__ comp,
                                                       const uint32_t *__restrict__ comp_ub,
                                                       const int32_t *__restrict__ ccnt, const int32_t *__restrict__ cj,
                                                       const float *__restrict__ cl, float kappa, float dn,
@@ -455,7 +485,7 @@ __global__ __launch_bounds__(256) void k_recheck_rows(const float *__restrict__ 
         const int cnt = ccnt[i];
         if (cnt == SCR_FORCE) {
             if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
-        } else if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
+        } else if (row_threshold(best, Emax, ub, comp, comp_ub, i, kappa, dn, thr)) {
             if (cnt > SCR_CAP) {
                 if (lane == 0) glist[atomicAdd(&counters[C_GATHER], 1)] = (int32_t)i;
             } else {
@@ -476,7 +506,7 @@ __global__ __launch_bounds__(256) void k_recheck_rows(const float *__restrict__ 
 template <bool F64>
 __global__ __launch_bounds__(256) void k_recheck_gather(const float *__restrict__ X, int64_t d, int64_t ld,
                                                         const float *__restrict__ best, const float *__restrict__ Emax,
-                                                        const int32_t *__restrict__ comp,
+                                                        const float *__restrict__ ub, const int32_t *__restrict__ comp,
                                                         const uint32_t *__restrict__ comp_ub,
                                                         const int32_t *__restrict__ glist, int32_t ng,
                                                         const int32_t *__restrict__ gcnt,
@@ -491,7 +521,7 @@ __global__ __launch_bounds__(256) void k_recheck_gather(const float *__restrict_
     double out_d2 = __builtin_huge_val();
     int out_j = -1, evaluated = 0;
     float thr;
-    if (row_threshold(best, Emax, comp, comp_ub, i, kappa, dn, thr)) {
+    if (row_threshold(best, Emax, ub, comp, comp_ub, i, kappa, dn, thr)) {
         const int cnt = gcnt[q];
         if (cnt > SCR_CAP2) {
             if (lane == 0) rlist[atomicAdd(&counters[C_OVF], 1)] = (int32_t)i;
@@ -1148,7 +1178,8 @@ struct MstPlan {
     int32_t precision;
     void *Xr;                       // screen representation (FP32, BF16 or FP8), [n_pad][d_pad]
     void *Xq;                       // the tile-pair screen's copy: rows in the tile order, chunk-major per tile
-    float *mu, *sq, *rn, *re, *Emax, *best, *cl, *gcl;
+    float *mu, *sq, *rn, *re, *Emax, *best, *ub, *cl, *gcl;
+    double *nsum;                   // sums of the norm and representation-error bounds (pair-bound decision)
     int32_t *pgrid, *grid_min, *sqi, *qg;
     float *pmin, *pmax, *cmin, *cmax;
     int2 *pairs, *pairs_r;          // all tile pairs (diagonal first); the pairs kept this round
@@ -1194,6 +1225,8 @@ struct MstPlan {
         rn = a.take<float>(n_pad);
         re = a.take<float>(n_pad);
         Emax = a.take<float>(n);
+        ub = a.take<float>(n);
+        nsum = a.take<double>(2);
         best = a.take<float>(n);
         cl = a.take<float>((size_t)n * SCR_CAP);
         rmax = a.take<uint32_t>(1);
@@ -1292,6 +1325,7 @@ size_t plan_bytes(MstPlan p) {
 // FP32 screen, whose representation is exact.  Thresholds: more than a
 // quarter of the points in the gathered pass, or more than 64 + n/64 rescans.
 constexpr double ESCALATE_GATHER = 0.25, ESCALATE_RESCAN = 1.0 / 64.0;
+constexpr double PB_RATIO = 4.0;  // separable / typical bound above which BF16 uses pair bounds
 
 void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t *parent, double *length,
              iso_mst_info *info, hipStream_t s, bool *escalate) {
@@ -1391,6 +1425,34 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     hipLaunchKernelGGL(k_row_bound, dim3(grid_for(n, 256)), dim3(256), 0, s, P.rn, P.re, n, bound, P.rmax, P.emax,
                        P.Emax);
     LAUNCH_CHECK();
+    // Pair bounds (BF16): when the separable bound of a typical row against
+    // the largest norm and representation error, pair_bound(r_mean, r_max,
+    // e_mean, e_max), exceeds PB_RATIO times the bound of two typical rows, the
+    // thresholds use each pair's own bound (heavy-tailed norms); the flag
+    // ISO_MST_PAIR_BOUNDS forces them.
+    bool pb = false;
+    if (rep == ISO_PREC_BF16) {
+        fill<double>(P.nsum, 0.0, 2, s);
+        hipLaunchKernelGGL(k_norm_sums, dim3(std::min<unsigned>(grid_for(n, 256), 1024u)), dim3(256), 0, s, P.rn,
+                           P.re, n, P.nsum);
+        LAUNCH_CHECK();
+        double hs[2] = {0.0, 0.0};
+        uint32_t hm[2] = {0u, 0u};
+        HIP_CHECK(hipMemcpyAsync(hs, P.nsum, sizeof(hs), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&hm[0], P.rmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&hm[1], P.emax, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        float rmx, emx;
+        std::memcpy(&rmx, &hm[0], sizeof(float));
+        std::memcpy(&emx, &hm[1], sizeof(float));
+        const double rm = hs[0] / (double)n, em = hs[1] / (double)n, g = bound.g;
+        auto pbound = [&](double ri, double rj, double ei, double ej) {
+            return g * (ri + rj) * (ri + rj) + (ei + ej) * (2.0 * (ri + rj) + ei + ej);
+        };
+        const double typ = pbound(rm, rm, em, em), sep = pbound(rm, rmx, em, emx);
+        pb = (P.options & ISO_MST_PAIR_BOUNDS) != 0 || (typ > 0.0 && sep > PB_RATIO * typ);
+    }
+    float *const ubp = pb ? P.ub : nullptr;
     hipLaunchKernelGGL(k_iota_comp, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.comp, n, P.n_pad);
     LAUNCH_CHECK();
 
@@ -1451,9 +1513,12 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
 
     int64_t ncomp = n;
     int rounds = 0, list_rounds = 0, final_components = 0;
+    // (the neighbour lists and the final round decide with the separable
+    // bound, which pair-bound data makes useless: every round is screened)
     enum { LISTS_NONE, LISTS_BUILDING, LISTS_READY, LISTS_OFF } lists =
-        (P.options & ISO_MST_NO_LISTS) ? LISTS_OFF : LISTS_NONE;
-    bool final_off = (P.options & ISO_MST_NO_FINAL) != 0;
+        ((P.options & ISO_MST_NO_LISTS) || pb) ? LISTS_OFF : LISTS_NONE;
+    bool final_off = (P.options & ISO_MST_NO_FINAL) != 0 || pb;
+    SA.ub = ubp;
 
     // The final round (at most FR_KC components left): true when it joined
     // them all, false when a point's candidate list overflowed (the round is
@@ -1626,8 +1691,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                P.best);
             LAUNCH_CHECK();
             fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,
-                               P.comp_ub);
+            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
+                               up, P.comp_ub);
             LAUNCH_CHECK();
             fill<int32_t>(P.counters + C_FORCE, 0, 1, s);
             hipLaunchKernelGGL(k_list_capture, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.comp_ub, P.best,
@@ -1697,6 +1762,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 lists = LISTS_BUILDING;
             }
             fill<uint32_t>(reinterpret_cast<uint32_t *>(P.best), 0x7F800000u, n, s);  // +inf
+            if (ubp) fill<uint32_t>(reinterpret_cast<uint32_t *>(ubp), 0x7F800000u, n, s);
             fill<int32_t>(P.ccnt, 0, n, s);
             SA.rows = nullptr;
             SA.nrows = 0;
@@ -1708,18 +1774,20 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 lists = LISTS_READY;
             }
             fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n, up,
-                               P.comp_ub);
+            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
+                               up, P.comp_ub);
             LAUNCH_CHECK();
         }
         fill<int32_t>(P.counters + C_OVF, 0, 1, s);
         fill<int32_t>(P.counters + C_GATHER, 0, 1, s);
         if (f64)
             hipLaunchKernelGGL(k_recheck_rows<true>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.best, P.Emax,
-                               P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist, P.counters);
+                               ubp, P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist,
+                               P.counters);
         else
             hipLaunchKernelGGL(k_recheck_rows<false>, dim3(row_grid(n)), dim3(256), 0, s, X, n, d, ld, P.best,
-                               P.Emax, P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist, P.counters);
+                               P.Emax, ubp, P.comp, P.comp_ub, P.ccnt, P.cj, P.cl, kappa, dn, P.rb_d2, P.rb_j, P.glist,
+                               P.counters);
         LAUNCH_CHECK();
         int32_t h_gather = 0;
         HIP_CHECK(hipMemcpyAsync(&h_gather, P.counters + C_GATHER, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1729,7 +1797,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             T.screen_launches += 1;
             T.screen_ms += scr.elapsed_ms();
         }
-        if (may_escalate && (double)h_gather > ESCALATE_GATHER * (double)n) {
+        // (with pair bounds an overflowing list reflects the loose early
+        // thresholds of the screen, not a loose bound: the gathered pass settles
+        // such rows, and only rows that overflow it again count)
+        if (may_escalate && !pb && (double)h_gather > ESCALATE_GATHER * (double)n) {
             give_up();
             return;
         }
@@ -1741,18 +1812,18 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             if (list_round) {
                 // the gathered rows' minima are now exact: a tighter U
                 fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, P.comp, n,
+                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
                                    up, P.comp_ub);
                 LAUNCH_CHECK();
             }
             if (f64)
                 hipLaunchKernelGGL(k_recheck_gather<true>, dim3(grid_for(h_gather, 4)), dim3(256), 0, s, X, d, ld,
-                                   P.best, P.Emax, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa, dn,
-                                   P.rb_d2, P.rb_j, P.rlist, P.counters);
+                                   P.best, P.Emax, ubp, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa,
+                                   dn, P.rb_d2, P.rb_j, P.rlist, P.counters);
             else
                 hipLaunchKernelGGL(k_recheck_gather<false>, dim3(grid_for(h_gather, 4)), dim3(256), 0, s, X, d, ld,
-                                   P.best, P.Emax, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa, dn,
-                                   P.rb_d2, P.rb_j, P.rlist, P.counters);
+                                   P.best, P.Emax, ubp, P.comp, P.comp_ub, P.glist, h_gather, P.gcnt, P.gcj, P.gcl, kappa,
+                                   dn, P.rb_d2, P.rb_j, P.rlist, P.counters);
             LAUNCH_CHECK();
             if (may_escalate) {
                 int32_t h_ovf = 0;
@@ -1880,6 +1951,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         info->list_rounds = list_rounds;
         info->final_components = final_components;
         info->screen_precision = rep;
+        info->pair_bounds = pb ? 1 : 0;
         info->candidates = cand;
         info->rescanned_rows = resc;
     }
@@ -1917,7 +1989,8 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
                     ISO_ERR_INVALID_ARG, "unknown precision %d", precision);
         ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
                     "unknown recheck %d", recheck);
-        ISO_REQUIRE((flags & ~(uint32_t)(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL | ISO_MST_NO_ESCALATE)) == 0,
+        ISO_REQUIRE((flags & ~(uint32_t)(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL | ISO_MST_NO_ESCALATE |
+                                          ISO_MST_PAIR_BOUNDS)) == 0,
                     ISO_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
         const int32_t options = (int32_t)flags;
         require_device();

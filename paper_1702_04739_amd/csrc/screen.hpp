@@ -78,6 +78,13 @@ struct ScreenArgs {
     int64_t col_split;       // gathered pass: columns per workgroup (multiple of SCR_COLS)
     int32_t *gcj;            // [nrows * SCR_CAP2]
     float *gcl;              // [nrows * SCR_CAP2]
+    // pair bounds (ub != nullptr, BF16 only): the capture thresholds use
+    // ub[i] = min over the partners screened so far of Dhat^2_ij + E_ij (an
+    // upper bound of the row's lightest D^2, +inf on entry) instead of
+    // b_i + Emax_i, and a partner is captured when Dhat^2_ij - E_ij <= kappa ub_i;
+    // for data whose norms are heavy tailed, where Emax_i (taken over the
+    // largest norm of any point) is far above the pairs' own bounds
+    float *ub;               // [n]
     // sweep outputs
     float *best;             // [n]
     int32_t *ccnt;           // [n] candidates (> SCR_CAP = overflow)
@@ -109,6 +116,7 @@ __host__ __device__ inline int fr_pair(int a, int b) { return a < b ? a * FR_KC 
 
 struct ScreenLDS {
     uint32_t rowbest[SCR_ROWS];
+    uint32_t rowub[SCR_ROWS];  // pair bounds: the row's running upper bound ub
     int32_t rowcnt[SCR_ROWS];
     int32_t rowovf[SCR_ROWS];
     float rowE[SCR_ROWS];
@@ -173,6 +181,7 @@ __device__ __forceinline__ void screen_init_rows(ScreenLDS &S, const ScreenArgs 
             i = i0 + q < A.n ? i0 + q : -1;
         }
         S.rowbest[q] = (GATHER && i >= 0) ? __float_as_uint(A.best_in[i]) : __float_as_uint(SCR_INF);
+        S.rowub[q] = (GATHER && i >= 0 && A.ub) ? __float_as_uint(A.ub[i]) : __float_as_uint(SCR_INF);
         S.rowcnt[q] = 0;
         S.rowovf[q] = 0;
         S.rowE[q] = i >= 0 ? A.Emax[i] : 0.0f;
@@ -212,6 +221,28 @@ __device__ __forceinline__ void screen_capture(ScreenLDS &S, const ScreenArgs &A
     if (!(L <= thr)) return;
     if (GATHER) {
         const int pos = atomicAdd(&A.gcnt[slot], 1);  // several workgroups share a slot
+        if (pos < SCR_CAP2) {
+            A.gcj[slot * SCR_CAP2 + pos] = (int32_t)j;
+            A.gcl[slot * SCR_CAP2 + pos] = L;
+        }
+    } else {
+        const int pos = atomicAdd(&S.rowcnt[rl], 1);
+        if (pos < SCR_CAP) {
+            S.lj[rl][pos] = (int32_t)j;
+            S.ll[rl][pos] = L;
+        } else {
+            S.rowovf[rl] = 1;
+        }
+    }
+}
+
+// Pair bounds: capture of one element whose lower bound L is already known.
+template <bool GATHER>
+__device__ __forceinline__ void screen_capture_lb(ScreenLDS &S, const ScreenArgs &A, int rl, int64_t slot, float L,
+                                                  float thr, int64_t j) {
+    if (!(L <= thr)) return;
+    if (GATHER) {
+        const int pos = atomicAdd(&A.gcnt[slot], 1);
         if (pos < SCR_CAP2) {
             A.gcj[slot * SCR_CAP2 + pos] = (int32_t)j;
             A.gcl[slot * SCR_CAP2 + pos] = L;
@@ -267,6 +298,7 @@ __device__ __forceinline__ void screen_finish(ScreenLDS &S, const ScreenArgs &A,
             const int64_t i = i0 + rl;
             if (i >= A.n) continue;
             A.best[i] = __uint_as_float(S.rowbest[rl]);
+            if (A.ub) A.ub[i] = __uint_as_float(S.rowub[rl]);
             const int cnt = S.rowovf[rl] ? SCR_CAP + 1 : S.rowcnt[rl];
             A.ccnt[i] = cnt;
             for (int q = 0; q < cnt && q < SCR_CAP; ++q) {

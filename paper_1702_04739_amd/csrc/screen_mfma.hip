@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                  : REP == ISO_PREC_INT8 ? reinterpret_cast<const T *>(A.XI8)
                                         : reinterpret_cast<const T *>(A.XT);
     const int64_t d_pad = A.d_pad;
+    const bool pb = REP == ISO_PREC_BF16 && A.ub != nullptr;  // pair bounds
 
     screen_init_rows<GATHER>(S, A, i0);
 
@@ -240,10 +241,12 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
             buf ^= 1;
         }
 
-        // phase A: masked Dhat^2 and the row minima
+        // phase A: masked Dhat^2 and the row minima (pair bounds: also each
+        // element's own bound E_ij, the row's least Dhat^2 + E_ij, and the
+        // element's lower bound kept in place of Dhat^2 for phase B)
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) {
-            float m = SCR_INF;
+            float m = SCR_INF, mu = SCR_INF;
 #pragma unroll
             for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
@@ -259,10 +262,16 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                     } else {
                         v = screen_value(acc[ib][jb][q], si[ib], S.csq[jl], ci[ib], S.ccomp[jl]);
                     }
-                    acc[ib][jb][q] = v;
                     m = fminf(m, v);
+                    if (pb) {
+                        const float E = pair_bound(A.bound, ri[ib], S.crn[jl], ei[ib], S.cre[jl]);
+                        mu = fminf(mu, v + E);
+                        v = v < SCR_INF ? fmaxf(lower_of(v, E), 0.0f) : SCR_INF;
+                    }
+                    acc[ib][jb][q] = v;
                 }
             screen_row_min(S, rl[ib], m);
+            if (pb && mu < SCR_INF) atomicMin(&S.rowub[rl[ib]], __float_as_uint(mu));
         }
         __syncthreads();
         if (GATHER) {
@@ -278,6 +287,14 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                     atomicMin(reinterpret_cast<uint32_t *>(A.best) + i, m);
                 else
                     S.rowbest[q] = g;
+                if (pb) {
+                    const uint32_t gu = reinterpret_cast<const volatile uint32_t *>(A.ub)[i];
+                    const uint32_t mu = S.rowub[q];
+                    if (mu < gu)
+                        atomicMin(reinterpret_cast<uint32_t *>(A.ub) + i, mu);
+                    else
+                        S.rowub[q] = gu;
+                }
             }
             __syncthreads();
         }
@@ -288,6 +305,17 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
             float tc, thr;
             screen_thresholds(S, rl[ib], A.kappa, tc, thr);
             const int64_t slot = GATHER ? i0 + rl[ib] : gi[ib];
+            if (pb) {
+                const float thr_pb = __uint_as_float(S.rowub[rl[ib]]) * A.kappa;
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int jl = 64 * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                        screen_capture_lb<GATHER>(S, A, rl[ib], slot, acc[ib][jb][q], thr_pb, j0 + jl);
+                    }
+                continue;
+            }
 #pragma unroll
             for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
@@ -297,7 +325,7 @@ __global__ __launch_bounds__(256, 2) void k_screen_mfma(ScreenArgs A) {
                 }
         }
         __syncthreads();
-        if (!GATHER) screen_compact(S, A.kappa);
+        if (!GATHER && !pb) screen_compact(S, A.kappa);
     }
     __syncthreads();
     screen_finish<GATHER>(S, A, i0);

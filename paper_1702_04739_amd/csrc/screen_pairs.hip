@@ -122,6 +122,17 @@ struct PairLDS {
     uint32_t umin;             // final round: the item's bound of its pair of components' lightest edge
 };
 
+// Pair bounds (BF16 plain rounds with A.ub set): per element its own bound
+// E_ij, the tile minima of Dhat^2 + E_ij (upper bounds) and of the lower bound
+// Dhat^2 - E_ij, and the columns' norm and representation-error bounds; kept in
+// the list-staging half of the epilogue buffer, which plain rounds leave idle.
+struct PBLDS {
+    uint32_t rminU[PT], rminL[PT];
+    uint32_t cminU[PH], cminL[PH];
+    float rrn[PT], rre[PT];
+    float crn[PH], cre[PH];
+};
+
 // After the K loop the first staging buffer holds up to LIST_STAGE
 // neighbour-list entries (point, partner, Dhat^2) and the second up to
 // CAP_STAGE candidates (point, partner, Dhat^2, threshold).
@@ -177,11 +188,12 @@ struct PWave {
     static constexpr int STAGE_U4 = (RR ? PH : SROWS) * 4;  // uint4 slots of one LDS stage
 };
 
-template <int REP, bool DIAG, int MODE>
+template <int REP, bool DIAG, int MODE, bool PB = false>
 __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
                                                             int64_t per_xcd, int64_t nitems) {
     constexpr bool LIST = MODE == MODE_LIST, FINAL = MODE == MODE_FINAL;
     static_assert(!(FINAL && DIAG), "the final round has no diagonal tile pairs");
+    static_assert(!PB || (MODE == MODE_PLAIN && REP == ISO_PREC_BF16), "pair bounds: BF16 plain rounds only");
     using P = PPrec<REP>;
     using T = typename P::T;
     using WL = PWave<REP>;
@@ -202,6 +214,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // register rows: the epilogue's list and candidate staging, which the
     // other layout keeps in the idle K stages
     __shared__ __attribute__((aligned(16))) uint4 xstage[RR ? 2 * SROWS * 4 : 1];
+    static_assert(sizeof(PBLDS) <= SROWS * 4 * sizeof(uint4), "pair-bound tables fit the list-staging half");
+    PBLDS &PS = *reinterpret_cast<PBLDS *>(xstage);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -286,6 +300,10 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         ci[ib] = A.comp[pid_w[ib]];
         sii[ib] = REP == ISO_PREC_INT8 ? A.sqi[pid_w[ib]] : 0;
     }
+    // pair bounds: norm and representation-error bounds of the rows and
+    // columns, kept in LDS until the epilogue (no registers held across the K loop)
+    const float rnr = PB ? A.rn[pid_r] : 0.0f, rer = PB ? A.re[pid_r] : 0.0f;
+    const float rnc = PB ? A.rn[pid_c] : 0.0f, rec = PB ? A.re[pid_c] : 0.0f;
     S.rid[tid] = pid_r;
     S.rmin[tid] = INF_BITS;
     S.rE[tid] = pid_r < A.n ? er : 0.0f;
@@ -299,6 +317,20 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         S.csq[tc] = sqc;
         if (REP == ISO_PREC_INT8) S.csqi[tc] = sqic;
         S.ccomp[tc] = cpc;
+        if constexpr (PB) {
+            PS.crn[tc] = rnc;
+            PS.cre[tc] = rec;
+        }
+    }
+    if constexpr (PB) {
+        PS.rrn[tid] = rnr;
+        PS.rre[tid] = rer;
+        PS.rminU[tid] = INF_BITS;
+        PS.rminL[tid] = INF_BITS;
+        if (tid < PH) {
+            PS.cminU[tid] = INF_BITS;
+            PS.cminL[tid] = INF_BITS;
+        }
     }
 
 #define ISO_ISSUE(STG, C)                                                                                     \
@@ -468,6 +500,31 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
 #undef ISO_ISSUE
     // (the epilogue uses only PairLDS, so no barrier is needed before it)
 
+    // The items' points' running minima (list thresholds, pair bounds) are
+    // read now, so that their latency overlaps the epilogue's arithmetic.  A
+    // value read early can only be larger than the current one (minima only
+    // fall), and it is the value of a real pair, so every threshold built
+    // from it remains a valid upper bound: an early read only captures more.
+    uint32_t pre_old[NPRE], pre_oldu[NPRE];
+    float pre_tau[NPRE];
+#pragma unroll
+    for (int e = 0; e < NPRE; ++e) {
+        const int u = tid + e * 64 * NW;
+        pre_old[e] = pre_oldu[e] = INF_BITS;
+        pre_tau[e] = 0.0f;
+        if (u >= PT + PH) continue;
+        const bool is_row = u < PT;
+        const int t = is_row ? u : u - PT;
+        const int64_t p = is_row ? S.rid[t] : S.cid[t];
+        if (p >= A.n) continue;
+        const uint32_t *const bp = FINAL ? reinterpret_cast<const uint32_t *>(A.bestc) +
+                                               (is_row ? compJ : compI) * A.bestc_stride + (is_row ? I0 + t : J0 + t)
+                                         : reinterpret_cast<const uint32_t *>(A.best) + p;
+        pre_old[e] = *reinterpret_cast<const volatile uint32_t *>(bp);
+        if constexpr (LIST) pre_tau[e] = A.ltau[p];
+        if constexpr (PB) pre_oldu[e] = reinterpret_cast<const volatile uint32_t *>(A.ub)[p];
+    }
+
     // ---- epilogue 1: masked Dhat^2 as bit patterns (padding has s = +inf; a
     // negative rounding result becomes +0), tile minima of rows (in-lane over
     // the lane's 32 columns, then lanes l, l+32) and of columns (in-lane over the
@@ -521,6 +578,64 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             if ((lane >> 5) == 0 && mm < INF_BITS) atomicMin(&S.rmin[RW * wi + 32 * ib + (lane & 31)], mm);
         }
     }
+    // ---- pair bounds: each element's own bound E_ij; the tile minima of the
+    // upper bounds Dhat^2 + E_ij and of the lower bounds max(Dhat^2 - E_ij, 0),
+    // which replace Dhat^2 in the accumulators for the captures (rolled over
+    // the columns, indexed register access, to keep the registers of the
+    // unrolled epilogue)
+    if constexpr (PB) {
+        float rr[NIB], re_[NIB];
+        uint32_t mu[NIB], ml[NIB];
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib) {
+            const int il = RW * wi + 32 * ib + (lane & 31);
+            rr[ib] = PS.rrn[il];
+            re_[ib] = PS.rre[il];
+            mu[ib] = ml[ib] = INF_BITS;
+        }
+#pragma unroll
+        for (int jb = 0; jb < NJB; ++jb) {
+            uint32_t ownU = INF_BITS, ownL = INF_BITS;
+#pragma unroll 1
+            for (int q = 0; q < 16; ++q) {
+                const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const float rj = PS.crn[jl], ej = PS.cre[jl];
+                uint32_t cU = INF_BITS, cL = INF_BITS;
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib) {
+                    const uint32_t v = __float_as_uint(acc[ib][jb][q]);
+                    const float vf = __uint_as_float(v);
+                    const float E = pair_bound(A.bound, rr[ib], rj, re_[ib], ej);
+                    const uint32_t uU = __float_as_uint(vf + E);
+                    const uint32_t uL = v < INF_BITS ? __float_as_uint(fmaxf(lower_of(vf, E), 0.0f)) : INF_BITS;
+                    mu[ib] = min(mu[ib], uU);
+                    ml[ib] = min(ml[ib], uL);
+                    cU = min(cU, uU);
+                    cL = min(cL, uL);
+                    acc[ib][jb][q] = __uint_as_float(uL);
+                }
+                const uint32_t cu = min32(cU), cl = min32(cL);
+                if ((lane & 31) == q) {
+                    ownU = cu;
+                    ownL = cl;
+                }
+            }
+            // lane q (< 16) of each half owns column (jb, q) of its half
+            if ((lane & 31) < 16) {
+                const int qo = lane & 15;
+                const int jl = CW * wj + 32 * jb + 8 * (qo >> 2) + 4 * (lane >> 5) + (qo & 3);
+                if (ownU < INF_BITS) atomicMin(&PS.cminU[jl], ownU);
+                if (ownL < INF_BITS) atomicMin(&PS.cminL[jl], ownL);
+            }
+        }
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib) {
+            const int il = RW * wi + 32 * ib + (lane & 31);
+            const uint32_t mmu = min_halves(mu[ib]), mml = min_halves(ml[ib]);
+            if ((lane >> 5) == 0 && mmu < INF_BITS) atomicMin(&PS.rminU[il], mmu);
+            if ((lane >> 5) == 0 && mml < INF_BITS) atomicMin(&PS.rminL[il], mml);
+        }
+    }
     if (tid < PH / 32) {
         S.chot[tid] = 0u;
         S.clst[tid] = 0u;
@@ -553,10 +668,29 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         uint32_t *const bp = FINAL ? reinterpret_cast<uint32_t *>(A.bestc) + (is_row ? compJ : compI) * A.bestc_stride +
                                          (is_row ? I0 + t : J0 + t)
                                    : reinterpret_cast<uint32_t *>(A.best) + p;
-        const uint32_t old = p < A.n ? *reinterpret_cast<const volatile uint32_t *>(bp) : INF_BITS;
+        const uint32_t old = pre_old[e];
         if (p < A.n && m < old) atomicMin(bp, m);
         const float cur = p < A.n ? __uint_as_float(min(old, m)) : SCR_INF;
         const float E = is_row ? S.rE[t] : S.cE[t];
+        if constexpr (PB) {
+            // the running upper bound ub; the row is hot when its least lower
+            // bound can reach kappa ub; the threshold base becomes ub
+            const uint32_t mU = is_row ? PS.rminU[t] : PS.cminU[t];
+            const uint32_t mL = is_row ? PS.rminL[t] : PS.cminL[t];
+            uint32_t *const up = reinterpret_cast<uint32_t *>(A.ub) + p;
+            const uint32_t oldu = pre_oldu[e];
+            if (p < A.n && mU < oldu) atomicMin(up, mU);
+            const float curu = p < A.n ? __uint_as_float(min(oldu, mU)) : SCR_INF;
+            const bool hotu = p < A.n && __uint_as_float(mL) <= curu * A.kappa;
+            if (is_row) {
+                S.rmin[t] = __float_as_uint(curu);
+                S.rhot[t] = hotu ? 1 : 0;
+            } else {
+                S.cmin[t] = __float_as_uint(curu);
+                if (hotu) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
+            }
+            continue;
+        }
         if constexpr (FINAL) {
             tmin[e] = m;
             if (cur < SCR_INF) atomicMin(&S.umin, __float_as_uint((cur + E) * A.up));
@@ -567,7 +701,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             continue;
         }
         const bool hot = p < A.n && __uint_as_float(m) <= (cur + 2.0f * E) * A.kappa;
-        const bool lst = LIST && p < A.n && __uint_as_float(m) <= A.ltau[p];
+        const bool lst = LIST && p < A.n && __uint_as_float(m) <= pre_tau[e];
         if (is_row) {
             S.rmin[t] = __float_as_uint(cur);
             S.rhot[t] = (hot ? 1 : 0) | (lst ? 2 : 0);
@@ -622,7 +756,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     float *const cv = reinterpret_cast<float *>(co + CAP_STAGE);
     float *const ct = cv + CAP_STAGE;
     auto commit = [&](int64_t p, int64_t o, float v, float thr) {
-        const float L = lower_of(v, pair_bound(A.bound, A.rn[p], A.rn[o], A.re[p], A.re[o]));
+        const float L = PB ? v : lower_of(v, pair_bound(A.bound, A.rn[p], A.rn[o], A.re[p], A.re[o]));
         if (!(L <= thr)) return;
         const int pos = atomicAdd(&A.ccnt[p], 1);
         if (pos < CAP) {
@@ -650,8 +784,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const float rb_ = __uint_as_float(S.rmin[il]);
         // (final round: also within reach of the pair's bound U; an element
         // above the cheap bound has L > U: the 2^-18 covers lower_of's slack and the roundings)
-        const float r_cheap = fminf((rb_ + 2.0f * Ei) * A.kappa, (upair + 2.0f * Ei) * (1.0f + 0x1p-18f));
-        const float r_thr = fminf((rb_ + Ei) * A.kappa, upair);
+        // (pair bounds: the staged values are lower bounds, rb_ is ub)
+        const float r_cheap = PB ? rb_ * A.kappa : fminf((rb_ + 2.0f * Ei) * A.kappa, (upair + 2.0f * Ei) * (1.0f + 0x1p-18f));
+        const float r_thr = PB ? rb_ * A.kappa : fminf((rb_ + Ei) * A.kappa, upair);
 #pragma unroll
         for (int jb = 0; jb < NJB; ++jb)
 #pragma unroll 1
@@ -675,8 +810,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const int64_t j = S.cid[jl];
             const float Ej = S.cE[jl];
             const float cb = __uint_as_float(S.cmin[jl]);
-            const float c_cheap = fminf((cb + 2.0f * Ej) * A.kappa, (upair + 2.0f * Ej) * (1.0f + 0x1p-18f));
-            const float c_thr = fminf((cb + Ej) * A.kappa, upair);
+            const float c_cheap = PB ? cb * A.kappa : fminf((cb + 2.0f * Ej) * A.kappa, (upair + 2.0f * Ej) * (1.0f + 0x1p-18f));
+            const float c_thr = PB ? cb * A.kappa : fminf((cb + Ej) * A.kappa, upair);
 #pragma unroll
             for (int ib = 0; ib < NIB; ++ib) {
                 const float v = acc[ib][jb][q];
@@ -782,14 +917,19 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t
     ISO_REQUIRE(A.perm != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without a tile order");
     const dim3 block(64 * NW);
     auto grid = [](int64_t per_xcd) { return dim3((unsigned)(8 * per_xcd)); };
-    const bool list = A.lcnt != nullptr, final_round = A.bestc != nullptr;
+    const bool list = A.lcnt != nullptr, final_round = A.bestc != nullptr, pb = A.ub != nullptr;
     ISO_REQUIRE(!(final_round && (list || ndiag > 0)), ISO_ERR_INTERNAL, "final round with lists or diagonal pairs");
+    ISO_REQUIRE(!pb || (REP == ISO_PREC_BF16 && !list && !final_round), ISO_ERR_INTERNAL,
+                "pair bounds only in plain BF16 rounds");
     // diagonal tile pairs (only i < j counted), two halves each ...
     if (ndiag > 0) {
         const int64_t items = 2 * ndiag, per_xcd = (items + 7) / 8;
         if (list)
             hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
                                items);
+        else if (pb)
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_PLAIN, REP == ISO_PREC_BF16>), grid(per_xcd), block, 0,
+                               s, A, pairs, per_xcd, items);
         else
             hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
                                items);
@@ -804,6 +944,9 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t
         else if (list)
             hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
                                per_xcd, items);
+        else if (pb)
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_PLAIN, REP == ISO_PREC_BF16>), grid(per_xcd), block, 0,
+                               s, A, pairs + ndiag, per_xcd, items);
         else
             hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
                                per_xcd, items);

@@ -77,14 +77,14 @@ def test_mst_argument_validation():
 
 
 def test_mst_flags_validation():
-    """iso_mst's flags argument takes exactly the ISO_MST_NO_* bits; unknown
+    """iso_mst's flags argument takes exactly the ISO_MST_* bits; unknown
     bits are rejected before any device work."""
     lib = _lib.load()
     dummy = _p(0x1000)
-    for bad in (0x8, 0x10, 0x100, 0x80000000):
+    for bad in (0x10, 0x20, 0x100, 0x80000000):
         assert lib.iso_mst(dummy, 10, 4, 4, 0, 0, bad, dummy, dummy, None, None, 0, None) == -1
         assert b"flag" in lib.iso_last_error()
-    assert _lib.MST_NO_LISTS | _lib.MST_NO_FINAL | _lib.MST_NO_ESCALATE == 0x7
+    assert _lib.MST_NO_LISTS | _lib.MST_NO_FINAL | _lib.MST_NO_ESCALATE | _lib.MST_PAIR_BOUNDS == 0xF
 
 
 def test_subpartition_argument_validation():
@@ -153,6 +153,7 @@ def test_header_constants_match_binding():
     assert defs["ISO_MST_NO_LISTS"] == _lib.MST_NO_LISTS
     assert defs["ISO_MST_NO_FINAL"] == _lib.MST_NO_FINAL
     assert defs["ISO_MST_NO_ESCALATE"] == _lib.MST_NO_ESCALATE
+    assert defs["ISO_MST_PAIR_BOUNDS"] == _lib.MST_PAIR_BOUNDS
     assert defs["ISO_OMEGA_FULL"] == _lib.OMEGA["full"]
     for code, name in _lib.ERRORS.items():
         if name in defs:

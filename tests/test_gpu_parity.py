@@ -88,6 +88,48 @@ def test_mst_fp64_recheck_identical(iso, orc, name, precision, rounds):
     assert abs(info["mst_weight"] - W) <= 1e-12 * max(W, 1e-300)
 
 
+@pytest.mark.parametrize("recheck", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_mst_pair_bounds(iso, orc, name, recheck):
+    """BF16 screen with each pair's own error bound in every capture threshold
+    (forced; every round screened, no escalation): the oracle's tree with the
+    FP64 recheck, the oracle's tree up to certified near ties with FP32."""
+    X, op, ol = _oracle_tree(orc, name)
+    H.log("case %s n=%d d=%d bf16 pair-bound screen + %s recheck" % (name, *X.shape, recheck))
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision="bf16", recheck=recheck, escalate=False,
+                                   pair_bounds=True)
+    H.log("  info %s" % info)
+    assert info["pair_bounds"] and info["screen_precision"] == "bf16"
+    assert info["list_rounds"] == 0 and info["final_components"] == 0
+    gp = parent.cpu().numpy()
+    if recheck == "fp64":
+        np.testing.assert_array_equal(gp, op)
+        np.testing.assert_allclose(length.cpu().numpy(), ol, rtol=1e-15, atol=0)
+    else:
+        swaps = H.check_tree_vs_oracle(X, gp, op, H.screen_tol(X.shape[1]))
+        if swaps == 0:
+            np.testing.assert_array_equal(gp, op)
+        W = ol.sum()
+        assert abs(info["mst_weight"] - W) <= 1e-6 * max(W, 1e-300)
+
+
+def test_pair_bounds_chosen_for_heavy_tailed_norms(iso, orc):
+    """Lognormal sparse rows (the communities recipe) have heavy-tailed norms:
+    a BF16 request switches to pair bounds by itself and keeps the BF16 screen
+    (no hand-over to FP32), with the oracle's tree; grid-valued image-like
+    rows (light tails) keep the separable bound."""
+    X, op, ol = _oracle_tree(orc, "c4-n1000-d4096")
+    parent, length, info = iso.mst(torch.from_numpy(X).cuda(), precision="bf16", recheck="fp64")
+    H.log("  c4 info %s" % info)
+    assert info["pair_bounds"] and info["screen_precision"] == "bf16" and info["rescanned_rows"] == 0
+    np.testing.assert_array_equal(parent.cpu().numpy(), op)
+    X3, op3, _ = _oracle_tree(orc, "c3-n1500-d784")
+    parent, _, info = iso.mst(torch.from_numpy(X3).cuda(), precision="bf16", recheck="fp64")
+    H.log("  c3 info %s" % info)
+    assert not info["pair_bounds"] and info["screen_precision"] == "bf16"
+    np.testing.assert_array_equal(parent.cpu().numpy(), op3)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_mst_fp32_recheck_near_ties_only(iso, orc, name, precision):
