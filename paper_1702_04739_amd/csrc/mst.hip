@@ -1112,14 +1112,21 @@ __global__ void k_tile_ranges(const int32_t *__restrict__ perm, const int32_t *_
 }
 
 // A tile pair is skipped when all of its points lie in one component (no pair
-// of it can be an outgoing edge).
+// of it can be an outgoing edge); a kept pair is screened with the component
+// mask (keep_m) when it is diagonal or its tiles share a component, else
+// without it (keep_u).  The order is sorted by component and pr.x <= pr.y, so
+// the tiles share a component exactly when the greatest of the first reaches
+// the least of the second.
 __global__ void k_pair_keep(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ tlo,
-                            const int32_t *__restrict__ thi, int32_t *__restrict__ keep) {
+                            const int32_t *__restrict__ thi, int32_t *__restrict__ keep_m,
+                            int32_t *__restrict__ keep_u) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= npairs) return;
     const int2 pr = pairs[k];
     const bool one = tlo[pr.x] == thi[pr.x] && tlo[pr.y] == thi[pr.y] && tlo[pr.x] == tlo[pr.y];
-    keep[k] = one ? 0 : 1;
+    const bool masked = pr.x == pr.y || thi[pr.x] >= tlo[pr.y];
+    keep_m[k] = !one && masked ? 1 : 0;
+    keep_u[k] = !one && !masked ? 1 : 0;
 }
 
 // Rows of the representation in the tile order, stored tile by tile and,
@@ -1159,11 +1166,15 @@ __global__ __launch_bounds__(256) void k_permute_rows_frag(const uint4 *__restri
     }
 }
 
-__global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ keep,
-                               const int32_t *__restrict__ pos, int2 *__restrict__ out) {
+// Stable partition of the kept pairs: the masked ones first (positions pos_m),
+// then the others (pos_u after the masked total pos_m[npairs]).
+__global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ keep_m,
+                               const int32_t *__restrict__ pos_m, const int32_t *__restrict__ keep_u,
+                               const int32_t *__restrict__ pos_u, int2 *__restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= npairs || !keep[k]) return;
-    out[pos[k]] = pairs[k];
+    if (k >= npairs) return;
+    if (keep_m[k]) out[pos_m[k]] = pairs[k];
+    if (keep_u[k]) out[pos_m[npairs] + pos_u[k]] = pairs[k];
 }
 
 // ------------------------------------------------------------------ plan
@@ -1184,7 +1195,7 @@ struct MstPlan {
     float *pmin, *pmax, *cmin, *cmax;
     int2 *pairs, *pairs_r;          // all tile pairs (diagonal first); the pairs kept this round
     int64_t npairs, nt;
-    int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos, *scan_scratch;  // pvals: the final round's sorted ids
+    int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos, *keepu, *kposu, *scan_scratch;  // pvals: the final round's sorted ids
     uint32_t *pkeys, *ptk, *ptv;
     void *psort;
     double *psum;
@@ -1272,6 +1283,8 @@ struct MstPlan {
         thi = a.take<int32_t>(nt);
         keep = a.take<int32_t>(npairs);
         kpos = a.take<int32_t>(npairs + 1);
+        keepu = a.take<int32_t>(npairs);
+        kposu = a.take<int32_t>(npairs + 1);
         scan_scratch = a.take<int32_t>(scan_scratch_bytes(std::max<int64_t>(npairs, n + 1)) / sizeof(int32_t));
         ltau = a.take<float>(n);
         lscnt = a.take<int32_t>(n);
@@ -1494,8 +1507,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     hipLaunchKernelGGL(k_perm_identity, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad);
     LAUNCH_CHECK();
     // The tile-pair screen reads its own copy of the representation (Xq), in
-    // the tile order and chunk-major within each tile; xq_plain: Xq holds the
-    // rows in the order P.perm (the final round overwrites it with its own).
+    // the tile order and chunk-major within each tile (the final round
+    // overwrites it with its own order; every later plain round copies it again).
     const int64_t row_u4 = (int64_t)(P.d_pad * rep_bytes(rep) / 16);
     auto tile_copy = [&](const int32_t *order, int64_t npos) {
         const int64_t nchunks = row_u4 / 4;
@@ -1507,7 +1520,6 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         LAUNCH_CHECK();
     };
     tile_copy(P.perm, P.n_pad);
-    bool xq_plain = true;
     SA.perm = P.perm;
     SA.Xtile = P.Xq;
 
@@ -1565,7 +1577,6 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                            P.fr_sstart, P.permF, P.posF);
         LAUNCH_CHECK();
         tile_copy(P.permF, ntF * GT);
-        xq_plain = false;
         ScreenArgs FA = SA;
         FA.perm = P.permF;
         FA.Xtile = P.Xq;
@@ -1712,41 +1723,42 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             }
         }
         if (!list_round) {
-            // Tile order and tile pairs of this round: once components average at
-            // least a tile, the points are ordered by component and tile pairs
-            // lying inside one component are dropped (until then every tile pair
-            // holds points of several components, and the order stays the identity).
+            // Tile order and tile pairs of this round.  The screen masks pairs
+            // of one component only in its first nmask tile pairs: in the first
+            // round (identity order, every point its own component) those are
+            // the diagonal pairs; from the second round on the points are
+            // ordered by component, tile pairs lying inside one component are
+            // dropped, and the diagonal pairs and those whose tiles share a
+            // component go first.
             const int2 *pairs_use = P.pairs;
-            int64_t ndiag = P.nt, noff = P.npairs - P.nt;
-            if (rounds > 1 && ncomp * pair_tile() <= n) {
+            int64_t nmask = P.nt, noff = P.npairs - P.nt;
+            if (rounds > 1) {
                 int kb = 1;
                 while ((int64_t(1) << kb) < ncomp) ++kb;
                 hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.pkeys, P.perm);
                 LAUNCH_CHECK();
                 radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, kb, P.psort, s);
                 tile_copy(P.perm, P.n_pad);
-                xq_plain = true;
                 hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(P.nt, 256)), dim3(256), 0, s, P.perm, P.comp, n, P.nt,
                                    pair_tile(), P.tlo, P.thi);
                 LAUNCH_CHECK();
                 hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.tlo,
-                                   P.thi, P.keep);
+                                   P.thi, P.keep, P.keepu);
                 LAUNCH_CHECK();
                 exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, P.scan_scratch, s);
+                exclusive_scan_i32(P.keepu, P.kposu, P.npairs, P.kposu + P.npairs, P.scan_scratch, s);
                 hipLaunchKernelGGL(k_pair_scatter, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs,
-                                   P.keep, P.kpos, P.pairs_r);
+                                   P.keep, P.kpos, P.keepu, P.kposu, P.pairs_r);
                 LAUNCH_CHECK();
                 int32_t hk[2] = {0, 0};
-                HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.nt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipMemcpyAsync(&hk[1], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipMemcpyAsync(&hk[1], P.kposu + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
                 HIP_CHECK(hipStreamSynchronize(s));
-                ISO_REQUIRE(hk[0] >= 0 && hk[0] <= hk[1] && hk[1] <= P.npairs, ISO_ERR_INTERNAL, "tile-pair compaction");
+                ISO_REQUIRE(hk[0] >= 0 && hk[1] >= 0 && hk[0] + hk[1] <= P.npairs, ISO_ERR_INTERNAL,
+                            "tile-pair compaction");
                 pairs_use = P.pairs_r;
-                ndiag = hk[0];
-                noff = hk[1] - hk[0];
-            } else if (!xq_plain) {
-                tile_copy(P.perm, P.n_pad);  // after a final round that fell back
-                xq_plain = true;
+                nmask = hk[0];
+                noff = hk[1];
             }
             if (lists == LISTS_NONE && rounds == 2) {
                 // the second round's screen builds the lists from the first
@@ -1767,7 +1779,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             SA.rows = nullptr;
             SA.nrows = 0;
             scr.start(s);
-            launch_screen_pairs(SA, pairs_use, ndiag, noff, s);
+            launch_screen_pairs(SA, pairs_use, nmask, noff, s);
             scr.stop(s);
             if (lists == LISTS_BUILDING) {
                 SA.lcnt = nullptr;

@@ -321,8 +321,10 @@ void launch_screen_rows(const ScreenArgs &A, bool gather, hipStream_t s);
 // ccnt[] zero on entry; both are updated with atomics, indexed by point id.
 int64_t pair_tile();
 std::vector<int2> make_pair_order(int64_t ntiles);
-// pairs: ndiag diagonal tile pairs, then noff others (positions in the tile
-// order A.perm).
-void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t noff, hipStream_t s);
+// pairs: nmask tile pairs screened with the component mask (every diagonal
+// pair, and any pair whose tiles may share a component), then noff pairs whose
+// two tiles share no component, which are screened without it (positions in
+// the tile order A.perm).
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t nmask, int64_t noff, hipStream_t s);
 
 }  // namespace iso

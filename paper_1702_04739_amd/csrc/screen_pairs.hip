@@ -33,10 +33,12 @@
 // reads eight consecutive whole cache lines.
 //
 // Tiles are runs of 256 positions of a tile order (A.perm maps positions to
-// points); once components are large the order groups points by component
-// and the caller drops tile pairs inside one component.  Work items (tile
-// pair, half) are enumerated with the diagonal pairs in a launch of their own
-// and the others in blocks of PAIR_SB x PAIR_SB tiles;
+// points); after the first round the order groups points by component and the
+// caller drops tile pairs inside one component.  Work items (tile pair, half)
+// are enumerated with the pairs that need the component mask (the diagonal
+// pairs, and pairs whose tiles share a component) in a launch of their own,
+// and the others, whose epilogue has no mask, in blocks of PAIR_SB x PAIR_SB
+// tiles;
 // each XCD receives a contiguous run of that order (workgroup ids are dealt
 // to the eight XCDs in turn), so the workgroups resident on one XCD share
 // their I and J tiles in its L2.
@@ -159,6 +161,56 @@ __device__ __forceinline__ uint32_t min_halves(uint32_t v) {
     return min(v, min((uint32_t)r[0], (uint32_t)r[1]));
 }
 
+// The same for signed values.
+__device__ __forceinline__ int32_t min_halves_i32(int32_t v) {
+    const auto r = __builtin_amdgcn_permlane32_swap((uint32_t)v, (uint32_t)v, false, false);
+    return min(v, min((int32_t)r[0], (int32_t)r[1]));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32(int32_t v) {
+    return __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, CTRL, 0xF, 0xF, false);
+}
+
+// Column minima of a 32 x 16 block held one row per lane (lane l mod 32 of
+// each half wave holds row l mod 32 of its half's sixteen columns c[0..15]):
+// a reduce-scatter over the five lane bits of the half.  Each step pairs every
+// lane with a partner that differs in one more bit and keeps half of the
+// columns (the lower half where that bit is 0): bit 4 by swapping the rows of
+// 16 lanes between the registers of columns q and q + 8, bit 3 by a rotation
+// of 16-lane rows by 8, bit 2 by the mirror of 8-lane half rows (lane l with
+// l xor 7), bits 1 and 0 by quad permutations.  Lanes 2 m and 2 m + 1 of each
+// half end with the minimum of column m over all 32 rows.  38 instructions for
+// 16 columns, against 16 separate 32-lane reductions.
+__device__ __forceinline__ int32_t col_min16(const int32_t (&c)[16], int lane) {
+    int32_t d[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        // rows 1 and 3 of column q trade places with rows 0 and 2 of column q + 8
+        const auto r = __builtin_amdgcn_permlane16_swap((uint32_t)c[q], (uint32_t)c[q + 8], false, false);
+        d[q] = min((int32_t)r[0], (int32_t)r[1]);  // column q + 8 (l >> 4 & 1)
+    }
+    const bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1, b1 = (lane >> 1) & 1;
+    int32_t e[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t lo = min(d[q], dpp_i32<0x128>(d[q]));          // row_ror:8 = lane xor 8
+        const int32_t hi = min(d[q + 4], dpp_i32<0x128>(d[q + 4]));
+        e[q] = b3 ? hi : lo;
+    }
+    int32_t f[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int32_t lo = min(e[q], dpp_i32<0x141>(e[q]));          // half-row mirror = lane xor 7
+        const int32_t hi = min(e[q + 2], dpp_i32<0x141>(e[q + 2]));
+        f[q] = b2 ? hi : lo;
+    }
+    const int32_t lo = min(f[0], dpp_i32<0x4E>(f[0]));                // quad lane xor 2
+    const int32_t hi = min(f[1], dpp_i32<0x4E>(f[1]));
+    const int32_t g = b1 ? hi : lo;
+    return min(g, dpp_i32<0xB1>(g));                                  // quad lane xor 1
+}
+
 // Appends (other, v) to point p's neighbour list, or lowers its smallest
 // dropped value once the list is full.
 __device__ __forceinline__ void list_push_global(const ScreenArgs &A, int64_t p, int32_t other, float v) {
@@ -188,11 +240,11 @@ struct PWave {
     static constexpr int STAGE_U4 = (RR ? PH : SROWS) * 4;  // uint4 slots of one LDS stage
 };
 
-template <int REP, bool DIAG, int MODE, bool PB = false>
+template <int REP, bool MASKED, int MODE, bool PB = false>
 __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const int2 *__restrict__ pairs,
                                                             int64_t per_xcd, int64_t nitems) {
     constexpr bool LIST = MODE == MODE_LIST, FINAL = MODE == MODE_FINAL;
-    static_assert(!(FINAL && DIAG), "the final round has no diagonal tile pairs");
+    static_assert(!(FINAL && MASKED), "the final round pairs tiles of different components only");
     static_assert(!PB || (MODE == MODE_PLAIN && REP == ISO_PREC_BF16), "pair bounds: BF16 plain rounds only");
     using P = PPrec<REP>;
     using T = typename P::T;
@@ -235,6 +287,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     const int32_t *__restrict__ perm = A.perm;
     // final round: rows' minima go to the column tile's component and back
     const int32_t compI = FINAL ? A.tcomp[pr.x] : 0, compJ = FINAL ? A.tcomp[pr.y] : 0;
+    // the diagonal tile pairs form each pair of points once (i < j)
+    const bool diag = MASKED && pr.x == pr.y;
 
     // asynchronous staging: each wave moves RUNS 1 KB runs of slots per chunk
     // with global_load_lds_dwordx4 (lane L of a run fills slot base + L); a run
@@ -525,12 +579,67 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         if constexpr (PB) pre_oldu[e] = reinterpret_cast<const volatile uint32_t *>(A.ub)[p];
     }
 
-    // ---- epilogue 1: masked Dhat^2 as bit patterns (padding has s = +inf; a
-    // negative rounding result becomes +0), tile minima of rows (in-lane over
-    // the lane's 32 columns, then lanes l, l+32) and of columns (in-lane over the
-    // lane's 4 rows, then the 32 lanes of the half wave; lane 16 jb + q of each
-    // half keeps column (jb, q) and merges it into LDS once at the end)
-    {
+    // ---- epilogue 1, items whose tiles share no component (the caller's
+    // guarantee for the unmasked launch; BF16, FP8 and FP32 without pair
+    // bounds): no mask.  Dhat^2 as signed 32-bit patterns (a negative rounding
+    // result, sign bit set, orders below every nonnegative value; the reduced
+    // minima are clamped at +0, and the accumulators keep the raw value, which
+    // the staging below clamps; padding has s = +inf), tile minima of rows
+    // (in-lane over the lane's columns, then lanes l, l+32) and of columns
+    // (in-lane over the lane's rows, then a reduce-scatter over the half wave:
+    // lanes 2 m, 2 m + 1 hold column m of a 32-column block; lane parity picks
+    // which of two blocks a lane merges into LDS)
+    constexpr bool UNMASKED = !MASKED && !PB && REP != ISO_PREC_INT8;
+    if constexpr (UNMASKED) {
+        {
+            int32_t m[NIB];
+#pragma unroll
+            for (int ib = 0; ib < NIB; ++ib) m[ib] = (int32_t)INF_BITS;
+            int32_t own[(NJB + 1) / 2];
+#pragma unroll
+            for (int jb = 0; jb < NJB; ++jb) {
+                int32_t c[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    const float sj = S.csq[jl];
+                    int32_t cq = (int32_t)INF_BITS;
+#pragma unroll
+                    for (int ib = 0; ib < NIB; ++ib) {
+                        const int32_t v = __float_as_int(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj));
+                        acc[ib][jb][q] = __int_as_float(v);
+                        m[ib] = min(m[ib], v);
+                        cq = min(cq, v);
+                    }
+                    c[q] = cq;
+                }
+                const int32_t cm = col_min16(c, lane);
+                if (jb & 1)
+                    own[jb >> 1] = (lane & 1) ? cm : own[jb >> 1];
+                else
+                    own[jb >> 1] = cm;
+            }
+#pragma unroll
+            for (int o = 0; o < (NJB + 1) / 2; ++o) {
+                const int jo = 2 * o + (lane & 1), qo = (lane & 31) >> 1;
+                const int jl = CW * wj + 32 * jo + 8 * (qo >> 2) + 4 * (lane >> 5) + (qo & 3);
+                const uint32_t v = (uint32_t)max(own[o], 0);
+                if (jo < NJB && v < INF_BITS) atomicMin(&S.cmin[jl], v);
+            }
+#pragma unroll
+            for (int ib = 0; ib < NIB; ++ib) {
+                const uint32_t mm = (uint32_t)max(min_halves_i32(m[ib]), 0);  // lanes l and l+32 hold the same rows
+                if ((lane >> 5) == 0 && mm < INF_BITS) atomicMin(&S.rmin[RW * wi + 32 * ib + (lane & 31)], mm);
+            }
+        }
+    }
+    // ---- epilogue 1, the other items: masked Dhat^2 as bit patterns (padding has
+    // s = +inf; a negative rounding result becomes +0), tile minima of rows
+    // (in-lane over the lane's 32 columns, then lanes l, l+32) and of columns
+    // (in-lane over the lane's 4 rows, then the 32 lanes of the half wave; lane
+    // 16 jb + q of each half keeps column (jb, q) and merges it into LDS once at
+    // the end)
+    if constexpr (!UNMASKED) {
         uint32_t m[NIB];
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib) m[ib] = INF_BITS;
@@ -557,7 +666,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                         tb = __float_as_int(fmaf(-2.0f, acc[ib][jb][q], si[ib] + sj));
                     }
                     uint32_t v = (cjj == ci[ib]) ? INF_BITS : (uint32_t)max(tb, 0);
-                    if (DIAG && half * PH + jl <= RW * wi + 32 * ib + (lane & 31)) v = INF_BITS;  // each pair once
+                    if (diag && half * PH + jl <= RW * wi + 32 * ib + (lane & 31)) v = INF_BITS;  // each pair once
                     acc[ib][jb][q] = __uint_as_float(v);
                     m[ib] = min(m[ib], v);
                     cmin = min(cmin, v);
@@ -765,6 +874,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         }
     };
     auto stage_cap = [&](int64_t p, int64_t o, float v, float thr) {
+        v = __int_as_float(max(__float_as_int(v), 0));  // an unmasked item's negative value becomes +0
         const int pos = atomicAdd(&S.ncap, 1);
         if (pos < CAP_STAGE) {
             cp[pos] = (int32_t)p;
@@ -829,6 +939,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         int32_t *lo = lp + LIST_STAGE;
         float *lvv = reinterpret_cast<float *>(lo + LIST_STAGE);
         auto stage = [&](int64_t p, int32_t other, float v) {
+            v = __int_as_float(max(__float_as_int(v), 0));
             const int pos = atomicAdd(&S.nlist, 1);
             if (pos < LIST_STAGE) {
                 lp[pos] = (int32_t)p;
@@ -912,18 +1023,18 @@ std::vector<int2> make_pair_order(int64_t nt) {
 namespace {
 
 template <int REP>
-void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t noff, hipStream_t s) {
+void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t nmask, int64_t noff, hipStream_t s) {
     ISO_REQUIRE(A.d_pad % PPrec<REP>::KC == 0, ISO_ERR_INTERNAL, "padded dimension is not a whole number of chunks");
     ISO_REQUIRE(A.perm != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without a tile order");
     const dim3 block(64 * NW);
     auto grid = [](int64_t per_xcd) { return dim3((unsigned)(8 * per_xcd)); };
     const bool list = A.lcnt != nullptr, final_round = A.bestc != nullptr, pb = A.ub != nullptr;
-    ISO_REQUIRE(!(final_round && (list || ndiag > 0)), ISO_ERR_INTERNAL, "final round with lists or diagonal pairs");
+    ISO_REQUIRE(!(final_round && (list || nmask > 0)), ISO_ERR_INTERNAL, "final round with lists or masked pairs");
     ISO_REQUIRE(!pb || (REP == ISO_PREC_BF16 && !list && !final_round), ISO_ERR_INTERNAL,
                 "pair bounds only in plain BF16 rounds");
-    // diagonal tile pairs (only i < j counted), two halves each ...
-    if (ndiag > 0) {
-        const int64_t items = 2 * ndiag, per_xcd = (items + 7) / 8;
+    // masked tile pairs (on the diagonal only i < j counted), two halves each ...
+    if (nmask > 0) {
+        const int64_t items = 2 * nmask, per_xcd = (items + 7) / 8;
         if (list)
             hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
                                items);
@@ -939,16 +1050,16 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t
     if (noff > 0) {
         const int64_t items = 2 * noff, per_xcd = (items + 7) / 8;
         if (final_round)
-            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_FINAL>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_FINAL>), grid(per_xcd), block, 0, s, A, pairs + nmask,
                                per_xcd, items);
         else if (list)
-            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs + nmask,
                                per_xcd, items);
         else if (pb)
             hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_PLAIN, REP == ISO_PREC_BF16>), grid(per_xcd), block, 0,
-                               s, A, pairs + ndiag, per_xcd, items);
+                               s, A, pairs + nmask, per_xcd, items);
         else
-            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs + ndiag,
+            hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs + nmask,
                                per_xcd, items);
         LAUNCH_CHECK();
     }
@@ -956,15 +1067,15 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t
 
 }  // namespace
 
-void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t ndiag, int64_t noff, hipStream_t s) {
+void launch_screen_pairs(const ScreenArgs &A, const int2 *pairs, int64_t nmask, int64_t noff, hipStream_t s) {
     if (A.rep == ISO_PREC_BF16)
-        launch_pairs<ISO_PREC_BF16>(A, pairs, ndiag, noff, s);
+        launch_pairs<ISO_PREC_BF16>(A, pairs, nmask, noff, s);
     else if (A.rep == ISO_PREC_FP8)
-        launch_pairs<ISO_PREC_FP8>(A, pairs, ndiag, noff, s);
+        launch_pairs<ISO_PREC_FP8>(A, pairs, nmask, noff, s);
     else if (A.rep == ISO_PREC_INT8)
-        launch_pairs<ISO_PREC_INT8>(A, pairs, ndiag, noff, s);
+        launch_pairs<ISO_PREC_INT8>(A, pairs, nmask, noff, s);
     else
-        launch_pairs<ISO_PREC_FP32>(A, pairs, ndiag, noff, s);
+        launch_pairs<ISO_PREC_FP32>(A, pairs, nmask, noff, s);
 }
 
 }  // namespace iso
