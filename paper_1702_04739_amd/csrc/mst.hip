@@ -1166,6 +1166,39 @@ __global__ __launch_bounds__(256) void k_permute_rows_frag(const uint4 *__restri
     }
 }
 
+// Per-position copies of the per-point values the tile-pair screen reads, in
+// the tile order `order` (npos positions; ids >= n are padding: Emax 0).
+// Optional inputs (nullptr) are skipped.
+__global__ void k_pos_gather(const int32_t *__restrict__ order, int64_t npos, int64_t n, const float *__restrict__ sq,
+                             const int32_t *__restrict__ comp, const float *__restrict__ Emax,
+                             const float *__restrict__ rn, const float *__restrict__ re, const int32_t *__restrict__ sqi,
+                             const float *__restrict__ ltau, float *__restrict__ psq, int32_t *__restrict__ pcomp,
+                             float *__restrict__ pEmax, float *__restrict__ prn, float *__restrict__ pre,
+                             int32_t *__restrict__ psqi, float *__restrict__ pltau) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= npos) return;
+    const int32_t id = order[pos];
+    const bool real = id < n;
+    psq[pos] = sq[id];
+    pcomp[pos] = comp[id];
+    pEmax[pos] = real ? Emax[id] : 0.0f;
+    if (rn) {
+        prn[pos] = rn[id];
+        pre[pos] = re[id];
+    }
+    if (sqi) psqi[pos] = sqi[id];
+    if (ltau) pltau[pos] = real ? ltau[id] : -1.0f;
+}
+
+// Folds running minima kept by position back into the per-point array.
+__global__ void k_pos_scatter(const int32_t *__restrict__ order, int64_t npos, int64_t n,
+                              const float *__restrict__ pv, float *__restrict__ v) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= npos) return;
+    const int32_t id = order[pos];
+    if (id < n) v[id] = pv[pos];
+}
+
 // Stable partition of the kept pairs: the masked ones first (positions pos_m),
 // then the others (pos_u after the masked total pos_m[npairs]).
 __global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ keep_m,
@@ -1196,6 +1229,8 @@ struct MstPlan {
     int2 *pairs, *pairs_r;          // all tile pairs (diagonal first); the pairs kept this round
     int64_t npairs, nt;
     int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos, *keepu, *kposu, *scan_scratch;  // pvals: the final round's sorted ids
+    float *psq, *pEmax, *prn, *pre, *pltau, *pbest, *pub;  // the tile-pair screen's per-position copies
+    int32_t *pcomp, *psqi;
     uint32_t *pkeys, *ptk, *ptv;
     void *psort;
     double *psum;
@@ -1285,6 +1320,18 @@ struct MstPlan {
         kpos = a.take<int32_t>(npairs + 1);
         keepu = a.take<int32_t>(npairs);
         kposu = a.take<int32_t>(npairs + 1);
+        {
+            const int64_t npos = std::max<int64_t>(n_pad, ntF_cap * GT);
+            psq = a.take<float>(npos);
+            pcomp = a.take<int32_t>(npos);
+            pEmax = a.take<float>(npos);
+            prn = a.take<float>(npos);
+            pre = a.take<float>(npos);
+            psqi = a.take<int32_t>(npos);
+            pltau = a.take<float>(npos);
+            pbest = a.take<float>(n_pad);
+            pub = a.take<float>(n_pad);
+        }
         scan_scratch = a.take<int32_t>(scan_scratch_bytes(std::max<int64_t>(npairs, n + 1)) / sizeof(int32_t));
         ltau = a.take<float>(n);
         lscnt = a.take<int32_t>(n);
@@ -1531,6 +1578,22 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         ((P.options & ISO_MST_NO_LISTS) || pb) ? LISTS_OFF : LISTS_NONE;
     bool final_off = (P.options & ISO_MST_NO_FINAL) != 0 || pb;
     SA.ub = ubp;
+    SA.psq = P.psq;
+    SA.pcomp = P.pcomp;
+    SA.pEmax = P.pEmax;
+    SA.prn = P.prn;
+    SA.pre = P.pre;
+    SA.psqi = P.psqi;
+    SA.pltau = P.pltau;
+    SA.pbest = P.pbest;
+    SA.pub = ubp ? P.pub : nullptr;
+    // the tile-pair screen's per-position copies for the tile order `order`
+    auto pos_gather = [&](const int32_t *order, int64_t npos, bool with_ltau) {
+        hipLaunchKernelGGL(k_pos_gather, dim3(grid_for(npos, 256)), dim3(256), 0, s, order, npos, n, P.sq, P.comp,
+                           P.Emax, ubp ? P.rn : nullptr, P.re, rep == ISO_PREC_INT8 ? P.sqi : nullptr,
+                           with_ltau ? P.ltau : nullptr, P.psq, P.pcomp, P.pEmax, P.prn, P.pre, P.psqi, P.pltau);
+        LAUNCH_CHECK();
+    };
 
     // The final round (at most FR_KC components left): true when it joined
     // them all, false when a point's candidate list overflowed (the round is
@@ -1577,6 +1640,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                            P.fr_sstart, P.permF, P.posF);
         LAUNCH_CHECK();
         tile_copy(P.permF, ntF * GT);
+        pos_gather(P.permF, ntF * GT, false);
         ScreenArgs FA = SA;
         FA.perm = P.permF;
         FA.Xtile = P.Xq;
@@ -1773,14 +1837,23 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 SA.lv = P.lv;
                 lists = LISTS_BUILDING;
             }
-            fill<uint32_t>(reinterpret_cast<uint32_t *>(P.best), 0x7F800000u, n, s);  // +inf
-            if (ubp) fill<uint32_t>(reinterpret_cast<uint32_t *>(ubp), 0x7F800000u, n, s);
+            pos_gather(P.perm, P.n_pad, SA.lcnt != nullptr);
+            fill<uint32_t>(reinterpret_cast<uint32_t *>(P.pbest), 0x7F800000u, P.n_pad, s);  // +inf
+            if (ubp) fill<uint32_t>(reinterpret_cast<uint32_t *>(P.pub), 0x7F800000u, P.n_pad, s);
             fill<int32_t>(P.ccnt, 0, n, s);
             SA.rows = nullptr;
             SA.nrows = 0;
             scr.start(s);
             launch_screen_pairs(SA, pairs_use, nmask, noff, s);
             scr.stop(s);
+            hipLaunchKernelGGL(k_pos_scatter, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, n, P.pbest,
+                               P.best);
+            LAUNCH_CHECK();
+            if (ubp) {
+                hipLaunchKernelGGL(k_pos_scatter, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, n,
+                                   P.pub, ubp);
+                LAUNCH_CHECK();
+            }
             if (lists == LISTS_BUILDING) {
                 SA.lcnt = nullptr;
                 lists = LISTS_READY;

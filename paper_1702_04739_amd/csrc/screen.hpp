@@ -68,6 +68,19 @@ struct ScreenArgs {
                              // (points sorted by component, padding last)
     const void *Xtile;       // tile-pair screen: the representation, rows in the tile order, stored tile by
                              // tile and chunk-major within a tile (the PT rows' bytes 64 c .. 64 c + 63 contiguous)
+    // tile-pair screen: per-position copies, in the tile order A.perm, of the
+    // per-point values it reads (gathered once per order, so that a work item's
+    // loads are coalesced and none waits for a point id): s, component, Emax
+    // (0 on padding), r and e (pair bounds), the exact integer squared norms
+    // (INT8) and the list thresholds (lists); and the running minima by
+    // position (plain and list rounds: +inf on entry, folded into best[] by the
+    // caller afterwards; the pair bounds' ub likewise)
+    const float *psq;
+    const int32_t *pcomp;
+    const float *pEmax, *prn, *pre;
+    const int32_t *psqi;
+    const float *pltau;
+    float *pbest, *pub;
     ScreenBound bound;       // error bound constants
     float kappa;             // capture threshold scale (recheck order slack and rounding)
     // gathered pass (rows == nullptr for the full sweep)

@@ -308,11 +308,10 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         soff[r] = (uint32_t)(trow * 64 + part * 16);
     }
     const int nchunks = (int)(d_pad / P::KC);
-    // Register rows (BF16): the first two chunks are requested before the tile
-    // constants, whose dependent loads then overlap them.  Both prologue issues
-    // are unconditional (with one chunk the second re-reads chunk 0 and is
-    // never used), so that the loop's first step sees the same loads in flight
-    // from either predecessor.
+    // Register rows (BF16): the first two chunks are requested right after the
+    // tile constants' DMA.  Both prologue issues are unconditional (with one chunk
+    // the second re-reads chunk 0 and is never used), so that the loop's first
+    // step sees the same loads in flight from either predecessor.
     static_assert(!RR || (NIB == 2 && NJB * 32 == PH && CRUNS == 2), "register-row layout");
     const char *colb = XJb + half * (PH * 64) + (int64_t)lane * 16;
     const char *rowb = XIb + (int64_t)(2 * w) * 2048 + (int64_t)lane * 16;
@@ -325,66 +324,57 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         _Pragma("unroll") for (int ib = 0; ib < 2; ++ib) _Pragma("unroll") for (int t = 0; t < 2; ++t) RG[ib][t] = \
             *reinterpret_cast<const uint4 *>(rowb + (int64_t)(C) * (PT * 64) + ib * 2048 + t * 1024);        \
     }
-    if constexpr (RR) {
-        ISO_RISSUE(stage0, rg0, 0)
-        ISO_RISSUE(stage1, rg1, nchunks > 1 ? 1 : 0)
-    }
 
-    // tile constants: the point ids first, then every load that depends on
-    // them, unconditionally (padding ids are clamped for Emax, which has n
-    // entries), so that each level costs one round trip
-    static_assert(64 * NW == PT, "one thread per row");
-    const int32_t pid_r = perm[I0 + tid];
-    const int32_t pid_c = perm[J0 + (tid & (PH - 1))];
-    int32_t pid_w[NIB];
-#pragma unroll
-    for (int ib = 0; ib < NIB; ++ib) pid_w[ib] = perm[I0 + RW * wi + 32 * ib + (lane & 31)];
-    const int64_t nlast = A.n - 1;
-    const float er = A.Emax[pid_r < A.n ? pid_r : nlast];
-    const float ec = A.Emax[pid_c < A.n ? pid_c : nlast];
-    const float sqc = A.sq[pid_c];
-    const int32_t cpc = A.comp[pid_c];
-    const int32_t sqic = REP == ISO_PREC_INT8 ? A.sqi[pid_c] : 0;
-    float si[NIB];
-    int ci[NIB];
-    int32_t sii[NIB];  // INT8: exact integer squared norms of the rows
-#pragma unroll
-    for (int ib = 0; ib < NIB; ++ib) {
-        si[ib] = A.sq[pid_w[ib]];
-        ci[ib] = A.comp[pid_w[ib]];
-        sii[ib] = REP == ISO_PREC_INT8 ? A.sqi[pid_w[ib]] : 0;
-    }
-    // pair bounds: norm and representation-error bounds of the rows and
-    // columns, kept in LDS until the epilogue (no registers held across the K loop)
-    const float rnr = PB ? A.rn[pid_r] : 0.0f, rer = PB ? A.re[pid_r] : 0.0f;
-    const float rnc = PB ? A.rn[pid_c] : 0.0f, rec = PB ? A.re[pid_c] : 0.0f;
-    S.rid[tid] = pid_r;
+    // Tile constants, from the per-position copies: the running tile minima
+    // start at +inf (written before any DMA is in flight, so no LDS write waits
+    // for one); the point ids, Emax, and the columns' s and components go to
+    // LDS by DMA (one dword per lane, ahead of the first chunks, so the first
+    // pipeline step's wait covers them); the rows' s and components, which stay
+    // in registers, are plain loads.
+    static_assert(64 * NW == PT && PH % 64 == 0, "one thread per row, whole waves per column set");
     S.rmin[tid] = INF_BITS;
-    S.rE[tid] = pid_r < A.n ? er : 0.0f;
-    {
-        // threads t and t + PH write the same column's values (no branch, so
-        // that the loads above are not sunk behind one)
-        const int tc = tid & (PH - 1);
-        S.cid[tc] = pid_c;
-        S.cmin[tc] = INF_BITS;
-        S.cE[tc] = pid_c < A.n ? ec : 0.0f;
-        S.csq[tc] = sqc;
-        if (REP == ISO_PREC_INT8) S.csqi[tc] = sqic;
-        S.ccomp[tc] = cpc;
-        if constexpr (PB) {
-            PS.crn[tc] = rnc;
-            PS.cre[tc] = rec;
-        }
-    }
+    if (tid < PH) S.cmin[tid] = INF_BITS;
     if constexpr (PB) {
-        PS.rrn[tid] = rnr;
-        PS.rre[tid] = rer;
         PS.rminU[tid] = INF_BITS;
         PS.rminL[tid] = INF_BITS;
         if (tid < PH) {
             PS.cminU[tid] = INF_BITS;
             PS.cminL[tid] = INF_BITS;
         }
+    }
+    auto dma4 = [&](const void *src, void *lds_wave_base) {
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_wave_base, 4, 0, 0);
+    };
+    dma4(perm + I0 + tid, &S.rid[64 * w]);
+    dma4(A.pEmax + I0 + tid, &S.rE[64 * w]);
+    if constexpr (PB) {
+        dma4(A.prn + I0 + tid, &PS.rrn[64 * w]);
+        dma4(A.pre + I0 + tid, &PS.rre[64 * w]);
+    }
+    if (w < PH / 64) {
+        dma4(perm + J0 + tid, &S.cid[64 * w]);
+        dma4(A.pEmax + J0 + tid, &S.cE[64 * w]);
+        dma4(A.psq + J0 + tid, &S.csq[64 * w]);
+        dma4(A.pcomp + J0 + tid, &S.ccomp[64 * w]);
+        if constexpr (REP == ISO_PREC_INT8) dma4(A.psqi + J0 + tid, &S.csqi[64 * w]);
+        if constexpr (PB) {
+            dma4(A.prn + J0 + tid, &PS.crn[64 * w]);
+            dma4(A.pre + J0 + tid, &PS.cre[64 * w]);
+        }
+    }
+    float si[NIB];
+    int ci[NIB];
+    int32_t sii[NIB];  // INT8: exact integer squared norms of the rows
+#pragma unroll
+    for (int ib = 0; ib < NIB; ++ib) {
+        const int64_t pos = I0 + RW * wi + 32 * ib + (lane & 31);
+        si[ib] = A.psq[pos];
+        ci[ib] = A.pcomp[pos];
+        sii[ib] = REP == ISO_PREC_INT8 ? A.psqi[pos] : 0;
+    }
+    if constexpr (RR) {
+        ISO_RISSUE(stage0, rg0, 0)
+        ISO_RISSUE(stage1, rg1, nchunks > 1 ? 1 : 0)
     }
 
 #define ISO_ISSUE(STG, C)                                                                                     \
@@ -571,12 +561,13 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const int t = is_row ? u : u - PT;
         const int64_t p = is_row ? S.rid[t] : S.cid[t];
         if (p >= A.n) continue;
+        const int64_t pos = is_row ? I0 + t : J0 + t;
         const uint32_t *const bp = FINAL ? reinterpret_cast<const uint32_t *>(A.bestc) +
-                                               (is_row ? compJ : compI) * A.bestc_stride + (is_row ? I0 + t : J0 + t)
-                                         : reinterpret_cast<const uint32_t *>(A.best) + p;
+                                               (is_row ? compJ : compI) * A.bestc_stride + pos
+                                         : reinterpret_cast<const uint32_t *>(A.pbest) + pos;
         pre_old[e] = *reinterpret_cast<const volatile uint32_t *>(bp);
-        if constexpr (LIST) pre_tau[e] = A.ltau[p];
-        if constexpr (PB) pre_oldu[e] = reinterpret_cast<const volatile uint32_t *>(A.ub)[p];
+        if constexpr (LIST) pre_tau[e] = A.pltau[pos];
+        if constexpr (PB) pre_oldu[e] = reinterpret_cast<const volatile uint32_t *>(A.pub)[pos];
     }
 
     // ---- epilogue 1, items whose tiles share no component (the caller's
@@ -774,9 +765,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const int t = is_row ? u : u - PT;
         const int64_t p = is_row ? S.rid[t] : S.cid[t];
         const uint32_t m = is_row ? S.rmin[t] : S.cmin[t];
-        uint32_t *const bp = FINAL ? reinterpret_cast<uint32_t *>(A.bestc) + (is_row ? compJ : compI) * A.bestc_stride +
-                                         (is_row ? I0 + t : J0 + t)
-                                   : reinterpret_cast<uint32_t *>(A.best) + p;
+        const int64_t pos = is_row ? I0 + t : J0 + t;
+        uint32_t *const bp = FINAL ? reinterpret_cast<uint32_t *>(A.bestc) + (is_row ? compJ : compI) * A.bestc_stride + pos
+                                   : reinterpret_cast<uint32_t *>(A.pbest) + pos;
         const uint32_t old = pre_old[e];
         if (p < A.n && m < old) atomicMin(bp, m);
         const float cur = p < A.n ? __uint_as_float(min(old, m)) : SCR_INF;
@@ -786,7 +777,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             // bound can reach kappa ub; the threshold base becomes ub
             const uint32_t mU = is_row ? PS.rminU[t] : PS.cminU[t];
             const uint32_t mL = is_row ? PS.rminL[t] : PS.cminL[t];
-            uint32_t *const up = reinterpret_cast<uint32_t *>(A.ub) + p;
+            uint32_t *const up = reinterpret_cast<uint32_t *>(A.pub) + pos;
             const uint32_t oldu = pre_oldu[e];
             if (p < A.n && mU < oldu) atomicMin(up, mU);
             const float curu = p < A.n ? __uint_as_float(min(oldu, mU)) : SCR_INF;
@@ -885,51 +876,70 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             commit(p, o, v, thr);
         }
     };
+    // The scans below visit few elements: a row's flagged elements are found
+    // by one compare per element, whose wave mask (any lane at or below its
+    // threshold) marks a column position; only marked positions are then
+    // read again (uniform position: indexed register read) and staged.  A
+    // flagged column is one register position of one half wave.
+    auto scan_row = [&](int ib, float thr, auto &&emit) {
+#pragma unroll
+        for (int jb = 0; jb < NJB; ++jb) {  // (jb static: only q indexes a register dynamically)
+            uint32_t any = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (__ballot(acc[ib][jb][q] <= thr)) any |= 1u << q;
+            while (any) {
+                const int q = __builtin_ctz(any);
+                any &= any - 1;
+                const float v = acc[ib][jb][q];
+                if (v <= thr) emit(CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3), v);
+            }
+        }
+    };
+    auto scan_col = [&](int jb, uint32_t bits, auto &&emit) {
+        bits = __builtin_amdgcn_readfirstlane(bits);
+        while (bits) {
+            const int jc = __builtin_ctz(bits);  // column within the 32-block
+            bits &= bits - 1;
+            const int q = ((jc >> 3) << 2) | (jc & 3);
+            const bool mine = (lane >> 5) == ((jc >> 2) & 1);
+            float v[NIB];
+#pragma unroll
+            for (int ib = 0; ib < NIB; ++ib) v[ib] = acc[ib][jb][q];
+            emit(CW * wj + 32 * jb + jc, v, mine);
+        }
+    };
 #pragma unroll
     for (int ib = 0; ib < NIB; ++ib) {
         const int il = RW * wi + 32 * ib + (lane & 31);
-        if (!(S.rhot[il] & 1)) continue;
+        const bool hot = S.rhot[il] & 1;
+        if (!__ballot(hot)) continue;
         const int64_t i = S.rid[il];
         const float Ei = S.rE[il];
         const float rb_ = __uint_as_float(S.rmin[il]);
         // (final round: also within reach of the pair's bound U; an element
         // above the cheap bound has L > U: the 2^-18 covers lower_of's slack and the roundings)
         // (pair bounds: the staged values are lower bounds, rb_ is ub)
-        const float r_cheap = PB ? rb_ * A.kappa : fminf((rb_ + 2.0f * Ei) * A.kappa, (upair + 2.0f * Ei) * (1.0f + 0x1p-18f));
+        const float r_cheap = !hot ? -SCR_INF
+                              : PB ? rb_ * A.kappa
+                                   : fminf((rb_ + 2.0f * Ei) * A.kappa, (upair + 2.0f * Ei) * (1.0f + 0x1p-18f));
         const float r_thr = PB ? rb_ * A.kappa : fminf((rb_ + Ei) * A.kappa, upair);
-#pragma unroll
-        for (int jb = 0; jb < NJB; ++jb)
-#pragma unroll 1
-            for (int q = 0; q < 16; ++q) {  // rolled (uniform q: indexed register reads) to keep the code small
-                const float v = acc[ib][jb][q];
-                if (!(v <= r_cheap)) continue;
-                const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                stage_cap(i, S.cid[jl], v, r_thr);
-            }
+        scan_row(ib, r_cheap, [&](int jl, float v) { stage_cap(i, S.cid[jl], v, r_thr); });
     }
     // columns: this wave's CW columns are bits [CW wj, +CW) of the hot set
 #pragma unroll
-    for (int jb = 0; jb < NJB; ++jb) {
-        const uint32_t hw = S.chot[(CW * wj) / 32 + jb];
-        if (!hw) continue;
-#pragma unroll 1
-        for (int q = 0; q < 16; ++q) {
-            const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);  // column within the 32-block
-            if (!((hw >> jc) & 1u)) continue;
-            const int jl = CW * wj + 32 * jb + jc;
+    for (int jb = 0; jb < NJB; ++jb)
+        scan_col(jb, S.chot[(CW * wj) / 32 + jb], [&](int jl, const float (&v)[NIB], bool mine) {
             const int64_t j = S.cid[jl];
             const float Ej = S.cE[jl];
             const float cb = __uint_as_float(S.cmin[jl]);
-            const float c_cheap = PB ? cb * A.kappa : fminf((cb + 2.0f * Ej) * A.kappa, (upair + 2.0f * Ej) * (1.0f + 0x1p-18f));
+            const float c_cheap =
+                PB ? cb * A.kappa : fminf((cb + 2.0f * Ej) * A.kappa, (upair + 2.0f * Ej) * (1.0f + 0x1p-18f));
             const float c_thr = PB ? cb * A.kappa : fminf((cb + Ej) * A.kappa, upair);
 #pragma unroll
-            for (int ib = 0; ib < NIB; ++ib) {
-                const float v = acc[ib][jb][q];
-                if (!(v <= c_cheap)) continue;
-                stage_cap(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v, c_thr);
-            }
-        }
-    }
+            for (int ib = 0; ib < NIB; ++ib)
+                if (mine && v[ib] <= c_cheap) stage_cap(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v[ib], c_thr);
+        });
 
     // ---- epilogue 4: neighbour lists (rows, then columns, whose tile minimum
     // reaches their list threshold), staged in the first staging buffer and
@@ -952,37 +962,21 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib) {
             const int il = RW * wi + 32 * ib + (lane & 31);
-            if (!(S.rhot[il] & 2)) continue;
+            const bool lst = S.rhot[il] & 2;
+            if (!__ballot(lst)) continue;
             const int64_t i = S.rid[il];
-            const float tau = A.ltau[i];
-#pragma unroll
-            for (int jb = 0; jb < NJB; ++jb)
-#pragma unroll 1
-                for (int q = 0; q < 16; ++q) {
-                    const float v = acc[ib][jb][q];
-                    if (!(v <= tau)) continue;
-                    const int jl = CW * wj + 32 * jb + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    stage(i, S.cid[jl], v);
-                }
+            const float tau = lst ? A.pltau[I0 + il] : -SCR_INF;
+            scan_row(ib, tau, [&](int jl, float v) { stage(i, S.cid[jl], v); });
         }
 #pragma unroll
-        for (int jb = 0; jb < NJB; ++jb) {
-            const uint32_t hw = S.clst[(CW * wj) / 32 + jb];
-            if (!hw) continue;
-#pragma unroll 1
-            for (int q = 0; q < 16; ++q) {
-                const int jc = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                if (!((hw >> jc) & 1u)) continue;
-                const int64_t j = S.cid[CW * wj + 32 * jb + jc];
-                const float tau = A.ltau[j];
+        for (int jb = 0; jb < NJB; ++jb)
+            scan_col(jb, S.clst[(CW * wj) / 32 + jb], [&](int jl, const float (&v)[NIB], bool mine) {
+                const int64_t j = S.cid[jl];
+                const float tau = A.pltau[J0 + jl];
 #pragma unroll
-                for (int ib = 0; ib < NIB; ++ib) {
-                    const float v = acc[ib][jb][q];
-                    if (!(v <= tau)) continue;
-                    stage(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v);
-                }
-            }
-        }
+                for (int ib = 0; ib < NIB; ++ib)
+                    if (mine && v[ib] <= tau) stage(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v[ib]);
+            });
     }
     __syncthreads();
     {
