@@ -1190,6 +1190,27 @@ __global__ void k_pos_gather(const int32_t *__restrict__ order, int64_t npos, in
     if (ltau) pltau[pos] = real ? ltau[id] : -1.0f;
 }
 
+// Largest r and e over each tile's positions (padding has r = e = 0).
+__global__ void k_tile_max(const float *__restrict__ prn, const float *__restrict__ pre, int64_t ntiles, int tile,
+                           float *__restrict__ trmax, float *__restrict__ temax) {
+    const int64_t T = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (T >= ntiles) return;
+    float r = 0.0f, e = 0.0f;
+    for (int q = lane; q < tile; q += 64) {
+        r = fmaxf(r, prn[T * tile + q]);
+        e = fmaxf(e, pre[T * tile + q]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        r = fmaxf(r, __shfl_xor(r, o));
+        e = fmaxf(e, __shfl_xor(e, o));
+    }
+    if (lane == 0) {
+        trmax[T] = r;
+        temax[T] = e;
+    }
+}
+
 // Folds running minima kept by position back into the per-point array.
 __global__ void k_pos_scatter(const int32_t *__restrict__ order, int64_t npos, int64_t n,
                               const float *__restrict__ pv, float *__restrict__ v) {
@@ -1230,6 +1251,7 @@ struct MstPlan {
     int64_t npairs, nt;
     int32_t *perm, *pvals, *tlo, *thi, *keep, *kpos, *keepu, *kposu, *scan_scratch;  // pvals: the final round's sorted ids
     float *psq, *pEmax, *prn, *pre, *pltau, *pbest, *pub;  // the tile-pair screen's per-position copies
+    float *trmax, *temax;                                   // and its per-tile largest r and e
     int32_t *pcomp, *psqi;
     uint32_t *pkeys, *ptk, *ptv;
     void *psort;
@@ -1331,6 +1353,8 @@ struct MstPlan {
             pltau = a.take<float>(npos);
             pbest = a.take<float>(n_pad);
             pub = a.take<float>(n_pad);
+            trmax = a.take<float>(npos / GT);
+            temax = a.take<float>(npos / GT);
         }
         scan_scratch = a.take<int32_t>(scan_scratch_bytes(std::max<int64_t>(npairs, n + 1)) / sizeof(int32_t));
         ltau = a.take<float>(n);
@@ -1587,11 +1611,18 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.pltau = P.pltau;
     SA.pbest = P.pbest;
     SA.pub = ubp ? P.pub : nullptr;
-    // the tile-pair screen's per-position copies for the tile order `order`
+    SA.trmax = P.trmax;
+    SA.temax = P.temax;
+    // the tile-pair screen's per-position copies and per-tile maxima for the
+    // tile order `order` (npos positions, a whole number of tiles)
     auto pos_gather = [&](const int32_t *order, int64_t npos, bool with_ltau) {
         hipLaunchKernelGGL(k_pos_gather, dim3(grid_for(npos, 256)), dim3(256), 0, s, order, npos, n, P.sq, P.comp,
-                           P.Emax, ubp ? P.rn : nullptr, P.re, rep == ISO_PREC_INT8 ? P.sqi : nullptr,
-                           with_ltau ? P.ltau : nullptr, P.psq, P.pcomp, P.pEmax, P.prn, P.pre, P.psqi, P.pltau);
+                           P.Emax, P.rn, P.re, rep == ISO_PREC_INT8 ? P.sqi : nullptr, with_ltau ? P.ltau : nullptr,
+                           P.psq, P.pcomp, P.pEmax, P.prn, P.pre, P.psqi, P.pltau);
+        LAUNCH_CHECK();
+        const int64_t ntiles = npos / GT;
+        hipLaunchKernelGGL(k_tile_max, dim3(grid_for(ntiles * 64, 256)), dim3(256), 0, s, P.prn, P.pre, ntiles, (int)GT,
+                           P.trmax, P.temax);
         LAUNCH_CHECK();
     };
 

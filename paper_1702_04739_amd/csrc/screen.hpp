@@ -81,6 +81,7 @@ struct ScreenArgs {
     const int32_t *psqi;
     const float *pltau;
     float *pbest, *pub;
+    const float *trmax, *temax;  // tile-pair screen: per tile of the order, the largest r and e of its points
     ScreenBound bound;       // error bound constants
     float kappa;             // capture threshold scale (recheck order slack and rounding)
     // gathered pass (rows == nullptr for the full sweep)

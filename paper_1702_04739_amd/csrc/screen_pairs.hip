@@ -550,18 +550,22 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // fall), and it is the value of a real pair, so every threshold built
     // from it remains a valid upper bound: an early read only captures more.
     uint32_t pre_old[NPRE], pre_oldu[NPRE];
-    float pre_tau[NPRE];
+    float pre_tau[NPRE], pre_r[NPRE], pre_e[NPRE];
 #pragma unroll
     for (int e = 0; e < NPRE; ++e) {
         const int u = tid + e * 64 * NW;
         pre_old[e] = pre_oldu[e] = INF_BITS;
-        pre_tau[e] = 0.0f;
+        pre_tau[e] = pre_r[e] = pre_e[e] = 0.0f;
         if (u >= PT + PH) continue;
         const bool is_row = u < PT;
         const int t = is_row ? u : u - PT;
         const int64_t p = is_row ? S.rid[t] : S.cid[t];
         if (p >= A.n) continue;
         const int64_t pos = is_row ? I0 + t : J0 + t;
+        if constexpr (!PB) {
+            pre_r[e] = A.prn[pos];
+            pre_e[e] = A.pre[pos];
+        }
         const uint32_t *const bp = FINAL ? reinterpret_cast<const uint32_t *>(A.bestc) +
                                                (is_row ? compJ : compI) * A.bestc_stride + pos
                                          : reinterpret_cast<const uint32_t *>(A.pbest) + pos;
@@ -755,8 +759,16 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // (compI, compJ): their merged minima also lower that pair's bound U (one
     // atomic per item), and a row or column is hot only while its tile minimum
     // can still reach U.
+    // (the capture thresholds: an element is staged when its Dhat^2 is at most
+    // the cheap bound (b + E + E_tile) kappa, where E_tile, the pair bound of
+    // the point against the largest r and e of the other tile, bounds every
+    // element's own E_ij; it is committed when its lower bound Dhat^2 - E_ij
+    // is at most (b + E) kappa.  After this epilogue the LDS holds these two
+    // thresholds in place of b and E.)
     float upair = SCR_INF;  // final round: U on the real-D^2 scale
     uint32_t tmin[NPRE];
+    float etile[NPRE];
+    const float rmxI = A.trmax[pr.x], emxI = A.temax[pr.x], rmxJ = A.trmax[pr.y], emxJ = A.temax[pr.y];
 #pragma unroll
     for (int e = 0; e < NPRE; ++e) {
         const int u = tid + e * 64 * NW;
@@ -772,6 +784,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         if (p < A.n && m < old) atomicMin(bp, m);
         const float cur = p < A.n ? __uint_as_float(min(old, m)) : SCR_INF;
         const float E = is_row ? S.rE[t] : S.cE[t];
+        etile[e] = fminf(pair_bound(A.bound, pre_r[e], is_row ? rmxJ : rmxI, pre_e[e], is_row ? emxJ : emxI), E);
         if constexpr (PB) {
             // the running upper bound ub; the row is hot when its least lower
             // bound can reach kappa ub; the threshold base becomes ub
@@ -781,12 +794,15 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const uint32_t oldu = pre_oldu[e];
             if (p < A.n && mU < oldu) atomicMin(up, mU);
             const float curu = p < A.n ? __uint_as_float(min(oldu, mU)) : SCR_INF;
-            const bool hotu = p < A.n && __uint_as_float(mL) <= curu * A.kappa;
+            const float thr = curu * A.kappa;  // (the staged values are already lower bounds)
+            const bool hotu = p < A.n && mL < INF_BITS && __uint_as_float(mL) <= thr;
             if (is_row) {
-                S.rmin[t] = __float_as_uint(curu);
+                S.rmin[t] = __float_as_uint(thr);
+                S.rE[t] = thr;
                 S.rhot[t] = hotu ? 1 : 0;
             } else {
-                S.cmin[t] = __float_as_uint(curu);
+                S.cmin[t] = __float_as_uint(thr);
+                S.cE[t] = thr;
                 if (hotu) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
             }
             continue;
@@ -800,13 +816,17 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
                 S.cmin[t] = __float_as_uint(cur);
             continue;
         }
-        const bool hot = p < A.n && __uint_as_float(m) <= (cur + 2.0f * E) * A.kappa;
+        // (a row or column with no valid element in the item, m = +inf, is never hot)
+        const float thr = (cur + E) * A.kappa, cheap = (cur + E + etile[e]) * A.kappa;
+        const bool hot = p < A.n && m < INF_BITS && __uint_as_float(m) <= cheap;
         const bool lst = LIST && p < A.n && __uint_as_float(m) <= pre_tau[e];
         if (is_row) {
-            S.rmin[t] = __float_as_uint(cur);
+            S.rmin[t] = __float_as_uint(thr);
+            S.rE[t] = cheap;
             S.rhot[t] = (hot ? 1 : 0) | (lst ? 2 : 0);
         } else {
-            S.cmin[t] = __float_as_uint(cur);
+            S.cmin[t] = __float_as_uint(thr);
+            S.cE[t] = cheap;
             if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
             if (lst) atomicOr(&S.clst[t >> 5], 1u << (t & 31));
         }
@@ -831,12 +851,21 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const int64_t p = is_row ? S.rid[t] : S.cid[t];
             const float cur = __uint_as_float(is_row ? S.rmin[t] : S.cmin[t]);
             const float E = is_row ? S.rE[t] : S.cE[t];
-            const float cheap = fminf((cur + 2.0f * E) * A.kappa, (upair + 2.0f * E) * (1.0f + 0x1p-18f));
-            const bool hot = p < A.n && __uint_as_float(tmin[e]) <= cheap;
-            if (is_row)
+            // (also within reach of the pair's bound U: an element above the
+            // cheap bound has L > U; the 2^-18 covers lower_of's slack and the roundings)
+            const float thr = fminf((cur + E) * A.kappa, upair);
+            const float cheap =
+                fminf((cur + E + etile[e]) * A.kappa, (upair + E + etile[e]) * (1.0f + 0x1p-18f));
+            const bool hot = p < A.n && tmin[e] < INF_BITS && __uint_as_float(tmin[e]) <= cheap;
+            if (is_row) {
+                S.rmin[t] = __float_as_uint(thr);
+                S.rE[t] = cheap;
                 S.rhot[t] = hot ? 1 : 0;
-            else if (hot)
-                atomicOr(&S.chot[t >> 5], 1u << (t & 31));
+            } else {
+                S.cmin[t] = __float_as_uint(thr);
+                S.cE[t] = cheap;
+                if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
+            }
         }
     }
     __syncthreads();
@@ -915,15 +944,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const bool hot = S.rhot[il] & 1;
         if (!__ballot(hot)) continue;
         const int64_t i = S.rid[il];
-        const float Ei = S.rE[il];
-        const float rb_ = __uint_as_float(S.rmin[il]);
-        // (final round: also within reach of the pair's bound U; an element
-        // above the cheap bound has L > U: the 2^-18 covers lower_of's slack and the roundings)
-        // (pair bounds: the staged values are lower bounds, rb_ is ub)
-        const float r_cheap = !hot ? -SCR_INF
-                              : PB ? rb_ * A.kappa
-                                   : fminf((rb_ + 2.0f * Ei) * A.kappa, (upair + 2.0f * Ei) * (1.0f + 0x1p-18f));
-        const float r_thr = PB ? rb_ * A.kappa : fminf((rb_ + Ei) * A.kappa, upair);
+        const float r_cheap = hot ? S.rE[il] : -SCR_INF;
+        const float r_thr = __uint_as_float(S.rmin[il]);
         scan_row(ib, r_cheap, [&](int jl, float v) { stage_cap(i, S.cid[jl], v, r_thr); });
     }
     // columns: this wave's CW columns are bits [CW wj, +CW) of the hot set
@@ -931,11 +953,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     for (int jb = 0; jb < NJB; ++jb)
         scan_col(jb, S.chot[(CW * wj) / 32 + jb], [&](int jl, const float (&v)[NIB], bool mine) {
             const int64_t j = S.cid[jl];
-            const float Ej = S.cE[jl];
-            const float cb = __uint_as_float(S.cmin[jl]);
-            const float c_cheap =
-                PB ? cb * A.kappa : fminf((cb + 2.0f * Ej) * A.kappa, (upair + 2.0f * Ej) * (1.0f + 0x1p-18f));
-            const float c_thr = PB ? cb * A.kappa : fminf((cb + Ej) * A.kappa, upair);
+            const float c_cheap = S.cE[jl];
+            const float c_thr = __uint_as_float(S.cmin[jl]);
 #pragma unroll
             for (int ib = 0; ib < NIB; ++ib)
                 if (mine && v[ib] <= c_cheap) stage_cap(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v[ib], c_thr);
@@ -1020,6 +1039,16 @@ template <int REP>
 void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t nmask, int64_t noff, hipStream_t s) {
     ISO_REQUIRE(A.d_pad % PPrec<REP>::KC == 0, ISO_ERR_INTERNAL, "padded dimension is not a whole number of chunks");
     ISO_REQUIRE(A.perm != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without a tile order");
+    ISO_REQUIRE(A.psq && A.pcomp && A.pEmax && A.prn && A.pre && A.trmax && A.temax && A.ccnt && A.rn && A.re,
+                ISO_ERR_INTERNAL, "tile-pair screen without its per-position inputs");
+    ISO_REQUIRE(A.bestc != nullptr || A.pbest != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without its minima");
+    ISO_REQUIRE(A.ub == nullptr || A.pub != nullptr, ISO_ERR_INTERNAL, "pair bounds without their minima");
+    ISO_REQUIRE(A.lcnt == nullptr || (A.pltau && A.ldrop && A.lj && A.lv), ISO_ERR_INTERNAL,
+                "neighbour lists without their arrays");
+    ISO_REQUIRE(A.bestc == nullptr || (A.tcomp && A.upair && A.gcj && A.gcl), ISO_ERR_INTERNAL,
+                "final round without its arrays");
+    ISO_REQUIRE(A.bestc != nullptr || (A.cj && A.cl), ISO_ERR_INTERNAL, "tile-pair screen without candidate lists");
+    ISO_REQUIRE(A.rep != ISO_PREC_INT8 || A.psqi != nullptr, ISO_ERR_INTERNAL, "INT8 screen without integer norms");
     const dim3 block(64 * NW);
     auto grid = [](int64_t per_xcd) { return dim3((unsigned)(8 * per_xcd)); };
     const bool list = A.lcnt != nullptr, final_round = A.bestc != nullptr, pb = A.ub != nullptr;
