@@ -94,8 +94,8 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
                                 "write_scale": w_scale},
            "commands": [
                "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch_dir> -o run -- python3 "
-               "<repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-compare --all-k 0 --paper-prim-n 0 "
-               "--calibrate-copy %d --precision %s" % (copy_mib, precision),
+               "<repo>/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-compare --all-k 0 --paper-prim-n 0 "
+               "--no-extras --calibrate-copy %d --precision %s" % (copy_mib, precision),
                "(the same with --pmc WRITE_SIZE -d <write_dir>)",
                "python bench.py --traffic-report <fetch_dir> <write_dir> --precision %s --calibrate-copy %d"
                % (precision, copy_mib)],
