@@ -137,9 +137,9 @@ struct PBLDS {
 
 // After the K loop the first staging buffer holds up to LIST_STAGE
 // neighbour-list entries (point, partner, Dhat^2) and the second up to
-// CAP_STAGE candidates (point, partner, Dhat^2, threshold).
+// CAP_STAGE candidates (point, partner, lower bound of D^2).
 constexpr int LIST_STAGE = SROWS * 4 * 16 / 12;
-constexpr int CAP_STAGE = SROWS * 4 * 16 / 16;
+constexpr int CAP_STAGE = SROWS * 4 * 16 / 12;
 
 constexpr uint32_t INF_BITS = 0x7F800000u;  // +inf; every screen value is a nonnegative float or +inf
 
@@ -759,12 +759,12 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     // (compI, compJ): their merged minima also lower that pair's bound U (one
     // atomic per item), and a row or column is hot only while its tile minimum
     // can still reach U.
-    // (the capture thresholds: an element is staged when its Dhat^2 is at most
-    // the cheap bound (b + E + E_tile) kappa, where E_tile, the pair bound of
-    // the point against the largest r and e of the other tile, bounds every
-    // element's own E_ij; it is committed when its lower bound Dhat^2 - E_ij
-    // is at most (b + E) kappa.  After this epilogue the LDS holds these two
-    // thresholds in place of b and E.)
+    // (the capture thresholds: E_tile, the pair bound of the point against the
+    // largest r and e of the other tile, bounds every element's own E_ij, so
+    // an element is captured when its lower bound Dhat^2 - E_tile is at most
+    // the threshold thr = (b + E) kappa (and, in the final round, U); a row or
+    // column is flagged when its tile minimum passes that test.  After this
+    // epilogue the LDS holds thr and E_tile in place of b and E.)
     float upair = SCR_INF;  // final round: U on the real-D^2 scale
     uint32_t tmin[NPRE];
     float etile[NPRE];
@@ -798,11 +798,11 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const bool hotu = p < A.n && mL < INF_BITS && __uint_as_float(mL) <= thr;
             if (is_row) {
                 S.rmin[t] = __float_as_uint(thr);
-                S.rE[t] = thr;
+                S.rE[t] = 0.0f;
                 S.rhot[t] = hotu ? 1 : 0;
             } else {
                 S.cmin[t] = __float_as_uint(thr);
-                S.cE[t] = thr;
+                S.cE[t] = 0.0f;
                 if (hotu) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
             }
             continue;
@@ -822,11 +822,11 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const bool lst = LIST && p < A.n && __uint_as_float(m) <= pre_tau[e];
         if (is_row) {
             S.rmin[t] = __float_as_uint(thr);
-            S.rE[t] = cheap;
+            S.rE[t] = etile[e];
             S.rhot[t] = (hot ? 1 : 0) | (lst ? 2 : 0);
         } else {
             S.cmin[t] = __float_as_uint(thr);
-            S.cE[t] = cheap;
+            S.cE[t] = etile[e];
             if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
             if (lst) atomicOr(&S.clst[t >> 5], 1u << (t & 31));
         }
@@ -859,11 +859,11 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const bool hot = p < A.n && tmin[e] < INF_BITS && __uint_as_float(tmin[e]) <= cheap;
             if (is_row) {
                 S.rmin[t] = __float_as_uint(thr);
-                S.rE[t] = cheap;
+                S.rE[t] = etile[e];
                 S.rhot[t] = hot ? 1 : 0;
             } else {
                 S.cmin[t] = __float_as_uint(thr);
-                S.cE[t] = cheap;
+                S.cE[t] = etile[e];
                 if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
             }
         }
@@ -871,46 +871,49 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     __syncthreads();
 
     // ---- epilogue 3: capture candidates (rows of hot rows, columns of hot
-    // columns).  Elements that pass the cheap test are staged in LDS (the
-    // second staging buffer, idle since the barrier before epilogue 2) with
-    // their threshold; after the barrier below all threads finish them at
-    // once (norm bounds from global memory, bound test, append), so the
-    // latency of those loads and of the returning atomics is paid once per
-    // work item rather than once per candidate.
+    // columns).  An element whose lower bound passes its row's or column's
+    // threshold is staged in LDS (the second staging buffer, idle since the
+    // barrier before epilogue 2) with that bound; after the barrier below all
+    // threads append them at once, so the latency of the returning atomics is
+    // paid once per work item rather than once per candidate.
     constexpr int CAP = FINAL ? SCR_CAP2 : SCR_CAP;
     int32_t *const cjs = FINAL ? A.gcj : A.cj;
     float *const cls = FINAL ? A.gcl : A.cl;
+    int32_t *const ccnt = A.ccnt;
     int32_t *const cp = reinterpret_cast<int32_t *>(RR ? xstage + SROWS * 4 : stage1);
     int32_t *const co = cp + CAP_STAGE;
     float *const cv = reinterpret_cast<float *>(co + CAP_STAGE);
-    float *const ct = cv + CAP_STAGE;
-    auto commit = [&](int64_t p, int64_t o, float v, float thr) {
-        const float L = PB ? v : lower_of(v, pair_bound(A.bound, A.rn[p], A.rn[o], A.re[p], A.re[o]));
-        if (!(L <= thr)) return;
-        const int pos = atomicAdd(&A.ccnt[p], 1);
+    auto commit = [&](int64_t p, int64_t o, float L) {
+        const int pos = atomicAdd(&ccnt[p], 1);
         if (pos < CAP) {
             cjs[p * CAP + pos] = (int32_t)o;
             cls[p * CAP + pos] = L;
         }
     };
-    auto stage_cap = [&](int64_t p, int64_t o, float v, float thr) {
+    // (p, o): the element's point and partner; v its Dhat^2 (pair bounds: its
+    // lower bound); thr and et the point's threshold and tile bound
+    auto stage_cap = [&](int64_t p, int64_t o, float v, float thr, float et) {
         v = __int_as_float(max(__float_as_int(v), 0));  // an unmasked item's negative value becomes +0
+        const float L = PB ? v : lower_of(v, et);
+        if (!(L <= thr)) return;
         const int pos = atomicAdd(&S.ncap, 1);
         if (pos < CAP_STAGE) {
             cp[pos] = (int32_t)p;
             co[pos] = (int32_t)o;
-            cv[pos] = v;
-            ct[pos] = thr;
+            cv[pos] = L;
         } else {
-            commit(p, o, v, thr);
+            commit(p, o, L);
         }
     };
+    // (the emit closures are taken by value, and the candidate counts through
+    // a local pointer: a closure or kernel argument reached through a
+    // reference here has made the compiler keep it in scratch memory)
     // The scans below visit few elements: a row's flagged elements are found
     // by one compare per element, whose wave mask (any lane at or below its
     // threshold) marks a column position; only marked positions are then
     // read again (uniform position: indexed register read) and staged.  A
     // flagged column is one register position of one half wave.
-    auto scan_row = [&](int ib, float thr, auto &&emit) {
+    auto scan_row = [&](int ib, float thr, auto emit) {
 #pragma unroll
         for (int jb = 0; jb < NJB; ++jb) {  // (jb static: only q indexes a register dynamically)
             uint32_t any = 0;
@@ -925,7 +928,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             }
         }
     };
-    auto scan_col = [&](int jb, uint32_t bits, auto &&emit) {
+    auto scan_col = [&](int jb, uint32_t bits, auto emit) {
         bits = __builtin_amdgcn_readfirstlane(bits);
         while (bits) {
             const int jc = __builtin_ctz(bits);  // column within the 32-block
@@ -944,20 +947,22 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         const bool hot = S.rhot[il] & 1;
         if (!__ballot(hot)) continue;
         const int64_t i = S.rid[il];
-        const float r_cheap = hot ? S.rE[il] : -SCR_INF;
-        const float r_thr = __uint_as_float(S.rmin[il]);
-        scan_row(ib, r_cheap, [&](int jl, float v) { stage_cap(i, S.cid[jl], v, r_thr); });
+        const float r_thr = __uint_as_float(S.rmin[il]), r_et = S.rE[il];
+        // (an element above this bound has lower_of(v, E_tile) > thr)
+        const float r_cheap = hot ? (r_thr + r_et) * (1.0f + 0x1p-18f) : -SCR_INF;
+        scan_row(ib, r_cheap, [&](int jl, float v) { stage_cap(i, S.cid[jl], v, r_thr, r_et); });
     }
     // columns: this wave's CW columns are bits [CW wj, +CW) of the hot set
 #pragma unroll
     for (int jb = 0; jb < NJB; ++jb)
         scan_col(jb, S.chot[(CW * wj) / 32 + jb], [&](int jl, const float (&v)[NIB], bool mine) {
             const int64_t j = S.cid[jl];
-            const float c_cheap = S.cE[jl];
-            const float c_thr = __uint_as_float(S.cmin[jl]);
+            const float c_thr = __uint_as_float(S.cmin[jl]), c_et = S.cE[jl];
+            const float c_cheap = (c_thr + c_et) * (1.0f + 0x1p-18f);
 #pragma unroll
             for (int ib = 0; ib < NIB; ++ib)
-                if (mine && v[ib] <= c_cheap) stage_cap(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v[ib], c_thr);
+                if (mine && v[ib] <= c_cheap)
+                    stage_cap(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v[ib], c_thr, c_et);
         });
 
     // ---- epilogue 4: neighbour lists (rows, then columns, whose tile minimum
@@ -1001,7 +1006,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
     {
         const int cnt = min(S.ncap, CAP_STAGE);
 #pragma unroll 1
-        for (int e = tid; e < cnt; e += 64 * NW) commit(cp[e], co[e], cv[e], ct[e]);
+        for (int e = tid; e < cnt; e += 64 * NW) commit(cp[e], co[e], cv[e]);
     }
     if constexpr (LIST) {
         const int32_t *lp = reinterpret_cast<const int32_t *>(RR ? xstage : stage0);
