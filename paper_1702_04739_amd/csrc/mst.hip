@@ -1551,6 +1551,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.n = n;
     SA.n_pad = P.n_pad;
     SA.d_pad = P.d_pad;
+    SA.d = d;
     SA.sq = P.sq;
     SA.rn = P.rn;
     SA.re = P.re;

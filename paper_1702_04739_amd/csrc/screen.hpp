@@ -59,6 +59,7 @@ struct ScreenArgs {
     const int32_t *sqi;      // INT8 screen: [n_pad] exact ||(x - mu) / 2^q||^2, 2^30 on padding
     float scale2;            // INT8 screen: 2^2q, the unit of the integer distances
     int64_t n, n_pad, d_pad;
+    int64_t d;               // coordinates that may be nonzero (the rest of d_pad is zero padding)
     const float *sq;         // [n_pad] fl(||x'||^2) as used in Dhat^2 (0 on padding)
     const float *rn;         // [n_pad] r_i
     const float *re;         // [n_pad] e_i

@@ -430,8 +430,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         // CRUNS 1 KB DMA runs per wave); wave w's rows are blocks 2 w, 2 w + 1
         // of tile I (four 16-byte loads per lane and chunk, straight into
         // registers, issued two chunks ahead).
-#define ISO_RCOMPUTE(SB, RG)                                                                                  \
-    _Pragma("unroll") for (int t = 0; t < 2; ++t) {                                                          \
+#define ISO_RCOMPUTE(SB, RG, NT)                                                                              \
+    _Pragma("unroll") for (int t = 0; t < 2; ++t) if (t < (NT)) {                                            \
         bf16x8 a[NJB];                                                                                        \
         _Pragma("unroll") for (int jb = 0; jb < NJB; ++jb) {                                                  \
             const uint4 v = SB[(jb * 2 + t) * 64 + lane];                                                     \
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             __builtin_amdgcn_s_waitcnt(VMCNT(0));                                                            \
         __builtin_amdgcn_s_barrier();                                                                        \
         if ((C) + 2 < nchunks) ISO_RISSUE(SN, RN, (C) + 2)                                                   \
-        ISO_RCOMPUTE(SB, RG)                                                                                 \
+        ISO_RCOMPUTE(SB, RG, (C) + 1 == nchunks && d_last_half ? 1 : 2)                                      \
     }
         // Steps inside the loop issue unconditionally, so every step finds
         // exactly two chunks (12 loads) in flight and the register loads need
@@ -462,8 +462,11 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         __builtin_amdgcn_s_waitcnt(VMCNT(CRUNS + 4));                                                        \
         __builtin_amdgcn_s_barrier();                                                                        \
         ISO_RISSUE(SN, RN, (C) + 2)                                                                          \
-        ISO_RCOMPUTE(SB, RG)                                                                                 \
+        ISO_RCOMPUTE(SB, RG, 2)                                                                              \
     }
+        // the last chunk's second 16-wide K step holds only zero padding when
+        // d ends in the chunk's first half: its MFMAs are skipped
+        const bool d_last_half = A.d <= (int64_t)(nchunks - 1) * P::KC + P::KC / 2;
         int c = 0;
         for (; c + 4 < nchunks; c += 3) {
             ISO_RSTEP_FULL(stage0, rg0, stage2, rg2, c)
@@ -1043,6 +1046,8 @@ namespace {
 template <int REP>
 void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t nmask, int64_t noff, hipStream_t s) {
     ISO_REQUIRE(A.d_pad % PPrec<REP>::KC == 0, ISO_ERR_INTERNAL, "padded dimension is not a whole number of chunks");
+    ISO_REQUIRE(A.d > A.d_pad - PPrec<REP>::KC && A.d <= A.d_pad, ISO_ERR_INTERNAL, "dimension %lld outside the last chunk of %lld",
+                (long long)A.d, (long long)A.d_pad);
     ISO_REQUIRE(A.perm != nullptr, ISO_ERR_INTERNAL, "tile-pair screen without a tile order");
     ISO_REQUIRE(A.psq && A.pcomp && A.pEmax && A.prn && A.pre && A.trmax && A.temax && A.ccnt && A.rn && A.re,
                 ISO_ERR_INTERNAL, "tile-pair screen without its per-position inputs");
