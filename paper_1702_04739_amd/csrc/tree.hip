@@ -276,13 +276,14 @@ __global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ pare
 
 // Everything Algorithm 1 reads about the vertex at x-order position q, packed
 // so that a level's first load is indexed by the position itself.
-struct VtxMeta {
+struct __attribute__((aligned(16))) VtxMeta {
     int32_t a0, a1;     // its children's output slots a0 .. a1-1
     int32_t slot, v;    // its own output slot and id
     int32_t root, pad;  // 1 for the root
     double om0, p0;     // its weight and potential
     double fe;          // phi of its parent edge (0 at the root)
 };
+static_assert(sizeof(VtxMeta) == 48, "a vertex record is three 16-byte pieces");
 
 struct DPArgs {
     const int32_t *level_start;  // level L occupies entries level_start[L] .. level_start[L+1]-1 of the position list
@@ -314,8 +315,7 @@ struct DPArgs {
 // subtree is constant, so a subtree that decides alike at both ends of an
 // interval decides alike, and contributes the same, everywhere inside it.
 template <int MM, bool REC, bool MASK>
-__device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
-    const VtxMeta vm = A.meta[q];
+__device__ inline void dp_vertex_vm(const DPArgs &A, const VtxMeta vm, int m) {
     const double N = A.Nvals[m];
     double w = vm.om0;
     double p = vm.p0;
@@ -385,6 +385,11 @@ __device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
     }
 }
 
+template <int MM, bool REC, bool MASK>
+__device__ inline void dp_vertex(const DPArgs &A, int32_t q, int m) {
+    dp_vertex_vm<MM, REC, MASK>(A, A.meta[q], m);
+}
+
 // The packed record of every x-order position (after slots and weights).
 __global__ void k_vtx_meta(const int32_t *__restrict__ order, const int32_t *__restrict__ koff,
                            const int32_t *__restrict__ slot, const int32_t *__restrict__ parent,
@@ -419,16 +424,76 @@ __global__ __launch_bounds__(256) void k_dp_level(DPArgs A, int32_t lo, int32_t 
     dp_vertex<MM, REC, MASK>(A, q, m);
 }
 
-// A run of narrow levels [L0, L1) inside one workgroup, a barrier between levels.
+// A run of narrow levels [L0, L1) inside one workgroup (every level at most
+// narrow_cap<REC>() vertices), a barrier between levels.  The vertex records
+// of the next level and the positions of the one after, which do not depend
+// on this level's results, are loaded while this level runs and kept in LDS,
+// so a level waits for one round trip (its children's contributions) instead
+// of three (position, record, children).
+template <bool REC>
+constexpr int narrow_cap() { return REC ? 1024 : NARROW_VERTS; }
+// threads of the narrow kernel: 1024 one-lane vertices, or 8 vertices of 64
+// lanes (512 threads, so that a lane may use 256 registers)
+template <int MM>
+constexpr int narrow_threads() { return MM == 1 ? 1024 : 512; }
+
 template <int MM, bool REC, bool MASK>
-__global__ __launch_bounds__(1024) void k_dp_narrow(DPArgs A, int32_t L0, int32_t L1) {
+__global__ __launch_bounds__(narrow_threads<MM>()) void k_dp_narrow(DPArgs A, int32_t L0, int32_t L1) {
     if (!REC && A.st->done) return;
-    const int m = threadIdx.x % MM;
-    const int slot = threadIdx.x / MM;
+    constexpr int CAP = narrow_cap<REC>();
+    static_assert(CAP <= narrow_threads<MM>(), "one thread per record of a narrow level");
+    __shared__ VtxMeta smeta[2][CAP];
+    __shared__ int32_t spos[2][CAP];
+    const int tid = threadIdx.x;
+    const int m = tid % MM;
+    const int slot = tid / MM;
     const int slots = blockDim.x / MM;
+    const bool own = tid < CAP;
+    // position of entry e of the list (the list is the identity without A.act)
+    auto pos_of = [&](int32_t e) { return A.act ? A.act[e] : e; };
+    // level L0's records, level L0+1's positions
+    {
+        const int32_t lo = A.level_start[L0], hi = A.level_start[L0 + 1];
+        if (own && tid < hi - lo) smeta[0][tid] = A.meta[pos_of(lo + tid)];
+        if (L0 + 1 < L1) {
+            const int32_t hi1 = A.level_start[L0 + 2];
+            if (own && tid < hi1 - hi) spos[1][tid] = pos_of(hi + tid);
+        }
+    }
+    __syncthreads();
     for (int32_t L = L0; L < L1; ++L) {
+        const int b = (L - L0) & 1;
         const int32_t lo = A.level_start[L], hi = A.level_start[L + 1];
-        for (int32_t e = lo + slot; e < hi; e += slots) dp_vertex<MM, REC, MASK>(A, A.act ? A.act[e] : e, m);
+        // level L+1's records (positions already in LDS) and level L+2's
+        // positions: issued before this level's work, stored after it
+        uint4 nx0{}, nx1{}, nx2{};  // one record as three 16-byte pieces (kept in registers)
+        int32_t np = 0;
+        bool has_m = false, has_p = false;
+        if (L + 1 < L1) {
+            const int32_t hi1 = A.level_start[L + 2];
+            if (own && tid < hi1 - hi) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(A.meta + spos[b ^ 1][tid]);
+                nx0 = src[0];
+                nx1 = src[1];
+                nx2 = src[2];
+                has_m = true;
+            }
+            if (L + 2 < L1) {
+                const int32_t hi2 = A.level_start[L + 3];
+                if (own && tid < hi2 - hi1) {
+                    np = pos_of(hi1 + tid);
+                    has_p = true;
+                }
+            }
+        }
+        for (int32_t e = lo + slot; e < hi; e += slots) dp_vertex_vm<MM, REC, MASK>(A, smeta[b][e - lo], m);
+        if (has_m) {
+            uint4 *dst = reinterpret_cast<uint4 *>(&smeta[b ^ 1][tid]);
+            dst[0] = nx0;
+            dst[1] = nx1;
+            dst[2] = nx2;
+        }
+        if (has_p) spos[b][tid] = np;
         __syncthreads();
     }
 }
@@ -744,7 +809,7 @@ int bits_for(int64_t maxval) {
 // ls holds the level starts of A's position list (A.level_start on the device).
 template <int MM, bool REC, bool MASK>
 void launch_levels(const DPArgs &A, const std::vector<int32_t> &ls, int32_t maxdepth, hipStream_t s) {
-    const int narrow_cap = (REC ? 1024 : NARROW_VERTS);
+    const int narrow_cap = iso::narrow_cap<REC>();
     int32_t L = 0;
     while (L <= maxdepth) {
         const int32_t width = ls[L + 1] - ls[L];
@@ -756,7 +821,8 @@ void launch_levels(const DPArgs &A, const std::vector<int32_t> &ls, int32_t maxd
                 ++L1;
             }
             if (any) {
-                hipLaunchKernelGGL((k_dp_narrow<MM, REC, MASK>), dim3(1), dim3(1024), 0, s, A, L, L1);
+                hipLaunchKernelGGL((k_dp_narrow<MM, REC, MASK>), dim3(1), dim3(narrow_threads<MM>()), 0, s, A, L,
+                                   L1);
                 LAUNCH_CHECK();
             }
             L = L1;
