@@ -1065,21 +1065,7 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t nmask, int64_t
     ISO_REQUIRE(!(final_round && (list || nmask > 0)), ISO_ERR_INTERNAL, "final round with lists or masked pairs");
     ISO_REQUIRE(!pb || (REP == ISO_PREC_BF16 && !list && !final_round), ISO_ERR_INTERNAL,
                 "pair bounds only in plain BF16 rounds");
-    // masked tile pairs (on the diagonal only i < j counted), two halves each ...
-    if (nmask > 0) {
-        const int64_t items = 2 * nmask, per_xcd = (items + 7) / 8;
-        if (list)
-            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
-                               items);
-        else if (pb)
-            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_PLAIN, REP == ISO_PREC_BF16>), grid(per_xcd), block, 0,
-                               s, A, pairs, per_xcd, items);
-        else
-            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
-                               items);
-        LAUNCH_CHECK();
-    }
-    // ... then the others
+    // the unmasked tile pairs, two halves each ...
     if (noff > 0) {
         const int64_t items = 2 * noff, per_xcd = (items + 7) / 8;
         if (final_round)
@@ -1094,6 +1080,22 @@ void launch_pairs(const ScreenArgs &A, const int2 *pairs, int64_t nmask, int64_t
         else
             hipLaunchKernelGGL((k_screen_pairs<REP, false, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs + nmask,
                                per_xcd, items);
+        LAUNCH_CHECK();
+    }
+    // ... then the masked tile pairs (on the diagonal only i < j counted), two
+    // halves each: a small launch, run after the large one, when most points'
+    // running minima are already low, so that few of its rows are flagged
+    if (nmask > 0) {
+        const int64_t items = 2 * nmask, per_xcd = (items + 7) / 8;
+        if (list)
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_LIST>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
+                               items);
+        else if (pb)
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_PLAIN, REP == ISO_PREC_BF16>), grid(per_xcd), block, 0,
+                               s, A, pairs, per_xcd, items);
+        else
+            hipLaunchKernelGGL((k_screen_pairs<REP, true, MODE_PLAIN>), grid(per_xcd), block, 0, s, A, pairs, per_xcd,
+                               items);
         LAUNCH_CHECK();
     }
 }
