@@ -1007,9 +1007,11 @@ __global__ void k_degree(const int32_t *__restrict__ eu, const int32_t *__restri
     atomicAdd(&deg[ev[e]], 1);
 }
 
+// Adjacency lists of the tree: arc a -> b of edge e sits in a's list, and
+// earc[2 e], earc[2 e + 1] record the positions of its two arcs (eu -> ev, ev -> eu).
 __global__ void k_fill_adj(const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
                            const int32_t *__restrict__ off, int32_t *__restrict__ cursor, int32_t *__restrict__ adj,
-                           int32_t *__restrict__ adje) {
+                           int32_t *__restrict__ adje, int32_t *__restrict__ earc) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     int a = eu[e], b = ev[e];
@@ -1019,52 +1021,59 @@ __global__ void k_fill_adj(const int32_t *__restrict__ eu, const int32_t *__rest
     int pb = off[b] + atomicAdd(&cursor[b], 1);
     adj[pb] = a;
     adje[pb] = (int32_t)e;
+    earc[2 * e] = pa;
+    earc[2 * e + 1] = pb;
 }
 
-// Rooting BFS from vertex 0, one launch per level.  Level L occupies
-// order[start[L] .. start[L] + cnt[L]); one wave per frontier vertex walks its
-// adjacency 64 entries at a time and appends the unvisited neighbours to level
-// L+1 (the depth CAS admits every vertex at most once, so order never
-// overflows even on a malformed edge set).  A launch whose level is empty
-// returns at once, so levels can be launched past the tree's depth.
-__global__ void k_bfs_init(int32_t *__restrict__ parent, double *__restrict__ length, int32_t *__restrict__ depth,
-                           int32_t *__restrict__ order, int32_t *__restrict__ start, int32_t *__restrict__ cnt) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    parent[0] = -1;
-    length[0] = 0.0;
-    depth[0] = 0;
-    order[0] = 0;
-    start[0] = 0;
-    cnt[0] = 1;
+// Rooting at vertex 0 by an Euler tour: the tour walks every arc once, and
+// after arc u -> v it takes the arc that follows v -> u in v's list
+// (cyclically); the arc that would lead back to the root's first arc (arc 0)
+// ends it.  Each arc's distance to the end of the tour comes from pointer
+// jumping (log2 of the arc count rounds); of an edge's two arcs the one taken
+// first, the farther from the end, goes from parent to child.  Whatever order
+// the adjacency lists have, the parents are the tree's unique ones.
+__global__ void k_tour_succ(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                            const int32_t *__restrict__ adje, const int32_t *__restrict__ earc, int64_t narcs,
+                            int32_t *__restrict__ nxt, int32_t *__restrict__ rk) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= narcs) return;
+    const int32_t e = adje[x];
+    const int32_t r = earc[2 * e] == (int32_t)x ? earc[2 * e + 1] : earc[2 * e];  // the reverse arc, in v's list
+    const int32_t v = adj[x];
+    int32_t nx = r + 1 < off[v + 1] ? r + 1 : off[v];
+    if (nx == 0) nx = -1;  // back at the root's first arc: the tour ends
+    nxt[x] = nx;
+    rk[x] = 1;
 }
 
-__global__ __launch_bounds__(256) void k_bfs_level(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
-                                                   const int32_t *__restrict__ adje, const double *__restrict__ elen,
-                                                   int32_t L, int32_t *__restrict__ parent,
-                                                   double *__restrict__ length, int32_t *__restrict__ depth,
-                                                   int32_t *__restrict__ order, int32_t *__restrict__ start,
-                                                   int32_t *__restrict__ cnt) {
-    const int32_t c = cnt[L];
-    if (c == 0) return;
-    const int32_t s0 = start[L];
-    const int32_t s1 = s0 + c;  // start of level L+1
-    if (blockIdx.x == 0 && threadIdx.x == 0) start[L + 1] = s1;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t q = wave; q < c; q += nwaves) {
-        const int32_t v = order[s0 + q];
-        const int32_t pv = parent[v];
-        const int32_t dv = depth[v];
-        for (int32_t a = off[v] + lane; a < off[v + 1]; a += 64) {
-            const int32_t w = adj[a];
-            if (w == pv) continue;
-            if (atomicCAS(&depth[w], -1, dv + 1) != -1) continue;
-            parent[w] = v;
-            length[w] = elen[adje[a]];
-            order[s1 + atomicAdd(&cnt[L + 1], 1)] = w;
-        }
+__global__ void k_tour_jump(const int32_t *__restrict__ nxt_in, const int32_t *__restrict__ rk_in, int64_t narcs,
+                            int32_t *__restrict__ nxt_out, int32_t *__restrict__ rk_out) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= narcs) return;
+    int32_t nx = nxt_in[x], r = rk_in[x];
+    if (nx >= 0) {
+        r += rk_in[nx];
+        nx = nxt_in[nx];
     }
+    nxt_out[x] = nx;
+    rk_out[x] = r;
+}
+
+__global__ void k_tour_orient(const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+                              const int32_t *__restrict__ earc, const int32_t *__restrict__ rk,
+                              const double *__restrict__ elen, int64_t m, int32_t *__restrict__ parent,
+                              double *__restrict__ length) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        parent[0] = -1;
+        length[0] = 0.0;
+    }
+    if (e >= m) return;
+    const int32_t a = eu[e], b = ev[e];
+    const bool a_first = rk[earc[2 * e]] > rk[earc[2 * e + 1]];  // arc a -> b taken before b -> a
+    const int32_t child = a_first ? b : a;
+    parent[child] = a_first ? a : b;
+    length[child] = elen[e];
 }
 
 // Deterministic FP64 sum of length[1..n) (one workgroup, fixed tree).
@@ -1258,7 +1267,7 @@ struct MstPlan {
     double *psum;
     uint32_t *rmax, *emax, *comp_ub;
     int32_t *comp, *ccnt, *cj, *glist, *gcnt, *gcj, *rlist, *rb_j, *cpar, *npar, *flag, *newid, *eu, *ev;
-    int32_t *deg, *aoff, *cursor, *adj, *adje, *fa, *fb, *lcnt, *depth;
+    int32_t *deg, *aoff, *cursor, *adj, *adje, *earc, *tnxt0, *tnxt1, *trk0, *trk1;
     float *ltau, *lv;               // neighbour lists: thresholds, [n][LIST_CAP] values
     int32_t *lscnt, *lj;            // entries offered, [n][LIST_CAP] partners
     uint32_t *ldrop;                // smallest dropped value
@@ -1318,10 +1327,11 @@ struct MstPlan {
         cursor = a.take<int32_t>(n);
         adj = a.take<int32_t>(2 * n);
         adje = a.take<int32_t>(2 * n);
-        fa = a.take<int32_t>(n);       // BFS order
-        fb = a.take<int32_t>(n + 1);   // BFS level starts
-        lcnt = a.take<int32_t>(n + 1); // BFS level sizes
-        depth = a.take<int32_t>(n);
+        earc = a.take<int32_t>(2 * n);   // the two arcs of each tree edge
+        tnxt0 = a.take<int32_t>(2 * n);  // Euler tour: successor and distance to the end, double-buffered
+        tnxt1 = a.take<int32_t>(2 * n);
+        trk0 = a.take<int32_t>(2 * n);
+        trk1 = a.take<int32_t>(2 * n);
         rb_d2 = a.take<double>(n);
         elen = a.take<double>(n);
         wsum = a.take<double>(1);
@@ -2011,48 +2021,32 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     exclusive_scan_i32(P.deg, P.aoff, n + 1, nullptr, P.scan_scratch, s);
     fill<int32_t>(P.cursor, 0, n, s);
     hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, m, P.aoff, P.cursor, P.adj,
-                       P.adje);
+                       P.adje, P.earc);
     LAUNCH_CHECK();
-    fill<int32_t>(P.depth, -1, n, s);
-    fill<int32_t>(P.lcnt, 0, n + 1, s);
-    hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, s, parent, length, P.depth, P.fa, P.fb, P.lcnt);
+    // rooting: Euler tour, pointer jumping, orientation
+    const int64_t narcs = 2 * m;
+    hipLaunchKernelGGL(k_tour_succ, dim3(grid_for(narcs, 256)), dim3(256), 0, s, P.aoff, P.adj, P.adje, P.earc, narcs,
+                       P.tnxt0, P.trk0);
     LAUNCH_CHECK();
-    // levels in batches of 32 between checks; a tree has at most n levels
-    // vertices reached = start of the first empty level
-    int32_t h_seen = 0;
-    {
-        constexpr int BATCH = 32;
-        int32_t L0 = 0;
-        while (true) {
-            const int32_t L1 = (int32_t)std::min<int64_t>(L0 + BATCH, n);
-            for (int32_t L = L0; L < L1; ++L) {
-                hipLaunchKernelGGL(k_bfs_level, dim3(1024), dim3(256), 0, s, P.aoff, P.adj, P.adje, P.elen, L, parent,
-                                   length, P.depth, P.fa, P.fb, P.lcnt);
-                LAUNCH_CHECK();
-            }
-            // sizes and starts of levels L0 .. L1 (level L1 is written by launch L1 - 1)
-            int32_t hc[BATCH + 1], hs[BATCH + 1];
-            const int cntn = L1 - L0 + 1 <= (int32_t)(n + 1 - L0) ? L1 - L0 + 1 : (int)(n + 1 - L0);
-            HIP_CHECK(hipMemcpyAsync(hc, P.lcnt + L0, sizeof(int32_t) * cntn, hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipMemcpyAsync(hs, P.fb + L0, sizeof(int32_t) * cntn, hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
-            int e = -1;
-            for (int q = 0; q < cntn; ++q)
-                if (hc[q] == 0) {
-                    e = q;
-                    break;
-                }
-            if (e >= 0) {
-                h_seen = hs[e];
-                break;
-            }
-            ISO_REQUIRE(L1 < n, ISO_ERR_INTERNAL, "tree BFS did not terminate");
-            L0 = L1;
-        }
+    int32_t *tn = P.tnxt0, *tr = P.trk0, *tn2 = P.tnxt1, *tr2 = P.trk1;
+    for (int64_t span = 1; span < narcs; span *= 2) {
+        hipLaunchKernelGGL(k_tour_jump, dim3(grid_for(narcs, 256)), dim3(256), 0, s, tn, tr, narcs, tn2, tr2);
+        LAUNCH_CHECK();
+        std::swap(tn, tn2);
+        std::swap(tr, tr2);
     }
+    hipLaunchKernelGGL(k_tour_orient, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, P.earc, tr, P.elen, m,
+                       parent, length);
+    LAUNCH_CHECK();
+    // the tour from the root covers every arc exactly when the edges form one tree
+    int32_t h_tour[2] = {0, 0};
+    HIP_CHECK(hipMemcpyAsync(&h_tour[0], tr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&h_tour[1], P.aoff + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     hipLaunchKernelGGL(k_sum_lengths, dim3(1), dim3(1024), 0, s, length, n, P.wsum);
     LAUNCH_CHECK();
-    ISO_REQUIRE(h_seen == n, ISO_ERR_INTERNAL, "tree BFS reached %d of %lld vertices", h_seen, (long long)n);
+    HIP_CHECK(hipStreamSynchronize(s));
+    ISO_REQUIRE(h_tour[1] > 0 && (int64_t)h_tour[0] == narcs, ISO_ERR_INTERNAL,
+                "the rooting tour covers %d of %lld arcs (root degree %d)", h_tour[0], (long long)narcs, h_tour[1]);
     whole.stop(s);
     if (timed) {
         timing().mst_calls += 1;
