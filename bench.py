@@ -344,6 +344,8 @@ def main():
     ap.add_argument("--recheck", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="smaller n of the same recipe (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-prune", action="store_true",
+                    help="screen every tile pair (no bounding-ball test); the tree is the same")
     ap.add_argument("--paper-prim-n", type=int, default=20000, metavar="M",
                     help="time the paper's Prim MST against this path's MST on an M-point sample (0: skip)")
     ap.add_argument("--all-k", type=int, default=10, metavar="K",
@@ -400,8 +402,10 @@ def main():
         log("calibration copy: %d bytes read, %d bytes written" % (src.numel() * 4, dst.numel() * 4))
         del src, dst
 
+    prune = not args.no_prune
+
     def step():
-        return iso.cluster(X, k, precision=args.precision, recheck=args.recheck)
+        return iso.cluster(X, k, precision=args.precision, recheck=args.recheck, prune=prune)
 
     for w in range(args.warmup):
         log("warmup %d" % w)
@@ -462,25 +466,29 @@ def main():
                    "candidates": info["mst"]["candidates"],
                    "rescanned_rows": info["mst"]["rescanned_rows"], "bisection_iters": info["sub"]["iters"],
                    "passes": info["sub"]["passes"], "max_depth": info["sub"]["max_depth"],
-                   "i_k": ik, "mst_weight": info["mst"]["mst_weight"]},
+                   "i_k": ik, "mst_weight": info["mst"]["mst_weight"],
+                   "prune": prune, "tile_pairs": info["mst"]["tile_pairs"],
+                   "tile_pairs_full": info["mst"]["tile_pairs_full"]},
     }
     if not args.no_compare:
         # the same step with other screen precisions (FP32: the reference
         # precision; INT8: exact integer Gram tiles, for 8-bit data like this
         # workload's q/256 coordinates), one warm-up + one step each
         out["compare"] = []
-        for prec in ("fp32", "int8"):
-            if prec == args.precision:
-                continue
-            log("comparison: %s screen, 1 warm-up + 1 step" % prec)
-            iso.cluster(X, k, precision=prec, recheck=args.recheck)
+        runs = [(prec, prune) for prec in ("fp32", "int8") if prec != args.precision]
+        runs.append((args.precision, not prune))  # the same screen with the other pruning setting
+        runs.append(("fp32", False))              # plain FP32, every tile pair
+        for prec, pr in runs:
+            log("comparison: %s screen%s, 1 warm-up + 1 step" % (prec, "" if pr else ", every tile pair"))
+            iso.cluster(X, k, precision=prec, recheck=args.recheck, prune=pr)
             torch.cuda.synchronize()
             c0 = time.perf_counter()
-            labc, ikc, infoc = iso.cluster(X, k, precision=prec, recheck=args.recheck)
+            labc, ikc, infoc = iso.cluster(X, k, precision=prec, recheck=args.recheck, prune=pr)
             torch.cuda.synchronize()
             c1 = time.perf_counter()
-            out["compare"].append({"screen": prec, "value": n / (c1 - c0), "ms_per_step": (c1 - c0) * 1e3,
-                                   "value_ratio": value / (n / (c1 - c0)),
+            out["compare"].append({"screen": prec, "prune": pr, "value": n / (c1 - c0),
+                                   "ms_per_step": (c1 - c0) * 1e3, "value_ratio": value / (n / (c1 - c0)),
+                                   "tile_pairs": infoc["mst"]["tile_pairs"],
                                    "same_tree": bool(torch.equal(infoc["parent"], info["parent"])),
                                    "same_labels": bool(torch.equal(labc, labels)), "i_k": ikc})
     if args.paper_prim_n > 0:

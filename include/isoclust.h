@@ -87,6 +87,9 @@ typedef int32_t iso_status;
                                    separable bound against the largest norm
                                    (chosen by itself when the points' norms are
                                    heavy tailed; every round is then screened) */
+#define ISO_MST_NO_PRUNE 0x10   /* screen every tile pair of a round, also those
+                                   whose bounding balls prove them too far
+                                   apart to matter                           */
 
 /* Vertex weight omega (eq. 2.2) and flow phi (eq. 2.1) readings. */
 #define ISO_OMEGA_TREE 0   /* omega(v) = sum of phi over v's tree edges         */
@@ -113,6 +116,9 @@ typedef struct {
                                 requested one, or ISO_PREC_FP32 when its error
                                 bound was too loose for the data (escalation)   */
     int32_t pair_bounds;     /* 1 when that screen used per-pair bounds        */
+    int64_t tile_pairs;      /* 256 x 256 tile pairs screened (all rounds)     */
+    int64_t tile_pairs_full; /* tile pairs the same rounds would screen without
+                                the bounding-ball test (ISO_MST_NO_PRUNE)      */
 } iso_mst_info;
 
 /* Device bytes iso_mst needs as workspace for n points in d dimensions (room
@@ -127,7 +133,11 @@ iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_
  * round may be decided by the neighbour lists the second round's screen
  * builds, and once at most 64 components remain one final round joins them
  * all (both are switched off by ISO_MST_NO_LISTS / ISO_MST_NO_FINAL in
- * `flags`; the tree does not change).
+ * `flags`; the tree does not change).  Points are ordered into tiles of nearby
+ * points, and a pair of tiles whose bounding balls are farther apart than any
+ * of their points' current lightest-edge bound is not screened (the
+ * bounding-ball test of dual-tree Boruvka; ISO_MST_NO_PRUNE turns it off; the
+ * tree does not change).
  *   X       [n*ld] FP32 points (read only).
  *   precision  ISO_PREC_* of the screen;  recheck  ISO_RECHECK_* (edge order);
  *   flags   OR of ISO_MST_NO_* bits, or 0.

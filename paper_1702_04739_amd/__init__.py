@@ -41,7 +41,7 @@ def version() -> str:
 
 
 def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = True, final_round: bool = True,
-        escalate: bool = True, pair_bounds: bool = False):
+        escalate: bool = True, pair_bounds: bool = False, prune: bool = True):
     """Euclidean minimum spanning tree of the rows of ``points`` (n x d, float32, GPU).
 
     Returns (parent int32[n] rooted at 0 with parent[0] = -1, length float64[n]
@@ -54,7 +54,10 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     whose error bound is too loose for the data hand over to the FP32 screen
     (``info["screen_precision"]`` tells which one built the tree).
     ``pair_bounds`` makes a BF16 screen use each pair's own error bound in its
-    capture thresholds (it does so by itself when the norms are heavy tailed)."""
+    capture thresholds (it does so by itself when the norms are heavy tailed).
+    ``prune`` lets a round skip the tile pairs whose bounding balls are too far
+    apart to hold a needed pair (``info["tile_pairs"]`` of
+    ``info["tile_pairs_full"]`` are screened); the tree is the same either way."""
     torch = _torch()
     _require_cuda(points, "points", torch.float32)
     if points.dim() != 2:
@@ -72,7 +75,8 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
     length = torch.empty(n, dtype=torch.float64, device=dev)
     info = _lib.MstInfo()
     flags = ((0 if lists else _lib.MST_NO_LISTS) | (0 if final_round else _lib.MST_NO_FINAL)
-             | (0 if escalate else _lib.MST_NO_ESCALATE) | (_lib.MST_PAIR_BOUNDS if pair_bounds else 0))
+             | (0 if escalate else _lib.MST_NO_ESCALATE) | (_lib.MST_PAIR_BOUNDS if pair_bounds else 0)
+             | (0 if prune else _lib.MST_NO_PRUNE))
     rc = lib.iso_mst(ctypes.c_void_p(points.data_ptr()), n, d, ld, _lib.PRECISION[precision], _lib.RECHECK[recheck],
                      flags,
                      ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(length.data_ptr()), ctypes.byref(info),
@@ -82,7 +86,8 @@ def mst(points, precision: str = "fp32", recheck: str = "fp32", lists: bool = Tr
                             "rescanned_rows": info.rescanned_rows, "mst_weight": info.mst_weight,
                             "final_components": info.final_components,
                             "screen_precision": {v: k for k, v in _lib.PRECISION.items()}[info.screen_precision],
-                            "pair_bounds": bool(info.pair_bounds)}
+                            "pair_bounds": bool(info.pair_bounds), "tile_pairs": info.tile_pairs,
+                            "tile_pairs_full": info.tile_pairs_full}
 
 
 def mst_prim(points, return_order: bool = False):
@@ -233,11 +238,11 @@ def subpartition_all_k(parent, length, kmax: int, sigma: float | None = None, ro
 
 
 def cluster(points, k: int, sigma: float | None = None, precision: str = "fp32", recheck: str = "fp32",
-            omega: str = "tree", alpha: float = 0.0, **kw):
+            omega: str = "tree", alpha: float = 0.0, prune: bool = True, **kw):
     """MST followed by the optimal k-subpartition (the paper's full hot path).
     ``omega="full"`` and/or ``alpha > 0`` use the full-graph weights of
-    eqs. 2.2 and 2.3 (O(n^2 d) extra work)."""
-    parent, length, minfo = mst(points, precision=precision, recheck=recheck)
+    eqs. 2.2 and 2.3 (O(n^2 d) extra work); ``prune`` as in ``mst``."""
+    parent, length, minfo = mst(points, precision=precision, recheck=recheck, prune=prune)
     om0 = p0 = None
     if omega == "full" or alpha > 0.0:
         if not sigma:

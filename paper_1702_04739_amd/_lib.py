@@ -23,6 +23,7 @@ MST_NO_LISTS = 0x1
 MST_NO_FINAL = 0x2
 MST_NO_ESCALATE = 0x4
 MST_PAIR_BOUNDS = 0x8
+MST_NO_PRUNE = 0x10
 OMEGA = {"tree": 0, "full": 1}
 PHI = {"exp": 0, "gauss_sq": 1}
 BRACKET = {"pow2": 0, "paper": 1}
@@ -44,7 +45,8 @@ class MstInfo(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("list_rounds", ctypes.c_int32), ("candidates", ctypes.c_int64),
                 ("rescanned_rows", ctypes.c_int64), ("mst_weight", ctypes.c_double),
                 ("final_components", ctypes.c_int32), ("screen_precision", ctypes.c_int32),
-                ("pair_bounds", ctypes.c_int32)]
+                ("pair_bounds", ctypes.c_int32), ("tile_pairs", ctypes.c_int64),
+                ("tile_pairs_full", ctypes.c_int64)]
 
 
 class SubOpts(ctypes.Structure):

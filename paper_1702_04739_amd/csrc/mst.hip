@@ -21,12 +21,14 @@
 //   hook/jump : each component hooks onto the component across its edge;
 //               mutual pairs keep the smaller id as root; pointer jumping;
 //   relabel   : compact component ids by an exclusive scan.
-// After the last round: FP64 edge lengths and a BFS from vertex 0 give the
-// parent list (Sec. 3.3) rooted at 0.
+// After the last round: FP64 edge lengths, and an Euler tour of the tree whose
+// first-taken arcs give the parent list (Sec. 3.3) rooted at vertex 0.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "screen.hpp"
@@ -45,7 +47,7 @@ enum Counter : int {
     C_NONFINITE = 2,    // nonfinite coordinate seen
     C_OVF = 3,          // overflow rows this round
     C_NOEDGE = 4,       // a component without an outgoing edge (internal error)
-    C_SEEN = 5,         // vertices reached by the rooting BFS
+    // 5 unused
     C_GATHER = 6,       // rows queued for the gathered pass this round
     C_FORCE = 7,        // rows the neighbour lists leave undecided this round
     C_CAND = 8,         // candidates re-evaluated (int64 at [8..9])
@@ -53,7 +55,9 @@ enum Counter : int {
     C_SUMSQ = 12,       // sum over components of size^2 (int64 at [12..13], timing only)
     C_I8BAD = 14,       // the points are not 8-bit integers on a common grid (INT8 screen)
     C_FRWORK = 16,      // final round: candidates its recheck would evaluate (int64 at [16..17])
-    C_COUNT = 18
+    C_PAIRS = 18,       // point pairs of the screened tile pairs (int64 at [18..19], pruned rounds)
+    C_TPFULL = 20,      // tile pairs a full screen would run (pruned rounds)
+    C_COUNT = 21
 };
 
 // ------------------------------------------------------------------ small kernels
@@ -1125,17 +1129,48 @@ __global__ void k_tile_ranges(const int32_t *__restrict__ perm, const int32_t *_
 // mask (keep_m) when it is diagonal or its tiles share a component, else
 // without it (keep_u).  The order is sorted by component and pr.x <= pr.y, so
 // the tiles share a component exactly when the greatest of the first reaches
-// the least of the second.
+// the least of the second.  Pruned rounds (phase 1 and 2, see the tile-pair
+// pruning above) keep in phase 1 the pairs whose balls meet (plb = 0) and in
+// phase 2 those with 0 < plb <= the larger reach of their tiles; they count
+// the tile pairs a full screen would run (phase 1, C_TPFULL) and the point
+// pairs of the kept ones (C_PAIRS: cnt_I cnt_J off the diagonal; on it
+// cnt (cnt - 1) / 2 when diag_all, i.e. every point its own component, else 0,
+// since a diagonal tile's pairs within one component are not counted).
 __global__ void k_pair_keep(const int2 *__restrict__ pairs, int64_t npairs, const int32_t *__restrict__ tlo,
-                            const int32_t *__restrict__ thi, int32_t *__restrict__ keep_m,
-                            int32_t *__restrict__ keep_u) {
+                            const int32_t *__restrict__ thi, const float *__restrict__ plb,
+                            const float *__restrict__ tthr, const int32_t *__restrict__ tcnt, int phase,
+                            int diag_all, int32_t *__restrict__ keep_m, int32_t *__restrict__ keep_u,
+                            int32_t *__restrict__ counters) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= npairs) return;
-    const int2 pr = pairs[k];
-    const bool one = tlo[pr.x] == thi[pr.x] && tlo[pr.y] == thi[pr.y] && tlo[pr.x] == tlo[pr.y];
-    const bool masked = pr.x == pr.y || thi[pr.x] >= tlo[pr.y];
-    keep_m[k] = !one && masked ? 1 : 0;
-    keep_u[k] = !one && !masked ? 1 : 0;
+    bool full = false;
+    unsigned long long np = 0;
+    if (k < npairs) {
+        const int2 pr = pairs[k];
+        const bool one = tlo[pr.x] == thi[pr.x] && tlo[pr.y] == thi[pr.y] && tlo[pr.x] == tlo[pr.y];
+        const bool masked = pr.x == pr.y || thi[pr.x] >= tlo[pr.y];
+        bool sel = !one;
+        full = sel;
+        if (phase == 1) {
+            sel = sel && plb[k] <= 0.0f;
+        } else if (phase == 2) {
+            const float l = plb[k];
+            sel = sel && l > 0.0f && l <= fmaxf(tthr[pr.x], tthr[pr.y]);
+        }
+        keep_m[k] = sel && masked ? 1 : 0;
+        keep_u[k] = sel && !masked ? 1 : 0;
+        if (phase > 0 && sel) {
+            const unsigned long long a = (unsigned long long)tcnt[pr.x], b = (unsigned long long)tcnt[pr.y];
+            np = pr.x != pr.y ? (masked ? 0ull : a * b) : (diag_all && a > 0 ? a * (a - 1) / 2 : 0ull);
+        }
+    }
+    if (phase == 0) return;
+    const unsigned long long nfull = __popcll(__ballot(phase == 1 && full));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) np += __shfl_xor(np, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        if (np) atomicAdd(reinterpret_cast<unsigned long long *>(&counters[C_PAIRS]), np);
+        if (nfull) atomicAdd(&counters[C_TPFULL], (int32_t)nfull);
+    }
 }
 
 // Rows of the representation in the tile order, stored tile by tile and,
@@ -1240,6 +1275,267 @@ __global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, c
     if (keep_u[k]) out[pos_m[npairs] + pos_u[k]] = pairs[k];
 }
 
+// ------------------------------------------------------------------ tile-pair pruning
+//
+// A tile pair whose two point sets are provably farther apart than the reach of
+// every one of their points is not screened (the bounding-ball test of
+// dual-tree Boruvka, March, Ram and Gray, KDD 2010, on the screen's tiles).
+// With c_T the centroid of tile T's rows and rad_T >= max ||x - c_T|| over
+// them (exact FP32 inputs), the triangle inequality gives, for every i in I and
+// j in J, D(i, j) >= LB = ||c_I - c_J|| - rad_I - rad_J.  The reach of a point
+// bounds every value the round can still need from it:
+//   R_i = kappa (b_i + Emax_i) once its running minimum b_i is known: its
+//   lightest edge has a recheck value of at most (1 + rho) (b_i + Emax_i),
+//   while a pair with real distance >= LB has one of at least (1 - rho) LB^2;
+//   (with pair bounds R_i = kappa ub_i, ub_i the running upper bound);
+//   R_i may be lowered to U_c dn, c = comp(i), U_c the component's upper
+//   bound of its lightest outgoing edge (recheck scale): the round needs only
+//   that edge of every component (the pair, within its own row's reach, keeps
+//   the row's capture);
+//   in the round that builds neighbour lists R_i >= tau_i + Emax_i as well
+//   (a list takes the partners with Dhat^2 <= tau_i, and Dhat^2 >= D^2 - Emax_i).
+// A tile pair with LB^2 > max R over both tiles then holds no edge the round
+// selects and no list entry, so every component's lightest edge, the lists
+// and the tree are those of the full screen (a row whose own lightest edge
+// lies beyond its component's U may keep a larger running minimum, which only
+// bounds its own candidates).
+// Each round screens first the tile pairs whose balls meet (LB = 0), then,
+// with the reach known, the other pairs that the bound cannot exclude.  Tiles
+// group nearby points: the first round orders the points by their nearest of
+// PIV pivot rows (the pivots in a nearest-neighbour chain), and the component
+// labels follow that order, so every later round's component order stays
+// spatial.  The final round applies the same bound per pair of components
+// (see run_mst).
+
+constexpr int PIV = 64;              // pivot rows of the first round's order
+constexpr int PRUNE_MIN_TILES = 4;   // fewer tiles: every pair is screened
+constexpr int64_t PRUNE_MAX_D = 8192;  // the tile centroid is held in LDS
+
+// Nearest pivot of each of `count` rows (row rows[r], or r when rows is null),
+// by FP32 sums of squared differences; 64 rows x 64 pivots per workgroup, 64
+// coordinates at a time through LDS; ties go to the smaller pivot index.
+// dist (nullable) receives the PIV squared distances of every row.
+__global__ __launch_bounds__(256) void k_pivot_near(const float *__restrict__ X, int64_t d, int64_t ld,
+                                                    const int32_t *__restrict__ rows, int64_t count,
+                                                    const int32_t *__restrict__ piv, uint32_t *__restrict__ key,
+                                                    float *__restrict__ dist) {
+    static_assert(PIV == 64, "one pivot per LDS row of the tile");
+    __shared__ float sx[64][65];
+    __shared__ float sp[PIV][65];
+    const int tid = threadIdx.x, tr = tid >> 4, tp = tid & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    float acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < d; k0 += 64) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int idx = tid + 256 * e, r = idx >> 6, c = idx & 63;
+            const int64_t k = k0 + c, g = r0 + r;
+            float v = 0.0f, w = 0.0f;
+            if (k < d) {
+                if (g < count) v = X[(rows ? (int64_t)rows[g] : g) * ld + k];
+                w = X[(int64_t)piv[r] * ld + k];
+            }
+            sx[r][c] = v;
+            sp[r][c] = w;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int c = 0; c < 64; ++c) {
+            float xa[4], pb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) xa[a] = sx[4 * tr + a][c];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) pb[b] = sp[4 * tp + b][c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float t = xa[a] - pb[b];
+                    acc[a][b] = fmaf(t, t, acc[a][b]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t g = r0 + 4 * tr + a;
+        float best = acc[a][0];
+        int bi = 4 * tp;
+#pragma unroll
+        for (int b = 1; b < 4; ++b)
+            if (acc[a][b] < best) {
+                best = acc[a][b];
+                bi = 4 * tp + b;
+            }
+        // the 16 lanes of one row group differ in their low four bits
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const float ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob < best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (g < count) {
+            if (tp == 0) key[g] = (uint32_t)bi;
+            if (dist)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) dist[g * PIV + 4 * tp + b] = acc[a][b];
+        }
+    }
+}
+
+// Sort keys of the first round's order: the rank of the point's pivot in the chain.
+__global__ void k_pivot_keys(uint32_t *__restrict__ keys, const int32_t *__restrict__ rank, int64_t n,
+                             int32_t *__restrict__ vals) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    keys[v] = (uint32_t)rank[keys[v]];
+    vals[v] = (int32_t)v;
+}
+
+// Component labels of the first round in the order's sequence: comp[order[p]] = p.
+__global__ void k_comp_from_order(const int32_t *__restrict__ order, int64_t n, int32_t *__restrict__ comp) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    comp[order[p]] = (int32_t)p;
+}
+
+// Ball of every tile of the order (GT positions each; ids >= n are padding):
+// cen = the centroid of its rows rounded to FP32, rad >= the largest distance
+// of a row from that stored centroid (FP64 sums, widened by their rounding
+// bound, rounded up), cnt = rows.  A tile without rows gets rad = -1.
+// Dynamic LDS: d floats.
+__global__ __launch_bounds__(256) void k_tile_ball(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                   const int32_t *__restrict__ order, float *__restrict__ cen,
+                                                   float *__restrict__ rad, int32_t *__restrict__ cnt) {
+    static_assert(GT == 256, "one position per thread");
+    extern __shared__ float cs[];
+    __shared__ int32_t rid[GT];
+    __shared__ double wmax[4];
+    const int tid = threadIdx.x;
+    const int64_t T = blockIdx.x;
+    const int32_t id = order[T * GT + tid];
+    rid[tid] = id < n ? id : -1;
+    const int nv = __syncthreads_count(id < n);
+    if (nv == 0) {
+        if (tid == 0) {
+            rad[T] = -1.0f;
+            cnt[T] = 0;
+        }
+        return;
+    }
+    for (int64_t k = tid; k < d; k += 256) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int r = 0; r < GT; r += 2) {
+            const int32_t v0 = rid[r], v1 = rid[r + 1];
+            if (v0 >= 0) s0 += (double)X[(int64_t)v0 * ld + k];
+            if (v1 >= 0) s1 += (double)X[(int64_t)v1 * ld + k];
+        }
+        const float c = (float)((s0 + s1) / (double)nv);
+        cs[k] = c;
+        cen[T * d + k] = c;
+    }
+    __syncthreads();
+    const int lane = tid & 63, w = tid >> 6;
+    double m = 0.0;
+    for (int r = w; r < GT; r += 4) {
+        const int32_t v = rid[r];
+        if (v < 0) continue;
+        const float *x = X + (int64_t)v * ld;
+        double s = 0.0;
+        for (int64_t k = lane; k < d; k += 64) {
+            const double t = (double)x[k] - (double)cs[k];
+            s = fma(t, t, s);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        m = fmax(m, s);
+    }
+    if (lane == 0) wmax[w] = m;
+    __syncthreads();
+    if (tid == 0) {
+        const double mm = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        // recursive FP64 sums of d + 64 nonnegative terms: relative error below (d + 64) 2^-53
+        const double r = sqrt(mm) * (1.0 + (double)(d + 68) * 0x1p-52);
+        float f = (float)r;
+        if ((double)f < r) f = nextafterf(f, SCR_INF);
+        rad[T] = f;
+        cnt[T] = nv;
+    }
+}
+
+// LB^2 of every tile pair, rounded down to FP32: LB = ||c_I - c_J|| - rad_I -
+// rad_J (FP64, the distance narrowed and the radii widened by their rounding
+// bounds), 0 when the balls meet; NaN when a tile has no row (such a pair holds
+// no pair of points and is never screened).  One wave per pair.
+__global__ __launch_bounds__(256) void k_pair_lb(const int2 *__restrict__ pairs, int64_t npairs,
+                                                 const float *__restrict__ cen, const float *__restrict__ rad,
+                                                 int64_t d, float *__restrict__ plb) {
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= npairs) return;
+    const int2 pr = pairs[k];
+    const float rI = rad[pr.x], rJ = rad[pr.y];
+    if (rI < 0.0f || rJ < 0.0f || pr.x == pr.y) {
+        if (lane == 0) plb[k] = (rI < 0.0f || rJ < 0.0f) ? __builtin_nanf("") : 0.0f;
+        return;
+    }
+    const float *a = cen + (int64_t)pr.x * d, *b = cen + (int64_t)pr.y * d;
+    double s = 0.0;
+    for (int64_t t = lane; t < d; t += 64) {
+        const double u = (double)a[t] - (double)b[t];
+        s = fma(u, u, s);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+        const double dist = sqrt(s) * (1.0 - (double)(d + 68) * 0x1p-52);
+        const double lb = dist - ((double)rI + (double)rJ) * (1.0 + 0x1p-52);
+        float f = 0.0f;
+        if (lb > 0.0) {
+            const double l2 = lb * lb * (1.0 - 0x1p-50);
+            f = (float)l2;
+            if ((double)f > l2) f = nextafterf(f, 0.0f);
+        }
+        plb[k] = f;
+    }
+}
+
+// Reach of every tile: the largest R over its points (padding, comp < 0,
+// excluded); -inf for a tile without points.  A point's reach is also capped
+// by its component's U (comp_ub, recheck scale; an unset U is NaN and caps
+// nothing): Boruvka needs only each component's lightest outgoing edge, whose
+// recheck value is at most U, and a pair with real distance >= LB has a
+// recheck value of at least (1 - rho) LB^2.  pub (pair bounds) and pltau (the
+// round that builds lists) are nullable.  One wave per tile.
+__global__ __launch_bounds__(256) void k_tile_reach(const float *__restrict__ pbest, const float *__restrict__ pEmax,
+                                                    const float *__restrict__ pub, const float *__restrict__ pltau,
+                                                    const int32_t *__restrict__ pcomp,
+                                                    const uint32_t *__restrict__ comp_ub, int64_t ntiles, float kappa,
+                                                    float dn, float *__restrict__ tthr) {
+    const int64_t T = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (T >= ntiles) return;
+    float m = -SCR_INF;
+    for (int q = lane; q < GT; q += 64) {
+        const int64_t pos = T * GT + q;
+        const int32_t c = pcomp[pos];
+        if (c < 0) continue;
+        float r = pub ? pub[pos] * kappa : (pbest[pos] + pEmax[pos]) * kappa;
+        r = fminf(r, __uint_as_float(comp_ub[c]) * dn);
+        if (pltau) {
+            const float tau = pltau[pos];
+            if (tau >= 0.0f) r = fmaxf(r, (tau + pEmax[pos]) * THR_UP);
+        }
+        m = fmaxf(m, r);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (lane == 0) tthr[T] = m;
+}
+
 // ------------------------------------------------------------------ plan
 
 size_t rep_bytes(int32_t precision) {
@@ -1280,6 +1576,10 @@ struct MstPlan {
     double *rowd;
     unsigned long long *W1, *W2;
     uint32_t *upair;
+    // tile-pair pruning: tile balls and reach, LB^2 per tile pair, pivots
+    float *cen, *rad, *tthr, *plb, *pivd;
+    int32_t *tcnt, *piv, *piv_rank;
+    int2 *pairsF2;                  // the final round's tile pairs of one phase
     double *rb_d2, *elen, *wsum;
     unsigned long long *ck1, *ck2;
     int32_t *counters;
@@ -1384,6 +1684,19 @@ struct MstPlan {
         W1 = a.take<unsigned long long>(FR_KC * FR_KC);
         W2 = a.take<unsigned long long>(FR_KC * FR_KC);
         upair = a.take<uint32_t>(FR_KC * FR_KC);
+        {
+            const int64_t ntb = std::max<int64_t>(nt, ntF_cap);
+            const int64_t nfp = ntF_cap * (ntF_cap - 1) / 2;
+            cen = a.take<float>((size_t)ntb * (size_t)std::min<int64_t>(d, PRUNE_MAX_D));
+            rad = a.take<float>(ntb);
+            tcnt = a.take<int32_t>(ntb);
+            tthr = a.take<float>(ntb);
+            plb = a.take<float>(std::max<int64_t>(npairs, nfp));
+            pairsF2 = a.take<int2>(nfp);
+            piv = a.take<int32_t>(PIV);
+            piv_rank = a.take<int32_t>(PIV);
+            pivd = a.take<float>(PIV * PIV);
+        }
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
     // they are sized for all rows (rows are gathered at most once per round).
@@ -1431,6 +1744,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     whole.start(s);
     *escalate = false;
     const bool may_escalate = rep != ISO_PREC_FP32 && !(P.options & ISO_MST_NO_ESCALATE);
+    const bool prune = !(P.options & ISO_MST_NO_PRUNE) && P.nt >= PRUNE_MIN_TILES && d <= PRUNE_MAX_D;
+    int64_t tp_run = 0, tp_full = 0;  // tile pairs screened, and those full screens would have run
     auto give_up = [&]() {
         whole.stop(s);
         if (timed) timing().mst_ms += whole.elapsed_ms();
@@ -1588,6 +1903,38 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     }
     hipLaunchKernelGGL(k_perm_identity, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad);
     LAUNCH_CHECK();
+    std::vector<int32_t> h_piv(PIV), h_rank(PIV, -1);
+    if (prune) {
+        // The first round's order: the points by their nearest pivot (rows
+        // q n / PIV), the pivots in a nearest-neighbour chain from the first;
+        // component labels follow the order.
+        for (int q = 0; q < PIV; ++q) h_piv[q] = (int32_t)((int64_t)q * n / PIV);
+        HIP_CHECK(hipMemcpyAsync(P.piv, h_piv.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_pivot_near, dim3(1), dim3(256), 0, s, X, d, ld, P.piv, (int64_t)PIV, P.piv, P.pkeys,
+                           P.pivd);
+        LAUNCH_CHECK();
+        std::vector<float> pd((size_t)PIV * PIV);
+        HIP_CHECK(hipMemcpyAsync(pd.data(), P.pivd, sizeof(float) * pd.size(), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        int cur = 0;
+        h_rank[0] = 0;
+        for (int q = 1; q < PIV; ++q) {
+            int nx = -1;
+            for (int c = 0; c < PIV; ++c)
+                if (h_rank[c] < 0 && (nx < 0 || pd[(size_t)cur * PIV + c] < pd[(size_t)cur * PIV + nx])) nx = c;
+            h_rank[nx] = q;
+            cur = nx;
+        }
+        HIP_CHECK(hipMemcpyAsync(P.piv_rank, h_rank.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_pivot_near, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, X, d, ld,
+                           static_cast<const int32_t *>(nullptr), n, P.piv, P.pkeys, static_cast<float *>(nullptr));
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_pivot_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.pkeys, P.piv_rank, n, P.perm);
+        LAUNCH_CHECK();
+        radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, 6, P.psort, s);
+        hipLaunchKernelGGL(k_comp_from_order, dim3(grid_for(n, 256)), dim3(256), 0, s, P.perm, n, P.comp);
+        LAUNCH_CHECK();
+    }
     // The tile-pair screen reads its own copy of the representation (Xq), in
     // the tile order and chunk-major within each tile (the final round
     // overwrites it with its own order; every later plain round copies it again).
@@ -1636,6 +1983,38 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                            P.trmax, P.temax);
         LAUNCH_CHECK();
     };
+
+    // Tile balls of the order (ntiles tiles) and LB^2 of the tile pairs `pairs`.
+    auto tile_bounds = [&](const int32_t *order, int64_t ntiles, const int2 *pairs, int64_t npr) {
+        hipLaunchKernelGGL(k_tile_ball, dim3((unsigned)ntiles), dim3(256), (size_t)d * sizeof(float), s, X, n, d, ld,
+                           order, P.cen, P.rad, P.tcnt);
+        LAUNCH_CHECK();
+        if (npr > 0) {
+            hipLaunchKernelGGL(k_pair_lb, dim3(grid_for(npr, 4)), dim3(256), 0, s, pairs, npr, P.cen, P.rad, d, P.plb);
+            LAUNCH_CHECK();
+        }
+    };
+    // The plain rounds' tile pairs of one phase (0: every pair that is not
+    // inside one component; 1, 2: the pruned phases) into pairs_r, masked ones
+    // first: returns (masked, unmasked) counts.
+    auto compact = [&](int phase, bool diag_all) -> std::pair<int64_t, int64_t> {
+        hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.tlo,
+                           P.thi, P.plb, P.tthr, P.tcnt, phase, diag_all ? 1 : 0, P.keep, P.keepu, P.counters);
+        LAUNCH_CHECK();
+        exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, P.scan_scratch, s);
+        exclusive_scan_i32(P.keepu, P.kposu, P.npairs, P.kposu + P.npairs, P.scan_scratch, s);
+        hipLaunchKernelGGL(k_pair_scatter, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.keep,
+                           P.kpos, P.keepu, P.kposu, P.pairs_r);
+        LAUNCH_CHECK();
+        int32_t hk[2] = {0, 0};
+        HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&hk[1], P.kposu + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        ISO_REQUIRE(hk[0] >= 0 && hk[1] >= 0 && hk[0] + hk[1] <= P.npairs, ISO_ERR_INTERNAL, "tile-pair compaction");
+        return {(int64_t)hk[0], (int64_t)hk[1]};
+    };
+    EventPair scr2(timed);
+    double fr_pairs = 0.0;  // point pairs the pruned final round screened
 
     // The final round (at most FR_KC components left): true when it joined
     // them all, false when a point's candidate list overflowed (the round is
@@ -1698,9 +2077,87 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         fill<uint32_t>(reinterpret_cast<uint32_t *>(P.bestc), 0x7F800000u, (int64_t)K * bstride, s);
         fill<uint32_t>(P.upair, 0x7F800000u, FR_KC * FR_KC, s);
         fill<int32_t>(P.ccnt, 0, n, s);
-        scr.start(s);
-        launch_screen_pairs(FA, P.pairsF, 0, (int64_t)fpairs.size(), s);
-        scr.stop(s);
+        const int64_t nF = (int64_t)fpairs.size();
+        const bool fr_pruned = prune && nF > 0;
+        if (fr_pruned) {
+            // Pruned per pair of components (a, b): the first phase screens the
+            // tile pairs whose balls meet and, for every pair of components,
+            // its tile pair of least LB, which gives every U(a, b); B(a, b) =
+            // the least over paths from a to b of the largest U on the path
+            // (U closed under the bottleneck path).  An edge of the contracted
+            // MST between a and b weighs at most B(a, b) (it is the lightest
+            // bottleneck link), so a tile pair with (1 - rho) LB^2 > B(a, b)
+            // holds none; the second phase screens the others.  The recheck
+            // then gives every MST edge exactly, and every other pair of
+            // components at most a heavier edge, which Kruskal leaves out.
+            tile_bounds(P.permF, ntF, P.pairsF, nF);
+            std::vector<float> hl(nF);
+            HIP_CHECK(hipMemcpyAsync(hl.data(), P.plb, sizeof(float) * nF, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            std::vector<int32_t> tcn(ntF);  // rows per tile (a component's last tile is partly padding)
+            for (int64_t t = 0; t < ntF; ++t)
+                tcn[t] = (int32_t)std::min<int64_t>(GT, (int64_t)hs[tco[t]] - (t * GT - pst[tco[t]]));
+            auto lbv = [&](int64_t k) { return std::isnan(hl[k]) ? SCR_INF : hl[k]; };
+            auto cpair = [&](int64_t k) { return fr_pair(tco[fpairs[k].x], tco[fpairs[k].y]); };
+            std::vector<int64_t> bestk(FR_KC * FR_KC, -1);
+            for (int64_t k = 0; k < nF; ++k) {
+                int64_t &b = bestk[cpair(k)];
+                if (b < 0 || lbv(k) < lbv(b)) b = k;
+            }
+            std::vector<char> sel1(nF, 0);
+            std::vector<int2> lst;
+            for (int64_t k = 0; k < nF; ++k)
+                if (hl[k] <= 0.0f || bestk[cpair(k)] == k) {
+                    sel1[k] = 1;
+                    lst.push_back(fpairs[k]);
+                    fr_pairs += (double)tcn[fpairs[k].x] * (double)tcn[fpairs[k].y];
+                }
+            const int64_t n1 = (int64_t)lst.size();
+            if (n1 > 0)
+                HIP_CHECK(hipMemcpyAsync(P.pairsF2, lst.data(), sizeof(int2) * n1, hipMemcpyHostToDevice, s));
+            scr.start(s);
+            launch_screen_pairs(FA, P.pairsF2, 0, n1, s);
+            scr.stop(s);
+            std::vector<uint32_t> hu(FR_KC * FR_KC);
+            HIP_CHECK(hipMemcpyAsync(hu.data(), P.upair, sizeof(uint32_t) * hu.size(), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            std::vector<float> B((size_t)K * K);
+            for (int a = 0; a < K; ++a)
+                for (int b = 0; b < K; ++b) {
+                    float u = 0.0f;
+                    if (a != b) std::memcpy(&u, &hu[fr_pair(a, b)], sizeof(float));
+                    B[(size_t)a * K + b] = u;
+                }
+            for (int m = 0; m < K; ++m)
+                for (int a = 0; a < K; ++a)
+                    for (int b = 0; b < K; ++b)
+                        B[(size_t)a * K + b] =
+                            std::min(B[(size_t)a * K + b], std::max(B[(size_t)a * K + m], B[(size_t)m * K + b]));
+            lst.clear();
+            for (int64_t k = 0; k < nF; ++k) {
+                if (sel1[k] || std::isnan(hl[k])) continue;
+                const int a = tco[fpairs[k].x], b = tco[fpairs[k].y];
+                if (hl[k] <= B[(size_t)a * K + b] * dn) {
+                    lst.push_back(fpairs[k]);
+                    fr_pairs += (double)tcn[fpairs[k].x] * (double)tcn[fpairs[k].y];
+                }
+            }
+            const int64_t n2 = (int64_t)lst.size();
+            if (n2 > 0)
+                HIP_CHECK(hipMemcpyAsync(P.pairsF2, lst.data(), sizeof(int2) * n2, hipMemcpyHostToDevice, s));
+            scr2.start(s);
+            launch_screen_pairs(FA, P.pairsF2, 0, n2, s);
+            scr2.stop(s);
+            HIP_CHECK(hipStreamSynchronize(s));  // (lst is the source of the copy above)
+            tp_run += n1 + n2;
+            tp_full += nF;
+        } else {
+            scr.start(s);
+            launch_screen_pairs(FA, P.pairsF, 0, nF, s);
+            scr.stop(s);
+            tp_run += nF;
+            tp_full += nF;
+        }
         // the recheck runs only when its work is modest: no overflowed list
         // and at most FR_EVAL_PER_POINT candidates per point on average (with
         // a loose screen bound, e.g. FP8 at large d, the plain rounds are cheaper)
@@ -1720,8 +2177,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 memcpy(&sumsq, &hc[C_SUMSQ], sizeof(sumsq));
                 iso_timing &T = timing();
                 T.screen_launches += 1;
-                T.screen_ms += scr.elapsed_ms();
-                T.screen_pairs += 0.5 * ((double)n * (double)n - (double)sumsq);
+                T.screen_ms += scr.elapsed_ms() + (fr_pruned ? scr2.elapsed_ms() : 0.0);
+                if (!prune) T.screen_pairs += 0.5 * ((double)n * (double)n - (double)sumsq);
                 T.screen_dim = (double)P.d_pad;
             }
             if (hc[C_OVF] > 0 || (double)work > FR_EVAL_PER_POINT * (double)n) return false;
@@ -1845,26 +2302,27 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 LAUNCH_CHECK();
                 radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, kb, P.psort, s);
                 tile_copy(P.perm, P.n_pad);
+            }
+            if (rounds > 1 || prune) {
                 hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(P.nt, 256)), dim3(256), 0, s, P.perm, P.comp, n, P.nt,
                                    pair_tile(), P.tlo, P.thi);
                 LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs, P.tlo,
-                                   P.thi, P.keep, P.keepu);
-                LAUNCH_CHECK();
-                exclusive_scan_i32(P.keep, P.kpos, P.npairs, P.kpos + P.npairs, P.scan_scratch, s);
-                exclusive_scan_i32(P.keepu, P.kposu, P.npairs, P.kposu + P.npairs, P.scan_scratch, s);
-                hipLaunchKernelGGL(k_pair_scatter, dim3(grid_for(P.npairs, 256)), dim3(256), 0, s, P.pairs, P.npairs,
-                                   P.keep, P.kpos, P.keepu, P.kposu, P.pairs_r);
-                LAUNCH_CHECK();
-                int32_t hk[2] = {0, 0};
-                HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipMemcpyAsync(&hk[1], P.kposu + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipStreamSynchronize(s));
-                ISO_REQUIRE(hk[0] >= 0 && hk[1] >= 0 && hk[0] + hk[1] <= P.npairs, ISO_ERR_INTERNAL,
-                            "tile-pair compaction");
+                if (prune) {
+                    tile_bounds(P.perm, P.nt, P.pairs, P.npairs);
+                    fill<int32_t>(P.counters + C_TPFULL, 0, 1, s);
+                }
+                std::tie(nmask, noff) = compact(prune ? 1 : 0, rounds == 1);
                 pairs_use = P.pairs_r;
-                nmask = hk[0];
-                noff = hk[1];
+            }
+            if (!prune) {
+                tp_run += nmask + noff;
+                tp_full += nmask + noff;
+            } else {
+                tp_run += nmask + noff;
+                int32_t hf = 0;
+                HIP_CHECK(hipMemcpyAsync(&hf, P.counters + C_TPFULL, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipStreamSynchronize(s));
+                tp_full += hf;
             }
             if (lists == LISTS_NONE && rounds == 2) {
                 // the second round's screen builds the lists from the first
@@ -1888,6 +2346,31 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             scr.start(s);
             launch_screen_pairs(SA, pairs_use, nmask, noff, s);
             scr.stop(s);
+            if (prune) {
+                // the second phase: the reach of every tile from the minima so
+                // far, then the pairs whose bound does not exclude them
+                hipLaunchKernelGGL(k_pos_scatter, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, n,
+                                   P.pbest, P.best);
+                LAUNCH_CHECK();
+                if (ubp) {
+                    hipLaunchKernelGGL(k_pos_scatter, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad,
+                                       n, P.pub, ubp);
+                    LAUNCH_CHECK();
+                }
+                fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
+                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
+                                   up, P.comp_ub);
+                LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_tile_reach, dim3(grid_for(P.nt, 4)), dim3(256), 0, s, P.pbest, P.pEmax,
+                                   ubp ? P.pub : nullptr, SA.lcnt ? P.pltau : nullptr, P.pcomp, P.comp_ub, P.nt,
+                                   kappa, dn, P.tthr);
+                LAUNCH_CHECK();
+                const std::pair<int64_t, int64_t> c2 = compact(2, rounds == 1);
+                tp_run += c2.first + c2.second;
+                scr2.start(s);
+                launch_screen_pairs(SA, P.pairs_r, c2.first, c2.second, s);
+                scr2.stop(s);
+            }
             hipLaunchKernelGGL(k_pos_scatter, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, n, P.pbest,
                                P.best);
             LAUNCH_CHECK();
@@ -1922,7 +2405,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         if (timed && !list_round) {
             iso_timing &T = timing();
             T.screen_launches += 1;
-            T.screen_ms += scr.elapsed_ms();
+            T.screen_ms += scr.elapsed_ms() + (prune ? scr2.elapsed_ms() : 0.0);
         }
         // (with pair bounds an overflowing list reflects the loose early
         // thresholds of the screen, not a loose bound: the gathered pass settles
@@ -1997,7 +2480,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         ISO_REQUIRE(h[C_NOEDGE] == 0, ISO_ERR_INTERNAL, "a component found no outgoing edge in round %d", rounds);
         ISO_REQUIRE(h[C_NCOMP] >= 1 && h[C_NCOMP] < ncomp, ISO_ERR_INTERNAL,
                     "Boruvka round %d did not contract (%lld -> %d components)", rounds, (long long)ncomp, h[C_NCOMP]);
-        if (timed && !list_round) {
+        if (timed && !list_round && !prune) {
             unsigned long long sumsq = 0;
             memcpy(&sumsq, &h[C_SUMSQ], sizeof(sumsq));
             iso_timing &T = timing();
@@ -2007,6 +2490,13 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         ncomp = h[C_NCOMP];
     }
 
+    if (timed && prune) {
+        unsigned long long pp = 0;
+        HIP_CHECK(hipMemcpyAsync(&pp, P.counters + C_PAIRS, sizeof(pp), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        timing().screen_pairs += (double)pp + fr_pairs;
+        timing().screen_dim = (double)P.d_pad;
+    }
     const int64_t m = n - 1;
     int32_t h_edges = 0;
     HIP_CHECK(hipMemcpyAsync(&h_edges, P.counters + C_EDGES, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -2065,6 +2555,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         info->pair_bounds = pb ? 1 : 0;
         info->candidates = cand;
         info->rescanned_rows = resc;
+        info->tile_pairs = tp_run;
+        info->tile_pairs_full = tp_full;
     }
 }
 
@@ -2101,7 +2593,7 @@ extern "C" iso_status iso_mst(const float *X, int64_t n, int64_t d, int64_t ld, 
         ISO_REQUIRE(recheck == ISO_RECHECK_FP32 || recheck == ISO_RECHECK_FP64, ISO_ERR_INVALID_ARG,
                     "unknown recheck %d", recheck);
         ISO_REQUIRE((flags & ~(uint32_t)(ISO_MST_NO_LISTS | ISO_MST_NO_FINAL | ISO_MST_NO_ESCALATE |
-                                          ISO_MST_PAIR_BOUNDS)) == 0,
+                                          ISO_MST_PAIR_BOUNDS | ISO_MST_NO_PRUNE)) == 0,
                     ISO_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
         const int32_t options = (int32_t)flags;
         require_device();

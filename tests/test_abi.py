@@ -81,10 +81,11 @@ def test_mst_flags_validation():
     bits are rejected before any device work."""
     lib = _lib.load()
     dummy = _p(0x1000)
-    for bad in (0x10, 0x20, 0x100, 0x80000000):
+    for bad in (0x20, 0x40, 0x100, 0x80000000):
         assert lib.iso_mst(dummy, 10, 4, 4, 0, 0, bad, dummy, dummy, None, None, 0, None) == -1
         assert b"flag" in lib.iso_last_error()
-    assert _lib.MST_NO_LISTS | _lib.MST_NO_FINAL | _lib.MST_NO_ESCALATE | _lib.MST_PAIR_BOUNDS == 0xF
+    assert (_lib.MST_NO_LISTS | _lib.MST_NO_FINAL | _lib.MST_NO_ESCALATE | _lib.MST_PAIR_BOUNDS
+            | _lib.MST_NO_PRUNE) == 0x1F
 
 
 def test_subpartition_argument_validation():
