@@ -1307,36 +1307,38 @@ __global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, c
 // spatial.  The final round applies the same bound per pair of components
 // (see run_mst).
 
-constexpr int PIV = 64;              // pivot rows of the first round's order
+constexpr int PIV = 32;              // pivot rows of the first round's order
 constexpr int PRUNE_MIN_TILES = 4;   // fewer tiles: every pair is screened
 constexpr int64_t PRUNE_MAX_D = 8192;  // the tile centroid is held in LDS
+constexpr int64_t PRUNE_MAX_TILES = 8192;  // the final round's supports: ntF^2 floats
 
 // Nearest pivot of each of `count` rows (row rows[r], or r when rows is null),
-// by FP32 sums of squared differences; 64 rows x 64 pivots per workgroup, 64
-// coordinates at a time through LDS; ties go to the smaller pivot index.
-// dist (nullable) receives the PIV squared distances of every row.
+// by FP32 sums of squared differences; 128 rows x PIV pivots per workgroup
+// (thread t: rows 4 (t / 8) .. +3, pivots 4 (t mod 8) .. +3), 64 coordinates
+// at a time through LDS; ties go to the smaller pivot index.  dist (nullable)
+// receives the PIV squared distances of every row.
 __global__ __launch_bounds__(256) void k_pivot_near(const float *__restrict__ X, int64_t d, int64_t ld,
                                                     const int32_t *__restrict__ rows, int64_t count,
                                                     const int32_t *__restrict__ piv, uint32_t *__restrict__ key,
                                                     float *__restrict__ dist) {
-    static_assert(PIV == 64, "one pivot per LDS row of the tile");
-    __shared__ float sx[64][65];
+    static_assert(PIV == 32, "eight groups of four pivots");
+    __shared__ float sx[128][65];
     __shared__ float sp[PIV][65];
-    const int tid = threadIdx.x, tr = tid >> 4, tp = tid & 15;
-    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int tid = threadIdx.x, tr = tid >> 3, tp = tid & 7;
+    const int64_t r0 = (int64_t)blockIdx.x * 128;
     float acc[4][4] = {};
     for (int64_t k0 = 0; k0 < d; k0 += 64) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < 32; ++e) {
             const int idx = tid + 256 * e, r = idx >> 6, c = idx & 63;
             const int64_t k = k0 + c, g = r0 + r;
-            float v = 0.0f, w = 0.0f;
-            if (k < d) {
-                if (g < count) v = X[(rows ? (int64_t)rows[g] : g) * ld + k];
-                w = X[(int64_t)piv[r] * ld + k];
-            }
-            sx[r][c] = v;
-            sp[r][c] = w;
+            sx[r][c] = (k < d && g < count) ? X[(rows ? (int64_t)rows[g] : g) * ld + k] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + 256 * e, r = idx >> 6, c = idx & 63;
+            const int64_t k = k0 + c;
+            sp[r][c] = k < d ? X[(int64_t)piv[r] * ld + k] : 0.0f;
         }
         __syncthreads();
 #pragma unroll 4
@@ -1367,9 +1369,9 @@ __global__ __launch_bounds__(256) void k_pivot_near(const float *__restrict__ X,
                 best = acc[a][b];
                 bi = 4 * tp + b;
             }
-        // the 16 lanes of one row group differ in their low four bits
+        // the 8 lanes of one row group differ in their low three bits
 #pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
+        for (int o = 1; o < 8; o <<= 1) {
             const float ob = __shfl_xor(best, o, 64);
             const int oi = __shfl_xor(bi, o, 64);
             if (ob < best || (ob == best && oi < bi)) {
@@ -1402,56 +1404,90 @@ __global__ void k_comp_from_order(const int32_t *__restrict__ order, int64_t n, 
     comp[order[p]] = (int32_t)p;
 }
 
-// Ball of every tile of the order (GT positions each; ids >= n are padding):
-// cen = the centroid of its rows rounded to FP32, rad >= the largest distance
-// of a row from that stored centroid (FP64 sums, widened by their rounding
-// bound, rounded up), cnt = rows.  A tile without rows gets rad = -1.
-// Dynamic LDS: d floats.
-__global__ __launch_bounds__(256) void k_tile_ball(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
-                                                   const int32_t *__restrict__ order, float *__restrict__ cen,
-                                                   float *__restrict__ rad, int32_t *__restrict__ cnt) {
+// Ball of every tile of the order (GT positions each; ids >= n are padding),
+// in two kernels: cen = the centroid of its rows (FP64 sums rounded to FP32)
+// and cnt = its rows, then rad >= the largest distance of a row from that
+// stored centroid (FP64 sums widened by their rounding bound, rounded up).
+// k_tile_centroid: grid (tiles, ceil(d / 256)), one coordinate per thread.
+__global__ __launch_bounds__(256) void k_tile_centroid(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                       const int32_t *__restrict__ order, float *__restrict__ cen,
+                                                       int32_t *__restrict__ cnt) {
     static_assert(GT == 256, "one position per thread");
-    extern __shared__ float cs[];
     __shared__ int32_t rid[GT];
-    __shared__ double wmax[4];
+    __shared__ int32_t first;
     const int tid = threadIdx.x;
     const int64_t T = blockIdx.x;
+    if (tid == 0) first = GT;
     const int32_t id = order[T * GT + tid];
-    rid[tid] = id < n ? id : -1;
-    const int nv = __syncthreads_count(id < n);
-    if (nv == 0) {
-        if (tid == 0) {
-            rad[T] = -1.0f;
-            cnt[T] = 0;
-        }
-        return;
-    }
-    for (int64_t k = tid; k < d; k += 256) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int r = 0; r < GT; r += 2) {
-            const int32_t v0 = rid[r], v1 = rid[r + 1];
-            if (v0 >= 0) s0 += (double)X[(int64_t)v0 * ld + k];
-            if (v1 >= 0) s1 += (double)X[(int64_t)v1 * ld + k];
-        }
-        const float c = (float)((s0 + s1) / (double)nv);
-        cs[k] = c;
-        cen[T * d + k] = c;
-    }
+    const bool valid = id < n;
+    rid[tid] = valid ? id : -1;
     __syncthreads();
-    const int lane = tid & 63, w = tid >> 6;
-    double m = 0.0;
-    for (int r = w; r < GT; r += 4) {
-        const int32_t v = rid[r];
-        if (v < 0) continue;
-        const float *x = X + (int64_t)v * ld;
-        double s = 0.0;
-        for (int64_t k = lane; k < d; k += 64) {
-            const double t = (double)x[k] - (double)cs[k];
-            s = fma(t, t, s);
+    if (valid) atomicMin(&first, tid);
+    const int nv = __syncthreads_count(valid);
+    if (blockIdx.y == 0 && tid == 0) cnt[T] = nv;
+    if (nv == 0) return;
+    const int64_t k = (int64_t)blockIdx.y * 256 + tid;
+    if (k >= d) return;
+    // (a padding position reads the tile's first row with weight 0)
+    const int64_t f = rid[first];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int r = 0; r < GT; r += 16) {
+        float x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int32_t v = rid[r + u];
+            x[u] = X[(v >= 0 ? (int64_t)v : f) * ld + k];
         }
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-        m = fmax(m, s);
+        for (int u = 0; u < 16; u += 4) {
+            s0 += rid[r + u] >= 0 ? (double)x[u] : 0.0;
+            s1 += rid[r + u + 1] >= 0 ? (double)x[u + 1] : 0.0;
+            s2 += rid[r + u + 2] >= 0 ? (double)x[u + 2] : 0.0;
+            s3 += rid[r + u + 3] >= 0 ? (double)x[u + 3] : 0.0;
+        }
+    }
+    cen[T * d + k] = (float)(((s0 + s1) + (s2 + s3)) / (double)nv);
+}
+
+// k_tile_radius: grid (tiles, 4), 64 positions per workgroup, each wave four
+// rows at a time; the centroid in dynamic LDS (d floats).  rad must hold 0
+// (or a smaller bound) before: blocks combine by an atomic max of the bits
+// (nonnegative floats order like their bits).
+__global__ __launch_bounds__(256) void k_tile_radius(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                     const int32_t *__restrict__ order, const float *__restrict__ cen,
+                                                     const int32_t *__restrict__ cnt, float *__restrict__ rad) {
+    extern __shared__ float cs[];
+    __shared__ double wmax[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t T = blockIdx.x;
+    if (cnt[T] == 0) return;
+    for (int64_t k = tid; k < d; k += 256) cs[k] = cen[T * d + k];
+    __syncthreads();
+    double m = 0.0;
+    const int64_t p0 = T * GT + (int64_t)blockIdx.y * 64 + w * 16;
+    for (int r0 = 0; r0 < 16; r0 += 4) {
+        int64_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t id = order[p0 + r0 + j];
+            v[j] = id < n ? (int64_t)id : -1;
+        }
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t k = lane; k < d; k += 64) {
+            const double c = (double)cs[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (v[j] >= 0) {
+                    const double t = (double)X[v[j] * ld + k] - c;
+                    a[j] = fma(t, t, a[j]);
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) a[j] += __shfl_xor(a[j], o, 64);
+            if (v[j] >= 0) m = fmax(m, a[j]);
+        }
     }
     if (lane == 0) wmax[w] = m;
     __syncthreads();
@@ -1461,27 +1497,179 @@ __global__ __launch_bounds__(256) void k_tile_ball(const float *__restrict__ X, 
         const double r = sqrt(mm) * (1.0 + (double)(d + 68) * 0x1p-52);
         float f = (float)r;
         if ((double)f < r) f = nextafterf(f, SCR_INF);
-        rad[T] = f;
-        cnt[T] = nv;
+        atomicMax(reinterpret_cast<unsigned int *>(rad) + T, __float_as_uint(f));
     }
 }
 
-// LB^2 of every tile pair, rounded down to FP32: LB = ||c_I - c_J|| - rad_I -
-// rad_J (FP64, the distance narrowed and the radii widened by their rounding
-// bounds), 0 when the balls meet; NaN when a tile has no row (such a pair holds
-// no pair of points and is never screened).  One wave per pair.
+// The support bound of the final round.  In high dimension the ball bound
+// is loose: a row's deviation from its tile's centroid is nearly orthogonal
+// to the direction of another tile, so the rows reach far less toward it than
+// the radius.  With u = x - c_I, v = y - c_J and Delta = c_I - c_J,
+//   D^2 = |Delta + u - v|^2 >= |Delta|^2 + 2 Delta.u - 2 Delta.v,
+// and for any KQ x d matrix Q, Delta.u = (Q Delta).(Q u) + ((I - Q'Q) Delta).u,
+// where |(I - Q'Q) Delta|^2 = |Delta|^2 - |Q Delta|^2 + (Q Delta)'(Q Q' - I)(Q Delta)
+// <= |Delta|^2 - (1 - eta) |Q Delta|^2, eta >= ||Q Q' - I||.  Hence
+//   D^2 >= |Delta|^2 - 2 (S_I(J) + S_J(I)) - 2 |Delta_perp| (rad_I + rad_J),
+//   S_I(J) = max over x in I of (Q x - Q c_I).(Q c_J - Q c_I),
+// with Q orthonormal rows spanning the differences of a few tile centroids
+// (the directions that separate clusters).  Everything in FP64, with margins
+// of 1e-9 of the magnitudes involved (|c_I| + |c_J| + rad_I + rad_J + 1)^2;
+// the FP64 rounding errors stay below 1e-11 of them for d <= PRUNE_MAX_D.
+constexpr int KQ = 32;  // rows of Q
+
+// z = Q x of every point (FP64): 256 points x KQ rows per workgroup, thread t
+// owns points 4 (t / 4) .. +3 and rows 8 (t mod 4) .. +7; 32 coordinates at a
+// time through LDS.
+__global__ __launch_bounds__(256) void k_project(const float *__restrict__ X, int64_t n, int64_t d, int64_t ld,
+                                                 const double *__restrict__ Q, double *__restrict__ z) {
+    static_assert(KQ == 32, "four groups of eight rows");
+    __shared__ float sx[256][33];
+    __shared__ double sq[KQ][33];
+    const int tid = threadIdx.x, tr = tid >> 2, tg = tid & 3;
+    const int64_t r0 = (int64_t)blockIdx.x * 256;
+    double acc[4][8] = {};
+    for (int64_t k0 = 0; k0 < d; k0 += 32) {
+#pragma unroll
+        for (int e = 0; e < 32; ++e) {
+            const int idx = tid + 256 * e, r = idx >> 5, c = idx & 31;
+            const int64_t k = k0 + c, g = r0 + r;
+            sx[r][c] = (k < d && g < n) ? X[g * ld + k] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e, r = idx >> 5, c = idx & 31;
+            const int64_t k = k0 + c;
+            sq[r][c] = k < d ? Q[(int64_t)r * d + k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int c = 0; c < 32; ++c) {
+            double xa[4], qb[8];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) xa[a] = (double)sx[4 * tr + a][c];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) qb[b] = sq[8 * tg + b][c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) acc[a][b] = fma(qb[b], xa[a], acc[a][b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t g = r0 + 4 * tr + a;
+        if (g < n)
+#pragma unroll
+            for (int b = 0; b < 8; ++b) z[g * KQ + 8 * tg + b] = acc[a][b];
+    }
+}
+
+// zc = Q c of every tile's stored centroid and cn >= |c| (FP64).  One
+// workgroup per tile: thread t sums row t mod 32 of Q over its eighth of d.
+__global__ __launch_bounds__(256) void k_tile_project(const float *__restrict__ cen, const int32_t *__restrict__ cnt,
+                                                      int64_t d, const double *__restrict__ Q,
+                                                      double *__restrict__ zc, double *__restrict__ cn) {
+    __shared__ double part[8][KQ + 1];
+    __shared__ double nrm[8];
+    const int tid = threadIdx.x, q = tid & 31, h = tid >> 5;
+    const int64_t T = blockIdx.x;
+    const float *c = cen + T * d;
+    const bool live = cnt[T] > 0;
+    double s = 0.0, s2 = 0.0;
+    if (live)
+        for (int64_t k = h; k < d; k += 8) {
+            const double v = (double)c[k];
+            s = fma(Q[(int64_t)q * d + k], v, s);
+            if (q == 0) s2 = fma(v, v, s2);
+        }
+    part[h][q] = s;
+    if (q == 0) nrm[h] = s2;
+    __syncthreads();
+    if (tid < KQ) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t += part[j][tid];
+        zc[T * KQ + tid] = t;
+    }
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t += nrm[j];
+        cn[T] = sqrt(t) * (1.0 + 1e-12);
+    }
+}
+
+// S[I][J] = max over the rows x of tile I of (z_x - zc_I).(zc_J - zc_I),
+// rounded up to FP32 (-inf for a tile without rows).  One workgroup per tile
+// I, one row per thread; 16 tiles J at a time through LDS.
+__global__ __launch_bounds__(256) void k_tile_support(const int32_t *__restrict__ order, int64_t n,
+                                                      const double *__restrict__ z, const double *__restrict__ zc,
+                                                      const int32_t *__restrict__ cnt, int64_t nt,
+                                                      float *__restrict__ S) {
+    __shared__ double zj[16][KQ + 1];
+    __shared__ double red[4][16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t T = blockIdx.x;
+    if (cnt[T] == 0) {
+        for (int64_t j = tid; j < nt; j += 256) S[T * nt + j] = -SCR_INF;
+        return;
+    }
+    const int32_t id = order[T * GT + tid];
+    const bool valid = id < n;
+    double u[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) u[q] = valid ? z[(int64_t)id * KQ + q] - zc[T * KQ + q] : 0.0;
+    for (int64_t J0 = 0; J0 < nt; J0 += 16) {
+        __syncthreads();
+        for (int e = tid; e < 16 * KQ; e += 256) {
+            const int jj = e / KQ, q = e % KQ;
+            const int64_t j = J0 + jj;
+            zj[jj][q] = j < nt ? zc[j * KQ + q] - zc[T * KQ + q] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int jj = 0; jj < 16; ++jj) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) t = fma(u[q], zj[jj][q], t);
+            double v = valid ? t : -__builtin_huge_val();
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+            if (lane == 0) red[w][jj] = v;
+        }
+        __syncthreads();
+        if (tid < 16 && J0 + tid < nt) {
+            const double m = fmax(fmax(red[0][tid], red[1][tid]), fmax(red[2][tid], red[3][tid]));
+            float f = (float)m;
+            if ((double)f < m) f = nextafterf(f, SCR_INF);
+            S[T * nt + J0 + tid] = f;
+        }
+    }
+}
+
+// LB^2 of every tile pair, rounded down to FP32: the larger of the ball bound
+// (LB = ||c_I - c_J|| - rad_I - rad_J, FP64, the distance narrowed and the
+// radii widened by their rounding bounds) and, when S is given, the support
+// bound above; 0 when neither excludes anything; NaN when a tile has no row
+// (such a pair holds no pair of points and is never screened).  One wave per
+// pair; nt is the row stride of S.
 __global__ __launch_bounds__(256) void k_pair_lb(const int2 *__restrict__ pairs, int64_t npairs,
                                                  const float *__restrict__ cen, const float *__restrict__ rad,
-                                                 int64_t d, float *__restrict__ plb) {
+                                                 const int32_t *__restrict__ cnt, int64_t d,
+                                                 const float *__restrict__ S, const double *__restrict__ zc,
+                                                 const double *__restrict__ cn, int64_t nt, double eta,
+                                                 float *__restrict__ plb) {
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (k >= npairs) return;
     const int2 pr = pairs[k];
-    const float rI = rad[pr.x], rJ = rad[pr.y];
-    if (rI < 0.0f || rJ < 0.0f || pr.x == pr.y) {
-        if (lane == 0) plb[k] = (rI < 0.0f || rJ < 0.0f) ? __builtin_nanf("") : 0.0f;
+    const bool empty = cnt[pr.x] == 0 || cnt[pr.y] == 0;
+    if (empty || pr.x == pr.y) {
+        if (lane == 0) plb[k] = empty ? __builtin_nanf("") : 0.0f;
         return;
     }
+    const float rI = rad[pr.x], rJ = rad[pr.y];
     const float *a = cen + (int64_t)pr.x * d, *b = cen + (int64_t)pr.y * d;
     double s = 0.0;
     for (int64_t t = lane; t < d; t += 64) {
@@ -1490,12 +1678,31 @@ __global__ __launch_bounds__(256) void k_pair_lb(const int2 *__restrict__ pairs,
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    double g2 = 0.0;
+    if (S) {
+        const double gq = lane < KQ ? zc[(int64_t)pr.x * KQ + lane] - zc[(int64_t)pr.y * KQ + lane] : 0.0;
+        g2 = gq * gq;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) g2 += __shfl_xor(g2, o, 64);
+    }
     if (lane == 0) {
         const double dist = sqrt(s) * (1.0 - (double)(d + 68) * 0x1p-52);
-        const double lb = dist - ((double)rI + (double)rJ) * (1.0 + 0x1p-52);
+        const double rs = ((double)rI + (double)rJ) * (1.0 + 0x1p-52);
+        const double lb = dist - rs;
+        double l2 = lb > 0.0 ? lb * lb * (1.0 - 0x1p-50) : 0.0;
+        if (S) {
+            // (the absolute slack 1e-10 mag^2 under the root covers the
+            // rounding of g2 = |Q Delta|^2, below 1e-11 mag^2)
+            const double sIJ = (double)S[(int64_t)pr.x * nt + pr.y], sJI = (double)S[(int64_t)pr.y * nt + pr.x];
+            const double mag = cn[pr.x] + cn[pr.y] + rs + 1.0;
+            const double perp =
+                sqrt(fmax(0.0, s * (1.0 + 1e-11) - g2 * (1.0 - eta) + 1e-10 * mag * mag)) * (1.0 + 1e-12);
+            const double sup = s * (1.0 - 1e-11) - 2.0 * (sIJ + sJI) - 2.0 * perp * rs -
+                               1e-9 * (s + 2.0 * (fabs(sIJ) + fabs(sJI)) + mag * mag);
+            l2 = fmax(l2, sup);
+        }
         float f = 0.0f;
-        if (lb > 0.0) {
-            const double l2 = lb * lb * (1.0 - 0x1p-50);
+        if (l2 > 0.0) {
             f = (float)l2;
             if ((double)f > l2) f = nextafterf(f, 0.0f);
         }
@@ -1577,9 +1784,12 @@ struct MstPlan {
     unsigned long long *W1, *W2;
     uint32_t *upair;
     // tile-pair pruning: tile balls and reach, LB^2 per tile pair, pivots
+    bool prune_ok;                  // sizes allow the tile-pair test (see make_plan)
     float *cen, *rad, *tthr, *plb, *pivd;
     int32_t *tcnt, *piv, *piv_rank;
     int2 *pairsF2;                  // the final round's tile pairs of one phase
+    double *Q, *z, *zc, *cn;        // final round's support bound: projection, points, tiles
+    float *S;                       // [ntF_cap][ntF_cap] supports
     double *rb_d2, *elen, *wsum;
     unsigned long long *ck1, *ck2;
     int32_t *counters;
@@ -1684,10 +1894,10 @@ struct MstPlan {
         W1 = a.take<unsigned long long>(FR_KC * FR_KC);
         W2 = a.take<unsigned long long>(FR_KC * FR_KC);
         upair = a.take<uint32_t>(FR_KC * FR_KC);
-        {
+        if (prune_ok) {
             const int64_t ntb = std::max<int64_t>(nt, ntF_cap);
             const int64_t nfp = ntF_cap * (ntF_cap - 1) / 2;
-            cen = a.take<float>((size_t)ntb * (size_t)std::min<int64_t>(d, PRUNE_MAX_D));
+            cen = a.take<float>((size_t)ntb * (size_t)d);
             rad = a.take<float>(ntb);
             tcnt = a.take<int32_t>(ntb);
             tthr = a.take<float>(ntb);
@@ -1696,6 +1906,11 @@ struct MstPlan {
             piv = a.take<int32_t>(PIV);
             piv_rank = a.take<int32_t>(PIV);
             pivd = a.take<float>(PIV * PIV);
+            Q = a.take<double>((size_t)KQ * (size_t)d);
+            z = a.take<double>((size_t)n * KQ);
+            zc = a.take<double>((size_t)ntb * KQ);
+            cn = a.take<double>(ntb);
+            S = a.take<float>((size_t)ntF_cap * (size_t)ntF_cap);
         }
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
@@ -1716,6 +1931,7 @@ MstPlan make_plan(int64_t n, int64_t d, int64_t ld, int32_t precision) {
     p.nt = p.n_pad / pair_tile();
     p.npairs = p.nt * (p.nt + 1) / 2;
     p.ntF_cap = (n + pair_tile() - 1) / pair_tile() + FR_KC;
+    p.prune_ok = p.nt >= PRUNE_MIN_TILES && d <= PRUNE_MAX_D && p.ntF_cap <= PRUNE_MAX_TILES;
     return p;
 }
 
@@ -1744,7 +1960,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     whole.start(s);
     *escalate = false;
     const bool may_escalate = rep != ISO_PREC_FP32 && !(P.options & ISO_MST_NO_ESCALATE);
-    const bool prune = !(P.options & ISO_MST_NO_PRUNE) && P.nt >= PRUNE_MIN_TILES && d <= PRUNE_MAX_D;
+    const bool prune = !(P.options & ISO_MST_NO_PRUNE) && P.prune_ok;
     int64_t tp_run = 0, tp_full = 0;  // tile pairs screened, and those full screens would have run
     auto give_up = [&]() {
         whole.stop(s);
@@ -1926,12 +2142,12 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             cur = nx;
         }
         HIP_CHECK(hipMemcpyAsync(P.piv_rank, h_rank.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_pivot_near, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, X, d, ld,
+        hipLaunchKernelGGL(k_pivot_near, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, s, X, d, ld,
                            static_cast<const int32_t *>(nullptr), n, P.piv, P.pkeys, static_cast<float *>(nullptr));
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_pivot_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.pkeys, P.piv_rank, n, P.perm);
         LAUNCH_CHECK();
-        radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, 6, P.psort, s);
+        radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, 5, P.psort, s);
         hipLaunchKernelGGL(k_comp_from_order, dim3(grid_for(n, 256)), dim3(256), 0, s, P.perm, n, P.comp);
         LAUNCH_CHECK();
     }
@@ -1985,12 +2201,84 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     };
 
     // Tile balls of the order (ntiles tiles) and LB^2 of the tile pairs `pairs`.
-    auto tile_bounds = [&](const int32_t *order, int64_t ntiles, const int2 *pairs, int64_t npr) {
-        hipLaunchKernelGGL(k_tile_ball, dim3((unsigned)ntiles), dim3(256), (size_t)d * sizeof(float), s, X, n, d, ld,
-                           order, P.cen, P.rad, P.tcnt);
+    // Tile balls of the order (ntiles tiles) and LB^2 of the tile pairs
+    // `pairs`; with `support` the support bound as well (the projection Q and
+    // the points' z = Q x are made at its first use, from the centroids of
+    // KQ + 1 tiles spread over the order).
+    bool have_q = false;
+    double h_eta = 0.0;
+    auto tile_bounds = [&](const int32_t *order, int64_t ntiles, const int2 *pairs, int64_t npr, bool support) {
+        hipLaunchKernelGGL(k_tile_centroid, dim3((unsigned)ntiles, (unsigned)((d + 255) / 256)), dim3(256), 0, s, X, n,
+                           d, ld, order, P.cen, P.tcnt);
         LAUNCH_CHECK();
+        fill<float>(P.rad, 0.0f, ntiles, s);
+        hipLaunchKernelGGL(k_tile_radius, dim3((unsigned)ntiles, 4), dim3(256), (size_t)d * sizeof(float), s, X, n, d,
+                           ld, order, P.cen, P.tcnt, P.rad);
+        LAUNCH_CHECK();
+        support = support && ntiles <= P.ntF_cap;
+        if (support && !have_q) {
+            // Gram-Schmidt (twice) in FP64 of the differences of the reference
+            // centroids to the first; directions that vanish stay zero rows
+            const int nref = KQ + 1;
+            std::vector<float> hc((size_t)nref * d);
+            std::vector<int32_t> hcnt(nref);
+            for (int q = 0; q < nref; ++q) {
+                const int64_t t = (int64_t)q * ntiles / nref;
+                HIP_CHECK(hipMemcpyAsync(hc.data() + (size_t)q * d, P.cen + t * d, sizeof(float) * d,
+                                         hipMemcpyDeviceToHost, s));
+                HIP_CHECK(hipMemcpyAsync(&hcnt[q], P.tcnt + t, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            }
+            HIP_CHECK(hipStreamSynchronize(s));
+            std::vector<double> hq((size_t)KQ * d, 0.0), v(d);
+            std::vector<int> live;
+            for (int q = 1; q < nref && hcnt[0] > 0; ++q) {
+                if (hcnt[q] == 0) continue;
+                double n0 = 0.0;
+                for (int64_t k = 0; k < d; ++k) {
+                    v[k] = (double)hc[(size_t)q * d + k] - (double)hc[k];
+                    n0 += v[k] * v[k];
+                }
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int j : live) {
+                        const double *qj = hq.data() + (size_t)j * d;
+                        double t = 0.0;
+                        for (int64_t k = 0; k < d; ++k) t += qj[k] * v[k];
+                        for (int64_t k = 0; k < d; ++k) v[k] -= t * qj[k];
+                    }
+                double nv = 0.0;
+                for (int64_t k = 0; k < d; ++k) nv += v[k] * v[k];
+                if (!(nv > 1e-16 * n0) || !(nv > 0.0)) continue;
+                const int row = (int)live.size();
+                const double inv = 1.0 / std::sqrt(nv);
+                for (int64_t k = 0; k < d; ++k) hq[(size_t)row * d + k] = v[k] * inv;
+                live.push_back(row);
+            }
+            // eta >= ||Q Q' - I|| over the nonzero rows (bounded by KQ times the largest entry)
+            double emax = 0.0;
+            for (int i : live)
+                for (int j : live) {
+                    double t = 0.0;
+                    for (int64_t k = 0; k < d; ++k) t += hq[(size_t)i * d + k] * hq[(size_t)j * d + k];
+                    emax = std::max(emax, std::fabs(t - (i == j ? 1.0 : 0.0)));
+                }
+            h_eta = (double)KQ * emax * 2.0 + 1e-13;
+            HIP_CHECK(hipMemcpyAsync(P.Q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, ld, P.Q, P.z);
+            LAUNCH_CHECK();
+            HIP_CHECK(hipStreamSynchronize(s));  // (hq is the source of the copy above)
+            have_q = true;
+        }
+        if (support) {
+            hipLaunchKernelGGL(k_tile_project, dim3((unsigned)ntiles), dim3(256), 0, s, P.cen, P.tcnt, d, P.Q, P.zc,
+                               P.cn);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_tile_support, dim3((unsigned)ntiles), dim3(256), 0, s, order, n, P.z, P.zc, P.tcnt,
+                               ntiles, P.S);
+            LAUNCH_CHECK();
+        }
         if (npr > 0) {
-            hipLaunchKernelGGL(k_pair_lb, dim3(grid_for(npr, 4)), dim3(256), 0, s, pairs, npr, P.cen, P.rad, d, P.plb);
+            hipLaunchKernelGGL(k_pair_lb, dim3(grid_for(npr, 4)), dim3(256), 0, s, pairs, npr, P.cen, P.rad, P.tcnt, d,
+                               support ? P.S : nullptr, P.zc, P.cn, ntiles, h_eta, P.plb);
             LAUNCH_CHECK();
         }
     };
@@ -2090,7 +2378,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             // holds none; the second phase screens the others.  The recheck
             // then gives every MST edge exactly, and every other pair of
             // components at most a heavier edge, which Kruskal leaves out.
-            tile_bounds(P.permF, ntF, P.pairsF, nF);
+            tile_bounds(P.permF, ntF, P.pairsF, nF, true);
             std::vector<float> hl(nF);
             HIP_CHECK(hipMemcpyAsync(hl.data(), P.plb, sizeof(float) * nF, hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
@@ -2308,7 +2596,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                    pair_tile(), P.tlo, P.thi);
                 LAUNCH_CHECK();
                 if (prune) {
-                    tile_bounds(P.perm, P.nt, P.pairs, P.npairs);
+                    tile_bounds(P.perm, P.nt, P.pairs, P.npairs, false);
                     fill<int32_t>(P.counters + C_TPFULL, 0, 1, s);
                 }
                 std::tie(nmask, noff) = compact(prune ? 1 : 0, rounds == 1);
