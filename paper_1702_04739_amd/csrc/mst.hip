@@ -1324,22 +1324,39 @@ __global__ __launch_bounds__(256) void k_pivot_near(const float *__restrict__ X,
     static_assert(PIV == 32, "eight groups of four pivots");
     __shared__ float sx[128][65];
     __shared__ float sp[PIV][65];
-    const int tid = threadIdx.x, tr = tid >> 3, tp = tid & 7;
+    __shared__ int64_t roff[128 + PIV];  // element offsets of the rows, then of the pivots; -1: no row
+    const int tid = threadIdx.x, tr = tid >> 3, tp = tid & 7, w = tid >> 6, c = tid & 63;
     const int64_t r0 = (int64_t)blockIdx.x * 128;
+    if (tid < 128) {
+        const int64_t g = r0 + tid;
+        roff[tid] = g < count ? (rows ? (int64_t)rows[g] : g) * ld : -1;
+    } else if (tid < 128 + PIV) {
+        roff[tid] = (int64_t)piv[tid - 128] * ld;
+    }
+    __syncthreads();
     float acc[4][4] = {};
     for (int64_t k0 = 0; k0 < d; k0 += 64) {
+        // every load first (no branch between them), then the LDS writes; a
+        // missing row or a coordinate beyond d reads X[0] and stores 0
+        const int64_t k = k0 + c;
+        float vx[32], vp[8];
 #pragma unroll
         for (int e = 0; e < 32; ++e) {
-            const int idx = tid + 256 * e, r = idx >> 6, c = idx & 63;
-            const int64_t k = k0 + c, g = r0 + r;
-            sx[r][c] = (k < d && g < count) ? X[(rows ? (int64_t)rows[g] : g) * ld + k] : 0.0f;
+            const int64_t o = roff[w + 4 * e];
+            const bool ok = o >= 0 && k < d;
+            vx[e] = X[ok ? o + k : 0];
+            vx[e] = ok ? vx[e] : 0.0f;
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int idx = tid + 256 * e, r = idx >> 6, c = idx & 63;
-            const int64_t k = k0 + c;
-            sp[r][c] = k < d ? X[(int64_t)piv[r] * ld + k] : 0.0f;
+            const bool ok = k < d;
+            vp[e] = X[ok ? roff[128 + w + 4 * e] + k : 0];
+            vp[e] = ok ? vp[e] : 0.0f;
         }
+#pragma unroll
+        for (int e = 0; e < 32; ++e) sx[w + 4 * e][c] = vx[e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sp[w + 4 * e][c] = vp[e];
         __syncthreads();
 #pragma unroll 4
         for (int c = 0; c < 64; ++c) {
@@ -1449,7 +1466,7 @@ __global__ __launch_bounds__(256) void k_tile_centroid(const float *__restrict__
     cen[T * d + k] = (float)(((s0 + s1) + (s2 + s3)) / (double)nv);
 }
 
-// k_tile_radius: grid (tiles, 4), 64 positions per workgroup, each wave four
+// k_tile_radius: grid (tiles, 4), 64 positions per workgroup, each wave eight
 // rows at a time; the centroid in dynamic LDS (d floats).  rad must hold 0
 // (or a smaller bound) before: blocks combine by an atomic max of the bits
 // (nonnegative floats order like their bits).
@@ -1465,28 +1482,34 @@ __global__ __launch_bounds__(256) void k_tile_radius(const float *__restrict__ X
     __syncthreads();
     double m = 0.0;
     const int64_t p0 = T * GT + (int64_t)blockIdx.y * 64 + w * 16;
-    for (int r0 = 0; r0 < 16; r0 += 4) {
-        int64_t v[4];
+    for (int r0 = 0; r0 < 16; r0 += 8) {
+        // eight rows at a time, loads without branches (a padding position
+        // reads row 0 and is left out of the maximum)
+        int64_t off[8];
+        bool ok[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 8; ++j) {
             const int32_t id = order[p0 + r0 + j];
-            v[j] = id < n ? (int64_t)id : -1;
+            ok[j] = id < n;
+            off[j] = ok[j] ? (int64_t)id * ld : 0;
         }
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int64_t k = lane; k < d; k += 64) {
             const double c = (double)cs[k];
+            float x[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (v[j] >= 0) {
-                    const double t = (double)X[v[j] * ld + k] - c;
-                    a[j] = fma(t, t, a[j]);
-                }
+            for (int j = 0; j < 8; ++j) x[j] = X[off[j] + k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double t = (double)x[j] - c;
+                a[j] = fma(t, t, a[j]);
+            }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 8; ++j) {
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) a[j] += __shfl_xor(a[j], o, 64);
-            if (v[j] >= 0) m = fmax(m, a[j]);
+            if (ok[j]) m = fmax(m, a[j]);
         }
     }
     if (lane == 0) wmax[w] = m;
@@ -1512,9 +1535,10 @@ __global__ __launch_bounds__(256) void k_tile_radius(const float *__restrict__ X
 //   D^2 >= |Delta|^2 - 2 (S_I(J) + S_J(I)) - 2 |Delta_perp| (rad_I + rad_J),
 //   S_I(J) = max over x in I of (Q x - Q c_I).(Q c_J - Q c_I),
 // with Q orthonormal rows spanning the differences of a few tile centroids
-// (the directions that separate clusters).  Everything in FP64, with margins
-// of 1e-9 of the magnitudes involved (|c_I| + |c_J| + rad_I + rad_J + 1)^2;
-// the FP64 rounding errors stay below 1e-11 of them for d <= PRUNE_MAX_D.
+// (the directions that separate clusters).  Q, z = Q x and zc = Q c are FP64
+// (rounding errors below 1e-11 of the magnitudes involved, mag^2 =
+// (|c_I| + |c_J| + rad_I + rad_J + 1)^2, for d <= PRUNE_MAX_D), the supports
+// FP32 (below 3e-6 mag^2 each); the bound keeps a margin of 4e-5 mag^2.
 constexpr int KQ = 32;  // rows of Q
 
 // z = Q x of every point (FP64): 256 points x KQ rows per workgroup, thread t
@@ -1525,22 +1549,32 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ X, in
     static_assert(KQ == 32, "four groups of eight rows");
     __shared__ float sx[256][33];
     __shared__ double sq[KQ][33];
-    const int tid = threadIdx.x, tr = tid >> 2, tg = tid & 3;
+    const int tid = threadIdx.x, tr = tid >> 2, tg = tid & 3, h = tid >> 5, c = tid & 31;
     const int64_t r0 = (int64_t)blockIdx.x * 256;
     double acc[4][8] = {};
     for (int64_t k0 = 0; k0 < d; k0 += 32) {
+        // every load first, then the LDS writes (rows beyond n and
+        // coordinates beyond d read X[0] or Q[0] and store 0)
+        const int64_t k = k0 + c;
+        float vx[32];
+        double vq[4];
 #pragma unroll
         for (int e = 0; e < 32; ++e) {
-            const int idx = tid + 256 * e, r = idx >> 5, c = idx & 31;
-            const int64_t k = k0 + c, g = r0 + r;
-            sx[r][c] = (k < d && g < n) ? X[g * ld + k] : 0.0f;
+            const int64_t g = r0 + h + 8 * e;
+            const bool ok = g < n && k < d;
+            vx[e] = X[ok ? g * ld + k : 0];
+            vx[e] = ok ? vx[e] : 0.0f;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int idx = tid + 256 * e, r = idx >> 5, c = idx & 31;
-            const int64_t k = k0 + c;
-            sq[r][c] = k < d ? Q[(int64_t)r * d + k] : 0.0;
+            const bool ok = k < d;
+            vq[e] = Q[ok ? (int64_t)(h + 8 * e) * d + k : 0];
+            vq[e] = ok ? vq[e] : 0.0;
         }
+#pragma unroll
+        for (int e = 0; e < 32; ++e) sx[h + 8 * e][c] = vx[e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sq[h + 8 * e][c] = vq[e];
         __syncthreads();
 #pragma unroll 4
         for (int c = 0; c < 32; ++c) {
@@ -1600,51 +1634,43 @@ __global__ __launch_bounds__(256) void k_tile_project(const float *__restrict__ 
     }
 }
 
-// S[I][J] = max over the rows x of tile I of (z_x - zc_I).(zc_J - zc_I),
-// rounded up to FP32 (-inf for a tile without rows).  One workgroup per tile
-// I, one row per thread; 16 tiles J at a time through LDS.
+// S[I][J] = max over the rows x of tile I of (z_x - zc_I).(zc_J - zc_I) in
+// FP32 (both factors rounded to FP32, FP32 sums: an error below 3e-6 |u| |g|,
+// which the pair bound's margin covers); -inf for a tile without rows.  One
+// workgroup per tile I: its rows' u = z_x - zc_I in LDS, one tile J per thread.
 __global__ __launch_bounds__(256) void k_tile_support(const int32_t *__restrict__ order, int64_t n,
                                                       const double *__restrict__ z, const double *__restrict__ zc,
                                                       const int32_t *__restrict__ cnt, int64_t nt,
                                                       float *__restrict__ S) {
-    __shared__ double zj[16][KQ + 1];
-    __shared__ double red[4][16];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    __shared__ float us[GT][KQ + 1];
+    __shared__ int32_t ok[GT];
+    const int tid = threadIdx.x;
     const int64_t T = blockIdx.x;
     if (cnt[T] == 0) {
         for (int64_t j = tid; j < nt; j += 256) S[T * nt + j] = -SCR_INF;
         return;
     }
-    const int32_t id = order[T * GT + tid];
-    const bool valid = id < n;
-    double u[KQ];
+    {
+        const int32_t id = order[T * GT + tid];
+        const bool valid = id < n;
+        ok[tid] = valid ? 1 : 0;
 #pragma unroll
-    for (int q = 0; q < KQ; ++q) u[q] = valid ? z[(int64_t)id * KQ + q] - zc[T * KQ + q] : 0.0;
-    for (int64_t J0 = 0; J0 < nt; J0 += 16) {
-        __syncthreads();
-        for (int e = tid; e < 16 * KQ; e += 256) {
-            const int jj = e / KQ, q = e % KQ;
-            const int64_t j = J0 + jj;
-            zj[jj][q] = j < nt ? zc[j * KQ + q] - zc[T * KQ + q] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int jj = 0; jj < 16; ++jj) {
-            double t = 0.0;
+        for (int q = 0; q < KQ; ++q) us[tid][q] = valid ? (float)(z[(int64_t)id * KQ + q] - zc[T * KQ + q]) : 0.0f;
+    }
+    __syncthreads();
+    for (int64_t J = tid; J - tid < nt; J += 256) {
+        const bool live = J < nt;
+        float g[KQ];
 #pragma unroll
-            for (int q = 0; q < KQ; ++q) t = fma(u[q], zj[jj][q], t);
-            double v = valid ? t : -__builtin_huge_val();
+        for (int q = 0; q < KQ; ++q) g[q] = live ? (float)(zc[J * KQ + q] - zc[T * KQ + q]) : 0.0f;
+        float m = -SCR_INF;
+        for (int r = 0; r < GT; ++r) {
+            float t = 0.0f;
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-            if (lane == 0) red[w][jj] = v;
+            for (int q = 0; q < KQ; ++q) t = fmaf(us[r][q], g[q], t);
+            m = ok[r] ? fmaxf(m, t) : m;
         }
-        __syncthreads();
-        if (tid < 16 && J0 + tid < nt) {
-            const double m = fmax(fmax(red[0][tid], red[1][tid]), fmax(red[2][tid], red[3][tid]));
-            float f = (float)m;
-            if ((double)f < m) f = nextafterf(f, SCR_INF);
-            S[T * nt + J0 + tid] = f;
-        }
+        if (live) S[T * nt + J] = m;
     }
 }
 
@@ -1697,8 +1723,9 @@ __global__ __launch_bounds__(256) void k_pair_lb(const int2 *__restrict__ pairs,
             const double mag = cn[pr.x] + cn[pr.y] + rs + 1.0;
             const double perp =
                 sqrt(fmax(0.0, s * (1.0 + 1e-11) - g2 * (1.0 - eta) + 1e-10 * mag * mag)) * (1.0 + 1e-12);
+            // (4e-5 mag^2 covers twice the two FP32 supports, each within 3e-6 mag^2)
             const double sup = s * (1.0 - 1e-11) - 2.0 * (sIJ + sJI) - 2.0 * perp * rs -
-                               1e-9 * (s + 2.0 * (fabs(sIJ) + fabs(sJI)) + mag * mag);
+                               1e-9 * (s + 2.0 * (fabs(sIJ) + fabs(sJI))) - 4e-5 * mag * mag;
             l2 = fmax(l2, sup);
         }
         float f = 0.0f;
@@ -2602,16 +2629,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 std::tie(nmask, noff) = compact(prune ? 1 : 0, rounds == 1);
                 pairs_use = P.pairs_r;
             }
-            if (!prune) {
-                tp_run += nmask + noff;
-                tp_full += nmask + noff;
-            } else {
-                tp_run += nmask + noff;
-                int32_t hf = 0;
-                HIP_CHECK(hipMemcpyAsync(&hf, P.counters + C_TPFULL, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipStreamSynchronize(s));
-                tp_full += hf;
-            }
+            tp_run += nmask + noff;
+            if (!prune) tp_full += nmask + noff;  // (pruned rounds: C_TPFULL, read with the round's counters)
             if (lists == LISTS_NONE && rounds == 2) {
                 // the second round's screen builds the lists from the first
                 // round's minima (still in best)
@@ -2766,6 +2785,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         HIP_CHECK(hipMemcpyAsync(h, P.counters, sizeof(h), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         ISO_REQUIRE(h[C_NOEDGE] == 0, ISO_ERR_INTERNAL, "a component found no outgoing edge in round %d", rounds);
+        if (prune && !list_round) tp_full += h[C_TPFULL];
         ISO_REQUIRE(h[C_NCOMP] >= 1 && h[C_NCOMP] < ncomp, ISO_ERR_INTERNAL,
                     "Boruvka round %d did not contract (%lld -> %d components)", rounds, (long long)ncomp, h[C_NCOMP]);
         if (timed && !list_round && !prune) {
