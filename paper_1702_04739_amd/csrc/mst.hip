@@ -1770,6 +1770,60 @@ __global__ __launch_bounds__(256) void k_tile_reach(const float *__restrict__ pb
     if (lane == 0) tthr[T] = m;
 }
 
+// Final round, tile pairs on the device.  k_fr_keep flags the pairs of two
+// different components (I < J; tiles hold single components).
+__global__ void k_fr_keep(const int2 *__restrict__ pairs, int64_t np, const int32_t *__restrict__ tco,
+                          int32_t *__restrict__ flag) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const int2 pr = pairs[k];
+    flag[k] = pr.x < pr.y && tco[pr.x] != tco[pr.y] ? 1 : 0;
+}
+
+// Per pair of components, its tile pair of least LB^2 (NaN as +inf; ties to
+// the first): the low word of best holds its index.
+__global__ void k_fr_best(const int2 *__restrict__ pairs, int64_t np, const int32_t *__restrict__ tco,
+                          const float *__restrict__ plb, unsigned long long *__restrict__ best) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const int2 pr = pairs[k];
+    const float l = plb[k];
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint(l == l ? l : SCR_INF) << 32) | (unsigned long long)(uint32_t)k;
+    atomicMin(&best[fr_pair(tco[pr.x], tco[pr.y])], key);
+}
+
+// Phase 1 (B == nullptr): the pairs whose balls meet and each pair of
+// components' pair of least LB; phase 2: the others with LB^2 <= B dn, B the
+// bottleneck bound of their pair of components.  Counts the point pairs of
+// the selected ones (C_PAIRS).
+__global__ void k_fr_select(const int2 *__restrict__ pairs, int64_t np, const int32_t *__restrict__ tco,
+                            const float *__restrict__ plb, const unsigned long long *__restrict__ best,
+                            const float *__restrict__ B, float dn, const int32_t *__restrict__ tcnt,
+                            int32_t *__restrict__ flag, int32_t *__restrict__ counters) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long npp = 0;
+    if (k < np) {
+        const int2 pr = pairs[k];
+        const int pc = fr_pair(tco[pr.x], tco[pr.y]);
+        const float l = plb[k];
+        const bool first = l <= 0.0f || (uint32_t)(best[pc] & 0xFFFFFFFFull) == (uint32_t)k;
+        const bool sel = B ? (!first && l <= B[pc] * dn) : first;
+        flag[k] = sel ? 1 : 0;
+        if (sel) npp = (unsigned long long)tcnt[pr.x] * (unsigned long long)tcnt[pr.y];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) npp += __shfl_xor(npp, o, 64);
+    if ((threadIdx.x & 63) == 0 && npp) atomicAdd(reinterpret_cast<unsigned long long *>(&counters[C_PAIRS]), npp);
+}
+
+// Stable compaction of the flagged pairs (pos: exclusive scan of flag).
+__global__ void k_flag_scatter(const int2 *__restrict__ pairs, int64_t np, const int32_t *__restrict__ flag,
+                               const int32_t *__restrict__ pos, int2 *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < np && flag[k]) out[pos[k]] = pairs[k];
+}
+
 // ------------------------------------------------------------------ plan
 
 size_t rep_bytes(int32_t precision) {
@@ -1803,7 +1857,10 @@ struct MstPlan {
     uint32_t *ldrop;                // smallest dropped value
     // final round: padded tile order, per (point, component) minima and records
     int32_t *permF, *posF, *tcompF, *fr_pstart, *fr_sstart, *rowj;
-    int2 *pairsF;
+    int2 *pairsF, *pairsFA;         // the final round's tile pairs of two components; every tile pair
+    int32_t *frk, *frpos;           // its selection flags and their exclusive scan
+    unsigned long long *frbest;     // per pair of components: (least LB^2, its tile pair)
+    float *frB;                     // per pair of components: the bottleneck bound
     int64_t ntF_cap;
     int32_t options;                // ISO_MST_NO_LISTS / ISO_MST_NO_FINAL / ISO_MST_NO_ESCALATE
     float *bestc;                   // final round: [component][position] minima, ntF_cap * GT positions per row
@@ -1903,7 +1960,9 @@ struct MstPlan {
             trmax = a.take<float>(npos / GT);
             temax = a.take<float>(npos / GT);
         }
-        scan_scratch = a.take<int32_t>(scan_scratch_bytes(std::max<int64_t>(npairs, n + 1)) / sizeof(int32_t));
+        scan_scratch = a.take<int32_t>(
+            scan_scratch_bytes(std::max<int64_t>(std::max<int64_t>(npairs, n + 1), ntF_cap * (ntF_cap + 1) / 2)) /
+            sizeof(int32_t));
         ltau = a.take<float>(n);
         lscnt = a.take<int32_t>(n);
         ldrop = a.take<uint32_t>(n);
@@ -1915,6 +1974,11 @@ struct MstPlan {
         fr_pstart = a.take<int32_t>(FR_KC);
         fr_sstart = a.take<int32_t>(FR_KC);
         pairsF = a.take<int2>(ntF_cap * (ntF_cap - 1) / 2);
+        pairsFA = a.take<int2>(ntF_cap * (ntF_cap + 1) / 2);
+        frk = a.take<int32_t>(ntF_cap * (ntF_cap + 1) / 2);
+        frpos = a.take<int32_t>(ntF_cap * (ntF_cap + 1) / 2 + 1);
+        frbest = a.take<unsigned long long>(FR_KC * FR_KC);
+        frB = a.take<float>(FR_KC * FR_KC);
         bestc = a.take<float>((size_t)FR_KC * ntF_cap * GT);
         rowd = a.take<double>((size_t)n * FR_KC);
         rowj = a.take<int32_t>((size_t)n * FR_KC);
@@ -2137,13 +2201,9 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     SA.gcj = P.gcj;
     SA.gcl = P.gcl;
     auto screen = [&](bool gather) { launch_screen_rows(SA, gather, s); };
-    {
-        const std::vector<int2> order = make_pair_order(P.n_pad / pair_tile());
-        ISO_REQUIRE((int64_t)order.size() == P.npairs, ISO_ERR_INTERNAL, "tile-pair order has %zu entries",
-                    order.size());
-        HIP_CHECK(hipMemcpyAsync(P.pairs, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-    }
+    ISO_REQUIRE(P.n_pad / pair_tile() == P.nt && P.npairs == P.nt * (P.nt + 1) / 2, ISO_ERR_INTERNAL,
+                "tile-pair order of %lld tiles", (long long)P.nt);
+    launch_pair_order(P.nt, P.pairs, s);
     hipLaunchKernelGGL(k_perm_identity, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad);
     LAUNCH_CHECK();
     std::vector<int32_t> h_piv(PIV), h_rank(PIV, -1);
@@ -2234,6 +2294,67 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     // KQ + 1 tiles spread over the order).
     bool have_q = false;
     double h_eta = 0.0;
+    std::vector<float> h_ref;    // reference centroids, KQ + 1 rows of d
+    std::vector<int32_t> h_refc;  // and their tiles' row counts
+    // the centroids of KQ + 1 tiles spread over the current order (P.cen)
+    auto fetch_ref = [&](int64_t ntiles) {
+        const int nref = KQ + 1;
+        h_ref.assign((size_t)nref * d, 0.0f);
+        h_refc.assign(nref, 0);
+        for (int q = 0; q < nref; ++q) {
+            const int64_t t = (int64_t)q * ntiles / nref;
+            HIP_CHECK(hipMemcpyAsync(h_ref.data() + (size_t)q * d, P.cen + t * d, sizeof(float) * d,
+                                     hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(&h_refc[q], P.tcnt + t, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+    };
+    // Q by Gram-Schmidt (twice) in FP64 of the differences of the reference
+    // centroids to the first (directions that vanish stay zero rows), eta, and
+    // z = Q x of every point (queued on the stream)
+    std::vector<double> hq;  // (the source of Q's copy: lives as long as the call)
+    auto build_q = [&]() {
+        const int nref = KQ + 1;
+        hq.assign((size_t)KQ * d, 0.0);
+        std::vector<double> v(d);
+        std::vector<int> live;
+        for (int q = 1; q < nref && h_refc[0] > 0; ++q) {
+            if (h_refc[q] == 0) continue;
+            double n0 = 0.0;
+            for (int64_t k = 0; k < d; ++k) {
+                v[k] = (double)h_ref[(size_t)q * d + k] - (double)h_ref[k];
+                n0 += v[k] * v[k];
+            }
+            for (int pass = 0; pass < 2; ++pass)
+                for (int j : live) {
+                    const double *qj = hq.data() + (size_t)j * d;
+                    double t = 0.0;
+                    for (int64_t k = 0; k < d; ++k) t += qj[k] * v[k];
+                    for (int64_t k = 0; k < d; ++k) v[k] -= t * qj[k];
+                }
+            double nv = 0.0;
+            for (int64_t k = 0; k < d; ++k) nv += v[k] * v[k];
+            if (!(nv > 1e-16 * n0) || !(nv > 0.0)) continue;
+            const int row = (int)live.size();
+            const double inv = 1.0 / std::sqrt(nv);
+            for (int64_t k = 0; k < d; ++k) hq[(size_t)row * d + k] = v[k] * inv;
+            live.push_back(row);
+        }
+        // eta >= ||Q Q' - I|| over the nonzero rows (bounded by KQ times the largest entry)
+        double emax = 0.0;
+        for (int i : live)
+            for (int j : live) {
+                if (j < i) continue;
+                double t = 0.0;
+                for (int64_t k = 0; k < d; ++k) t += hq[(size_t)i * d + k] * hq[(size_t)j * d + k];
+                emax = std::max(emax, std::fabs(t - (i == j ? 1.0 : 0.0)));
+            }
+        h_eta = (double)KQ * emax * 2.0 + 1e-13;
+        HIP_CHECK(hipMemcpyAsync(P.Q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, ld, P.Q, P.z);
+        LAUNCH_CHECK();
+        have_q = true;
+    };
     auto tile_bounds = [&](const int32_t *order, int64_t ntiles, const int2 *pairs, int64_t npr, bool support) {
         hipLaunchKernelGGL(k_tile_centroid, dim3((unsigned)ntiles, (unsigned)((d + 255) / 256)), dim3(256), 0, s, X, n,
                            d, ld, order, P.cen, P.tcnt);
@@ -2244,56 +2365,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         LAUNCH_CHECK();
         support = support && ntiles <= P.ntF_cap;
         if (support && !have_q) {
-            // Gram-Schmidt (twice) in FP64 of the differences of the reference
-            // centroids to the first; directions that vanish stay zero rows
-            const int nref = KQ + 1;
-            std::vector<float> hc((size_t)nref * d);
-            std::vector<int32_t> hcnt(nref);
-            for (int q = 0; q < nref; ++q) {
-                const int64_t t = (int64_t)q * ntiles / nref;
-                HIP_CHECK(hipMemcpyAsync(hc.data() + (size_t)q * d, P.cen + t * d, sizeof(float) * d,
-                                         hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipMemcpyAsync(&hcnt[q], P.tcnt + t, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            }
-            HIP_CHECK(hipStreamSynchronize(s));
-            std::vector<double> hq((size_t)KQ * d, 0.0), v(d);
-            std::vector<int> live;
-            for (int q = 1; q < nref && hcnt[0] > 0; ++q) {
-                if (hcnt[q] == 0) continue;
-                double n0 = 0.0;
-                for (int64_t k = 0; k < d; ++k) {
-                    v[k] = (double)hc[(size_t)q * d + k] - (double)hc[k];
-                    n0 += v[k] * v[k];
-                }
-                for (int pass = 0; pass < 2; ++pass)
-                    for (int j : live) {
-                        const double *qj = hq.data() + (size_t)j * d;
-                        double t = 0.0;
-                        for (int64_t k = 0; k < d; ++k) t += qj[k] * v[k];
-                        for (int64_t k = 0; k < d; ++k) v[k] -= t * qj[k];
-                    }
-                double nv = 0.0;
-                for (int64_t k = 0; k < d; ++k) nv += v[k] * v[k];
-                if (!(nv > 1e-16 * n0) || !(nv > 0.0)) continue;
-                const int row = (int)live.size();
-                const double inv = 1.0 / std::sqrt(nv);
-                for (int64_t k = 0; k < d; ++k) hq[(size_t)row * d + k] = v[k] * inv;
-                live.push_back(row);
-            }
-            // eta >= ||Q Q' - I|| over the nonzero rows (bounded by KQ times the largest entry)
-            double emax = 0.0;
-            for (int i : live)
-                for (int j : live) {
-                    double t = 0.0;
-                    for (int64_t k = 0; k < d; ++k) t += hq[(size_t)i * d + k] * hq[(size_t)j * d + k];
-                    emax = std::max(emax, std::fabs(t - (i == j ? 1.0 : 0.0)));
-                }
-            h_eta = (double)KQ * emax * 2.0 + 1e-13;
-            HIP_CHECK(hipMemcpyAsync(P.Q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, ld, P.Q, P.z);
-            LAUNCH_CHECK();
-            HIP_CHECK(hipStreamSynchronize(s));  // (hq is the source of the copy above)
-            have_q = true;
+            fetch_ref(ntiles);
+            build_q();
         }
         if (support) {
             hipLaunchKernelGGL(k_tile_project, dim3((unsigned)ntiles), dim3(256), 0, s, P.cen, P.tcnt, d, P.Q, P.zc,
@@ -2329,7 +2402,6 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         return {(int64_t)hk[0], (int64_t)hk[1]};
     };
     EventPair scr2(timed);
-    double fr_pairs = 0.0;  // point pairs the pruned final round screened
 
     // The final round (at most FR_KC components left): true when it joined
     // them all, false when a point's candidate list overflowed (the round is
@@ -2355,14 +2427,27 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         const int64_t ntF = (int64_t)tco.size();
         ISO_REQUIRE(srt == n && ntF <= P.ntF_cap, ISO_ERR_INTERNAL, "final-round tile order (%lld points, %lld tiles)",
                     (long long)srt, (long long)ntF);
-        std::vector<int2> fpairs;
-        for (const int2 &pr : make_pair_order(ntF))
-            if (pr.x < pr.y && tco[pr.x] != tco[pr.y]) fpairs.push_back(pr);
         HIP_CHECK(hipMemcpyAsync(P.fr_pstart, pst.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
         HIP_CHECK(hipMemcpyAsync(P.fr_sstart, sst.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
         HIP_CHECK(hipMemcpyAsync(P.tcompF, tco.data(), sizeof(int32_t) * ntF, hipMemcpyHostToDevice, s));
-        if (!fpairs.empty())
-            HIP_CHECK(hipMemcpyAsync(P.pairsF, fpairs.data(), sizeof(int2) * fpairs.size(), hipMemcpyHostToDevice, s));
+        // flagged tile pairs of `pairs` (np) into out, in order; returns their count
+        auto fr_compact = [&](const int2 *pairs, int64_t np, int2 *out) -> int64_t {
+            exclusive_scan_i32(P.frk, P.frpos, np, P.frpos + np, P.scan_scratch, s);
+            hipLaunchKernelGGL(k_flag_scatter, dim3(grid_for(np, 256)), dim3(256), 0, s, pairs, np, P.frk, P.frpos,
+                               out);
+            LAUNCH_CHECK();
+            int32_t c = 0;
+            HIP_CHECK(hipMemcpyAsync(&c, P.frpos + np, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            ISO_REQUIRE(c >= 0 && c <= np, ISO_ERR_INTERNAL, "final-round tile-pair compaction");
+            return c;
+        };
+        // the tile pairs of two different components, in the tile-pair order
+        const int64_t nall = ntF * (ntF + 1) / 2;
+        launch_pair_order(ntF, P.pairsFA, s);
+        hipLaunchKernelGGL(k_fr_keep, dim3(grid_for(nall, 256)), dim3(256), 0, s, P.pairsFA, nall, P.tcompF, P.frk);
+        LAUNCH_CHECK();
+        const int64_t nF = fr_compact(P.pairsFA, nall, P.pairsF);
         // points sorted by component, then placed at their padded positions
         // (padding positions hold the padding row n_pad - 1: +inf distances)
         int kb = 1;
@@ -2392,7 +2477,6 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         fill<uint32_t>(reinterpret_cast<uint32_t *>(P.bestc), 0x7F800000u, (int64_t)K * bstride, s);
         fill<uint32_t>(P.upair, 0x7F800000u, FR_KC * FR_KC, s);
         fill<int32_t>(P.ccnt, 0, n, s);
-        const int64_t nF = (int64_t)fpairs.size();
         const bool fr_pruned = prune && nF > 0;
         if (fr_pruned) {
             // Pruned per pair of components (a, b): the first phase screens the
@@ -2406,37 +2490,21 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             // then gives every MST edge exactly, and every other pair of
             // components at most a heavier edge, which Kruskal leaves out.
             tile_bounds(P.permF, ntF, P.pairsF, nF, true);
-            std::vector<float> hl(nF);
-            HIP_CHECK(hipMemcpyAsync(hl.data(), P.plb, sizeof(float) * nF, hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
-            std::vector<int32_t> tcn(ntF);  // rows per tile (a component's last tile is partly padding)
-            for (int64_t t = 0; t < ntF; ++t)
-                tcn[t] = (int32_t)std::min<int64_t>(GT, (int64_t)hs[tco[t]] - (t * GT - pst[tco[t]]));
-            auto lbv = [&](int64_t k) { return std::isnan(hl[k]) ? SCR_INF : hl[k]; };
-            auto cpair = [&](int64_t k) { return fr_pair(tco[fpairs[k].x], tco[fpairs[k].y]); };
-            std::vector<int64_t> bestk(FR_KC * FR_KC, -1);
-            for (int64_t k = 0; k < nF; ++k) {
-                int64_t &b = bestk[cpair(k)];
-                if (b < 0 || lbv(k) < lbv(b)) b = k;
-            }
-            std::vector<char> sel1(nF, 0);
-            std::vector<int2> lst;
-            for (int64_t k = 0; k < nF; ++k)
-                if (hl[k] <= 0.0f || bestk[cpair(k)] == k) {
-                    sel1[k] = 1;
-                    lst.push_back(fpairs[k]);
-                    fr_pairs += (double)tcn[fpairs[k].x] * (double)tcn[fpairs[k].y];
-                }
-            const int64_t n1 = (int64_t)lst.size();
-            if (n1 > 0)
-                HIP_CHECK(hipMemcpyAsync(P.pairsF2, lst.data(), sizeof(int2) * n1, hipMemcpyHostToDevice, s));
+            fill<unsigned long long>(P.frbest, U64_MAX, FR_KC * FR_KC, s);
+            hipLaunchKernelGGL(k_fr_best, dim3(grid_for(nF, 256)), dim3(256), 0, s, P.pairsF, nF, P.tcompF, P.plb,
+                               P.frbest);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_fr_select, dim3(grid_for(nF, 256)), dim3(256), 0, s, P.pairsF, nF, P.tcompF, P.plb,
+                               P.frbest, static_cast<const float *>(nullptr), dn, P.tcnt, P.frk, P.counters);
+            LAUNCH_CHECK();
+            const int64_t n1 = fr_compact(P.pairsF, nF, P.pairsF2);
             scr.start(s);
             launch_screen_pairs(FA, P.pairsF2, 0, n1, s);
             scr.stop(s);
             std::vector<uint32_t> hu(FR_KC * FR_KC);
             HIP_CHECK(hipMemcpyAsync(hu.data(), P.upair, sizeof(uint32_t) * hu.size(), hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
-            std::vector<float> B((size_t)K * K);
+            std::vector<float> B((size_t)K * K), hb(FR_KC * FR_KC, 0.0f);
             for (int a = 0; a < K; ++a)
                 for (int b = 0; b < K; ++b) {
                     float u = 0.0f;
@@ -2444,26 +2512,22 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                     B[(size_t)a * K + b] = u;
                 }
             for (int m = 0; m < K; ++m)
-                for (int a = 0; a < K; ++a)
-                    for (int b = 0; b < K; ++b)
-                        B[(size_t)a * K + b] =
-                            std::min(B[(size_t)a * K + b], std::max(B[(size_t)a * K + m], B[(size_t)m * K + b]));
-            lst.clear();
-            for (int64_t k = 0; k < nF; ++k) {
-                if (sel1[k] || std::isnan(hl[k])) continue;
-                const int a = tco[fpairs[k].x], b = tco[fpairs[k].y];
-                if (hl[k] <= B[(size_t)a * K + b] * dn) {
-                    lst.push_back(fpairs[k]);
-                    fr_pairs += (double)tcn[fpairs[k].x] * (double)tcn[fpairs[k].y];
+                for (int a = 0; a < K; ++a) {
+                    const float bam = B[(size_t)a * K + m];
+                    float *row = B.data() + (size_t)a * K;
+                    const float *rm = B.data() + (size_t)m * K;
+                    for (int b = 0; b < K; ++b) row[b] = std::min(row[b], std::max(bam, rm[b]));
                 }
-            }
-            const int64_t n2 = (int64_t)lst.size();
-            if (n2 > 0)
-                HIP_CHECK(hipMemcpyAsync(P.pairsF2, lst.data(), sizeof(int2) * n2, hipMemcpyHostToDevice, s));
+            for (int a = 0; a < K; ++a)
+                for (int b = a + 1; b < K; ++b) hb[fr_pair(a, b)] = B[(size_t)a * K + b];
+            HIP_CHECK(hipMemcpyAsync(P.frB, hb.data(), sizeof(float) * hb.size(), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_fr_select, dim3(grid_for(nF, 256)), dim3(256), 0, s, P.pairsF, nF, P.tcompF, P.plb,
+                               P.frbest, P.frB, dn, P.tcnt, P.frk, P.counters);
+            LAUNCH_CHECK();
+            const int64_t n2 = fr_compact(P.pairsF, nF, P.pairsF2);  // (synchronises: hb has been read)
             scr2.start(s);
             launch_screen_pairs(FA, P.pairsF2, 0, n2, s);
             scr2.stop(s);
-            HIP_CHECK(hipStreamSynchronize(s));  // (lst is the source of the copy above)
             tp_run += n1 + n2;
             tp_full += nF;
         } else {
@@ -2629,6 +2693,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 std::tie(nmask, noff) = compact(prune ? 1 : 0, rounds == 1);
                 pairs_use = P.pairs_r;
             }
+            // the final round's projection is built from this order's tiles
+            // while the first phase of this round's screen runs
+            const bool want_q = prune && !have_q && !final_off;
+            if (want_q) fetch_ref(P.nt);
             tp_run += nmask + noff;
             if (!prune) tp_full += nmask + noff;  // (pruned rounds: C_TPFULL, read with the round's counters)
             if (lists == LISTS_NONE && rounds == 2) {
@@ -2653,6 +2721,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             scr.start(s);
             launch_screen_pairs(SA, pairs_use, nmask, noff, s);
             scr.stop(s);
+            if (want_q) build_q();
             if (prune) {
                 // the second phase: the reach of every tile from the minima so
                 // far, then the pairs whose bound does not exclude them
@@ -2802,7 +2871,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         unsigned long long pp = 0;
         HIP_CHECK(hipMemcpyAsync(&pp, P.counters + C_PAIRS, sizeof(pp), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        timing().screen_pairs += (double)pp + fr_pairs;
+        timing().screen_pairs += (double)pp;
         timing().screen_dim = (double)P.d_pad;
     }
     const int64_t m = n - 1;

@@ -1026,19 +1026,32 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
 int64_t pair_tile() { return PT; }
 
 // Tile pairs (I <= J) of nt tiles: the nt diagonal pairs first, then the
-// others in blocks of PAIR_SB x PAIR_SB tiles.
-std::vector<int2> make_pair_order(int64_t nt) {
+// others in blocks of PAIR_SB x PAIR_SB tiles, block rows in turn, each by
+// block column, within a block row-major.  Written on the device: one thread
+// per diagonal pair, and one per block pair (bi, bj), bi <= bj, which finds
+// its offset from the counts of the blocks before it.
+__global__ void k_pair_order(int64_t nt, int2 *__restrict__ out) {
     constexpr int64_t SB = PAIR_SB;
-    std::vector<int2> out;
-    out.reserve((size_t)(nt * (nt + 1) / 2));
-    for (int64_t I = 0; I < nt; ++I) out.push_back(make_int2((int)I, (int)I));
     const int64_t nb = (nt + SB - 1) / SB;
-    for (int64_t bi = 0; bi < nb; ++bi)
-        for (int64_t bj = bi; bj < nb; ++bj)
-            for (int64_t I = bi * SB; I < (bi + 1) * SB && I < nt; ++I)
-                for (int64_t J = bj * SB; J < (bj + 1) * SB && J < nt; ++J)
-                    if (I < J) out.push_back(make_int2((int)I, (int)J));
-    return out;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nt) out[q] = make_int2((int)q, (int)q);
+    const int64_t bi = q / nb, bj = q - bi * nb;
+    if (bi >= nb || bj < bi) return;
+    auto sz = [&](int64_t b) { return std::min<int64_t>(SB, nt - b * SB); };
+    auto end = [&](int64_t b) { return std::min<int64_t>(nt, (b + 1) * SB); };
+    int64_t off = nt;
+    for (int64_t b = 0; b < bi; ++b) off += sz(b) * (sz(b) - 1) / 2 + sz(b) * (nt - end(b));
+    if (bj > bi) off += sz(bi) * (sz(bi) - 1) / 2 + sz(bi) * (std::min<int64_t>(nt, bj * SB) - end(bi));
+    for (int64_t I = bi * SB; I < end(bi); ++I)
+        for (int64_t J = bj * SB; J < end(bj); ++J)
+            if (I < J) out[off++] = make_int2((int)I, (int)J);
+}
+
+void launch_pair_order(int64_t nt, int2 *out, hipStream_t s) {
+    const int64_t nb = (nt + PAIR_SB - 1) / PAIR_SB;
+    const int64_t threads = std::max<int64_t>(nt, nb * nb);
+    hipLaunchKernelGGL(k_pair_order, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nt, out);
+    LAUNCH_CHECK();
 }
 
 namespace {
