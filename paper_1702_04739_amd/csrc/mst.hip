@@ -2203,7 +2203,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     auto screen = [&](bool gather) { launch_screen_rows(SA, gather, s); };
     ISO_REQUIRE(P.n_pad / pair_tile() == P.nt && P.npairs == P.nt * (P.nt + 1) / 2, ISO_ERR_INTERNAL,
                 "tile-pair order of %lld tiles", (long long)P.nt);
-    launch_pair_order(P.nt, P.pairs, s);
+    launch_pair_order(P.nt, P.pairs, s, prune);
     hipLaunchKernelGGL(k_perm_identity, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad);
     LAUNCH_CHECK();
     std::vector<int32_t> h_piv(PIV), h_rank(PIV, -1);
@@ -2444,7 +2444,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         };
         // the tile pairs of two different components, in the tile-pair order
         const int64_t nall = ntF * (ntF + 1) / 2;
-        launch_pair_order(ntF, P.pairsFA, s);
+        launch_pair_order(ntF, P.pairsFA, s, prune);
         hipLaunchKernelGGL(k_fr_keep, dim3(grid_for(nall, 256)), dim3(256), 0, s, P.pairsFA, nall, P.tcompF, P.frk);
         LAUNCH_CHECK();
         const int64_t nF = fr_compact(P.pairsFA, nall, P.pairsF);

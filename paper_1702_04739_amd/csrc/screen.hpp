@@ -336,8 +336,9 @@ void launch_screen_rows(const ScreenArgs &A, bool gather, hipStream_t s);
 // ccnt[] zero on entry; both are updated with atomics, indexed by point id.
 int64_t pair_tile();
 // The order of the ntiles (ntiles + 1) / 2 tile pairs (I <= J), written to out
-// on the stream: the diagonal pairs first, then the others in small blocks.
-void launch_pair_order(int64_t ntiles, int2 *out, hipStream_t s);
+// on the stream: the diagonal pairs first, then the others in small blocks,
+// block row by block row, or with `band` by distance from the diagonal.
+void launch_pair_order(int64_t ntiles, int2 *out, hipStream_t s, bool band);
 // pairs: nmask tile pairs screened with the component mask (every diagonal
 // pair, and any pair whose tiles may share a component), then noff pairs whose
 // two tiles share no component, which are screened without it (positions in

@@ -1026,11 +1026,13 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
 int64_t pair_tile() { return PT; }
 
 // Tile pairs (I <= J) of nt tiles: the nt diagonal pairs first, then the
-// others in blocks of PAIR_SB x PAIR_SB tiles, block rows in turn, each by
-// block column, within a block row-major.  Written on the device: one thread
-// per diagonal pair, and one per block pair (bi, bj), bi <= bj, which finds
-// its offset from the counts of the blocks before it.
-__global__ void k_pair_order(int64_t nt, int2 *__restrict__ out) {
+// others in blocks of PAIR_SB x PAIR_SB tiles, within a block row-major.  The
+// blocks go block row by block row (each by block column), or, with `band`,
+// band by band (bj - bi = 0, 1, ...; each by block row): with tiles of nearby
+// points the pairs of near tiles, which set most running minima, come first.
+// Written on the device: one thread per diagonal pair, and one per block pair
+// (bi, bj), bi <= bj, which finds its offset from the counts before it.
+__global__ void k_pair_order(int64_t nt, int band, int2 *__restrict__ out) {
     constexpr int64_t SB = PAIR_SB;
     const int64_t nb = (nt + SB - 1) / SB;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1040,17 +1042,26 @@ __global__ void k_pair_order(int64_t nt, int2 *__restrict__ out) {
     auto sz = [&](int64_t b) { return std::min<int64_t>(SB, nt - b * SB); };
     auto end = [&](int64_t b) { return std::min<int64_t>(nt, (b + 1) * SB); };
     int64_t off = nt;
-    for (int64_t b = 0; b < bi; ++b) off += sz(b) * (sz(b) - 1) / 2 + sz(b) * (nt - end(b));
-    if (bj > bi) off += sz(bi) * (sz(bi) - 1) / 2 + sz(bi) * (std::min<int64_t>(nt, bj * SB) - end(bi));
+    if (band) {
+        // band 0 holds nb - 1 full diagonal blocks and the last one; band x > 0
+        // holds nb - 1 - x full blocks and one against the last block row
+        const int64_t sl = sz(nb - 1), dl = bj - bi;
+        for (int64_t x = 0; x < dl; ++x)
+            off += x == 0 ? (nb - 1) * (SB * (SB - 1) / 2) + sl * (sl - 1) / 2 : (nb - 1 - x) * SB * SB + SB * sl;
+        off += bi * (dl == 0 ? SB * (SB - 1) / 2 : SB * SB);
+    } else {
+        for (int64_t b = 0; b < bi; ++b) off += sz(b) * (sz(b) - 1) / 2 + sz(b) * (nt - end(b));
+        if (bj > bi) off += sz(bi) * (sz(bi) - 1) / 2 + sz(bi) * (std::min<int64_t>(nt, bj * SB) - end(bi));
+    }
     for (int64_t I = bi * SB; I < end(bi); ++I)
         for (int64_t J = bj * SB; J < end(bj); ++J)
             if (I < J) out[off++] = make_int2((int)I, (int)J);
 }
 
-void launch_pair_order(int64_t nt, int2 *out, hipStream_t s) {
+void launch_pair_order(int64_t nt, int2 *out, hipStream_t s, bool band) {
     const int64_t nb = (nt + PAIR_SB - 1) / PAIR_SB;
     const int64_t threads = std::max<int64_t>(nt, nb * nb);
-    hipLaunchKernelGGL(k_pair_order, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nt, out);
+    hipLaunchKernelGGL(k_pair_order, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, nt, band ? 1 : 0, out);
     LAUNCH_CHECK();
 }
 
