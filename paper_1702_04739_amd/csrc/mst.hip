@@ -83,7 +83,7 @@ void fill(T *p, T v, int64_t n, hipStream_t s) {
 
 // ------------------------------------------------------------------ screen representation
 
-constexpr int COL_RB = 1024;   // rows per partial column sum
+constexpr int COL_RB = 256;    // rows per partial column sum
 constexpr int GRID_NONE = 1 << 20;
 
 // Exponent q of the coarsest binary grid 2^q holding the finite float x
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void k_colstats_partial(const float *__restric
     int q = GRID_NONE;
     bool bad = false;
     float mn = __builtin_huge_valf(), mx = -__builtin_huge_valf();
+#pragma unroll 8
     for (int64_t i = lo; i < hi; ++i) {
         const float x = X[i * ld + t];
         bad |= !isfinite(x);
@@ -1642,7 +1643,7 @@ __global__ __launch_bounds__(256) void k_tile_support(const int32_t *__restrict_
                                                       const double *__restrict__ z, const double *__restrict__ zc,
                                                       const int32_t *__restrict__ cnt, int64_t nt,
                                                       float *__restrict__ S) {
-    __shared__ float us[GT][KQ + 1];
+    __shared__ __align__(16) float us[GT][KQ + 4];  // (rows 16-byte aligned: vector LDS reads)
     __shared__ int32_t ok[GT];
     const int tid = threadIdx.x;
     const int64_t T = blockIdx.x;
@@ -1650,19 +1651,28 @@ __global__ __launch_bounds__(256) void k_tile_support(const int32_t *__restrict_
         for (int64_t j = tid; j < nt; j += 256) S[T * nt + j] = -SCR_INF;
         return;
     }
+    __shared__ double zt[KQ];
+    if (tid < KQ) zt[tid] = zc[T * KQ + tid];
     {
+        // (loads without branches: a padding row reads point 0 and is left out)
         const int32_t id = order[T * GT + tid];
         const bool valid = id < n;
         ok[tid] = valid ? 1 : 0;
+        const double *zi = z + (valid ? (int64_t)id : 0) * KQ;
+        double v[KQ];
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) us[tid][q] = valid ? (float)(z[(int64_t)id * KQ + q] - zc[T * KQ + q]) : 0.0f;
+        for (int q = 0; q < KQ; ++q) v[q] = zi[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) us[tid][q] = valid ? (float)(v[q] - zt[q]) : 0.0f;
     }
     __syncthreads();
     for (int64_t J = tid; J - tid < nt; J += 256) {
         const bool live = J < nt;
+        const double *zj = zc + (live ? J : T) * KQ;
         float g[KQ];
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) g[q] = live ? (float)(zc[J * KQ + q] - zc[T * KQ + q]) : 0.0f;
+        for (int q = 0; q < KQ; ++q) g[q] = (float)(zj[q] - zt[q]);
         float m = -SCR_INF;
         for (int r = 0; r < GT; ++r) {
             float t = 0.0f;
@@ -1674,67 +1684,111 @@ __global__ __launch_bounds__(256) void k_tile_support(const int32_t *__restrict_
     }
 }
 
+// Squared distances between the stored tile centroids, FP64 sums of the
+// (exact) FP64 differences, rounded down to FP32: Dm[I][J] for I, J < nt (both
+// halves).  Grid (ceil(nt / 32), ceil(nt / 32)); 32 x 32 tile pairs per
+// workgroup, thread t: row 32 t / 256, columns 4 (t mod 8) .. +3; 32
+// coordinates at a time through LDS.
+__global__ __launch_bounds__(256) void k_tile_dist(const float *__restrict__ cen, int64_t nt, int64_t d,
+                                                   float *__restrict__ Dm) {
+    __shared__ float sa[32][33];
+    __shared__ float sb[32][33];
+    const int tid = threadIdx.x, i = tid >> 3, jg = tid & 7;
+    const int64_t I0 = (int64_t)blockIdx.x * 32, J0 = (int64_t)blockIdx.y * 32;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k0 = 0; k0 < d; k0 += 32) {
+        float va[4], vb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e, r = idx >> 5, c = idx & 31;
+            const int64_t k = k0 + c;
+            const bool oka = I0 + r < nt && k < d, okb = J0 + r < nt && k < d;
+            va[e] = cen[oka ? (I0 + r) * d + k : 0];
+            vb[e] = cen[okb ? (J0 + r) * d + k : 0];
+            va[e] = oka ? va[e] : 0.0f;
+            vb[e] = okb ? vb[e] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e, r = idx >> 5, c = idx & 31;
+            sa[r][c] = va[e];
+            sb[r][c] = vb[e];
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int c = 0; c < 32; ++c) {
+            const double x = (double)sa[i][c];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const double t = x - (double)sb[4 * jg + jj][c];
+                acc[jj] = fma(t, t, acc[jj]);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t I = I0 + i;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        const int64_t J = J0 + 4 * jg + jj;
+        if (I < nt && J < nt) {
+            float f = (float)acc[jj];
+            if ((double)f > acc[jj]) f = nextafterf(f, 0.0f);
+            Dm[I * nt + J] = f;
+        }
+    }
+}
+
 // LB^2 of every tile pair, rounded down to FP32: the larger of the ball bound
-// (LB = ||c_I - c_J|| - rad_I - rad_J, FP64, the distance narrowed and the
-// radii widened by their rounding bounds) and, when S is given, the support
-// bound above; 0 when neither excludes anything; NaN when a tile has no row
-// (such a pair holds no pair of points and is never screened).  One wave per
-// pair; nt is the row stride of S.
+// (LB = ||c_I - c_J|| - rad_I - rad_J, the distance from Dm narrowed by the
+// rounding of its FP64 sum and of its FP32 storage, the radii widened) and,
+// when S is given, the support bound above; 0 when neither excludes anything;
+// NaN when a tile has no row (such a pair holds no pair of points and is never
+// screened).  One thread per pair; nt is the row stride of Dm and S.
 __global__ __launch_bounds__(256) void k_pair_lb(const int2 *__restrict__ pairs, int64_t npairs,
-                                                 const float *__restrict__ cen, const float *__restrict__ rad,
+                                                 const float *__restrict__ Dm, const float *__restrict__ rad,
                                                  const int32_t *__restrict__ cnt, int64_t d,
                                                  const float *__restrict__ S, const double *__restrict__ zc,
                                                  const double *__restrict__ cn, int64_t nt, double eta,
                                                  float *__restrict__ plb) {
-    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= npairs) return;
     const int2 pr = pairs[k];
     const bool empty = cnt[pr.x] == 0 || cnt[pr.y] == 0;
     if (empty || pr.x == pr.y) {
-        if (lane == 0) plb[k] = empty ? __builtin_nanf("") : 0.0f;
+        plb[k] = empty ? __builtin_nanf("") : 0.0f;
         return;
     }
+    const double s = (double)Dm[(int64_t)pr.x * nt + pr.y];  // <= |c_I - c_J|^2 (1 + (d + 4) 2^-53)
     const float rI = rad[pr.x], rJ = rad[pr.y];
-    const float *a = cen + (int64_t)pr.x * d, *b = cen + (int64_t)pr.y * d;
-    double s = 0.0;
-    for (int64_t t = lane; t < d; t += 64) {
-        const double u = (double)a[t] - (double)b[t];
-        s = fma(u, u, s);
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-    double g2 = 0.0;
+    const double dist = sqrt(s) * (1.0 - (double)(d + 68) * 0x1p-52);
+    const double rs = ((double)rI + (double)rJ) * (1.0 + 0x1p-52);
+    const double lb = dist - rs;
+    double l2 = lb > 0.0 ? lb * lb * (1.0 - 0x1p-50) : 0.0;
     if (S) {
-        const double gq = lane < KQ ? zc[(int64_t)pr.x * KQ + lane] - zc[(int64_t)pr.y * KQ + lane] : 0.0;
-        g2 = gq * gq;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) g2 += __shfl_xor(g2, o, 64);
-    }
-    if (lane == 0) {
-        const double dist = sqrt(s) * (1.0 - (double)(d + 68) * 0x1p-52);
-        const double rs = ((double)rI + (double)rJ) * (1.0 + 0x1p-52);
-        const double lb = dist - rs;
-        double l2 = lb > 0.0 ? lb * lb * (1.0 - 0x1p-50) : 0.0;
-        if (S) {
-            // (the absolute slack 1e-10 mag^2 under the root covers the
-            // rounding of g2 = |Q Delta|^2, below 1e-11 mag^2)
-            const double sIJ = (double)S[(int64_t)pr.x * nt + pr.y], sJI = (double)S[(int64_t)pr.y * nt + pr.x];
-            const double mag = cn[pr.x] + cn[pr.y] + rs + 1.0;
-            const double perp =
-                sqrt(fmax(0.0, s * (1.0 + 1e-11) - g2 * (1.0 - eta) + 1e-10 * mag * mag)) * (1.0 + 1e-12);
-            // (4e-5 mag^2 covers twice the two FP32 supports, each within 3e-6 mag^2)
-            const double sup = s * (1.0 - 1e-11) - 2.0 * (sIJ + sJI) - 2.0 * perp * rs -
-                               1e-9 * (s + 2.0 * (fabs(sIJ) + fabs(sJI))) - 4e-5 * mag * mag;
-            l2 = fmax(l2, sup);
+        // (the absolute slack 1e-10 mag^2 under the root covers the rounding
+        // of g2 = |Q Delta|^2, below 1e-11 mag^2; s is at most 2^-24 + (d + 4)
+        // 2^-53 below |Delta|^2 and enters the root with a margin of 1e-6)
+        double g2 = 0.0;
+        const double *za = zc + (int64_t)pr.x * KQ, *zb = zc + (int64_t)pr.y * KQ;
+#pragma unroll 8
+        for (int q = 0; q < KQ; ++q) {
+            const double t = za[q] - zb[q];
+            g2 = fma(t, t, g2);
         }
-        float f = 0.0f;
-        if (l2 > 0.0) {
-            f = (float)l2;
-            if ((double)f > l2) f = nextafterf(f, 0.0f);
-        }
-        plb[k] = f;
+        const double sIJ = (double)S[(int64_t)pr.x * nt + pr.y], sJI = (double)S[(int64_t)pr.y * nt + pr.x];
+        const double mag = cn[pr.x] + cn[pr.y] + rs + 1.0;
+        const double perp =
+            sqrt(fmax(0.0, s * (1.0 + 1e-6) - g2 * (1.0 - eta) + 1e-10 * mag * mag)) * (1.0 + 1e-12);
+        const double sup = s * (1.0 - 1e-11) - 2.0 * (sIJ + sJI) - 2.0 * perp * rs -
+                           1e-9 * (s + 2.0 * (fabs(sIJ) + fabs(sJI))) - 4e-5 * mag * mag;
+        l2 = fmax(l2, sup);
     }
+    float f = 0.0f;
+    if (l2 > 0.0) {
+        f = (float)l2;
+        if ((double)f > l2) f = nextafterf(f, 0.0f);
+    }
+    plb[k] = f;
 }
 
 // Reach of every tile: the largest R over its points (padding, comp < 0,
@@ -1874,6 +1928,7 @@ struct MstPlan {
     int2 *pairsF2;                  // the final round's tile pairs of one phase
     double *Q, *z, *zc, *cn;        // final round's support bound: projection, points, tiles
     float *S;                       // [ntF_cap][ntF_cap] supports
+    float *Dm;                      // [ntb][ntb] squared distances between tile centroids
     double *rb_d2, *elen, *wsum;
     unsigned long long *ck1, *ck2;
     int32_t *counters;
@@ -2002,6 +2057,7 @@ struct MstPlan {
             zc = a.take<double>((size_t)ntb * KQ);
             cn = a.take<double>(ntb);
             S = a.take<float>((size_t)ntF_cap * (size_t)ntF_cap);
+            Dm = a.take<float>((size_t)ntb * (size_t)ntb);
         }
     }
     // The gathered pass's candidate lists reuse the memory of nothing else:
@@ -2377,8 +2433,11 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             LAUNCH_CHECK();
         }
         if (npr > 0) {
-            hipLaunchKernelGGL(k_pair_lb, dim3(grid_for(npr, 4)), dim3(256), 0, s, pairs, npr, P.cen, P.rad, P.tcnt, d,
-                               support ? P.S : nullptr, P.zc, P.cn, ntiles, h_eta, P.plb);
+            const unsigned tb = (unsigned)((ntiles + 31) / 32);
+            hipLaunchKernelGGL(k_tile_dist, dim3(tb, tb), dim3(256), 0, s, P.cen, ntiles, d, P.Dm);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_pair_lb, dim3(grid_for(npr, 256)), dim3(256), 0, s, pairs, npr, P.Dm, P.rad, P.tcnt,
+                               d, support ? P.S : nullptr, P.zc, P.cn, ntiles, h_eta, P.plb);
             LAUNCH_CHECK();
         }
     };
