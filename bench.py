@@ -65,9 +65,13 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
     prefix = "k_screen_pairs<%d, " % {"fp32": 0, "bf16": 1, "fp8": 2, "int8": 3}[precision]
 
     def per_kernel(d, counter):
-        """Summed counter over the screen's dispatches (diagonal and
-        off-diagonal), the number of screen rounds, and the copy's value."""
-        total, rounds, copy = 0.0, 0, None
+        """Summed counter over the screen's dispatches (both phases of a round,
+        diagonal and off-diagonal), the number of screened rounds, and the
+        copy's value.  A screened round is a run of consecutive screen
+        dispatches of one mode (the profiled step's rounds are plain, list
+        building and final, so the mode changes at every round)."""
+        import re
+        total, copy, modes = 0.0, None, []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
                 if r["Counter_Name"] != counter:
@@ -75,9 +79,12 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
                 v = float(r["Counter_Value"])
                 if prefix in r["Kernel_Name"]:
                     total += v
-                    rounds += 1 if (prefix + "false") in r["Kernel_Name"] else 0
+                    m = re.search(r"k_screen_pairs<\d+, \w+, (\d+)", r["Kernel_Name"])
+                    modes.append((int(r["Dispatch_Id"]), m.group(1) if m else "?"))
                 elif "copyBuffer" in r["Kernel_Name"] and copy is None and v > 0.25 * copy_mib * 1024:
                     copy = v
+        modes.sort()
+        rounds = sum(1 for i, (_, md) in enumerate(modes) if i == 0 or md != modes[i - 1][1])
         return total, rounds, copy
 
     ft, fr, fc = per_kernel(fetch_dir, "FETCH_SIZE")
@@ -100,7 +107,8 @@ def traffic_report(fetch_dir, write_dir, precision, copy_mib):
                "python bench.py --traffic-report <fetch_dir> <write_dir> --precision %s --calibrate-copy %d"
                % (precision, copy_mib)],
            "note": "FETCH_SIZE and WRITE_SIZE summed over the screen's dispatches of every screened round (the "
-                   "plain first round, the second round that also builds the neighbour lists, the final round) "
+                   "plain first round, the second round that also builds the neighbour lists, the final round; "
+                   "each round's two phases and its masked and unmasked dispatches) "
                    "and divided by the number of those rounds; each counter is scaled by what it reads for the "
                    "plain device copy run first in the same process (FETCH_SIZE counts half the copied bytes, "
                    "WRITE_SIZE all).  The algorithmic minimum is one read of the BF16 representation (n_pad x "

@@ -130,20 +130,30 @@ __global__ __launch_bounds__(256) void k_colstats_partial(const float *__restric
 // Centre mu_t: the coordinate mean rounded to the coarsest binary grid 2^q_t
 // that holds every value of the column, so that centring keeps values that
 // sit on a grid (e.g. q/256) on it; 0 for empty columns and beyond d.
-__global__ void k_colstats_final(const double *__restrict__ psum, const int32_t *__restrict__ pgrid, int64_t nrb,
-                                 int64_t n, int64_t d, int64_t d_pad, float *__restrict__ mu) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per coordinate: lane l sums the partials l, l + 64, ... (a fixed
+// order), then the wave combines them.
+__global__ __launch_bounds__(256) void k_colstats_final(const double *__restrict__ psum,
+                                                        const int32_t *__restrict__ pgrid, int64_t nrb, int64_t n,
+                                                        int64_t d, int64_t d_pad, float *__restrict__ mu) {
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (t >= d_pad) return;
     if (t >= d) {
-        mu[t] = 0.0f;
+        if (lane == 0) mu[t] = 0.0f;
         return;
     }
     double s = 0.0;
     int q = GRID_NONE;
-    for (int64_t rb = 0; rb < nrb; ++rb) {
+    for (int64_t rb = lane; rb < nrb; rb += 64) {
         s = s + psum[rb * d + t];
         q = min(q, pgrid[rb * d + t]);
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        q = min(q, __shfl_xor(q, o, 64));
+    }
+    if (lane != 0) return;
     if (q == GRID_NONE) {
         mu[t] = 0.0f;
         return;
@@ -1839,12 +1849,28 @@ __global__ void k_fr_keep(const int2 *__restrict__ pairs, int64_t np, const int3
 __global__ void k_fr_best(const int2 *__restrict__ pairs, int64_t np, const int32_t *__restrict__ tco,
                           const float *__restrict__ plb, unsigned long long *__restrict__ best) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= np) return;
-    const int2 pr = pairs[k];
-    const float l = plb[k];
-    const unsigned long long key =
-        ((unsigned long long)__float_as_uint(l == l ? l : SCR_INF) << 32) | (unsigned long long)(uint32_t)k;
-    atomicMin(&best[fr_pair(tco[pr.x], tco[pr.y])], key);
+    const bool live = k < np;
+    int pc = -1;
+    unsigned long long key = ~0ull;
+    if (live) {
+        const int2 pr = pairs[k];
+        const float l = plb[k];
+        key = ((unsigned long long)__float_as_uint(l == l ? l : SCR_INF) << 32) | (unsigned long long)(uint32_t)k;
+        pc = fr_pair(tco[pr.x], tco[pr.y]);
+    }
+    // consecutive pairs mostly join the same two components: a wave whose
+    // live lanes agree takes its minimum first and issues one atomic
+    const int pc0 = __shfl(pc, 0, 64);
+    if (__all(!live || pc == pc0)) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const unsigned long long ok = __shfl_xor(key, o, 64);
+            key = ok < key ? ok : key;
+        }
+        if ((threadIdx.x & 63) == 0 && pc0 >= 0) atomicMin(&best[pc0], key);
+    } else if (live) {
+        atomicMin(&best[pc], key);
+    }
 }
 
 // Phase 1 (B == nullptr): the pairs whose balls meet and each pair of
@@ -2150,7 +2176,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                     "spanning at most 255 steps");
         if (h_qg != GRID_NONE) inv_step = (float)std::ldexp(1.0, -h_qg);
     } else {
-        hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 256)), dim3(256), 0, s, P.psum, P.pgrid, P.nrb, n,
+        hipLaunchKernelGGL(k_colstats_final, dim3(grid_for(P.d_pad, 4)), dim3(256), 0, s, P.psum, P.pgrid, P.nrb, n,
                            d, P.d_pad, P.mu);
         LAUNCH_CHECK();
     }
