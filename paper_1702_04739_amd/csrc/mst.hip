@@ -1319,7 +1319,7 @@ __global__ void k_pair_scatter(const int2 *__restrict__ pairs, int64_t npairs, c
 // (see run_mst).
 
 constexpr int PIV = 32;              // pivot rows of the first round's order
-constexpr int PRUNE_MIN_TILES = 4;   // fewer tiles: every pair is screened
+constexpr int PRUNE_MIN_TILES = 32;  // fewer tiles (n < 8,192): every pair is screened, which costs less
 constexpr int64_t PRUNE_MAX_D = 8192;  // the tile centroid is held in LDS
 constexpr int64_t PRUNE_MAX_TILES = 8192;  // the final round's supports: ntF^2 floats
 

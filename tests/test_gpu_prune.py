@@ -5,9 +5,10 @@ must be the one every-tile-pair screening builds, bit for bit (parent array and
 FP64 lengths), for every screen precision, with and without the neighbour lists
 and the final round, with pair bounds, and with tiles that hold no point.  On
 clustered data (the image-like recipe: ten separated centres) most tile pairs
-are skipped; against the oracle the pruned tree is checked by the parity tests
-(their cases above 768 points prune) and here on a case whose final round is
-pruned.
+are skipped; against the oracle the pruned tree is checked here on a case whose
+final round is pruned, on a lattice (ties everywhere) and on a mixture with
+outliers, and at full size by the digest tests.  Below 8,192 points (32 tiles)
+every pair is screened.
 """
 import numpy as np
 import pytest
@@ -32,11 +33,14 @@ CASES = {
     "c3-n20000-d784": lambda: datagen.config(3, n=20000),
     "c2-n20000-d64": lambda: datagen.config(2, n=20000),
     "c5-n20000-d128": lambda: datagen.config(5, n=20000),
-    "c1-n2000-d16": lambda: datagen.config(1),
-    "uniform-n4000-d8": lambda: datagen.uniform(4000, 8),
-    "duplicates-n3000": lambda: datagen.with_duplicates(3000, 5, 600),
+    "c1-n10000-d16": lambda: datagen.config(1, n=10000),
+    "uniform-n9000-d8": lambda: datagen.uniform(9000, 8),
+    "duplicates-n9000": lambda: datagen.with_duplicates(9000, 5, 1800),
     # n a multiple of the tile: the padded order ends with a tile of padding only
-    "c3-n1024-d784": lambda: datagen.config(3, n=1024),
+    "c3-n8192-d784": lambda: datagen.config(3, n=8192),
+    # ties everywhere (every lattice edge has length 1) and a degenerate set
+    "lattice-96x96": lambda: datagen.lattice(96, 2),
+    "constant-n9000": lambda: np.full((9000, 6), 0.25, np.float32),
 }
 
 
@@ -86,9 +90,9 @@ def test_pruned_plain_rounds(iso, rounds):
 def test_pruned_pair_bounds(iso):
     """Heavy-tailed norms (the communities recipe): the BF16 screen with pair
     bounds, where a point's reach is its running upper bound."""
-    Xh = datagen.config(4, n=4000)
+    Xh = datagen.config(4, n=9000)
     X = torch.from_numpy(Xh).cuda()
-    H.log("c4 n=4000 d=4096 bf16 pair bounds")
+    H.log("c4 n=9000 d=4096 bf16 pair bounds")
     p0, l0, i0 = _run(iso, X, precision="bf16", recheck="fp32", pair_bounds=True, escalate=False, prune=False)
     p1, l1, i1 = _run(iso, X, precision="bf16", recheck="fp32", pair_bounds=True, escalate=False, prune=True)
     H.log("  full %s" % i0)
@@ -102,11 +106,24 @@ def test_pruned_final_round_matches_oracle(iso):
     """A case whose final round is pruned per pair of components, against the
     oracle's FP64 tree."""
     import oracle
-    Xh = datagen.config(5, n=6000)
+    Xh = datagen.config(5, n=9000)
     op, ol, _, _ = oracle.prim_mst(Xh)
     parent, length, info = iso.mst(torch.from_numpy(Xh).cuda(), precision="bf16", recheck="fp64")
-    H.log("  c5 n=6000 info %s" % info)
+    H.log("  c5 n=9000 info %s" % info)
     assert info["final_components"] > 1
     assert info["tile_pairs"] < info["tile_pairs_full"]
+    np.testing.assert_array_equal(parent.cpu().numpy(), op)
+    np.testing.assert_allclose(length.cpu().numpy(), ol, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("name", ["lattice-96x96", "c1-n10000-d16"])
+def test_pruned_ties_match_oracle(iso, name):
+    """Many equal distances (a square lattice) and a mixture with outliers,
+    FP64 recheck: the pruned tree is the oracle's, edge for edge."""
+    import oracle
+    Xh = CASES[name]()
+    op, ol, _, _ = oracle.prim_mst(Xh)
+    parent, length, info = iso.mst(torch.from_numpy(Xh).cuda(), precision="fp32", recheck="fp64")
+    H.log("  %s info %s" % (name, info))
     np.testing.assert_array_equal(parent.cpu().numpy(), op)
     np.testing.assert_allclose(length.cpu().numpy(), ol, rtol=1e-15, atol=0)
