@@ -490,13 +490,20 @@ def main():
             log("comparison: %s screen%s, 1 warm-up + 1 step" % (prec, "" if pr else ", every tile pair"))
             iso.cluster(X, k, precision=prec, recheck=args.recheck, prune=pr)
             torch.cuda.synchronize()
+            _lib.timing_enable(True)
             c0 = time.perf_counter()
             labc, ikc, infoc = iso.cluster(X, k, precision=prec, recheck=args.recheck, prune=pr)
             torch.cuda.synchronize()
             c1 = time.perf_counter()
+            Tc = _lib.timing_read()
+            _lib.timing_enable(False)
+            # the same screen's roofline in this configuration (its own peak)
+            ach = 2.0 * d * Tc["screen_pairs"] / (Tc["screen_ms"] * 1e-3) / 1e12 if Tc["screen_ms"] > 0 else None
             out["compare"].append({"screen": prec, "prune": pr, "value": n / (c1 - c0),
                                    "ms_per_step": (c1 - c0) * 1e3, "value_ratio": value / (n / (c1 - c0)),
                                    "tile_pairs": infoc["mst"]["tile_pairs"],
+                                   "screen_ms": Tc["screen_ms"], "screen_tflops": ach,
+                                   "screen_frac": ach / PEAKS_TFLOPS[prec] if ach else None,
                                    "same_tree": bool(torch.equal(infoc["parent"], info["parent"])),
                                    "same_labels": bool(torch.equal(labc, labels)), "i_k": ikc})
     if args.paper_prim_n > 0:

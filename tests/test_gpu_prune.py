@@ -127,3 +127,18 @@ def test_pruned_ties_match_oracle(iso, name):
     H.log("  %s info %s" % (name, info))
     np.testing.assert_array_equal(parent.cpu().numpy(), op)
     np.testing.assert_allclose(length.cpu().numpy(), ol, rtol=1e-15, atol=0)
+
+
+def test_pruned_strided_input(iso):
+    """Rows with a stride larger than d (a column slice of a wider array): the
+    pruning kernels read X through ld like the screen and the recheck."""
+    Xw = datagen.config(5, n=9000)
+    wide = np.concatenate([Xw, np.ones((Xw.shape[0], 7), np.float32)], axis=1)
+    Xs = torch.from_numpy(wide).cuda()[:, :Xw.shape[1]]
+    assert Xs.stride(0) == Xw.shape[1] + 7
+    p0, l0, _ = _run(iso, torch.from_numpy(Xw).cuda(), precision="bf16", recheck="fp32", prune=False)
+    p1, l1, i1 = _run(iso, Xs, precision="bf16", recheck="fp32", prune=True)
+    H.log("  strided info %s" % i1)
+    assert i1["tile_pairs"] < i1["tile_pairs_full"]
+    np.testing.assert_array_equal(p1, p0)
+    np.testing.assert_array_equal(l1, l0)
