@@ -187,37 +187,57 @@ __global__ void k_omega_tree(const int32_t *__restrict__ parent, const double *_
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int32_t p = parent[v];
+    const double fv = phi[v];
     double s = 0.0;
     bool parent_done = p < 0;
-    for (int32_t a = koff[v]; a < koff[v + 1]; ++a) {
-        const int32_t c = (int32_t)kids[a];
-        if (!parent_done && p < c) {
-            s = s + phi[v];
-            parent_done = true;
+    // the children in batches of 16: all loads of a batch first (a hub's
+    // children are 40 round trips instead of 629), then the sum in id order
+    const int32_t a1 = koff[v + 1];
+    for (int32_t a0 = koff[v]; a0 < a1; a0 += 16) {
+        int32_t c[16];
+        double f[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c[u] = (int32_t)kids[min(a0 + u, a1 - 1)];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) f[u] = phi[c[u]];
+        const int nb = min(16, a1 - a0);
+        for (int u = 0; u < nb; ++u) {
+            if (!parent_done && p < c[u]) {
+                s = s + fv;
+                parent_done = true;
+            }
+            s = s + f[u];
         }
-        s = s + phi[c];
     }
-    if (!parent_done) s = s + phi[v];
+    if (!parent_done) s = s + fv;
     om0[v] = s;
 }
 
 // Sums and minima of phi (tree edges), omega0 and p0; bracket of Algorithm 2.
-__global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ parent, const double *__restrict__ phi,
-                                                const double *__restrict__ om0, const double *__restrict__ p0,
-                                                int64_t n, int bracket, TreeState *__restrict__ st) {
-    __shared__ double s_sum[3][1024];
-    __shared__ double s_min[3][1024];
+// k_stats_part: STATS_BLOCKS workgroups, each over a contiguous range of the
+// vertices, write partial sums and minima; k_stats (one workgroup) combines
+// them in a fixed order and sets the bracket.
+constexpr int STATS_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_stats_part(const int32_t *__restrict__ parent, const double *__restrict__ phi,
+                                                    const double *__restrict__ om0, const double *__restrict__ p0,
+                                                    int64_t n, double *__restrict__ part) {
+    __shared__ double s_sum[3][256];
+    __shared__ double s_min[3][256];
+    const int64_t per = (n + STATS_BLOCKS - 1) / STATS_BLOCKS;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
     double ps = 0.0, os = 0.0, qs = 0.0;
     double pm = __builtin_huge_val(), om = __builtin_huge_val(), qm = __builtin_huge_val();
-    for (int64_t v = threadIdx.x; v < n; v += 1024) {
+    for (int64_t v = lo + threadIdx.x; v < hi; v += 256) {
+        const double f = phi[v], o = om0[v], q = p0[v];
         if (parent[v] >= 0) {
-            ps = ps + phi[v];
-            pm = fmin(pm, phi[v]);
+            ps = ps + f;
+            pm = fmin(pm, f);
         }
-        os = os + om0[v];
-        om = fmin(om, om0[v]);
-        qs = qs + p0[v];
-        qm = fmin(qm, p0[v]);
+        os = os + o;
+        om = fmin(om, o);
+        qs = qs + q;
+        qm = fmin(qm, q);
     }
     s_sum[0][threadIdx.x] = ps;
     s_sum[1][threadIdx.x] = os;
@@ -226,7 +246,32 @@ __global__ __launch_bounds__(1024) void k_stats(const int32_t *__restrict__ pare
     s_min[1][threadIdx.x] = om;
     s_min[2][threadIdx.x] = qm;
     __syncthreads();
-    for (int w = 512; w >= 1; w >>= 1) {
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 3; ++q) {
+                s_sum[q][threadIdx.x] = s_sum[q][threadIdx.x] + s_sum[q][threadIdx.x + w];
+                s_min[q][threadIdx.x] = fmin(s_min[q][threadIdx.x], s_min[q][threadIdx.x + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        part[blockIdx.x * 6 + threadIdx.x] = s_sum[threadIdx.x][0];
+        part[blockIdx.x * 6 + 3 + threadIdx.x] = s_min[threadIdx.x][0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_stats(const double *__restrict__ part, int bracket,
+                                               TreeState *__restrict__ st) {
+    static_assert(STATS_BLOCKS == 256, "one partial per thread");
+    __shared__ double s_sum[3][256];
+    __shared__ double s_min[3][256];
+    for (int q = 0; q < 3; ++q) {
+        s_sum[q][threadIdx.x] = part[threadIdx.x * 6 + q];
+        s_min[q][threadIdx.x] = part[threadIdx.x * 6 + 3 + q];
+    }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) {
             for (int q = 0; q < 3; ++q) {
                 s_sum[q][threadIdx.x] = s_sum[q][threadIdx.x] + s_sum[q][threadIdx.x + w];
@@ -730,6 +775,7 @@ struct SubPlan {
     int32_t *nchild, *koff, *slot, *level_start, *cf, *rank, *cidx, *rep0, *rep1, *cnt, *cl_size_tmp, *lab_tmp, *scan_scratch;
     double2 *cpw;
     double *phi, *om0, *p0, *Nvals, *num, *den, *cl_num_tmp, *cl_den_tmp;
+    double *stats_part;             // [STATS_BLOCKS][6] partial sums and minima
     uint8_t *cut, *joined;
     TreeState *st;
     void *sort_scratch, *sel_scratch;
@@ -771,6 +817,7 @@ struct SubPlan {
         den = a.take<double>(n);
         cl_num_tmp = a.take<double>(k);
         cl_den_tmp = a.take<double>(k);
+        stats_part = a.take<double>(STATS_BLOCKS * 6);
         cut = a.take<uint8_t>(n);
         joined = a.take<uint8_t>(n);
         st = a.take<TreeState>(1);
@@ -912,7 +959,9 @@ void run_sub(SubPlan &P, const int32_t *parent, const double *length, int32_t ro
         hipLaunchKernelGGL(k_omega_tree, dim3(gn), dim3(256), 0, s, parent, P.phi, kids, P.koff, n, P.om0);
         LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, parent, P.phi, om0, p0, n, o.bracket, P.st);
+    hipLaunchKernelGGL(k_stats_part, dim3(STATS_BLOCKS), dim3(256), 0, s, parent, P.phi, om0, p0, n, P.stats_part);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(256), 0, s, P.stats_part, o.bracket, P.st);
     LAUNCH_CHECK();
     std::vector<int32_t> ls(maxdepth + 2);
     HIP_CHECK(hipMemcpyAsync(ls.data(), P.level_start, sizeof(int32_t) * (maxdepth + 2), hipMemcpyDeviceToHost, s));
