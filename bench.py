@@ -24,8 +24,10 @@ sys.path.insert(0, ROOT)
 METRIC = "points/s for MST+subpartition (n=200k,d=784) BF16-refined vs FP32; % MFMA peak"
 WORKLOAD = 3
 PEAKS_TFLOPS = {"int8": 5000.0, "fp8": 5000.0, "bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
-# one screen launch = the diagonal tile pairs' dispatch followed by the off-diagonal one
-SCREEN_KERNEL = "k_screen_pairs<%s> (diagonal + off-diagonal dispatch)"
+# one screen "launch" = one screened round: its two phases (the tile pairs whose
+# bounding balls meet, then those the bound does not exclude), each with the
+# off-diagonal dispatch and the diagonal (masked) one
+SCREEN_KERNEL = "k_screen_pairs<%s> (one screened round: both phases, masked + unmasked dispatches)"
 SCREEN_SOURCES = ["paper_1702_04739_amd/csrc/screen_pairs.hip", "paper_1702_04739_amd/csrc/screen.hpp"]
 
 
