@@ -832,6 +832,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             S.cE[t] = etile[e];
             if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
             if (lst) atomicOr(&S.clst[t >> 5], 1u << (t & 31));
+            // (the columns' s are no longer read: their slots take the
+            // columns' list thresholds for the list scan)
+            if constexpr (LIST) S.csq[t] = pre_tau[e];
         }
     }
     if constexpr (FINAL) {
@@ -999,7 +1002,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
         for (int jb = 0; jb < NJB; ++jb)
             scan_col(jb, S.clst[(CW * wj) / 32 + jb], [&](int jl, const float (&v)[NIB], bool mine) {
                 const int64_t j = S.cid[jl];
-                const float tau = A.pltau[J0 + jl];
+                const float tau = S.csq[jl];  // the column's list threshold (see the merge)
 #pragma unroll
                 for (int ib = 0; ib < NIB; ++ib)
                     if (mine && v[ib] <= tau) stage(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v[ib]);
