@@ -2123,6 +2123,36 @@ size_t plan_bytes(MstPlan p) {
 constexpr double ESCALATE_GATHER = 0.25, ESCALATE_RESCAN = 1.0 / 64.0;
 constexpr double PB_RATIO = 4.0;  // separable / typical bound above which BF16 uses pair bounds
 
+// A second stream for the pruning's work that reads only X (the points'
+// nearest pivots, their projection z = Q x), so that it overlaps the main
+// stream's work; events order it after its inputs and before its consumers.
+// Non-blocking, default priority; the destructor waits for it (the workspace
+// it writes may be freed after the call) and releases it.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr;
+    void start() {
+        HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&ev_key, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&ev_z, hipEventDisableTiming));
+    }
+    // work queued on s from now on runs after the main stream's work so far
+    void after(hipStream_t main) {
+        HIP_CHECK(hipEventRecord(ev0, main));
+        HIP_CHECK(hipStreamWaitEvent(s, ev0, 0));
+    }
+    ~AuxStream() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev_key) (void)hipEventDestroy(ev_key);
+        if (ev_z) (void)hipEventDestroy(ev_z);
+    }
+};
+
 void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t *parent, double *length,
              iso_mst_info *info, hipStream_t s, bool *escalate) {
     const int64_t n = P.n, d = P.d, ld = P.ld;
@@ -2146,6 +2176,21 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     P.gcl = reinterpret_cast<float *>(gbuf + (size_t)n * SCR_CAP2 * sizeof(int32_t));
 
     fill<int32_t>(P.counters, 0, C_COUNT, s);
+    // The pruned first round orders the points by their nearest pivot (rows
+    // q n / PIV); that assignment reads only X and runs on the second stream
+    // while the main stream computes the representation.
+    AuxStream aux;
+    std::vector<int32_t> h_piv(PIV), h_rank(PIV, -1);
+    if (prune) {
+        aux.start();
+        for (int q = 0; q < PIV; ++q) h_piv[q] = (int32_t)((int64_t)q * n / PIV);
+        HIP_CHECK(hipMemcpyAsync(P.piv, h_piv.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
+        aux.after(s);
+        hipLaunchKernelGGL(k_pivot_near, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, aux.s, X, d, ld,
+                           static_cast<const int32_t *>(nullptr), n, P.piv, P.pkeys, static_cast<float *>(nullptr));
+        LAUNCH_CHECK();
+        HIP_CHECK(hipEventRecord(aux.ev_key, aux.s));
+    }
     fill<uint32_t>(P.rmax, 0u, 1, s);
     fill<uint32_t>(P.emax, 0u, 1, s);
     fill<int32_t>(P.grid_min, GRID_NONE, 1, s);
@@ -2288,14 +2333,12 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     launch_pair_order(P.nt, P.pairs, s, prune);
     hipLaunchKernelGGL(k_perm_identity, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad);
     LAUNCH_CHECK();
-    std::vector<int32_t> h_piv(PIV), h_rank(PIV, -1);
     if (prune) {
-        // The first round's order: the points by their nearest pivot (rows
-        // q n / PIV), the pivots in a nearest-neighbour chain from the first;
-        // component labels follow the order.
-        for (int q = 0; q < PIV; ++q) h_piv[q] = (int32_t)((int64_t)q * n / PIV);
-        HIP_CHECK(hipMemcpyAsync(P.piv, h_piv.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_pivot_near, dim3(1), dim3(256), 0, s, X, d, ld, P.piv, (int64_t)PIV, P.piv, P.pkeys,
+        // The first round's order: the points by their nearest pivot, the
+        // pivots in a nearest-neighbour chain from the first; component labels
+        // follow the order.  (The pivots' own distances: keys into the sort's
+        // spare keys, which the assignment on the second stream does not touch.)
+        hipLaunchKernelGGL(k_pivot_near, dim3(1), dim3(256), 0, s, X, d, ld, P.piv, (int64_t)PIV, P.piv, P.ptk,
                            P.pivd);
         LAUNCH_CHECK();
         std::vector<float> pd((size_t)PIV * PIV);
@@ -2311,9 +2354,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             cur = nx;
         }
         HIP_CHECK(hipMemcpyAsync(P.piv_rank, h_rank.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_pivot_near, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, s, X, d, ld,
-                           static_cast<const int32_t *>(nullptr), n, P.piv, P.pkeys, static_cast<float *>(nullptr));
-        LAUNCH_CHECK();
+        HIP_CHECK(hipStreamWaitEvent(s, aux.ev_key, 0));  // every point's nearest pivot
         hipLaunchKernelGGL(k_pivot_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, P.pkeys, P.piv_rank, n, P.perm);
         LAUNCH_CHECK();
         radix_sort_pairs_u32(P.pkeys, reinterpret_cast<uint32_t *>(P.perm), P.ptk, P.ptv, n, 5, P.psort, s);
@@ -2433,8 +2474,11 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             }
         h_eta = (double)KQ * emax * 2.0 + 1e-13;
         HIP_CHECK(hipMemcpyAsync(P.Q, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, ld, P.Q, P.z);
+        // z on the second stream (it reads X and Q only); the supports wait for it
+        aux.after(s);
+        hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, aux.s, X, n, d, ld, P.Q, P.z);
         LAUNCH_CHECK();
+        HIP_CHECK(hipEventRecord(aux.ev_z, aux.s));
         have_q = true;
     };
     auto tile_bounds = [&](const int32_t *order, int64_t ntiles, const int2 *pairs, int64_t npr, bool support) {
@@ -2454,6 +2498,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             hipLaunchKernelGGL(k_tile_project, dim3((unsigned)ntiles), dim3(256), 0, s, P.cen, P.tcnt, d, P.Q, P.zc,
                                P.cn);
             LAUNCH_CHECK();
+            HIP_CHECK(hipStreamWaitEvent(s, aux.ev_z, 0));
             hipLaunchKernelGGL(k_tile_support, dim3((unsigned)ntiles), dim3(256), 0, s, order, n, P.z, P.zc, P.tcnt,
                                ntiles, P.S);
             LAUNCH_CHECK();
