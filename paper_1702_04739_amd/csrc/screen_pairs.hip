@@ -833,8 +833,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             if (hot) atomicOr(&S.chot[t >> 5], 1u << (t & 31));
             if (lst) atomicOr(&S.clst[t >> 5], 1u << (t & 31));
             // (the columns' s are no longer read: their slots take the
-            // columns' list thresholds for the list scan)
-            if constexpr (LIST) S.csq[t] = pre_tau[e];
+            // columns' list thresholds for the list scan, -inf where the
+            // column's tile minimum is above its threshold)
+            if constexpr (LIST) S.csq[t] = lst ? pre_tau[e] : -SCR_INF;
         }
     }
     if constexpr (FINAL) {
@@ -998,15 +999,30 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_pairs(ScreenArgs A, const
             const float tau = lst ? A.pltau[I0 + il] : -SCR_INF;
             scan_row(ib, tau, [&](int jl, float v) { stage(i, S.cid[jl], v); });
         }
+        // columns: every element against its own column's threshold (from
+        // LDS), one compare per element as for the rows, instead of a walk
+        // over the flagged columns
 #pragma unroll
-        for (int jb = 0; jb < NJB; ++jb)
-            scan_col(jb, S.clst[(CW * wj) / 32 + jb], [&](int jl, const float (&v)[NIB], bool mine) {
-                const int64_t j = S.cid[jl];
-                const float tau = S.csq[jl];  // the column's list threshold (see the merge)
+        for (int jb = 0; jb < NJB; ++jb) {
+            if (!S.clst[(CW * wj) / 32 + jb]) continue;
+            const int cb = CW * wj + 32 * jb + 4 * (lane >> 5);  // + 8 (q / 4) + q mod 4: the lane's column q
 #pragma unroll
-                for (int ib = 0; ib < NIB; ++ib)
-                    if (mine && v[ib] <= tau) stage(j, S.rid[RW * wi + 32 * ib + (lane & 31)], v[ib]);
-            });
+            for (int ib = 0; ib < NIB; ++ib) {
+                uint32_t any = 0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (__ballot(acc[ib][jb][q] <= S.csq[cb + 8 * (q >> 2) + (q & 3)])) any |= 1u << q;
+                if (!any) continue;
+                const int64_t irow = S.rid[RW * wi + 32 * ib + (lane & 31)];
+                while (any) {
+                    const int q = __builtin_ctz(any);
+                    any &= any - 1;
+                    const int jl = cb + 8 * (q >> 2) + (q & 3);
+                    const float v = acc[ib][jb][q];
+                    if (v <= S.csq[jl]) stage(S.cid[jl], irow, v);
+                }
+            }
+        }
     }
     __syncthreads();
     {
