@@ -396,10 +396,15 @@ __device__ inline bool key_less(double d2a, int ja, double d2b, int jb) {
 // U_c = min over rows i of c of (b_i + Emax_i) (1 + rho), rounded up: an upper
 // bound on the recheck value of c's lightest outgoing edge.  With pair bounds
 // (ub != nullptr) ub_i, the least Dhat^2 + E_ij screened, replaces b_i + Emax_i.
-__global__ void k_comp_ub(const float *__restrict__ best, const float *__restrict__ Emax,
-                          const float *__restrict__ ub, const int32_t *__restrict__ comp, int64_t n, float up,
-                          uint32_t *__restrict__ comp_ub) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Thread t takes the point at position t of the tile order `order` (npos
+// positions, ids >= n are padding): the order keeps the points of a component
+// together (components only merge), so a wave's points mostly share one
+// component and the grouped atomic issues one or two atomics per wave.
+__global__ void k_comp_ub(const int32_t *__restrict__ order, int64_t npos, const float *__restrict__ best,
+                          const float *__restrict__ Emax, const float *__restrict__ ub,
+                          const int32_t *__restrict__ comp, int64_t n, float up, uint32_t *__restrict__ comp_ub) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = pos < npos ? order[pos] : n;
     const float b = i < n ? best[i] : SCR_INF;
     const bool active = b < SCR_INF;
     const float u = active ? (ub ? ub[i] : b + Emax[i]) * up : 0.0f;
@@ -2774,8 +2779,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                P.best);
             LAUNCH_CHECK();
             fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
-                               up, P.comp_ub);
+            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, P.best,
+                               P.Emax, ubp, P.comp, n, up, P.comp_ub);
             LAUNCH_CHECK();
             fill<int32_t>(P.counters + C_FORCE, 0, 1, s);
             hipLaunchKernelGGL(k_list_capture, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.comp_ub, P.best,
@@ -2864,8 +2869,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                     LAUNCH_CHECK();
                 }
                 fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
-                                   up, P.comp_ub);
+                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, P.best,
+                                   P.Emax, ubp, P.comp, n, up, P.comp_ub);
                 LAUNCH_CHECK();
                 hipLaunchKernelGGL(k_tile_reach, dim3(grid_for(P.nt, 4)), dim3(256), 0, s, P.pbest, P.pEmax,
                                    ubp ? P.pub : nullptr, SA.lcnt ? P.pltau : nullptr, P.pcomp, P.comp_ub, P.nt,
@@ -2890,8 +2895,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                 lists = LISTS_READY;
             }
             fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
-                               up, P.comp_ub);
+            hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, P.best,
+                               P.Emax, ubp, P.comp, n, up, P.comp_ub);
             LAUNCH_CHECK();
         }
         fill<int32_t>(P.counters + C_OVF, 0, 1, s);
@@ -2928,8 +2933,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             if (list_round) {
                 // the gathered rows' minima are now exact: a tighter U
                 fill<uint32_t>(P.comp_ub, U32_MAX, ncomp, s);
-                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(n, 256)), dim3(256), 0, s, P.best, P.Emax, ubp, P.comp, n,
-                                   up, P.comp_ub);
+                hipLaunchKernelGGL(k_comp_ub, dim3(grid_for(P.n_pad, 256)), dim3(256), 0, s, P.perm, P.n_pad, P.best,
+                                   P.Emax, ubp, P.comp, n, up, P.comp_ub);
                 LAUNCH_CHECK();
             }
             if (f64)
