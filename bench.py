@@ -363,6 +363,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, nargs="+", default=[4000, 8000])
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads, the sparse-communities precision comparison and graph weights")
+    ap.add_argument("--only-graph-weights", action="store_true",
+                    help="time only the full-graph weights at the blobs and anisotropic-mixture sizes and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, run one plain device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--traffic-report", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -389,6 +391,10 @@ def main():
         print("bench.py measures one GPU only: the MST screen shards over tile pairs with one min-all-reduce per "
               "Boruvka round, but no multi-GPU path is built; run with --gpus 1", flush=True)
         sys.exit(2)
+
+    if args.only_graph_weights:
+        print(json.dumps({"graph_weights": graph_weights_timing()}), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -12,8 +12,10 @@
 // in ascending order, k_gw_dist forms every distance D(i, j) of the slab in
 // parallel (64 x 64 tiles, 4 x 4 per thread, coordinates staged in LDS as
 // FP64) and stores it transposed (slab column major, so that the next pass
-// reads consecutive rows), then k_gw_sum lets one thread per row add the
-// slab's phi(D) and D to its running sums in ascending j.
+// reads consecutive rows), then k_gw_sum adds the slab's phi(D) and D to the
+// rows' running sums in ascending j: a workgroup of 64 rows forms phi of 32
+// columns at a time with all its threads (loads and exp in parallel) and one
+// thread per row adds them in order.
 #include <cmath>
 
 #include "common.hpp"
@@ -86,21 +88,48 @@ __global__ __launch_bounds__(256) void k_gw_dist(const double *__restrict__ Xd, 
     }
 }
 
-// Row i adds phi(D(i, j)) and D(i, j) of the slab's columns, ascending j, j != i.
+// Rows i0 .. i0+63 add phi(D(i, j)) and D(i, j) of the slab's columns,
+// ascending j, j != i.  Per step of GW_SC columns every thread loads and maps
+// GW_SC / 4 elements (coalesced over the rows) into LDS, then the first wave
+// adds them, one lane per row, in column order.
+constexpr int GW_SR = 64, GW_SC = 32;
 template <int PHI>
-__global__ void k_gw_sum(const double *__restrict__ Dt, int64_t n, int64_t j0, int64_t w, double sigma,
-                         double *__restrict__ so, double *__restrict__ sp) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double a = so[i], b = sp[i];
-    for (int64_t jj = 0; jj < w; ++jj) {
-        if (j0 + jj == i) continue;
-        const double dist = Dt[jj * n + i];
-        a = a + (PHI == ISO_PHI_GAUSS_SQ ? exp(-(dist * dist) / (2.0 * sigma * sigma)) : exp(-dist / sigma));
-        b = b + dist;
+__global__ __launch_bounds__(256) void k_gw_sum(const double *__restrict__ Dt, int64_t n, int64_t j0, int64_t w,
+                                                double sigma, double *__restrict__ so, double *__restrict__ sp) {
+    __shared__ double dd[GW_SC][GW_SR + 1], pp[GW_SC][GW_SR + 1];
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * GW_SR;
+    const int64_t iown = i0 + tid;  // the row lane tid < GW_SR adds
+    double a = 0.0, b = 0.0;
+    if (tid < GW_SR && iown < n) {
+        a = so[iown];
+        b = sp[iown];
     }
-    so[i] = a;
-    sp[i] = b;
+    for (int64_t c0 = 0; c0 < w; c0 += GW_SC) {
+#pragma unroll
+        for (int q = 0; q < GW_SC * GW_SR / 256; ++q) {
+            const int idx = tid + 256 * q;
+            const int cl = idx / GW_SR, rl = idx % GW_SR;
+            const int64_t jj = c0 + cl, i = i0 + rl;
+            const double dist = (jj < w && i < n) ? Dt[jj * n + i] : 0.0;
+            dd[cl][rl] = dist;
+            pp[cl][rl] = PHI == ISO_PHI_GAUSS_SQ ? exp(-(dist * dist) / (2.0 * sigma * sigma)) : exp(-dist / sigma);
+        }
+        __syncthreads();
+        if (tid < GW_SR) {
+            const int cn = w - c0 < GW_SC ? (int)(w - c0) : GW_SC;
+            for (int cl = 0; cl < cn; ++cl) {
+                if (j0 + c0 + cl == iown) continue;
+                a = a + pp[cl][tid];
+                b = b + dd[cl][tid];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < GW_SR && iown < n) {
+        so[iown] = a;
+        sp[iown] = b;
+    }
 }
 
 __global__ void k_gw_zero(double *__restrict__ so, double *__restrict__ sp, int64_t n) {
@@ -172,10 +201,11 @@ extern "C" iso_status iso_graph_weights(const float *X, int64_t n, int64_t d, in
             hipLaunchKernelGGL(k_gw_dist, dim3((unsigned)((n + GW_T - 1) / GW_T), (unsigned)((w + GW_T - 1) / GW_T)),
                                dim3(256), 0, s, Xd, n, d, j0, w, Dt);
             LAUNCH_CHECK();
+            const unsigned gs = (unsigned)((n + GW_SR - 1) / GW_SR);
             if (phi_kind == ISO_PHI_GAUSS_SQ)
-                hipLaunchKernelGGL(k_gw_sum<ISO_PHI_GAUSS_SQ>, dim3(gn), dim3(256), 0, s, Dt, n, j0, w, sigma, so, sp);
+                hipLaunchKernelGGL(k_gw_sum<ISO_PHI_GAUSS_SQ>, dim3(gs), dim3(256), 0, s, Dt, n, j0, w, sigma, so, sp);
             else
-                hipLaunchKernelGGL(k_gw_sum<ISO_PHI_EXP_DIST>, dim3(gn), dim3(256), 0, s, Dt, n, j0, w, sigma, so, sp);
+                hipLaunchKernelGGL(k_gw_sum<ISO_PHI_EXP_DIST>, dim3(gs), dim3(256), 0, s, Dt, n, j0, w, sigma, so, sp);
             LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(k_gw_finish, dim3(gn), dim3(256), 0, s, so, sp, n, alpha, omega0, p0);
