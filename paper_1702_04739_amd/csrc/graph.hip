@@ -43,7 +43,10 @@ __global__ __launch_bounds__(256) void k_gw_dist(const double *__restrict__ Xd, 
                                                  int64_t w, double *__restrict__ Dt) {
     __shared__ double xr[GW_T][GW_K + 1], xc[GW_T][GW_K + 1];
     const int tid = threadIdx.x;
-    const int ti = tid & 15, tj = tid >> 4;  // rows 4 ti .. +3, slab columns 4 tj .. +3 of the tile
+    // rows ti + 16 a and slab columns tj + 16 b (a, b < 4) of the tile: the 16
+    // rows a wave's lanes read at once are consecutive, so their FP64 LDS reads
+    // fall in distinct banks, and the stores cover 16 consecutive rows
+    const int ti = tid & 15, tj = tid >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * GW_T, c0 = (int64_t)blockIdx.y * GW_T;
     double acc[4][4];
 #pragma unroll
@@ -62,9 +65,9 @@ __global__ __launch_bounds__(256) void k_gw_dist(const double *__restrict__ Xd, 
         for (int c = 0; c < tn; ++c) {
             double xa[4], xb[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) xa[a] = xr[4 * ti + a][c];
+            for (int a = 0; a < 4; ++a) xa[a] = xr[ti + 16 * a][c];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xb[b] = xc[4 * tj + b][c];
+            for (int b = 0; b < 4; ++b) xb[b] = xc[tj + 16 * b][c];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -78,11 +81,11 @@ __global__ __launch_bounds__(256) void k_gw_dist(const double *__restrict__ Xd, 
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int64_t jj = c0 + 4 * tj + b;
+        const int64_t jj = c0 + tj + 16 * b;
         if (jj >= w) continue;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int64_t i = i0 + 4 * ti + a;
+            const int64_t i = i0 + ti + 16 * a;
             if (i < n) Dt[jj * n + i] = sqrt(acc[a][b]);
         }
     }
