@@ -2135,12 +2135,13 @@ constexpr double PB_RATIO = 4.0;  // separable / typical bound above which BF16 
 // it writes may be freed after the call) and releases it.
 struct AuxStream {
     hipStream_t s = nullptr;
-    hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr;
+    hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr, ev_len = nullptr;
     void start() {
         HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&ev_key, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&ev_z, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&ev_len, hipEventDisableTiming));
     }
     // work queued on s from now on runs after the main stream's work so far
     void after(hipStream_t main) {
@@ -2155,6 +2156,7 @@ struct AuxStream {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev_key) (void)hipEventDestroy(ev_key);
         if (ev_z) (void)hipEventDestroy(ev_z);
+        if (ev_len) (void)hipEventDestroy(ev_len);
     }
 };
 
@@ -3015,8 +3017,14 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     HIP_CHECK(hipStreamSynchronize(s));
     ISO_REQUIRE(h_edges == m, ISO_ERR_INTERNAL, "MST has %d edges, expected %lld", h_edges, (long long)m);
 
-    hipLaunchKernelGGL(k_refine, dim3(grid_for(m, 256)), dim3(256), 0, s, X, d, ld, P.eu, P.ev, m, P.elen);
+    // The FP64 lengths read only X and the edge list, and the rooting needs
+    // them only for its last step: with the second stream started they run
+    // there, beside the rooting's small latency-bound launches.
+    if (aux.s) aux.after(s);
+    hipLaunchKernelGGL(k_refine, dim3(grid_for(m, 256)), dim3(256), 0, aux.s ? aux.s : s, X, d, ld, P.eu, P.ev, m,
+                       P.elen);
     LAUNCH_CHECK();
+    if (aux.s) HIP_CHECK(hipEventRecord(aux.ev_len, aux.s));
     fill<int32_t>(P.deg, 0, n + 1, s);
     hipLaunchKernelGGL(k_degree, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, m, P.deg);
     LAUNCH_CHECK();
@@ -3037,6 +3045,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         std::swap(tn, tn2);
         std::swap(tr, tr2);
     }
+    if (aux.s) HIP_CHECK(hipStreamWaitEvent(s, aux.ev_len, 0));  // the lengths
     hipLaunchKernelGGL(k_tour_orient, dim3(grid_for(m, 256)), dim3(256), 0, s, P.eu, P.ev, P.earc, tr, P.elen, m,
                        parent, length);
     LAUNCH_CHECK();
