@@ -27,6 +27,8 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -1272,6 +1274,16 @@ __global__ void k_tile_max(const float *__restrict__ prn, const float *__restric
 }
 
 // Folds running minima kept by position back into the per-point array.
+// The projection's reference tiles q ntiles / nref (q < nref): their centroids
+// (rows of out) and point counts (out_cnt), gathered for one copy to the host.
+__global__ void k_ref_gather(const float *__restrict__ cen, const int32_t *__restrict__ tcnt, int64_t ntiles,
+                             int64_t d, int nref, float *__restrict__ out, int32_t *__restrict__ out_cnt) {
+    const int q = blockIdx.x;
+    const int64_t t = (int64_t)q * ntiles / nref;
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) out[(int64_t)q * d + k] = cen[t * d + k];
+    if (threadIdx.x == 0) out_cnt[q] = tcnt[t];
+}
+
 __global__ void k_pos_scatter(const int32_t *__restrict__ order, int64_t npos, int64_t n,
                               const float *__restrict__ pv, float *__restrict__ v) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1958,6 +1970,7 @@ struct MstPlan {
     int32_t *tcnt, *piv, *piv_rank;
     int2 *pairsF2;                  // the final round's tile pairs of one phase
     double *Q, *z, *zc, *cn;        // final round's support bound: projection, points, tiles
+    float *refbuf;                  // the projection's reference centroids and counts, for one copy
     float *S;                       // [ntF_cap][ntF_cap] supports
     float *Dm;                      // [ntb][ntb] squared distances between tile centroids
     double *rb_d2, *elen, *wsum;
@@ -2084,6 +2097,7 @@ struct MstPlan {
             piv_rank = a.take<int32_t>(PIV);
             pivd = a.take<float>(PIV * PIV);
             Q = a.take<double>((size_t)KQ * (size_t)d);
+            refbuf = a.take<float>((size_t)(KQ + 1) * (size_t)(d + 1));
             z = a.take<double>((size_t)n * KQ);
             zc = a.take<double>((size_t)ntb * KQ);
             cn = a.take<double>(ntb);
@@ -2129,34 +2143,80 @@ constexpr double ESCALATE_GATHER = 0.25, ESCALATE_RESCAN = 1.0 / 64.0;
 constexpr double PB_RATIO = 4.0;  // separable / typical bound above which BF16 uses pair bounds
 
 // A second stream for the pruning's work that reads only X (the points'
-// nearest pivots, their projection z = Q x), so that it overlaps the main
-// stream's work; events order it after its inputs and before its consumers.
-// Non-blocking, default priority; the destructor waits for it (the workspace
-// it writes may be freed after the call) and releases it.
+// nearest pivots, their projection z = Q x, the FP64 edge lengths), so that it
+// overlaps the main stream's work; events order it after its inputs and before
+// its consumers.  Non-blocking, default priority.  Creating and destroying a
+// stream per call costs more than the work it overlaps, so the streams (with
+// their events) are kept per device for the life of the process: a call takes
+// one from its device's pool (a new one when the pool is empty) and gives it
+// back at the end, after making the main stream wait for everything queued on
+// it (the workspace it writes may be reused once the main stream moves on).
+// On an error the stream is synchronised and destroyed instead.
+struct AuxSet {
+    hipStream_t s = nullptr;
+    hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr, ev_len = nullptr, ev_end = nullptr;
+};
+
+struct AuxPool {
+    std::mutex mu;
+    std::vector<std::pair<int, AuxSet>> free;  // (device, set)
+};
+AuxPool &aux_pool() {
+    static AuxPool *p = new AuxPool();  // never destroyed: the streams live until the process ends
+    return *p;
+}
+
 struct AuxStream {
     hipStream_t s = nullptr;
-    hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr, ev_len = nullptr;
-    void start() {
-        HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        HIP_CHECK(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
-        HIP_CHECK(hipEventCreateWithFlags(&ev_key, hipEventDisableTiming));
-        HIP_CHECK(hipEventCreateWithFlags(&ev_z, hipEventDisableTiming));
-        HIP_CHECK(hipEventCreateWithFlags(&ev_len, hipEventDisableTiming));
+    hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr, ev_len = nullptr, ev_end = nullptr;
+    hipStream_t main = nullptr;
+    int dev = -1;
+    int uncaught = 0;
+    void start(hipStream_t main_stream) {
+        main = main_stream;
+        uncaught = std::uncaught_exceptions();
+        HIP_CHECK(hipGetDevice(&dev));
+        AuxSet a;
+        {
+            std::lock_guard<std::mutex> lock(aux_pool().mu);
+            auto &fl = aux_pool().free;
+            for (size_t i = 0; i < fl.size(); ++i)
+                if (fl[i].first == dev) {
+                    a = fl[i].second;
+                    fl.erase(fl.begin() + (std::ptrdiff_t)i);
+                    break;
+                }
+        }
+        if (!a.s) {
+            HIP_CHECK(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+            for (hipEvent_t *e : {&a.ev0, &a.ev_key, &a.ev_z, &a.ev_len, &a.ev_end})
+                HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        }
+        s = a.s;
+        ev0 = a.ev0;
+        ev_key = a.ev_key;
+        ev_z = a.ev_z;
+        ev_len = a.ev_len;
+        ev_end = a.ev_end;
     }
     // work queued on s from now on runs after the main stream's work so far
-    void after(hipStream_t main) {
-        HIP_CHECK(hipEventRecord(ev0, main));
+    void after(hipStream_t m) {
+        HIP_CHECK(hipEventRecord(ev0, m));
         HIP_CHECK(hipStreamWaitEvent(s, ev0, 0));
     }
     ~AuxStream() {
-        if (s) {
-            (void)hipStreamSynchronize(s);
-            (void)hipStreamDestroy(s);
+        if (!s) return;
+        const bool ok = std::uncaught_exceptions() == uncaught && hipEventRecord(ev_end, s) == hipSuccess &&
+                        hipStreamWaitEvent(main, ev_end, 0) == hipSuccess;
+        if (ok) {
+            std::lock_guard<std::mutex> lock(aux_pool().mu);
+            aux_pool().free.push_back({dev, AuxSet{s, ev0, ev_key, ev_z, ev_len, ev_end}});
+            return;
         }
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev_key) (void)hipEventDestroy(ev_key);
-        if (ev_z) (void)hipEventDestroy(ev_z);
-        if (ev_len) (void)hipEventDestroy(ev_len);
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        for (hipEvent_t e : {ev0, ev_key, ev_z, ev_len, ev_end})
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -2189,7 +2249,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     AuxStream aux;
     std::vector<int32_t> h_piv(PIV), h_rank(PIV, -1);
     if (prune) {
-        aux.start();
+        aux.start(s);
         for (int q = 0; q < PIV; ++q) h_piv[q] = (int32_t)((int64_t)q * n / PIV);
         HIP_CHECK(hipMemcpyAsync(P.piv, h_piv.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
         aux.after(s);
@@ -2428,16 +2488,19 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     std::vector<int32_t> h_refc;  // and their tiles' row counts
     // the centroids of KQ + 1 tiles spread over the current order (P.cen)
     auto fetch_ref = [&](int64_t ntiles) {
+        // gathered on the device first: one copy instead of two per reference
+        // (each copy to pageable memory waits for the stream)
         const int nref = KQ + 1;
-        h_ref.assign((size_t)nref * d, 0.0f);
-        h_refc.assign(nref, 0);
-        for (int q = 0; q < nref; ++q) {
-            const int64_t t = (int64_t)q * ntiles / nref;
-            HIP_CHECK(hipMemcpyAsync(h_ref.data() + (size_t)q * d, P.cen + t * d, sizeof(float) * d,
-                                     hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipMemcpyAsync(&h_refc[q], P.tcnt + t, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        }
+        int32_t *cnt_dev = reinterpret_cast<int32_t *>(P.refbuf + (size_t)nref * d);
+        hipLaunchKernelGGL(k_ref_gather, dim3(nref), dim3(256), 0, s, P.cen, P.tcnt, ntiles, d, nref, P.refbuf,
+                           cnt_dev);
+        LAUNCH_CHECK();
+        std::vector<float> hb((size_t)nref * (d + 1));
+        HIP_CHECK(hipMemcpyAsync(hb.data(), P.refbuf, sizeof(float) * hb.size(), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
+        h_ref.assign(hb.begin(), hb.begin() + (size_t)nref * d);
+        h_refc.assign(nref, 0);
+        std::memcpy(h_refc.data(), hb.data() + (size_t)nref * d, sizeof(int32_t) * nref);
     };
     // Q by Gram-Schmidt (twice) in FP64 of the differences of the reference
     // centroids to the first (directions that vanish stay zero rows), eta, and
