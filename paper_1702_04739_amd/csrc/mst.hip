@@ -2152,9 +2152,12 @@ constexpr double PB_RATIO = 4.0;  // separable / typical bound above which BF16 
 // back at the end, after making the main stream wait for everything queued on
 // it (the workspace it writes may be reused once the main stream moves on).
 // On an error the stream is synchronised and destroyed instead.
+constexpr size_t PIN_BYTES = size_t(2) << 20;  // pinned staging of small device-to-host reads
+
 struct AuxSet {
     hipStream_t s = nullptr;
     hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr, ev_len = nullptr, ev_end = nullptr;
+    char *pin = nullptr;
 };
 
 struct AuxPool {
@@ -2169,6 +2172,7 @@ AuxPool &aux_pool() {
 struct AuxStream {
     hipStream_t s = nullptr;
     hipEvent_t ev0 = nullptr, ev_key = nullptr, ev_z = nullptr, ev_len = nullptr, ev_end = nullptr;
+    char *pin = nullptr;
     hipStream_t main = nullptr;
     int dev = -1;
     int uncaught = 0;
@@ -2189,10 +2193,13 @@ struct AuxStream {
         }
         if (!a.s) {
             HIP_CHECK(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+            s = a.s;  // (released by the destructor if what follows fails)
             for (hipEvent_t *e : {&a.ev0, &a.ev_key, &a.ev_z, &a.ev_len, &a.ev_end})
                 HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+            HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&a.pin), PIN_BYTES, hipHostMallocDefault));
         }
         s = a.s;
+        pin = a.pin;
         ev0 = a.ev0;
         ev_key = a.ev_key;
         ev_z = a.ev_z;
@@ -2210,13 +2217,45 @@ struct AuxStream {
                         hipStreamWaitEvent(main, ev_end, 0) == hipSuccess;
         if (ok) {
             std::lock_guard<std::mutex> lock(aux_pool().mu);
-            aux_pool().free.push_back({dev, AuxSet{s, ev0, ev_key, ev_z, ev_len, ev_end}});
+            aux_pool().free.push_back({dev, AuxSet{s, ev0, ev_key, ev_z, ev_len, ev_end, pin}});
             return;
         }
         (void)hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(main);
         (void)hipStreamDestroy(s);
         for (hipEvent_t e : {ev0, ev_key, ev_z, ev_len, ev_end})
             if (e) (void)hipEventDestroy(e);
+        if (pin) (void)hipHostFree(pin);
+    }
+};
+
+// Small device-to-host reads staged through the pinned buffer: a copy to
+// pageable memory waits for the stream by itself, so several of them cost
+// several waits; staged, they queue behind the kernels and share the one
+// synchronisation, after which sync() moves them to their destinations.
+// A read too large for the buffer is a direct copy.
+struct HostReads {
+    char *pin = nullptr;
+    size_t used = 0;
+    struct Pending {
+        void *dst;
+        size_t off, bytes;
+    };
+    std::vector<Pending> pend;
+    void get(void *dst, const void *src, size_t bytes, hipStream_t s) {
+        if (!pin || used + bytes > PIN_BYTES) {
+            HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+            return;
+        }
+        HIP_CHECK(hipMemcpyAsync(pin + used, src, bytes, hipMemcpyDeviceToHost, s));
+        pend.push_back({dst, used, bytes});
+        used += (bytes + 15) & ~size_t(15);
+    }
+    void sync(hipStream_t s) {
+        HIP_CHECK(hipStreamSynchronize(s));
+        for (const Pending &q : pend) std::memcpy(q.dst, pin + q.off, q.bytes);
+        pend.clear();
+        used = 0;
     }
 };
 
@@ -2247,9 +2286,11 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     // q n / PIV); that assignment reads only X and runs on the second stream
     // while the main stream computes the representation.
     AuxStream aux;
+    aux.start(s);
+    HostReads R;
+    R.pin = aux.pin;
     std::vector<int32_t> h_piv(PIV), h_rank(PIV, -1);
     if (prune) {
-        aux.start(s);
         for (int q = 0; q < PIV; ++q) h_piv[q] = (int32_t)((int64_t)q * n / PIV);
         HIP_CHECK(hipMemcpyAsync(P.piv, h_piv.data(), sizeof(int32_t) * PIV, hipMemcpyHostToDevice, s));
         aux.after(s);
@@ -2265,8 +2306,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                        ld, P.psum, P.pgrid, P.pmin, P.pmax, P.counters);
     LAUNCH_CHECK();
     int32_t h_nonfinite = 0;
-    HIP_CHECK(hipMemcpyAsync(&h_nonfinite, P.counters + C_NONFINITE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    R.get(&h_nonfinite, P.counters + C_NONFINITE, sizeof(int32_t), s);
+    R.sync(s);
     ISO_REQUIRE(h_nonfinite == 0, ISO_ERR_NONFINITE, "points contain a NaN or infinite coordinate");
     float inv_step = 1.0f;  // INT8: 2^-qg
     int32_t h_qg = GRID_NONE;
@@ -2280,9 +2321,9 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                            P.mu, P.counters);
         LAUNCH_CHECK();
         int32_t hb[2] = {0, 0};
-        HIP_CHECK(hipMemcpyAsync(&hb[0], P.counters + C_I8BAD, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(&h_qg, P.qg, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(&hb[0], P.counters + C_I8BAD, sizeof(int32_t), s);
+        R.get(&h_qg, P.qg, sizeof(int32_t), s);
+        R.sync(s);
         ISO_REQUIRE(hb[0] == 0, ISO_ERR_INVALID_ARG,
                     "the INT8 screen needs 8-bit data: every coordinate on one binary grid 2^q with each column "
                     "spanning at most 255 steps");
@@ -2313,8 +2354,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     // FP32; only fl(s_i + s_j) and the final fused multiply-add round, which
     // costs at most 3.01 u (r_i + r_j)^2.
     int32_t h_grid = GRID_NONE;
-    HIP_CHECK(hipMemcpyAsync(&h_grid, P.grid_min, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    R.get(&h_grid, P.grid_min, sizeof(int32_t), s);
+    R.sync(s);
     bound.g_exact = (float)(4.0 * u);
     bound.rlim = (h_grid != GRID_NONE && h_grid > -120)
                      ? (float)(std::sqrt(2.0) * std::ldexp(1.0, h_grid + 11) * (1.0 - 0x1p-20))
@@ -2348,10 +2389,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         LAUNCH_CHECK();
         double hs[2] = {0.0, 0.0};
         uint32_t hm[2] = {0u, 0u};
-        HIP_CHECK(hipMemcpyAsync(hs, P.nsum, sizeof(hs), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(&hm[0], P.rmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(&hm[1], P.emax, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(hs, P.nsum, sizeof(hs), s);
+        R.get(&hm[0], P.rmax, sizeof(uint32_t), s);
+        R.get(&hm[1], P.emax, sizeof(uint32_t), s);
+        R.sync(s);
         float rmx, emx;
         std::memcpy(&rmx, &hm[0], sizeof(float));
         std::memcpy(&emx, &hm[1], sizeof(float));
@@ -2409,8 +2450,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                            P.pivd);
         LAUNCH_CHECK();
         std::vector<float> pd((size_t)PIV * PIV);
-        HIP_CHECK(hipMemcpyAsync(pd.data(), P.pivd, sizeof(float) * pd.size(), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(pd.data(), P.pivd, sizeof(float) * pd.size(), s);
+        R.sync(s);
         int cur = 0;
         h_rank[0] = 0;
         for (int q = 1; q < PIV; ++q) {
@@ -2496,8 +2537,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                            cnt_dev);
         LAUNCH_CHECK();
         std::vector<float> hb((size_t)nref * (d + 1));
-        HIP_CHECK(hipMemcpyAsync(hb.data(), P.refbuf, sizeof(float) * hb.size(), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(hb.data(), P.refbuf, sizeof(float) * hb.size(), s);
+        R.sync(s);
         h_ref.assign(hb.begin(), hb.begin() + (size_t)nref * d);
         h_refc.assign(nref, 0);
         std::memcpy(h_refc.data(), hb.data() + (size_t)nref * d, sizeof(int32_t) * nref);
@@ -2595,9 +2636,9 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                            P.kpos, P.keepu, P.kposu, P.pairs_r);
         LAUNCH_CHECK();
         int32_t hk[2] = {0, 0};
-        HIP_CHECK(hipMemcpyAsync(&hk[0], P.kpos + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(&hk[1], P.kposu + P.npairs, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(&hk[0], P.kpos + P.npairs, sizeof(int32_t), s);
+        R.get(&hk[1], P.kposu + P.npairs, sizeof(int32_t), s);
+        R.sync(s);
         ISO_REQUIRE(hk[0] >= 0 && hk[1] >= 0 && hk[0] + hk[1] <= P.npairs, ISO_ERR_INTERNAL, "tile-pair compaction");
         return {(int64_t)hk[0], (int64_t)hk[1]};
     };
@@ -2613,8 +2654,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         fill<int32_t>(P.flag, 0, K, s);
         histogram_i32(P.comp, n, K, P.flag, s);
         std::vector<int32_t> hs(K), pst(K), sst(K), tco;
-        HIP_CHECK(hipMemcpyAsync(hs.data(), P.flag, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(hs.data(), P.flag, sizeof(int32_t) * K, s);
+        R.sync(s);
         int64_t pos = 0, srt = 0;
         for (int c = 0; c < K; ++c) {
             sst[c] = (int32_t)srt;
@@ -2637,8 +2678,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                out);
             LAUNCH_CHECK();
             int32_t c = 0;
-            HIP_CHECK(hipMemcpyAsync(&c, P.frpos + np, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
+            R.get(&c, P.frpos + np, sizeof(int32_t), s);
+            R.sync(s);
             ISO_REQUIRE(c >= 0 && c <= np, ISO_ERR_INTERNAL, "final-round tile-pair compaction");
             return c;
         };
@@ -2702,8 +2743,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             launch_screen_pairs(FA, P.pairsF2, 0, n1, s);
             scr.stop(s);
             std::vector<uint32_t> hu(FR_KC * FR_KC);
-            HIP_CHECK(hipMemcpyAsync(hu.data(), P.upair, sizeof(uint32_t) * hu.size(), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
+            R.get(hu.data(), P.upair, sizeof(uint32_t) * hu.size(), s);
+            R.sync(s);
             std::vector<float> B((size_t)K * K), hb(FR_KC * FR_KC, 0.0f);
             for (int a = 0; a < K; ++a)
                 for (int b = 0; b < K; ++b) {
@@ -2747,8 +2788,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             hipLaunchKernelGGL(k_fr_count, dim3(row_grid(n)), dim3(256), 0, s, n, P.comp, P.Emax, P.bestc, P.posF,
                                bstride, P.upair, P.ccnt, P.gcj, P.gcl, kappa, dn, P.counters);
             LAUNCH_CHECK();
-            HIP_CHECK(hipMemcpyAsync(hc, P.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
+            R.get(hc, P.counters, sizeof(hc), s);
+            R.sync(s);
             unsigned long long work = 0;
             memcpy(&work, &hc[C_FRWORK], sizeof(work));
             if (timed) {
@@ -2778,10 +2819,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         LAUNCH_CHECK();
         std::vector<unsigned long long> w1(FR_KC * FR_KC), w2(FR_KC * FR_KC);
         int32_t h[C_COUNT];
-        HIP_CHECK(hipMemcpyAsync(w1.data(), P.W1, sizeof(unsigned long long) * w1.size(), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(w2.data(), P.W2, sizeof(unsigned long long) * w2.size(), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(h, P.counters, sizeof(h), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(w1.data(), P.W1, sizeof(unsigned long long) * w1.size(), s);
+        R.get(w2.data(), P.W2, sizeof(unsigned long long) * w2.size(), s);
+        R.get(h, P.counters, sizeof(h), s);
+        R.sync(s);
         // Kruskal over the components' lightest edges, ordered by (D^2, ids)
         struct CE {
             unsigned long long d2, ids;
@@ -2815,7 +2856,7 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         HIP_CHECK(hipMemcpyAsync(P.ev + off, nv.data(), sizeof(int32_t) * nv.size(), hipMemcpyHostToDevice, s));
         const int32_t total = off + K - 1;
         HIP_CHECK(hipMemcpyAsync(P.counters + C_EDGES, &total, sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.sync(s);
         final_components = K;
         return true;
     };
@@ -2853,8 +2894,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                P.cl, P.counters);
             LAUNCH_CHECK();
             int32_t h_force = 0;
-            HIP_CHECK(hipMemcpyAsync(&h_force, P.counters + C_FORCE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
+            R.get(&h_force, P.counters + C_FORCE, sizeof(int32_t), s);
+            R.sync(s);
             // an undecided row costs a row sweep over all points, a screen
             // round about half of one per row: lists pay below ~1/6 undecided
             if ((double)h_force <= 0.15 * (double)n) {
@@ -2976,8 +3017,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
                                P.counters);
         LAUNCH_CHECK();
         int32_t h_gather = 0;
-        HIP_CHECK(hipMemcpyAsync(&h_gather, P.counters + C_GATHER, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(&h_gather, P.counters + C_GATHER, sizeof(int32_t), s);
+        R.sync(s);
         if (timed && !list_round) {
             iso_timing &T = timing();
             T.screen_launches += 1;
@@ -3013,8 +3054,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
             LAUNCH_CHECK();
             if (may_escalate) {
                 int32_t h_ovf = 0;
-                HIP_CHECK(hipMemcpyAsync(&h_ovf, P.counters + C_OVF, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIP_CHECK(hipStreamSynchronize(s));
+                R.get(&h_ovf, P.counters + C_OVF, sizeof(int32_t), s);
+                R.sync(s);
                 if ((double)h_ovf > 64.0 + ESCALATE_RESCAN * (double)n) {
                     give_up();
                     return;
@@ -3051,8 +3092,8 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
         hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, s, P.comp, n, P.npar, P.newid);
         LAUNCH_CHECK();
         int32_t h[C_COUNT];
-        HIP_CHECK(hipMemcpyAsync(h, P.counters, sizeof(h), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(h, P.counters, sizeof(h), s);
+        R.sync(s);
         ISO_REQUIRE(h[C_NOEDGE] == 0, ISO_ERR_INTERNAL, "a component found no outgoing edge in round %d", rounds);
         if (prune && !list_round) tp_full += h[C_TPFULL];
         ISO_REQUIRE(h[C_NCOMP] >= 1 && h[C_NCOMP] < ncomp, ISO_ERR_INTERNAL,
@@ -3069,15 +3110,15 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
 
     if (timed && prune) {
         unsigned long long pp = 0;
-        HIP_CHECK(hipMemcpyAsync(&pp, P.counters + C_PAIRS, sizeof(pp), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(&pp, P.counters + C_PAIRS, sizeof(pp), s);
+        R.sync(s);
         timing().screen_pairs += (double)pp;
         timing().screen_dim = (double)P.d_pad;
     }
     const int64_t m = n - 1;
     int32_t h_edges = 0;
-    HIP_CHECK(hipMemcpyAsync(&h_edges, P.counters + C_EDGES, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    R.get(&h_edges, P.counters + C_EDGES, sizeof(int32_t), s);
+    R.sync(s);
     ISO_REQUIRE(h_edges == m, ISO_ERR_INTERNAL, "MST has %d edges, expected %lld", h_edges, (long long)m);
 
     // The FP64 lengths read only X and the edge list, and the rooting needs
@@ -3114,11 +3155,11 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     LAUNCH_CHECK();
     // the tour from the root covers every arc exactly when the edges form one tree
     int32_t h_tour[2] = {0, 0};
-    HIP_CHECK(hipMemcpyAsync(&h_tour[0], tr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipMemcpyAsync(&h_tour[1], P.aoff + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    R.get(&h_tour[0], tr, sizeof(int32_t), s);
+    R.get(&h_tour[1], P.aoff + 1, sizeof(int32_t), s);
     hipLaunchKernelGGL(k_sum_lengths, dim3(1), dim3(1024), 0, s, length, n, P.wsum);
     LAUNCH_CHECK();
-    HIP_CHECK(hipStreamSynchronize(s));
+    R.sync(s);
     ISO_REQUIRE(h_tour[1] > 0 && (int64_t)h_tour[0] == narcs, ISO_ERR_INTERNAL,
                 "the rooting tour covers %d of %lld arcs (root degree %d)", h_tour[0], (long long)narcs, h_tour[1]);
     whole.stop(s);
@@ -3128,10 +3169,10 @@ void run_mst(MstPlan &P, Arena &arena, const float *X, int32_t recheck, int32_t 
     }
     if (info) {
         long long cand = 0, resc = 0;
-        HIP_CHECK(hipMemcpyAsync(&cand, P.counters + C_CAND, sizeof(cand), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(&resc, P.counters + C_RESCAN, sizeof(resc), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(&info->mst_weight, P.wsum, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        R.get(&cand, P.counters + C_CAND, sizeof(cand), s);
+        R.get(&resc, P.counters + C_RESCAN, sizeof(resc), s);
+        R.get(&info->mst_weight, P.wsum, sizeof(double), s);
+        R.sync(s);
         info->rounds = rounds;
         info->list_rounds = list_rounds;
         info->final_components = final_components;
