@@ -149,6 +149,11 @@ iso_status iso_mst_workspace_size(int64_t n, int64_t d, int32_t precision, size_
  *   ws      device workspace of iso_mst_workspace_size bytes, or NULL (the
  *           library then allocates and frees it on `stream`).
  *   stream  HIP stream (NULL: the default stream); the call synchronises it.
+ *           Part of the work runs on a second stream of the library's,
+ *           ordered by events; `stream` waits for all of it before the call
+ *           returns.  The library keeps, per device and for the life of the
+ *           process, one such stream with its events and a 2 MB pinned
+ *           staging buffer for each call running at once.
  * Errors: n < 2, d < 1, ld < d, null pointers, unknown precision, recheck or
  * flag bits (INVALID_ARG); a non-finite coordinate (NONFINITE); the INT8
  * screen on data that is not 8-bit (INVALID_ARG). */
